@@ -1,0 +1,239 @@
+"""ctypes front end of ``sn_oracle.c`` plus plain rollout / gradient drivers (FP64, host).
+
+TEST INFRASTRUCTURE: see the package docstring.  The drivers are literal loops over the
+paper's explicit time iteration (Alg. "Execution of the solver", one Runge-Kutta stage for
+explicit Euler); the adjoint drivers walk the same loop backwards with the exact
+transpose of each step.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Callable, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sn_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_lp = ctypes.POINTER(ctypes.c_int64)
+
+
+def build_oracle(force: bool = True) -> str:
+    """Compile the C oracle with gcc (OpenMP over independent cells / ordinates)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+               _SRC, "-o", _LIB + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build_oracle()
+        L = ctypes.CDLL(_LIB)
+        L.oracle_version.restype = ctypes.c_int
+        L.oracle_step.restype = ctypes.c_int
+        L.oracle_step.argtypes = [ctypes.c_int64, ctypes.c_int32, _ip, _dp, _dp, ctypes.c_int32,
+                                  _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_double,
+                                  ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, _dp, _dp, ctypes.c_int64, _lp]
+        L.oracle_adjoint_step.restype = ctypes.c_int
+        L.oracle_adjoint_step.argtypes = [ctypes.c_int64, ctypes.c_int32, _ip, _dp, _dp,
+                                          ctypes.c_int32, _dp, _dp, _dp, _dp, _dp, _dp,
+                                          ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_mass.restype = ctypes.c_double
+        L.oracle_mass.argtypes = [ctypes.c_int64, _dp, ctypes.c_int32, _dp, _dp]
+        L.oracle_scalar_flux.restype = ctypes.c_int
+        L.oracle_scalar_flux.argtypes = [ctypes.c_int64, ctypes.c_int32, _dp, _dp, _dp]
+        L.oracle_dose_accumulate.restype = ctypes.c_int
+        L.oracle_dose_accumulate.argtypes = [ctypes.c_int64, ctypes.c_int32, _dp, _dp, _dp,
+                                             ctypes.c_double, _dp]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleProblem:
+    """The arrays one step needs, converted once to contiguous FP64 / int32."""
+
+    def __init__(self, face_nbr, face_normal, area, omega, w, sigma_t, sigma_s, K=None,
+                 rho=None, source=None, inflow=None, neumann=False):
+        self.face_nbr = np.ascontiguousarray(face_nbr, dtype=np.int32)
+        self.nc, self.mf = self.face_nbr.shape
+        self.face_normal = _f64(face_normal).reshape(self.nc, self.mf, 2)
+        self.area = _f64(area)
+        self.omega = _f64(omega).reshape(-1, 3)
+        self.w = _f64(w)
+        self.nq = int(self.w.shape[0])
+        self.K = _f64(K)
+        self.sigma_t = _f64(sigma_t)
+        self.sigma_s = _f64(sigma_s)
+        self.rho = _f64(rho)
+        self.source = _f64(source)
+        self.inflow = _f64(inflow)
+        self.neumann = bool(neumann)
+
+    @classmethod
+    def from_problem(cls, P, **over):
+        kw = dict(face_nbr=P.mesh.face_nbr, face_normal=P.mesh.face_normal, area=P.mesh.area,
+                  omega=P.omega, w=P.w, sigma_t=P.sigma_t, sigma_s=P.sigma_s, K=P.K, rho=P.rho,
+                  source=P.source, inflow=P.inflow)
+        kw.update(over)
+        return cls(**kw)
+
+    def replace(self, **over):
+        kw = dict(face_nbr=self.face_nbr, face_normal=self.face_normal, area=self.area,
+                  omega=self.omega, w=self.w, sigma_t=self.sigma_t, sigma_s=self.sigma_s,
+                  K=self.K, rho=self.rho, source=self.source, inflow=self.inflow,
+                  neumann=self.neumann)
+        kw.update(over)
+        return OracleProblem(**kw)
+
+
+def step(op: OracleProblem, psi: np.ndarray, dt: float, alpha_t: float = 1.0,
+         alpha_s: float = 1.0, inflow_scale: float = 1.0, cells: Optional[np.ndarray] = None):
+    """One explicit Euler S_N step (Sec. 4.2 with eq. upwind1stOrder2 and eq. SNEqns)."""
+    psi = _f64(psi).reshape(op.nc, op.nq)
+    if cells is None:
+        out = np.empty((op.nc, op.nq))
+        sel, nsel = None, 0
+    else:
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.empty((cells.shape[0], op.nq))
+        sel, nsel = cells.ctypes.data_as(_lp), cells.shape[0]
+    rc = lib().oracle_step(op.nc, op.mf, op.face_nbr.ctypes.data_as(_ip), _d(op.face_normal),
+                           _d(op.area), op.nq, _d(op.omega), _d(op.w), _d(op.K),
+                           _d(op.sigma_t), _d(op.sigma_s), _d(op.rho), _d(op.source),
+                           _d(op.inflow), float(inflow_scale), int(op.neumann), float(dt),
+                           float(alpha_t), float(alpha_s), _d(psi), _d(out), nsel, sel)
+    if rc != 0:
+        raise ValueError("oracle_step rejected its arguments")
+    return out
+
+
+def adjoint_step(op: OracleProblem, psi_n: np.ndarray, lam_np1: np.ndarray, dt: float,
+                 alpha_t: float = 1.0, alpha_s: float = 1.0, g_sigma_t=None, g_sigma_s=None,
+                 g_rho=None):
+    """Exact transpose of :func:`step` applied to ``lam_np1``; gradients accumulate in place."""
+    psi_n = _f64(psi_n).reshape(op.nc, op.nq)
+    lam_np1 = _f64(lam_np1).reshape(op.nc, op.nq)
+    out = np.empty((op.nc, op.nq))
+    rc = lib().oracle_adjoint_step(op.nc, op.mf, op.face_nbr.ctypes.data_as(_ip),
+                                   _d(op.face_normal), _d(op.area), op.nq, _d(op.omega),
+                                   _d(op.w), _d(op.K), _d(op.sigma_t), _d(op.sigma_s),
+                                   _d(op.rho), int(op.neumann), float(dt), float(alpha_t),
+                                   float(alpha_s), _d(psi_n), _d(lam_np1), _d(out),
+                                   _d(g_sigma_t), _d(g_sigma_s), _d(g_rho))
+    if rc != 0:
+        raise ValueError("oracle_adjoint_step rejected its arguments")
+    return out
+
+
+def mass(op: OracleProblem, psi) -> float:
+    """Total mass sum_i A_i sum_q w_q psi_iq (solver log quantity, Sec. 5.1)."""
+    psi = _f64(psi).reshape(op.nc, op.nq)
+    return float(lib().oracle_mass(op.nc, _d(op.area), op.nq, _d(op.w), _d(psi)))
+
+
+def scalar_flux(op: OracleProblem, psi) -> np.ndarray:
+    """Psi_i = sum_q w_q psi_iq (Sec. 7.2)."""
+    psi = _f64(psi).reshape(op.nc, op.nq)
+    out = np.empty(op.nc)
+    lib().oracle_scalar_flux(op.nc, op.nq, _d(op.w), _d(psi), _d(out))
+    return out
+
+
+def dose_accumulate(op: OracleProblem, psi, coeff: float, dose: np.ndarray) -> np.ndarray:
+    """D_i += coeff / rho_i sum_q w_q psi_iq (dose integral of Sec. 2, left endpoint)."""
+    psi = _f64(psi).reshape(op.nc, op.nq)
+    assert dose.dtype == np.float64 and dose.flags.c_contiguous
+    lib().oracle_dose_accumulate(op.nc, op.nq, _d(op.w), _d(psi), _d(op.rho), float(coeff),
+                                 _d(dose))
+    return dose
+
+
+# ----------------------------------------------------------------------------------------
+# Rollouts (the time loop of the solver algorithm, explicit Euler: one stage per step)
+# ----------------------------------------------------------------------------------------
+
+def rollout(op: OracleProblem, psi0, dt: float, nsteps: int, alpha_t=None, alpha_s=None,
+            inflow_scale=None, dose_coeff=None, keep_states: bool = False):
+    """Run ``nsteps`` explicit steps.  Per-step sequences may be given for ``alpha_t``,
+    ``alpha_s``, ``inflow_scale`` and ``dose_coeff`` (the dose adds ``dose_coeff[n]`` times the
+    density-weighted scalar flux of the state *entering* step n).
+
+    Returns ``(psi_N, dose or None, states or None)``; ``states[n]`` is psi^n for n < N.
+    """
+    psi = _f64(psi0).reshape(op.nc, op.nq).copy()
+    dose = np.zeros(op.nc) if dose_coeff is not None else None
+    states = [] if keep_states else None
+    for n in range(nsteps):
+        at = 1.0 if alpha_t is None else float(alpha_t[n])
+        as_ = 1.0 if alpha_s is None else float(alpha_s[n])
+        isc = 1.0 if inflow_scale is None else float(inflow_scale[n])
+        if keep_states:
+            states.append(psi)
+        if dose is not None:
+            dose_accumulate(op, psi, float(dose_coeff[n]), dose)
+        psi = step(op, psi, dt, at, as_, isc)
+    return psi, dose, states
+
+
+def rollout_gradient(op: OracleProblem, psi0, dt: float, nsteps: int,
+                     dJ_dpsiN: Optional[np.ndarray] = None, dJ_ddose: Optional[np.ndarray] = None,
+                     alpha_t=None, alpha_s=None, inflow_scale=None, dose_coeff=None):
+    """Reverse pass of :func:`rollout` for a functional J(psi^N, D) that is linear in its
+    arguments with the given partial derivatives.  Returns a dict with ``psi0``,
+    ``sigma_t``, ``sigma_s`` and (when ``op.rho`` is given) ``rho`` gradients.
+
+    Recurrence: lam^N = dJ/dpsi^N; lam^n = T_n^T lam^{n+1} + dJ/dpsi^n, where the dose term
+    of step n gives dJ/dpsi^n_iq = coeff_n w_q (dJ/dD_i) / rho_i, and the explicit density
+    derivative of D_i = (1/rho_i) sum_n coeff_n phi_i^n is -D_i/rho_i (dJ/dD_i).
+    """
+    _, dose, states = rollout(op, psi0, dt, nsteps, alpha_t, alpha_s, inflow_scale, dose_coeff,
+                              keep_states=True)
+    nc, nq = op.nc, op.nq
+    lam = np.zeros((nc, nq)) if dJ_dpsiN is None else _f64(dJ_dpsiN).reshape(nc, nq).copy()
+    g_t = np.zeros(nc)
+    g_s = np.zeros(nc)
+    g_r = np.zeros(nc) if op.rho is not None else None
+    rho = op.rho if op.rho is not None else np.ones(nc)
+    for n in range(nsteps - 1, -1, -1):
+        at = 1.0 if alpha_t is None else float(alpha_t[n])
+        as_ = 1.0 if alpha_s is None else float(alpha_s[n])
+        lam = adjoint_step(op, states[n], lam, dt, at, as_, g_t, g_s, g_r)
+        if dJ_ddose is not None and dose_coeff is not None:
+            lam += float(dose_coeff[n]) * op.w[None, :] * (dJ_ddose / rho)[:, None]
+    if g_r is not None and dJ_ddose is not None and dose is not None:
+        g_r += -dose / rho * dJ_ddose
+    return {"psi0": lam, "sigma_t": g_t, "sigma_s": g_s, "rho": g_r, "dose": dose}
+
+
+def rel_l2(x, ref) -> float:
+    """||x - ref||_2 / ||ref||_2 over all entries."""
+    x = np.asarray(x, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    nr = np.linalg.norm(ref)
+    return float(np.linalg.norm(x - ref) / (nr if nr > 0 else 1.0))

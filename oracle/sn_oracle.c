@@ -1,0 +1,227 @@
+/*
+ * sn_oracle.c -- plain FP64 CPU reference of the explicit S_N step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links or calls this file: it is
+ * used by tests/, by the smoke check of the graft entry point and by the CPU-baseline leg of
+ * bench.py.  It shares no code, header or constant with the HIP library.
+ *
+ * What it computes (KiT-RT, arXiv 2205.08417):
+ *   S_N equations with density (eq. SNEqns, eq. BoltzmannCSDTrafo)
+ *       d_t psi_q + Omega_q . grad(psi_q / rho) + Sigma_t psi_q = sum_p w_p Sigma_s(Omega_q.Omega_p) psi_p (+ q)
+ *   discretised with the cell-centred finite-volume scheme of Sec. 4.2: first-order upwind
+ *   numerical flux (eq. upwind1stOrder, specialised to S_N in eq. upwind1stOrder2) and the
+ *   explicit Euler update
+ *       psi_i^{n+1} = psi_i^n - dt/A_i sum_{j in N(i)} F_up(psi_j, psi_i) + dt R(psi_i^n).
+ *   Cells carry n_{i,j} = outward unit normal times face length (Sec. 4.1).
+ *
+ * Readings where the paper leaves freedom (all listed in the design notes):
+ *   - H(x) = 1 for x > 0 and 0 otherwise: a face with Omega.n = 0 takes the neighbour branch,
+ *     whose contribution is 0 * u either way.
+ *   - isotropic scattering is the kernel 1/(4 pi) (Sigma_t = Sigma_{s,0}, Sec. 2).
+ *   - the source q_i is an angular density added as dt*q_i to every ordinate.
+ *   - per-step multipliers alpha_t, alpha_s scale Sigma_t and Sigma_s (energy dependence of
+ *     the CSD cross sections, eq. BoltzmannCSDTrafo); 1 for time-dependent problems.
+ *   - boundary faces take a ghost value of u = psi/rho: inflow[b*nq+q]*inflow_scale
+ *     (Dirichlet; vacuum when inflow is NULL), or the cell's own u (Neumann).
+ *
+ * Array conventions (all host memory, caller-owned, row-major):
+ *   face_nbr[c*mf+f]        >= 0 neighbour, -1-b boundary face b, INT32_MIN unused slot
+ *   face_normal[(c*mf+f)*2] outward normal times length
+ *   omega[q*3]              unit direction (x, y, z); streaming uses (x, y)
+ *   K[q*nq+p]               dense kernel: S_q = sum_p K[q][p] w_p psi_p; NULL = isotropic
+ *   psi[c*nq+q]
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_UNUSED_FACE INT32_MIN
+
+static const double oracle_pi = 3.14159265358979323846264338327950288;
+
+int oracle_version(void) { return 1; }
+
+/* Scattering source of cell c at ordinate q: sum_p k(Omega_q.Omega_p) w_p psi_cp (eq. SNEqns). */
+static double scatter_source(int32_t nq, const double* w, const double* K, const double* psi_c, int32_t q)
+{
+    double s = 0.0;
+    if (K == NULL) {
+        for (int32_t p = 0; p < nq; ++p) s += w[p] * psi_c[p];
+        return s / (4.0 * oracle_pi);
+    }
+    for (int32_t p = 0; p < nq; ++p) s += K[(size_t)q * nq + p] * w[p] * psi_c[p];
+    return s;
+}
+
+/* One explicit Euler step.  With sel != NULL only cells sel[0..nsel) are computed and row k
+ * of psi_out belongs to cell sel[k]; otherwise psi_out is [nc][nq]. */
+int oracle_step(int64_t nc, int32_t mf, const int32_t* face_nbr, const double* face_normal,
+                const double* area, int32_t nq, const double* omega, const double* w,
+                const double* K, const double* sigma_t, const double* sigma_s, const double* rho,
+                const double* source, const double* inflow, double inflow_scale, int32_t neumann,
+                double dt, double alpha_t, double alpha_s, const double* psi_in, double* psi_out,
+                int64_t nsel, const int64_t* sel)
+{
+    if (nc < 0 || mf < 1 || nq < 1 || !face_nbr || !face_normal || !area || !omega || !w ||
+        !sigma_t || !sigma_s || !psi_in || !psi_out)
+        return -1;
+    int64_t count = sel ? nsel : nc;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < count; ++k) {
+        int64_t i = sel ? sel[k] : k;
+        const double* psi_i = psi_in + (size_t)i * nq;
+        double rho_i = rho ? rho[i] : 1.0;
+        double* out = psi_out + (size_t)k * nq;
+        for (int32_t q = 0; q < nq; ++q) {
+            /* numerical flux sum over the faces of cell i (eq. upwind1stOrder2) */
+            double flux = 0.0;
+            for (int32_t f = 0; f < mf; ++f) {
+                int32_t j = face_nbr[(size_t)i * mf + f];
+                if (j == ORACLE_UNUSED_FACE) continue;
+                const double* n = face_normal + ((size_t)i * mf + f) * 2;
+                double s = omega[(size_t)q * 3 + 0] * n[0] + omega[(size_t)q * 3 + 1] * n[1];
+                double u_i = psi_i[q] / rho_i;
+                double u_j;
+                if (j >= 0) {
+                    u_j = psi_in[(size_t)j * nq + q] / (rho ? rho[j] : 1.0);
+                } else if (neumann) {
+                    u_j = u_i;
+                } else {
+                    int64_t b = -1 - (int64_t)j;
+                    u_j = inflow ? inflow[(size_t)b * nq + q] * inflow_scale : 0.0;
+                }
+                double H = s > 0.0 ? 1.0 : 0.0;
+                flux += s * u_i * H + s * u_j * (1.0 - H);
+            }
+            /* right-hand side: absorption/total, scattering, source */
+            double R = -alpha_t * sigma_t[i] * psi_i[q]
+                       + alpha_s * sigma_s[i] * scatter_source(nq, w, K, psi_i, q)
+                       + (source ? source[i] : 0.0);
+            out[q] = psi_i[q] - dt / area[i] * flux + dt * R;
+        }
+    }
+    return 0;
+}
+
+/* Transposed step: lam_n = T^T lam_np1, where psi^{n+1} = T psi^n + b is the step above.
+ * The transpose is formed by walking the forward step's coefficients and scattering each
+ * one, multiplied by lam_np1 at the output entry, into the input entry it came from.
+ * Gradient contributions of this step are ADDED to g_sigma_t, g_sigma_s, g_rho (each may be
+ * NULL):  sum_{i,q} lam_np1[i][q] * d psi^{n+1}[i][q] / d theta  at psi = psi_n. */
+int oracle_adjoint_step(int64_t nc, int32_t mf, const int32_t* face_nbr, const double* face_normal,
+                        const double* area, int32_t nq, const double* omega, const double* w,
+                        const double* K, const double* sigma_t, const double* sigma_s,
+                        const double* rho, int32_t neumann, double dt, double alpha_t,
+                        double alpha_s, const double* psi_n, const double* lam_np1, double* lam_n,
+                        double* g_sigma_t, double* g_sigma_s, double* g_rho)
+{
+    if (nc < 0 || mf < 1 || nq < 1 || !face_nbr || !face_normal || !area || !omega || !w ||
+        !sigma_t || !sigma_s || !psi_n || !lam_np1 || !lam_n)
+        return -1;
+    memset(lam_n, 0, sizeof(double) * (size_t)nc * nq);
+
+    /* streaming: each coefficient couples the same ordinate q, so ordinates are independent */
+#pragma omp parallel for schedule(static)
+    for (int32_t q = 0; q < nq; ++q) {
+        for (int64_t i = 0; i < nc; ++i) {
+            double l = lam_np1[(size_t)i * nq + q];
+            for (int32_t f = 0; f < mf; ++f) {
+                int32_t j = face_nbr[(size_t)i * mf + f];
+                if (j == ORACLE_UNUSED_FACE) continue;
+                const double* n = face_normal + ((size_t)i * mf + f) * 2;
+                double s = omega[(size_t)q * 3 + 0] * n[0] + omega[(size_t)q * 3 + 1] * n[1];
+                double a = -dt / area[i] * s;  /* coefficient of the upwind u in psi^{n+1}_iq */
+                int64_t up;
+                if (s > 0.0) up = i;
+                else if (j >= 0) up = j;
+                else if (neumann) up = i;
+                else continue;                   /* Dirichlet ghost: affine part b */
+                double rho_up = rho ? rho[up] : 1.0;
+                lam_n[(size_t)up * nq + q] += a / rho_up * l;
+            }
+        }
+    }
+    /* gradient w.r.t. rho: d(psi_up/rho_up)/d rho_up = -psi_up/rho_up^2 */
+    if (g_rho && rho) {
+        for (int64_t i = 0; i < nc; ++i) {
+            for (int32_t q = 0; q < nq; ++q) {
+                double l = lam_np1[(size_t)i * nq + q];
+                for (int32_t f = 0; f < mf; ++f) {
+                    int32_t j = face_nbr[(size_t)i * mf + f];
+                    if (j == ORACLE_UNUSED_FACE) continue;
+                    const double* n = face_normal + ((size_t)i * mf + f) * 2;
+                    double s = omega[(size_t)q * 3 + 0] * n[0] + omega[(size_t)q * 3 + 1] * n[1];
+                    double a = -dt / area[i] * s;
+                    int64_t up;
+                    if (s > 0.0) up = i;
+                    else if (j >= 0) up = j;
+                    else if (neumann) up = i;
+                    else continue;
+                    double r = rho[up];
+                    g_rho[up] += a * (-psi_n[(size_t)up * nq + q] / (r * r)) * l;
+                }
+            }
+        }
+    }
+    /* local terms: identity, total cross section, scattering (couples ordinates of one cell) */
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nc; ++i) {
+        const double* l = lam_np1 + (size_t)i * nq;
+        const double* psi_i = psi_n + (size_t)i * nq;
+        double* out = lam_n + (size_t)i * nq;
+        double gt = 0.0, gs = 0.0;
+        for (int32_t q = 0; q < nq; ++q) {
+            out[q] += (1.0 - dt * alpha_t * sigma_t[i]) * l[q];
+            double c = dt * alpha_s * sigma_s[i];
+            for (int32_t p = 0; p < nq; ++p) {
+                double kqp = K ? K[(size_t)q * nq + p] : 1.0 / (4.0 * oracle_pi);
+                out[p] += c * kqp * w[p] * l[q];
+            }
+            gt += -dt * alpha_t * psi_i[q] * l[q];
+            gs += dt * alpha_s * scatter_source(nq, w, K, psi_i, q) * l[q];
+        }
+        if (g_sigma_t) g_sigma_t[i] += gt;
+        if (g_sigma_s) g_sigma_s[i] += gs;
+    }
+    return 0;
+}
+
+/* Total mass sum_i A_i sum_q w_q psi_iq (the quantity the solver log reports, Sec. 5.1). */
+double oracle_mass(int64_t nc, const double* area, int32_t nq, const double* w, const double* psi)
+{
+    double m = 0.0;
+    for (int64_t i = 0; i < nc; ++i) {
+        double phi = 0.0;
+        for (int32_t q = 0; q < nq; ++q) phi += w[q] * psi[(size_t)i * nq + q];
+        m += area[i] * phi;
+    }
+    return m;
+}
+
+/* Scalar flux Psi_i = sum_q w_q psi_iq (quadrature of int_{S^2} psi dOmega, Sec. 7.2). */
+int oracle_scalar_flux(int64_t nc, int32_t nq, const double* w, const double* psi, double* phi)
+{
+    if (!w || !psi || !phi) return -1;
+    for (int64_t i = 0; i < nc; ++i) {
+        double s = 0.0;
+        for (int32_t q = 0; q < nq; ++q) s += w[q] * psi[(size_t)i * nq + q];
+        phi[i] = s;
+    }
+    return 0;
+}
+
+/* One left-endpoint term of the dose integral of Sec. 2 in pseudo-time:
+ *   D_i += coeff / rho_i * sum_q w_q psi_iq,  coeff = dt_n * S(E_n). */
+int oracle_dose_accumulate(int64_t nc, int32_t nq, const double* w, const double* psi,
+                           const double* rho, double coeff, double* dose)
+{
+    if (!w || !psi || !dose) return -1;
+    for (int64_t i = 0; i < nc; ++i) {
+        double s = 0.0;
+        for (int32_t q = 0; q < nq; ++q) s += w[q] * psi[(size_t)i * nq + q];
+        dose[i] += coeff / (rho ? rho[i] : 1.0) * s;
+    }
+    return 0;
+}

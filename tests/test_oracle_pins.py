@@ -1,0 +1,390 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test targets a term of the update so that a dropped term, a wrong sign, a wrong index
+or a transposed operand fails at least one of them:
+
+* hand-derived golden values on the four-triangle mesh (streaming orientation, upwind
+  choice, boundary ghosts, density placement, isotropic normalisation, source, dense
+  kernel orientation);
+* closed forms: exact absorption decay, source steady state, uniform-state invariants;
+* conservation (streaming antisymmetry, kernel column normalisation);
+* the adjoint through the dot-product identity and FP64 central finite differences.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2205_08417_amd import inputs as I
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "four_triangles.json")
+
+
+def _op_from_mesh(o, mesh, omega, w, **kw):
+    nc = mesh.ncells
+    kw.setdefault("sigma_t", np.zeros(nc))
+    kw.setdefault("sigma_s", np.zeros(nc))
+    return o.OracleProblem(mesh.face_nbr, mesh.face_normal, mesh.area, omega, w, **kw)
+
+
+# ---------------------------------------------------------------- golden (brute force by hand)
+
+@pytest.mark.parametrize("case", ["streaming", "isotropic_collision_source", "dense_kernel",
+                                  "density"])
+def test_golden_four_triangles(oracle_lib, case):
+    o = oracle_lib
+    d = json.load(open(GOLD))
+    c = d["cases"][case]
+    op = o.OracleProblem(np.array(d["face_nbr"]), np.array(d["face_normal"]),
+                         np.array(d["area"]), np.array(d["omega"]), np.array(c["w"]),
+                         np.array(c["sigma_t"], float), np.array(c["sigma_s"], float),
+                         K=np.array(c["K"]) if "K" in c else None,
+                         rho=np.array(c["rho"]) if "rho" in c else None,
+                         source=np.array(c["source"]) if "source" in c else None,
+                         inflow=np.array(d["inflow"]))
+    out = o.step(op, np.array(d["psi"]), d["dt"])
+    np.testing.assert_allclose(out, np.array(c["expected"]), rtol=0, atol=1e-13)
+
+
+def test_golden_vacuum_and_neumann(oracle_lib):
+    """Vacuum drops the ghost terms; Neumann replaces the ghost by the cell's own u."""
+    o = oracle_lib
+    d = json.load(open(GOLD))
+    c = d["cases"]["streaming"]
+    base = dict(face_nbr=np.array(d["face_nbr"]), face_normal=np.array(d["face_normal"]),
+                area=np.array(d["area"]), omega=np.array(d["omega"]), w=np.array(c["w"]),
+                sigma_t=np.zeros(4), sigma_s=np.zeros(4))
+    psi = np.array(d["psi"])
+    vac = o.step(o.OracleProblem(**base), psi, d["dt"])
+    # ghost terms: cell3/A had -(dt/A)(-1)(0.5) = +0.1, cell0/B +0.16*1.0, cell3/B +0.12*0.5
+    expect = np.array(c["expected"]) - np.array([[0, 0.16], [0, 0], [0, 0], [0.1, 0.06]])
+    np.testing.assert_allclose(vac, expect, atol=1e-13)
+    neu = o.step(o.OracleProblem(neumann=True, **base), psi, d["dt"])
+    # Neumann: the boundary face contributes s*u_own for either sign: cell3/A -1*4,
+    # cell0/B -0.8*4, cell3/B -0.6*1 (replacing the ghost terms)
+    expect_n = vac - 0.2 * np.array([[0, -3.2], [0, 0], [0, 0], [-4.0, -0.6]])
+    np.testing.assert_allclose(neu, expect_n, atol=1e-13)
+
+
+# ---------------------------------------------------------------- closed forms
+
+def test_absorption_decay_exact(oracle_lib):
+    """Uniform state on a torus with pure absorption: psi^n = (1 - dt sigma)^n psi^0 and
+    |psi^n - exp(-sigma t_n)| <= n (dt sigma)^2 / 2 (explicit Euler of d_t psi = -sigma psi)."""
+    o = oracle_lib
+    m = I.periodic_mesh(6, 1.0)
+    omega, w = I.product_quadrature(4, 8)
+    nc, nq = m.ncells, w.size
+    sig = 2.5
+    op = _op_from_mesh(o, m, omega, w, sigma_t=np.full(nc, sig))
+    dt = 0.01
+    psi = np.ones((nc, nq))
+    for n in range(1, 41):
+        psi = o.step(op, psi, dt)
+        exact_disc = (1 - dt * sig) ** n
+        np.testing.assert_allclose(psi, exact_disc, rtol=1e-13)
+        assert np.max(np.abs(psi - math.exp(-sig * dt * n))) <= n * (dt * sig) ** 2 / 2
+
+
+def test_source_steady_state_closed_form(oracle_lib):
+    """Uniform absorber with source q: psi^n = q/sigma (1 - (1 - dt sigma)^n) -> q/sigma."""
+    o = oracle_lib
+    m = I.periodic_mesh(5, 1.0)
+    omega, w = I.product_quadrature(2, 8)
+    nc, nq = m.ncells, w.size
+    sig, q, dt = 3.0, 0.7, 0.02
+    op = _op_from_mesh(o, m, omega, w, sigma_t=np.full(nc, sig), source=np.full(nc, q))
+    psi = np.zeros((nc, nq))
+    for n in range(1, 61):
+        psi = o.step(op, psi, dt)
+        np.testing.assert_allclose(psi, q / sig * (1 - (1 - dt * sig) ** n), rtol=1e-12)
+
+
+def test_isotropic_uniform_state_stationary(oracle_lib):
+    """sigma_a = 0, isotropic scattering, uniform psi on a torus: nothing changes, because
+    sum_p w_p / (4 pi) = 1 and the streaming of a constant vanishes on closed cells."""
+    o = oracle_lib
+    m = I.periodic_mesh(6, 1.0)
+    omega, w = I.product_quadrature(8, 8)
+    nc, nq = m.ncells, w.size
+    op = _op_from_mesh(o, m, omega, w, sigma_t=np.full(nc, 4.0), sigma_s=np.full(nc, 4.0))
+    psi = np.full((nc, nq), 1.7)
+    out = psi
+    for _ in range(20):
+        out = o.step(op, out, 0.01)
+    np.testing.assert_allclose(out, 1.7, rtol=1e-14)
+    # the same state under a dropped 1/(4 pi) would not be stationary
+    op_bad = op.replace(K=np.ones((nq, nq)))
+    assert np.max(np.abs(o.step(op_bad, psi, 0.01) - 1.7)) > 1e-2
+
+
+def test_uniform_u_with_matching_inflow_stationary(oracle_lib):
+    """Streaming only, non-uniform density: psi_i = rho_i * c with ghost u = c is a steady
+    state (the flux of u = psi/rho is constant).  Using rho_i instead of rho_j for a
+    neighbour value would break it."""
+    o = oracle_lib
+    m = I.jittered_delaunay_mesh(10, 0.0, 1.0, seed=5)
+    omega, w = I.product_quadrature(4, 8)
+    nc, nq = m.ncells, w.size
+    rng = np.random.default_rng(3)
+    rho = rng.uniform(0.2, 3.0, nc)
+    cval = 0.37
+    inflow = np.full((m.nbfaces, nq), cval)
+    op = _op_from_mesh(o, m, omega, w, rho=rho, inflow=inflow)
+    psi = rho[:, None] * cval * np.ones((nc, nq))
+    out = o.step(op, psi, 1e-3)
+    np.testing.assert_allclose(out, psi, rtol=1e-12)
+
+
+def test_upwind_direction_single_spike(oracle_lib):
+    """A spike in one cell moves only into neighbours across faces with Omega.n > 0."""
+    o = oracle_lib
+    m = I.jittered_delaunay_mesh(9, 0.0, 1.0, seed=11)
+    omega = np.array([[0.8, 0.6, 0.0]])
+    w = np.array([4 * math.pi])
+    nc = m.ncells
+    op = _op_from_mesh(o, m, omega, w)
+    c0 = int(np.argmin(np.sum((m.centroid - 0.5) ** 2, axis=1)))
+    psi = np.zeros((nc, 1))
+    psi[c0] = 1.0
+    out = o.step(op, psi, 1e-3)
+    s = m.face_normal[c0] @ omega[0, :2]
+    down = {int(m.face_nbr[c0, f]) for f in range(3) if s[f] > 0}
+    nz = set(np.nonzero(out[:, 0])[0].tolist())
+    assert nz == down | {c0}
+    np.testing.assert_allclose(out[c0, 0], 1 - 1e-3 / m.area[c0] * s[s > 0].sum(), rtol=1e-14)
+    for f in range(3):
+        if s[f] > 0:
+            j = m.face_nbr[c0, f]
+            np.testing.assert_allclose(out[j, 0], 1e-3 / m.area[j] * s[f], rtol=1e-14)
+
+
+# ---------------------------------------------------------------- conservation / kernels
+
+def _spike_problem(o, K=None, n=14, seed=2, npol=4, naz=8):
+    m = I.jittered_delaunay_mesh(n, -1.0, 1.0, seed)
+    omega, w = I.product_quadrature(npol, naz)
+    nc, nq = m.ncells, w.size
+    r2 = np.sum(m.centroid ** 2, axis=1)
+    rng = np.random.default_rng(seed)
+    psi = np.where(r2[:, None] < 0.05, rng.uniform(0.5, 2.0, (nc, nq)), 0.0)
+    op = _op_from_mesh(o, m, omega, w, sigma_t=np.full(nc, 2.0), sigma_s=np.full(nc, 2.0), K=K)
+    return m, omega, w, op, psi
+
+
+def test_mass_conservation_isotropic(oracle_lib):
+    o = oracle_lib
+    m, omega, w, op, psi = _spike_problem(o)
+    dt = I.cfl_dt(m, omega, 0.5)
+    m0 = o.mass(op, psi)
+    for _ in range(10):            # support stays well inside the domain
+        psi = o.step(op, psi, dt)
+    np.testing.assert_allclose(o.mass(op, psi), m0, rtol=1e-13)
+    assert np.all(psi >= 0)
+
+
+def test_mass_conservation_hg_and_transpose_sensitivity(oracle_lib):
+    """Column-normalised HG conserves particles; the transposed kernel would not."""
+    o = oracle_lib
+    omega, w = I.product_quadrature(4, 8)
+    K = I.henyey_greenstein_kernel(omega, w, 0.8)
+    m, omega, w, op, psi = _spike_problem(o, K=K)
+    dt = I.cfl_dt(m, omega, 0.5)
+    m0 = o.mass(op, psi)
+    p = psi
+    for _ in range(10):
+        p = o.step(op, p, dt)
+    np.testing.assert_allclose(o.mass(op, p), m0, rtol=1e-13)
+    bad = o.step(op.replace(K=np.ascontiguousarray(K.T)), psi, dt)
+    assert abs(o.mass(op, bad) - m0) > 1e-6 * m0
+
+
+def test_dense_isotropic_kernel_equals_isotropic_path(oracle_lib):
+    o = oracle_lib
+    m, omega, w, op, psi = _spike_problem(o)
+    dt = I.cfl_dt(m, omega, 0.5)
+    a = o.step(op, psi, dt)
+    b = o.step(op.replace(K=I.isotropic_kernel(w.size)), psi, dt)
+    np.testing.assert_allclose(b, a, rtol=1e-14, atol=1e-16)
+
+
+def test_mu_symmetry_preserved(oracle_lib):
+    """Ordinates mirrored in mu stream identically; a mu-symmetric state stays symmetric."""
+    o = oracle_lib
+    omega, w = I.product_quadrature(4, 8)
+    K = I.henyey_greenstein_kernel(omega, w, 0.7)
+    m, omega, w, op, psi = _spike_problem(o, K=K)
+    naz = 8
+    mirror = np.concatenate([np.arange(naz) + (3 - k) * naz for k in range(4)])
+    psi = 0.5 * (psi + psi[:, mirror])
+    dt = I.cfl_dt(m, omega, 0.5)
+    for _ in range(5):
+        psi = o.step(op, psi, dt)
+    np.testing.assert_allclose(psi, psi[:, mirror], rtol=1e-12, atol=1e-300)
+
+
+def test_relabelling_cells_is_exact(oracle_lib):
+    """Per-cell arithmetic does not depend on cell numbering: a permuted mesh gives the
+    permuted result bit for bit."""
+    o = oracle_lib
+    m, omega, w, op, psi = _spike_problem(o)
+    nc = m.ncells
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(nc)                    # new cell k is old cell perm[k]
+    inv = np.empty(nc, np.int64)
+    inv[perm] = np.arange(nc)
+    fn = m.face_nbr[perm].astype(np.int64)
+    fn = np.where(fn >= 0, inv[np.maximum(fn, 0)], fn).astype(np.int32)
+    op2 = o.OracleProblem(fn, m.face_normal[perm], m.area[perm], omega, w,
+                          op.sigma_t[perm], op.sigma_s[perm])
+    dt = I.cfl_dt(m, omega, 0.5)
+    a = o.step(op, psi, dt)
+    b = o.step(op2, psi[perm], dt)
+    assert np.array_equal(b, a[perm])
+
+
+def test_selected_cells_match_full_step(oracle_lib):
+    o = oracle_lib
+    m, omega, w, op, psi = _spike_problem(o)
+    dt = I.cfl_dt(m, omega, 0.5)
+    full = o.step(op, psi, dt)
+    sel = np.array([5, 0, 77, 3, m.ncells - 1])
+    part = o.step(op, psi, dt, cells=sel)
+    assert np.array_equal(part, full[sel])
+
+
+def test_positivity_checkerboard(oracle_lib):
+    o = oracle_lib
+    P = I.build("checkerboard_s16", n_side=22, n_polar=4, n_azimuth=8, nsteps=30)
+    op = o.OracleProblem.from_problem(P)
+    psi, _, _ = o.rollout(op, P.psi0, P.dt, P.nsteps)
+    assert np.all(psi >= 0) and psi.max() > 0
+
+
+# ---------------------------------------------------------------- reductions
+
+def test_reductions_closed_form(oracle_lib):
+    o = oracle_lib
+    m = I.jittered_delaunay_mesh(8, 0.0, 2.0, seed=4)
+    omega, w = I.product_quadrature(4, 4)
+    nc, nq = m.ncells, w.size
+    rho = np.linspace(0.5, 2.0, nc)
+    op = _op_from_mesh(o, m, omega, w, rho=rho)
+    psi = np.full((nc, nq), 0.25)
+    np.testing.assert_allclose(o.mass(op, psi), 4.0 * 4 * math.pi * 0.25, rtol=1e-14)
+    np.testing.assert_allclose(o.scalar_flux(op, psi), math.pi, rtol=1e-14)
+    dose = np.ones(nc)
+    o.dose_accumulate(op, psi, 0.3, dose)
+    np.testing.assert_allclose(dose, 1.0 + 0.3 * math.pi / rho, rtol=1e-14)
+
+
+# ---------------------------------------------------------------- adjoint
+
+def _random_linear_problem(o, K=None, neumann=False, seed=9):
+    m = I.jittered_delaunay_mesh(9, 0.0, 1.0, seed)
+    omega, w = I.product_quadrature(4, 4)
+    nc, nq = m.ncells, w.size
+    rng = np.random.default_rng(seed)
+    op = _op_from_mesh(o, m, omega, w, sigma_t=rng.uniform(0.5, 3, nc),
+                       sigma_s=rng.uniform(0, 0.5, nc), rho=rng.uniform(0.5, 2, nc), K=K,
+                       neumann=neumann)
+    return m, omega, w, op, rng
+
+
+@pytest.mark.parametrize("dense,neumann", [(False, False), (True, False), (False, True)])
+def test_adjoint_dot_product(oracle_lib, dense, neumann):
+    """<lam, T psi> = <T^T lam, psi> for the homogeneous step (no source, vacuum)."""
+    o = oracle_lib
+    omega, w = I.product_quadrature(4, 4)
+    K = I.henyey_greenstein_kernel(omega, w, 0.6) if dense else None
+    m, omega, w, op, rng = _random_linear_problem(o, K=K, neumann=neumann)
+    nc, nq = m.ncells, w.size
+    psi = rng.standard_normal((nc, nq))
+    lam = rng.standard_normal((nc, nq))
+    dt, at, as_ = 0.003, 1.3, 0.7
+    lhs = np.sum(lam * o.step(op, psi, dt, at, as_))
+    rhs = np.sum(o.adjoint_step(op, psi, lam, dt, at, as_) * psi)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-13)
+
+
+def _objective_fd(o, op, psi0, dt, nsteps, weights, attr, cell, h):
+    vals = []
+    for sgn in (+1, -1):
+        arr = getattr(op, attr).copy()
+        arr[cell] += sgn * h
+        opp = op.replace(**{attr: arr})
+        psiN, _, _ = o.rollout(opp, psi0, dt, nsteps)
+        vals.append(np.sum(weights * psiN))
+    return (vals[0] - vals[1]) / (2 * h)
+
+
+@pytest.mark.parametrize("dense", [False, True])
+def test_adjoint_gradient_central_fd(oracle_lib, dense):
+    """Gradients of J = sum_{i in R} A_i sum_q w_q psi^N_iq w.r.t. sigma_t, sigma_s, rho
+    agree with FP64 central differences."""
+    o = oracle_lib
+    omega, w = I.product_quadrature(4, 4)
+    K = I.henyey_greenstein_kernel(omega, w, 0.6) if dense else None
+    m, omega, w, op, rng = _random_linear_problem(o, K=K)
+    nc, nq = m.ncells, w.size
+    op = op.replace(source=rng.uniform(0, 1, nc), inflow=rng.uniform(0, 1, (m.nbfaces, nq)))
+    psi0 = rng.uniform(0, 1, (nc, nq))
+    dt = I.cfl_dt(m, omega, 0.4, op.rho)
+    nsteps = 12
+    region = I.region_mask(m, (0.5, 1.0, 0.0, 0.5))
+    weights = (region * m.area)[:, None] * w[None, :]
+    g = o.rollout_gradient(op, psi0, dt, nsteps, dJ_dpsiN=weights)
+    cells = rng.choice(nc, 6, replace=False)
+    for attr in ("sigma_t", "sigma_s", "rho"):
+        for c in cells:
+            h = 1e-5 * max(abs(getattr(op, attr)[c]), 1.0)
+            fd = _objective_fd(o, op, psi0, dt, nsteps, weights, attr, c, h)
+            # FD round-off is ~eps*|J|/h; tiny gradients are checked against that floor
+            np.testing.assert_allclose(g[attr][c], fd, rtol=2e-7,
+                                       atol=1e-7 * np.max(np.abs(g[attr])))
+    # initial-state gradient: J is linear in psi0
+    d = rng.standard_normal((nc, nq))
+    J = lambda p: np.sum(weights * o.rollout(op, p, dt, nsteps)[0])
+    np.testing.assert_allclose(J(psi0 + d) - J(psi0), np.sum(g["psi0"] * d), rtol=1e-10)
+
+
+def test_dose_gradient_central_fd(oracle_lib):
+    """Dose functional J = sum_T A D - sum_O A D with per-step coefficients and varying
+    alpha: gradients w.r.t. rho (streaming + explicit 1/rho) agree with central FD."""
+    o = oracle_lib
+    m = I.jittered_delaunay_mesh(9, 0.0, 1.0, seed=21)
+    omega, w = I.product_quadrature(4, 4)
+    K = I.henyey_greenstein_kernel(omega, w, 0.7)
+    nc, nq = m.ncells, w.size
+    rng = np.random.default_rng(21)
+    rho = rng.uniform(0.3, 2.0, nc)
+    top = np.abs(m.bface_mid[:, 1] - 1.0) < 1e-12
+    inflow = np.where(top[:, None], 1.0, 0.0) * np.exp(-(omega[:, 1] + 1) ** 2)[None, :]
+    op = _op_from_mesh(o, m, omega, w, sigma_t=np.ones(nc), sigma_s=np.ones(nc), K=K, rho=rho,
+                       inflow=np.ascontiguousarray(inflow))
+    nsteps = 15
+    dt = I.cfl_dt(m, omega, 0.5, rho)
+    at = np.linspace(1.0, 1.4, nsteps)
+    isc = np.linspace(2.0, 1.0, nsteps)
+    coeff = dt * np.linspace(1.0, 3.0, nsteps)
+    T = I.region_mask(m, (0.3, 0.7, 0.3, 0.7))
+    O = I.region_mask(m, (0.0, 0.3, 0.0, 0.3))
+    dJdD = m.area * (T.astype(float) - O.astype(float))
+
+    def J(opp):
+        _, dose, _ = o.rollout(opp, np.zeros((nc, nq)), dt, nsteps, alpha_t=at, alpha_s=at,
+                               inflow_scale=isc, dose_coeff=coeff)
+        return np.sum(dJdD * dose)
+
+    g = o.rollout_gradient(op, np.zeros((nc, nq)), dt, nsteps, dJ_ddose=dJdD, alpha_t=at,
+                           alpha_s=at, inflow_scale=isc, dose_coeff=coeff)
+    for c in rng.choice(nc, 6, replace=False):
+        h = 1e-6 * rho[c]
+        r = rho.copy(); r[c] += h
+        jp = J(op.replace(rho=r))
+        r[c] -= 2 * h
+        jm = J(op.replace(rho=r))
+        np.testing.assert_allclose(g["rho"][c], (jp - jm) / (2 * h), rtol=1e-6,
+                                   atol=1e-7 * np.max(np.abs(g["rho"])))
