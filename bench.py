@@ -1,0 +1,158 @@
+"""Throughput of the explicit S_N step on one MI355X.
+
+Workload (default): the FP32 isotropic checkerboard -- seeded Delaunay mesh of 316 x 316
+jittered points on [0, 7]^2 (198 450 triangles), 16 x 16 product quadrature (256 ordinates),
+absorbers sigma_t = 10 in a checker pattern, source q = 1 in the centre square, vacuum
+boundary, explicit Euler at CFL 0.5.  A step is one call of the library's step (upwind
+flux over every face and ordinate, isotropic scattering, absorption, source) on states
+resident in HBM.
+
+Prints one JSON line: cell-ordinate updates/s over the timed steps, the roofline of the step
+kernel (algorithmic bytes / measured kernel time vs 8 TB/s), and the FP64 oracle timed on
+the host cores over a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--graph] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cell-ordinate updates/s per S_N step (FP32 vs mixed) + adjoint/forward ratio"
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, vendor figure
+WORKLOAD = "checkerboard_s16"
+STEP_SOURCE = os.path.join(ROOT, "paper_2205_08417_amd", "csrc", "sn_step.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sn_step_checkerboard_s16_traffic.json")
+
+
+def kernel_source_sha() -> str:
+    return hashlib.sha256(open(STEP_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they were taken on
+    the current step kernel source (else None)."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(P, budget_s: float = 12.0):
+    """Oracle (FP64, OpenMP over cells) on the same mesh and quadrature: as many steps from
+    the workload's initial state as fit the time budget (at least 2)."""
+    from oracle import oracle as o
+    op = o.OracleProblem.from_problem(P)
+    psi = P.psi0
+    t0 = time.perf_counter()
+    psi = o.step(op, psi, P.dt)
+    t1 = time.perf_counter() - t0
+    n = max(2, min(60, int(budget_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    for _ in range(n):
+        psi = o.step(op, psi, P.dt)
+    el = time.perf_counter() - t0
+    return {"value": P.ncells * P.nq * n / el, "unit": "cell-ordinate updates/s",
+            "cores": o.num_threads(), "kind": "oracle",
+            "sample": f"{n} FP64 oracle steps of the full {WORKLOAD} workload "
+                      f"({P.ncells} cells x {P.nq} ordinates), {el:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the timed steps from a captured HIP graph")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the S_N step library runs on a single device "
+              "(a spatial decomposition across GPUs is described in the design notes but not "
+              "built). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2205_08417_amd import inputs as I
+    from paper_2205_08417_amd.solver import Solver
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    P = I.build(WORKLOAD)
+    S = Solver(P)
+    a = S.initial_state()
+    b = torch.empty_like(a)
+    step_args = S.args()
+    print(f"# {WORKLOAD}: {P.ncells} cells x {P.nq} ordinates, dt={P.dt:.4e}", file=sys.stderr,
+          flush=True)
+
+    def run(n, x, y):
+        for _ in range(n):
+            S.step(x, y, step_args)
+            x, y = y, x
+        return x, y
+
+    stream = torch.cuda.current_stream()
+    a, b = run(args.warmup, a, b)
+    torch.cuda.synchronize()
+    K = args.steps
+    if args.graph:
+        K = 2 * ((K + 1) // 2)                      # pairs keep the ping-pong order fixed
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            run(2, a, b)
+        g.replay()
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(K // 2):
+            g.replay()
+        end.record(stream)
+    else:
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        a, b = run(K, a, b)
+        end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    ms_step = ms / K
+    updates = P.ncells * P.nq
+    value = updates * K / (ms * 1e-3)
+
+    alg_bytes = P.ncells * (8 * P.nq + 64)          # 8 B per update + 64 B per cell record
+    achieved = alg_bytes / (ms_step * 1e-3) / 1e9
+    traffic = measured_traffic()
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-ordinate updates/s", "n_gpus": 1,
+        "steps": K, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "cells": P.ncells, "ordinates": P.nq,
+                   "scattering": "isotropic", "precision": "fp32", "mesh": "seeded jittered "
+                   "Delaunay 316x316 points on [0,7]^2", "graph": bool(args.graph)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_step<4,true,false,float>",
+                     "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(P)
+    S.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

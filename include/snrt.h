@@ -1,0 +1,222 @@
+/*
+ * snrt.h -- C ABI of libsnrt, the MI355X (gfx950) explicit S_N step library.
+ *
+ * The library advances the discrete-ordinates equations of KiT-RT (arXiv 2205.08417)
+ *
+ *     d_t psi_q + Omega_q . grad(psi_q / rho) + alpha_t Sigma_t psi_q
+ *         = alpha_s Sigma_s sum_p w_p k(Omega_q . Omega_p) psi_p + q          (eq. SNEqns,
+ *                                                                   eq. BoltzmannCSDTrafo)
+ *
+ * on an unstructured cell-centred 2-D grid (Sec. 4.1) by one explicit Euler step with the
+ * first-order upwind numerical flux (Sec. 4.2, eq. upwind1stOrder2):
+ *
+ *     psi'_iq = psi_iq - dt/A_i sum_f s_ifq u_up(f,q)
+ *               + dt ( -alpha_t sigma_t,i psi_iq + alpha_s sigma_s,i S_iq + q_i ),
+ *     s_ifq = Omega_q,x n_if,x + Omega_q,y n_if,y,   u = psi / rho,
+ *     u_up = u_i if s_ifq > 0, else the neighbour's u (or the boundary ghost),
+ *     S_iq = sum_p K[q][p] w_p psi_ip   (isotropic: K = 1/(4 pi)).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns snrt_status; it never aborts and never throws.  On failure
+ *     snrt_last_error() describes the cause (thread-local, valid until the next call on the
+ *     same thread).
+ *   - Setup calls (snrt_*_create) take HOST FP64 arrays, copy them, and return a handle
+ *     owned by the library (free it with the matching *_destroy).  The handle lives on the
+ *     HIP device that was current at creation; later calls must run with that device current.
+ *   - Per-step calls take DEVICE pointers owned by the caller and a HIP stream (hipStream_t
+ *     passed as void*; NULL = the null stream).  They only enqueue work: no host
+ *     synchronisation, no allocation.
+ *   - psi-like arrays are [ncells][nq] row-major, ordinates fastest, with cells in the
+ *     handle's INTERNAL order (a space-filling-curve renumbering chosen at mesh creation;
+ *     snrt_permute converts between user and internal order).  Per-cell arrays ([ncells])
+ *     are in internal order too.  Boundary-face arrays ([nbfaces][nq]) keep the user's
+ *     boundary-face numbering.
+ *   - Outputs never alias inputs (SNRT_E_ALIAS).
+ *   - Calls that share a handle's internal scratch (snrt_mass) must not overlap in time on
+ *     different streams.
+ */
+#ifndef SNRT_H
+#define SNRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SNRT_ABI_VERSION 1
+
+typedef enum {
+    SNRT_OK = 0,
+    SNRT_E_ARG = -1,          /* null / out-of-range argument */
+    SNRT_E_SHAPE = -2,        /* sizes disagree between handles or with the arrays */
+    SNRT_E_ALIAS = -3,        /* an output aliases an input */
+    SNRT_E_UNSUPPORTED = -4,  /* valid request this build does not implement */
+    SNRT_E_HIP = -5,          /* HIP runtime error (text in snrt_last_error) */
+    SNRT_E_OOM = -6,          /* device allocation failed */
+    SNRT_E_NONFINITE = -7     /* NaN/Inf in a scalar argument */
+} snrt_status;
+
+typedef enum {
+    SNRT_FP32 = 0,    /* dense scattering product in FP32 */
+    SNRT_BF16X3 = 1,  /* BF16 MFMA, hi+lo split of both operands, three products, FP32 accumulate */
+    SNRT_BF16X1 = 2   /* BF16 MFMA, single product (fast, ~1e-3 relative) */
+} snrt_precision;
+
+/* mesh flags */
+#define SNRT_REORDER_HILBERT 0u  /* renumber cells along a Hilbert curve of the centroids */
+#define SNRT_NO_REORDER      1u  /* keep the user's numbering (internal == user order) */
+
+/* boundary treatment of step arguments */
+#define SNRT_BC_DIRICHLET 0      /* ghost u = inflow[b][q] * inflow_scale; vacuum if inflow NULL */
+#define SNRT_BC_NEUMANN   1      /* ghost u = the cell's own u */
+
+#define SNRT_MAX_NQ 1024         /* ordinates per cell supported by the kernels */
+
+typedef struct snrt_mesh snrt_mesh;
+typedef struct snrt_quad snrt_quad;
+typedef struct snrt_scatter snrt_scatter;
+
+int snrt_abi_version(void);
+const char* snrt_last_error(void);
+
+/* ---------------------------------------------------------------- setup (host FP64 input) */
+
+/* Unstructured grid of Sec. 4.1.  Cell i holds max_faces (3 = triangles, 4 = quadrilaterals)
+ * face slots:
+ *   face_nbr[i*max_faces+f]         >= 0 neighbour cell (user numbering), -1-b boundary face b
+ *                                   (0 <= b < nbfaces), INT32_MIN for an unused slot
+ *   face_normal[(i*max_faces+f)*2]  n_ij: outward unit normal times face length
+ *   area[i]                         A_i > 0
+ *   centroid[i*2]                   used only for the renumbering (may be NULL with
+ *                                   SNRT_NO_REORDER)
+ * Adjacency must be symmetric.  Returns SNRT_E_ARG for malformed connectivity or areas. */
+snrt_status snrt_mesh_create(snrt_mesh** out, int64_t ncells, int32_t max_faces,
+                             const int32_t* face_nbr, const double* face_normal,
+                             const double* area, const double* centroid, int64_t nbfaces,
+                             uint32_t flags);
+/* internal_to_user[k] = user index of internal cell k (host array of ncells). */
+snrt_status snrt_mesh_permutation(const snrt_mesh* mesh, int64_t* internal_to_user);
+snrt_status snrt_mesh_info(const snrt_mesh* mesh, int64_t* ncells, int64_t* nbfaces,
+                           int32_t* max_faces);
+void snrt_mesh_destroy(snrt_mesh* mesh);
+
+/* Ordinate set (Sec. 3.2): omega[q*3] unit directions (x, y, z), w[q] > 0 weights.
+ * 1 <= nq <= SNRT_MAX_NQ.  The streaming uses (x, y); dense kernels use the full vector. */
+snrt_status snrt_quad_create(snrt_quad** out, int32_t nq, const double* omega, const double* w);
+void snrt_quad_destroy(snrt_quad* quad);
+
+/* Scattering operator S_q = sum_p K[q][p] w_p psi_p of eq. SNEqns.
+ * snrt_scatter_isotropic: K = 1/(4 pi) (Sigma_t = Sigma_{s,0} convention of Sec. 2), reduced
+ *   per cell without forming K.
+ * snrt_scatter_dense: K host [nq*nq] row-major (K[q*nq+p]), applied as a GEMM
+ *   S = Psi B with B[p][q] = w_p K[q][p], at the given precision.  BF16 modes need
+ *   nq % 64 == 0. */
+snrt_status snrt_scatter_isotropic(snrt_scatter** out, const snrt_quad* quad);
+snrt_status snrt_scatter_dense(snrt_scatter** out, const snrt_quad* quad, const double* K,
+                               snrt_precision precision);
+void snrt_scatter_destroy(snrt_scatter* scatter);
+
+/* Bytes of device workspace snrt_step / snrt_step_adjoint need for this combination
+ * (0 for isotropic scattering; one [ncells][nq] FP32 buffer for dense scattering). */
+snrt_status snrt_workspace_size(const snrt_mesh* mesh, const snrt_quad* quad,
+                                const snrt_scatter* scatter, size_t* bytes);
+
+/* ---------------------------------------------------------------- per step (device input) */
+
+/* Materials and step scalars.  Device arrays of ncells in internal order unless noted.
+ *   sigma_t, sigma_s   required
+ *   inv_rho            1/rho (eq. BoltzmannCSDTrafo), NULL means rho = 1
+ *   source             isotropic source q_i added as dt*q_i to every ordinate, NULL = 0
+ *   inflow             [nbfaces][nq] ghost u = psi/rho on boundary faces (Dirichlet), scaled
+ *                      by inflow_scale; NULL = vacuum.  Ignored for SNRT_BC_NEUMANN.
+ *   dt                 step; alpha_t, alpha_s multiply sigma_t, sigma_s (1 for time
+ *                      problems; energy dependence of CSD cross sections otherwise). */
+typedef struct {
+    const float* sigma_t;
+    const float* sigma_s;
+    const float* inv_rho;
+    const float* source;
+    const float* inflow;
+    double inflow_scale;
+    double dt;
+    double alpha_t;
+    double alpha_s;
+    int32_t boundary;     /* SNRT_BC_* */
+} snrt_step_args;
+
+typedef struct {
+    const double* sigma_t;
+    const double* sigma_s;
+    const double* inv_rho;
+    const double* source;
+    const double* inflow;
+    double inflow_scale;
+    double dt;
+    double alpha_t;
+    double alpha_s;
+    int32_t boundary;
+} snrt_step_args_f64;
+
+/* One explicit Euler S_N step, FP32: psi_out = step(psi_in).  ws: device workspace of at
+ * least snrt_workspace_size bytes (may be NULL when that size is 0). */
+snrt_status snrt_step(const snrt_mesh* mesh, const snrt_quad* quad, const snrt_scatter* scatter,
+                      const snrt_step_args* args, const float* psi_in, float* psi_out,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* The same step in FP64 throughout (parity template of the FP32 kernels).  Dense scattering
+ * runs as an FP64 product regardless of the scatter handle's precision. */
+snrt_status snrt_step_f64(const snrt_mesh* mesh, const snrt_quad* quad,
+                          const snrt_scatter* scatter, const snrt_step_args_f64* args,
+                          const double* psi_in, double* psi_out, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* Adjoint of snrt_step (exact transpose of its linear part, psi' = T psi + b):
+ *     lam_n = T^T lam_np1,
+ * and the step's gradient contributions, ADDED to each non-NULL output ([ncells], FP32):
+ *     g_sigma_t[c] += -dt alpha_t sum_q lam_np1[c][q] psi_n[c][q]
+ *     g_sigma_s[c] += dt alpha_s sum_q lam_np1[c][q] S_n[c][q]
+ *     g_rho[c]     += sum_q lam_np1 . d psi'/d rho_c   (needs args->inv_rho)
+ * psi_n is the state the forward step was applied to.  args->source/inflow do not enter.
+ * ws as for snrt_step. */
+snrt_status snrt_step_adjoint(const snrt_mesh* mesh, const snrt_quad* quad,
+                              const snrt_scatter* scatter, const snrt_step_args* args,
+                              const float* psi_n, const float* lam_np1, float* lam_n,
+                              float* g_sigma_t, float* g_sigma_s, float* g_rho, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* FP64 adjoint (parity template). */
+snrt_status snrt_step_adjoint_f64(const snrt_mesh* mesh, const snrt_quad* quad,
+                                  const snrt_scatter* scatter, const snrt_step_args_f64* args,
+                                  const double* psi_n, const double* lam_np1, double* lam_n,
+                                  double* g_sigma_t, double* g_sigma_s, double* g_rho,
+                                  void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- reductions */
+
+/* Total mass sum_i A_i sum_q w_q psi_iq accumulated in FP64 (solver log, Sec. 5.1), written
+ * to out_dev (one device double).  Deterministic two-pass tree. */
+snrt_status snrt_mass(const snrt_mesh* mesh, const snrt_quad* quad, const float* psi,
+                      double* out_dev, void* stream);
+
+/* Scalar flux phi_i = sum_q w_q psi_iq (Sec. 7.2), FP64 accumulation rounded to FP32. */
+snrt_status snrt_scalar_flux(const snrt_mesh* mesh, const snrt_quad* quad, const float* psi,
+                             float* phi, void* stream);
+
+/* Dose term (Sec. 2, integral in pseudo-time, left endpoint):
+ *     dose[i] += coeff * inv_rho[i] * sum_q w_q psi_iq      (FP64, inv_rho NULL = 1). */
+snrt_status snrt_dose_accumulate(const snrt_mesh* mesh, const snrt_quad* quad, const float* psi,
+                                 const float* inv_rho, double coeff, double* dose,
+                                 void* stream);
+
+/* Row permutation between user (direction 0 -> internal) and internal (direction 1 -> user)
+ * cell order for [ncells][row_bytes] device arrays; row_bytes a positive multiple of 4. */
+snrt_status snrt_permute(const snrt_mesh* mesh, int32_t to_user, const void* in, void* out,
+                         int64_t row_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNRT_H */

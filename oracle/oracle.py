@@ -43,6 +43,7 @@ def lib():
             build_oracle()
         L = ctypes.CDLL(_LIB)
         L.oracle_version.restype = ctypes.c_int
+        L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_step.restype = ctypes.c_int
         L.oracle_step.argtypes = [ctypes.c_int64, ctypes.c_int32, _ip, _dp, _dp, ctypes.c_int32,
                                   _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_double,
@@ -229,6 +230,11 @@ def rollout_gradient(op: OracleProblem, psi0, dt: float, nsteps: int,
     if g_r is not None and dJ_ddose is not None and dose is not None:
         g_r += -dose / rho * dJ_ddose
     return {"psi0": lam, "sigma_t": g_t, "sigma_s": g_s, "rho": g_r, "dose": dose}
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().oracle_num_threads())
 
 
 def rel_l2(x, ref) -> float:

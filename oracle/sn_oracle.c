@@ -43,6 +43,20 @@ static const double oracle_pi = 3.14159265358979323846264338327950288;
 
 int oracle_version(void) { return 1; }
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads a parallel region of this library uses (reported beside CPU timings). */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* Scattering source of cell c at ordinate q: sum_p k(Omega_q.Omega_p) w_p psi_cp (eq. SNEqns). */
 static double scatter_source(int32_t nq, const double* w, const double* K, const double* psi_c, int32_t q)
 {
@@ -68,40 +82,58 @@ int oracle_step(int64_t nc, int32_t mf, const int32_t* face_nbr, const double* f
         !sigma_t || !sigma_s || !psi_in || !psi_out)
         return -1;
     int64_t count = sel ? nsel : nc;
-#pragma omp parallel for schedule(static)
-    for (int64_t k = 0; k < count; ++k) {
-        int64_t i = sel ? sel[k] : k;
-        const double* psi_i = psi_in + (size_t)i * nq;
-        double rho_i = rho ? rho[i] : 1.0;
-        double* out = psi_out + (size_t)k * nq;
-        for (int32_t q = 0; q < nq; ++q) {
-            /* numerical flux sum over the faces of cell i (eq. upwind1stOrder2) */
-            double flux = 0.0;
-            for (int32_t f = 0; f < mf; ++f) {
-                int32_t j = face_nbr[(size_t)i * mf + f];
-                if (j == ORACLE_UNUSED_FACE) continue;
-                const double* n = face_normal + ((size_t)i * mf + f) * 2;
-                double s = omega[(size_t)q * 3 + 0] * n[0] + omega[(size_t)q * 3 + 1] * n[1];
-                double u_i = psi_i[q] / rho_i;
-                double u_j;
-                if (j >= 0) {
-                    u_j = psi_in[(size_t)j * nq + q] / (rho ? rho[j] : 1.0);
-                } else if (neumann) {
-                    u_j = u_i;
-                } else {
-                    int64_t b = -1 - (int64_t)j;
-                    u_j = inflow ? inflow[(size_t)b * nq + q] * inflow_scale : 0.0;
-                }
-                double H = s > 0.0 ? 1.0 : 0.0;
-                flux += s * u_i * H + s * u_j * (1.0 - H);
-            }
-            /* right-hand side: absorption/total, scattering, source */
-            double R = -alpha_t * sigma_t[i] * psi_i[q]
-                       + alpha_s * sigma_s[i] * scatter_source(nq, w, K, psi_i, q)
-                       + (source ? source[i] : 0.0);
-            out[q] = psi_i[q] - dt / area[i] * flux + dt * R;
+    int failed = 0;
+#pragma omp parallel
+    {
+        /* scattering source of the current cell, all ordinates (eq. SNEqns) */
+        double* S = (double*)malloc(sizeof(double) * (size_t)nq);
+        if (!S) {
+#pragma omp atomic write
+            failed = 1;
         }
+#pragma omp for schedule(static)
+        for (int64_t k = 0; k < count; ++k) {
+            if (!S) continue;
+            int64_t i = sel ? sel[k] : k;
+            const double* psi_i = psi_in + (size_t)i * nq;
+            double rho_i = rho ? rho[i] : 1.0;
+            double* out = psi_out + (size_t)k * nq;
+            if (K == NULL) {
+                double iso = scatter_source(nq, w, NULL, psi_i, 0);
+                for (int32_t q = 0; q < nq; ++q) S[q] = iso;
+            } else {
+                for (int32_t q = 0; q < nq; ++q) S[q] = scatter_source(nq, w, K, psi_i, q);
+            }
+            for (int32_t q = 0; q < nq; ++q) {
+                /* numerical flux sum over the faces of cell i (eq. upwind1stOrder2) */
+                double flux = 0.0;
+                for (int32_t f = 0; f < mf; ++f) {
+                    int32_t j = face_nbr[(size_t)i * mf + f];
+                    if (j == ORACLE_UNUSED_FACE) continue;
+                    const double* n = face_normal + ((size_t)i * mf + f) * 2;
+                    double s = omega[(size_t)q * 3 + 0] * n[0] + omega[(size_t)q * 3 + 1] * n[1];
+                    double u_i = psi_i[q] / rho_i;
+                    double u_j;
+                    if (j >= 0) {
+                        u_j = psi_in[(size_t)j * nq + q] / (rho ? rho[j] : 1.0);
+                    } else if (neumann) {
+                        u_j = u_i;
+                    } else {
+                        int64_t b = -1 - (int64_t)j;
+                        u_j = inflow ? inflow[(size_t)b * nq + q] * inflow_scale : 0.0;
+                    }
+                    double H = s > 0.0 ? 1.0 : 0.0;
+                    flux += s * u_i * H + s * u_j * (1.0 - H);
+                }
+                /* right-hand side: absorption/total, scattering, source */
+                double R = -alpha_t * sigma_t[i] * psi_i[q] + alpha_s * sigma_s[i] * S[q]
+                           + (source ? source[i] : 0.0);
+                out[q] = psi_i[q] - dt / area[i] * flux + dt * R;
+            }
+        }
+        free(S);
     }
+    if (failed) return -2;
     return 0;
 }
 
@@ -172,6 +204,7 @@ int oracle_adjoint_step(int64_t nc, int32_t mf, const int32_t* face_nbr, const d
         const double* psi_i = psi_n + (size_t)i * nq;
         double* out = lam_n + (size_t)i * nq;
         double gt = 0.0, gs = 0.0;
+        double iso = K ? 0.0 : scatter_source(nq, w, NULL, psi_i, 0);
         for (int32_t q = 0; q < nq; ++q) {
             out[q] += (1.0 - dt * alpha_t * sigma_t[i]) * l[q];
             double c = dt * alpha_s * sigma_s[i];
@@ -180,7 +213,8 @@ int oracle_adjoint_step(int64_t nc, int32_t mf, const int32_t* face_nbr, const d
                 out[p] += c * kqp * w[p] * l[q];
             }
             gt += -dt * alpha_t * psi_i[q] * l[q];
-            gs += dt * alpha_s * scatter_source(nq, w, K, psi_i, q) * l[q];
+            double S_q = K ? scatter_source(nq, w, K, psi_i, q) : iso;
+            gs += dt * alpha_s * S_q * l[q];
         }
         if (g_sigma_t) g_sigma_t[i] += gt;
         if (g_sigma_s) g_sigma_s[i] += gs;

@@ -1,0 +1,639 @@
+// C ABI of libsnrt: argument validation, handle lifetime, mesh renumbering and launches.
+// Declarations and the meaning of every argument are in include/snrt.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "snrt_internal.h"
+
+namespace snrt {
+
+namespace {
+thread_local std::string g_last_error;
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+template <typename T>
+snrt_status dev_alloc(T** p, size_t count, const char* what) {
+    *p = nullptr;
+    if (count == 0) return SNRT_OK;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        set_error(std::string("device allocation failed for ") + what + ": " +
+                  hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? SNRT_E_OOM : SNRT_E_HIP;
+    }
+    return SNRT_OK;
+}
+
+template <typename T>
+snrt_status upload(T* dst, const T* src, size_t count, const char* what) {
+    if (count == 0) return SNRT_OK;
+    hipError_t e = hipMemcpy(dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, what);
+}
+
+void dev_free(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+snrt_status check_device(int dev, const char* what) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, what);
+    if (cur != dev) {
+        set_error(std::string(what) + ": handle belongs to device " + std::to_string(dev) +
+                  " but device " + std::to_string(cur) + " is current");
+        return SNRT_E_ARG;
+    }
+    return SNRT_OK;
+}
+
+// Hilbert index of (x, y) on a 2^16 x 2^16 grid (the standard quadrant-rotation recursion).
+uint64_t hilbert_index(uint32_t x, uint32_t y) {
+    const uint32_t n = 1u << 16;
+    uint64_t d = 0;
+    for (uint32_t s = n >> 1; s > 0; s >>= 1) {
+        const uint32_t rx = (x & s) ? 1u : 0u;
+        const uint32_t ry = (y & s) ? 1u : 0u;
+        d += (uint64_t)s * s * ((3u * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = n - 1 - x;
+                y = n - 1 - y;
+            }
+            std::swap(x, y);
+        }
+    }
+    return d;
+}
+
+bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
+    const auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return pa < pb + bbytes && pb < pa + abytes;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+snrt_status hip_fail(hipError_t e, const char* what) {
+    set_error(std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+    return SNRT_E_HIP;
+}
+
+}  // namespace snrt
+
+using namespace snrt;
+
+#define SNRT_REQUIRE(cond, code, msg) \
+    do {                              \
+        if (!(cond)) {                \
+            set_error(msg);           \
+            return code;              \
+        }                             \
+    } while (0)
+
+#define SNRT_TRY(expr)                       \
+    do {                                     \
+        snrt_status _s = (expr);             \
+        if (_s != SNRT_OK) return _s;        \
+    } while (0)
+
+extern "C" {
+
+int snrt_abi_version(void) { return SNRT_ABI_VERSION; }
+
+const char* snrt_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------------------------------------- mesh
+
+void snrt_mesh_destroy(snrt_mesh* m) {
+    if (!m) return;
+    dev_free(m->geom32);
+    dev_free(m->geom64);
+    dev_free(m->d_to_user);
+    dev_free(m->d_partial);
+    delete m;
+}
+
+snrt_status snrt_mesh_create(snrt_mesh** out, int64_t nc, int32_t mf, const int32_t* face_nbr,
+                             const double* face_normal, const double* area,
+                             const double* centroid, int64_t nbf, uint32_t flags) {
+    g_last_error.clear();
+    SNRT_REQUIRE(out, SNRT_E_ARG, "snrt_mesh_create: out is NULL");
+    *out = nullptr;
+    SNRT_REQUIRE(nc >= 0 && nc < (int64_t)INT32_MAX, SNRT_E_ARG,
+                 "snrt_mesh_create: ncells out of range");
+    SNRT_REQUIRE(mf == 3 || mf == 4, SNRT_E_UNSUPPORTED, "snrt_mesh_create: max_faces must be 3 or 4");
+    SNRT_REQUIRE(nbf >= 0 && nbf < (int64_t)INT32_MAX, SNRT_E_ARG,
+                 "snrt_mesh_create: nbfaces out of range");
+    SNRT_REQUIRE(flags == SNRT_REORDER_HILBERT || flags == SNRT_NO_REORDER, SNRT_E_ARG,
+                 "snrt_mesh_create: unknown flags");
+    SNRT_REQUIRE(nc == 0 || (face_nbr && face_normal && area), SNRT_E_ARG,
+                 "snrt_mesh_create: NULL mesh array");
+    const bool reorder = flags == SNRT_REORDER_HILBERT;
+    SNRT_REQUIRE(nc == 0 || !reorder || centroid, SNRT_E_ARG,
+                 "snrt_mesh_create: centroids are needed for the Hilbert renumbering");
+
+    // connectivity and geometry checks
+    for (int64_t i = 0; i < nc; ++i) {
+        SNRT_REQUIRE(is_finite(area[i]) && area[i] > 0.0, SNRT_E_ARG,
+                     "snrt_mesh_create: non-positive or non-finite area at cell " + std::to_string(i));
+        int used = 0;
+        for (int f = 0; f < mf; ++f) {
+            const int32_t j = face_nbr[i * mf + f];
+            if (j == kUnusedFace) continue;
+            ++used;
+            const double nx = face_normal[(i * mf + f) * 2], ny = face_normal[(i * mf + f) * 2 + 1];
+            SNRT_REQUIRE(is_finite(nx) && is_finite(ny), SNRT_E_ARG,
+                         "snrt_mesh_create: non-finite face normal at cell " + std::to_string(i));
+            if (j >= 0) {
+                SNRT_REQUIRE(j < nc && j != i, SNRT_E_ARG,
+                             "snrt_mesh_create: bad neighbour index at cell " + std::to_string(i));
+                bool back = false;
+                for (int g = 0; g < mf; ++g) back |= face_nbr[(int64_t)j * mf + g] == (int32_t)i;
+                SNRT_REQUIRE(back, SNRT_E_ARG,
+                             "snrt_mesh_create: adjacency not symmetric at cell " + std::to_string(i));
+            } else {
+                const int64_t b = -1 - (int64_t)j;
+                SNRT_REQUIRE(b < nbf, SNRT_E_ARG,
+                             "snrt_mesh_create: boundary face id >= nbfaces at cell " + std::to_string(i));
+            }
+        }
+        SNRT_REQUIRE(used >= 1, SNRT_E_ARG, "snrt_mesh_create: cell without faces");
+    }
+
+    // internal order: Hilbert curve through the centroids' bounding box
+    std::vector<int64_t> to_user(nc);
+    std::iota(to_user.begin(), to_user.end(), 0);
+    if (reorder && nc > 1) {
+        double x0 = centroid[0], x1 = centroid[0], y0 = centroid[1], y1 = centroid[1];
+        for (int64_t i = 0; i < nc; ++i) {
+            SNRT_REQUIRE(is_finite(centroid[2 * i]) && is_finite(centroid[2 * i + 1]), SNRT_E_ARG,
+                         "snrt_mesh_create: non-finite centroid");
+            x0 = std::min(x0, centroid[2 * i]);
+            x1 = std::max(x1, centroid[2 * i]);
+            y0 = std::min(y0, centroid[2 * i + 1]);
+            y1 = std::max(y1, centroid[2 * i + 1]);
+        }
+        const double span = std::max(std::max(x1 - x0, y1 - y0), 1e-300);
+        std::vector<uint64_t> key(nc);
+        for (int64_t i = 0; i < nc; ++i) {
+            const double fx = (centroid[2 * i] - x0) / span, fy = (centroid[2 * i + 1] - y0) / span;
+            const uint32_t ix = (uint32_t)std::min(65535.0, std::floor(fx * 65536.0));
+            const uint32_t iy = (uint32_t)std::min(65535.0, std::floor(fy * 65536.0));
+            key[i] = hilbert_index(ix, iy);
+        }
+        std::stable_sort(to_user.begin(), to_user.end(),
+                         [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+    }
+    std::vector<int64_t> to_int(nc);
+    for (int64_t k = 0; k < nc; ++k) to_int[to_user[k]] = k;
+
+    std::vector<CellGeom32> g32(nc);
+    std::vector<CellGeom64> g64(nc);
+    for (int64_t k = 0; k < nc; ++k) {
+        const int64_t i = to_user[k];
+        CellGeom32& a = g32[k];
+        CellGeom64& b = g64[k];
+        std::memset(&a, 0, sizeof(a));
+        std::memset(&b, 0, sizeof(b));
+        for (int f = 0; f < 4; ++f) {
+            int32_t j = f < mf ? face_nbr[i * mf + f] : kUnusedFace;
+            if (j >= 0) j = (int32_t)to_int[j];
+            a.nbr[f] = b.nbr[f] = j;
+            if (f < mf && j != kUnusedFace) {
+                b.n[f][0] = face_normal[(i * mf + f) * 2];
+                b.n[f][1] = face_normal[(i * mf + f) * 2 + 1];
+                a.n[f][0] = (float)b.n[f][0];
+                a.n[f][1] = (float)b.n[f][1];
+            }
+        }
+        b.area = area[i];
+        b.inv_area = 1.0 / area[i];
+        a.area = (float)area[i];
+        a.inv_area = (float)(1.0 / area[i]);
+    }
+
+    snrt_mesh* m = new snrt_mesh();
+    hipError_t e = hipGetDevice(&m->device);
+    if (e != hipSuccess) {
+        delete m;
+        return hip_fail(e, "snrt_mesh_create: hipGetDevice");
+    }
+    m->nc = nc;
+    m->nbf = nbf;
+    m->mf = mf;
+    m->to_user = std::move(to_user);
+    m->n_partial = (nc + kCellsPerBlock - 1) / kCellsPerBlock;
+    snrt_status s = SNRT_OK;
+    if ((s = dev_alloc(&m->geom32, nc, "geometry")) != SNRT_OK ||
+        (s = dev_alloc(&m->geom64, nc, "geometry")) != SNRT_OK ||
+        (s = dev_alloc(&m->d_to_user, nc, "permutation")) != SNRT_OK ||
+        (s = dev_alloc(&m->d_partial, std::max<int64_t>(m->n_partial, 1), "partials")) != SNRT_OK ||
+        (s = upload(m->geom32, g32.data(), nc, "snrt_mesh_create: upload")) != SNRT_OK ||
+        (s = upload(m->geom64, g64.data(), nc, "snrt_mesh_create: upload")) != SNRT_OK ||
+        (s = upload(m->d_to_user, m->to_user.data(), nc, "snrt_mesh_create: upload")) != SNRT_OK) {
+        snrt_mesh_destroy(m);
+        return s;
+    }
+    *out = m;
+    return SNRT_OK;
+}
+
+snrt_status snrt_mesh_permutation(const snrt_mesh* m, int64_t* internal_to_user) {
+    g_last_error.clear();
+    SNRT_REQUIRE(m && (internal_to_user || m->nc == 0), SNRT_E_ARG,
+                 "snrt_mesh_permutation: NULL argument");
+    if (m->nc) std::memcpy(internal_to_user, m->to_user.data(), sizeof(int64_t) * m->nc);
+    return SNRT_OK;
+}
+
+snrt_status snrt_mesh_info(const snrt_mesh* m, int64_t* nc, int64_t* nbf, int32_t* mf) {
+    g_last_error.clear();
+    SNRT_REQUIRE(m, SNRT_E_ARG, "snrt_mesh_info: NULL mesh");
+    if (nc) *nc = m->nc;
+    if (nbf) *nbf = m->nbf;
+    if (mf) *mf = m->mf;
+    return SNRT_OK;
+}
+
+// ------------------------------------------------------------------------------- quadrature
+
+void snrt_quad_destroy(snrt_quad* q) {
+    if (!q) return;
+    dev_free(q->tab32);
+    dev_free(q->tab64);
+    delete q;
+}
+
+snrt_status snrt_quad_create(snrt_quad** out, int32_t nq, const double* omega, const double* w) {
+    g_last_error.clear();
+    SNRT_REQUIRE(out, SNRT_E_ARG, "snrt_quad_create: out is NULL");
+    *out = nullptr;
+    SNRT_REQUIRE(nq >= 1 && nq <= SNRT_MAX_NQ, SNRT_E_UNSUPPORTED,
+                 "snrt_quad_create: nq must be in [1, 1024]");
+    SNRT_REQUIRE(omega && w, SNRT_E_ARG, "snrt_quad_create: NULL array");
+    const double four_pi = 4.0 * 3.14159265358979323846264338327950288;
+    std::vector<double> t64(4 * (size_t)nq);
+    for (int32_t q = 0; q < nq; ++q) {
+        const double ox = omega[3 * q], oy = omega[3 * q + 1], oz = omega[3 * q + 2];
+        SNRT_REQUIRE(is_finite(ox) && is_finite(oy) && is_finite(oz) && is_finite(w[q]) && w[q] > 0.0,
+                     SNRT_E_ARG, "snrt_quad_create: non-finite ordinate or non-positive weight");
+        t64[q] = ox;
+        t64[nq + q] = oy;
+        t64[2 * nq + q] = w[q];
+        t64[3 * nq + q] = w[q] / four_pi;
+    }
+    std::vector<float> t32(t64.size());
+    for (size_t i = 0; i < t64.size(); ++i) t32[i] = (float)t64[i];
+    snrt_quad* qd = new snrt_quad();
+    hipError_t e = hipGetDevice(&qd->device);
+    if (e != hipSuccess) {
+        delete qd;
+        return hip_fail(e, "snrt_quad_create: hipGetDevice");
+    }
+    qd->nq = nq;
+    qd->w_host.assign(w, w + nq);
+    snrt_status s = SNRT_OK;
+    if ((s = dev_alloc(&qd->tab32, t32.size(), "ordinates")) != SNRT_OK ||
+        (s = dev_alloc(&qd->tab64, t64.size(), "ordinates")) != SNRT_OK ||
+        (s = upload(qd->tab32, t32.data(), t32.size(), "snrt_quad_create: upload")) != SNRT_OK ||
+        (s = upload(qd->tab64, t64.data(), t64.size(), "snrt_quad_create: upload")) != SNRT_OK) {
+        snrt_quad_destroy(qd);
+        return s;
+    }
+    *out = qd;
+    return SNRT_OK;
+}
+
+// ------------------------------------------------------------------------------- scattering
+
+void snrt_scatter_destroy(snrt_scatter* sc) {
+    if (!sc) return;
+    DenseB& B = sc->B;
+    dev_free(B.b32);
+    dev_free(B.bt32);
+    dev_free(B.b64);
+    dev_free(B.bt64);
+    dev_free(B.b_hi);
+    dev_free(B.b_lo);
+    dev_free(B.bt_hi);
+    dev_free(B.bt_lo);
+    delete sc;
+}
+
+snrt_status snrt_scatter_isotropic(snrt_scatter** out, const snrt_quad* q) {
+    g_last_error.clear();
+    SNRT_REQUIRE(out && q, SNRT_E_ARG, "snrt_scatter_isotropic: NULL argument");
+    snrt_scatter* sc = new snrt_scatter();
+    sc->device = q->device;
+    sc->dense = false;
+    sc->B.nq = q->nq;
+    *out = sc;
+    return SNRT_OK;
+}
+
+snrt_status snrt_scatter_dense(snrt_scatter** out, const snrt_quad* q, const double* K,
+                               snrt_precision precision) {
+    g_last_error.clear();
+    SNRT_REQUIRE(out && q && K, SNRT_E_ARG, "snrt_scatter_dense: NULL argument");
+    *out = nullptr;
+    SNRT_REQUIRE(precision == SNRT_FP32 || precision == SNRT_BF16X3 || precision == SNRT_BF16X1,
+                 SNRT_E_ARG, "snrt_scatter_dense: unknown precision");
+    const int32_t nq = q->nq;
+    if (precision != SNRT_FP32) {
+        SNRT_REQUIRE(nq % 64 == 0, SNRT_E_UNSUPPORTED,
+                     "snrt_scatter_dense: BF16 modes need nq % 64 == 0");
+    }
+    SNRT_TRY(check_device(q->device, "snrt_scatter_dense"));
+    const size_t n2 = (size_t)nq * nq;
+    std::vector<double> b64(n2), bt64(n2);
+    for (int32_t p = 0; p < nq; ++p)
+        for (int32_t qq = 0; qq < nq; ++qq) {
+            const double kqp = K[(size_t)qq * nq + p];
+            SNRT_REQUIRE(is_finite(kqp), SNRT_E_ARG, "snrt_scatter_dense: non-finite kernel entry");
+            b64[(size_t)p * nq + qq] = q->w_host[p] * kqp;                        // w_p K[q][p]
+            bt64[(size_t)p * nq + qq] = q->w_host[qq] * K[(size_t)p * nq + qq];   // w_q K[p][q]
+        }
+    std::vector<float> b32(n2), bt32(n2);
+    for (size_t i = 0; i < n2; ++i) {
+        b32[i] = (float)b64[i];
+        bt32[i] = (float)bt64[i];
+    }
+    snrt_scatter* sc = new snrt_scatter();
+    sc->device = q->device;
+    sc->dense = true;
+    DenseB& B = sc->B;
+    B.nq = nq;
+    B.precision = precision;
+    snrt_status s = SNRT_OK;
+    if ((s = dev_alloc(&B.b32, n2, "B")) != SNRT_OK || (s = dev_alloc(&B.bt32, n2, "B^T")) != SNRT_OK ||
+        (s = dev_alloc(&B.b64, n2, "B")) != SNRT_OK || (s = dev_alloc(&B.bt64, n2, "B^T")) != SNRT_OK ||
+        (s = upload(B.b32, b32.data(), n2, "snrt_scatter_dense: upload")) != SNRT_OK ||
+        (s = upload(B.bt32, bt32.data(), n2, "snrt_scatter_dense: upload")) != SNRT_OK ||
+        (s = upload(B.b64, b64.data(), n2, "snrt_scatter_dense: upload")) != SNRT_OK ||
+        (s = upload(B.bt64, bt64.data(), n2, "snrt_scatter_dense: upload")) != SNRT_OK) {
+        snrt_scatter_destroy(sc);
+        return s;
+    }
+    if (precision != SNRT_FP32) {
+        if ((s = dev_alloc(&B.b_hi, n2, "B hi")) != SNRT_OK ||
+            (s = dev_alloc(&B.b_lo, n2, "B lo")) != SNRT_OK ||
+            (s = dev_alloc(&B.bt_hi, n2, "B^T hi")) != SNRT_OK ||
+            (s = dev_alloc(&B.bt_lo, n2, "B^T lo")) != SNRT_OK) {
+            snrt_scatter_destroy(sc);
+            return s;
+        }
+        hipError_t e = launch_split_bf16(B.b32, B.b_hi, B.b_lo, nq, nullptr);
+        if (e == hipSuccess) e = launch_split_bf16(B.bt32, B.bt_hi, B.bt_lo, nq, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            snrt_scatter_destroy(sc);
+            return hip_fail(e, "snrt_scatter_dense: BF16 split");
+        }
+    }
+    *out = sc;
+    return SNRT_OK;
+}
+
+snrt_status snrt_workspace_size(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
+                                size_t* bytes) {
+    g_last_error.clear();
+    SNRT_REQUIRE(m && q && sc && bytes, SNRT_E_ARG, "snrt_workspace_size: NULL argument");
+    SNRT_REQUIRE(sc->B.nq == q->nq, SNRT_E_SHAPE, "snrt_workspace_size: scatter/quad nq differ");
+    *bytes = sc->dense ? (size_t)m->nc * q->nq * sizeof(double) : 0;
+    return SNRT_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------ steps
+
+namespace {
+
+template <typename ArgsT>
+snrt_status check_step_common(const char* fn, const snrt_mesh* m, const snrt_quad* q,
+                              const snrt_scatter* sc, const ArgsT* a, size_t elem,
+                              const void* in, void* out, void* ws, size_t ws_bytes) {
+    SNRT_REQUIRE(m && q && sc && a, SNRT_E_ARG, std::string(fn) + ": NULL handle or args");
+    SNRT_REQUIRE(sc->B.nq == q->nq, SNRT_E_SHAPE, std::string(fn) + ": scatter/quad nq differ");
+    SNRT_TRY(check_device(m->device, fn));
+    SNRT_REQUIRE(q->device == m->device && sc->device == m->device, SNRT_E_ARG,
+                 std::string(fn) + ": handles on different devices");
+    SNRT_REQUIRE(is_finite(a->dt) && is_finite(a->alpha_t) && is_finite(a->alpha_s) &&
+                     is_finite(a->inflow_scale),
+                 SNRT_E_NONFINITE, std::string(fn) + ": non-finite scalar argument");
+    SNRT_REQUIRE(a->boundary == SNRT_BC_DIRICHLET || a->boundary == SNRT_BC_NEUMANN, SNRT_E_ARG,
+                 std::string(fn) + ": unknown boundary mode");
+    if (m->nc == 0) return SNRT_OK;
+    SNRT_REQUIRE(a->sigma_t && a->sigma_s, SNRT_E_ARG, std::string(fn) + ": sigma_t/sigma_s NULL");
+    SNRT_REQUIRE(in && out, SNRT_E_ARG, std::string(fn) + ": NULL state pointer");
+    SNRT_REQUIRE(aligned16(in) && aligned16(out), SNRT_E_ARG,
+                 std::string(fn) + ": state pointers must be 16-byte aligned");
+    const size_t bytes = (size_t)m->nc * q->nq * elem;
+    SNRT_REQUIRE(!ranges_overlap(in, bytes, out, bytes), SNRT_E_ALIAS,
+                 std::string(fn) + ": output aliases input");
+    if (sc->dense) {
+        const size_t need = (size_t)m->nc * q->nq * elem;
+        SNRT_REQUIRE(ws && ws_bytes >= need, SNRT_E_ARG,
+                     std::string(fn) + ": dense scattering needs a workspace of " +
+                         std::to_string(need) + " bytes");
+        SNRT_REQUIRE(aligned16(ws), SNRT_E_ARG, std::string(fn) + ": workspace must be 16-byte aligned");
+        SNRT_REQUIRE(!ranges_overlap(ws, need, in, bytes) && !ranges_overlap(ws, need, out, bytes),
+                     SNRT_E_ALIAS, std::string(fn) + ": workspace aliases a state array");
+    }
+    return SNRT_OK;
+}
+
+StepArgs32 to32(const snrt_step_args* a) {
+    StepArgs32 r;
+    r.sigma_t = a->sigma_t;
+    r.sigma_s = a->sigma_s;
+    r.inv_rho = a->inv_rho;
+    r.source = a->source;
+    r.inflow = a->boundary == SNRT_BC_NEUMANN ? nullptr : a->inflow;
+    r.inflow_scale = (float)a->inflow_scale;
+    r.dt = (float)a->dt;
+    r.alpha_t = (float)a->alpha_t;
+    r.alpha_s = (float)a->alpha_s;
+    r.neumann = a->boundary == SNRT_BC_NEUMANN;
+    return r;
+}
+
+StepArgs64 to64(const snrt_step_args_f64* a) {
+    StepArgs64 r;
+    r.sigma_t = a->sigma_t;
+    r.sigma_s = a->sigma_s;
+    r.inv_rho = a->inv_rho;
+    r.source = a->source;
+    r.inflow = a->boundary == SNRT_BC_NEUMANN ? nullptr : a->inflow;
+    r.inflow_scale = a->inflow_scale;
+    r.dt = a->dt;
+    r.alpha_t = a->alpha_t;
+    r.alpha_s = a->alpha_s;
+    r.neumann = a->boundary == SNRT_BC_NEUMANN;
+    return r;
+}
+
+// S = Psi B (forward) or G = Lambda B^T (adjoint) into the workspace, FP32 state
+hipError_t dense_product32(const snrt_scatter* sc, const float* A, float* C, int64_t M,
+                           bool transpose, hipStream_t st) {
+    const DenseB& B = sc->B;
+    if (B.precision == SNRT_FP32)
+        return launch_gemm32(A, transpose ? B.bt32 : B.b32, C, M, B.nq, st);
+    return launch_gemm_bf16(A, transpose ? B.bt_hi : B.b_hi, transpose ? B.bt_lo : B.b_lo, C, M,
+                            B.nq, B.precision == SNRT_BF16X3, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+snrt_status snrt_step(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
+                      const snrt_step_args* a, const float* psi_in, float* psi_out, void* ws,
+                      size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    SNRT_TRY(check_step_common("snrt_step", m, q, sc, a, sizeof(float), psi_in, psi_out, ws,
+                               ws_bytes));
+    if (m->nc == 0) return SNRT_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const float* S = nullptr;
+    if (sc->dense) {
+        float* Sbuf = static_cast<float*>(ws);
+        hipError_t e = dense_product32(sc, psi_in, Sbuf, m->nc, false, st);
+        if (e != hipSuccess) return hip_fail(e, "snrt_step: scattering product");
+        S = Sbuf;
+    }
+    hipError_t e = launch_step32(*m, *q, to32(a), psi_in, psi_out, S, st);
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_step: launch");
+}
+
+snrt_status snrt_step_f64(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
+                          const snrt_step_args_f64* a, const double* psi_in, double* psi_out,
+                          void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    SNRT_TRY(check_step_common("snrt_step_f64", m, q, sc, a, sizeof(double), psi_in, psi_out, ws,
+                               ws_bytes));
+    if (m->nc == 0) return SNRT_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double* S = nullptr;
+    if (sc->dense) {
+        double* Sbuf = static_cast<double*>(ws);
+        hipError_t e = launch_gemm64(psi_in, sc->B.b64, Sbuf, m->nc, q->nq, st);
+        if (e != hipSuccess) return hip_fail(e, "snrt_step_f64: scattering product");
+        S = Sbuf;
+    }
+    hipError_t e = launch_step64(*m, *q, to64(a), psi_in, psi_out, S, st);
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_step_f64: launch");
+}
+
+snrt_status snrt_step_adjoint(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
+                              const snrt_step_args* a, const float* psi_n, const float* lam_np1,
+                              float* lam_n, float* g_t, float* g_s, float* g_r, void* ws,
+                              size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    SNRT_TRY(check_step_common("snrt_step_adjoint", m, q, sc, a, sizeof(float), lam_np1, lam_n,
+                               ws, ws_bytes));
+    if (m->nc == 0) return SNRT_OK;
+    SNRT_REQUIRE(psi_n && aligned16(psi_n), SNRT_E_ARG,
+                 "snrt_step_adjoint: psi_n NULL or misaligned");
+    const size_t bytes = (size_t)m->nc * q->nq * sizeof(float);
+    SNRT_REQUIRE(!ranges_overlap(psi_n, bytes, lam_n, bytes), SNRT_E_ALIAS,
+                 "snrt_step_adjoint: lam_n aliases psi_n");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const float* G = nullptr;
+    if (sc->dense) {
+        float* Gbuf = static_cast<float*>(ws);
+        hipError_t e = dense_product32(sc, lam_np1, Gbuf, m->nc, true, st);
+        if (e != hipSuccess) return hip_fail(e, "snrt_step_adjoint: scattering product");
+        G = Gbuf;
+    }
+    hipError_t e = launch_adjoint32(*m, *q, to32(a), psi_n, lam_np1, lam_n, g_t, g_s, g_r, G, st);
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_step_adjoint: launch");
+}
+
+snrt_status snrt_step_adjoint_f64(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
+                                  const snrt_step_args_f64* a, const double* psi_n,
+                                  const double* lam_np1, double* lam_n, double* g_t, double* g_s,
+                                  double* g_r, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    SNRT_TRY(check_step_common("snrt_step_adjoint_f64", m, q, sc, a, sizeof(double), lam_np1,
+                               lam_n, ws, ws_bytes));
+    if (m->nc == 0) return SNRT_OK;
+    SNRT_REQUIRE(psi_n && aligned16(psi_n), SNRT_E_ARG,
+                 "snrt_step_adjoint_f64: psi_n NULL or misaligned");
+    const size_t bytes = (size_t)m->nc * q->nq * sizeof(double);
+    SNRT_REQUIRE(!ranges_overlap(psi_n, bytes, lam_n, bytes), SNRT_E_ALIAS,
+                 "snrt_step_adjoint_f64: lam_n aliases psi_n");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double* G = nullptr;
+    if (sc->dense) {
+        double* Gbuf = static_cast<double*>(ws);
+        hipError_t e = launch_gemm64(lam_np1, sc->B.bt64, Gbuf, m->nc, q->nq, st);
+        if (e != hipSuccess) return hip_fail(e, "snrt_step_adjoint_f64: scattering product");
+        G = Gbuf;
+    }
+    hipError_t e = launch_adjoint64(*m, *q, to64(a), psi_n, lam_np1, lam_n, g_t, g_s, g_r, G, st);
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_step_adjoint_f64: launch");
+}
+
+// ------------------------------------------------------------------------------- reductions
+
+snrt_status snrt_mass(const snrt_mesh* m, const snrt_quad* q, const float* psi, double* out,
+                      void* stream) {
+    g_last_error.clear();
+    SNRT_REQUIRE(m && q && out, SNRT_E_ARG, "snrt_mass: NULL argument");
+    SNRT_REQUIRE(psi || m->nc == 0, SNRT_E_ARG, "snrt_mass: NULL psi");
+    SNRT_TRY(check_device(m->device, "snrt_mass"));
+    hipError_t e = launch_mass(*m, *q, psi, out, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_mass: launch");
+}
+
+snrt_status snrt_scalar_flux(const snrt_mesh* m, const snrt_quad* q, const float* psi,
+                             float* phi, void* stream) {
+    g_last_error.clear();
+    SNRT_REQUIRE(m && q, SNRT_E_ARG, "snrt_scalar_flux: NULL handle");
+    SNRT_REQUIRE((psi && phi) || m->nc == 0, SNRT_E_ARG, "snrt_scalar_flux: NULL array");
+    SNRT_TRY(check_device(m->device, "snrt_scalar_flux"));
+    hipError_t e = launch_scalar_flux(*m, *q, psi, phi, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_scalar_flux: launch");
+}
+
+snrt_status snrt_dose_accumulate(const snrt_mesh* m, const snrt_quad* q, const float* psi,
+                                 const float* inv_rho, double coeff, double* dose, void* stream) {
+    g_last_error.clear();
+    SNRT_REQUIRE(m && q, SNRT_E_ARG, "snrt_dose_accumulate: NULL handle");
+    SNRT_REQUIRE((psi && dose) || m->nc == 0, SNRT_E_ARG, "snrt_dose_accumulate: NULL array");
+    SNRT_REQUIRE(is_finite(coeff), SNRT_E_NONFINITE, "snrt_dose_accumulate: non-finite coeff");
+    SNRT_TRY(check_device(m->device, "snrt_dose_accumulate"));
+    hipError_t e = launch_dose(*m, *q, psi, inv_rho, coeff, dose, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_dose_accumulate: launch");
+}
+
+snrt_status snrt_permute(const snrt_mesh* m, int32_t to_user, const void* in, void* out,
+                         int64_t row_bytes, void* stream) {
+    g_last_error.clear();
+    SNRT_REQUIRE(m, SNRT_E_ARG, "snrt_permute: NULL mesh");
+    SNRT_REQUIRE(to_user == 0 || to_user == 1, SNRT_E_ARG, "snrt_permute: direction must be 0 or 1");
+    SNRT_REQUIRE(row_bytes > 0 && row_bytes % 4 == 0, SNRT_E_ARG,
+                 "snrt_permute: row_bytes must be a positive multiple of 4");
+    if (m->nc == 0) return SNRT_OK;
+    SNRT_REQUIRE(in && out, SNRT_E_ARG, "snrt_permute: NULL array");
+    SNRT_REQUIRE(((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 3u) == 0,
+                 SNRT_E_ARG, "snrt_permute: arrays must be 4-byte aligned");
+    const size_t bytes = (size_t)m->nc * row_bytes;
+    SNRT_REQUIRE(!ranges_overlap(in, bytes, out, bytes), SNRT_E_ALIAS, "snrt_permute: out aliases in");
+    SNRT_TRY(check_device(m->device, "snrt_permute"));
+    hipError_t e = launch_permute(*m, to_user, in, out, row_bytes, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_permute: launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// Internal types shared by the libsnrt translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/snrt.h"
+
+namespace snrt {
+
+constexpr int32_t kUnusedFace = INT32_MIN;
+constexpr int kWave = 64;              // CDNA wavefront width
+constexpr int kStepBlock = 256;        // 4 waves, one cell per wave
+constexpr int kCellsPerBlock = kStepBlock / kWave;
+constexpr int kNumXcd = 8;             // MI355X: 8 accelerator complex dies
+
+// Per-cell geometry record, one 64-byte line: neighbours, n_ij (outward normal x length),
+// 1/A_i and A_i.  Unused face slots have nbr = kUnusedFace and a zero normal.
+struct alignas(64) CellGeom32 {
+    int32_t nbr[4];
+    float n[4][2];
+    float inv_area;
+    float area;
+    float pad[2];
+};
+static_assert(sizeof(CellGeom32) == 64, "one cache line per cell");
+
+struct alignas(32) CellGeom64 {
+    int32_t nbr[4];
+    double n[4][2];
+    double inv_area;
+    double area;
+    double pad[2];
+};
+static_assert(sizeof(CellGeom64) == 128, "two cache lines per cell");
+
+// Dense scattering operands on the device: B for the forward product S = Psi B and B^T for
+// the adjoint product Lambda B^T, in FP32 / FP64 and as BF16 hi/lo pairs for MFMA.
+struct DenseB {
+    int32_t nq = 0;
+    snrt_precision precision = SNRT_FP32;
+    float* b32 = nullptr;        // [nq][nq]  B[p][q] = w_p K[q][p]   (forward)
+    float* bt32 = nullptr;       // [nq][nq]  B^T[p][q] = w_q K[p][q] (adjoint)
+    double* b64 = nullptr;
+    double* bt64 = nullptr;
+    uint16_t* b_hi = nullptr;    // BF16 bit patterns, layout chosen by the GEMM kernel
+    uint16_t* b_lo = nullptr;
+    uint16_t* bt_hi = nullptr;
+    uint16_t* bt_lo = nullptr;
+};
+
+}  // namespace snrt
+
+struct snrt_mesh {
+    int device = 0;
+    int64_t nc = 0;
+    int64_t nbf = 0;
+    int32_t mf = 3;
+    std::vector<int64_t> to_user;          // internal -> user
+    snrt::CellGeom32* geom32 = nullptr;
+    snrt::CellGeom64* geom64 = nullptr;
+    int64_t* d_to_user = nullptr;          // device copy of to_user
+    double* d_partial = nullptr;           // per-block partial sums for snrt_mass
+    int64_t n_partial = 0;
+};
+
+struct snrt_quad {
+    int device = 0;
+    int32_t nq = 0;
+    // FP32 ordinate table, 4 rows of nq: Omega_x, Omega_y, w, w/(4 pi)
+    float* tab32 = nullptr;
+    double* tab64 = nullptr;
+    std::vector<double> w_host;
+};
+
+struct snrt_scatter {
+    int device = 0;
+    bool dense = false;
+    snrt::DenseB B;
+};
+
+namespace snrt {
+
+void set_error(const std::string& msg);
+snrt_status hip_fail(hipError_t e, const char* what);
+
+// Kernel launchers (return hipGetLastError() after the launch).
+struct StepArgs32 {
+    const float *sigma_t, *sigma_s, *inv_rho, *source, *inflow;
+    float inflow_scale, dt, alpha_t, alpha_s;
+    int32_t neumann;
+};
+struct StepArgs64 {
+    const double *sigma_t, *sigma_s, *inv_rho, *source, *inflow;
+    double inflow_scale, dt, alpha_t, alpha_s;
+    int32_t neumann;
+};
+
+hipError_t launch_step32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
+                         const float* psi_in, float* psi_out, const float* S, hipStream_t st);
+hipError_t launch_step64(const snrt_mesh& m, const snrt_quad& q, const StepArgs64& a,
+                         const double* psi_in, double* psi_out, const double* S, hipStream_t st);
+hipError_t launch_adjoint32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
+                            const float* psi_n, const float* lam_np1, float* lam_n,
+                            float* g_t, float* g_s, float* g_r, const float* G, hipStream_t st);
+hipError_t launch_adjoint64(const snrt_mesh& m, const snrt_quad& q, const StepArgs64& a,
+                            const double* psi_n, const double* lam_np1, double* lam_n,
+                            double* g_t, double* g_s, double* g_r, const double* G,
+                            hipStream_t st);
+
+// Dense scattering products C[M][N] = A[M][K] B[K][N] with M = ncells, N = K = nq.
+hipError_t launch_gemm32(const float* A, const float* B, float* C, int64_t M, int32_t nq,
+                         hipStream_t st);
+hipError_t launch_gemm64(const double* A, const double* B, double* C, int64_t M, int32_t nq,
+                         hipStream_t st);
+hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
+                            int64_t M, int32_t nq, bool three_products, hipStream_t st);
+// Re-layout of an FP32 [nq][nq] matrix into the BF16 hi/lo operand format of the MFMA GEMM.
+hipError_t launch_split_bf16(const float* B, uint16_t* hi, uint16_t* lo, int32_t nq,
+                             hipStream_t st);
+
+hipError_t launch_mass(const snrt_mesh& m, const snrt_quad& q, const float* psi, double* out,
+                       hipStream_t st);
+hipError_t launch_scalar_flux(const snrt_mesh& m, const snrt_quad& q, const float* psi,
+                              float* phi, hipStream_t st);
+hipError_t launch_dose(const snrt_mesh& m, const snrt_quad& q, const float* psi,
+                       const float* inv_rho, double coeff, double* dose, hipStream_t st);
+hipError_t launch_permute(const snrt_mesh& m, int to_user, const void* in, void* out,
+                          int64_t row_bytes, hipStream_t st);
+
+// XCD-aware mapping of a hardware block index to a logical block index: blocks are
+// dispatched round-robin over the XCDs, so give XCD x a contiguous range of logical blocks.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+    int64_t x = b % kNumXcd;
+    int64_t k = b / kNumXcd;
+    int64_t q = nb / kNumXcd, r = nb % kNumXcd;
+    return x * q + (x < r ? x : r) + k;
+}
+
+}  // namespace snrt

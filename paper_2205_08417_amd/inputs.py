@@ -233,6 +233,57 @@ def periodic_mesh(n: int, length: float = 1.0, diagonal_flip: bool = True) -> Me
                 bface_mid=np.zeros((0, 2)))
 
 
+def quad_grid_mesh(nx: int, ny: int, lo=(0.0, 0.0), hi=(1.0, 1.0)) -> Mesh:
+    """Structured ``nx x ny`` grid of rectangles (quadrilateral cells, four faces each).
+
+    Face f of a cell is its CCW edge ``v_f -> v_{f+1}`` (bottom, right, top, left).
+    """
+    xs = np.linspace(lo[0], hi[0], nx + 1)
+    ys = np.linspace(lo[1], hi[1], ny + 1)
+    nc = nx * ny
+    cid = lambda i, j: j * nx + i
+    face_nbr = np.empty((nc, 4), dtype=np.int64)
+    normal = np.empty((nc, 4, 2))
+    area = np.empty(nc)
+    centroid = np.empty((nc, 2))
+    cells = np.empty((nc, 4), dtype=np.int64)
+    bcell, bmid = [], []
+    for j in range(ny):
+        for i in range(nx):
+            c = cid(i, j)
+            v = [(xs[i], ys[j]), (xs[i + 1], ys[j]), (xs[i + 1], ys[j + 1]), (xs[i], ys[j + 1])]
+            cells[c] = [j * (nx + 1) + i, j * (nx + 1) + i + 1, (j + 1) * (nx + 1) + i + 1,
+                        (j + 1) * (nx + 1) + i]
+            nb = [cid(i, j - 1) if j > 0 else -1, cid(i + 1, j) if i < nx - 1 else -1,
+                  cid(i, j + 1) if j < ny - 1 else -1, cid(i - 1, j) if i > 0 else -1]
+            for f in range(4):
+                a, b = v[f], v[(f + 1) % 4]
+                normal[c, f] = (b[1] - a[1], -(b[0] - a[0]))
+                face_nbr[c, f] = nb[f]
+            area[c] = (xs[i + 1] - xs[i]) * (ys[j + 1] - ys[j])
+            centroid[c] = (0.5 * (xs[i] + xs[i + 1]), 0.5 * (ys[j] + ys[j + 1]))
+    bc, bf = np.nonzero(face_nbr < 0)
+    face_nbr[bc, bf] = -1 - np.arange(bc.shape[0])
+    pts = np.array([(x, y) for y in ys for x in xs])
+    mids = np.array([0.5 * (np.array(pts[cells[c, f]]) + np.array(pts[cells[c, (f + 1) % 4]]))
+                     for c, f in zip(bc, bf)]).reshape(-1, 2)
+    return Mesh(points=pts, cells=cells, face_nbr=face_nbr.astype(np.int32),
+                face_normal=normal, area=area, centroid=centroid,
+                bface_cell=bc.astype(np.int64), bface_mid=mids)
+
+
+def pad_faces(mesh: Mesh, max_faces: int = 4) -> Mesh:
+    """Same mesh with unused face slots (``INT32_MIN``, zero normal) appended per cell."""
+    nc, mf = mesh.face_nbr.shape
+    if max_faces < mf:
+        raise ValueError("cannot drop faces")
+    nbr = np.full((nc, max_faces), INT32_MIN, dtype=np.int32)
+    nbr[:, :mf] = mesh.face_nbr
+    nrm = np.zeros((nc, max_faces, 2))
+    nrm[:, :mf] = mesh.face_normal
+    return dataclasses.replace(mesh, face_nbr=nbr, face_normal=nrm)
+
+
 # ----------------------------------------------------------------------------------------
 # Scattering kernels (eq. SNEqns; total = scattering cross section, Sec. 2)
 # ----------------------------------------------------------------------------------------
@@ -267,10 +318,13 @@ def cfl_dt(mesh: Mesh, omega: np.ndarray, cfl: float, rho: Optional[np.ndarray] 
 
     The bound keeps the streaming part of the explicit update a convex combination.
     """
-    n = mesh.face_normal                                   # [nc, mf, 2]
-    s = np.einsum("cfd,qd->cfq", n, omega[:, :2])          # [nc, mf, nq]
-    valid = (mesh.face_nbr != INT32_MIN)[:, :, None]
-    out = np.where(valid, np.maximum(s, 0.0), 0.0).sum(axis=1).max(axis=1)
+    ox, oy = omega[:, 0], omega[:, 1]
+    out = np.empty(mesh.ncells)
+    for c0 in range(0, mesh.ncells, 4096):              # chunks bound the [c, f, q] temporary
+        n = mesh.face_normal[c0:c0 + 4096]
+        s = n[:, :, 0, None] * ox[None, None, :] + n[:, :, 1, None] * oy[None, None, :]
+        valid = (mesh.face_nbr[c0:c0 + 4096] != INT32_MIN)[:, :, None]
+        out[c0:c0 + 4096] = np.where(valid, np.maximum(s, 0.0), 0.0).sum(axis=1).max(axis=1)
     r = np.ones(mesh.ncells) if rho is None else rho
     return float(cfl * np.min(mesh.area * r / out))
 

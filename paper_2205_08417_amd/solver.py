@@ -1,0 +1,173 @@
+"""Torch-facing layer over the libsnrt C ABI: problem upload, stepping, rollouts.
+
+PyTorch supplies device memory and streams only; every step of the S_N path runs in the
+HIP kernels behind ``snrt``.  States live on the device in the library's internal cell
+order (a Hilbert renumbering); :meth:`Solver.to_internal` / :meth:`Solver.to_user` move
+between that order and the user's with the library's own permute kernel.
+"""
+from __future__ import annotations
+
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import snrt
+from .inputs import Problem
+
+_PREC = {"fp32": snrt.SNRT_FP32, "bf16x3": snrt.SNRT_BF16X3, "bf16x1": snrt.SNRT_BF16X1}
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("the S_N library needs a HIP device; none is visible")
+
+
+class Solver:
+    """Device-resident S_N problem: mesh / quadrature / scattering handles and materials.
+
+    ``precision`` selects the dense scattering product (``fp32``, ``bf16x3``, ``bf16x1``);
+    isotropic problems ignore it.  ``fp64`` additionally uploads FP64 copies of the
+    materials for the FP64 parity template (:meth:`step_f64`).
+    """
+
+    def __init__(self, P: Problem, device: str = "cuda", precision: str = "fp32",
+                 reorder: bool = True, fp64: bool = False):
+        _require_gpu()
+        self.P = P
+        self.device = torch.device(device)
+        self.nc, self.nq = P.ncells, P.nq
+        m = P.mesh
+        flags = snrt.SNRT_REORDER_HILBERT if reorder else snrt.SNRT_NO_REORDER
+        with torch.cuda.device(self.device):
+            self.mesh = snrt.snrt_mesh_create(m.face_nbr, m.face_normal, m.area, m.centroid,
+                                              m.nbfaces, flags)
+            self.quad = snrt.snrt_quad_create(P.omega, P.w)
+            if P.K is None:
+                self.scatter = snrt.snrt_scatter_isotropic(self.quad)
+            else:
+                self.scatter = snrt.snrt_scatter_dense(self.quad, P.K, _PREC[precision])
+            self.ws_bytes = snrt.snrt_workspace_size(self.mesh, self.quad, self.scatter)
+        self.perm = snrt.snrt_mesh_permutation(self.mesh)
+        self.ws = (torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+                   if self.ws_bytes else None)
+        self.mats32 = self._materials(torch.float32)
+        self.mats64 = self._materials(torch.float64) if fp64 else None
+
+    # ------------------------------------------------------------------ layout helpers
+    def _materials(self, dtype):
+        P = self.P
+        r = {"sigma_t": self.cells_to_internal(P.sigma_t, dtype),
+             "sigma_s": self.cells_to_internal(P.sigma_s, dtype),
+             "inv_rho": None if P.rho is None else self.cells_to_internal(1.0 / P.rho, dtype),
+             "source": None if P.source is None else self.cells_to_internal(P.source, dtype),
+             "inflow": None if P.inflow is None else
+             torch.as_tensor(P.inflow, dtype=dtype).to(self.device).contiguous()}
+        return r
+
+    def to_internal(self, x, dtype=torch.float32) -> torch.Tensor:
+        """[nc, ...] user-order array or tensor -> device tensor in internal order."""
+        src = torch.as_tensor(np.asarray(x) if not torch.is_tensor(x) else x, dtype=dtype)
+        src = src.to(self.device).contiguous()
+        out = torch.empty_like(src)
+        row = src[0].numel() * src.element_size() if src.shape[0] else 4
+        snrt.snrt_permute(self.mesh, 0, src, out, row)
+        return out
+
+    def to_user(self, x: torch.Tensor) -> torch.Tensor:
+        """Device tensor in internal order -> device tensor in user order."""
+        x = x.contiguous()
+        out = torch.empty_like(x)
+        row = x[0].numel() * x.element_size() if x.shape[0] else 4
+        snrt.snrt_permute(self.mesh, 1, x, out, row)
+        return out
+
+    def cells_to_internal(self, a, dtype=torch.float32) -> torch.Tensor:
+        return self.to_internal(np.asarray(a).reshape(self.nc, 1), dtype).reshape(self.nc)
+
+    def initial_state(self, dtype=torch.float32) -> torch.Tensor:
+        return self.to_internal(self.P.psi0, dtype)
+
+    # ------------------------------------------------------------------ steps
+    def args(self, dt=None, alpha_t=1.0, alpha_s=1.0, inflow_scale=1.0, fp64=False,
+             mats=None, boundary=snrt.SNRT_BC_DIRICHLET):
+        M = mats or (self.mats64 if fp64 else self.mats32)
+        return snrt.step_args(M["sigma_t"], M["sigma_s"], self.P.dt if dt is None else dt,
+                              inv_rho=M["inv_rho"], source=M["source"], inflow=M["inflow"],
+                              inflow_scale=inflow_scale, alpha_t=alpha_t, alpha_s=alpha_s,
+                              boundary=boundary)
+
+    def step(self, psi_in, psi_out, args=None, **kw):
+        snrt.snrt_step(self.mesh, self.quad, self.scatter, args or self.args(**kw), psi_in,
+                       psi_out, self.ws, self.ws_bytes)
+
+    def step_f64(self, psi_in, psi_out, args=None, **kw):
+        if self.mats64 is None:
+            self.mats64 = self._materials(torch.float64)
+        kw["fp64"] = True
+        snrt.snrt_step_f64(self.mesh, self.quad, self.scatter, args or self.args(**kw), psi_in,
+                           psi_out, self.ws, self.ws_bytes)
+
+    def adjoint_step(self, psi_n, lam_np1, lam_n, g_sigma_t=None, g_sigma_s=None, g_rho=None,
+                     args=None, **kw):
+        snrt.snrt_step_adjoint(self.mesh, self.quad, self.scatter, args or self.args(**kw),
+                               psi_n, lam_np1, lam_n, g_sigma_t, g_sigma_s, g_rho, self.ws,
+                               self.ws_bytes)
+
+    def adjoint_step_f64(self, psi_n, lam_np1, lam_n, g_sigma_t=None, g_sigma_s=None,
+                         g_rho=None, args=None, **kw):
+        if self.mats64 is None:
+            self.mats64 = self._materials(torch.float64)
+        kw["fp64"] = True
+        snrt.snrt_step_adjoint_f64(self.mesh, self.quad, self.scatter, args or self.args(**kw),
+                                   psi_n, lam_np1, lam_n, g_sigma_t, g_sigma_s, g_rho, self.ws,
+                                   self.ws_bytes)
+
+    def rollout(self, psi0: torch.Tensor, nsteps: int, fp64: bool = False,
+                alpha_t: Optional[Sequence[float]] = None,
+                alpha_s: Optional[Sequence[float]] = None,
+                inflow_scale: Optional[Sequence[float]] = None,
+                dose_coeff: Optional[Sequence[float]] = None,
+                dose: Optional[torch.Tensor] = None):
+        """Advance ``nsteps`` explicit steps (ping-pong buffers).  Returns ``(psi, dose)``;
+        the dose (FP64, internal order) adds ``dose_coeff[n]`` times the density-weighted
+        scalar flux of the state entering step n."""
+        a = psi0.clone()
+        b = torch.empty_like(a)
+        if dose_coeff is not None and dose is None:
+            dose = torch.zeros(self.nc, dtype=torch.float64, device=self.device)
+        stepper = self.step_f64 if fp64 else self.step
+        for n in range(nsteps):
+            if dose_coeff is not None:
+                snrt.snrt_dose_accumulate(self.mesh, self.quad, a, self.mats32["inv_rho"],
+                                          float(dose_coeff[n]), dose)
+            stepper(a, b, alpha_t=1.0 if alpha_t is None else float(alpha_t[n]),
+                    alpha_s=1.0 if alpha_s is None else float(alpha_s[n]),
+                    inflow_scale=1.0 if inflow_scale is None else float(inflow_scale[n]))
+            a, b = b, a
+        return a, dose
+
+    # ------------------------------------------------------------------ reductions
+    def mass(self, psi: torch.Tensor) -> float:
+        out = torch.empty(1, dtype=torch.float64, device=self.device)
+        snrt.snrt_mass(self.mesh, self.quad, psi, out)
+        return float(out.item())
+
+    def scalar_flux(self, psi: torch.Tensor) -> torch.Tensor:
+        phi = torch.empty(self.nc, dtype=torch.float32, device=self.device)
+        snrt.snrt_scalar_flux(self.mesh, self.quad, psi, phi)
+        return phi
+
+    def close(self):
+        for fn, h in ((snrt.snrt_scatter_destroy, "scatter"), (snrt.snrt_quad_destroy, "quad"),
+                      (snrt.snrt_mesh_destroy, "mesh")):
+            v = getattr(self, h, None)
+            if v:
+                fn(v)
+                setattr(self, h, None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,300 @@
+"""GPU parity of the forward step (FP64 template and FP32 path) against the FP64 oracle.
+
+All calls go through the C ABI (``paper_2205_08417_amd.snrt`` via ``Solver``).  Inputs come
+from the seeded generators; expected values from the oracle only.
+
+Tolerances: the FP64 template follows the same arithmetic up to reassociation, so it must
+agree to 1e-12 relative L2 over 100 steps; the FP32 path must agree to 1e-5 (rounding of
+inputs and of every step, ~1e-7 per step).
+"""
+import dataclasses
+import functools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from _util import rel_l2, small_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2205_08417_amd import inputs as I  # noqa: E402
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "four_triangles.json")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2205_08417_amd import snrt
+    snrt.lib()          # fail loudly if the native library is missing
+
+
+@functools.lru_cache(maxsize=None)
+def _workload(name, **over):
+    return I.build(name, **over)
+
+
+def _solver(P, **kw):
+    from paper_2205_08417_amd.solver import Solver
+    return Solver(P, **kw)
+
+
+def _oracle(P, nsteps=None, **kw):
+    from oracle import oracle as o
+    op = o.OracleProblem.from_problem(P, **kw)
+    return o.rollout(op, P.psi0, P.dt, P.nsteps if nsteps is None else nsteps)[0]
+
+
+def _gpu_rollout(P, nsteps, fp64=False, **kw):
+    S = _solver(P, fp64=fp64, **kw)
+    dt = torch.float64 if fp64 else torch.float32
+    psi, _ = S.rollout(S.initial_state(dt), nsteps, fp64=fp64)
+    out = S.to_user(psi).cpu().numpy()
+    S.close()
+    return out
+
+
+# ------------------------------------------------------------------ golden four-triangle mesh
+
+@pytest.mark.parametrize("case", ["streaming", "isotropic_collision_source", "dense_kernel",
+                                  "density"])
+@pytest.mark.parametrize("fp64", [True, False])
+def test_golden_four_triangles(case, fp64):
+    d = json.load(open(GOLD))
+    c = d["cases"][case]
+    m = I.four_triangle_mesh()
+    P = I.Problem(name="golden", mesh=m, omega=np.array(d["omega"]), w=np.array(c["w"]),
+                  K=np.array(c["K"]) if "K" in c else None,
+                  sigma_t=np.array(c["sigma_t"], float), sigma_s=np.array(c["sigma_s"], float),
+                  rho=np.array(c["rho"]) if "rho" in c else None,
+                  source=np.array(c["source"]) if "source" in c else None,
+                  inflow=np.array(d["inflow"]), psi0=np.array(d["psi"]), dt=d["dt"], nsteps=1)
+    out = _gpu_rollout(P, 1, fp64=fp64)
+    tol = 1e-13 if fp64 else 1e-6
+    np.testing.assert_allclose(out, np.array(c["expected"]), rtol=0, atol=tol * 4)
+
+
+# ------------------------------------------------------------------ the named workloads
+
+def test_linesource_fp64_template_100_steps():
+    """Line source, 3 872 triangles x 64 ordinates, 100 steps: FP64 template vs oracle."""
+    P = I.build("linesource_s8")
+    ref = _oracle(P)
+    out = _gpu_rollout(P, P.nsteps, fp64=True)
+    assert rel_l2(out, ref) <= 1e-12
+
+
+def test_linesource_fp32_100_steps():
+    P = I.build("linesource_s8")
+    ref = _oracle(P)
+    out = _gpu_rollout(P, P.nsteps)
+    err = rel_l2(out, ref)
+    print(f"linesource fp32 rel-L2 after 100 steps: {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_checkerboard_reduced_fp32_and_fp64():
+    """Checkerboard at 50x50 points (4 702 cells), 256 ordinates, 100 steps: absorbers
+    sigma_t = 10, source, vacuum boundary."""
+    P = I.build("checkerboard_s16", n_side=50, nsteps=100)
+    ref = _oracle(P)
+    assert rel_l2(_gpu_rollout(P, 100, fp64=True), ref) <= 1e-12
+    err = rel_l2(_gpu_rollout(P, 100), ref)
+    print(f"checkerboard(50) fp32 rel-L2 after 100 steps: {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_checkerboard_full_size_100_steps():
+    """Full size: 198 450 cells x 256 ordinates, the launch configuration the benchmark
+    times, 100 steps vs the oracle (which takes ~30 s on 8 host cores)."""
+    P = _workload("checkerboard_s16")
+    ref = _oracle(P, nsteps=100)
+    out = _gpu_rollout(P, 100)
+    err = rel_l2(out, ref)
+    print(f"checkerboard full fp32 rel-L2 after 100 steps: {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_checkerboard_full_size_one_step_sampled_rough_state():
+    """One FP32 step from a state spanning 6 decades, sampled cells (all boundary cells and a
+    random interior sample) computed one by one by the oracle."""
+    from oracle import oracle as o
+    P = _workload("checkerboard_s16")
+    P = dataclasses.replace(P, psi0=I.random_state(P.ncells, P.nq, seed=17))
+    out = _gpu_rollout(P, 1)
+    rng = np.random.default_rng(3)
+    cells = np.unique(np.concatenate([P.mesh.bface_cell, rng.choice(P.ncells, 3000, False)]))
+    op = o.OracleProblem.from_problem(P)
+    ref = o.step(op, P.psi0, P.dt, cells=cells)
+    assert rel_l2(out[cells], ref) <= 2e-7
+    # elementwise: error bounded by FP32 rounding of the largest contributing term
+    scale = np.max(P.psi0[cells], axis=1, keepdims=True)
+    assert np.max(np.abs(out[cells] - ref) / scale) <= 1e-6
+
+
+# ------------------------------------------------------------------ mesh / ordinate variants
+
+@pytest.mark.parametrize("npol,naz", [(3, 5), (4, 25), (8, 24), (1, 2)])
+def test_ordinate_counts_not_multiple_of_64(npol, naz):
+    P = small_problem(I.jittered_delaunay_mesh(12, 0.0, 1.0, seed=npol), npol, naz, seed=1,
+                      source=True, inflow=True)
+    ref = _oracle(P, nsteps=20)
+    assert rel_l2(_gpu_rollout(P, 20, fp64=True), ref) <= 1e-12
+    assert rel_l2(_gpu_rollout(P, 20), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("npol,naz", [(8, 8), (8, 16), (16, 32), (32, 32)])
+def test_exact_vector_paths(npol, naz):
+    P = small_problem(I.jittered_delaunay_mesh(9, 0.0, 1.0, seed=2), npol, naz, seed=2,
+                      rho=True, source=True, inflow=True)
+    ref = _oracle(P, nsteps=10)
+    assert rel_l2(_gpu_rollout(P, 10, fp64=True), ref) <= 1e-12
+    assert rel_l2(_gpu_rollout(P, 10), ref) <= 1e-5
+
+
+def test_quadrilateral_mesh():
+    P = small_problem(I.quad_grid_mesh(13, 9), 4, 16, seed=4, rho=True, source=True, inflow=True)
+    ref = _oracle(P, nsteps=15)
+    assert rel_l2(_gpu_rollout(P, 15, fp64=True), ref) <= 1e-12
+    assert rel_l2(_gpu_rollout(P, 15), ref) <= 1e-5
+
+
+def test_padded_triangles_unused_face_slot():
+    m = I.pad_faces(I.jittered_delaunay_mesh(10, 0.0, 1.0, seed=6), 4)
+    P = small_problem(m, 4, 16, seed=6, inflow=True)
+    ref = _oracle(P, nsteps=10)
+    assert rel_l2(_gpu_rollout(P, 10, fp64=True), ref) <= 1e-12
+
+
+def test_neumann_boundary():
+    from oracle import oracle as o
+    from paper_2205_08417_amd import snrt
+    P = small_problem(I.jittered_delaunay_mesh(10, 0.0, 1.0, seed=8), 4, 16, seed=8, rho=True,
+                      inflow=True)
+    op = o.OracleProblem.from_problem(P, neumann=True)
+    ref = o.step(op, P.psi0, P.dt)
+    S = _solver(P, fp64=True)
+    a = S.initial_state(torch.float64)
+    b = torch.empty_like(a)
+    S.step_f64(a, b, boundary=snrt.SNRT_BC_NEUMANN)
+    assert rel_l2(S.to_user(b).cpu().numpy(), ref) <= 1e-13
+
+
+def test_density_and_csd_scalars():
+    """Per-step alpha_t, alpha_s and inflow_scale with non-uniform density."""
+    from oracle import oracle as o
+    P = small_problem(I.jittered_delaunay_mesh(11, 0.0, 1.0, seed=9), 4, 16, seed=9, rho=True,
+                      inflow=True, source=True)
+    op = o.OracleProblem.from_problem(P)
+    at, as_, isc = [1.3, 0.7, 1.1], [0.5, 1.2, 0.9], [2.0, 0.5, 1.5]
+    ref = o.rollout(op, P.psi0, P.dt, 3, alpha_t=at, alpha_s=as_, inflow_scale=isc)[0]
+    for fp64, tol in ((True, 1e-13), (False, 1e-6)):
+        S = _solver(P, fp64=fp64)
+        psi, _ = S.rollout(S.initial_state(torch.float64 if fp64 else torch.float32), 3,
+                           fp64=fp64, alpha_t=at, alpha_s=as_, inflow_scale=isc)
+        assert rel_l2(S.to_user(psi).cpu().numpy(), ref) <= tol
+
+
+# ------------------------------------------------------------------ dense scattering (FP32)
+
+def test_dense_fp32_product_linesource_reduced():
+    """HG g=0.9 line source at 25x25 points with 8x8 ordinates, 50 steps, FP32 product."""
+    P = I.build("linesource_hg_s32", n_side=25, n_polar=8, n_azimuth=8, nsteps=50)
+    ref = _oracle(P)
+    assert rel_l2(_gpu_rollout(P, 50, fp64=True), ref) <= 1e-12
+    err = rel_l2(_gpu_rollout(P, 50, precision="fp32"), ref)
+    print(f"dense fp32 rel-L2 after 50 steps: {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_dense_isotropic_matrix_equals_isotropic_path():
+    P = small_problem(I.jittered_delaunay_mesh(10, 0.0, 1.0, seed=10), 4, 16, seed=10)
+    a = _gpu_rollout(P, 5, fp64=True)
+    P.K = I.isotropic_kernel(P.nq)
+    b = _gpu_rollout(P, 5, fp64=True)
+    np.testing.assert_allclose(b, a, rtol=1e-13, atol=1e-15)
+
+
+# ------------------------------------------------------------------ reductions
+
+def test_reductions_match_oracle():
+    from oracle import oracle as o
+    P = small_problem(I.jittered_delaunay_mesh(14, 0.0, 2.0, seed=12), 8, 8, seed=12, rho=True)
+    op = o.OracleProblem.from_problem(P)
+    S = _solver(P)
+    psi = S.initial_state()
+    psi32 = P.psi0.astype(np.float32).astype(np.float64)
+    np.testing.assert_allclose(S.mass(psi), o.mass(op, psi32), rtol=1e-13)
+    phi = S.to_user(S.scalar_flux(psi).reshape(-1, 1)).cpu().numpy().ravel()
+    np.testing.assert_allclose(phi, o.scalar_flux(op, psi32), rtol=1e-6)
+    dose = torch.zeros(P.ncells, dtype=torch.float64, device="cuda")
+    from paper_2205_08417_amd import snrt
+    snrt.snrt_dose_accumulate(S.mesh, S.quad, psi, S.mats32["inv_rho"], 0.37, dose)
+    snrt.snrt_dose_accumulate(S.mesh, S.quad, psi, S.mats32["inv_rho"], 0.11, dose)
+    ref = np.zeros(P.ncells)
+    op32 = op.replace(rho=1.0 / (1.0 / P.rho).astype(np.float32).astype(np.float64))
+    o.dose_accumulate(op32, psi32, 0.37, ref)
+    o.dose_accumulate(op32, psi32, 0.11, ref)
+    got = S.to_user(dose.reshape(-1, 1)).cpu().numpy().ravel()
+    np.testing.assert_allclose(got, ref, rtol=1e-12)
+
+
+# ------------------------------------------------------------------ invariances / edge cases
+
+def test_renumbering_is_bitwise_invisible():
+    P = I.build("checkerboard_s16", n_side=40, nsteps=20)
+    a = _gpu_rollout(P, 20, reorder=True)
+    b = _gpu_rollout(P, 20, reorder=False)
+    assert np.array_equal(a, b)
+
+
+def test_deterministic():
+    P = I.build("linesource_s8")
+    assert np.array_equal(_gpu_rollout(P, 30), _gpu_rollout(P, 30))
+
+
+def test_empty_mesh():
+    from paper_2205_08417_amd import snrt
+    m = I.Mesh(points=np.zeros((0, 2)), cells=np.zeros((0, 3), np.int64),
+               face_nbr=np.zeros((0, 3), np.int32), face_normal=np.zeros((0, 3, 2)),
+               area=np.zeros(0), centroid=np.zeros((0, 2)), bface_cell=np.zeros(0, np.int64),
+               bface_mid=np.zeros((0, 2)))
+    mesh = snrt.snrt_mesh_create(m.face_nbr, m.face_normal, m.area, m.centroid, 0)
+    omega, w = I.product_quadrature(8, 8)
+    quad = snrt.snrt_quad_create(omega, w)
+    sc = snrt.snrt_scatter_isotropic(quad)
+    e = torch.empty(0, device="cuda")
+    args = snrt.step_args(e, e, 0.1)
+    snrt.snrt_step(mesh, quad, sc, args, e, e)
+    out = torch.full((1,), 7.0, dtype=torch.float64, device="cuda")
+    snrt.snrt_mass(mesh, quad, e, out)
+    assert out.item() == 0.0
+    for fn, h in ((snrt.snrt_scatter_destroy, sc), (snrt.snrt_quad_destroy, quad),
+                  (snrt.snrt_mesh_destroy, mesh)):
+        fn(h)
+
+
+def test_errors_alias_alignment_workspace():
+    from paper_2205_08417_amd import snrt
+    P = I.build("linesource_hg_s32", n_side=10, n_polar=8, n_azimuth=8, nsteps=1)
+    S = _solver(P, precision="fp32")
+    psi = S.initial_state()
+    with pytest.raises(snrt.SnrtError) as ei:
+        S.step(psi, psi)
+    assert ei.value.status == snrt.SNRT_E_ALIAS
+    buf = torch.empty(psi.numel() + 1, device="cuda")
+    with pytest.raises(snrt.SnrtError) as ei:
+        S.step(psi, buf[1:])
+    assert ei.value.status == snrt.SNRT_E_ARG
+    out = torch.empty_like(psi)
+    with pytest.raises(snrt.SnrtError) as ei:
+        snrt.snrt_step(S.mesh, S.quad, S.scatter, S.args(), psi, out, None, 0)
+    assert "workspace" in str(ei.value)
+    with pytest.raises(snrt.SnrtError) as ei:
+        S.step(psi, out, dt=float("nan"))
+    assert ei.value.status == snrt.SNRT_E_NONFINITE
