@@ -29,12 +29,17 @@ if ROOT not in sys.path:
 METRIC = "cell-ordinate updates/s per S_N step (FP32 vs mixed) + adjoint/forward ratio"
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, vendor figure
 WORKLOAD = "checkerboard_s16"
-STEP_SOURCE = os.path.join(ROOT, "paper_2205_08417_amd", "csrc", "sn_step.hip")
+STEP_SOURCES = [os.path.join(ROOT, "paper_2205_08417_amd", "csrc", f)
+                for f in ("sn_step_kernels.h", "sn_step_f32.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sn_step_checkerboard_s16_traffic.json")
 
 
 def kernel_source_sha() -> str:
-    return hashlib.sha256(open(STEP_SOURCE, "rb").read()).hexdigest()[:16]
+    """Hash of the step kernel's sources: counter figures are only reused for this source."""
+    h = hashlib.sha256()
+    for f in STEP_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
@@ -58,7 +63,7 @@ def cpu_baseline(P, budget_s: float = 12.0):
     t0 = time.perf_counter()
     psi = o.step(op, psi, P.dt)
     t1 = time.perf_counter() - t0
-    n = max(2, min(60, int(budget_s / max(t1, 1e-6))))
+    n = max(2, min(1000, int(budget_s / max(t1, 1e-6))))
     t0 = time.perf_counter()
     for _ in range(n):
         psi = o.step(op, psi, P.dt)
@@ -77,6 +82,8 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="replay the timed steps from a captured HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain device copy of one state (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the S_N step library runs on a single device "
@@ -92,6 +99,16 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = 198450 * 256
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
+                          "launches": args.steps}))
+        return
     P = I.build(WORKLOAD)
     S = Solver(P)
     a = S.initial_state()
@@ -145,7 +162,7 @@ def main():
                    "Delaunay 316x316 points on [0,7]^2", "graph": bool(args.graph)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_step<4,true,false,float>",
+                     "kernel": "k_step<4,true,3,false,false,float>",
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
     if not args.no_cpu_baseline:

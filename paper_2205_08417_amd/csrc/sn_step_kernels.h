@@ -1,0 +1,674 @@
+// Explicit S_N step and its adjoint on gfx950 (kernel templates; instantiated by
+// sn_step_f32.hip, sn_step_f64.hip and sn_adjoint.hip).
+//
+// One wavefront owns one cell; lane l owns the V contiguous ordinates [l*V, l*V+V) of that
+// cell (psi is [cell][ordinate], ordinates fastest), so the own row and every neighbour row
+// are read with fully coalesced 16-byte loads.  The cell's geometry record is wave-uniform
+// and arrives through scalar loads.  Isotropic scattering is a wavefront reduction of the
+// cell's own row; dense scattering reads the GEMM result S = Psi B.
+//
+// Forward (Sec. 4.2, eq. upwind1stOrder2; eq. SNEqns / BoltzmannCSDTrafo):
+//   psi'_q = psi_q (1 - dt a_t sig_t) - dt/A sum_f s_fq u_up + dt a_s sig_s S_q + dt q_src,
+//   s_fq = Omega_q . n_f, u_up = own u if s_fq > 0 else neighbour u / boundary ghost.
+// Adjoint (exact transpose of the linear part; a downwind gather):
+//   lam_q = l_q (1 - dt a_t sig_t) - dt/rho sum_{f: s>0} s (l_q/A - l_nbr,q/A_nbr)
+//           + dt a_s sig_s (B^T-side scattering),
+// plus per-cell gradient sums, one wavefront reduction each.
+#pragma once
+
+#include <type_traits>
+
+#include "snrt_internal.h"
+
+namespace snrt {
+
+template <typename T> struct GeomOf;
+template <> struct GeomOf<float> { using type = CellGeom32; };
+template <> struct GeomOf<double> { using type = CellGeom64; };
+
+template <typename T> struct ArgsOf;
+template <> struct ArgsOf<float> { using type = StepArgs32; };
+template <> struct ArgsOf<double> { using type = StepArgs64; };
+
+// Load / store V contiguous elements of one lane.  EXACT: the lane's slice is in range and
+// 16-byte aligned when V*sizeof(T) >= 16 (the row length is a multiple of 64 elements).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+template <int V, bool EXACT, typename T>
+__device__ __forceinline__ void load_slice(const T* __restrict__ row, int q0, int nq, T (&r)[V]) {
+    if constexpr (EXACT) {
+        constexpr int B = V * (int)sizeof(T);
+        if constexpr (B % 16 == 0) {
+            const f32x4* p = reinterpret_cast<const f32x4*>(row + q0);
+#pragma unroll
+            for (int i = 0; i < B / 16; ++i) {
+                f32x4 v = p[i];
+                __builtin_memcpy(&r[i * (16 / sizeof(T))], &v, 16);
+            }
+        } else if constexpr (B == 8) {
+            f32x2 v = *reinterpret_cast<const f32x2*>(row + q0);
+            __builtin_memcpy(&r[0], &v, 8);
+        } else {
+            r[0] = row[q0];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) r[j] = (q0 + j < nq) ? row[q0 + j] : T(0);
+    }
+}
+
+// Output rows are written once and not re-read by this kernel: stream them past the caches.
+template <int V, bool EXACT, typename T>
+__device__ __forceinline__ void store_slice(T* __restrict__ row, int q0, int nq, const T (&r)[V],
+                                            bool nt = true) {
+    if constexpr (EXACT) {
+        constexpr int B = V * (int)sizeof(T);
+        if constexpr (B % 16 == 0) {
+            f32x4* p = reinterpret_cast<f32x4*>(row + q0);
+#pragma unroll
+            for (int i = 0; i < B / 16; ++i) {
+                f32x4 v;
+                __builtin_memcpy(&v, &r[i * (16 / sizeof(T))], 16);
+                if (nt)
+                    __builtin_nontemporal_store(v, &p[i]);
+                else
+                    p[i] = v;
+            }
+        } else if constexpr (B == 8) {
+            f32x2 v;
+            __builtin_memcpy(&v, &r[0], 8);
+            if (nt)
+                __builtin_nontemporal_store(v, reinterpret_cast<f32x2*>(row + q0));
+            else
+                *reinterpret_cast<f32x2*>(row + q0) = v;
+        } else {
+            if (nt)
+                __builtin_nontemporal_store(r[0], row + q0);
+            else
+                row[q0] = r[0];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+            if (q0 + j < nq) row[q0 + j] = r[j];
+    }
+}
+
+// ---------------------------------------------------------------- buffer-resource access
+// Rows are addressed as 32-bit byte offsets into a buffer resource (base, size): the row
+// offset is one scalar multiply, the lane offset a constant, and reads outside the buffer
+// return 0 instead of faulting.  Every array the step touches is below 4 GiB (checked by
+// the library before launch).
+
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int32_t kRsrcWord3 = 0x00020000;   // raw buffer, 32-bit data format (CDNA)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int32_t)bytes, kRsrcWord3);
+}
+
+// V contiguous elements of this lane from the row at byte offset soff (EXACT: the row has
+// 64*V elements; otherwise lanes past nq read 0).
+// Cache-policy bits of buffer accesses on CDNA3/4: 1 = sc0, 2 = nt (streaming), 16 = sc1.
+constexpr int kAuxDefault = 0;
+constexpr int kAuxStream = 2;
+
+template <int V, bool EXACT, typename T, int AUX = kAuxDefault>
+__device__ __forceinline__ void buf_load_row(__amdgpu_buffer_rsrc_t r, uint32_t soff, int q0,
+                                             int nq, T (&out)[V]) {
+    if constexpr (EXACT) {
+        constexpr int B = V * (int)sizeof(T);
+        const uint32_t voff = (uint32_t)q0 * sizeof(T);
+        if constexpr (B % 16 == 0) {
+#pragma unroll
+            for (int i = 0; i < B / 16; ++i) {
+                i32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16 * i, soff, AUX);
+                __builtin_memcpy(&out[i * (16 / sizeof(T))], &v, 16);
+            }
+        } else if constexpr (B == 8) {
+            i32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX);
+            __builtin_memcpy(&out[0], &v, 8);
+        } else {
+            int32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX);
+            __builtin_memcpy(&out[0], &v, 4);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const int q = q0 + k < nq ? q0 + k : nq - 1;           // clamp, then zero
+            T v;
+            if constexpr (sizeof(T) == 4) {
+                int32_t b = __builtin_amdgcn_raw_buffer_load_b32(r, (uint32_t)q * 4u, soff, AUX);
+                __builtin_memcpy(&v, &b, 4);
+            } else {
+                i32x2 b = __builtin_amdgcn_raw_buffer_load_b64(r, (uint32_t)q * 8u, soff, AUX);
+                __builtin_memcpy(&v, &b, 8);
+            }
+            out[k] = q0 + k < nq ? v : T(0);
+        }
+    }
+}
+
+template <int V, bool EXACT, typename T, int AUX = kAuxDefault>
+__device__ __forceinline__ void buf_store_row(__amdgpu_buffer_rsrc_t r, uint32_t soff, int q0,
+                                              int nq, const T (&in)[V]) {
+    if constexpr (EXACT) {
+        constexpr int B = V * (int)sizeof(T);
+        const uint32_t voff = (uint32_t)q0 * sizeof(T);
+        if constexpr (B % 16 == 0) {
+#pragma unroll
+            for (int i = 0; i < B / 16; ++i) {
+                i32x4 v;
+                __builtin_memcpy(&v, &in[i * (16 / sizeof(T))], 16);
+                __builtin_amdgcn_raw_buffer_store_b128(v, r, voff + 16 * i, soff, AUX);
+            }
+        } else if constexpr (B == 8) {
+            i32x2 v;
+            __builtin_memcpy(&v, &in[0], 8);
+            __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, AUX);
+        } else {
+            int32_t v;
+            __builtin_memcpy(&v, &in[0], 4);
+            __builtin_amdgcn_raw_buffer_store_b32(v, r, voff, soff, AUX);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            if (q0 + k >= nq) continue;
+            if constexpr (sizeof(T) == 4) {
+                int32_t b;
+                __builtin_memcpy(&b, &in[k], 4);
+                __builtin_amdgcn_raw_buffer_store_b32(b, r, (uint32_t)(q0 + k) * 4u, soff, AUX);
+            } else {
+                i32x2 b;
+                __builtin_memcpy(&b, &in[k], 8);
+                __builtin_amdgcn_raw_buffer_store_b64(b, r, (uint32_t)(q0 + k) * 8u, soff, AUX);
+            }
+        }
+    }
+}
+
+// Element i of a per-cell array through a scalar load with a 32-bit byte offset.
+template <typename T>
+__device__ __forceinline__ T cell_val(const T* __restrict__ a, int32_t i) {
+    const uint32_t off = (uint32_t)i * (uint32_t)sizeof(T);
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(a) + off);
+}
+
+template <typename G>
+__device__ __forceinline__ const G* cell_rec(const G* __restrict__ g, int32_t i) {
+    const uint32_t off = (uint32_t)i * (uint32_t)sizeof(G);
+    return reinterpret_cast<const G*>(reinterpret_cast<const char*>(g) + off);
+}
+
+// Butterfly all-reduce over the 64 lanes; every lane ends with the same (bitwise) value.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// FP32 all-reduce without LDS traffic: DPP swaps inside each 16-lane row (xor 1, xor 2,
+// half-row mirror, row mirror leave every lane of a row with the same row sum), then the
+// four row sums are read into scalars and added in a fixed order.  Deterministic and
+// wave-uniform.
+template <int CTRL>
+__device__ __forceinline__ float dpp_partner(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+    v += dpp_partner<0xB1>(v);    // quad_perm(1,0,3,2): lane ^ 1
+    v += dpp_partner<0x4E>(v);    // quad_perm(2,3,0,1): lane ^ 2
+    v += dpp_partner<0x141>(v);   // row_half_mirror: lane i <-> 7 - i within 8
+    v += dpp_partner<0x140>(v);   // row_mirror: lane i <-> 15 - i within 16
+    const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
+    const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
+    const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+    const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
+template <typename T>
+__device__ __forceinline__ T cell_sum(T v) {
+    if constexpr (sizeof(T) == 4)
+        return wave_sum_dpp(v);
+    else
+        return wave_sum(v);
+}
+
+// --------------------------------------------------------------------------- forward step
+//
+// Persistent, XCD-partitioned launch: the grid is a multiple of the XCD count; XCD x owns
+// the contiguous (Hilbert-ordered) cell range [x*cpx, (x+1)*cpx) and its waves sweep that
+// range together, one cell per wave per iteration, so neighbour rows are read from the
+// XCD's own L2 shortly after (or before) their owner reads them.  The ordinate table is
+// loaded once per wave.  Rows are read with the default (L2-allocating) policy because each
+// is read again as a neighbour; output rows are written with the streaming policy.
+//
+// Three-stage software pipeline with straight-line memory operations:
+//   stage A (two cells ahead):  the 16-byte neighbour list (scalar load);
+//   stage B (one cell ahead):   own row, the MF face rows, normals and coefficients;
+//   stage C (this cell):        arithmetic and the row store.
+// Every face gets a row pointer and a scale chosen with scalar selects: interior faces read
+// the neighbour row scaled by its 1/rho, Dirichlet faces the inflow row scaled by
+// inflow_scale, Neumann faces the cell's own row scaled by its 1/rho, vacuum and unused
+// faces the cell's own row scaled by 0.  No load sits under a branch, so the waits of
+// stage C cover only this cell's loads.
+
+// Wave-uniform cell index in a scalar register (cell counts are below 2^31).
+__device__ __forceinline__ int32_t uniform_cell(int32_t c) {
+    return __builtin_amdgcn_readfirstlane(c);
+}
+
+template <int MF>
+struct NbrList {
+    int32_t j[MF];
+};
+
+template <int V, int MF, bool DENSE, typename T>
+struct FwdStage {
+    T p[V];
+    T up[MF][V];
+    T src[V];
+    T ghost[MF];
+    T nx[MF], ny[MF];
+    T irho, keep, cflux, cscat, csrc;
+};
+
+// Buffer resources and scalars of one launch.
+template <typename T>
+struct FwdCtx {
+    __amdgpu_buffer_rsrc_t psi, inflow, out, S;
+    uint32_t row_bytes;
+    const T *src_arr;
+    T src_mul, inflow_scale;
+    bool dirichlet, neumann;
+};
+
+template <int MF, typename T>
+__device__ __forceinline__ void fwd_load_nbr(NbrList<MF>& nb,
+                                             const typename GeomOf<T>::type* __restrict__ geom,
+                                             int32_t c)
+{
+    const auto* g = cell_rec(geom, c);
+#pragma unroll
+    for (int f = 0; f < MF; ++f) nb.j[f] = g->nbr[f];
+}
+
+template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T, int LA_OWN = kAuxDefault,
+          int LA_NBR = kAuxDefault>
+__device__ __forceinline__ void fwd_load_stage(FwdStage<V, MF, DENSE, T>& d, const NbrList<MF>& nb,
+                                               const typename GeomOf<T>::type* __restrict__ geom,
+                                               int32_t c, int32_t nq, int q0,
+                                               const typename ArgsOf<T>::type& a,
+                                               const FwdCtx<T>& x)
+{
+    const auto* g = cell_rec(geom, c);
+    const uint32_t own = (uint32_t)c * x.row_bytes;
+    buf_load_row<V, EXACT, T, LA_OWN>(x.psi, own, q0, nq, d.p);
+    d.irho = RHO ? cell_val(a.inv_rho, c) : T(1);
+    // boundary faces: Dirichlet reads the inflow row (scale inflow_scale), Neumann the
+    // cell's own row (scale 1/rho), vacuum the own row with scale 0
+    const T bscale = x.dirichlet ? x.inflow_scale : (x.neumann ? d.irho : T(0));
+#pragma unroll
+    for (int f = 0; f < MF; ++f) {
+        const int32_t j = nb.j[f];
+        const bool bnd = j < 0;
+        const int32_t bidx = x.dirichlet ? -1 - j : c;
+        const uint32_t off = (uint32_t)(bnd ? bidx : j) * x.row_bytes;
+        const T rho_j = RHO ? cell_val(a.inv_rho, bnd ? c : j) : T(1);
+        d.ghost[f] = bnd ? bscale : rho_j;
+        buf_load_row<V, EXACT, T, LA_NBR>(bnd && x.dirichlet ? x.inflow : x.psi, off, q0, nq,
+                                          d.up[f]);
+        d.nx[f] = g->n[f][0];
+        d.ny[f] = g->n[f][1];
+    }
+    if constexpr (DENSE) buf_load_row<V, EXACT>(x.S, own, q0, nq, d.src);
+    d.keep = T(1) - a.dt * a.alpha_t * cell_val(a.sigma_t, c);
+    d.cflux = a.dt * g->inv_area;
+    d.cscat = a.dt * a.alpha_s * cell_val(a.sigma_s, c);
+    d.csrc = x.src_mul * cell_val(x.src_arr, c);
+}
+
+template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T, int SA = kAuxStream>
+__device__ __forceinline__ void fwd_compute(const FwdStage<V, MF, DENSE, T>& d, const T (&ox)[V],
+                                            const T (&oy)[V], const T (&wi)[V], int32_t c,
+                                            int32_t nq, int q0, const FwdCtx<T>& x)
+{
+    T src[V];
+    if constexpr (DENSE) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) src[k] = d.src[k];
+    } else {
+        T part = T(0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) part += wi[k] * d.p[k];
+        const T phi = cell_sum(part);              // (1/4pi) sum_p w_p psi_p
+#pragma unroll
+        for (int k = 0; k < V; ++k) src[k] = phi;
+    }
+    T u[V], acc[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        u[k] = RHO ? d.p[k] * d.irho : d.p[k];
+        acc[k] = T(0);
+    }
+#pragma unroll
+    for (int f = 0; f < MF; ++f) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const T s = ox[k] * d.nx[f] + oy[k] * d.ny[f];
+            const T ub = d.up[f][k] * d.ghost[f];
+            acc[k] += (s > T(0)) ? s * u[k] : s * ub;
+        }
+    }
+    T o[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k)
+        o[k] = d.p[k] * d.keep - d.cflux * acc[k] + d.cscat * src[k] + d.csrc;
+    buf_store_row<V, EXACT, T, SA>(x.out, (uint32_t)c * x.row_bytes, q0, nq, o);
+}
+
+template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T>
+__global__ __launch_bounds__(kStepBlock) void k_step(
+    const typename GeomOf<T>::type* __restrict__ geom, int64_t nc, int32_t nq,
+    const T* __restrict__ tab, typename ArgsOf<T>::type a, const T* __restrict__ psi_in,
+    T* __restrict__ psi_out, const T* __restrict__ S, int64_t cells_per_xcd, uint32_t nbf)
+{
+    // XCD x owns cells [x*cpx, (x+1)*cpx) and all its waves sweep that range together,
+    // four consecutive cells per block per iteration: a row is read as a neighbour within a
+    // short window of its owner's read, while it is still in the XCD's L2.
+    const int x = blockIdx.x % kNumXcd;
+    const int kx = blockIdx.x / kNumXcd;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t stride = (int32_t)(gridDim.x / kNumXcd) * kCellsPerBlock;
+    const int64_t xb = x * cells_per_xcd;
+    if (xb >= nc) return;
+    const int32_t xend = (int32_t)(xb + cells_per_xcd < nc ? xb + cells_per_xcd : nc);
+    int32_t c = (int32_t)xb + kx * kCellsPerBlock + wave;
+    if (c >= xend) return;
+    const int q0 = lane * V;
+
+    FwdCtx<T> cx;
+    cx.row_bytes = (uint32_t)nq * sizeof(T);
+    const uint32_t state_bytes = (uint32_t)nc * cx.row_bytes;
+    cx.psi = make_rsrc(psi_in, state_bytes);
+    cx.out = make_rsrc(psi_out, state_bytes);
+    cx.inflow = make_rsrc(a.inflow ? a.inflow : psi_in, a.inflow ? nbf * cx.row_bytes : 0u);
+    cx.S = make_rsrc(DENSE ? S : psi_in, DENSE ? state_bytes : 0u);
+    // optional per-cell source: read a valid array and scale by 0 when there is none
+    cx.src_arr = a.source ? a.source : a.sigma_t;
+    cx.src_mul = a.source ? a.dt : T(0);
+    cx.inflow_scale = a.inflow_scale;
+    cx.dirichlet = a.inflow != nullptr && !a.neumann;
+    cx.neumann = a.neumann != 0;
+    // prefetches address the clamped cell min(c', xend-1) in [xbeg, xend): always in bounds
+    auto clampc = [xend](int32_t cc) { return uniform_cell(cc < xend ? cc : xend - 1); };
+
+    T ox[V], oy[V], wi[V];
+    load_slice<V, EXACT>(tab, q0, nq, ox);
+    load_slice<V, EXACT>(tab + nq, q0, nq, oy);
+    load_slice<V, EXACT>(tab + 3 * nq, q0, nq, wi);
+
+    NbrList<MF> n0, n1, n2;
+    FwdStage<V, MF, DENSE, T> sa, sb;
+    fwd_load_nbr<MF, T>(n0, geom, c);
+    fwd_load_stage<V, EXACT, MF, RHO, DENSE>(sa, n0, geom, c, nq, q0, a, cx);
+    fwd_load_nbr<MF, T>(n1, geom, clampc(c + stride));
+    for (;;) {
+        // stage B of the next cell into sb, stage A of the one after, stage C of this cell
+        fwd_load_stage<V, EXACT, MF, RHO, DENSE>(sb, n1, geom, clampc(c + stride), nq, q0, a, cx);
+        fwd_load_nbr<MF, T>(n2, geom, clampc(c + 2 * stride));
+        fwd_compute<V, EXACT, MF, RHO, DENSE>(sa, ox, oy, wi, c, nq, q0, cx);
+        c += stride;
+        if (c >= xend) break;
+        n1 = n2;
+        fwd_load_stage<V, EXACT, MF, RHO, DENSE>(sa, n1, geom, clampc(c + stride), nq, q0, a, cx);
+        fwd_load_nbr<MF, T>(n2, geom, clampc(c + 2 * stride));
+        fwd_compute<V, EXACT, MF, RHO, DENSE>(sb, ox, oy, wi, c, nq, q0, cx);
+        c += stride;
+        if (c >= xend) break;
+        n1 = n2;
+    }
+}
+
+// --------------------------------------------------------------------------- adjoint step
+
+template <int V, bool EXACT, bool DENSE, typename T>
+__global__ __launch_bounds__(kStepBlock) void k_adjoint(
+    const typename GeomOf<T>::type* __restrict__ geom, int64_t nc, int32_t mf, int32_t nq,
+    const T* __restrict__ tab, typename ArgsOf<T>::type a, const T* __restrict__ psi_n,
+    const T* __restrict__ lam_np1, T* __restrict__ lam_n, T* __restrict__ g_t,
+    T* __restrict__ g_s, T* __restrict__ g_r, const T* __restrict__ G)
+{
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t c = lb * kCellsPerBlock + wave;
+    if (c >= nc) return;
+    const int q0 = lane * V;
+
+    T ox[V], oy[V], wi[V];
+    load_slice<V, EXACT>(tab, q0, nq, ox);
+    load_slice<V, EXACT>(tab + nq, q0, nq, oy);
+    load_slice<V, EXACT>(tab + 3 * nq, q0, nq, wi);
+
+    const auto* g = geom + c;
+    int32_t nbr[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) nbr[f] = (f < mf) ? g->nbr[f] : kUnusedFace;
+
+    T l[V], p[V];
+    load_slice<V, EXACT>(lam_np1 + c * (int64_t)nq, q0, nq, l);
+    load_slice<V, EXACT>(psi_n + c * (int64_t)nq, q0, nq, p);
+    T ln[4][V];
+    T ia_n[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        ia_n[f] = T(0);
+        if (nbr[f] >= 0) {
+            load_slice<V, EXACT>(lam_np1 + (int64_t)nbr[f] * nq, q0, nq, ln[f]);
+            ia_n[f] = geom[nbr[f]].inv_area;
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) ln[f][j] = T(0);
+        }
+    }
+
+    const T ia = g->inv_area;
+    T x[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) x[j] = T(0);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        if (nbr[f] == kUnusedFace) continue;
+        const T nx = g->n[f][0], ny = g->n[f][1];
+        const bool interior = nbr[f] >= 0;
+        const bool all_signs = !interior && a.neumann;   // Neumann ghost = own value
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const T s = ox[j] * nx + oy[j] * ny;
+            const T d = l[j] * ia - ln[f][j] * ia_n[f];
+            x[j] += (s > T(0) || all_signs) ? s * d : T(0);
+        }
+    }
+
+    const T irho = a.inv_rho ? a.inv_rho[c] : T(1);
+    const T keep = T(1) - a.dt * a.alpha_t * a.sigma_t[c];
+    const T cscat = a.dt * a.alpha_s * a.sigma_s[c];
+    const T cstream = a.dt * irho;
+
+    T src[V];
+    T part_s;                                     // per-lane part of sum_q l_q S_q
+    if constexpr (DENSE) {
+        load_slice<V, EXACT>(G + c * (int64_t)nq, q0, nq, src);   // (Lambda B^T)_cq
+        part_s = T(0);
+#pragma unroll
+        for (int j = 0; j < V; ++j) part_s += p[j] * src[j];
+    } else {
+        T pl = T(0), pw = T(0);
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            pl += l[j];
+            pw += wi[j] * p[j];
+        }
+        const T lsum = wave_sum(pl);
+        const T scell = wave_sum(pw);           // isotropic S of the cell
+#pragma unroll
+        for (int j = 0; j < V; ++j) src[j] = wi[j] * lsum;
+        part_s = (lane == 0) ? scell * lsum : T(0);
+    }
+
+    T o[V];
+    T part_t = T(0), part_r = T(0);
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        o[j] = l[j] * keep - cstream * x[j] + cscat * src[j];
+        part_t += l[j] * p[j];
+        part_r += p[j] * x[j];
+    }
+    store_slice<V, EXACT>(lam_n + c * (int64_t)nq, q0, nq, o);
+
+    if (g_t) {
+        const T s = wave_sum(part_t);
+        if (lane == 0) g_t[c] += -a.dt * a.alpha_t * s;
+    }
+    if (g_s) {
+        const T s = wave_sum(part_s);
+        if (lane == 0) g_s[c] += a.dt * a.alpha_s * s;
+    }
+    if (g_r) {
+        const T s = wave_sum(part_r);
+        if (lane == 0) g_r[c] += a.dt * irho * irho * s;
+    }
+}
+
+// --------------------------------------------------------------------------- dispatch helpers
+
+template <typename T, typename F>
+hipError_t dispatch_v(int32_t nq, F&& f) {
+    const bool exact = (nq % kWave) == 0;
+    const int v = exact ? nq / kWave : (nq + kWave - 1) / kWave;
+    if (exact) {
+        switch (v) {
+            case 1: return f(std::integral_constant<int, 1>{}, std::true_type{});
+            case 2: return f(std::integral_constant<int, 2>{}, std::true_type{});
+            case 4: return f(std::integral_constant<int, 4>{}, std::true_type{});
+            case 8: return f(std::integral_constant<int, 8>{}, std::true_type{});
+            case 16: return f(std::integral_constant<int, 16>{}, std::true_type{});
+            default: break;
+        }
+    }
+    if (v <= 1) return f(std::integral_constant<int, 1>{}, std::false_type{});
+    if (v <= 2) return f(std::integral_constant<int, 2>{}, std::false_type{});
+    if (v <= 4) return f(std::integral_constant<int, 4>{}, std::false_type{});
+    if (v <= 8) return f(std::integral_constant<int, 8>{}, std::false_type{});
+    return f(std::integral_constant<int, 16>{}, std::false_type{});
+}
+
+// Launch shape of the persistent step: ``blocks_per_cu`` resident 4-wave blocks per CU
+// (rounded to the XCD count), never more blocks than there are CPW-cell groups.
+struct StepShape {
+    unsigned blocks;
+    int64_t cells_per_xcd;
+};
+
+inline StepShape step_shape(const snrt_mesh& m, int cpw, int resident_blocks_per_cu) {
+    int bpc = tune().step_blocks_per_cu;
+    if (resident_blocks_per_cu > 0 && bpc > resident_blocks_per_cu) bpc = resident_blocks_per_cu;
+    int64_t want = (m.nc + (int64_t)kCellsPerBlock * cpw - 1) / ((int64_t)kCellsPerBlock * cpw);
+    int64_t cap = (int64_t)m.num_cu * bpc;
+    int64_t b = want < cap ? want : cap;
+    b = (b / kNumXcd) * kNumXcd;             // equal block count per XCD, never above cap
+    if (b < kNumXcd) b = kNumXcd;
+    int64_t cpx = (m.nc + kNumXcd - 1) / kNumXcd;
+    cpx = ((cpx + cpw - 1) / cpw) * cpw;
+    return {(unsigned)b, cpx};
+}
+
+// Blocks of a kernel that fit on one CU at once (registers / LDS), queried once.  A
+// persistent grid larger than this would run its last blocks after the others finish.
+template <typename K>
+int resident_blocks(K kernel) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, kStepBlock, 0) != hipSuccess)
+        n = 0;
+    return n;
+}
+
+template <typename T, int V, bool E, int MF, bool RHO, bool DENSE>
+hipError_t launch_fwd(const typename GeomOf<T>::type* geom, const snrt_mesh& m, const T* tab,
+                      int32_t nq, const typename ArgsOf<T>::type& a, const T* psi_in,
+                      T* psi_out, const T* S, hipStream_t st)
+{
+    static const int occ = resident_blocks(k_step<V, E, MF, RHO, DENSE, T>);
+    const StepShape sh = step_shape(m, 1, occ);
+    hipLaunchKernelGGL((k_step<V, E, MF, RHO, DENSE, T>), dim3(sh.blocks), dim3(kStepBlock),
+                       0, st, geom, m.nc, nq, tab, a, psi_in, psi_out, S, sh.cells_per_xcd,
+                       (uint32_t)m.nbf);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step_t(const typename GeomOf<T>::type* geom, const snrt_mesh& m,
+                         const T* tab, int32_t nq, const typename ArgsOf<T>::type& a,
+                         const T* psi_in, T* psi_out, const T* S, hipStream_t st)
+{
+    if (m.nc == 0) return hipSuccess;
+    const bool rho = a.inv_rho != nullptr, dense = S != nullptr, mf4 = m.mf == 4;
+    return dispatch_v<T>(nq, [&](auto vc, auto ex) {
+        constexpr int V = decltype(vc)::value;
+        constexpr bool E = decltype(ex)::value;
+        auto go = [&](auto mfc, auto rc, auto dc) {
+            constexpr int MF = decltype(mfc)::value;
+            constexpr bool R = decltype(rc)::value;
+            constexpr bool D = decltype(dc)::value;
+            return launch_fwd<T, V, E, MF, R, D>(geom, m, tab, nq, a, psi_in, psi_out, S, st);
+        };
+        using I3 = std::integral_constant<int, 3>;
+        using I4 = std::integral_constant<int, 4>;
+        using Tt = std::true_type;
+        using Ff = std::false_type;
+        if (!mf4) {
+            if (rho) return dense ? go(I3{}, Tt{}, Tt{}) : go(I3{}, Tt{}, Ff{});
+            return dense ? go(I3{}, Ff{}, Tt{}) : go(I3{}, Ff{}, Ff{});
+        }
+        if (rho) return dense ? go(I4{}, Tt{}, Tt{}) : go(I4{}, Tt{}, Ff{});
+        return dense ? go(I4{}, Ff{}, Tt{}) : go(I4{}, Ff{}, Ff{});
+    });
+}
+
+inline unsigned step_blocks(int64_t nc) {
+    return (unsigned)((nc + kCellsPerBlock - 1) / kCellsPerBlock);
+}
+
+template <typename T>
+hipError_t launch_adjoint_t(const typename GeomOf<T>::type* geom, const snrt_mesh& m,
+                            const T* tab, int32_t nq, const typename ArgsOf<T>::type& a,
+                            const T* psi_n, const T* lam_np1, T* lam_n, T* g_t, T* g_s, T* g_r,
+                            const T* G, hipStream_t st)
+{
+    if (m.nc == 0) return hipSuccess;
+    return dispatch_v<T>(nq, [&](auto vc, auto ex) {
+        constexpr int V = decltype(vc)::value;
+        constexpr bool E = decltype(ex)::value;
+        if (G)
+            hipLaunchKernelGGL((k_adjoint<V, E, true, T>), dim3(step_blocks(m.nc)),
+                               dim3(kStepBlock), 0, st, geom, m.nc, m.mf, nq, tab, a, psi_n,
+                               lam_np1, lam_n, g_t, g_s, g_r, G);
+        else
+            hipLaunchKernelGGL((k_adjoint<V, E, false, T>), dim3(step_blocks(m.nc)),
+                               dim3(kStepBlock), 0, st, geom, m.nc, m.mf, nq, tab, a, psi_n,
+                               lam_np1, lam_n, g_t, g_s, g_r, G);
+        return hipGetLastError();
+    });
+}
+
+}  // namespace snrt

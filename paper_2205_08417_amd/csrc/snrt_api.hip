@@ -2,6 +2,8 @@
 // Declarations and the meaning of every argument are in include/snrt.h.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -82,6 +84,18 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+const Tune& tune() {
+    static const Tune t = [] {
+        Tune r;
+        if (const char* e = std::getenv("SNRT_STEP_TUNE")) {
+            int bpc = 0;
+            if (std::sscanf(e, "%d", &bpc) == 1 && bpc >= 1 && bpc <= 64) r.step_blocks_per_cu = bpc;
+        }
+        return r;
+    }();
+    return t;
+}
 
 snrt_status hip_fail(hipError_t e, const char* what) {
     set_error(std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
@@ -208,8 +222,11 @@ snrt_status snrt_mesh_create(snrt_mesh** out, int64_t nc, int32_t mf, const int3
         for (int f = 0; f < 4; ++f) {
             int32_t j = f < mf ? face_nbr[i * mf + f] : kUnusedFace;
             if (j >= 0) j = (int32_t)to_int[j];
+            // an unused slot becomes a face to the cell itself with a zero normal: it then
+            // contributes nothing to the flux and needs no special case in the kernels
+            if (j == kUnusedFace) j = (int32_t)k;
             a.nbr[f] = b.nbr[f] = j;
-            if (f < mf && j != kUnusedFace) {
+            if (f < mf && face_nbr[i * mf + f] != kUnusedFace) {
                 b.n[f][0] = face_normal[(i * mf + f) * 2];
                 b.n[f][1] = face_normal[(i * mf + f) * 2 + 1];
                 a.n[f][0] = (float)b.n[f][0];
@@ -227,6 +244,11 @@ snrt_status snrt_mesh_create(snrt_mesh** out, int64_t nc, int32_t mf, const int3
     if (e != hipSuccess) {
         delete m;
         return hip_fail(e, "snrt_mesh_create: hipGetDevice");
+    }
+    e = hipDeviceGetAttribute(&m->num_cu, hipDeviceAttributeMultiprocessorCount, m->device);
+    if (e != hipSuccess || m->num_cu <= 0) {
+        delete m;
+        return hip_fail(e, "snrt_mesh_create: compute unit count");
     }
     m->nc = nc;
     m->nbf = nbf;
@@ -439,6 +461,9 @@ snrt_status check_step_common(const char* fn, const snrt_mesh* m, const snrt_qua
     SNRT_REQUIRE(aligned16(in) && aligned16(out), SNRT_E_ARG,
                  std::string(fn) + ": state pointers must be 16-byte aligned");
     const size_t bytes = (size_t)m->nc * q->nq * elem;
+    SNRT_REQUIRE(bytes < (size_t(1) << 32) && (size_t)m->nbf * q->nq * elem < (size_t(1) << 32),
+                 SNRT_E_UNSUPPORTED,
+                 std::string(fn) + ": a state array of 4 GiB or more is not supported");
     SNRT_REQUIRE(!ranges_overlap(in, bytes, out, bytes), SNRT_E_ALIAS,
                  std::string(fn) + ": output aliases input");
     if (sc->dense) {

@@ -18,7 +18,7 @@ constexpr int kCellsPerBlock = kStepBlock / kWave;
 constexpr int kNumXcd = 8;             // MI355X: 8 accelerator complex dies
 
 // Per-cell geometry record, one 64-byte line: neighbours, n_ij (outward normal x length),
-// 1/A_i and A_i.  Unused face slots have nbr = kUnusedFace and a zero normal.
+// 1/A_i and A_i.  An unused face slot points at the cell itself with a zero normal.
 struct alignas(64) CellGeom32 {
     int32_t nbr[4];
     float n[4][2];
@@ -65,6 +65,7 @@ struct snrt_mesh {
     int64_t* d_to_user = nullptr;          // device copy of to_user
     double* d_partial = nullptr;           // per-block partial sums for snrt_mass
     int64_t n_partial = 0;
+    int num_cu = 256;                      // compute units of the device (launch shapes)
 };
 
 struct snrt_quad {
@@ -83,6 +84,13 @@ struct snrt_scatter {
 };
 
 namespace snrt {
+
+// Launch-shape knobs of the persistent kernels.  Defaults are the tuned values for MI355X;
+// SNRT_STEP_TUNE="<blocks per CU>" overrides them (read once per process).
+struct Tune {
+    int step_blocks_per_cu = 3;
+};
+const Tune& tune();
 
 void set_error(const std::string& msg);
 snrt_status hip_fail(hipError_t e, const char* what);
