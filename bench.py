@@ -28,6 +28,8 @@ if ROOT not in sys.path:
 
 METRIC = "cell-ordinate updates/s per S_N step (FP32 vs mixed) + adjoint/forward ratio"
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, vendor figure
+BF16_PEAK_TFLOPS = 2500.0       # MI355X dense BF16 MFMA, vendor figure
+DENSE_WORKLOAD = "linesource_hg_s32"
 WORKLOAD = "checkerboard_s16"
 STEP_SOURCES = [os.path.join(ROOT, "paper_2205_08417_amd", "csrc", f)
                 for f in ("sn_step_kernels.h", "sn_step_f32.hip")]
@@ -74,6 +76,60 @@ def cpu_baseline(P, budget_s: float = 12.0):
                       f"({P.ncells} cells x {P.nq} ordinates), {el:.1f} s wall"}
 
 
+def timed(fn, n, stream):
+    """Average milliseconds of ``fn`` over n calls, bracketed by events on ``stream``."""
+    import torch
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(n):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / n
+
+
+def bench_dense(steps: int, warmup: int):
+    """Anisotropic HG line source (100 352 cells x 1024 ordinates) with the BF16 hi+lo MFMA
+    scattering product: whole-step rate and the product's MFMA utilisation."""
+    import torch
+    from paper_2205_08417_amd import inputs as I
+    from paper_2205_08417_amd import snrt
+    from paper_2205_08417_amd.solver import Solver
+
+    P = I.build(DENSE_WORKLOAD)
+    S = Solver(P, precision="bf16x3")
+    a = S.initial_state()
+    b = torch.empty_like(a)
+    sbuf = torch.empty_like(a)
+    args = S.args()
+    stream = torch.cuda.current_stream()
+    state = [a, b]
+
+    def one_step():
+        S.step(state[0], state[1], args)
+        state.reverse()
+
+    def product():
+        snrt.snrt_scatter_apply(S.mesh, S.quad, S.scatter, state[0], sbuf)
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    ms_step = timed(one_step, steps, stream)
+    ms_prod = timed(product, steps, stream)
+    flops = 3 * 2.0 * P.ncells * P.nq * P.nq          # three BF16 products per output
+    tflops = flops / (ms_prod * 1e-3) / 1e12
+    S.close()
+    return {"workload": DENSE_WORKLOAD, "cells": P.ncells, "ordinates": P.nq,
+            "scattering": "Henyey-Greenstein g=0.9, dense, column-normalised",
+            "precision": "bf16x3 (hi+lo split, FP32 accumulate)", "steps": steps,
+            "value": P.ncells * P.nq / (ms_step * 1e-3), "unit": "cell-ordinate updates/s",
+            "ms_per_step": ms_step,
+            "scatter_product": {"kernel": "k_gemm_bf16<true>", "ms": ms_prod,
+                                "executed_tflops": tflops, "peak_tflops": BF16_PEAK_TFLOPS,
+                                "mfma_utilization": tflops / BF16_PEAK_TFLOPS}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +138,9 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="replay the timed steps from a captured HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the mixed-precision anisotropic measurement")
+    ap.add_argument("--dense-steps", type=int, default=40)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of one state (for HBM counter scaling)")
     args = ap.parse_args()
@@ -165,9 +224,11 @@ def main():
                      "kernel": "k_step<4,true,3,false,false,float>",
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
+    S.close()
+    if not args.no_dense:
+        out["mixed_precision"] = bench_dense(args.dense_steps, 5)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P)
-    S.close()
     print(json.dumps(out), flush=True)
 
 

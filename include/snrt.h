@@ -112,14 +112,15 @@ void snrt_quad_destroy(snrt_quad* quad);
  *   per cell without forming K.
  * snrt_scatter_dense: K host [nq*nq] row-major (K[q*nq+p]), applied as a GEMM
  *   S = Psi B with B[p][q] = w_p K[q][p], at the given precision.  BF16 modes need
- *   nq % 64 == 0. */
+ *   nq % 256 == 0 (SNRT_E_UNSUPPORTED otherwise). */
 snrt_status snrt_scatter_isotropic(snrt_scatter** out, const snrt_quad* quad);
 snrt_status snrt_scatter_dense(snrt_scatter** out, const snrt_quad* quad, const double* K,
                                snrt_precision precision);
 void snrt_scatter_destroy(snrt_scatter* scatter);
 
 /* Bytes of device workspace snrt_step / snrt_step_adjoint need for this combination
- * (0 for isotropic scattering; one [ncells][nq] FP32 buffer for dense scattering). */
+ * (0 for isotropic scattering; one [ncells][nq] FP64-sized buffer for dense scattering, which
+ * serves both the FP32 and the FP64 entry points). */
 snrt_status snrt_workspace_size(const snrt_mesh* mesh, const snrt_quad* quad,
                                 const snrt_scatter* scatter, size_t* bytes);
 
@@ -192,6 +193,15 @@ snrt_status snrt_step_adjoint_f64(const snrt_mesh* mesh, const snrt_quad* quad,
                                   const double* psi_n, const double* lam_np1, double* lam_n,
                                   double* g_sigma_t, double* g_sigma_s, double* g_rho,
                                   void* ws, size_t ws_bytes, void* stream);
+
+/* The dense scattering product alone (the S term of eq. SNEqns without the update):
+ *   transpose = 0:  S[c][q] = sum_p K[q][p] w_p psi[c][p]          (S = Psi B)
+ *   transpose = 1:  S[c][p] = w_p sum_q K[q][p] psi[c][q]          (Lambda B^T, adjoint side)
+ * psi, S: device [ncells][nq] FP32, S must not alias psi.  Only for dense scatter handles
+ * (SNRT_E_UNSUPPORTED for isotropic). */
+snrt_status snrt_scatter_apply(const snrt_mesh* mesh, const snrt_quad* quad,
+                               const snrt_scatter* scatter, const float* psi, float* S,
+                               int32_t transpose, void* stream);
 
 /* ---------------------------------------------------------------- reductions */
 

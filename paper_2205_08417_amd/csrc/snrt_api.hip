@@ -372,8 +372,8 @@ snrt_status snrt_scatter_dense(snrt_scatter** out, const snrt_quad* q, const dou
                  SNRT_E_ARG, "snrt_scatter_dense: unknown precision");
     const int32_t nq = q->nq;
     if (precision != SNRT_FP32) {
-        SNRT_REQUIRE(nq % 64 == 0, SNRT_E_UNSUPPORTED,
-                     "snrt_scatter_dense: BF16 modes need nq % 64 == 0");
+        SNRT_REQUIRE(nq % 256 == 0, SNRT_E_UNSUPPORTED,
+                     "snrt_scatter_dense: BF16 modes need nq % 256 == 0");
     }
     SNRT_TRY(check_device(q->device, "snrt_scatter_dense"));
     const size_t n2 = (size_t)nq * nq;
@@ -608,6 +608,23 @@ snrt_status snrt_step_adjoint_f64(const snrt_mesh* m, const snrt_quad* q, const 
     }
     hipError_t e = launch_adjoint64(*m, *q, to64(a), psi_n, lam_np1, lam_n, g_t, g_s, g_r, G, st);
     return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_step_adjoint_f64: launch");
+}
+
+snrt_status snrt_scatter_apply(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
+                               const float* psi, float* S, int32_t transpose, void* stream) {
+    g_last_error.clear();
+    SNRT_REQUIRE(m && q && sc, SNRT_E_ARG, "snrt_scatter_apply: NULL handle");
+    SNRT_REQUIRE(sc->dense, SNRT_E_UNSUPPORTED, "snrt_scatter_apply: needs a dense scatter handle");
+    SNRT_REQUIRE(sc->B.nq == q->nq, SNRT_E_SHAPE, "snrt_scatter_apply: scatter/quad nq differ");
+    SNRT_REQUIRE(transpose == 0 || transpose == 1, SNRT_E_ARG, "snrt_scatter_apply: transpose is 0 or 1");
+    SNRT_TRY(check_device(m->device, "snrt_scatter_apply"));
+    if (m->nc == 0) return SNRT_OK;
+    SNRT_REQUIRE(psi && S && aligned16(psi) && aligned16(S), SNRT_E_ARG,
+                 "snrt_scatter_apply: NULL or misaligned array");
+    const size_t bytes = (size_t)m->nc * q->nq * sizeof(float);
+    SNRT_REQUIRE(!ranges_overlap(psi, bytes, S, bytes), SNRT_E_ALIAS, "snrt_scatter_apply: S aliases psi");
+    hipError_t e = dense_product32(sc, psi, S, m->nc, transpose != 0, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_scatter_apply: launch");
 }
 
 // ------------------------------------------------------------------------------- reductions

@@ -43,8 +43,8 @@ EXPORTS = [
     "snrt_mesh_info", "snrt_mesh_destroy", "snrt_quad_create", "snrt_quad_destroy",
     "snrt_scatter_isotropic", "snrt_scatter_dense", "snrt_scatter_destroy",
     "snrt_workspace_size", "snrt_step", "snrt_step_f64", "snrt_step_adjoint",
-    "snrt_step_adjoint_f64", "snrt_mass", "snrt_scalar_flux", "snrt_dose_accumulate",
-    "snrt_permute",
+    "snrt_step_adjoint_f64", "snrt_scatter_apply", "snrt_mass", "snrt_scalar_flux",
+    "snrt_dose_accumulate", "snrt_permute",
 ]
 
 
@@ -103,6 +103,7 @@ def lib() -> ctypes.CDLL:
                                     _vp, _vp, _vp, ctypes.c_size_t, _vp]),
         "snrt_step_adjoint_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp,
                                         _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+        "snrt_scatter_apply": (_st, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp]),
         "snrt_mass": (_st, [_vp, _vp, _vp, _vp, _vp]),
         "snrt_scalar_flux": (_st, [_vp, _vp, _vp, _vp, _vp]),
         "snrt_dose_accumulate": (_st, [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp]),
@@ -266,6 +267,11 @@ def snrt_step_adjoint_f64(mesh, quad, scatter, args: StepArgs, psi_n, lam_np1, l
                                        _ptr(lam_np1), _ptr(lam_n), _ptr(g_sigma_t),
                                        _ptr(g_sigma_s), _ptr(g_rho), _ptr(ws), int(ws_bytes),
                                        _stream(stream)))
+
+
+def snrt_scatter_apply(mesh, quad, scatter, psi, S, transpose=0, stream=None) -> None:
+    _check("snrt_scatter_apply", lib().snrt_scatter_apply(mesh, quad, scatter, _ptr(psi), _ptr(S),
+                                                          int(transpose), _stream(stream)))
 
 
 def snrt_mass(mesh, quad, psi, out_dev, stream=None) -> None:
