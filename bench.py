@@ -130,6 +130,41 @@ def bench_dense(steps: int, warmup: int):
                                 "mfma_utilization": tflops / BF16_PEAK_TFLOPS}}
 
 
+def bench_adjoint(nsteps: int = 400, ckpt: int = 20):
+    """Checkerboard adjoint workload (51 842 cells x 256 ordinates, 400 steps, checkpoints
+    every 20): forward rollout vs backward pass (segment recompute + adjoint steps) for
+    J = integrated scalar flux over [5,6]x[3,4]."""
+    import torch
+    from paper_2205_08417_amd import inputs as I
+    from paper_2205_08417_amd.solver import Solver, differentiable_rollout
+
+    P = I.build("checkerboard_adjoint_s16", nsteps=nsteps)
+    S = Solver(P)
+    region = I.region_mask(P.mesh, P.meta["detector"])
+    W = S.to_internal((region * P.mesh.area)[:, None] * P.w[None, :])
+    st = S.mats32["sigma_t"].clone().requires_grad_(True)
+    ss = S.mats32["sigma_s"].clone().requires_grad_(True)
+    psi0 = S.initial_state()
+    stream = torch.cuda.current_stream()
+    # warm-up (compiles nothing, but settles clocks and allocations)
+    differentiable_rollout(S, psi0, 20, st, ss, ckpt_every=ckpt).sum().backward()
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record(stream)
+    psiN = differentiable_rollout(S, psi0, nsteps, st, ss, ckpt_every=ckpt)
+    J = torch.sum(W * psiN)
+    e[1].record(stream)
+    J.backward()
+    e[2].record(stream)
+    torch.cuda.synchronize()
+    fwd, bwd = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+    S.close()
+    return {"workload": "checkerboard_adjoint_s16", "cells": P.ncells, "ordinates": P.nq,
+            "steps": nsteps, "checkpoint_every": ckpt, "forward_ms": fwd, "backward_ms": bwd,
+            "adjoint_forward_ratio": bwd / fwd,
+            "note": "backward = segment recompute from checkpoints + adjoint steps"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +176,8 @@ def main():
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the mixed-precision anisotropic measurement")
     ap.add_argument("--dense-steps", type=int, default=40)
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward cost measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of one state (for HBM counter scaling)")
     args = ap.parse_args()
@@ -227,6 +264,8 @@ def main():
     S.close()
     if not args.no_dense:
         out["mixed_precision"] = bench_dense(args.dense_steps, 5)
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P)
     print(json.dumps(out), flush=True)

@@ -220,6 +220,18 @@ snrt_status snrt_dose_accumulate(const snrt_mesh* mesh, const snrt_quad* quad, c
                                  const float* inv_rho, double coeff, double* dose,
                                  void* stream);
 
+/* Adjoint of snrt_dose_accumulate for a functional J(D): with g_dose = dJ/dD,
+ *     lam[i][q] += coeff * w_q * inv_rho[i] * g_dose[i]          (lam FP32, g_dose FP64)
+ * (the dose term of step n contributes coeff_n w_q (dJ/dD_i) / rho_i to dJ/dpsi^n_iq). */
+snrt_status snrt_dose_adjoint(const snrt_mesh* mesh, const snrt_quad* quad, const float* inv_rho,
+                              double coeff, const double* g_dose, float* lam, void* stream);
+
+/* Explicit density derivative of the dose D_i = (1/rho_i) sum_n coeff_n phi_i^n:
+ *     g_rho[i] += -dose[i] * inv_rho[i] * g_dose[i]             (g_rho FP32, dose/g_dose FP64) */
+snrt_status snrt_dose_density_grad(const snrt_mesh* mesh, const double* dose,
+                                   const float* inv_rho, const double* g_dose, float* g_rho,
+                                   void* stream);
+
 /* Row permutation between user (direction 0 -> internal) and internal (direction 1 -> user)
  * cell order for [ncells][row_bytes] device arrays; row_bytes a positive multiple of 4. */
 snrt_status snrt_permute(const snrt_mesh* mesh, int32_t to_user, const void* in, void* out,

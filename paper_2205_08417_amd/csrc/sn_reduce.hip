@@ -103,6 +103,32 @@ __global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ in
     for (int64_t i = threadIdx.x; i < words; i += 256) out[dst * words + i] = in[src * words + i];
 }
 
+// lam[c][q] += coeff * w_q * inv_rho[c] * g_dose[c]: one wavefront per cell
+__global__ __launch_bounds__(kStepBlock) void k_dose_adjoint(const double* __restrict__ w,
+                                                             const float* __restrict__ inv_rho,
+                                                             double coeff,
+                                                             const double* __restrict__ g_dose,
+                                                             float* __restrict__ lam, int64_t nc,
+                                                             int32_t nq)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+    const int64_t c = (int64_t)blockIdx.x * kCellsPerBlock + wave;
+    if (c >= nc) return;
+    const double g = coeff * (inv_rho ? (double)inv_rho[c] : 1.0) * g_dose[c];
+    float* row = lam + c * (int64_t)nq;
+    for (int q = lane; q < nq; q += kWave) row[q] = (float)((double)row[q] + g * w[q]);
+}
+
+__global__ __launch_bounds__(256) void k_dose_density_grad(const double* __restrict__ dose,
+                                                           const float* __restrict__ inv_rho,
+                                                           const double* __restrict__ g_dose,
+                                                           float* __restrict__ g_rho, int64_t nc)
+{
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= nc) return;
+    g_rho[c] = (float)((double)g_rho[c] - dose[c] * (inv_rho ? (double)inv_rho[c] : 1.0) * g_dose[c]);
+}
+
 inline unsigned blocks_for(int64_t nc) {
     return (unsigned)((nc + kCellsPerBlock - 1) / kCellsPerBlock);
 }
@@ -146,6 +172,22 @@ hipError_t launch_permute(const snrt_mesh& m, int to_user, const void* in, void*
     hipLaunchKernelGGL(k_permute, dim3((unsigned)m.nc), dim3(256), 0, st,
                        static_cast<const uint32_t*>(in), static_cast<uint32_t*>(out),
                        m.d_to_user, m.nc, row_bytes / 4, to_user);
+    return hipGetLastError();
+}
+
+hipError_t launch_dose_adjoint(const snrt_mesh& m, const snrt_quad& q, const float* inv_rho,
+                               double coeff, const double* g_dose, float* lam, hipStream_t st) {
+    if (m.nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dose_adjoint, dim3(blocks_for(m.nc)), dim3(kStepBlock), 0, st,
+                       q.tab64 + 2 * (int64_t)q.nq, inv_rho, coeff, g_dose, lam, m.nc, q.nq);
+    return hipGetLastError();
+}
+
+hipError_t launch_dose_density_grad(const snrt_mesh& m, const double* dose, const float* inv_rho,
+                                    const double* g_dose, float* g_rho, hipStream_t st) {
+    if (m.nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dose_density_grad, dim3((unsigned)((m.nc + 255) / 256)), dim3(256), 0, st,
+                       dose, inv_rho, g_dose, g_rho, m.nc);
     return hipGetLastError();
 }
 

@@ -660,6 +660,30 @@ snrt_status snrt_dose_accumulate(const snrt_mesh* m, const snrt_quad* q, const f
     return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_dose_accumulate: launch");
 }
 
+snrt_status snrt_dose_adjoint(const snrt_mesh* m, const snrt_quad* q, const float* inv_rho,
+                              double coeff, const double* g_dose, float* lam, void* stream) {
+    g_last_error.clear();
+    SNRT_REQUIRE(m && q, SNRT_E_ARG, "snrt_dose_adjoint: NULL handle");
+    SNRT_REQUIRE((g_dose && lam) || m->nc == 0, SNRT_E_ARG, "snrt_dose_adjoint: NULL array");
+    SNRT_REQUIRE(is_finite(coeff), SNRT_E_NONFINITE, "snrt_dose_adjoint: non-finite coeff");
+    SNRT_TRY(check_device(m->device, "snrt_dose_adjoint"));
+    hipError_t e = launch_dose_adjoint(*m, *q, inv_rho, coeff, g_dose, lam,
+                                       static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_dose_adjoint: launch");
+}
+
+snrt_status snrt_dose_density_grad(const snrt_mesh* m, const double* dose, const float* inv_rho,
+                                   const double* g_dose, float* g_rho, void* stream) {
+    g_last_error.clear();
+    SNRT_REQUIRE(m, SNRT_E_ARG, "snrt_dose_density_grad: NULL mesh");
+    SNRT_REQUIRE((dose && g_dose && g_rho) || m->nc == 0, SNRT_E_ARG,
+                 "snrt_dose_density_grad: NULL array");
+    SNRT_TRY(check_device(m->device, "snrt_dose_density_grad"));
+    hipError_t e = launch_dose_density_grad(*m, dose, inv_rho, g_dose, g_rho,
+                                            static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_dose_density_grad: launch");
+}
+
 snrt_status snrt_permute(const snrt_mesh* m, int32_t to_user, const void* in, void* out,
                          int64_t row_bytes, void* stream) {
     g_last_error.clear();

@@ -138,6 +138,10 @@ hipError_t launch_dose(const snrt_mesh& m, const snrt_quad& q, const float* psi,
                        const float* inv_rho, double coeff, double* dose, hipStream_t st);
 hipError_t launch_permute(const snrt_mesh& m, int to_user, const void* in, void* out,
                           int64_t row_bytes, hipStream_t st);
+hipError_t launch_dose_adjoint(const snrt_mesh& m, const snrt_quad& q, const float* inv_rho,
+                               double coeff, const double* g_dose, float* lam, hipStream_t st);
+hipError_t launch_dose_density_grad(const snrt_mesh& m, const double* dose, const float* inv_rho,
+                                    const double* g_dose, float* g_rho, hipStream_t st);
 
 // XCD-aware mapping of a hardware block index to a logical block index: blocks are
 // dispatched round-robin over the XCDs, so give XCD x a contiguous range of logical blocks.

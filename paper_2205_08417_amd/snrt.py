@@ -44,7 +44,7 @@ EXPORTS = [
     "snrt_scatter_isotropic", "snrt_scatter_dense", "snrt_scatter_destroy",
     "snrt_workspace_size", "snrt_step", "snrt_step_f64", "snrt_step_adjoint",
     "snrt_step_adjoint_f64", "snrt_scatter_apply", "snrt_mass", "snrt_scalar_flux",
-    "snrt_dose_accumulate", "snrt_permute",
+    "snrt_dose_accumulate", "snrt_dose_adjoint", "snrt_dose_density_grad", "snrt_permute",
 ]
 
 
@@ -107,6 +107,8 @@ def lib() -> ctypes.CDLL:
         "snrt_mass": (_st, [_vp, _vp, _vp, _vp, _vp]),
         "snrt_scalar_flux": (_st, [_vp, _vp, _vp, _vp, _vp]),
         "snrt_dose_accumulate": (_st, [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp]),
+        "snrt_dose_adjoint": (_st, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
+        "snrt_dose_density_grad": (_st, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "snrt_permute": (_st, [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int64, _vp]),
     }
     for name, (res, args) in sig.items():
@@ -287,6 +289,17 @@ def snrt_dose_accumulate(mesh, quad, psi, inv_rho, coeff, dose, stream=None) -> 
     _check("snrt_dose_accumulate",
            lib().snrt_dose_accumulate(mesh, quad, _ptr(psi), _ptr(inv_rho), float(coeff),
                                       _ptr(dose), _stream(stream)))
+
+
+def snrt_dose_adjoint(mesh, quad, inv_rho, coeff, g_dose, lam, stream=None) -> None:
+    _check("snrt_dose_adjoint", lib().snrt_dose_adjoint(mesh, quad, _ptr(inv_rho), float(coeff),
+                                                        _ptr(g_dose), _ptr(lam), _stream(stream)))
+
+
+def snrt_dose_density_grad(mesh, dose, inv_rho, g_dose, g_rho, stream=None) -> None:
+    _check("snrt_dose_density_grad",
+           lib().snrt_dose_density_grad(mesh, _ptr(dose), _ptr(inv_rho), _ptr(g_dose), _ptr(g_rho),
+                                        _stream(stream)))
 
 
 def snrt_permute(mesh, to_user: int, src, dst, row_bytes: int, stream=None) -> None:

@@ -171,3 +171,124 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------------------------------
+# Differentiable rollout: hand-written adjoint steps with checkpoint-and-recompute
+# ------------------------------------------------------------------------------------------
+
+def _seq(x, n, default=1.0):
+    return [default] * n if x is None else [float(v) for v in x]
+
+
+class SNRollout(torch.autograd.Function):
+    """``nsteps`` explicit S_N steps as one differentiable operation.
+
+    Inputs (device tensors, internal cell order): ``psi0`` [nc, nq] (FP32, or FP64 for the
+    parity template), per-cell ``sigma_t``, ``sigma_s`` and optional density ``rho``.  The
+    forward pass keeps the state every ``ckpt_every`` steps; the backward pass recomputes
+    each segment from its checkpoint (bit-identical: the kernels are deterministic) and walks
+    it backwards with the library's adjoint step:
+
+        lam^N = dJ/dpsi^N,  lam^n = T_n^T lam^{n+1} + dJ/dpsi^n,
+        dJ/dsigma_t, dJ/dsigma_s, dJ/drho accumulated by the adjoint kernel per step.
+
+    With ``dose_coeff`` the dose D_i += coeff_n (1/rho_i) phi_i(psi^n) is accumulated before
+    every step n (FP64) and returned as a second output; its adjoint adds
+    coeff_n w_q (dJ/dD_i)/rho_i to lam^n and -D_i/rho_i dJ/dD_i to dJ/drho_i.
+    """
+
+    @staticmethod
+    def forward(ctx, psi0, sigma_t, sigma_s, rho, solver, nsteps, ckpt_every, alpha_t, alpha_s,
+                inflow_scale, dose_coeff):
+        S = solver
+        fp64 = psi0.dtype == torch.float64
+        if fp64 and dose_coeff is not None:
+            raise ValueError("the dose accumulation runs on FP32 states")
+        at, as_, isc = (_seq(alpha_t, nsteps), _seq(alpha_s, nsteps), _seq(inflow_scale, nsteps))
+        inv_rho = None if rho is None else torch.reciprocal(rho.detach()).contiguous()
+        st, ss = sigma_t.detach().contiguous(), sigma_s.detach().contiguous()
+        M = S.mats64 if fp64 else S.mats32
+        if M is None:
+            S.mats64 = S._materials(torch.float64)
+            M = S.mats64
+
+        def args(n):
+            return snrt.step_args(st, ss, S.P.dt, inv_rho=inv_rho, source=M["source"],
+                                  inflow=M["inflow"], inflow_scale=isc[n], alpha_t=at[n],
+                                  alpha_s=as_[n])
+
+        stepper = snrt.snrt_step_f64 if fp64 else snrt.snrt_step
+        a = psi0.detach().contiguous().clone()
+        b = torch.empty_like(a)
+        dose = (torch.zeros(S.nc, dtype=torch.float64, device=a.device)
+                if dose_coeff is not None else None)
+        ckpts = []
+        for n in range(nsteps):
+            if n % ckpt_every == 0:
+                ckpts.append(a.clone())
+            if dose is not None:
+                snrt.snrt_dose_accumulate(S.mesh, S.quad, a, inv_rho, float(dose_coeff[n]), dose)
+            stepper(S.mesh, S.quad, S.scatter, args(n), a, b, S.ws, S.ws_bytes)
+            a, b = b, a
+        ctx.S, ctx.fp64, ctx.nsteps, ctx.K = S, fp64, nsteps, ckpt_every
+        ctx.args, ctx.ckpts, ctx.dose_coeff = args, ckpts, dose_coeff
+        ctx.has_rho = rho is not None
+        ctx.save_for_backward(st, ss, inv_rho if inv_rho is not None else st,
+                              dose if dose is not None else st)
+        if dose is not None:
+            return a, dose
+        return a
+
+    @staticmethod
+    def backward(ctx, g_psi, g_dose=None):
+        S, fp64, N, K = ctx.S, ctx.fp64, ctx.nsteps, ctx.K
+        st, ss, inv_rho, dose = ctx.saved_tensors
+        if not ctx.has_rho:
+            inv_rho = None
+        if ctx.dose_coeff is None:
+            dose = None
+        dt = torch.float64 if fp64 else torch.float32
+        dev = st.device
+        lam = (torch.zeros((S.nc, S.nq), dtype=dt, device=dev) if g_psi is None
+               else g_psi.to(dt).contiguous().clone())
+        lam_new = torch.empty_like(lam)
+        g_t = torch.zeros(S.nc, dtype=dt, device=dev)
+        g_s = torch.zeros(S.nc, dtype=dt, device=dev)
+        g_r = torch.zeros(S.nc, dtype=dt, device=dev) if inv_rho is not None else None
+        gd = None if (g_dose is None or dose is None) else g_dose.to(torch.float64).contiguous()
+        stepper = snrt.snrt_step_f64 if fp64 else snrt.snrt_step
+        adjoint = snrt.snrt_step_adjoint_f64 if fp64 else snrt.snrt_step_adjoint
+        seg = [torch.empty_like(lam) for _ in range(K)]
+        for k in range(len(ctx.ckpts) - 1, -1, -1):
+            n0 = k * K
+            L = min(K, N - n0)
+            states = [ctx.ckpts[k]] + seg[1:L]
+            for i in range(L - 1):                          # recompute the segment
+                stepper(S.mesh, S.quad, S.scatter, ctx.args(n0 + i), states[i], states[i + 1],
+                        S.ws, S.ws_bytes)
+            for i in range(L - 1, -1, -1):
+                n = n0 + i
+                adjoint(S.mesh, S.quad, S.scatter, ctx.args(n), states[i], lam, lam_new, g_t, g_s,
+                        g_r, S.ws, S.ws_bytes)
+                if gd is not None:
+                    snrt.snrt_dose_adjoint(S.mesh, S.quad, inv_rho, float(ctx.dose_coeff[n]), gd,
+                                           lam_new)
+                lam, lam_new = lam_new, lam
+        if gd is not None and g_r is not None:
+            snrt.snrt_dose_density_grad(S.mesh, dose, inv_rho, gd, g_r)
+        return (lam, g_t, g_s, g_r, None, None, None, None, None, None, None)
+
+
+def differentiable_rollout(solver: Solver, psi0, nsteps, sigma_t=None, sigma_s=None, rho=None,
+                           ckpt_every: int = 20, alpha_t=None, alpha_s=None, inflow_scale=None,
+                           dose_coeff=None):
+    """Convenience wrapper of :class:`SNRollout`; materials default to the problem's."""
+    fp64 = psi0.dtype == torch.float64
+    if fp64 and solver.mats64 is None:
+        solver.mats64 = solver._materials(torch.float64)
+    M = solver.mats64 if fp64 else solver.mats32
+    sigma_t = M["sigma_t"] if sigma_t is None else sigma_t
+    sigma_s = M["sigma_s"] if sigma_s is None else sigma_s
+    return SNRollout.apply(psi0, sigma_t, sigma_s, rho, solver, int(nsteps), int(ckpt_every),
+                           alpha_t, alpha_s, inflow_scale, dose_coeff)

@@ -1,0 +1,212 @@
+"""GPU parity of the adjoint step and of the differentiable rollout (checkpoint-and-recompute)
+against the FP64 oracle's transposed step and reverse pass.
+
+Tolerances: the FP64 template agrees with the oracle to 1e-12; FP32 adjoint steps to 1e-5;
+FP32 rollout gradients to 1e-4 relative (L2 over cells).  Central finite differences
+(h = 1e-4 relative) are taken on the FP64 template, where round-off stays far below the
+truncation error.
+"""
+import numpy as np
+import pytest
+
+from _util import rel_l2, small_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2205_08417_amd import inputs as I  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2205_08417_amd import snrt
+    snrt.lib()
+
+
+def _solver(P, **kw):
+    from paper_2205_08417_amd.solver import Solver
+    return Solver(P, **kw)
+
+
+def _cells_user(S, x):
+    return S.to_user(x.reshape(S.nc, -1)).cpu().numpy().reshape(S.nc, -1).squeeze(-1)
+
+
+# ------------------------------------------------------------------ single adjoint step
+
+@pytest.mark.parametrize("dense,rho,neumann", [(False, False, False), (False, True, False),
+                                               (True, True, False), (False, True, True)])
+def test_adjoint_step_matches_oracle(dense, rho, neumann):
+    from oracle import oracle as o
+    from paper_2205_08417_amd import snrt
+    omega, w = I.product_quadrature(4, 16)
+    K = I.henyey_greenstein_kernel(omega, w, 0.7) if dense else None
+    P = small_problem(I.jittered_delaunay_mesh(11, 0.0, 1.0, seed=31), omega_w=(omega, w), K=K,
+                      rho=rho, seed=31, scatter=(0.2, 1.0))
+    rng = np.random.default_rng(5)
+    lam = rng.standard_normal((P.ncells, P.nq))
+    op = o.OracleProblem.from_problem(P, neumann=neumann)
+    gt, gs = np.zeros(P.ncells), np.zeros(P.ncells)
+    gr = np.zeros(P.ncells) if rho else None
+    ref = o.adjoint_step(op, P.psi0, lam, P.dt, 1.2, 0.8, gt, gs, gr)
+    bc = snrt.SNRT_BC_NEUMANN if neumann else snrt.SNRT_BC_DIRICHLET
+    for fp64, tol in ((True, 1e-12), (False, 1e-5)):
+        S = _solver(P, fp64=fp64)
+        dt = torch.float64 if fp64 else torch.float32
+        psi = S.to_internal(P.psi0, dt)
+        l1 = S.to_internal(lam, dt)
+        l0 = torch.empty_like(l1)
+        g = [torch.zeros(P.ncells, dtype=dt, device="cuda") for _ in range(3)]
+        fn = S.adjoint_step_f64 if fp64 else S.adjoint_step
+        fn(psi, l1, l0, g[0], g[1], g[2] if rho else None, alpha_t=1.2, alpha_s=0.8, boundary=bc)
+        assert rel_l2(S.to_user(l0).cpu().numpy(), ref) <= tol
+        assert rel_l2(_cells_user(S, g[0]), gt) <= tol
+        assert rel_l2(_cells_user(S, g[1]), gs) <= tol
+        if rho:
+            assert rel_l2(_cells_user(S, g[2]), gr) <= tol
+        S.close()
+
+
+def test_dot_product_identity_full_size_checkerboard():
+    """<lam, T psi> = <T^T lam, psi> on the full adjoint workload (51 842 x 256), FP32."""
+    P = I.build("checkerboard_adjoint_s16")
+    P.source = None
+    S = _solver(P)
+    rng = np.random.default_rng(2)
+    psi = torch.tensor(rng.standard_normal((P.ncells, P.nq)), dtype=torch.float32, device="cuda")
+    lam = torch.tensor(rng.standard_normal((P.ncells, P.nq)), dtype=torch.float32, device="cuda")
+    t_psi = torch.empty_like(psi)
+    S.step(psi, t_psi)
+    tt_lam = torch.empty_like(lam)
+    S.adjoint_step(psi, lam, tt_lam)
+    lhs = float(torch.sum(lam.double() * t_psi.double()))
+    rhs = float(torch.sum(tt_lam.double() * psi.double()))
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+# ------------------------------------------------------------------ differentiable rollout
+
+def _detector_weights(P):
+    box = P.meta.get("detector", [0.5, 1.0, 0.0, 0.5])
+    region = I.region_mask(P.mesh, box)
+    return (region * P.mesh.area)[:, None] * P.w[None, :]
+
+
+def _gpu_gradients(P, nsteps, ckpt, fp64=False, rho=False):
+    from paper_2205_08417_amd.solver import differentiable_rollout
+    S = _solver(P, fp64=fp64)
+    dt = torch.float64 if fp64 else torch.float32
+    psi0 = S.to_internal(P.psi0, dt).requires_grad_(True)
+    st = S.cells_to_internal(P.sigma_t, dt).requires_grad_(True)
+    ss = S.cells_to_internal(P.sigma_s, dt).requires_grad_(True)
+    r = S.cells_to_internal(P.rho, dt).requires_grad_(True) if rho else None
+    W = S.to_internal(_detector_weights(P), dt)
+    psiN = differentiable_rollout(S, psi0, nsteps, st, ss, r, ckpt_every=ckpt)
+    J = torch.sum(W * psiN)
+    J.backward()
+    out = {"J": float(J), "psi0": S.to_user(psi0.grad).cpu().numpy(),
+           "sigma_t": _cells_user(S, st.grad), "sigma_s": _cells_user(S, ss.grad)}
+    if rho:
+        out["rho"] = _cells_user(S, r.grad)
+    S.close()
+    return out
+
+
+def test_rollout_gradients_fp32_vs_oracle_checkerboard():
+    """Reduced adjoint workload: checkerboard 40x40 points (3 042 cells), 256 ordinates,
+    60 steps, checkpoints every 20; J = integrated scalar flux over [5,6]x[3,4]."""
+    from oracle import oracle as o
+    P = I.build("checkerboard_adjoint_s16", n_side=40, nsteps=60)
+    P.psi0 = I.random_state(P.ncells, P.nq, seed=3, decades=2)
+    ref = o.rollout_gradient(o.OracleProblem.from_problem(P), P.psi0, P.dt, 60,
+                             dJ_dpsiN=_detector_weights(P))
+    g = _gpu_gradients(P, 60, 20)
+    for k in ("sigma_t", "sigma_s", "psi0"):
+        err = rel_l2(g[k], ref[k])
+        print(f"gradient {k}: rel-L2 vs oracle adjoint = {err:.2e}")
+        assert err <= 1e-4, k
+
+
+def test_rollout_gradients_density_dense_fp32_vs_oracle():
+    from oracle import oracle as o
+    omega, w = I.product_quadrature(16, 16)
+    K = I.henyey_greenstein_kernel(omega, w, 0.8)
+    P = small_problem(I.jittered_delaunay_mesh(12, 0.0, 1.0, seed=41), omega_w=(omega, w), K=K,
+                      rho=True, seed=41, source=True, inflow=True, nsteps=25)
+    ref = o.rollout_gradient(o.OracleProblem.from_problem(P), P.psi0, P.dt, 25,
+                             dJ_dpsiN=_detector_weights(P))
+    g = _gpu_gradients(P, 25, 7, rho=True)
+    for k in ("sigma_t", "sigma_s", "rho", "psi0"):
+        err = rel_l2(g[k], ref[k])
+        print(f"dense gradient {k}: rel-L2 vs oracle adjoint = {err:.2e}")
+        assert err <= 1e-4, k
+
+
+def test_checkpoint_interval_is_bitwise_invisible():
+    P = I.build("checkerboard_adjoint_s16", n_side=24, nsteps=23)
+    a = _gpu_gradients(P, 23, 23)
+    b = _gpu_gradients(P, 23, 5)
+    c = _gpu_gradients(P, 23, 1)
+    for k in ("sigma_t", "sigma_s", "psi0"):
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k])
+
+
+def test_central_fd_fp64_template():
+    """20 cells drawn (seeded) among those with |g| >= 1e-3 max|g|; h = 1e-4 max(|theta|, 1)."""
+    from paper_2205_08417_amd.solver import differentiable_rollout
+    P = I.build("checkerboard_adjoint_s16", n_side=30, nsteps=30)
+    P.psi0 = I.random_state(P.ncells, P.nq, seed=4, decades=1)
+    g = _gpu_gradients(P, 30, 10, fp64=True)
+    S = _solver(P, fp64=True)
+    W = S.to_internal(_detector_weights(P), torch.float64)
+    psi0 = S.to_internal(P.psi0, torch.float64)
+
+    def J(attr, cell, h):
+        arr = getattr(P, attr).copy()
+        arr[cell] += h
+        t = S.cells_to_internal(arr, torch.float64)
+        kw = {"sigma_t": t} if attr == "sigma_t" else {"sigma_s": t}
+        with torch.no_grad():
+            out = differentiable_rollout(S, psi0, 30, ckpt_every=30, **kw)
+        return float(torch.sum(W * out))
+
+    rng = np.random.default_rng(7)
+    for attr in ("sigma_t", "sigma_s"):
+        gg = g[attr]
+        cand = np.nonzero(np.abs(gg) >= 1e-3 * np.max(np.abs(gg)))[0]
+        for c in rng.choice(cand, min(10, cand.size), replace=False):
+            h = 1e-4 * max(abs(getattr(P, attr)[c]), 1.0)
+            fd = (J(attr, c, h) - J(attr, c, -h)) / (2 * h)
+            np.testing.assert_allclose(gg[c], fd, rtol=1e-5)
+
+
+def test_dose_density_gradient_vs_oracle():
+    """CSD-like: dose accumulated every step with varying coefficients, beam inflow, varying
+    alpha; J = sum_T A D - sum_O A D; gradient w.r.t. density."""
+    from oracle import oracle as o
+    from paper_2205_08417_amd.solver import differentiable_rollout
+    P = I.build("csd_phantom_s512", n_side=14, n_polar=4, n_azimuth=16, nsteps=30, rho_air=0.3)
+    n = P.nsteps
+    at = np.linspace(1.0, 1.3, n)
+    isc = np.asarray(P.meta["inflow_scale"])
+    coeff = np.asarray(P.meta["dose_coeff"])
+    T = I.region_mask(P.mesh, (3.0, 7.0, 7.0, 10.0))
+    O = I.region_mask(P.mesh, (0.0, 3.5, 5.0, 10.0))
+    dJdD = P.mesh.area * (T.astype(float) - O.astype(float))
+    ref = o.rollout_gradient(o.OracleProblem.from_problem(P), P.psi0, P.dt, n, dJ_ddose=dJdD,
+                             alpha_t=at, alpha_s=at, inflow_scale=isc, dose_coeff=coeff)
+    S = _solver(P)
+    psi0 = S.initial_state()
+    r = S.cells_to_internal(P.rho).requires_grad_(True)
+    psiN, dose = differentiable_rollout(S, psi0, n, rho=r, ckpt_every=8, alpha_t=at, alpha_s=at,
+                                        inflow_scale=isc, dose_coeff=coeff)
+    w_d = S.cells_to_internal(dJdD, torch.float64)
+    J = torch.sum(w_d * dose)
+    J.backward()
+    assert rel_l2(_cells_user(S, dose), ref["dose"]) <= 1e-5
+    err = rel_l2(_cells_user(S, r.grad), ref["rho"])
+    print(f"dose density gradient rel-L2 vs oracle: {err:.2e}")
+    assert err <= 1e-4
