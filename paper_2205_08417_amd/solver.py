@@ -136,16 +136,26 @@ class Solver:
         b = torch.empty_like(a)
         if dose_coeff is not None and dose is None:
             dose = torch.zeros(self.nc, dtype=torch.float64, device=self.device)
-        stepper = self.step_f64 if fp64 else self.step
+        if fp64 and self.mats64 is None:
+            self.mats64 = self._materials(torch.float64)
+        step = snrt.snrt_step_f64 if fp64 else snrt.snrt_step
+        stream = torch.cuda.current_stream().cuda_stream
+        ws = self.ws.data_ptr() if self.ws is not None else None
+        pa, pb = a.data_ptr(), b.data_ptr()
+        cache = {}
         for n in range(nsteps):
+            key = (1.0 if alpha_t is None else float(alpha_t[n]),
+                   1.0 if alpha_s is None else float(alpha_s[n]),
+                   1.0 if inflow_scale is None else float(inflow_scale[n]))
+            if key not in cache:
+                cache[key] = self.args(alpha_t=key[0], alpha_s=key[1], inflow_scale=key[2],
+                                       fp64=fp64)
             if dose_coeff is not None:
-                snrt.snrt_dose_accumulate(self.mesh, self.quad, a, self.mats32["inv_rho"],
-                                          float(dose_coeff[n]), dose)
-            stepper(a, b, alpha_t=1.0 if alpha_t is None else float(alpha_t[n]),
-                    alpha_s=1.0 if alpha_s is None else float(alpha_s[n]),
-                    inflow_scale=1.0 if inflow_scale is None else float(inflow_scale[n]))
-            a, b = b, a
-        return a, dose
+                snrt.snrt_dose_accumulate(self.mesh, self.quad, pa, self.mats32["inv_rho"],
+                                          float(dose_coeff[n]), dose, stream)
+            step(self.mesh, self.quad, self.scatter, cache[key], pa, pb, ws, self.ws_bytes, stream)
+            pa, pb = pb, pa
+        return (a if pa == a.data_ptr() else b), dose
 
     # ------------------------------------------------------------------ reductions
     def mass(self, psi: torch.Tensor) -> float:
@@ -213,26 +223,38 @@ class SNRollout(torch.autograd.Function):
             S.mats64 = S._materials(torch.float64)
             M = S.mats64
 
+        cache = {}
+
         def args(n):
-            return snrt.step_args(st, ss, S.P.dt, inv_rho=inv_rho, source=M["source"],
-                                  inflow=M["inflow"], inflow_scale=isc[n], alpha_t=at[n],
-                                  alpha_s=as_[n])
+            # one argument record per distinct (alpha_t, alpha_s, inflow_scale)
+            key = (at[n], as_[n], isc[n])
+            if key not in cache:
+                cache[key] = snrt.step_args(st, ss, S.P.dt, inv_rho=inv_rho, source=M["source"],
+                                            inflow=M["inflow"], inflow_scale=isc[n],
+                                            alpha_t=at[n], alpha_s=as_[n])
+            return cache[key]
 
         stepper = snrt.snrt_step_f64 if fp64 else snrt.snrt_step
+        stream = torch.cuda.current_stream().cuda_stream
+        ws = S.ws.data_ptr() if S.ws is not None else None
         a = psi0.detach().contiguous().clone()
         b = torch.empty_like(a)
+        pa, pb = a.data_ptr(), b.data_ptr()
         dose = (torch.zeros(S.nc, dtype=torch.float64, device=a.device)
                 if dose_coeff is not None else None)
         ckpts = []
         for n in range(nsteps):
             if n % ckpt_every == 0:
-                ckpts.append(a.clone())
+                ckpts.append(a.clone() if pa == a.data_ptr() else b.clone())
             if dose is not None:
-                snrt.snrt_dose_accumulate(S.mesh, S.quad, a, inv_rho, float(dose_coeff[n]), dose)
-            stepper(S.mesh, S.quad, S.scatter, args(n), a, b, S.ws, S.ws_bytes)
-            a, b = b, a
+                snrt.snrt_dose_accumulate(S.mesh, S.quad, pa, inv_rho, float(dose_coeff[n]),
+                                          dose, stream)
+            stepper(S.mesh, S.quad, S.scatter, args(n), pa, pb, ws, S.ws_bytes, stream)
+            pa, pb = pb, pa
+        a = a if pa == a.data_ptr() else b
         ctx.S, ctx.fp64, ctx.nsteps, ctx.K = S, fp64, nsteps, ckpt_every
         ctx.args, ctx.ckpts, ctx.dose_coeff = args, ckpts, dose_coeff
+        ctx.stream, ctx.ws = stream, ws
         ctx.has_rho = rho is not None
         ctx.save_for_backward(st, ss, inv_rho if inv_rho is not None else st,
                               dose if dose is not None else st)
@@ -259,22 +281,28 @@ class SNRollout(torch.autograd.Function):
         gd = None if (g_dose is None or dose is None) else g_dose.to(torch.float64).contiguous()
         stepper = snrt.snrt_step_f64 if fp64 else snrt.snrt_step
         adjoint = snrt.snrt_step_adjoint_f64 if fp64 else snrt.snrt_step_adjoint
+        stream, ws = ctx.stream, ctx.ws
         seg = [torch.empty_like(lam) for _ in range(K)]
+        seg_ptr = [t.data_ptr() for t in seg]
+        pl, pn = lam.data_ptr(), lam_new.data_ptr()
+        gtp, gsp = g_t.data_ptr(), g_s.data_ptr()
+        grp = g_r.data_ptr() if g_r is not None else None
         for k in range(len(ctx.ckpts) - 1, -1, -1):
             n0 = k * K
             L = min(K, N - n0)
-            states = [ctx.ckpts[k]] + seg[1:L]
+            states = [ctx.ckpts[k].data_ptr()] + seg_ptr[1:L]
             for i in range(L - 1):                          # recompute the segment
                 stepper(S.mesh, S.quad, S.scatter, ctx.args(n0 + i), states[i], states[i + 1],
-                        S.ws, S.ws_bytes)
+                        ws, S.ws_bytes, stream)
             for i in range(L - 1, -1, -1):
                 n = n0 + i
-                adjoint(S.mesh, S.quad, S.scatter, ctx.args(n), states[i], lam, lam_new, g_t, g_s,
-                        g_r, S.ws, S.ws_bytes)
+                adjoint(S.mesh, S.quad, S.scatter, ctx.args(n), states[i], pl, pn, gtp, gsp, grp,
+                        ws, S.ws_bytes, stream)
                 if gd is not None:
                     snrt.snrt_dose_adjoint(S.mesh, S.quad, inv_rho, float(ctx.dose_coeff[n]), gd,
-                                           lam_new)
-                lam, lam_new = lam_new, lam
+                                           pn, stream)
+                pl, pn = pn, pl
+        lam = lam if pl == lam.data_ptr() else lam_new
         if gd is not None and g_r is not None:
             snrt.snrt_dose_density_grad(S.mesh, dose, inv_rho, gd, g_r)
         return (lam, g_t, g_s, g_r, None, None, None, None, None, None, None)
