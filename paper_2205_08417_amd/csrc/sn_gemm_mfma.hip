@@ -7,15 +7,19 @@
 // relative, is dropped).  The single-product mode keeps only A_hi B_hi.
 //
 // Tiling for v_mfma_f32_32x32x16_bf16 (64-lane wavefronts):
-//   block tile 128 (cells) x 256 (ordinates), 8 waves as 2 x 4, each wave 64 x 64 =
-//   2 x 2 MFMA tiles with FP32 accumulators; K staged through LDS in chunks of 32.
-//   A (Psi, FP32 rows) is split while it is copied to LDS; B arrives pre-split and
-//   transposed ([n][k] BF16) so that both operands are read from LDS as 16-byte
-//   fragments along K.  LDS rows are padded to 40 elements (80 B), which keeps the eight
-//   16-byte reads of each quarter-wave on distinct banks.
-//   The next chunk's global data is fetched into registers while the current chunk is
-//   multiplied.  Consecutive logical blocks share an A row block (its N tiles), and the
-//   XCD-aware block order keeps them on one XCD so A is fetched from HBM once.
+//   block tile 256 (cells) x 256 (ordinates), 8 waves as 2 x 4, each wave 128 x 64 =
+//   4 x 2 MFMA tiles with FP32 accumulators.  K runs in chunks of 32 through two LDS
+//   stages with one barrier per chunk: after the barrier the block writes chunk k+1 into
+//   the idle stage, issues the global loads of chunk k+2 into registers, and multiplies
+//   chunk k out of the other stage.
+//   A (Psi, FP32 rows) is split into hi/lo as it is written to LDS; B arrives pre-split
+//   and pre-tiled (plane[kc][n][kk] = part of B[kc*32 + kk][n]), so one chunk of a block's
+//   256 columns is a contiguous 16 KB run per half.  Every LDS plane is [256][32] bf16
+//   (64-byte rows) with the 16-byte granule g of row r stored at position g ^ ((r>>2)&3):
+//   the fragment reads of 16 consecutive rows and the stores of 4 consecutive rows then
+//   fall on distinct banks without padding.
+//   Consecutive logical blocks share an A row block (its N tiles) and the XCD-aware block
+//   order keeps them on one XCD, so A is fetched from HBM about once.
 // MFMA operand layout (32x32x16): lane l supplies row (A) / column (B) l % 32 and the eight
 // K values (l / 32) * 8 + [0, 8); accumulator i of lane l is row (i/4)*8 + (l/32)*4 + i%4,
 // column l % 32.
@@ -31,8 +35,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 128, BN = 256, BK = 32, LDSK = BK + 8;
+constexpr int BM = 256, BN = 256, BK = 32;
 constexpr int kThreads = 512;
+constexpr int kPlane = BM * BK;          // bf16 elements of one LDS plane (16 KB)
 constexpr int kRsrcWord3 = 0x00020000;
 
 __device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
@@ -59,6 +64,9 @@ __device__ __forceinline__ void split4(f32x4 v, uint32_t (&hi)[2], uint32_t (&lo
     lo[1] = l[2] | (l[3] << 16);
 }
 
+// position of 16-byte granule g in LDS row r
+__device__ __forceinline__ int swz(int r, int g) { return g ^ ((r >> 2) & 3); }
+
 template <bool THREE>
 __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict__ A,
                                                         const uint16_t* __restrict__ Bhi,
@@ -66,10 +74,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict_
                                                         float* __restrict__ C, int64_t M,
                                                         int32_t nq)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t sAh[BM * LDSK];
-    __shared__ __attribute__((aligned(16))) uint16_t sAl[BM * LDSK];
-    __shared__ __attribute__((aligned(16))) uint16_t sBh[BN * LDSK];
-    __shared__ __attribute__((aligned(16))) uint16_t sBl[THREE ? BN * LDSK : 8];
+    constexpr int NP = THREE ? 4 : 2;    // planes per stage: A hi, B hi (, A lo, B lo)
+    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * NP * kPlane];
 
     const int nN = nq / BN;
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -77,87 +83,105 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict_
     const int n0 = (int)(lb % nN) * BN;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int wm = (wave >> 2) * 64;        // wave tile origin inside the block tile
+    const int wm = (wave >> 2) * 128;    // wave tile origin inside the block tile
     const int wn = (wave & 3) * 64;
+    const int nk = nq / BK;
 
     // A rows as a buffer resource: rows past M read as zero
     const uint32_t a_bytes = (uint32_t)((M - m0 < BM ? M - m0 : BM) * (int64_t)nq * 4);
     const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<float*>(A + m0 * nq), 0, (int32_t)a_bytes, kRsrcWord3);
 
-    // global -> register staging: A 128 x 32 floats = 1024 float4 (2 per thread);
-    // B 256 x 32 bf16 per half = 1024 16-byte pieces per half (2 per thread per half)
-    f32x4 ga[2];
+    // global -> register staging of one chunk: A 256 x 32 floats = 2048 float4 (4 per
+    // thread); B 256 x 32 bf16 per half = 1024 16-byte pieces per half (2 per thread)
+    f32x4 ga[4];
     u32x4 gbh[2], gbl[2];
-    auto fetch = [&](int k0) {
+    auto fetch = [&](int kc) {
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int idx = tid + e * kThreads;
-            const int r = idx >> 3, k4 = idx & 7;
+        for (int e = 0; e < 4; ++e) {
+            const int p = tid + e * kThreads;
+            const int r = p >> 3, g4 = p & 7;
             i32x4 v = __builtin_amdgcn_raw_buffer_load_b128(
-                ra, (uint32_t)((r * nq + k0 + k4 * 4) * 4), 0, 0);
+                ra, (uint32_t)((r * nq + kc * BK + g4 * 4) * 4), 0, 0);
             ga[e] = __builtin_bit_cast(f32x4, v);
         }
+        const size_t tile = ((size_t)kc * nq + n0) * BK;
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-            const int idx = tid + e * kThreads;
-            const int n = idx >> 2, k8 = idx & 3;
-            const size_t off = (size_t)(n0 + n) * nq + k0 + k8 * 8;
-            gbh[e] = *reinterpret_cast<const u32x4*>(Bhi + off);
-            if constexpr (THREE) gbl[e] = *reinterpret_cast<const u32x4*>(Blo + off);
+            const int p = tid + e * kThreads;
+            gbh[e] = *reinterpret_cast<const u32x4*>(Bhi + tile + (size_t)p * 8);
+            if constexpr (THREE) gbl[e] = *reinterpret_cast<const u32x4*>(Blo + tile + (size_t)p * 8);
         }
     };
-    auto stash = [&]() {
+    auto stash = [&](int s) {
+        uint16_t* Ah = lds + (s * NP + 0) * kPlane;
+        uint16_t* Bh = lds + (s * NP + 1) * kPlane;
+        uint16_t* Al = lds + (s * NP + 2) * kPlane;
+        uint16_t* Bl = lds + (s * NP + 3) * kPlane;
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int idx = tid + e * kThreads;
-            const int r = idx >> 3, k4 = idx & 7;
+        for (int e = 0; e < 4; ++e) {
+            const int p = tid + e * kThreads;
+            const int r = p >> 3, g4 = p & 7;
+            const int o = r * BK + swz(r, g4 >> 1) * 8 + (g4 & 1) * 4;
             uint32_t hi[2], lo[2];
             split4(ga[e], hi, lo);
-            *reinterpret_cast<uint2*>(&sAh[r * LDSK + k4 * 4]) = make_uint2(hi[0], hi[1]);
-            *reinterpret_cast<uint2*>(&sAl[r * LDSK + k4 * 4]) = make_uint2(lo[0], lo[1]);
+            *reinterpret_cast<uint2*>(&Ah[o]) = make_uint2(hi[0], hi[1]);
+            if constexpr (THREE) *reinterpret_cast<uint2*>(&Al[o]) = make_uint2(lo[0], lo[1]);
         }
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-            const int idx = tid + e * kThreads;
-            const int n = idx >> 2, k8 = idx & 3;
-            *reinterpret_cast<u32x4*>(&sBh[n * LDSK + k8 * 8]) = gbh[e];
-            if constexpr (THREE) *reinterpret_cast<u32x4*>(&sBl[n * LDSK + k8 * 8]) = gbl[e];
+            const int p = tid + e * kThreads;
+            const int n = p >> 2, g = p & 3;
+            const int o = n * BK + swz(n, g) * 8;
+            *reinterpret_cast<u32x4*>(&Bh[o]) = gbh[e];
+            if constexpr (THREE) *reinterpret_cast<u32x4*>(&Bl[o]) = gbl[e];
         }
     };
 
-    f32x16 acc[2][2];
+    f32x16 acc[4][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
     const int fr = lane & 31;            // fragment row / column
-    const int fk = (lane >> 5) * 8;      // fragment K offset
+    // fragment offset inside a plane for K step ks: row fr, granule ks*2 + lane/32 (swizzled;
+    // the wave-tile origins are multiples of 32 and leave the swizzle unchanged)
+    int foff[2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) foff[ks] = fr * BK + swz(fr, ks * 2 + (lane >> 5)) * 8;
+
     fetch(0);
-    for (int k0 = 0; k0 < nq; k0 += BK) {
-        __syncthreads();                 // previous chunk's fragments are consumed
-        stash();
-        __syncthreads();
-        if (k0 + BK < nq) fetch(k0 + BK);
+    stash(0);
+    if (nk > 1) fetch(1);
+    for (int kc = 0; kc < nk; ++kc) {
+        __syncthreads();                 // chunk kc staged; the idle stage is free again
+        const int s = kc & 1;
+        if (kc + 1 < nk) stash(s ^ 1);
+        if (kc + 2 < nk) fetch(kc + 2);
+        const uint16_t* Ah = lds + (s * NP + 0) * kPlane;
+        const uint16_t* Bh = lds + (s * NP + 1) * kPlane;
+        const uint16_t* Al = lds + (s * NP + 2) * kPlane;
+        const uint16_t* Bl = lds + (s * NP + 3) * kPlane;
 #pragma unroll
-        for (int ks = 0; ks < BK; ks += 16) {
-            bf16x8 ah[2], al[2], bh[2], bl[2];
+        for (int ks = 0; ks < 2; ++ks) {
+            bf16x8 ah[4], al[4], bh[2], bl[2];
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const int ar = (wm + t * 32 + fr) * LDSK + ks + fk;
-                const int bc = (wn + t * 32 + fr) * LDSK + ks + fk;
-                ah[t] = *reinterpret_cast<const bf16x8*>(&sAh[ar]);
-                bh[t] = *reinterpret_cast<const bf16x8*>(&sBh[bc]);
-                if constexpr (THREE) {
-                    al[t] = *reinterpret_cast<const bf16x8*>(&sAl[ar]);
-                    bl[t] = *reinterpret_cast<const bf16x8*>(&sBl[bc]);
-                }
+            for (int j = 0; j < 2; ++j) {
+                const int o = (wn + j * 32) * BK + foff[ks];
+                bh[j] = *reinterpret_cast<const bf16x8*>(&Bh[o]);
+                if constexpr (THREE) bl[j] = *reinterpret_cast<const bf16x8*>(&Bl[o]);
             }
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 4; ++i) {
+                const int o = (wm + i * 32) * BK + foff[ks];
+                ah[i] = *reinterpret_cast<const bf16x8*>(&Ah[o]);
+                if constexpr (THREE) al[i] = *reinterpret_cast<const bf16x8*>(&Al[o]);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
@@ -169,28 +193,32 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict_
         }
     }
 
-    // epilogue: accumulator i of lane l is row (i/4)*8 + (l/32)*4 + i%4, column l%32
+    // epilogue: accumulator r of lane l is row (r/4)*8 + (l/32)*4 + r%4, column l%32; S is
+    // consumed once by the step kernel, so it is streamed past the caches
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int col = n0 + wn + j * 32 + fr;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int64_t row = m0 + wm + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-                if (row < M) C[row * nq + col] = acc[i][j][r];
+                if (row < M) __builtin_nontemporal_store(acc[i][j][r], &C[row * nq + col]);
             }
         }
 }
 
-// hi[n][k] = bf16(B[k][n]), lo[n][k] = bf16(B[k][n] - hi): transposed BF16 halves
+// Tiled halves: hi[(kc*nq + n)*32 + kk] = bf16(B[kc*32 + kk][n]), lo = bf16(B - hi)
 __global__ __launch_bounds__(256) void k_split(const float* __restrict__ B, uint16_t* __restrict__ hi,
                                                uint16_t* __restrict__ lo, int32_t nq)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= (int64_t)nq * nq) return;
-    const int n = (int)(i / nq), k = (int)(i % nq);
-    const float x = B[(int64_t)k * nq + n];
+    const int kk = (int)(i % BK);
+    const int64_t t = i / BK;
+    const int n = (int)(t % nq);
+    const int kc = (int)(t / nq);
+    const float x = B[(int64_t)(kc * BK + kk) * nq + n];
     const uint32_t h = bf16_rne_bits(x);
     hi[i] = (uint16_t)h;
     lo[i] = (uint16_t)bf16_rne_bits(x - bf16_to_f32(h));
@@ -200,6 +228,7 @@ __global__ __launch_bounds__(256) void k_split(const float* __restrict__ B, uint
 
 hipError_t launch_split_bf16(const float* B, uint16_t* hi, uint16_t* lo, int32_t nq,
                              hipStream_t st) {
+    if (nq % BN != 0) return hipErrorNotSupported;
     const int64_t n = (int64_t)nq * nq;
     hipLaunchKernelGGL(k_split, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, B, hi, lo, nq);
     return hipGetLastError();

@@ -305,12 +305,12 @@ template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T, int LA_OW
           int LA_NBR = kAuxDefault>
 __device__ __forceinline__ void fwd_load_stage(FwdStage<V, MF, DENSE, T>& d, const NbrList<MF>& nb,
                                                const typename GeomOf<T>::type* __restrict__ geom,
-                                               int32_t c, int32_t nq, int q0,
+                                               int32_t c, uint32_t cb, int32_t nq, int q0,
                                                const typename ArgsOf<T>::type& a,
                                                const FwdCtx<T>& x)
 {
     const auto* g = cell_rec(geom, c);
-    const uint32_t own = (uint32_t)c * x.row_bytes;
+    const uint32_t own = (uint32_t)c * x.row_bytes + cb;
     buf_load_row<V, EXACT, T, LA_OWN>(x.psi, own, q0, nq, d.p);
     d.irho = RHO ? cell_val(a.inv_rho, c) : T(1);
     // boundary faces: Dirichlet reads the inflow row (scale inflow_scale), Neumann the
@@ -321,7 +321,7 @@ __device__ __forceinline__ void fwd_load_stage(FwdStage<V, MF, DENSE, T>& d, con
         const int32_t j = nb.j[f];
         const bool bnd = j < 0;
         const int32_t bidx = x.dirichlet ? -1 - j : c;
-        const uint32_t off = (uint32_t)(bnd ? bidx : j) * x.row_bytes;
+        const uint32_t off = (uint32_t)(bnd ? bidx : j) * x.row_bytes + cb;
         const T rho_j = RHO ? cell_val(a.inv_rho, bnd ? c : j) : T(1);
         d.ghost[f] = bnd ? bscale : rho_j;
         buf_load_row<V, EXACT, T, LA_NBR>(bnd && x.dirichlet ? x.inflow : x.psi, off, q0, nq,
@@ -339,7 +339,7 @@ __device__ __forceinline__ void fwd_load_stage(FwdStage<V, MF, DENSE, T>& d, con
 template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T, int SA = kAuxStream>
 __device__ __forceinline__ void fwd_compute(const FwdStage<V, MF, DENSE, T>& d, const T (&ox)[V],
                                             const T (&oy)[V], const T (&wi)[V], int32_t c,
-                                            int32_t nq, int q0, const FwdCtx<T>& x)
+                                            uint32_t cb, int32_t nq, int q0, const FwdCtx<T>& x)
 {
     T src[V];
     if constexpr (DENSE) {
@@ -372,29 +372,39 @@ __device__ __forceinline__ void fwd_compute(const FwdStage<V, MF, DENSE, T>& d, 
 #pragma unroll
     for (int k = 0; k < V; ++k)
         o[k] = d.p[k] * d.keep - d.cflux * acc[k] + d.cscat * src[k] + d.csrc;
-    buf_store_row<V, EXACT, T, SA>(x.out, (uint32_t)c * x.row_bytes, q0, nq, o);
+    buf_store_row<V, EXACT, T, SA>(x.out, (uint32_t)c * x.row_bytes + cb, q0, nq, o);
 }
 
 template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T>
 __global__ __launch_bounds__(kStepBlock) void k_step(
     const typename GeomOf<T>::type* __restrict__ geom, int64_t nc, int32_t nq,
     const T* __restrict__ tab, typename ArgsOf<T>::type a, const T* __restrict__ psi_in,
-    T* __restrict__ psi_out, const T* __restrict__ S, int64_t cells_per_xcd, uint32_t nbf)
+    T* __restrict__ psi_out, const T* __restrict__ S, int64_t items_per_xcd, uint32_t nbf,
+    int32_t shift)
 {
-    // XCD x owns cells [x*cpx, (x+1)*cpx) and all its waves sweep that range together,
-    // four consecutive cells per block per iteration: a row is read as a neighbour within a
-    // short window of its owner's read, while it is still in the XCD's L2.
+    // Work items: with dense scattering no ordinate couples to another inside the step, so
+    // a row may be cut into 2^shift chunks of 64*V ordinates, one item each (item i is chunk
+    // i & (2^shift - 1) of cell i >> shift).  Isotropic scattering needs the whole row in
+    // one wave (shift = 0).
+    // XCD x owns items [x*ipx, (x+1)*ipx) and all its waves sweep that range together,
+    // four consecutive items per block per iteration: a row is read as a neighbour within a
+    // short window of its owner's read, while it is still in the XCD's L2.  ipx and the
+    // sweep stride are multiples of 4 >= 2^shift, so a wave keeps one chunk throughout.
     const int x = blockIdx.x % kNumXcd;
     const int kx = blockIdx.x / kNumXcd;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kWave - 1);
     const int32_t stride = (int32_t)(gridDim.x / kNumXcd) * kCellsPerBlock;
-    const int64_t xb = x * cells_per_xcd;
-    if (xb >= nc) return;
-    const int32_t xend = (int32_t)(xb + cells_per_xcd < nc ? xb + cells_per_xcd : nc);
+    const int64_t ni = DENSE ? nc << shift : nc;
+    const int64_t xb = x * items_per_xcd;
+    if (xb >= ni) return;
+    const int32_t xend = (int32_t)(xb + items_per_xcd < ni ? xb + items_per_xcd : ni);
     int32_t c = (int32_t)xb + kx * kCellsPerBlock + wave;
     if (c >= xend) return;
     const int q0 = lane * V;
+    const int32_t sh = DENSE ? shift : 0;
+    const int chunk = DENSE ? (c & ((1 << sh) - 1)) : 0;
+    const uint32_t cb = (uint32_t)chunk * (uint32_t)(kWave * V * sizeof(T));
 
     FwdCtx<T> cx;
     cx.row_bytes = (uint32_t)nq * sizeof(T);
@@ -409,30 +419,35 @@ __global__ __launch_bounds__(kStepBlock) void k_step(
     cx.inflow_scale = a.inflow_scale;
     cx.dirichlet = a.inflow != nullptr && !a.neumann;
     cx.neumann = a.neumann != 0;
-    // prefetches address the clamped cell min(c', xend-1) in [xbeg, xend): always in bounds
-    auto clampc = [xend](int32_t cc) { return uniform_cell(cc < xend ? cc : xend - 1); };
+    // prefetches address the clamped item min(i', xend-1) in [xbeg, xend): always in bounds
+    auto clampc = [xend, sh](int32_t cc) {
+        return uniform_cell((cc < xend ? cc : xend - 1) >> sh);
+    };
 
+    const int tq = chunk * kWave * V + q0;      // this lane's first ordinate
     T ox[V], oy[V], wi[V];
-    load_slice<V, EXACT>(tab, q0, nq, ox);
-    load_slice<V, EXACT>(tab + nq, q0, nq, oy);
-    load_slice<V, EXACT>(tab + 3 * nq, q0, nq, wi);
+    load_slice<V, EXACT>(tab, tq, nq, ox);
+    load_slice<V, EXACT>(tab + nq, tq, nq, oy);
+    load_slice<V, EXACT>(tab + 3 * nq, tq, nq, wi);
 
     NbrList<MF> n0, n1, n2;
     FwdStage<V, MF, DENSE, T> sa, sb;
-    fwd_load_nbr<MF, T>(n0, geom, c);
-    fwd_load_stage<V, EXACT, MF, RHO, DENSE>(sa, n0, geom, c, nq, q0, a, cx);
+    fwd_load_nbr<MF, T>(n0, geom, clampc(c));
+    fwd_load_stage<V, EXACT, MF, RHO, DENSE>(sa, n0, geom, clampc(c), cb, nq, q0, a, cx);
     fwd_load_nbr<MF, T>(n1, geom, clampc(c + stride));
     for (;;) {
-        // stage B of the next cell into sb, stage A of the one after, stage C of this cell
-        fwd_load_stage<V, EXACT, MF, RHO, DENSE>(sb, n1, geom, clampc(c + stride), nq, q0, a, cx);
+        // stage B of the next item into sb, stage A of the one after, stage C of this item
+        fwd_load_stage<V, EXACT, MF, RHO, DENSE>(sb, n1, geom, clampc(c + stride), cb, nq, q0,
+                                                 a, cx);
         fwd_load_nbr<MF, T>(n2, geom, clampc(c + 2 * stride));
-        fwd_compute<V, EXACT, MF, RHO, DENSE>(sa, ox, oy, wi, c, nq, q0, cx);
+        fwd_compute<V, EXACT, MF, RHO, DENSE>(sa, ox, oy, wi, clampc(c), cb, nq, q0, cx);
         c += stride;
         if (c >= xend) break;
         n1 = n2;
-        fwd_load_stage<V, EXACT, MF, RHO, DENSE>(sa, n1, geom, clampc(c + stride), nq, q0, a, cx);
+        fwd_load_stage<V, EXACT, MF, RHO, DENSE>(sa, n1, geom, clampc(c + stride), cb, nq, q0,
+                                                 a, cx);
         fwd_load_nbr<MF, T>(n2, geom, clampc(c + 2 * stride));
-        fwd_compute<V, EXACT, MF, RHO, DENSE>(sb, ox, oy, wi, c, nq, q0, cx);
+        fwd_compute<V, EXACT, MF, RHO, DENSE>(sb, ox, oy, wi, clampc(c), cb, nq, q0, cx);
         c += stride;
         if (c >= xend) break;
         n1 = n2;
@@ -580,16 +595,17 @@ struct StepShape {
     int64_t cells_per_xcd;
 };
 
-inline StepShape step_shape(const snrt_mesh& m, int cpw, int resident_blocks_per_cu) {
+inline StepShape step_shape(const snrt_mesh& m, int64_t items, int cpw,
+                            int resident_blocks_per_cu) {
     int bpc = tune().step_blocks_per_cu;
     if (resident_blocks_per_cu > 0 && bpc > resident_blocks_per_cu) bpc = resident_blocks_per_cu;
-    int64_t want = (m.nc + (int64_t)kCellsPerBlock * cpw - 1) / ((int64_t)kCellsPerBlock * cpw);
+    int64_t want = (items + (int64_t)kCellsPerBlock - 1) / (int64_t)kCellsPerBlock;
     int64_t cap = (int64_t)m.num_cu * bpc;
     int64_t b = want < cap ? want : cap;
     b = (b / kNumXcd) * kNumXcd;             // equal block count per XCD, never above cap
     if (b < kNumXcd) b = kNumXcd;
-    int64_t cpx = (m.nc + kNumXcd - 1) / kNumXcd;
-    cpx = ((cpx + cpw - 1) / cpw) * cpw;
+    int64_t cpx = (items + kNumXcd - 1) / kNumXcd;
+    cpx = ((cpx + cpw - 1) / cpw) * cpw;     // a multiple of cpw items per XCD
     return {(unsigned)b, cpx};
 }
 
@@ -606,14 +622,22 @@ int resident_blocks(K kernel) {
 template <typename T, int V, bool E, int MF, bool RHO, bool DENSE>
 hipError_t launch_fwd(const typename GeomOf<T>::type* geom, const snrt_mesh& m, const T* tab,
                       int32_t nq, const typename ArgsOf<T>::type& a, const T* psi_in,
-                      T* psi_out, const T* S, hipStream_t st)
+                      T* psi_out, const T* S, int shift, hipStream_t st)
 {
     static const int occ = resident_blocks(k_step<V, E, MF, RHO, DENSE, T>);
-    const StepShape sh = step_shape(m, 1, occ);
+    const StepShape sh = step_shape(m, m.nc << shift, shift ? kCellsPerBlock : 1, occ);
     hipLaunchKernelGGL((k_step<V, E, MF, RHO, DENSE, T>), dim3(sh.blocks), dim3(kStepBlock),
                        0, st, geom, m.nc, nq, tab, a, psi_in, psi_out, S, sh.cells_per_xcd,
-                       (uint32_t)m.nbf);
+                       (uint32_t)m.nbf, (int32_t)shift);
     return hipGetLastError();
+}
+
+// Dense scattering with 256-ordinate-multiple rows of 2 or 4 chunks runs as 4-ordinate
+// lanes over row chunks; returns the chunk shift (0: whole rows).
+inline int dense_chunk_shift(int32_t nq) {
+    if (nq == 2 * kWave * 4) return 1;
+    if (nq == 4 * kWave * 4) return 2;
+    return 0;
 }
 
 template <typename T>
@@ -623,14 +647,16 @@ hipError_t launch_step_t(const typename GeomOf<T>::type* geom, const snrt_mesh& 
 {
     if (m.nc == 0) return hipSuccess;
     const bool rho = a.inv_rho != nullptr, dense = S != nullptr, mf4 = m.mf == 4;
-    return dispatch_v<T>(nq, [&](auto vc, auto ex) {
+    const int shift = dense ? dense_chunk_shift(nq) : 0;
+    return dispatch_v<T>(shift ? kWave * 4 : nq, [&](auto vc, auto ex) {
         constexpr int V = decltype(vc)::value;
         constexpr bool E = decltype(ex)::value;
         auto go = [&](auto mfc, auto rc, auto dc) {
             constexpr int MF = decltype(mfc)::value;
             constexpr bool R = decltype(rc)::value;
             constexpr bool D = decltype(dc)::value;
-            return launch_fwd<T, V, E, MF, R, D>(geom, m, tab, nq, a, psi_in, psi_out, S, st);
+            return launch_fwd<T, V, E, MF, R, D>(geom, m, tab, nq, a, psi_in, psi_out, S,
+                                                 shift, st);
         };
         using I3 = std::integral_constant<int, 3>;
         using I4 = std::integral_constant<int, 4>;
