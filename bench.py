@@ -130,6 +130,82 @@ def bench_dense(steps: int, warmup: int):
                                 "mfma_utilization": tflops / BF16_PEAK_TFLOPS}}
 
 
+def library_gemm_ceiling(M: int, nq: int, reps: int = 10):
+    """Context only (not the product path): hipBLASLt BF16 GEMM of the scattering product's
+    shape through torch.matmul, in TFLOP/s of its single product."""
+    import torch
+    a = torch.randn(M, nq, device="cuda", dtype=torch.bfloat16)
+    b = torch.randn(nq, nq, device="cuda", dtype=torch.bfloat16)
+    stream = torch.cuda.current_stream()
+    torch.matmul(a, b)
+    torch.cuda.synchronize()
+    ms = timed(lambda: torch.matmul(a, b), reps, stream)
+    return 2.0 * M * nq * nq / (ms * 1e-3) / 1e12
+
+
+def copy_ceiling(nbytes: int, reps: int = 20):
+    """Measured bandwidth ceiling: a device-to-device copy of one state (read + write), GB/s."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = timed(lambda: dst.copy_(src), reps, stream)
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def bench_csd(steps: int, warmup: int):
+    """CSD dose workload: phantom of 388 x 388 points (299 538 cells), 16 x 32 = 512
+    ordinates, HG g=0.95 with the BF16 hi+lo product, densities in the streaming, the beam
+    inflow scaled by S(E_n) G_E(E_n) at every energy step and the FP64 dose accumulated
+    before every step -- the first warmup + steps energy steps of the 500-step run."""
+    import torch
+    from paper_2205_08417_amd import inputs as I
+    from paper_2205_08417_amd import snrt
+    from paper_2205_08417_amd.solver import Solver
+
+    P = I.build("csd_phantom_s512")
+    S = Solver(P, precision="bf16x3")
+    isc, coeff = P.meta["inflow_scale"], P.meta["dose_coeff"]
+    n_all = min(warmup + steps, P.nsteps)
+    args = [S.args(inflow_scale=float(isc[n])) for n in range(n_all)]
+    state = [S.initial_state(), None]
+    state[1] = torch.empty_like(state[0])
+    dose = torch.zeros(S.nc, dtype=torch.float64, device="cuda")
+    sbuf = torch.empty_like(state[0])
+    stream = torch.cuda.current_stream()
+    inv_rho = S.mats32["inv_rho"]
+    counter = [0]
+
+    def one_step():
+        n = counter[0]
+        snrt.snrt_dose_accumulate(S.mesh, S.quad, state[0], inv_rho, float(coeff[n]), dose)
+        S.step(state[0], state[1], args[n])
+        state.reverse()
+        counter[0] = n + 1
+
+    for _ in range(n_all - steps):
+        one_step()
+    torch.cuda.synchronize()
+    ms_step = timed(one_step, n_all - counter[0], stream)
+    ms_prod = timed(lambda: snrt.snrt_scatter_apply(S.mesh, S.quad, S.scatter, state[0], sbuf),
+                    10, stream)
+    flops = 3 * 2.0 * P.ncells * P.nq * P.nq
+    tflops = flops / (ms_prod * 1e-3) / 1e12
+    S.close()
+    return {"workload": "csd_phantom_s512", "cells": P.ncells, "ordinates": P.nq,
+            "scattering": "Henyey-Greenstein g=0.95, dense, column-normalised",
+            "precision": "bf16x3 (hi+lo split, FP32 accumulate)", "steps": n_all - warmup,
+            "energy_MeV": [float(P.meta["energy"][warmup]), float(P.meta["energy"][n_all - 1])],
+            "value": P.ncells * P.nq / (ms_step * 1e-3), "unit": "cell-ordinate updates/s",
+            "ms_per_step": ms_step,
+            "note": "a step = dose accumulation + scattering product + flux/update kernel",
+            "scatter_product": {"kernel": "k_gemm_bf16<true>", "ms": ms_prod,
+                                "executed_tflops": tflops, "peak_tflops": BF16_PEAK_TFLOPS,
+                                "mfma_utilization": tflops / BF16_PEAK_TFLOPS}}
+
+
 def bench_adjoint(nsteps: int = 400, ckpt: int = 20):
     """Checkerboard adjoint workload (51 842 cells x 256 ordinates, 400 steps, checkpoints
     every 20): forward rollout vs backward pass (segment recompute + adjoint steps) for
@@ -265,8 +341,15 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
     S.close()
+    copy_gbs = copy_ceiling(P.ncells * P.nq * 4)
+    out["roofline"]["copy_ceiling_gbs"] = copy_gbs
+    out["roofline"]["frac_of_copy"] = achieved / copy_gbs
     if not args.no_dense:
         out["mixed_precision"] = bench_dense(args.dense_steps, 5)
+        out["mixed_precision"]["scatter_product"]["hipblaslt_bf16_single_product_tflops"] = \
+            library_gemm_ceiling(out["mixed_precision"]["cells"],
+                                 out["mixed_precision"]["ordinates"])
+        out["csd_dose"] = bench_csd(args.dense_steps, 5)
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint()
     if not args.no_cpu_baseline:

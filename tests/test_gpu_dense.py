@@ -78,6 +78,40 @@ def test_bf16x3_full_size_linesource_sampled():
     assert err <= 1e-4
 
 
+def test_bf16x3_full_size_csd_sampled():
+    """Full CSD phantom (299 538 cells x 512 ordinates, HG g=0.95, densities 1.85 / 1 /
+    0.001, beam inflow scaled by S(E) G_E) in the benchmark's launch shape: the dose
+    accumulated from a rough state, then one step; sampled cells checked one by one (beam
+    faces, the air cavity and random cells), the dose everywhere."""
+    from oracle import oracle as o
+    from paper_2205_08417_amd.solver import Solver
+    P = I.build("csd_phantom_s512")
+    P = dataclasses.replace(P, psi0=I.random_state(P.ncells, P.nq, seed=11, decades=4))
+    isc, c0 = float(P.meta["inflow_scale"][0]), float(P.meta["dose_coeff"][0])
+    S = Solver(P, precision="bf16x3")
+    psi, dose = S.rollout(S.initial_state(), 1, inflow_scale=[isc], dose_coeff=[c0])
+    out = S.to_user(psi).cpu().numpy()
+    dose = S.to_user(dose.reshape(S.nc, 1)).cpu().numpy().ravel()
+    S.close()
+    rng = np.random.default_rng(2)
+    beam = np.unique(P.mesh.bface_cell[np.abs(P.mesh.bface_mid[:, 1] - 10.0) < 1e-12])
+    c = P.mesh.centroid
+    air = np.nonzero((c[:, 0] - 4.0) ** 2 + (c[:, 1] - 7.0) ** 2 <= 0.75 ** 2)[0]
+    cells = np.unique(np.concatenate([beam[:80], air[:40], rng.choice(P.ncells, 120, False)]))
+    op = o.OracleProblem.from_problem(P)
+    ref = o.step(op, P.psi0, P.dt, inflow_scale=isc, cells=cells)
+    err = rel_l2(out[cells], ref)
+    print(f"bf16x3 full-size CSD sampled: {err:.3e}")
+    assert err <= 1e-4
+    # the GPU sums the FP32 state it holds in FP64 and scales by the FP32 copy of 1/rho
+    # (relative rounding <= 6e-8)
+    psi32 = P.psi0.astype(np.float32).astype(np.float64)
+    dref = o.dose_accumulate(op, psi32, c0, np.zeros(P.ncells))
+    derr = rel_l2(dose, dref)
+    print(f"dose rel-L2: {derr:.3e}")
+    assert derr <= 1e-6
+
+
 def test_bf16_requires_256_multiple():
     from paper_2205_08417_amd import snrt
     omega, w = I.product_quadrature(8, 8)
