@@ -4,10 +4,12 @@
 //   mass         M = sum_i A_i phi_i                              (solver log, Sec. 5.1)
 //   dose         D_i += coeff * (1/rho_i) * phi_i                 (Sec. 2, pseudo-time form)
 //
-// One wavefront per cell; lane l sums ordinates l, l+64, ... in FP64, then a butterfly
-// reduction.  The mass is a deterministic two-pass tree: per-block partials, then one block
-// folds them in a fixed order.
-#include "snrt_internal.h"
+// Persistent wavefronts stride over the cells; lane l owns the V contiguous ordinates
+// [l*V, l*V+V) of a row (16-byte loads) and keeps their FP64 weights in registers, sums its
+// slice in FP64 and the wave adds the 64 partial sums with a butterfly.  The next row is
+// loaded while the current one is reduced.  The mass is a deterministic two-pass tree: one
+// partial per wave (a fixed set of cells in a fixed order), then one block folds them.
+#include "sn_step_kernels.h"
 
 namespace snrt {
 
@@ -19,34 +21,67 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return v;
 }
 
-// phi of cell c in FP64 (all lanes get the value)
-__device__ __forceinline__ double cell_phi(const float* __restrict__ psi,
-                                           const double* __restrict__ w, int64_t c, int32_t nq,
-                                           int lane) {
-    const float* row = psi + c * (int64_t)nq;
-    double s = 0.0;
-    for (int q = lane; q < nq; q += kWave) s += w[q] * (double)row[q];
-    return wave_sum_d(s);
+constexpr int kReduceBlocksPerCu = 4;
+
+template <int V, bool EXACT>
+struct RowPhi {
+    double wv[V];
+    int q0;
+    int32_t nq;
+    __device__ __forceinline__ RowPhi(const double* __restrict__ w, int32_t nq_, int lane)
+        : q0(lane * V), nq(nq_) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) wv[k] = (q0 + k < nq) ? w[q0 + k] : 0.0;
+    }
+    __device__ __forceinline__ void load(const float* __restrict__ psi, int64_t c, float (&r)[V]) const {
+        load_slice<V, EXACT>(psi + c * (int64_t)nq, q0, nq, r);
+    }
+    __device__ __forceinline__ double sum(const float (&r)[V]) const {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < V; ++k) s += wv[k] * (double)r[k];
+        return wave_sum_d(s);
+    }
+};
+
+// Visit every cell c of this wave's share in increasing order with phi(c); the row of the
+// next cell is in flight while the current one is reduced.
+template <int V, bool EXACT, typename F>
+__device__ __forceinline__ void for_each_phi(const float* __restrict__ psi,
+                                             const double* __restrict__ w, int64_t nc,
+                                             int32_t nq, F&& visit) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    const RowPhi<V, EXACT> rp(w, nq, lane);
+    int64_t c = gw;
+    if (c >= nc) return;
+    float cur[V], nxt[V];
+    rp.load(psi, c, cur);
+    for (;;) {
+        const int64_t cn = c + nw;
+        if (cn < nc) rp.load(psi, cn, nxt);
+        visit(c, rp.sum(cur));
+        if (cn >= nc) break;
+#pragma unroll
+        for (int k = 0; k < V; ++k) cur[k] = nxt[k];
+        c = cn;
+    }
 }
 
+template <int V, bool EXACT>
 __global__ __launch_bounds__(kStepBlock) void k_mass_partial(const CellGeom64* __restrict__ geom,
                                                              const float* __restrict__ psi,
                                                              const double* __restrict__ w,
                                                              int64_t nc, int32_t nq,
                                                              double* __restrict__ partial)
 {
-    __shared__ double red[kCellsPerBlock];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
-    const int64_t c = (int64_t)blockIdx.x * kCellsPerBlock + wave;
-    double v = 0.0;
-    if (c < nc) v = geom[c].area * cell_phi(psi, w, c, nq, lane);
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < kCellsPerBlock; ++i) s += red[i];
-        partial[blockIdx.x] = s;
-    }
+    double acc = 0.0;
+    for_each_phi<V, EXACT>(psi, w, nc, nq, [&](int64_t c, double phi) {
+        acc += geom[c].area * phi;
+    });
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) partial[gw] = acc;
 }
 
 __global__ __launch_bounds__(1024) void k_fold(const double* __restrict__ partial, int64_t n,
@@ -65,29 +100,29 @@ __global__ __launch_bounds__(1024) void k_fold(const double* __restrict__ partia
     if (t == 0) *out = red[0];
 }
 
+template <int V, bool EXACT>
 __global__ __launch_bounds__(kStepBlock) void k_scalar_flux(const float* __restrict__ psi,
                                                             const double* __restrict__ w,
                                                             int64_t nc, int32_t nq,
                                                             float* __restrict__ phi)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
-    const int64_t c = (int64_t)blockIdx.x * kCellsPerBlock + wave;
-    if (c >= nc) return;
-    const double s = cell_phi(psi, w, c, nq, lane);
-    if (lane == 0) phi[c] = (float)s;
+    const bool lane0 = (threadIdx.x & (kWave - 1)) == 0;
+    for_each_phi<V, EXACT>(psi, w, nc, nq, [&](int64_t c, double s) {
+        if (lane0) phi[c] = (float)s;
+    });
 }
 
+template <int V, bool EXACT>
 __global__ __launch_bounds__(kStepBlock) void k_dose(const float* __restrict__ psi,
                                                      const double* __restrict__ w,
                                                      const float* __restrict__ inv_rho,
                                                      double coeff, int64_t nc, int32_t nq,
                                                      double* __restrict__ dose)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
-    const int64_t c = (int64_t)blockIdx.x * kCellsPerBlock + wave;
-    if (c >= nc) return;
-    const double s = cell_phi(psi, w, c, nq, lane);
-    if (lane == 0) dose[c] += coeff * (inv_rho ? (double)inv_rho[c] : 1.0) * s;
+    const bool lane0 = (threadIdx.x & (kWave - 1)) == 0;
+    for_each_phi<V, EXACT>(psi, w, nc, nq, [&](int64_t c, double s) {
+        if (lane0) dose[c] += coeff * (inv_rho ? (double)inv_rho[c] : 1.0) * s;
+    });
 }
 
 // out[k] = in[src(k)] row copy in 4-byte words; to_user: out[perm[k]] = in[k]
@@ -103,7 +138,8 @@ __global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ in
     for (int64_t i = threadIdx.x; i < words; i += 256) out[dst * words + i] = in[src * words + i];
 }
 
-// lam[c][q] += coeff * w_q * inv_rho[c] * g_dose[c]: one wavefront per cell
+// lam[c][q] += coeff * w_q * inv_rho[c] * g_dose[c]: persistent waves, V ordinates per lane
+template <int V, bool EXACT>
 __global__ __launch_bounds__(kStepBlock) void k_dose_adjoint(const double* __restrict__ w,
                                                              const float* __restrict__ inv_rho,
                                                              double coeff,
@@ -111,12 +147,22 @@ __global__ __launch_bounds__(kStepBlock) void k_dose_adjoint(const double* __res
                                                              float* __restrict__ lam, int64_t nc,
                                                              int32_t nq)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
-    const int64_t c = (int64_t)blockIdx.x * kCellsPerBlock + wave;
-    if (c >= nc) return;
-    const double g = coeff * (inv_rho ? (double)inv_rho[c] : 1.0) * g_dose[c];
-    float* row = lam + c * (int64_t)nq;
-    for (int q = lane; q < nq; q += kWave) row[q] = (float)((double)row[q] + g * w[q]);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    const int q0 = lane * V;
+    double wv[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) wv[k] = (q0 + k < nq) ? w[q0 + k] : 0.0;
+    for (int64_t c = gw; c < nc; c += nw) {
+        const double g = coeff * (inv_rho ? (double)inv_rho[c] : 1.0) * g_dose[c];
+        float* row = lam + c * (int64_t)nq;
+        float r[V];
+        load_slice<V, EXACT>(row, q0, nq, r);
+#pragma unroll
+        for (int k = 0; k < V; ++k) r[k] = (float)((double)r[k] + g * wv[k]);
+        store_slice<V, EXACT>(row, q0, nq, r, false);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_dose_density_grad(const double* __restrict__ dose,
@@ -133,6 +179,17 @@ inline unsigned blocks_for(int64_t nc) {
     return (unsigned)((nc + kCellsPerBlock - 1) / kCellsPerBlock);
 }
 
+// Persistent reduction grid: at most kReduceBlocksPerCu blocks per CU and never more waves than
+// the mesh holds partial slots for.
+inline unsigned reduce_blocks(const snrt_mesh& m) {
+    int64_t b = (int64_t)m.num_cu * kReduceBlocksPerCu;
+    const int64_t cap = m.n_partial / kCellsPerBlock;
+    if (b > cap) b = cap;
+    const int64_t want = (m.nc + kCellsPerBlock - 1) / kCellsPerBlock;
+    if (b > want) b = want;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
 }  // namespace
 
 hipError_t launch_mass(const snrt_mesh& m, const snrt_quad& q, const float* psi, double* out,
@@ -141,29 +198,42 @@ hipError_t launch_mass(const snrt_mesh& m, const snrt_quad& q, const float* psi,
         hipLaunchKernelGGL(k_fold, dim3(1), dim3(1024), 0, st, m.d_partial, (int64_t)0, out);
         return hipGetLastError();
     }
-    const unsigned nb = blocks_for(m.nc);
-    hipLaunchKernelGGL(k_mass_partial, dim3(nb), dim3(kStepBlock), 0, st, m.geom64, psi,
-                       q.tab64 + 2 * (int64_t)q.nq, m.nc, q.nq, m.d_partial);
-    hipError_t e = hipGetLastError();
+    const unsigned nb = reduce_blocks(m);
+    hipError_t e = dispatch_v<float>(q.nq, [&](auto vc, auto ex) {
+        constexpr int V = decltype(vc)::value;
+        constexpr bool E = decltype(ex)::value;
+        hipLaunchKernelGGL((k_mass_partial<V, E>), dim3(nb), dim3(kStepBlock), 0, st, m.geom64,
+                           psi, q.tab64 + 2 * (int64_t)q.nq, m.nc, q.nq, m.d_partial);
+        return hipGetLastError();
+    });
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fold, dim3(1), dim3(1024), 0, st, m.d_partial, (int64_t)nb, out);
+    hipLaunchKernelGGL(k_fold, dim3(1), dim3(1024), 0, st, m.d_partial,
+                       (int64_t)nb * kCellsPerBlock, out);
     return hipGetLastError();
 }
 
 hipError_t launch_scalar_flux(const snrt_mesh& m, const snrt_quad& q, const float* psi,
                               float* phi, hipStream_t st) {
     if (m.nc == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scalar_flux, dim3(blocks_for(m.nc)), dim3(kStepBlock), 0, st, psi,
-                       q.tab64 + 2 * (int64_t)q.nq, m.nc, q.nq, phi);
-    return hipGetLastError();
+    return dispatch_v<float>(q.nq, [&](auto vc, auto ex) {
+        constexpr int V = decltype(vc)::value;
+        constexpr bool E = decltype(ex)::value;
+        hipLaunchKernelGGL((k_scalar_flux<V, E>), dim3(reduce_blocks(m)), dim3(kStepBlock), 0,
+                           st, psi, q.tab64 + 2 * (int64_t)q.nq, m.nc, q.nq, phi);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_dose(const snrt_mesh& m, const snrt_quad& q, const float* psi,
                        const float* inv_rho, double coeff, double* dose, hipStream_t st) {
     if (m.nc == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dose, dim3(blocks_for(m.nc)), dim3(kStepBlock), 0, st, psi,
-                       q.tab64 + 2 * (int64_t)q.nq, inv_rho, coeff, m.nc, q.nq, dose);
-    return hipGetLastError();
+    return dispatch_v<float>(q.nq, [&](auto vc, auto ex) {
+        constexpr int V = decltype(vc)::value;
+        constexpr bool E = decltype(ex)::value;
+        hipLaunchKernelGGL((k_dose<V, E>), dim3(reduce_blocks(m)), dim3(kStepBlock), 0, st, psi,
+                           q.tab64 + 2 * (int64_t)q.nq, inv_rho, coeff, m.nc, q.nq, dose);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_permute(const snrt_mesh& m, int to_user, const void* in, void* out,
@@ -178,9 +248,14 @@ hipError_t launch_permute(const snrt_mesh& m, int to_user, const void* in, void*
 hipError_t launch_dose_adjoint(const snrt_mesh& m, const snrt_quad& q, const float* inv_rho,
                                double coeff, const double* g_dose, float* lam, hipStream_t st) {
     if (m.nc == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dose_adjoint, dim3(blocks_for(m.nc)), dim3(kStepBlock), 0, st,
-                       q.tab64 + 2 * (int64_t)q.nq, inv_rho, coeff, g_dose, lam, m.nc, q.nq);
-    return hipGetLastError();
+    return dispatch_v<float>(q.nq, [&](auto vc, auto ex) {
+        constexpr int V = decltype(vc)::value;
+        constexpr bool E = decltype(ex)::value;
+        hipLaunchKernelGGL((k_dose_adjoint<V, E>), dim3(reduce_blocks(m)), dim3(kStepBlock), 0,
+                           st, q.tab64 + 2 * (int64_t)q.nq, inv_rho, coeff, g_dose, lam, m.nc,
+                           q.nq);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_dose_density_grad(const snrt_mesh& m, const double* dose, const float* inv_rho,

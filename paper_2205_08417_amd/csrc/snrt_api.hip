@@ -254,7 +254,7 @@ snrt_status snrt_mesh_create(snrt_mesh** out, int64_t nc, int32_t mf, const int3
     m->nbf = nbf;
     m->mf = mf;
     m->to_user = std::move(to_user);
-    m->n_partial = (nc + kCellsPerBlock - 1) / kCellsPerBlock;
+    m->n_partial = std::max<int64_t>((nc + kCellsPerBlock - 1) / kCellsPerBlock, 16);
     snrt_status s = SNRT_OK;
     if ((s = dev_alloc(&m->geom32, nc, "geometry")) != SNRT_OK ||
         (s = dev_alloc(&m->geom64, nc, "geometry")) != SNRT_OK ||
