@@ -61,6 +61,15 @@ def lib():
         L.oracle_dose_accumulate.restype = ctypes.c_int
         L.oracle_dose_accumulate.argtypes = [ctypes.c_int64, ctypes.c_int32, _dp, _dp, _dp,
                                              ctypes.c_double, _dp]
+        L.oracle_limited_gradient.restype = ctypes.c_int
+        L.oracle_limited_gradient.argtypes = [ctypes.c_int64, ctypes.c_int32, _ip, _dp, _dp, _dp,
+                                              _dp, ctypes.c_int32, _dp, _dp, ctypes.c_double,
+                                              ctypes.c_int32, _dp, _dp, _dp]
+        L.oracle_step2.restype = ctypes.c_int
+        L.oracle_step2.argtypes = [ctypes.c_int64, ctypes.c_int32, _ip, _dp, _dp, _dp, _dp,
+                                   ctypes.c_int32, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                   ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double, _dp, _dp]
         _lib = L
     return _lib
 
@@ -80,10 +89,13 @@ class OracleProblem:
     """The arrays one step needs, converted once to contiguous FP64 / int32."""
 
     def __init__(self, face_nbr, face_normal, area, omega, w, sigma_t, sigma_s, K=None,
-                 rho=None, source=None, inflow=None, neumann=False):
+                 rho=None, source=None, inflow=None, neumann=False, face_mid=None,
+                 centroid=None):
         self.face_nbr = np.ascontiguousarray(face_nbr, dtype=np.int32)
         self.nc, self.mf = self.face_nbr.shape
         self.face_normal = _f64(face_normal).reshape(self.nc, self.mf, 2)
+        self.face_mid = None if face_mid is None else _f64(face_mid).reshape(self.nc, self.mf, 2)
+        self.centroid = None if centroid is None else _f64(centroid).reshape(self.nc, 2)
         self.area = _f64(area)
         self.omega = _f64(omega).reshape(-1, 3)
         self.w = _f64(w)
@@ -100,7 +112,8 @@ class OracleProblem:
     def from_problem(cls, P, **over):
         kw = dict(face_nbr=P.mesh.face_nbr, face_normal=P.mesh.face_normal, area=P.mesh.area,
                   omega=P.omega, w=P.w, sigma_t=P.sigma_t, sigma_s=P.sigma_s, K=P.K, rho=P.rho,
-                  source=P.source, inflow=P.inflow)
+                  source=P.source, inflow=P.inflow, face_mid=P.mesh.face_mid,
+                  centroid=P.mesh.centroid)
         kw.update(over)
         return cls(**kw)
 
@@ -108,7 +121,7 @@ class OracleProblem:
         kw = dict(face_nbr=self.face_nbr, face_normal=self.face_normal, area=self.area,
                   omega=self.omega, w=self.w, sigma_t=self.sigma_t, sigma_s=self.sigma_s,
                   K=self.K, rho=self.rho, source=self.source, inflow=self.inflow,
-                  neumann=self.neumann)
+                  neumann=self.neumann, face_mid=self.face_mid, centroid=self.centroid)
         kw.update(over)
         return OracleProblem(**kw)
 
@@ -149,6 +162,41 @@ def adjoint_step(op: OracleProblem, psi_n: np.ndarray, lam_np1: np.ndarray, dt: 
                                    _d(g_sigma_t), _d(g_sigma_s), _d(g_rho))
     if rc != 0:
         raise ValueError("oracle_adjoint_step rejected its arguments")
+    return out
+
+
+def limited_gradient(op: OracleProblem, psi: np.ndarray, inflow_scale: float = 1.0):
+    """Psi_i grad(u_i) per cell and ordinate (Green-Gauss + Barth-Jespersen, Sec. 4.2
+    second order schemes): returns (gx, gy), each [nc][nq]."""
+    psi = _f64(psi).reshape(op.nc, op.nq)
+    if op.face_mid is None or op.centroid is None:
+        raise ValueError("the second-order scheme needs face midpoints and centroids")
+    gx = np.empty((op.nc, op.nq))
+    gy = np.empty((op.nc, op.nq))
+    rc = lib().oracle_limited_gradient(op.nc, op.mf, op.face_nbr.ctypes.data_as(_ip),
+                                       _d(op.face_normal), _d(op.face_mid), _d(op.centroid),
+                                       _d(op.area), op.nq, _d(op.rho), _d(op.inflow),
+                                       float(inflow_scale), int(op.neumann), _d(psi), _d(gx),
+                                       _d(gy))
+    if rc != 0:
+        raise ValueError("oracle_limited_gradient rejected its arguments")
+    return gx, gy
+
+
+def step2(op: OracleProblem, psi: np.ndarray, dt: float, alpha_t: float = 1.0,
+          alpha_s: float = 1.0, inflow_scale: float = 1.0) -> np.ndarray:
+    """One Heun step of the second-order scheme (Sec. 4.2): (psi + L(L(psi))) / 2."""
+    psi = _f64(psi).reshape(op.nc, op.nq)
+    if op.face_mid is None or op.centroid is None:
+        raise ValueError("the second-order scheme needs face midpoints and centroids")
+    out = np.empty((op.nc, op.nq))
+    rc = lib().oracle_step2(op.nc, op.mf, op.face_nbr.ctypes.data_as(_ip), _d(op.face_normal),
+                            _d(op.face_mid), _d(op.centroid), _d(op.area), op.nq, _d(op.omega),
+                            _d(op.w), _d(op.K), _d(op.sigma_t), _d(op.sigma_s), _d(op.rho),
+                            _d(op.source), _d(op.inflow), float(inflow_scale), int(op.neumann),
+                            float(dt), float(alpha_t), float(alpha_s), _d(psi), _d(out))
+    if rc != 0:
+        raise ValueError(f"oracle_step2 failed ({rc})")
     return out
 
 

@@ -259,3 +259,212 @@ int oracle_dose_accumulate(int64_t nc, int32_t nq, const double* w, const double
     }
     return 0;
 }
+
+/* ---------------------------------------------------------------------------------------
+ * Second-order scheme (Sec. 4.2, second order finite volume schemes): the flux inputs are
+ * linear reconstructions u_i + Psi_i grad(u_i) . r_ij with a Green-Gauss gradient built
+ * from face averages and the Barth-Jespersen limiter Psi_i, and time advances with the
+ * two-stage Heun scheme  psi* = L(psi^n), psi** = L(psi*), psi^{n+1} = (psi^n + psi**)/2,
+ * where L is one explicit Euler stage with the reconstructed upwind flux.
+ *
+ * Readings (listed in the design notes):
+ *   - the reconstructed variable is u = psi/rho, the quantity the upwind flux transports;
+ *   - the limiter's increment is the one the reconstruction adds, Delta_2 = grad u_i . r_ij
+ *     (the printed factor 1/2 contradicts the reconstruction the limiter is meant to bound);
+ *   - g_max and g_min are the extremes of u over the cell and every value across its faces,
+ *     the definition of the cited Barth-Jespersen limiter.  Taken face by face, as the
+ *     printed formula can be read, the limiter clips smooth data so often that the scheme
+ *     is only first order (measured), against the section's claim of second order;
+ *   - a boundary face's u_j is the first-order ghost value; it enters the Green-Gauss sum
+ *     and the limiter like a neighbour value and is not itself reconstructed;
+ *   - both Heun stages use the step's alpha_t, alpha_s and inflow scale and add dt*R (the
+ *     first-order update's source term), not dt/A_i*R.
+ * Extra arrays: face_mid[(c*mf+f)*2] is the midpoint of face slot f as seen from cell c (on
+ * a periodic mesh, in c's unwrapped frame) and centroid[c*2] the cell centroid.
+ * --------------------------------------------------------------------------------------- */
+
+/* u on the far side of face f of cell i at ordinate q: neighbour value or ghost value */
+static double far_u(int64_t i, int32_t mf, const int32_t* face_nbr, int32_t f, int32_t nq,
+                    int32_t q, const double* rho, const double* inflow, double inflow_scale,
+                    int32_t neumann, const double* psi)
+{
+    int32_t j = face_nbr[(size_t)i * mf + f];
+    double u_i = psi[(size_t)i * nq + q] / (rho ? rho[i] : 1.0);
+    if (j >= 0) return psi[(size_t)j * nq + q] / (rho ? rho[j] : 1.0);
+    if (neumann) return u_i;
+    int64_t b = -1 - (int64_t)j;
+    return inflow ? inflow[(size_t)b * nq + q] * inflow_scale : 0.0;
+}
+
+/* Limited gradient Psi_i grad(u_i) of every cell and ordinate into gx, gy [nc][nq]. */
+int oracle_limited_gradient(int64_t nc, int32_t mf, const int32_t* face_nbr,
+                            const double* face_normal, const double* face_mid,
+                            const double* centroid, const double* area, int32_t nq,
+                            const double* rho, const double* inflow, double inflow_scale,
+                            int32_t neumann, const double* psi, double* gx, double* gy)
+{
+    if (nc < 0 || mf < 1 || nq < 1 || !face_nbr || !face_normal || !face_mid || !centroid ||
+        !area || !psi || !gx || !gy)
+        return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nc; ++i) {
+        double rho_i = rho ? rho[i] : 1.0;
+        for (int32_t q = 0; q < nq; ++q) {
+            double u_i = psi[(size_t)i * nq + q] / rho_i;
+            /* Green-Gauss with the face value (u_i + u_j)/2 */
+            double ax = 0.0, ay = 0.0;
+            for (int32_t f = 0; f < mf; ++f) {
+                if (face_nbr[(size_t)i * mf + f] == ORACLE_UNUSED_FACE) continue;
+                const double* n = face_normal + ((size_t)i * mf + f) * 2;
+                double u_j = far_u(i, mf, face_nbr, f, nq, q, rho, inflow, inflow_scale,
+                                   neumann, psi);
+                ax += 0.5 * (u_i + u_j) * n[0];
+                ay += 0.5 * (u_i + u_j) * n[1];
+            }
+            ax /= area[i];
+            ay /= area[i];
+            /* extremes of u over the cell and all the values across its faces */
+            double gmax = u_i, gmin = u_i;
+            for (int32_t f = 0; f < mf; ++f) {
+                if (face_nbr[(size_t)i * mf + f] == ORACLE_UNUSED_FACE) continue;
+                double u_j = far_u(i, mf, face_nbr, f, nq, q, rho, inflow, inflow_scale,
+                                   neumann, psi);
+                if (u_j > gmax) gmax = u_j;
+                if (u_j < gmin) gmin = u_j;
+            }
+            /* Barth-Jespersen: the smallest admissible scaling over the faces */
+            double lim = 1.0;
+            for (int32_t f = 0; f < mf; ++f) {
+                if (face_nbr[(size_t)i * mf + f] == ORACLE_UNUSED_FACE) continue;
+                const double* m = face_mid + ((size_t)i * mf + f) * 2;
+                double rx = m[0] - centroid[(size_t)i * 2 + 0];
+                double ry = m[1] - centroid[(size_t)i * 2 + 1];
+                double d2 = ax * rx + ay * ry;
+                double t = 1.0;
+                if (d2 > 0.0)
+                    t = (gmax - u_i) / d2;
+                else if (d2 < 0.0)
+                    t = (gmin - u_i) / d2;
+                if (t > 1.0) t = 1.0;
+                if (t < lim) lim = t;
+            }
+            gx[(size_t)i * nq + q] = lim * ax;
+            gy[(size_t)i * nq + q] = lim * ay;
+        }
+    }
+    return 0;
+}
+
+/* Slot of cell j whose neighbour is cell i (the shared face seen from j), or -1. */
+static int32_t back_slot(int64_t j, int64_t i, int32_t mf, const int32_t* face_nbr)
+{
+    for (int32_t f = 0; f < mf; ++f)
+        if (face_nbr[(size_t)j * mf + f] == (int32_t)i) return f;
+    return -1;
+}
+
+/* One explicit Euler stage with the reconstructed upwind flux: out = psi - dt/A sum F + dt R. */
+static int stage2(int64_t nc, int32_t mf, const int32_t* face_nbr, const double* face_normal,
+                  const double* face_mid, const double* centroid, const double* area, int32_t nq,
+                  const double* omega, const double* w, const double* K, const double* sigma_t,
+                  const double* sigma_s, const double* rho, const double* source,
+                  const double* inflow, double inflow_scale, int32_t neumann, double dt,
+                  double alpha_t, double alpha_s, const double* psi, double* out, double* gx,
+                  double* gy)
+{
+    int rc = oracle_limited_gradient(nc, mf, face_nbr, face_normal, face_mid, centroid, area, nq,
+                                     rho, inflow, inflow_scale, neumann, psi, gx, gy);
+    if (rc != 0) return rc;
+    int failed = 0;
+#pragma omp parallel
+    {
+        double* S = (double*)malloc(sizeof(double) * (size_t)nq);
+        if (!S) {
+#pragma omp atomic write
+            failed = 1;
+        }
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < nc; ++i) {
+            if (!S) continue;
+            const double* psi_i = psi + (size_t)i * nq;
+            double rho_i = rho ? rho[i] : 1.0;
+            if (K == NULL) {
+                double iso = scatter_source(nq, w, NULL, psi_i, 0);
+                for (int32_t q = 0; q < nq; ++q) S[q] = iso;
+            } else {
+                for (int32_t q = 0; q < nq; ++q) S[q] = scatter_source(nq, w, K, psi_i, q);
+            }
+            for (int32_t q = 0; q < nq; ++q) {
+                double u_i = psi_i[q] / rho_i;
+                double flux = 0.0;
+                for (int32_t f = 0; f < mf; ++f) {
+                    int32_t j = face_nbr[(size_t)i * mf + f];
+                    if (j == ORACLE_UNUSED_FACE) continue;
+                    const double* n = face_normal + ((size_t)i * mf + f) * 2;
+                    const double* m = face_mid + ((size_t)i * mf + f) * 2;
+                    double s = omega[(size_t)q * 3 + 0] * n[0] + omega[(size_t)q * 3 + 1] * n[1];
+                    /* own side: u_i + Psi_i grad u_i . r_ij */
+                    double ui_rec = u_i + gx[(size_t)i * nq + q] * (m[0] - centroid[(size_t)i * 2])
+                                        + gy[(size_t)i * nq + q] * (m[1] - centroid[(size_t)i * 2 + 1]);
+                    double uj_rec;
+                    if (j >= 0) {
+                        /* far side: u_j + Psi_j grad u_j . r_ji, r_ji from x_j to the same face */
+                        int32_t fb = back_slot(j, i, mf, face_nbr);
+                        if (fb < 0) {
+#pragma omp atomic write
+                            failed = 3;
+                            uj_rec = 0.0;
+                        } else {
+                            const double* mj = face_mid + ((size_t)j * mf + fb) * 2;
+                            double u_j = psi[(size_t)j * nq + q] / (rho ? rho[j] : 1.0);
+                            uj_rec = u_j + gx[(size_t)j * nq + q] * (mj[0] - centroid[(size_t)j * 2])
+                                         + gy[(size_t)j * nq + q] * (mj[1] - centroid[(size_t)j * 2 + 1]);
+                        }
+                    } else {
+                        uj_rec = far_u(i, mf, face_nbr, f, nq, q, rho, inflow, inflow_scale,
+                                       neumann, psi);
+                    }
+                    double H = s > 0.0 ? 1.0 : 0.0;
+                    flux += s * ui_rec * H + s * uj_rec * (1.0 - H);
+                }
+                double R = -alpha_t * sigma_t[i] * psi_i[q] + alpha_s * sigma_s[i] * S[q]
+                           + (source ? source[i] : 0.0);
+                out[(size_t)i * nq + q] = psi_i[q] - dt / area[i] * flux + dt * R;
+            }
+        }
+        free(S);
+    }
+    return failed ? -1 - failed : 0;
+}
+
+/* One Heun step of the second-order scheme: psi_out = (psi_in + L(L(psi_in))) / 2. */
+int oracle_step2(int64_t nc, int32_t mf, const int32_t* face_nbr, const double* face_normal,
+                 const double* face_mid, const double* centroid, const double* area, int32_t nq,
+                 const double* omega, const double* w, const double* K, const double* sigma_t,
+                 const double* sigma_s, const double* rho, const double* source,
+                 const double* inflow, double inflow_scale, int32_t neumann, double dt,
+                 double alpha_t, double alpha_s, const double* psi_in, double* psi_out)
+{
+    if (nc < 0 || mf < 1 || nq < 1 || !face_nbr || !face_normal || !face_mid || !centroid ||
+        !area || !omega || !w || !sigma_t || !sigma_s || !psi_in || !psi_out)
+        return -1;
+    size_t n = (size_t)nc * nq;
+    double* star = (double*)malloc(sizeof(double) * (n ? n : 1));
+    double* gx = (double*)malloc(sizeof(double) * (n ? n : 1));
+    double* gy = (double*)malloc(sizeof(double) * (n ? n : 1));
+    int rc = (star && gx && gy) ? 0 : -2;
+    if (rc == 0)
+        rc = stage2(nc, mf, face_nbr, face_normal, face_mid, centroid, area, nq, omega, w, K,
+                    sigma_t, sigma_s, rho, source, inflow, inflow_scale, neumann, dt, alpha_t,
+                    alpha_s, psi_in, star, gx, gy);
+    if (rc == 0)
+        rc = stage2(nc, mf, face_nbr, face_normal, face_mid, centroid, area, nq, omega, w, K,
+                    sigma_t, sigma_s, rho, source, inflow, inflow_scale, neumann, dt, alpha_t,
+                    alpha_s, star, psi_out, gx, gy);
+    if (rc == 0)
+        for (size_t k = 0; k < n; ++k) psi_out[k] = 0.5 * (psi_in[k] + psi_out[k]);
+    free(star);
+    free(gx);
+    free(gy);
+    return rc;
+}

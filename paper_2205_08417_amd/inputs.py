@@ -73,6 +73,8 @@ class Mesh:
     centroid: np.ndarray      # [nc, 2] FP64
     bface_cell: np.ndarray    # [nbf] owning cell of boundary face b
     bface_mid: np.ndarray     # [nbf, 2] midpoint of boundary face b
+    face_mid: Optional[np.ndarray] = None   # [nc, mf, 2] midpoint of every face slot, seen
+                                            # from its cell (unwrapped on periodic meshes)
 
     @property
     def ncells(self) -> int:
@@ -118,9 +120,10 @@ def _faces_from_triangles(points: np.ndarray, tris: np.ndarray, nbrs: np.ndarray
     nbf = bc.shape[0]
     face_nbr[bc, bf] = -1 - np.arange(nbf)
     mids = 0.5 * (p[bc, (bf + 1) % 3] + p[bc, (bf + 2) % 3])
+    fmid = np.stack([0.5 * (p[:, (k + 1) % 3] + p[:, (k + 2) % 3]) for k in range(3)], axis=1)
     return Mesh(points=points, cells=tris, face_nbr=face_nbr.astype(np.int32),
                 face_normal=normal, area=area, centroid=centroid,
-                bface_cell=bc.astype(np.int64), bface_mid=mids)
+                bface_cell=bc.astype(np.int64), bface_mid=mids, face_mid=fmid)
 
 
 def jittered_delaunay_mesh(n: int, lo: float, hi: float, seed: int, jitter: float = 0.25,
@@ -226,11 +229,13 @@ def periodic_mesh(n: int, length: float = 1.0, diagonal_flip: bool = True) -> Me
     d2 = (lverts[:, 2] - lverts[:, 0]) * h
     area = 0.5 * (d1[:, 0] * d2[:, 1] - d1[:, 1] * d2[:, 0])
     centroid = lverts.mean(axis=1) * h
+    fmid = np.stack([0.5 * (lverts[:, (k + 1) % 3] + lverts[:, (k + 2) % 3]) * h
+                     for k in range(3)], axis=1)
     pts = np.array([[i * h, j * h] for i in range(n) for j in range(n)])
     cells = np.stack([vid(lverts[:, k]) for k in range(3)], axis=1)
     return Mesh(points=pts, cells=cells, face_nbr=face_nbr.astype(np.int32), face_normal=normal,
                 area=area, centroid=centroid, bface_cell=np.zeros(0, np.int64),
-                bface_mid=np.zeros((0, 2)))
+                bface_mid=np.zeros((0, 2)), face_mid=fmid)
 
 
 def quad_grid_mesh(nx: int, ny: int, lo=(0.0, 0.0), hi=(1.0, 1.0)) -> Mesh:
@@ -244,6 +249,7 @@ def quad_grid_mesh(nx: int, ny: int, lo=(0.0, 0.0), hi=(1.0, 1.0)) -> Mesh:
     cid = lambda i, j: j * nx + i
     face_nbr = np.empty((nc, 4), dtype=np.int64)
     normal = np.empty((nc, 4, 2))
+    fmid = np.empty((nc, 4, 2))
     area = np.empty(nc)
     centroid = np.empty((nc, 2))
     cells = np.empty((nc, 4), dtype=np.int64)
@@ -259,6 +265,7 @@ def quad_grid_mesh(nx: int, ny: int, lo=(0.0, 0.0), hi=(1.0, 1.0)) -> Mesh:
             for f in range(4):
                 a, b = v[f], v[(f + 1) % 4]
                 normal[c, f] = (b[1] - a[1], -(b[0] - a[0]))
+                fmid[c, f] = (0.5 * (a[0] + b[0]), 0.5 * (a[1] + b[1]))
                 face_nbr[c, f] = nb[f]
             area[c] = (xs[i + 1] - xs[i]) * (ys[j + 1] - ys[j])
             centroid[c] = (0.5 * (xs[i] + xs[i + 1]), 0.5 * (ys[j] + ys[j + 1]))
@@ -269,7 +276,7 @@ def quad_grid_mesh(nx: int, ny: int, lo=(0.0, 0.0), hi=(1.0, 1.0)) -> Mesh:
                      for c, f in zip(bc, bf)]).reshape(-1, 2)
     return Mesh(points=pts, cells=cells, face_nbr=face_nbr.astype(np.int32),
                 face_normal=normal, area=area, centroid=centroid,
-                bface_cell=bc.astype(np.int64), bface_mid=mids)
+                bface_cell=bc.astype(np.int64), bface_mid=mids, face_mid=fmid)
 
 
 def pad_faces(mesh: Mesh, max_faces: int = 4) -> Mesh:
@@ -281,7 +288,11 @@ def pad_faces(mesh: Mesh, max_faces: int = 4) -> Mesh:
     nbr[:, :mf] = mesh.face_nbr
     nrm = np.zeros((nc, max_faces, 2))
     nrm[:, :mf] = mesh.face_normal
-    return dataclasses.replace(mesh, face_nbr=nbr, face_normal=nrm)
+    mid = None
+    if mesh.face_mid is not None:
+        mid = np.zeros((nc, max_faces, 2))
+        mid[:, :mf] = mesh.face_mid
+    return dataclasses.replace(mesh, face_nbr=nbr, face_normal=nrm, face_mid=mid)
 
 
 # ----------------------------------------------------------------------------------------
