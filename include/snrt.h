@@ -203,6 +203,43 @@ snrt_status snrt_scatter_apply(const snrt_mesh* mesh, const snrt_quad* quad,
                                const snrt_scatter* scatter, const float* psi, float* S,
                                int32_t transpose, void* stream);
 
+/* ---------------------------------------------------------------- second-order step */
+
+/* Face-slot midpoints for the second-order scheme (Sec. 4.2, second order finite volume
+ * schemes).  face_mid: HOST FP64 [ncells*max_faces*2] in the user's cell order, the
+ * midpoint of face slot f of cell c as seen from c (on a periodic mesh, in c's unwrapped
+ * frame); entries of unused slots are ignored.  Needs the centroids passed to
+ * snrt_mesh_create (SNRT_E_ARG if there were none).  Copied; may be called again to replace
+ * them.  Not thread-safe against concurrent steps on the same mesh. */
+snrt_status snrt_mesh_set_face_midpoints(snrt_mesh* mesh, const double* face_mid);
+
+/* Bytes of device workspace snrt_step2 (fp64 = 0) or snrt_step2_f64 (fp64 = 1) needs: the
+ * intermediate stage state, its limited gradient (two components) and, for dense
+ * scattering, the scattering product -- each [ncells][nq] of the step's element type. */
+snrt_status snrt_step2_workspace_size(const snrt_mesh* mesh, const snrt_quad* quad,
+                                      const snrt_scatter* scatter, int32_t fp64, size_t* bytes);
+
+/* One step of the second-order scheme: the Heun method
+ *     psi* = L(psi_in),  psi** = L(psi*),  psi_out = (psi_in + psi**) / 2,
+ * where L is the explicit Euler update above with the upwind flux fed by limited linear
+ * reconstructions of u = psi/rho on both sides of every face,
+ *     u~_i = u_i + Psi_i grad(u_i) . r_if,   r_if = face midpoint - centroid_i,
+ * grad(u_i) the Green-Gauss gradient from face averages (u_i + u_j)/2 (boundary faces use
+ * the ghost value) and Psi_i the Barth-Jespersen limiter with the extremes of u over the
+ * cell and its face neighbours and the increment grad(u_i) . r_if.  Ghost values are not
+ * reconstructed.  Both stages use args (the same alpha_t, alpha_s, inflow_scale).
+ * Requires snrt_mesh_set_face_midpoints (SNRT_E_ARG otherwise) and a workspace of
+ * snrt_step2_workspace_size bytes; psi_out must not alias psi_in or the workspace. */
+snrt_status snrt_step2(const snrt_mesh* mesh, const snrt_quad* quad, const snrt_scatter* scatter,
+                       const snrt_step_args* args, const float* psi_in, float* psi_out,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* The second-order step in FP64 throughout (parity template). */
+snrt_status snrt_step2_f64(const snrt_mesh* mesh, const snrt_quad* quad,
+                           const snrt_scatter* scatter, const snrt_step_args_f64* args,
+                           const double* psi_in, double* psi_out, void* ws, size_t ws_bytes,
+                           void* stream);
+
 /* ---------------------------------------------------------------- reductions */
 
 /* Total mass sum_i A_i sum_q w_q psi_iq accumulated in FP64 (solver log, Sec. 5.1), written

@@ -134,6 +134,8 @@ void snrt_mesh_destroy(snrt_mesh* m) {
     dev_free(m->geom64);
     dev_free(m->d_to_user);
     dev_free(m->d_partial);
+    dev_free(m->recon32);
+    dev_free(m->recon64);
     delete m;
 }
 
@@ -254,6 +256,8 @@ snrt_status snrt_mesh_create(snrt_mesh** out, int64_t nc, int32_t mf, const int3
     m->nbf = nbf;
     m->mf = mf;
     m->to_user = std::move(to_user);
+    m->face_nbr_user.assign(face_nbr, face_nbr + nc * mf);
+    if (centroid) m->centroid_user.assign(centroid, centroid + nc * 2);
     m->n_partial = std::max<int64_t>((nc + kCellsPerBlock - 1) / kCellsPerBlock, 16);
     snrt_status s = SNRT_OK;
     if ((s = dev_alloc(&m->geom32, nc, "geometry")) != SNRT_OK ||
@@ -267,6 +271,68 @@ snrt_status snrt_mesh_create(snrt_mesh** out, int64_t nc, int32_t mf, const int3
         return s;
     }
     *out = m;
+    return SNRT_OK;
+}
+
+snrt_status snrt_mesh_set_face_midpoints(snrt_mesh* m, const double* face_mid) {
+    g_last_error.clear();
+    SNRT_REQUIRE(m, SNRT_E_ARG, "snrt_mesh_set_face_midpoints: NULL mesh");
+    const int64_t nc = m->nc;
+    const int32_t mf = m->mf;
+    SNRT_REQUIRE(nc == 0 || face_mid, SNRT_E_ARG, "snrt_mesh_set_face_midpoints: NULL face_mid");
+    SNRT_REQUIRE(nc == 0 || (int64_t)m->centroid_user.size() == 2 * nc, SNRT_E_ARG,
+                 "snrt_mesh_set_face_midpoints: the mesh was created without centroids");
+    SNRT_TRY(check_device(m->device, "snrt_mesh_set_face_midpoints"));
+    const std::vector<int32_t>& nbr = m->face_nbr_user;
+    const std::vector<double>& cen = m->centroid_user;
+    std::vector<CellRecon32> r32(nc);
+    std::vector<CellRecon64> r64(nc);
+    for (int64_t k = 0; k < nc; ++k) {
+        const int64_t i = m->to_user[k];
+        CellRecon64& b = r64[k];
+        CellRecon32& a = r32[k];
+        std::memset(&a, 0, sizeof(a));
+        std::memset(&b, 0, sizeof(b));
+        for (int f = 0; f < mf; ++f) {
+            const int32_t j = nbr[i * mf + f];
+            if (j == kUnusedFace) continue;
+            const double* mid = face_mid + (i * mf + f) * 2;
+            SNRT_REQUIRE(is_finite(mid[0]) && is_finite(mid[1]), SNRT_E_ARG,
+                         "snrt_mesh_set_face_midpoints: non-finite midpoint at cell " +
+                             std::to_string(i));
+            b.r_own[f][0] = mid[0] - cen[2 * i];
+            b.r_own[f][1] = mid[1] - cen[2 * i + 1];
+            if (j >= 0) {
+                int g = 0;
+                while (g < mf && nbr[(int64_t)j * mf + g] != (int32_t)i) ++g;
+                // adjacency was checked symmetric at creation, so the back slot exists
+                const double* mj = face_mid + ((int64_t)j * mf + g) * 2;
+                SNRT_REQUIRE(is_finite(mj[0]) && is_finite(mj[1]), SNRT_E_ARG,
+                             "snrt_mesh_set_face_midpoints: non-finite midpoint at cell " +
+                                 std::to_string(j));
+                b.r_far[f][0] = mj[0] - cen[2 * (int64_t)j];
+                b.r_far[f][1] = mj[1] - cen[2 * (int64_t)j + 1];
+            }
+            for (int d = 0; d < 2; ++d) {
+                a.r_own[f][d] = (float)b.r_own[f][d];
+                a.r_far[f][d] = (float)b.r_far[f][d];
+            }
+        }
+    }
+    if (!m->recon32) {
+        snrt_status s = SNRT_OK;
+        if ((s = dev_alloc(&m->recon32, std::max<int64_t>(nc, 1), "reconstruction vectors")) != SNRT_OK)
+            return s;
+        if ((s = dev_alloc(&m->recon64, std::max<int64_t>(nc, 1), "reconstruction vectors")) != SNRT_OK) {
+            dev_free(m->recon32);
+            m->recon32 = nullptr;
+            return s;
+        }
+    }
+    snrt_status s = SNRT_OK;
+    if ((s = upload(m->recon32, r32.data(), nc, "snrt_mesh_set_face_midpoints: upload")) != SNRT_OK ||
+        (s = upload(m->recon64, r64.data(), nc, "snrt_mesh_set_face_midpoints: upload")) != SNRT_OK)
+        return s;
     return SNRT_OK;
 }
 
@@ -432,6 +498,18 @@ snrt_status snrt_workspace_size(const snrt_mesh* m, const snrt_quad* q, const sn
     SNRT_REQUIRE(m && q && sc && bytes, SNRT_E_ARG, "snrt_workspace_size: NULL argument");
     SNRT_REQUIRE(sc->B.nq == q->nq, SNRT_E_SHAPE, "snrt_workspace_size: scatter/quad nq differ");
     *bytes = sc->dense ? (size_t)m->nc * q->nq * sizeof(double) : 0;
+    return SNRT_OK;
+}
+
+snrt_status snrt_step2_workspace_size(const snrt_mesh* m, const snrt_quad* q,
+                                      const snrt_scatter* sc, int32_t fp64, size_t* bytes) {
+    g_last_error.clear();
+    SNRT_REQUIRE(m && q && sc && bytes, SNRT_E_ARG, "snrt_step2_workspace_size: NULL argument");
+    SNRT_REQUIRE(fp64 == 0 || fp64 == 1, SNRT_E_ARG, "snrt_step2_workspace_size: fp64 is 0 or 1");
+    SNRT_REQUIRE(sc->B.nq == q->nq, SNRT_E_SHAPE,
+                 "snrt_step2_workspace_size: scatter/quad nq differ");
+    const size_t row = (size_t)m->nc * q->nq * (fp64 ? sizeof(double) : sizeof(float));
+    *bytes = row * (sc->dense ? 4 : 3);
     return SNRT_OK;
 }
 
@@ -608,6 +686,72 @@ snrt_status snrt_step_adjoint_f64(const snrt_mesh* m, const snrt_quad* q, const 
     }
     hipError_t e = launch_adjoint64(*m, *q, to64(a), psi_n, lam_np1, lam_n, g_t, g_s, g_r, G, st);
     return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_step_adjoint_f64: launch");
+}
+
+}  // extern "C"
+
+namespace {
+
+// Heun step of the second-order scheme on the workspace [star | G (two planes) | S].
+template <typename T, typename ArgsT>
+snrt_status step2_common(const char* fn, const snrt_mesh* m, const snrt_quad* q,
+                         const snrt_scatter* sc, const ArgsT* a, const T* psi_in, T* psi_out,
+                         void* ws, size_t ws_bytes, void* stream) {
+    SNRT_TRY(check_step_common(fn, m, q, sc, a, sizeof(T), psi_in, psi_out, ws, ws_bytes));
+    if (m->nc == 0) return SNRT_OK;
+    SNRT_REQUIRE(m->recon32 && m->recon64, SNRT_E_ARG,
+                 std::string(fn) + ": call snrt_mesh_set_face_midpoints first");
+    const size_t row = (size_t)m->nc * q->nq * sizeof(T);
+    const size_t need = row * (sc->dense ? 4 : 3);
+    SNRT_REQUIRE(ws && ws_bytes >= need, SNRT_E_ARG,
+                 std::string(fn) + ": needs a workspace of " + std::to_string(need) + " bytes");
+    SNRT_REQUIRE(aligned16(ws), SNRT_E_ARG, std::string(fn) + ": workspace must be 16-byte aligned");
+    SNRT_REQUIRE(!ranges_overlap(ws, need, psi_in, row) && !ranges_overlap(ws, need, psi_out, row),
+                 SNRT_E_ALIAS, std::string(fn) + ": workspace aliases a state array");
+    T* star = static_cast<T*>(ws);
+    T* G = star + (size_t)m->nc * q->nq;
+    T* S = sc->dense ? G + 2 * (size_t)m->nc * q->nq : nullptr;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    const T* in[2] = {psi_in, star};
+    T* outp[2] = {star, psi_out};
+    for (int stage = 0; stage < 2 && e == hipSuccess; ++stage) {
+        if constexpr (sizeof(T) == 4) {
+            const StepArgs32 a32 = to32(a);
+            e = launch_grad2_32(*m, *q, a32, in[stage], G, st);
+            if (e == hipSuccess && S) e = dense_product32(sc, in[stage], S, m->nc, false, st);
+            if (e == hipSuccess)
+                e = launch_flux2_32(*m, *q, a32, in[stage], G, S, stage ? psi_in : nullptr,
+                                    outp[stage], st);
+        } else {
+            const StepArgs64 a64 = to64(a);
+            e = launch_grad2_64(*m, *q, a64, in[stage], G, st);
+            if (e == hipSuccess && S) e = launch_gemm64(in[stage], sc->B.b64, S, m->nc, q->nq, st);
+            if (e == hipSuccess)
+                e = launch_flux2_64(*m, *q, a64, in[stage], G, S, stage ? psi_in : nullptr,
+                                    outp[stage], st);
+        }
+    }
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, (std::string(fn) + ": launch").c_str());
+}
+
+}  // namespace
+
+extern "C" {
+
+snrt_status snrt_step2(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
+                       const snrt_step_args* a, const float* psi_in, float* psi_out, void* ws,
+                       size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    return step2_common<float>("snrt_step2", m, q, sc, a, psi_in, psi_out, ws, ws_bytes, stream);
+}
+
+snrt_status snrt_step2_f64(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
+                           const snrt_step_args_f64* a, const double* psi_in, double* psi_out,
+                           void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    return step2_common<double>("snrt_step2_f64", m, q, sc, a, psi_in, psi_out, ws, ws_bytes,
+                                stream);
 }
 
 snrt_status snrt_scatter_apply(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,

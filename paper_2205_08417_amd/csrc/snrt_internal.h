@@ -37,6 +37,21 @@ struct alignas(32) CellGeom64 {
 };
 static_assert(sizeof(CellGeom64) == 128, "two cache lines per cell");
 
+// Reconstruction vectors of the second-order scheme, per face slot: r_own = face midpoint
+// - own centroid, r_far = the same face's midpoint - the neighbour's centroid (zero for
+// boundary faces, whose ghost value is not reconstructed, and for unused slots).
+struct alignas(64) CellRecon32 {
+    float r_own[4][2];
+    float r_far[4][2];
+};
+static_assert(sizeof(CellRecon32) == 64, "one cache line per cell");
+
+struct alignas(64) CellRecon64 {
+    double r_own[4][2];
+    double r_far[4][2];
+};
+static_assert(sizeof(CellRecon64) == 128, "two cache lines per cell");
+
 // Dense scattering operands on the device: B for the forward product S = Psi B and B^T for
 // the adjoint product Lambda B^T, in FP32 / FP64 and as BF16 hi/lo pairs for MFMA.
 struct DenseB {
@@ -66,6 +81,11 @@ struct snrt_mesh {
     double* d_partial = nullptr;           // per-block partial sums for snrt_mass
     int64_t n_partial = 0;
     int num_cu = 256;                      // compute units of the device (launch shapes)
+    // host copies kept for the second-order set-up (user order)
+    std::vector<int32_t> face_nbr_user;    // [nc*mf]
+    std::vector<double> centroid_user;     // [nc*2], empty if none was given
+    snrt::CellRecon32* recon32 = nullptr;  // second-order reconstruction vectors (internal
+    snrt::CellRecon64* recon64 = nullptr;  // order); NULL until face midpoints are set
 };
 
 struct snrt_quad {
@@ -129,6 +149,19 @@ hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t*
 // Re-layout of an FP32 [nq][nq] matrix into the BF16 hi/lo operand format of the MFMA GEMM.
 hipError_t launch_split_bf16(const float* B, uint16_t* hi, uint16_t* lo, int32_t nq,
                              hipStream_t st);
+
+// Second-order scheme (sn_step2.hip): limited gradient of a stage input and the stage
+// update with reconstructed face values; final = true writes (psi_n + stage) / 2.
+hipError_t launch_grad2_32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
+                           const float* psi, float* G, hipStream_t st);
+hipError_t launch_grad2_64(const snrt_mesh& m, const snrt_quad& q, const StepArgs64& a,
+                           const double* psi, double* G, hipStream_t st);
+hipError_t launch_flux2_32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
+                           const float* psi, const float* G, const float* S,
+                           const float* psi_n, float* out, hipStream_t st);
+hipError_t launch_flux2_64(const snrt_mesh& m, const snrt_quad& q, const StepArgs64& a,
+                           const double* psi, const double* G, const double* S,
+                           const double* psi_n, double* out, hipStream_t st);
 
 hipError_t launch_mass(const snrt_mesh& m, const snrt_quad& q, const float* psi, double* out,
                        hipStream_t st);

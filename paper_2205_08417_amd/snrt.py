@@ -45,6 +45,7 @@ EXPORTS = [
     "snrt_workspace_size", "snrt_step", "snrt_step_f64", "snrt_step_adjoint",
     "snrt_step_adjoint_f64", "snrt_scatter_apply", "snrt_mass", "snrt_scalar_flux",
     "snrt_dose_accumulate", "snrt_dose_adjoint", "snrt_dose_density_grad", "snrt_permute",
+    "snrt_mesh_set_face_midpoints", "snrt_step2_workspace_size", "snrt_step2", "snrt_step2_f64",
 ]
 
 
@@ -110,6 +111,13 @@ def lib() -> ctypes.CDLL:
         "snrt_dose_adjoint": (_st, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
         "snrt_dose_density_grad": (_st, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "snrt_permute": (_st, [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int64, _vp]),
+        "snrt_mesh_set_face_midpoints": (_st, [_vp, _dp]),
+        "snrt_step2_workspace_size": (_st, [_vp, _vp, _vp, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_size_t)]),
+        "snrt_step2": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp,
+                             ctypes.c_size_t, _vp]),
+        "snrt_step2_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp,
+                                 ctypes.c_size_t, _vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -182,6 +190,11 @@ def snrt_mesh_create(face_nbr, face_normal, area, centroid=None, nbfaces=0,
     return h.value
 
 
+def snrt_mesh_set_face_midpoints(mesh: int, face_mid) -> None:
+    arr, p = _f64(face_mid)
+    _check("snrt_mesh_set_face_midpoints", lib().snrt_mesh_set_face_midpoints(mesh, p))
+
+
 def snrt_mesh_permutation(mesh: int) -> np.ndarray:
     nc = ctypes.c_int64()
     _check("snrt_mesh_info", lib().snrt_mesh_info(mesh, ctypes.byref(nc), None, None))
@@ -229,6 +242,27 @@ def snrt_scatter_dense(quad: int, K, precision=SNRT_FP32) -> int:
 
 def snrt_scatter_destroy(scatter: int) -> None:
     lib().snrt_scatter_destroy(scatter)
+
+
+def snrt_step2_workspace_size(mesh: int, quad: int, scatter: int, fp64: bool = False) -> int:
+    n = ctypes.c_size_t()
+    _check("snrt_step2_workspace_size",
+           lib().snrt_step2_workspace_size(mesh, quad, scatter, int(bool(fp64)), ctypes.byref(n)))
+    return n.value
+
+
+def snrt_step2(mesh, quad, scatter, args: StepArgs, psi_in, psi_out, ws=None, ws_bytes=0,
+               stream=None) -> None:
+    _check("snrt_step2", lib().snrt_step2(mesh, quad, scatter, ctypes.byref(args), _ptr(psi_in),
+                                          _ptr(psi_out), _ptr(ws), int(ws_bytes),
+                                          _stream(stream)))
+
+
+def snrt_step2_f64(mesh, quad, scatter, args: StepArgs, psi_in, psi_out, ws=None, ws_bytes=0,
+                   stream=None) -> None:
+    _check("snrt_step2_f64", lib().snrt_step2_f64(mesh, quad, scatter, ctypes.byref(args),
+                                                  _ptr(psi_in), _ptr(psi_out), _ptr(ws),
+                                                  int(ws_bytes), _stream(stream)))
 
 
 def snrt_workspace_size(mesh: int, quad: int, scatter: int) -> int:

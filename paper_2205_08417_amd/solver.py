@@ -48,7 +48,10 @@ class Solver:
             else:
                 self.scatter = snrt.snrt_scatter_dense(self.quad, P.K, _PREC[precision])
             self.ws_bytes = snrt.snrt_workspace_size(self.mesh, self.quad, self.scatter)
+            if m.face_mid is not None:
+                snrt.snrt_mesh_set_face_midpoints(self.mesh, m.face_mid)
         self.perm = snrt.snrt_mesh_permutation(self.mesh)
+        self.ws2 = {}   # second-order workspaces by element type, allocated on first use
         self.ws = (torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
                    if self.ws_bytes else None)
         self.mats32 = self._materials(torch.float32)
@@ -108,6 +111,26 @@ class Solver:
         snrt.snrt_step_f64(self.mesh, self.quad, self.scatter, args or self.args(**kw), psi_in,
                            psi_out, self.ws, self.ws_bytes)
 
+    def _ws2(self, fp64: bool):
+        if fp64 not in self.ws2:
+            n = snrt.snrt_step2_workspace_size(self.mesh, self.quad, self.scatter, fp64)
+            self.ws2[fp64] = (torch.empty(max(n, 16), dtype=torch.uint8, device=self.device), n)
+        return self.ws2[fp64]
+
+    def step2(self, psi_in, psi_out, args=None, **kw):
+        """One Heun step of the second-order scheme (limited linear reconstruction)."""
+        ws, n = self._ws2(False)
+        snrt.snrt_step2(self.mesh, self.quad, self.scatter, args or self.args(**kw), psi_in,
+                        psi_out, ws, n)
+
+    def step2_f64(self, psi_in, psi_out, args=None, **kw):
+        if self.mats64 is None:
+            self.mats64 = self._materials(torch.float64)
+        kw["fp64"] = True
+        ws, n = self._ws2(True)
+        snrt.snrt_step2_f64(self.mesh, self.quad, self.scatter, args or self.args(**kw), psi_in,
+                            psi_out, ws, n)
+
     def adjoint_step(self, psi_n, lam_np1, lam_n, g_sigma_t=None, g_sigma_s=None, g_rho=None,
                      args=None, **kw):
         snrt.snrt_step_adjoint(self.mesh, self.quad, self.scatter, args or self.args(**kw),
@@ -128,7 +151,7 @@ class Solver:
                 alpha_s: Optional[Sequence[float]] = None,
                 inflow_scale: Optional[Sequence[float]] = None,
                 dose_coeff: Optional[Sequence[float]] = None,
-                dose: Optional[torch.Tensor] = None):
+                dose: Optional[torch.Tensor] = None, order: int = 1):
         """Advance ``nsteps`` explicit steps (ping-pong buffers).  Returns ``(psi, dose)``;
         the dose (FP64, internal order) adds ``dose_coeff[n]`` times the density-weighted
         scalar flux of the state entering step n."""
@@ -138,9 +161,18 @@ class Solver:
             dose = torch.zeros(self.nc, dtype=torch.float64, device=self.device)
         if fp64 and self.mats64 is None:
             self.mats64 = self._materials(torch.float64)
-        step = snrt.snrt_step_f64 if fp64 else snrt.snrt_step
+        if order == 2:
+            step = snrt.snrt_step2_f64 if fp64 else snrt.snrt_step2
+            w2, ws_bytes = self._ws2(fp64)
+            ws = w2.data_ptr()
+        elif order == 1:
+            step = snrt.snrt_step_f64 if fp64 else snrt.snrt_step
+            ws = self.ws.data_ptr() if self.ws is not None else None
+            ws_bytes = self.ws_bytes
+        else:
+            raise ValueError("order is 1 (explicit Euler, first-order flux) or 2 (Heun, "
+                             "limited linear reconstruction)")
         stream = torch.cuda.current_stream().cuda_stream
-        ws = self.ws.data_ptr() if self.ws is not None else None
         pa, pb = a.data_ptr(), b.data_ptr()
         cache = {}
         for n in range(nsteps):
@@ -153,7 +185,7 @@ class Solver:
             if dose_coeff is not None:
                 snrt.snrt_dose_accumulate(self.mesh, self.quad, pa, self.mats32["inv_rho"],
                                           float(dose_coeff[n]), dose, stream)
-            step(self.mesh, self.quad, self.scatter, cache[key], pa, pb, ws, self.ws_bytes, stream)
+            step(self.mesh, self.quad, self.scatter, cache[key], pa, pb, ws, ws_bytes, stream)
             pa, pb = pb, pa
         return (a if pa == a.data_ptr() else b), dose
 
