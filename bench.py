@@ -206,6 +206,43 @@ def bench_csd(steps: int, warmup: int):
                                 "mfma_utilization": tflops / BF16_PEAK_TFLOPS}}
 
 
+def bench_second_order(steps: int, warmup: int):
+    """Second-order scheme on the headline checkerboard (198 450 cells x 256 ordinates,
+    isotropic, FP32): one Heun step = two stages of limited-gradient + reconstructed-flux
+    kernels.  Algorithmic bytes per step: per stage the gradient kernel reads psi and writes
+    the two-component gradient (12 B per update) and the update kernel reads psi and the
+    gradient and writes the stage result (16 B), the final stage also reads psi^n (4 B):
+    60 B per update, plus 2 x 64 B of geometry and 2 x 64 B of reconstruction vectors per
+    cell and stage."""
+    import torch
+    from paper_2205_08417_amd import inputs as I
+    from paper_2205_08417_amd.solver import Solver
+
+    P = I.build(WORKLOAD)
+    S = Solver(P)
+    state = [S.initial_state(), None]
+    state[1] = torch.empty_like(state[0])
+    args = S.args()
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        S.step2(state[0], state[1], args)
+        state.reverse()
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    ms = timed(one_step, steps, stream)
+    alg = P.ncells * (60 * P.nq + 2 * 2 * (64 + 64))
+    S.close()
+    return {"workload": WORKLOAD, "cells": P.ncells, "ordinates": P.nq,
+            "scheme": "second order: Green-Gauss + Barth-Jespersen reconstruction, Heun",
+            "steps": steps, "ms_per_step": ms, "value": P.ncells * P.nq / (ms * 1e-3),
+            "unit": "cell-ordinate updates/s", "algorithmic_bytes_per_step": alg,
+            "achieved_gbs": alg / (ms * 1e-3) / 1e9,
+            "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 def bench_adjoint(nsteps: int = 400, ckpt: int = 20):
     """Checkerboard adjoint workload (51 842 cells x 256 ordinates, 400 steps, checkpoints
     every 20): forward rollout vs backward pass (segment recompute + adjoint steps) for
@@ -257,6 +294,8 @@ def main():
     ap.add_argument("--dense-steps", type=int, default=40)
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward cost measurement")
+    ap.add_argument("--no-second-order", action="store_true",
+                    help="skip the second-order (Heun, reconstructed flux) measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of one state (for HBM counter scaling)")
     args = ap.parse_args()
@@ -352,6 +391,8 @@ def main():
         out["csd_dose"] = bench_csd(args.dense_steps, 5)
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint()
+    if not args.no_second_order:
+        out["second_order"] = bench_second_order(min(args.steps, 200), 5)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P)
     print(json.dumps(out), flush=True)
