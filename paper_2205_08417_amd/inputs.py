@@ -299,6 +299,13 @@ def pad_faces(mesh: Mesh, max_faces: int = 4) -> Mesh:
 # Scattering kernels (eq. SNEqns; total = scattering cross section, Sec. 2)
 # ----------------------------------------------------------------------------------------
 
+def hg_legendre_moments(g: float, N: int) -> np.ndarray:
+    """Legendre moments ``2 pi int P_l(mu) k_HG(mu) dmu = g^l`` (l = 0..N) of the
+    Henyey-Greenstein kernel normalised to ``int k dOmega = 1``: the diagonal entries of the
+    moment-projected scattering (eq. SNEqns2) for HG scattering."""
+    return float(g) ** np.arange(N + 1, dtype=np.float64)
+
+
 def isotropic_kernel(nq: int) -> np.ndarray:
     """Dense ``K = 1/(4 pi)``: the isotropic kernel written as a matrix."""
     return np.full((nq, nq), 1.0 / FOUR_PI)
