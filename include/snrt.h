@@ -116,11 +116,24 @@ void snrt_quad_destroy(snrt_quad* quad);
 snrt_status snrt_scatter_isotropic(snrt_scatter** out, const snrt_quad* quad);
 snrt_status snrt_scatter_dense(snrt_scatter** out, const snrt_quad* quad, const double* K,
                                snrt_precision precision);
+
+/* Moment-projected scattering O Sigma M (eq. SNEqns2): S = O diag(sigma) M psi with the real
+ * spherical harmonics m_j of degree <= N = degree ((N+1)^2 moments; Sec. 3.1),
+ * O[q][j] = m_j(Omega_q), M[j][q] = w_q m_j(Omega_q), and sigma_l[l] (host, l = 0..N) the
+ * kernel's Legendre moments 2 pi int P_l(mu) k(mu) dmu, repeated on the 2l+1 moments of degree
+ * l (sigma_0 = 1 conserves particles; Henyey-Greenstein: g^l).  Equivalent to the dense
+ * kernel K[q][p] = sum_j m_j(Omega_q) sigma_l(j) m_j(Omega_p), applied as two products through
+ * the moments.  0 <= degree <= 30.  BF16 modes need nq % 256 == 0 and pad the moment count
+ * with zeros to a multiple of 256.  Steps with this handle need snrt_workspace_size bytes;
+ * snrt_scatter_apply does not accept it (SNRT_E_UNSUPPORTED). */
+snrt_status snrt_scatter_moments(snrt_scatter** out, const snrt_quad* quad, int32_t degree,
+                                 const double* sigma_l, snrt_precision precision);
 void snrt_scatter_destroy(snrt_scatter* scatter);
 
 /* Bytes of device workspace snrt_step / snrt_step_adjoint need for this combination
- * (0 for isotropic scattering; one [ncells][nq] FP64-sized buffer for dense scattering, which
- * serves both the FP32 and the FP64 entry points). */
+ * (0 for isotropic scattering; one [ncells][nq] FP64-sized buffer for a dense kernel, plus
+ * [ncells][moments, padded] for the moment form; the size serves both the FP32 and the FP64
+ * entry points). */
 snrt_status snrt_workspace_size(const snrt_mesh* mesh, const snrt_quad* quad,
                                 const snrt_scatter* scatter, size_t* bytes);
 

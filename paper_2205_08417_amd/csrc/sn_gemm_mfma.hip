@@ -1,5 +1,7 @@
-// Dense scattering product S = Psi B on the CDNA4 matrix cores (eq. SNEqns with a dense
-// kernel: S_cq = sum_p psi_cp B[p][q], B[p][q] = w_p K[q][p]).
+// Scattering products C = A X on the CDNA4 matrix cores: the dense kernel S = Psi B of
+// eq. SNEqns (B[p][q] = w_p K[q][p], K = N = nq) and the two skinny products of the
+// moment-projected form O Sigma M of eq. SNEqns2 (K or N = the padded moment count).
+// A is [M][K] FP32 row-major, C is [M][N] FP32; K % 32 == 0 and N % 256 == 0.
 //
 // Split precision: every FP32 operand x is written as hi + lo with hi = bf16(x) and
 // lo = bf16(x - hi) (round to nearest even; x - hi is exact in FP32), and the product is
@@ -12,8 +14,8 @@
 //   stages with one barrier per chunk: after the barrier the block writes chunk k+1 into
 //   the idle stage, issues the global loads of chunk k+2 into registers, and multiplies
 //   chunk k out of the other stage.
-//   A (Psi, FP32 rows) is split into hi/lo as it is written to LDS; B arrives pre-split
-//   and pre-tiled (plane[kc][n][kk] = part of B[kc*32 + kk][n]), so one chunk of a block's
+//   A (Psi, FP32 rows) is split into hi/lo as it is written to LDS; X arrives pre-split
+//   and pre-tiled (plane[kc][n][kk] = part of X[kc*32 + kk][n]), so one chunk of a block's
 //   256 columns is a contiguous 16 KB run per half.  Every LDS plane is [256][32] bf16
 //   (64-byte rows) with the 16-byte granule g of row r stored at position g ^ ((r>>2)&3):
 //   the fragment reads of 16 consecutive rows and the stores of 4 consecutive rows then
@@ -72,12 +74,12 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict_
                                                         const uint16_t* __restrict__ Bhi,
                                                         const uint16_t* __restrict__ Blo,
                                                         float* __restrict__ C, int64_t M,
-                                                        int32_t nq)
+                                                        int32_t K, int32_t N)
 {
     constexpr int NP = THREE ? 4 : 2;    // planes per stage: A hi, B hi (, A lo, B lo)
     __shared__ __attribute__((aligned(16))) uint16_t lds[2 * NP * kPlane];
 
-    const int nN = nq / BN;
+    const int nN = N / BN;
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t m0 = (lb / nN) * BM;
     const int n0 = (int)(lb % nN) * BN;
@@ -85,12 +87,12 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict_
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = (wave >> 2) * 128;    // wave tile origin inside the block tile
     const int wn = (wave & 3) * 64;
-    const int nk = nq / BK;
+    const int nk = K / BK;
 
     // A rows as a buffer resource: rows past M read as zero
-    const uint32_t a_bytes = (uint32_t)((M - m0 < BM ? M - m0 : BM) * (int64_t)nq * 4);
+    const uint32_t a_bytes = (uint32_t)((M - m0 < BM ? M - m0 : BM) * (int64_t)K * 4);
     const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(A + m0 * nq), 0, (int32_t)a_bytes, kRsrcWord3);
+        const_cast<float*>(A + m0 * K), 0, (int32_t)a_bytes, kRsrcWord3);
 
     // global -> register staging of one chunk: A 256 x 32 floats = 2048 float4 (4 per
     // thread); B 256 x 32 bf16 per half = 1024 16-byte pieces per half (2 per thread)
@@ -102,10 +104,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict_
             const int p = tid + e * kThreads;
             const int r = p >> 3, g4 = p & 7;
             i32x4 v = __builtin_amdgcn_raw_buffer_load_b128(
-                ra, (uint32_t)((r * nq + kc * BK + g4 * 4) * 4), 0, 0);
+                ra, (uint32_t)((r * K + kc * BK + g4 * 4) * 4), 0, 0);
             ga[e] = __builtin_bit_cast(f32x4, v);
         }
-        const size_t tile = ((size_t)kc * nq + n0) * BK;
+        const size_t tile = ((size_t)kc * N + n0) * BK;
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int p = tid + e * kThreads;
@@ -203,22 +205,22 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict_
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int64_t row = m0 + wm + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-                if (row < M) __builtin_nontemporal_store(acc[i][j][r], &C[row * nq + col]);
+                if (row < M) __builtin_nontemporal_store(acc[i][j][r], &C[row * N + col]);
             }
         }
 }
 
-// Tiled halves: hi[(kc*nq + n)*32 + kk] = bf16(B[kc*32 + kk][n]), lo = bf16(B - hi)
+// Tiled halves of X [K][N]: hi[(kc*N + n)*32 + kk] = bf16(X[kc*32 + kk][n]), lo = bf16(X - hi)
 __global__ __launch_bounds__(256) void k_split(const float* __restrict__ B, uint16_t* __restrict__ hi,
-                                               uint16_t* __restrict__ lo, int32_t nq)
+                                               uint16_t* __restrict__ lo, int32_t K, int32_t N)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= (int64_t)nq * nq) return;
+    if (i >= (int64_t)K * N) return;
     const int kk = (int)(i % BK);
     const int64_t t = i / BK;
-    const int n = (int)(t % nq);
-    const int kc = (int)(t / nq);
-    const float x = B[(int64_t)(kc * BK + kk) * nq + n];
+    const int n = (int)(t % N);
+    const int kc = (int)(t / N);
+    const float x = B[(int64_t)(kc * BK + kk) * N + n];
     const uint32_t h = bf16_rne_bits(x);
     hi[i] = (uint16_t)h;
     lo[i] = (uint16_t)bf16_rne_bits(x - bf16_to_f32(h));
@@ -226,25 +228,26 @@ __global__ __launch_bounds__(256) void k_split(const float* __restrict__ B, uint
 
 }  // namespace
 
-hipError_t launch_split_bf16(const float* B, uint16_t* hi, uint16_t* lo, int32_t nq,
+hipError_t launch_split_bf16(const float* B, uint16_t* hi, uint16_t* lo, int32_t K, int32_t N,
                              hipStream_t st) {
-    if (nq % BN != 0) return hipErrorNotSupported;
-    const int64_t n = (int64_t)nq * nq;
-    hipLaunchKernelGGL(k_split, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, B, hi, lo, nq);
+    if (K % BK != 0 || N % BN != 0) return hipErrorNotSupported;
+    const int64_t n = (int64_t)K * N;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_split, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, B, hi, lo, K, N);
     return hipGetLastError();
 }
 
 hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
-                            int64_t M, int32_t nq, bool three_products, hipStream_t st) {
+                            int64_t M, int32_t K, int32_t N, bool three_products, hipStream_t st) {
     if (M == 0) return hipSuccess;
-    if (nq % BN != 0) return hipErrorNotSupported;
-    const int64_t blocks = ((M + BM - 1) / BM) * (nq / BN);
+    if (K % BK != 0 || N % BN != 0 || K == 0) return hipErrorNotSupported;
+    const int64_t blocks = ((M + BM - 1) / BM) * (N / BN);
     if (three_products)
         hipLaunchKernelGGL(k_gemm_bf16<true>, dim3((unsigned)blocks), dim3(kThreads), 0, st, A,
-                           Bhi, Blo, C, M, nq);
+                           Bhi, Blo, C, M, K, N);
     else
         hipLaunchKernelGGL(k_gemm_bf16<false>, dim3((unsigned)blocks), dim3(kThreads), 0, st, A,
-                           Bhi, Blo, C, M, nq);
+                           Bhi, Blo, C, M, K, N);
     return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
-// Dense scattering product S = Psi B in FP32 / FP64 on the vector ALUs (eq. SNEqns with a
-// dense kernel: S_cq = sum_p psi_cp B[p][q], B[p][q] = w_p K[q][p]).
+// Scattering products C = A X in FP32 / FP64 on the vector ALUs: the dense kernel S = Psi B
+// of eq. SNEqns (S_cq = sum_p psi_cp B[p][q], B[p][q] = w_p K[q][p]) and the two skinny
+// products of the moment-projected form of eq. SNEqns2.  A [M][K], X [K][N], C [M][N].
 //
 // A plain LDS-tiled product: 64 x 64 output tile per 256-thread block, 4 x 4 outputs per
 // thread, K staged in chunks of 16.  M (cells) runs over blockIdx.x, N (ordinates) over
@@ -77,23 +78,23 @@ __global__ __launch_bounds__(256) void k_gemm_simple(const T* __restrict__ A,
 }
 
 template <typename T>
-hipError_t launch(const T* A, const T* B, T* C, int64_t M, int32_t nq, hipStream_t st) {
-    if (M == 0) return hipSuccess;
-    dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((nq + BN - 1) / BN));
-    hipLaunchKernelGGL(k_gemm_simple<T>, grid, dim3(256), 0, st, A, B, C, M, nq, nq);
+hipError_t launch(const T* A, const T* B, T* C, int64_t M, int32_t K, int32_t N, hipStream_t st) {
+    if (M == 0 || N == 0) return hipSuccess;
+    dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN));
+    hipLaunchKernelGGL(k_gemm_simple<T>, grid, dim3(256), 0, st, A, B, C, M, N, K);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_gemm32(const float* A, const float* B, float* C, int64_t M, int32_t nq,
-                         hipStream_t st) {
-    return launch<float>(A, B, C, M, nq, st);
+hipError_t launch_gemm32(const float* A, const float* B, float* C, int64_t M, int32_t K,
+                         int32_t N, hipStream_t st) {
+    return launch<float>(A, B, C, M, K, N, st);
 }
 
-hipError_t launch_gemm64(const double* A, const double* B, double* C, int64_t M, int32_t nq,
-                         hipStream_t st) {
-    return launch<double>(A, B, C, M, nq, st);
+hipError_t launch_gemm64(const double* A, const double* B, double* C, int64_t M, int32_t K,
+                         int32_t N, hipStream_t st) {
+    return launch<double>(A, B, C, M, K, N, st);
 }
 
 }  // namespace snrt

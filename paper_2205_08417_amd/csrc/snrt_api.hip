@@ -390,6 +390,7 @@ snrt_status snrt_quad_create(snrt_quad** out, int32_t nq, const double* omega, c
     }
     qd->nq = nq;
     qd->w_host.assign(w, w + nq);
+    qd->omega_host.assign(omega, omega + (size_t)nq * 3);
     snrt_status s = SNRT_OK;
     if ((s = dev_alloc(&qd->tab32, t32.size(), "ordinates")) != SNRT_OK ||
         (s = dev_alloc(&qd->tab64, t64.size(), "ordinates")) != SNRT_OK ||
@@ -406,15 +407,13 @@ snrt_status snrt_quad_create(snrt_quad** out, int32_t nq, const double* omega, c
 
 void snrt_scatter_destroy(snrt_scatter* sc) {
     if (!sc) return;
-    DenseB& B = sc->B;
-    dev_free(B.b32);
-    dev_free(B.bt32);
-    dev_free(B.b64);
-    dev_free(B.bt64);
-    dev_free(B.b_hi);
-    dev_free(B.b_lo);
-    dev_free(B.bt_hi);
-    dev_free(B.bt_lo);
+    for (GemmOperand* ops : {sc->B.fwd, sc->B.adj})
+        for (int i = 0; i < 2; ++i) {
+            dev_free(ops[i].f32);
+            dev_free(ops[i].f64);
+            dev_free(ops[i].hi);
+            dev_free(ops[i].lo);
+        }
     delete sc;
 }
 
@@ -428,6 +427,72 @@ snrt_status snrt_scatter_isotropic(snrt_scatter** out, const snrt_quad* q) {
     *out = sc;
     return SNRT_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Upload X [K][N] (host FP64) in FP64, FP32 and, for the BF16 modes, as tiled hi/lo parts.
+snrt_status make_operand(GemmOperand& op, const std::vector<double>& x, int32_t K, int32_t N,
+                         snrt_precision precision, const char* fn) {
+    const size_t n = (size_t)K * N;
+    op.K = K;
+    op.N = N;
+    std::vector<float> x32(n);
+    for (size_t i = 0; i < n; ++i) x32[i] = (float)x[i];
+    snrt_status s = SNRT_OK;
+    if ((s = dev_alloc(&op.f32, n, "scattering operand")) != SNRT_OK ||
+        (s = dev_alloc(&op.f64, n, "scattering operand")) != SNRT_OK ||
+        (s = upload(op.f32, x32.data(), n, fn)) != SNRT_OK ||
+        (s = upload(op.f64, x.data(), n, fn)) != SNRT_OK)
+        return s;
+    if (precision == SNRT_FP32) return SNRT_OK;
+    if ((s = dev_alloc(&op.hi, n, "scattering operand (BF16 hi)")) != SNRT_OK ||
+        (s = dev_alloc(&op.lo, n, "scattering operand (BF16 lo)")) != SNRT_OK)
+        return s;
+    hipError_t e = launch_split_bf16(op.f32, op.hi, op.lo, K, N, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, fn);
+}
+
+// Real spherical harmonics m_l^k of the moment equations up to degree N at a direction given
+// in the paper's parametrisation (mu = z, phi = atan2(x, y)); out[l*l + l + k].  Built from
+// the normalised complex harmonics with associated Legendre functions (Condon-Shortley
+// phase) by the three-term recurrence in l: m_l^0 = Y_l^0, m_l^{+-k} = (-1)^k sqrt(2) times
+// the real / imaginary part of Y_l^k.
+void real_harmonics(int N, double x, double y, double z, double* out) {
+    const int W = N + 1;
+    std::vector<double> P((size_t)W * W, 0.0);
+    auto p = [&](int l, int k) -> double& { return P[(size_t)l * W + k]; };
+    const double mu = z;
+    const double s = std::sqrt(std::max(0.0, 1.0 - mu * mu));
+    const double phi = std::atan2(x, y);
+    p(0, 0) = 1.0;
+    for (int k = 1; k <= N; ++k) p(k, k) = -(2.0 * k - 1.0) * s * p(k - 1, k - 1);
+    for (int k = 0; k < N; ++k) p(k + 1, k) = (2.0 * k + 1.0) * mu * p(k, k);
+    for (int k = 0; k <= N; ++k)
+        for (int l = k + 2; l <= N; ++l)
+            p(l, k) = ((2.0 * l - 1.0) * mu * p(l - 1, k) - (l + k - 1.0) * p(l - 2, k)) / (l - k);
+    const double four_pi = 4.0 * 3.14159265358979323846;
+    for (int l = 0; l <= N; ++l) {
+        double ratio = 1.0;                       // (l-k)!/(l+k)!, built up as k grows
+        for (int k = 0; k <= l; ++k) {
+            if (k > 0) ratio /= (double)(l + k) * (double)(l - k + 1);
+            const double norm = std::sqrt((2.0 * l + 1.0) / four_pi * ratio);
+            if (k == 0) {
+                out[l * l + l] = norm * p(l, 0);
+            } else {
+                const double c = ((k & 1) ? -1.0 : 1.0) * std::sqrt(2.0) * norm * p(l, k);
+                out[l * l + l + k] = c * std::cos(k * phi);
+                out[l * l + l - k] = c * std::sin(k * phi);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
 
 snrt_status snrt_scatter_dense(snrt_scatter** out, const snrt_quad* q, const double* K,
                                snrt_precision precision) {
@@ -451,10 +516,59 @@ snrt_status snrt_scatter_dense(snrt_scatter** out, const snrt_quad* q, const dou
             b64[(size_t)p * nq + qq] = q->w_host[p] * kqp;                        // w_p K[q][p]
             bt64[(size_t)p * nq + qq] = q->w_host[qq] * K[(size_t)p * nq + qq];   // w_q K[p][q]
         }
-    std::vector<float> b32(n2), bt32(n2);
-    for (size_t i = 0; i < n2; ++i) {
-        b32[i] = (float)b64[i];
-        bt32[i] = (float)bt64[i];
+    snrt_scatter* sc = new snrt_scatter();
+    sc->device = q->device;
+    sc->dense = true;
+    DenseB& B = sc->B;
+    B.nq = nq;
+    B.precision = precision;
+    B.chain = 1;
+    snrt_status s = SNRT_OK;
+    if ((s = make_operand(B.fwd[0], b64, nq, nq, precision, "snrt_scatter_dense: upload")) != SNRT_OK ||
+        (s = make_operand(B.adj[0], bt64, nq, nq, precision, "snrt_scatter_dense: upload")) != SNRT_OK) {
+        snrt_scatter_destroy(sc);
+        return s;
+    }
+    *out = sc;
+    return SNRT_OK;
+}
+
+snrt_status snrt_scatter_moments(snrt_scatter** out, const snrt_quad* q, int32_t degree,
+                                 const double* sigma_l, snrt_precision precision) {
+    g_last_error.clear();
+    SNRT_REQUIRE(out && q && sigma_l, SNRT_E_ARG, "snrt_scatter_moments: NULL argument");
+    *out = nullptr;
+    SNRT_REQUIRE(precision == SNRT_FP32 || precision == SNRT_BF16X3 || precision == SNRT_BF16X1,
+                 SNRT_E_ARG, "snrt_scatter_moments: unknown precision");
+    SNRT_REQUIRE(degree >= 0 && degree <= 30, SNRT_E_ARG,
+                 "snrt_scatter_moments: degree must be in [0, 30]");
+    const int32_t nq = q->nq;
+    if (precision != SNRT_FP32) {
+        SNRT_REQUIRE(nq % 256 == 0, SNRT_E_UNSUPPORTED,
+                     "snrt_scatter_moments: BF16 modes need nq % 256 == 0");
+    }
+    for (int l = 0; l <= degree; ++l)
+        SNRT_REQUIRE(is_finite(sigma_l[l]), SNRT_E_ARG,
+                     "snrt_scatter_moments: non-finite Legendre moment");
+    SNRT_TRY(check_device(q->device, "snrt_scatter_moments"));
+    const int32_t nm = (degree + 1) * (degree + 1);
+    const int32_t mid = precision == SNRT_FP32 ? nm : ((nm + 255) / 256) * 256;
+    // Mt[q][j] = w_q m_j(Omega_q), Ot[j][q] = sigma_l(j) m_j(Omega_q); zero past nm
+    std::vector<double> mt((size_t)nq * mid, 0.0), ot((size_t)mid * nq, 0.0);
+    std::vector<double> mtT((size_t)mid * nq, 0.0), otT((size_t)nq * mid, 0.0);
+    std::vector<double> m(nm);
+    for (int32_t qq = 0; qq < nq; ++qq) {
+        const double* o = q->omega_host.data() + (size_t)qq * 3;
+        real_harmonics(degree, o[0], o[1], o[2], m.data());
+        for (int l = 0; l <= degree; ++l)
+            for (int j = l * l; j < (l + 1) * (l + 1); ++j) {
+                const double a = q->w_host[qq] * m[j];
+                const double b = sigma_l[l] * m[j];
+                mt[(size_t)qq * mid + j] = a;
+                mtT[(size_t)j * nq + qq] = a;
+                ot[(size_t)j * nq + qq] = b;
+                otT[(size_t)qq * mid + j] = b;
+            }
     }
     snrt_scatter* sc = new snrt_scatter();
     sc->device = q->device;
@@ -462,42 +576,43 @@ snrt_status snrt_scatter_dense(snrt_scatter** out, const snrt_quad* q, const dou
     DenseB& B = sc->B;
     B.nq = nq;
     B.precision = precision;
+    B.chain = 2;
+    B.mid = mid;
+    B.degree = degree;
     snrt_status s = SNRT_OK;
-    if ((s = dev_alloc(&B.b32, n2, "B")) != SNRT_OK || (s = dev_alloc(&B.bt32, n2, "B^T")) != SNRT_OK ||
-        (s = dev_alloc(&B.b64, n2, "B")) != SNRT_OK || (s = dev_alloc(&B.bt64, n2, "B^T")) != SNRT_OK ||
-        (s = upload(B.b32, b32.data(), n2, "snrt_scatter_dense: upload")) != SNRT_OK ||
-        (s = upload(B.bt32, bt32.data(), n2, "snrt_scatter_dense: upload")) != SNRT_OK ||
-        (s = upload(B.b64, b64.data(), n2, "snrt_scatter_dense: upload")) != SNRT_OK ||
-        (s = upload(B.bt64, bt64.data(), n2, "snrt_scatter_dense: upload")) != SNRT_OK) {
+    const char* fn = "snrt_scatter_moments: upload";
+    if ((s = make_operand(B.fwd[0], mt, nq, mid, precision, fn)) != SNRT_OK ||
+        (s = make_operand(B.fwd[1], ot, mid, nq, precision, fn)) != SNRT_OK ||
+        (s = make_operand(B.adj[0], otT, nq, mid, precision, fn)) != SNRT_OK ||
+        (s = make_operand(B.adj[1], mtT, mid, nq, precision, fn)) != SNRT_OK) {
         snrt_scatter_destroy(sc);
         return s;
-    }
-    if (precision != SNRT_FP32) {
-        if ((s = dev_alloc(&B.b_hi, n2, "B hi")) != SNRT_OK ||
-            (s = dev_alloc(&B.b_lo, n2, "B lo")) != SNRT_OK ||
-            (s = dev_alloc(&B.bt_hi, n2, "B^T hi")) != SNRT_OK ||
-            (s = dev_alloc(&B.bt_lo, n2, "B^T lo")) != SNRT_OK) {
-            snrt_scatter_destroy(sc);
-            return s;
-        }
-        hipError_t e = launch_split_bf16(B.b32, B.b_hi, B.b_lo, nq, nullptr);
-        if (e == hipSuccess) e = launch_split_bf16(B.bt32, B.bt_hi, B.bt_lo, nq, nullptr);
-        if (e == hipSuccess) e = hipDeviceSynchronize();
-        if (e != hipSuccess) {
-            snrt_scatter_destroy(sc);
-            return hip_fail(e, "snrt_scatter_dense: BF16 split");
-        }
     }
     *out = sc;
     return SNRT_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Elements of the scattering product's workspace: S [nc][nq] and, for the moment form, the
+// moments U [nc][mid] between its two products.
+size_t product_ws_elems(const snrt_scatter* sc, int64_t nc) {
+    if (!sc->dense) return 0;
+    return (size_t)nc * (size_t)(sc->B.nq + (sc->B.chain == 2 ? sc->B.mid : 0));
+}
+
+}  // namespace
+
+extern "C" {
 
 snrt_status snrt_workspace_size(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
                                 size_t* bytes) {
     g_last_error.clear();
     SNRT_REQUIRE(m && q && sc && bytes, SNRT_E_ARG, "snrt_workspace_size: NULL argument");
     SNRT_REQUIRE(sc->B.nq == q->nq, SNRT_E_SHAPE, "snrt_workspace_size: scatter/quad nq differ");
-    *bytes = sc->dense ? (size_t)m->nc * q->nq * sizeof(double) : 0;
+    *bytes = product_ws_elems(sc, m->nc) * sizeof(double);
     return SNRT_OK;
 }
 
@@ -508,8 +623,8 @@ snrt_status snrt_step2_workspace_size(const snrt_mesh* m, const snrt_quad* q,
     SNRT_REQUIRE(fp64 == 0 || fp64 == 1, SNRT_E_ARG, "snrt_step2_workspace_size: fp64 is 0 or 1");
     SNRT_REQUIRE(sc->B.nq == q->nq, SNRT_E_SHAPE,
                  "snrt_step2_workspace_size: scatter/quad nq differ");
-    const size_t row = (size_t)m->nc * q->nq * (fp64 ? sizeof(double) : sizeof(float));
-    *bytes = row * (sc->dense ? 4 : 3);
+    const size_t elem = fp64 ? sizeof(double) : sizeof(float);
+    *bytes = ((size_t)m->nc * q->nq * 3 + product_ws_elems(sc, m->nc)) * elem;
     return SNRT_OK;
 }
 
@@ -545,7 +660,7 @@ snrt_status check_step_common(const char* fn, const snrt_mesh* m, const snrt_qua
     SNRT_REQUIRE(!ranges_overlap(in, bytes, out, bytes), SNRT_E_ALIAS,
                  std::string(fn) + ": output aliases input");
     if (sc->dense) {
-        const size_t need = (size_t)m->nc * q->nq * elem;
+        const size_t need = product_ws_elems(sc, m->nc) * elem;
         SNRT_REQUIRE(ws && ws_bytes >= need, SNRT_E_ARG,
                      std::string(fn) + ": dense scattering needs a workspace of " +
                          std::to_string(need) + " bytes");
@@ -587,13 +702,39 @@ StepArgs64 to64(const snrt_step_args_f64* a) {
 }
 
 // S = Psi B (forward) or G = Lambda B^T (adjoint) into the workspace, FP32 state
-hipError_t dense_product32(const snrt_scatter* sc, const float* A, float* C, int64_t M,
-                           bool transpose, hipStream_t st) {
+// C = A X0 [X1] (forward) or A X0^T-side chain (adjoint); scratch holds the moments between
+// the two products of the moment form ([M][mid]).
+hipError_t scatter_product32(const snrt_scatter* sc, const float* A, float* C, int64_t M,
+                             bool transpose, float* scratch, hipStream_t st) {
     const DenseB& B = sc->B;
-    if (B.precision == SNRT_FP32)
-        return launch_gemm32(A, transpose ? B.bt32 : B.b32, C, M, B.nq, st);
-    return launch_gemm_bf16(A, transpose ? B.bt_hi : B.b_hi, transpose ? B.bt_lo : B.b_lo, C, M,
-                            B.nq, B.precision == SNRT_BF16X3, st);
+    const GemmOperand* ops = transpose ? B.adj : B.fwd;
+    const float* in = A;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < B.chain && e == hipSuccess; ++i) {
+        float* out = (i == B.chain - 1) ? C : scratch;
+        const GemmOperand& op = ops[i];
+        if (B.precision == SNRT_FP32)
+            e = launch_gemm32(in, op.f32, out, M, op.K, op.N, st);
+        else
+            e = launch_gemm_bf16(in, op.hi, op.lo, out, M, op.K, op.N,
+                                 B.precision == SNRT_BF16X3, st);
+        in = out;
+    }
+    return e;
+}
+
+hipError_t scatter_product64(const snrt_scatter* sc, const double* A, double* C, int64_t M,
+                             bool transpose, double* scratch, hipStream_t st) {
+    const DenseB& B = sc->B;
+    const GemmOperand* ops = transpose ? B.adj : B.fwd;
+    const double* in = A;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < B.chain && e == hipSuccess; ++i) {
+        double* out = (i == B.chain - 1) ? C : scratch;
+        e = launch_gemm64(in, ops[i].f64, out, M, ops[i].K, ops[i].N, st);
+        in = out;
+    }
+    return e;
 }
 
 }  // namespace
@@ -611,7 +752,8 @@ snrt_status snrt_step(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter
     const float* S = nullptr;
     if (sc->dense) {
         float* Sbuf = static_cast<float*>(ws);
-        hipError_t e = dense_product32(sc, psi_in, Sbuf, m->nc, false, st);
+        hipError_t e = scatter_product32(sc, psi_in, Sbuf, m->nc, false,
+                                         Sbuf + (size_t)m->nc * q->nq, st);
         if (e != hipSuccess) return hip_fail(e, "snrt_step: scattering product");
         S = Sbuf;
     }
@@ -630,7 +772,8 @@ snrt_status snrt_step_f64(const snrt_mesh* m, const snrt_quad* q, const snrt_sca
     const double* S = nullptr;
     if (sc->dense) {
         double* Sbuf = static_cast<double*>(ws);
-        hipError_t e = launch_gemm64(psi_in, sc->B.b64, Sbuf, m->nc, q->nq, st);
+        hipError_t e = scatter_product64(sc, psi_in, Sbuf, m->nc, false,
+                                         Sbuf + (size_t)m->nc * q->nq, st);
         if (e != hipSuccess) return hip_fail(e, "snrt_step_f64: scattering product");
         S = Sbuf;
     }
@@ -655,7 +798,8 @@ snrt_status snrt_step_adjoint(const snrt_mesh* m, const snrt_quad* q, const snrt
     const float* G = nullptr;
     if (sc->dense) {
         float* Gbuf = static_cast<float*>(ws);
-        hipError_t e = dense_product32(sc, lam_np1, Gbuf, m->nc, true, st);
+        hipError_t e = scatter_product32(sc, lam_np1, Gbuf, m->nc, true,
+                                         Gbuf + (size_t)m->nc * q->nq, st);
         if (e != hipSuccess) return hip_fail(e, "snrt_step_adjoint: scattering product");
         G = Gbuf;
     }
@@ -680,7 +824,8 @@ snrt_status snrt_step_adjoint_f64(const snrt_mesh* m, const snrt_quad* q, const 
     const double* G = nullptr;
     if (sc->dense) {
         double* Gbuf = static_cast<double*>(ws);
-        hipError_t e = launch_gemm64(lam_np1, sc->B.bt64, Gbuf, m->nc, q->nq, st);
+        hipError_t e = scatter_product64(sc, lam_np1, Gbuf, m->nc, true,
+                                         Gbuf + (size_t)m->nc * q->nq, st);
         if (e != hipSuccess) return hip_fail(e, "snrt_step_adjoint_f64: scattering product");
         G = Gbuf;
     }
@@ -702,7 +847,7 @@ snrt_status step2_common(const char* fn, const snrt_mesh* m, const snrt_quad* q,
     SNRT_REQUIRE(m->recon32 && m->recon64, SNRT_E_ARG,
                  std::string(fn) + ": call snrt_mesh_set_face_midpoints first");
     const size_t row = (size_t)m->nc * q->nq * sizeof(T);
-    const size_t need = row * (sc->dense ? 4 : 3);
+    const size_t need = row * 3 + product_ws_elems(sc, m->nc) * sizeof(T);
     SNRT_REQUIRE(ws && ws_bytes >= need, SNRT_E_ARG,
                  std::string(fn) + ": needs a workspace of " + std::to_string(need) + " bytes");
     SNRT_REQUIRE(aligned16(ws), SNRT_E_ARG, std::string(fn) + ": workspace must be 16-byte aligned");
@@ -711,6 +856,7 @@ snrt_status step2_common(const char* fn, const snrt_mesh* m, const snrt_quad* q,
     T* star = static_cast<T*>(ws);
     T* G = star + (size_t)m->nc * q->nq;
     T* S = sc->dense ? G + 2 * (size_t)m->nc * q->nq : nullptr;
+    T* U = sc->dense ? S + (size_t)m->nc * q->nq : nullptr;     // moments between products
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
     const T* in[2] = {psi_in, star};
@@ -719,14 +865,14 @@ snrt_status step2_common(const char* fn, const snrt_mesh* m, const snrt_quad* q,
         if constexpr (sizeof(T) == 4) {
             const StepArgs32 a32 = to32(a);
             e = launch_grad2_32(*m, *q, a32, in[stage], G, st);
-            if (e == hipSuccess && S) e = dense_product32(sc, in[stage], S, m->nc, false, st);
+            if (e == hipSuccess && S) e = scatter_product32(sc, in[stage], S, m->nc, false, U, st);
             if (e == hipSuccess)
                 e = launch_flux2_32(*m, *q, a32, in[stage], G, S, stage ? psi_in : nullptr,
                                     outp[stage], st);
         } else {
             const StepArgs64 a64 = to64(a);
             e = launch_grad2_64(*m, *q, a64, in[stage], G, st);
-            if (e == hipSuccess && S) e = launch_gemm64(in[stage], sc->B.b64, S, m->nc, q->nq, st);
+            if (e == hipSuccess && S) e = scatter_product64(sc, in[stage], S, m->nc, false, U, st);
             if (e == hipSuccess)
                 e = launch_flux2_64(*m, *q, a64, in[stage], G, S, stage ? psi_in : nullptr,
                                     outp[stage], st);
@@ -759,6 +905,8 @@ snrt_status snrt_scatter_apply(const snrt_mesh* m, const snrt_quad* q, const snr
     g_last_error.clear();
     SNRT_REQUIRE(m && q && sc, SNRT_E_ARG, "snrt_scatter_apply: NULL handle");
     SNRT_REQUIRE(sc->dense, SNRT_E_UNSUPPORTED, "snrt_scatter_apply: needs a dense scatter handle");
+    SNRT_REQUIRE(sc->B.chain == 1, SNRT_E_UNSUPPORTED,
+                 "snrt_scatter_apply: the moment form needs a workspace; use the step entry points");
     SNRT_REQUIRE(sc->B.nq == q->nq, SNRT_E_SHAPE, "snrt_scatter_apply: scatter/quad nq differ");
     SNRT_REQUIRE(transpose == 0 || transpose == 1, SNRT_E_ARG, "snrt_scatter_apply: transpose is 0 or 1");
     SNRT_TRY(check_device(m->device, "snrt_scatter_apply"));
@@ -767,7 +915,8 @@ snrt_status snrt_scatter_apply(const snrt_mesh* m, const snrt_quad* q, const snr
                  "snrt_scatter_apply: NULL or misaligned array");
     const size_t bytes = (size_t)m->nc * q->nq * sizeof(float);
     SNRT_REQUIRE(!ranges_overlap(psi, bytes, S, bytes), SNRT_E_ALIAS, "snrt_scatter_apply: S aliases psi");
-    hipError_t e = dense_product32(sc, psi, S, m->nc, transpose != 0, static_cast<hipStream_t>(stream));
+    hipError_t e = scatter_product32(sc, psi, S, m->nc, transpose != 0, nullptr,
+                                     static_cast<hipStream_t>(stream));
     return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_scatter_apply: launch");
 }
 

@@ -52,19 +52,30 @@ struct alignas(64) CellRecon64 {
 };
 static_assert(sizeof(CellRecon64) == 128, "two cache lines per cell");
 
-// Dense scattering operands on the device: B for the forward product S = Psi B and B^T for
-// the adjoint product Lambda B^T, in FP32 / FP64 and as BF16 hi/lo pairs for MFMA.
+// Right operand X [K][N] of a scattering product C = A X on the device, in every precision
+// the products use: FP32 and FP64 row-major, and BF16 hi/lo parts tiled by K chunks of 32
+// ([K/32][N][32]) for the MFMA kernel.
+struct GemmOperand {
+    int32_t K = 0, N = 0;
+    float* f32 = nullptr;
+    double* f64 = nullptr;
+    uint16_t* hi = nullptr;
+    uint16_t* lo = nullptr;
+};
+
+// The scattering product as a chain of right operands, forward (S = Psi X0 [X1]) and adjoint
+// (Lambda B^T):
+//   dense kernel (chain 1):  X0 = B, B[p][q] = w_p K[q][p];  adjoint X0 = B^T;
+//   moments (chain 2, eq. SNEqns2):  X0 = M^T [nq][mid] (w_q m_j(Omega_q)), X1 = (Sigma O)^T
+//   [mid][nq] (sigma_l(j) m_j(Omega_q)); adjoint X0 = X1^T, X1 = X0^T.  mid = the moment
+//   count (N+1)^2, padded with zero columns to a multiple of 256 for the MFMA kernel.
 struct DenseB {
     int32_t nq = 0;
     snrt_precision precision = SNRT_FP32;
-    float* b32 = nullptr;        // [nq][nq]  B[p][q] = w_p K[q][p]   (forward)
-    float* bt32 = nullptr;       // [nq][nq]  B^T[p][q] = w_q K[p][q] (adjoint)
-    double* b64 = nullptr;
-    double* bt64 = nullptr;
-    uint16_t* b_hi = nullptr;    // BF16 bit patterns, layout chosen by the GEMM kernel
-    uint16_t* b_lo = nullptr;
-    uint16_t* bt_hi = nullptr;
-    uint16_t* bt_lo = nullptr;
+    int32_t chain = 1;
+    int32_t mid = 0;
+    int32_t degree = -1;          // moment degree N (chain 2)
+    GemmOperand fwd[2], adj[2];
 };
 
 }  // namespace snrt
@@ -95,6 +106,7 @@ struct snrt_quad {
     float* tab32 = nullptr;
     double* tab64 = nullptr;
     std::vector<double> w_host;
+    std::vector<double> omega_host;        // [nq*3] unit directions (x, y, z)
 };
 
 struct snrt_scatter {
@@ -139,15 +151,15 @@ hipError_t launch_adjoint64(const snrt_mesh& m, const snrt_quad& q, const StepAr
                             double* g_t, double* g_s, double* g_r, const double* G,
                             hipStream_t st);
 
-// Dense scattering products C[M][N] = A[M][K] B[K][N] with M = ncells, N = K = nq.
-hipError_t launch_gemm32(const float* A, const float* B, float* C, int64_t M, int32_t nq,
-                         hipStream_t st);
-hipError_t launch_gemm64(const double* A, const double* B, double* C, int64_t M, int32_t nq,
-                         hipStream_t st);
+// Scattering products C[M][N] = A[M][K] X[K][N] (M = ncells).
+hipError_t launch_gemm32(const float* A, const float* B, float* C, int64_t M, int32_t K,
+                         int32_t N, hipStream_t st);
+hipError_t launch_gemm64(const double* A, const double* B, double* C, int64_t M, int32_t K,
+                         int32_t N, hipStream_t st);
 hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
-                            int64_t M, int32_t nq, bool three_products, hipStream_t st);
-// Re-layout of an FP32 [nq][nq] matrix into the BF16 hi/lo operand format of the MFMA GEMM.
-hipError_t launch_split_bf16(const float* B, uint16_t* hi, uint16_t* lo, int32_t nq,
+                            int64_t M, int32_t K, int32_t N, bool three_products, hipStream_t st);
+// Re-layout of an FP32 [K][N] matrix into the BF16 hi/lo operand format of the MFMA GEMM.
+hipError_t launch_split_bf16(const float* B, uint16_t* hi, uint16_t* lo, int32_t K, int32_t N,
                              hipStream_t st);
 
 // Second-order scheme (sn_step2.hip): limited gradient of a stage input and the stage

@@ -46,6 +46,7 @@ EXPORTS = [
     "snrt_step_adjoint_f64", "snrt_scatter_apply", "snrt_mass", "snrt_scalar_flux",
     "snrt_dose_accumulate", "snrt_dose_adjoint", "snrt_dose_density_grad", "snrt_permute",
     "snrt_mesh_set_face_midpoints", "snrt_step2_workspace_size", "snrt_step2", "snrt_step2_f64",
+    "snrt_scatter_moments",
 ]
 
 
@@ -112,6 +113,8 @@ def lib() -> ctypes.CDLL:
         "snrt_dose_density_grad": (_st, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "snrt_permute": (_st, [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int64, _vp]),
         "snrt_mesh_set_face_midpoints": (_st, [_vp, _dp]),
+        "snrt_scatter_moments": (_st, [ctypes.POINTER(_vp), _vp, ctypes.c_int32, _dp,
+                                       ctypes.c_int]),
         "snrt_step2_workspace_size": (_st, [_vp, _vp, _vp, ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_size_t)]),
         "snrt_step2": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp,
@@ -237,6 +240,14 @@ def snrt_scatter_dense(quad: int, K, precision=SNRT_FP32) -> int:
     h = _vp()
     _check("snrt_scatter_dense", lib().snrt_scatter_dense(ctypes.byref(h), quad, pk,
                                                           int(precision)))
+    return h.value
+
+
+def snrt_scatter_moments(quad: int, sigma_l, precision=SNRT_FP32) -> int:
+    arr, p = _f64(sigma_l)
+    h = _vp()
+    _check("snrt_scatter_moments",
+           lib().snrt_scatter_moments(ctypes.byref(h), quad, int(arr.size - 1), p, int(precision)))
     return h.value
 
 

@@ -27,12 +27,14 @@ class Solver:
     """Device-resident S_N problem: mesh / quadrature / scattering handles and materials.
 
     ``precision`` selects the dense scattering product (``fp32``, ``bf16x3``, ``bf16x1``);
-    isotropic problems ignore it.  ``fp64`` additionally uploads FP64 copies of the
+    isotropic problems ignore it.  ``moments`` (Legendre moments sigma_0..sigma_N of the
+    scattering kernel) selects the moment-projected scattering O Sigma M instead of ``P.K``.  ``fp64`` additionally uploads FP64 copies of the
     materials for the FP64 parity template (:meth:`step_f64`).
     """
 
     def __init__(self, P: Problem, device: str = "cuda", precision: str = "fp32",
-                 reorder: bool = True, fp64: bool = False):
+                 reorder: bool = True, fp64: bool = False,
+                 moments: Optional[Sequence[float]] = None):
         _require_gpu()
         self.P = P
         self.device = torch.device(device)
@@ -43,7 +45,10 @@ class Solver:
             self.mesh = snrt.snrt_mesh_create(m.face_nbr, m.face_normal, m.area, m.centroid,
                                               m.nbfaces, flags)
             self.quad = snrt.snrt_quad_create(P.omega, P.w)
-            if P.K is None:
+            if moments is not None:
+                # moment-projected scattering O Sigma M (eq. SNEqns2) with Legendre moments
+                self.scatter = snrt.snrt_scatter_moments(self.quad, moments, _PREC[precision])
+            elif P.K is None:
                 self.scatter = snrt.snrt_scatter_isotropic(self.quad)
             else:
                 self.scatter = snrt.snrt_scatter_dense(self.quad, P.K, _PREC[precision])
