@@ -279,10 +279,15 @@ class SNRollout(torch.autograd.Function):
         pa, pb = a.data_ptr(), b.data_ptr()
         dose = (torch.zeros(S.nc, dtype=torch.float64, device=a.device)
                 if dose_coeff is not None else None)
+        # one allocation holds every checkpoint (no allocator traffic inside the time loop)
+        n_ck = (nsteps + ckpt_every - 1) // ckpt_every
+        ck_store = torch.empty((max(n_ck, 1),) + tuple(a.shape), dtype=a.dtype, device=a.device)
         ckpts = []
         for n in range(nsteps):
             if n % ckpt_every == 0:
-                ckpts.append(a.clone() if pa == a.data_ptr() else b.clone())
+                dst = ck_store[len(ckpts)]
+                dst.copy_(a if pa == a.data_ptr() else b)
+                ckpts.append(dst)
             if dose is not None:
                 snrt.snrt_dose_accumulate(S.mesh, S.quad, pa, inv_rho, float(dose_coeff[n]),
                                           dose, stream)
@@ -319,8 +324,8 @@ class SNRollout(torch.autograd.Function):
         stepper = snrt.snrt_step_f64 if fp64 else snrt.snrt_step
         adjoint = snrt.snrt_step_adjoint_f64 if fp64 else snrt.snrt_step_adjoint
         stream, ws = ctx.stream, ctx.ws
-        seg = [torch.empty_like(lam) for _ in range(K)]
-        seg_ptr = [t.data_ptr() for t in seg]
+        seg = torch.empty((K,) + tuple(lam.shape), dtype=lam.dtype, device=lam.device)
+        seg_ptr = [seg[i].data_ptr() for i in range(K)]
         pl, pn = lam.data_ptr(), lam_new.data_ptr()
         gtp, gsp = g_t.data_ptr(), g_s.data_ptr()
         grp = g_r.data_ptr() if g_r is not None else None
