@@ -1,0 +1,96 @@
+"""Pins of the oracle's IMEX step (Sec. 4.2): collision operator implicit, streaming and
+source explicit.  Closed forms (backward-Euler decay, a stationary uniform state, the mass
+balance of the implicit collision), positivity beyond the explicit stability limit, and the
+Sherman-Morrison solution of the isotropic system, which the oracle does not use (it solves
+the per-cell system with LU)."""
+import dataclasses
+
+import numpy as np
+
+from _util import small_problem
+
+from oracle import oracle as o
+from paper_2205_08417_amd import inputs as I
+
+
+def test_backward_euler_decay_of_pure_absorption():
+    mesh = I.periodic_mesh(5)
+    P = small_problem(mesh, seed=1)
+    sig = 4.0
+    P = dataclasses.replace(P, sigma_t=np.full(P.ncells, sig), sigma_s=np.zeros(P.ncells),
+                            psi0=np.full((P.ncells, P.nq), 3.0))
+    out = o.step_imex(o.OracleProblem.from_problem(P), P.psi0, P.dt)
+    np.testing.assert_allclose(out, 3.0 / (1 + P.dt * sig), rtol=1e-14)
+
+
+def test_uniform_isotropic_state_is_stationary():
+    mesh = I.jittered_delaunay_mesh(9, 0.0, 1.0, seed=2)
+    P = small_problem(mesh, seed=2)
+    sig = np.full(P.ncells, 50.0)
+    P = dataclasses.replace(P, sigma_t=sig, sigma_s=sig, psi0=np.full((P.ncells, P.nq), 0.4),
+                            inflow=np.full((mesh.nbfaces, P.nq), 0.4))
+    out = o.step_imex(o.OracleProblem.from_problem(P), P.psi0, P.dt * 30)
+    np.testing.assert_allclose(out, 0.4, rtol=1e-12)
+
+
+def test_mass_balance_of_implicit_collision():
+    """On a torus the flux sum vanishes, so sum_q w_q psi' = sum_q w_q b / (1 + dt(sigma_t -
+    sigma_s)) per cell for isotropic scattering with sum w = 4 pi."""
+    mesh = I.periodic_mesh(6)
+    P = small_problem(mesh, seed=3, source=True)
+    P = dataclasses.replace(P, sigma_s=0.6 * P.sigma_t)
+    op = o.OracleProblem.from_problem(P)
+    dt = 5 * P.dt
+    out = o.step_imex(op, P.psi0, dt)
+    zero = np.zeros(P.ncells)
+    b = o.step(op.replace(sigma_t=zero, sigma_s=zero), P.psi0, dt)
+    lhs = out @ P.w
+    rhs = (b @ P.w) / (1 + dt * (P.sigma_t - P.sigma_s))
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-12)
+
+
+def test_positive_beyond_explicit_limit():
+    """dt sigma = 200: the explicit collision factor 1 - dt sigma is hugely negative; the IMEX
+    step stays positive and below the incoming maximum."""
+    mesh = I.jittered_delaunay_mesh(8, 0.0, 1.0, seed=4)
+    P = small_problem(mesh, seed=4, inflow=True)
+    sig_t = 200.0 / P.dt
+    P = dataclasses.replace(P, sigma_t=np.full(P.ncells, sig_t),
+                            sigma_s=np.full(P.ncells, 0.9 * sig_t))
+    op = o.OracleProblem.from_problem(P)
+    out = o.step_imex(op, P.psi0, P.dt)
+    assert np.all(out > 0) and out.max() <= max(P.psi0.max(), P.inflow.max())
+    exp = o.step(op, P.psi0, P.dt)
+    assert exp.min() < 0
+
+
+def test_isotropic_system_matches_sherman_morrison():
+    mesh = I.jittered_delaunay_mesh(9, 0.0, 1.0, seed=5)
+    P = small_problem(mesh, seed=5, rho=True, source=True, inflow=True, scatter=(1.0, 3.0))
+    op = o.OracleProblem.from_problem(P)
+    dt = 3 * P.dt
+    out = o.step_imex(op, P.psi0, dt, alpha_t=1.2, alpha_s=0.7, inflow_scale=0.5)
+    zero = np.zeros(P.ncells)
+    b = o.step(op.replace(sigma_t=zero, sigma_s=zero), P.psi0, dt, inflow_scale=0.5)
+    a = 1 + dt * 1.2 * P.sigma_t
+    c = dt * 0.7 * P.sigma_s
+    W = P.w.sum() / (4 * np.pi)
+    phi4 = (b @ P.w) / (4 * np.pi) / (a - c * W)       # (sum_p w_p psi'_p) / (4 pi)
+    ref = (b + (c * phi4)[:, None]) / a[:, None]
+    np.testing.assert_allclose(out, ref, rtol=1e-12, atol=1e-15)
+
+
+def test_dense_kernel_system():
+    """With a dense HG kernel the oracle's solution satisfies the system it solves."""
+    omega, w = I.product_quadrature(4, 8)
+    K = I.henyey_greenstein_kernel(omega, w, 0.6)
+    P = small_problem(I.jittered_delaunay_mesh(7, 0.0, 1.0, seed=6), omega_w=(omega, w), K=K,
+                      seed=6, scatter=(1.0, 2.0))
+    op = o.OracleProblem.from_problem(P)
+    dt = 4 * P.dt
+    out = o.step_imex(op, P.psi0, dt)
+    zero = np.zeros(P.ncells)
+    b = o.step(op.replace(sigma_t=zero, sigma_s=zero), P.psi0, dt)
+    S = (out * w[None, :]) @ K.T
+    res = (1 + dt * P.sigma_t)[:, None] * out - (dt * P.sigma_s)[:, None] * S - b
+    assert np.abs(res).max() <= 1e-12 * np.abs(b).max()
