@@ -216,6 +216,22 @@ snrt_status snrt_scatter_apply(const snrt_mesh* mesh, const snrt_quad* quad,
                                const snrt_scatter* scatter, const float* psi, float* S,
                                int32_t transpose, void* stream);
 
+/* IMEX step (Sec. 4.2): the linear collision operator R psi = -alpha_t sigma_t psi +
+ * alpha_s sigma_s S(psi) is taken implicitly, streaming and the source explicitly:
+ *     (I - dt R_i) psi_out_i = psi_in_i - dt/A_i sum_f F_up(psi_in) + dt q_i.
+ * Isotropic scattering only (SNRT_E_UNSUPPORTED for dense or moment handles): the per-cell
+ * system has the closed-form solution
+ *     psi'_q = (b_q + c B / (a - c W)) / a,  a = 1 + dt alpha_t sigma_t, c = dt alpha_s sigma_s,
+ *     B = sum_q w_q b_q / (4 pi),  W = sum_q w_q / (4 pi),
+ * which stays positive for any dt sigma (the streaming part keeps its CFL limit).  No
+ * workspace. */
+snrt_status snrt_step_imex(const snrt_mesh* mesh, const snrt_quad* quad,
+                           const snrt_scatter* scatter, const snrt_step_args* args,
+                           const float* psi_in, float* psi_out, void* stream);
+snrt_status snrt_step_imex_f64(const snrt_mesh* mesh, const snrt_quad* quad,
+                               const snrt_scatter* scatter, const snrt_step_args_f64* args,
+                               const double* psi_in, double* psi_out, void* stream);
+
 /* ---------------------------------------------------------------- second-order step */
 
 /* Face-slot midpoints for the second-order scheme (Sec. 4.2, second order finite volume

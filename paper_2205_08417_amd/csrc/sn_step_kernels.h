@@ -279,6 +279,7 @@ struct FwdStage {
     T ghost[MF];
     T nx[MF], ny[MF];
     T irho, keep, cflux, cscat, csrc;
+    T imex_a;                       // 1 + dt alpha_t sigma_t (implicit collision only)
 };
 
 // Buffer resources and scalars of one launch.
@@ -330,17 +331,55 @@ __device__ __forceinline__ void fwd_load_stage(FwdStage<V, MF, DENSE, T>& d, con
         d.ny[f] = g->n[f][1];
     }
     if constexpr (DENSE) buf_load_row<V, EXACT>(x.S, own, q0, nq, d.src);
-    d.keep = T(1) - a.dt * a.alpha_t * cell_val(a.sigma_t, c);
+    const T st_c = cell_val(a.sigma_t, c);
+    d.keep = T(1) - a.dt * a.alpha_t * st_c;
+    d.imex_a = T(1) + a.dt * a.alpha_t * st_c;
     d.cflux = a.dt * g->inv_area;
     d.cscat = a.dt * a.alpha_s * cell_val(a.sigma_s, c);
     d.csrc = x.src_mul * cell_val(x.src_arr, c);
 }
 
-template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T, int SA = kAuxStream>
+template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T, int SA = kAuxStream,
+          bool IMEX = false>
 __device__ __forceinline__ void fwd_compute(const FwdStage<V, MF, DENSE, T>& d, const T (&ox)[V],
                                             const T (&oy)[V], const T (&wi)[V], int32_t c,
-                                            uint32_t cb, int32_t nq, int q0, const FwdCtx<T>& x)
+                                            uint32_t cb, int32_t nq, int q0, const FwdCtx<T>& x,
+                                            T w4 = T(0))
 {
+    if constexpr (IMEX) {
+        // (a - c K~) psi' = b, K~ = w/(4 pi) (isotropic): with B = sum_q (w_q/4pi) b_q and
+        // W = sum_q w_q/(4 pi), the scalar flux of psi' is B / (a - c W) times 4 pi, so
+        // psi'_q = (b_q + c B / (a - c W)) / a  (Sherman-Morrison on the rank-one kernel)
+        T u[V], acc[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            u[k] = RHO ? d.p[k] * d.irho : d.p[k];
+            acc[k] = T(0);
+        }
+#pragma unroll
+        for (int f = 0; f < MF; ++f) {
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const T s = ox[k] * d.nx[f] + oy[k] * d.ny[f];
+                const T ub = d.up[f][k] * d.ghost[f];
+                acc[k] += (s > T(0)) ? s * u[k] : s * ub;
+            }
+        }
+        T b[V];
+        T part = T(0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            b[k] = d.p[k] - d.cflux * acc[k] + d.csrc;
+            part += wi[k] * b[k];
+        }
+        const T B = cell_sum(part);
+        const T phi4 = B / (d.imex_a - d.cscat * w4);
+        T o[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) o[k] = (b[k] + d.cscat * phi4) / d.imex_a;
+        buf_store_row<V, EXACT, T, SA>(x.out, (uint32_t)c * x.row_bytes + cb, q0, nq, o);
+        return;
+    }
     T src[V];
     if constexpr (DENSE) {
 #pragma unroll
@@ -375,7 +414,7 @@ __device__ __forceinline__ void fwd_compute(const FwdStage<V, MF, DENSE, T>& d, 
     buf_store_row<V, EXACT, T, SA>(x.out, (uint32_t)c * x.row_bytes + cb, q0, nq, o);
 }
 
-template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T>
+template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T, bool IMEX = false>
 __global__ __launch_bounds__(kStepBlock) void k_step(
     const typename GeomOf<T>::type* __restrict__ geom, int64_t nc, int32_t nq,
     const T* __restrict__ tab, typename ArgsOf<T>::type a, const T* __restrict__ psi_in,
@@ -429,6 +468,13 @@ __global__ __launch_bounds__(kStepBlock) void k_step(
     load_slice<V, EXACT>(tab, tq, nq, ox);
     load_slice<V, EXACT>(tab + nq, tq, nq, oy);
     load_slice<V, EXACT>(tab + 3 * nq, tq, nq, wi);
+    T w4 = T(0);                                // sum_q w_q / (4 pi), implicit collision only
+    if constexpr (IMEX) {
+        T part = T(0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) part += wi[k];
+        w4 = cell_sum(part);
+    }
 
     NbrList<MF> n0, n1, n2;
     FwdStage<V, MF, DENSE, T> sa, sb;
@@ -440,14 +486,16 @@ __global__ __launch_bounds__(kStepBlock) void k_step(
         fwd_load_stage<V, EXACT, MF, RHO, DENSE>(sb, n1, geom, clampc(c + stride), cb, nq, q0,
                                                  a, cx);
         fwd_load_nbr<MF, T>(n2, geom, clampc(c + 2 * stride));
-        fwd_compute<V, EXACT, MF, RHO, DENSE>(sa, ox, oy, wi, clampc(c), cb, nq, q0, cx);
+        fwd_compute<V, EXACT, MF, RHO, DENSE, T, kAuxStream, IMEX>(sa, ox, oy, wi, clampc(c), cb,
+                                                                  nq, q0, cx, w4);
         c += stride;
         if (c >= xend) break;
         n1 = n2;
         fwd_load_stage<V, EXACT, MF, RHO, DENSE>(sa, n1, geom, clampc(c + stride), cb, nq, q0,
                                                  a, cx);
         fwd_load_nbr<MF, T>(n2, geom, clampc(c + 2 * stride));
-        fwd_compute<V, EXACT, MF, RHO, DENSE>(sb, ox, oy, wi, clampc(c), cb, nq, q0, cx);
+        fwd_compute<V, EXACT, MF, RHO, DENSE, T, kAuxStream, IMEX>(sb, ox, oy, wi, clampc(c), cb,
+                                                                  nq, q0, cx, w4);
         c += stride;
         if (c >= xend) break;
         n1 = n2;
@@ -619,14 +667,14 @@ int resident_blocks(K kernel) {
     return n;
 }
 
-template <typename T, int V, bool E, int MF, bool RHO, bool DENSE>
+template <typename T, int V, bool E, int MF, bool RHO, bool DENSE, bool IMEX = false>
 hipError_t launch_fwd(const typename GeomOf<T>::type* geom, const snrt_mesh& m, const T* tab,
                       int32_t nq, const typename ArgsOf<T>::type& a, const T* psi_in,
                       T* psi_out, const T* S, int shift, hipStream_t st)
 {
-    static const int occ = resident_blocks(k_step<V, E, MF, RHO, DENSE, T>);
+    static const int occ = resident_blocks(k_step<V, E, MF, RHO, DENSE, T, IMEX>);
     const StepShape sh = step_shape(m, m.nc << shift, shift ? kCellsPerBlock : 1, occ);
-    hipLaunchKernelGGL((k_step<V, E, MF, RHO, DENSE, T>), dim3(sh.blocks), dim3(kStepBlock),
+    hipLaunchKernelGGL((k_step<V, E, MF, RHO, DENSE, T, IMEX>), dim3(sh.blocks), dim3(kStepBlock),
                        0, st, geom, m.nc, nq, tab, a, psi_in, psi_out, S, sh.cells_per_xcd,
                        (uint32_t)m.nbf, (int32_t)shift);
     return hipGetLastError();
@@ -638,6 +686,30 @@ inline int dense_chunk_shift(int32_t nq) {
     if (nq == 2 * kWave * 4) return 1;
     if (nq == 4 * kWave * 4) return 2;
     return 0;
+}
+
+// Implicit-collision (IMEX) step, isotropic scattering only.
+template <typename T>
+hipError_t launch_imex_t(const typename GeomOf<T>::type* geom, const snrt_mesh& m,
+                         const T* tab, int32_t nq, const typename ArgsOf<T>::type& a,
+                         const T* psi_in, T* psi_out, hipStream_t st)
+{
+    if (m.nc == 0) return hipSuccess;
+    const bool rho = a.inv_rho != nullptr, mf4 = m.mf == 4;
+    return dispatch_v<T>(nq, [&](auto vc, auto ex) {
+        constexpr int V = decltype(vc)::value;
+        constexpr bool E = decltype(ex)::value;
+        auto go = [&](auto mfc, auto rc) {
+            constexpr int MF = decltype(mfc)::value;
+            constexpr bool R = decltype(rc)::value;
+            return launch_fwd<T, V, E, MF, R, false, true>(geom, m, tab, nq, a, psi_in, psi_out,
+                                                           nullptr, 0, st);
+        };
+        using I3 = std::integral_constant<int, 3>;
+        using I4 = std::integral_constant<int, 4>;
+        if (mf4) return rho ? go(I4{}, std::true_type{}) : go(I4{}, std::false_type{});
+        return rho ? go(I3{}, std::true_type{}) : go(I3{}, std::false_type{});
+    });
 }
 
 template <typename T>

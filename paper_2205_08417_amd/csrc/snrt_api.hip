@@ -900,6 +900,34 @@ snrt_status snrt_step2_f64(const snrt_mesh* m, const snrt_quad* q, const snrt_sc
                                 stream);
 }
 
+snrt_status snrt_step_imex(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
+                           const snrt_step_args* a, const float* psi_in, float* psi_out,
+                           void* stream) {
+    g_last_error.clear();
+    SNRT_REQUIRE(sc, SNRT_E_ARG, "snrt_step_imex: NULL scatter handle");
+    SNRT_REQUIRE(!sc->dense, SNRT_E_UNSUPPORTED,
+                 "snrt_step_imex: only isotropic scattering has the closed-form implicit solve");
+    SNRT_TRY(check_step_common("snrt_step_imex", m, q, sc, a, sizeof(float), psi_in, psi_out,
+                               nullptr, 0));
+    if (m->nc == 0) return SNRT_OK;
+    hipError_t e = launch_imex32(*m, *q, to32(a), psi_in, psi_out, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_step_imex: launch");
+}
+
+snrt_status snrt_step_imex_f64(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
+                               const snrt_step_args_f64* a, const double* psi_in,
+                               double* psi_out, void* stream) {
+    g_last_error.clear();
+    SNRT_REQUIRE(sc, SNRT_E_ARG, "snrt_step_imex_f64: NULL scatter handle");
+    SNRT_REQUIRE(!sc->dense, SNRT_E_UNSUPPORTED,
+                 "snrt_step_imex_f64: only isotropic scattering has the closed-form implicit solve");
+    SNRT_TRY(check_step_common("snrt_step_imex_f64", m, q, sc, a, sizeof(double), psi_in,
+                               psi_out, nullptr, 0));
+    if (m->nc == 0) return SNRT_OK;
+    hipError_t e = launch_imex64(*m, *q, to64(a), psi_in, psi_out, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_step_imex_f64: launch");
+}
+
 snrt_status snrt_scatter_apply(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
                                const float* psi, float* S, int32_t transpose, void* stream) {
     g_last_error.clear();

@@ -162,6 +162,12 @@ hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t*
 hipError_t launch_split_bf16(const float* B, uint16_t* hi, uint16_t* lo, int32_t K, int32_t N,
                              hipStream_t st);
 
+// IMEX step with the isotropic collision operator taken implicitly (sn_step_imex.hip).
+hipError_t launch_imex32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
+                         const float* psi_in, float* psi_out, hipStream_t st);
+hipError_t launch_imex64(const snrt_mesh& m, const snrt_quad& q, const StepArgs64& a,
+                         const double* psi_in, double* psi_out, hipStream_t st);
+
 // Second-order scheme (sn_step2.hip): limited gradient of a stage input and the stage
 // update with reconstructed face values; final = true writes (psi_n + stage) / 2.
 hipError_t launch_grad2_32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,

@@ -46,7 +46,7 @@ EXPORTS = [
     "snrt_step_adjoint_f64", "snrt_scatter_apply", "snrt_mass", "snrt_scalar_flux",
     "snrt_dose_accumulate", "snrt_dose_adjoint", "snrt_dose_density_grad", "snrt_permute",
     "snrt_mesh_set_face_midpoints", "snrt_step2_workspace_size", "snrt_step2", "snrt_step2_f64",
-    "snrt_scatter_moments",
+    "snrt_scatter_moments", "snrt_step_imex", "snrt_step_imex_f64",
 ]
 
 
@@ -113,6 +113,8 @@ def lib() -> ctypes.CDLL:
         "snrt_dose_density_grad": (_st, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "snrt_permute": (_st, [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int64, _vp]),
         "snrt_mesh_set_face_midpoints": (_st, [_vp, _dp]),
+        "snrt_step_imex": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp]),
+        "snrt_step_imex_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp]),
         "snrt_scatter_moments": (_st, [ctypes.POINTER(_vp), _vp, ctypes.c_int32, _dp,
                                        ctypes.c_int]),
         "snrt_step2_workspace_size": (_st, [_vp, _vp, _vp, ctypes.c_int32,
@@ -253,6 +255,18 @@ def snrt_scatter_moments(quad: int, sigma_l, precision=SNRT_FP32) -> int:
 
 def snrt_scatter_destroy(scatter: int) -> None:
     lib().snrt_scatter_destroy(scatter)
+
+
+def snrt_step_imex(mesh, quad, scatter, args: StepArgs, psi_in, psi_out, stream=None) -> None:
+    _check("snrt_step_imex", lib().snrt_step_imex(mesh, quad, scatter, ctypes.byref(args),
+                                                  _ptr(psi_in), _ptr(psi_out), _stream(stream)))
+
+
+def snrt_step_imex_f64(mesh, quad, scatter, args: StepArgs, psi_in, psi_out,
+                       stream=None) -> None:
+    _check("snrt_step_imex_f64", lib().snrt_step_imex_f64(mesh, quad, scatter, ctypes.byref(args),
+                                                          _ptr(psi_in), _ptr(psi_out),
+                                                          _stream(stream)))
 
 
 def snrt_step2_workspace_size(mesh: int, quad: int, scatter: int, fp64: bool = False) -> int:

@@ -122,6 +122,18 @@ class Solver:
             self.ws2[fp64] = (torch.empty(max(n, 16), dtype=torch.uint8, device=self.device), n)
         return self.ws2[fp64]
 
+    def step_imex(self, psi_in, psi_out, args=None, **kw):
+        """One IMEX step: implicit isotropic collision, explicit streaming and source."""
+        snrt.snrt_step_imex(self.mesh, self.quad, self.scatter, args or self.args(**kw), psi_in,
+                            psi_out)
+
+    def step_imex_f64(self, psi_in, psi_out, args=None, **kw):
+        if self.mats64 is None:
+            self.mats64 = self._materials(torch.float64)
+        kw["fp64"] = True
+        snrt.snrt_step_imex_f64(self.mesh, self.quad, self.scatter, args or self.args(**kw),
+                                psi_in, psi_out)
+
     def step2(self, psi_in, psi_out, args=None, **kw):
         """One Heun step of the second-order scheme (limited linear reconstruction)."""
         ws, n = self._ws2(False)
@@ -156,7 +168,7 @@ class Solver:
                 alpha_s: Optional[Sequence[float]] = None,
                 inflow_scale: Optional[Sequence[float]] = None,
                 dose_coeff: Optional[Sequence[float]] = None,
-                dose: Optional[torch.Tensor] = None, order: int = 1):
+                dose: Optional[torch.Tensor] = None, order: int = 1, imex: bool = False):
         """Advance ``nsteps`` explicit steps (ping-pong buffers).  Returns ``(psi, dose)``;
         the dose (FP64, internal order) adds ``dose_coeff[n]`` times the density-weighted
         scalar flux of the state entering step n."""
@@ -166,7 +178,11 @@ class Solver:
             dose = torch.zeros(self.nc, dtype=torch.float64, device=self.device)
         if fp64 and self.mats64 is None:
             self.mats64 = self._materials(torch.float64)
-        if order == 2:
+        if imex:
+            fn = snrt.snrt_step_imex_f64 if fp64 else snrt.snrt_step_imex
+            step = lambda m, q, sc, args, a, b, ws_, n_, st: fn(m, q, sc, args, a, b, st)  # noqa
+            ws, ws_bytes = None, 0
+        elif order == 2:
             step = snrt.snrt_step2_f64 if fp64 else snrt.snrt_step2
             w2, ws_bytes = self._ws2(fp64)
             ws = w2.data_ptr()
