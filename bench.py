@@ -8,8 +8,11 @@ flux over every face and ordinate, isotropic scattering, absorption, source) on 
 resident in HBM.
 
 Prints one JSON line: cell-ordinate updates/s over the timed steps, the roofline of the step
-kernel (algorithmic bytes / measured kernel time vs 8 TB/s), and the FP64 oracle timed on
-the host cores over a bounded sample of the same workload.
+kernel (algorithmic bytes / measured kernel time vs 8 TB/s, and vs a measured device copy),
+and the FP64 oracle timed on the host cores over a bounded sample of the same workload.
+Further sections time the other paths on their own workloads: adjoint/forward, the dense BF16
+hi+lo product (line source), the CSD dose step, moment-projected scattering, the
+second-order Heun step and the IMEX step.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--graph] [--no-cpu-baseline]
 """
@@ -280,6 +283,35 @@ def bench_second_order(steps: int, warmup: int):
             "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+def bench_imex(steps: int, warmup: int):
+    """IMEX step (implicit isotropic collision) on the headline checkerboard: same bytes as
+    the explicit step (8 B per update + 64 B per cell)."""
+    import torch
+    from paper_2205_08417_amd import inputs as I
+    from paper_2205_08417_amd.solver import Solver
+
+    P = I.build(WORKLOAD)
+    S = Solver(P)
+    state = [S.initial_state(), None]
+    state[1] = torch.empty_like(state[0])
+    args = S.args()
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        S.step_imex(state[0], state[1], args)
+        state.reverse()
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    ms = timed(one_step, steps, stream)
+    alg = P.ncells * (8 * P.nq + 64)
+    S.close()
+    return {"workload": WORKLOAD, "scheme": "IMEX: implicit isotropic collision", "steps": steps,
+            "ms_per_step": ms, "value": P.ncells * P.nq / (ms * 1e-3),
+            "unit": "cell-ordinate updates/s", "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 def bench_adjoint(nsteps: int = 400, ckpt: int = 20):
     """Checkerboard adjoint workload (51 842 cells x 256 ordinates, 400 steps, checkpoints
     every 20): forward rollout vs backward pass (segment recompute + adjoint steps) for
@@ -431,6 +463,7 @@ def main():
         out["moments"] = bench_moments(args.dense_steps, 5)
     if not args.no_second_order:
         out["second_order"] = bench_second_order(min(args.steps, 200), 5)
+        out["imex"] = bench_imex(min(args.steps, 200), 5)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P)
     print(json.dumps(out), flush=True)
