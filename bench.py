@@ -445,7 +445,7 @@ def main():
                    "Delaunay 316x316 points on [0,7]^2", "graph": bool(args.graph)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_step<4,true,3,false,false,float>",
+                     "kernel": "k_step<4,true,3,false,false,float,false>",
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
     S.close()
