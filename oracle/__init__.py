@@ -1,4 +1,5 @@
-"""FP64 CPU oracle of the explicit S_N step -- TEST INFRASTRUCTURE.
+"""FP64 CPU oracle of the explicit S_N step (and of the P_N step in ``oracle.pn``) -- TEST
+INFRASTRUCTURE.
 
 Only ``tests/``, the graft entry point's ``smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The product path (``paper_2205_08417_amd``) never

@@ -238,10 +238,13 @@ def periodic_mesh(n: int, length: float = 1.0, diagonal_flip: bool = True) -> Me
                 bface_mid=np.zeros((0, 2)), face_mid=fmid)
 
 
-def quad_grid_mesh(nx: int, ny: int, lo=(0.0, 0.0), hi=(1.0, 1.0)) -> Mesh:
+def quad_grid_mesh(nx: int, ny: int, lo=(0.0, 0.0), hi=(1.0, 1.0), periodic_x: bool = False,
+                   periodic_y: bool = False) -> Mesh:
     """Structured ``nx x ny`` grid of rectangles (quadrilateral cells, four faces each).
 
-    Face f of a cell is its CCW edge ``v_f -> v_{f+1}`` (bottom, right, top, left).
+    Face f of a cell is its CCW edge ``v_f -> v_{f+1}`` (bottom, right, top, left).  With
+    ``periodic_x`` / ``periodic_y`` the grid wraps around in that direction (face midpoints
+    stay in the cell's own frame); the remaining boundary faces are numbered as usual.
     """
     xs = np.linspace(lo[0], hi[0], nx + 1)
     ys = np.linspace(lo[1], hi[1], ny + 1)
@@ -260,8 +263,10 @@ def quad_grid_mesh(nx: int, ny: int, lo=(0.0, 0.0), hi=(1.0, 1.0)) -> Mesh:
             v = [(xs[i], ys[j]), (xs[i + 1], ys[j]), (xs[i + 1], ys[j + 1]), (xs[i], ys[j + 1])]
             cells[c] = [j * (nx + 1) + i, j * (nx + 1) + i + 1, (j + 1) * (nx + 1) + i + 1,
                         (j + 1) * (nx + 1) + i]
-            nb = [cid(i, j - 1) if j > 0 else -1, cid(i + 1, j) if i < nx - 1 else -1,
-                  cid(i, j + 1) if j < ny - 1 else -1, cid(i - 1, j) if i > 0 else -1]
+            nb = [cid(i, j - 1) if j > 0 else (cid(i, ny - 1) if periodic_y else -1),
+                  cid(i + 1, j) if i < nx - 1 else (cid(0, j) if periodic_x else -1),
+                  cid(i, j + 1) if j < ny - 1 else (cid(i, 0) if periodic_y else -1),
+                  cid(i - 1, j) if i > 0 else (cid(nx - 1, j) if periodic_x else -1)]
             for f in range(4):
                 a, b = v[f], v[(f + 1) % 4]
                 normal[c, f] = (b[1] - a[1], -(b[0] - a[0]))
