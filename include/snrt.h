@@ -298,6 +298,63 @@ snrt_status snrt_dose_density_grad(const snrt_mesh* mesh, const double* dose,
                                    const float* inv_rho, const double* g_dose, float* g_rho,
                                    void* stream);
 
+/* ---------------------------------------------------------------- P_N solver (Sec. 4.3) */
+
+/* The P_N moment system of degree N (Sec. 3.1, P_N closure): the state of a cell is the
+ * vector u of the (N+1)^2 moments u_j = int psi m_j dOmega with the real spherical harmonics
+ * m_j, j = l^2 + l + k (the ordering of snrt_scatter_moments), and
+ *     d_t u + A_x d_x (u/rho) + A_y d_y (u/rho) + alpha_t sigma_t u
+ *         = alpha_s sigma_s Sigma u + sqrt(4 pi) q e_0,
+ *     A_x = int m m^T Omega_x dOmega,  A_y = int m m^T Omega_y dOmega,
+ *     Sigma = diag(sigma_l(j)) (the kernel's Legendre moments on every moment of degree l).
+ * One explicit Euler step uses the upwind flux of Sec. 4.3 with the Jacobians split into
+ * their positive and negative semidefinite parts A = A^+ + A^- (eigen-decomposition):
+ *     F(u_i, u_j) = sum_{l=x,y} n_l (A_l^+ u_i/rho_i + A_l^- u_j/rho_j)   if n_l > 0,
+ *                               n_l (A_l^- u_i/rho_i + A_l^+ u_j/rho_j)   otherwise,
+ *     u_i' = u_i - dt/A_i sum_f F + dt (-alpha_t sigma_t u_i + alpha_s sigma_s Sigma u_i
+ *                                        + sqrt(4 pi) q_i e_0).
+ * The kernels evaluate the algebraically identical per-cell form
+ * (A_x X + A_y Y + |A_x| P + |A_y| Q) / 2 with |A| = A^+ - A^- and X, Y, P, Q sums over the
+ * faces of n (u_i/rho_i + u_j/rho_j) and |n| (u_i/rho_i - u_j/rho_j); results agree with the
+ * face-by-face formula up to rounding. */
+typedef struct snrt_pn snrt_pn;
+
+/* Host-only: the library's A_x, A_y, |A_x| = A_x^+ - A_x^-, |A_y| for degree N (each
+ * [(N+1)^2][(N+1)^2] row-major FP64, any pointer may be NULL).  No device is used.
+ * 0 <= degree <= 30. */
+snrt_status snrt_pn_operators(int32_t degree, double* ax, double* ay, double* ax_abs,
+                              double* ay_abs);
+
+/* P_N system of the given degree (0..30) on the current device.  sigma_l: host [degree+1]
+ * Legendre moments of the scattering kernel (2 pi int P_l(mu) k(mu) dmu; sigma_0 = 1
+ * conserves particles), NULL = isotropic (1, 0, 0, ...).  Degrees up to 9 run a fully
+ * unrolled kernel; larger degrees a chunked one. */
+snrt_status snrt_pn_create(snrt_pn** out, int32_t degree, const double* sigma_l);
+void snrt_pn_destroy(snrt_pn* pn);
+snrt_status snrt_pn_info(const snrt_pn* pn, int32_t* degree, int32_t* nmoments);
+
+/* Elements of a P_N state array: the tiled layout below, ceil(ncells/64)*64*nmoments. */
+snrt_status snrt_pn_state_elems(const snrt_mesh* mesh, const snrt_pn* pn, int64_t* elems);
+
+/* P_N state layout.  Cells in the mesh's internal order, grouped in tiles of 64 cells,
+ * moment-major inside a tile: element (internal cell c, moment j) is at
+ * ((c / 64) * nmoments + j) * 64 + c % 64.  Padding cells of the last tile are never read.
+ * snrt_pn_layout converts device arrays between the user's [ncells][nmoments] rows in user
+ * cell order (to_user = 0: user -> tiled; 1: tiled -> user), elem_bytes 4 (FP32) or 8. */
+snrt_status snrt_pn_layout(const snrt_mesh* mesh, const snrt_pn* pn, int32_t to_user,
+                           int32_t elem_bytes, const void* in, void* out, void* stream);
+
+/* One explicit Euler P_N step, u_out = step(u_in), both device arrays in the tiled layout,
+ * 16-byte aligned, not aliased.  args as for snrt_step, with two differences: source is the
+ * isotropic q_i (entering moment 0 as sqrt(4 pi) dt q_i) and inflow holds ghost MOMENTS
+ * [nbfaces][nmoments] in u/rho units (scaled by inflow_scale; NULL = vacuum; Neumann uses
+ * the cell's own u/rho).  No workspace. */
+snrt_status snrt_pn_step(const snrt_mesh* mesh, const snrt_pn* pn, const snrt_step_args* args,
+                         const float* u_in, float* u_out, void* stream);
+snrt_status snrt_pn_step_f64(const snrt_mesh* mesh, const snrt_pn* pn,
+                             const snrt_step_args_f64* args, const double* u_in, double* u_out,
+                             void* stream);
+
 /* Row permutation between user (direction 0 -> internal) and internal (direction 1 -> user)
  * cell order for [ncells][row_bytes] device arrays; row_bytes a positive multiple of 4. */
 snrt_status snrt_permute(const snrt_mesh* mesh, int32_t to_user, const void* in, void* out,

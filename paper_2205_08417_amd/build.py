@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsnrt.so")
 SOURCES = ["snrt_api.hip", "sn_step_f32.hip", "sn_step_f64.hip", "sn_adjoint.hip",
            "sn_reduce.hip", "sn_gemm_simple.hip", "sn_gemm_mfma.hip", "sn_step2.hip",
-           "sn_step_imex.hip"]
+           "sn_step_imex.hip", "sn_pn.hip", "snrt_pn_api.hip"]
 ARCH = os.environ.get("SNRT_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

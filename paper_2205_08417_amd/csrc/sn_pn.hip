@@ -1,0 +1,442 @@
+// P_N step on gfx950 (Sec. 3.1 P_N closure, Sec. 4.3 upwind flux with A^+ / A^-).
+//
+// The upwind flux of a face with outward normal n (times its length) is
+//   F = sum_l n_l (A_l^{s} u_i + A_l^{-s} u_j),   s = sign(n_l),  u = moments / rho,
+// and with A^{+-} = (A +- |A|)/2 this is n_l A_l (u_i + u_j)/2 + |n_l| |A_l| (u_i - u_j)/2.
+// Summed over the faces of cell i the matrices factor out:
+//   sum_f F = (A_x X + A_y Y + |A_x| P + |A_y| Q) / 2,
+//   X = sum_f n_x,f (u_i + u_f),  Y = sum_f n_y,f (u_i + u_f),
+//   P = sum_f |n_x,f| (u_i - u_f),  Q = sum_f |n_y,f| (u_i - u_f),
+// so a cell gathers four vectors from its neighbours and applies four fixed operators once,
+// instead of one dense product per face and direction.  A_x, A_y have at most four entries
+// per row and |A_x|, |A_y| are block diagonal over the reflection classes (pn_pattern.h);
+// the unrolled kernel applies exactly those entries, with the coefficients as wave-uniform
+// scalar loads from a packed table.
+//
+// Layout: one lane per cell.  The state is stored in tiles of 64 cells, moment-major inside
+// a tile: element (cell c, moment m) at ((c / 64) * nm + m) * 64 + c % 64.  A wavefront's own
+// moments are 256-byte coalesced rows, a neighbour's moment is one element of a nearby
+// tile, and consecutive moments of any cell are 64 elements apart, so every load of a lane
+// is a 32-bit buffer offset plus a compile-time (or scalar) moment stride.
+#include <utility>
+
+#include "pn_pattern.h"
+#include "sn_step_kernels.h"
+
+namespace snrt {
+
+namespace {
+
+constexpr int kTile = 64;
+constexpr double kSqrt4Pi = 3.5449077018110320546;   // int m_0 dOmega = sqrt(4 pi)
+
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4) {
+        const int32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+        return __builtin_bit_cast(float, v);
+    } else {
+        const i32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+        return __builtin_bit_cast(double, v);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_st(T x, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int32_t, x), r, voff, soff, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(i32x2, x), r, voff, soff, 0);
+    }
+}
+
+// Byte offset of (cell x, moment 0) in the tiled layout with nm moments.
+template <typename T>
+__device__ __forceinline__ uint32_t tile_off(int x, int nm) {
+    return ((uint32_t)(x >> 6) * (uint32_t)nm * kTile + (uint32_t)(x & 63)) * (uint32_t)sizeof(T);
+}
+
+// Per-lane face data: where the partner's moments are and how to scale them to u = mom/rho.
+template <int MF, typename T>
+struct PnFaces {
+    uint32_t off[MF];   // partner's (tile, lane) byte offset; own cell for boundary faces
+    T sc[MF];           // 1/rho of the partner (Neumann: own 1/rho; Dirichlet: 0)
+    T nx[MF], ny[MF];
+    int32_t ghost[MF];  // boundary face id whose ghost moments come from args.inflow, else -1
+    T sx, sy, ax, ay;   // sum n_x, sum n_y, sum |n_x|, sum |n_y|
+    bool any_ghost;
+};
+
+template <int MF, typename T, typename G, typename A>
+__device__ __forceinline__ void pn_faces(const G& g, const A& a, int c, int nm, T irho_c,
+                                         PnFaces<MF, T>& F) {
+    F.sx = F.sy = F.ax = F.ay = T(0);
+    F.any_ghost = false;
+    const uint32_t own = tile_off<T>(c, nm);
+#pragma unroll
+    for (int f = 0; f < MF; ++f) {
+        const int32_t j = g.nbr[f];
+        F.nx[f] = (T)g.n[f][0];
+        F.ny[f] = (T)g.n[f][1];
+        F.sx += F.nx[f];
+        F.sy += F.ny[f];
+        F.ax += fabs(F.nx[f]);
+        F.ay += fabs(F.ny[f]);
+        F.ghost[f] = -1;
+        if (j >= 0) {
+            F.off[f] = tile_off<T>(j, nm);
+            F.sc[f] = a.inv_rho ? a.inv_rho[j] : T(1);
+        } else {
+            F.off[f] = own;
+            F.sc[f] = a.neumann ? irho_c : T(0);
+            if (!a.neumann && a.inflow) {
+                F.ghost[f] = -1 - j;
+                F.any_ghost = true;
+            }
+        }
+    }
+}
+
+// The four aggregates of input moment m (soff = m * 64 * sizeof(T)).
+template <int MF, typename T, typename A>
+__device__ __forceinline__ void pn_gather(__amdgpu_buffer_rsrc_t rs, const PnFaces<MF, T>& F,
+                                          const A& a, uint32_t own, uint32_t soff, int m, int nm,
+                                          T irho_c, T& X, T& Y, T& P, T& Q) {
+    const T uo = buf_ld<T>(rs, own, soff) * irho_c;
+    X = F.sx * uo;
+    Y = F.sy * uo;
+    P = F.ax * uo;
+    Q = F.ay * uo;
+#pragma unroll
+    for (int f = 0; f < MF; ++f) {
+        T v = buf_ld<T>(rs, F.off[f], soff) * F.sc[f];
+        if (F.any_ghost && F.ghost[f] >= 0)
+            v += (T)a.inflow_scale * a.inflow[(int64_t)F.ghost[f] * nm + m];
+        X = fma(F.nx[f], v, X);
+        Y = fma(F.ny[f], v, Y);
+        P = fma(-fabs(F.nx[f]), v, P);
+        Q = fma(-fabs(F.ny[f]), v, Q);
+    }
+}
+
+template <int KIND, typename T>
+__device__ __forceinline__ T pick(T X, T Y, T P, T Q) {
+    if constexpr (KIND == pn::kOpX) return X;
+    else if constexpr (KIND == pn::kOpY) return Y;
+    else if constexpr (KIND == pn::kOpP) return P;
+    else return Q;
+}
+
+template <int N, int IDX, typename T>
+__device__ __forceinline__ void apply_op(T (&acc)[pn::nmom(N)], T X, T Y, T P, T Q,
+                                         const T* __restrict__ W) {
+    constexpr pn::Op op = pn::OpTable<N>::ops[IDX];
+    constexpr int k = op.k;
+    constexpr int kind = op.kind;
+    acc[k] = fma(pick<kind>(X, Y, P, Q), W[IDX], acc[k]);
+}
+
+template <int N, int S, typename T, int... I>
+__device__ __forceinline__ void apply_ops(T (&acc)[pn::nmom(N)], T X, T Y, T P, T Q,
+                                          const T* __restrict__ W, std::integer_sequence<int, I...>) {
+    (apply_op<N, S + I>(acc, X, Y, P, Q, W), ...);
+}
+
+template <class F, int... I>
+__device__ __forceinline__ void for_each_index(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+
+// Cell update: u' = u (1 - dt a_t s_t + dt a_s s_s sigma_l(k)) - dt/A flux_k (+ source on m_0).
+template <typename T, typename A>
+struct PnUpdate {
+    T dtA, c1, c2, q0;
+    __device__ __forceinline__ PnUpdate(const A& a, T inv_area, int c) {
+        dtA = (T)a.dt * inv_area;
+        c1 = (T)a.dt * (T)a.alpha_t * a.sigma_t[c];
+        c2 = (T)a.dt * (T)a.alpha_s * a.sigma_s[c];
+        q0 = a.source ? (T)a.dt * a.source[c] * (T)kSqrt4Pi : T(0);
+    }
+    __device__ __forceinline__ T operator()(T uk, T flux, T sig, bool first) const {
+        T v = uk * (T(1) - c1 + c2 * sig) - dtA * flux;
+        return first ? v + q0 : v;
+    }
+};
+
+// Waves per SIMD the unrolled kernel is compiled for: the accumulators of all (N+1)^2
+// moments plus the face data and the load pipeline (about 72 registers in FP32, 120 in
+// FP64) must fit the per-wave share of the 512 VGPRs.
+template <int N, typename T>
+constexpr int pn_min_waves() {
+    constexpr int need = pn::nmom(N) * (int)(sizeof(T) / 4) + (sizeof(T) == 4 ? 72 : 120);
+    constexpr int w = 512 / ((need + 7) / 8 * 8);
+    return w < 1 ? 1 : w > 8 ? 8 : w;
+}
+
+// Moments whose gather loads are in flight ahead of the one being applied.
+constexpr int kPnPrefetch = 4;
+// Ghost offset of a face without an inflow ghost: past the end of the inflow buffer, so the
+// buffer load returns 0 (the inflow array is below 2 GiB; checked by the library).
+constexpr uint32_t kNoGhost = 0x80000000u;
+
+// The moment loop of the unrolled kernel, a software pipeline: the loads of moment
+// m + kPnPrefetch are issued before the operators of moment m are applied, and a scheduling
+// barrier closes each moment so the compiler keeps that shape instead of hoisting every
+// load of the unrolled loop (which exhausts the registers).  GHOST: the wavefront holds a
+// cell with an inflow ghost face; each face then also reads its ghost moments (zero for
+// the other faces) from the inflow buffer ri.
+template <bool GHOST, int N, int MF, typename T>
+__device__ __forceinline__ void pn_fused_moments(T (&acc)[pn::nmom(N)], const PnFaces<MF, T>& F,
+                                                 __amdgpu_buffer_rsrc_t rs,
+                                                 __amdgpu_buffer_rsrc_t ri,
+                                                 const uint32_t (&goff)[MF], T gscale,
+                                                 uint32_t own, T irho_c, const T* Ws) {
+    constexpr int NM = pn::nmom(N);
+    constexpr int D = NM < kPnPrefetch ? NM : kPnPrefetch;
+    constexpr int L = GHOST ? 2 * MF + 1 : MF + 1;
+    constexpr uint32_t kPlane = kTile * sizeof(T);
+    auto load = [&](int m, T (&raw)[L]) {
+        raw[0] = buf_ld<T>(rs, own, (uint32_t)m * kPlane);
+#pragma unroll
+        for (int f = 0; f < MF; ++f) raw[f + 1] = buf_ld<T>(rs, F.off[f], (uint32_t)m * kPlane);
+        if constexpr (GHOST) {
+#pragma unroll
+            for (int f = 0; f < MF; ++f)
+                raw[MF + 1 + f] = buf_ld<T>(ri, goff[f], (uint32_t)m * (uint32_t)sizeof(T));
+        }
+    };
+    T ring[D][L];
+#pragma unroll
+    for (int m = 0; m < D; ++m) load(m, ring[m]);
+
+    for_each_index(
+        [&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            T raw[L];
+#pragma unroll
+            for (int i = 0; i < L; ++i) raw[i] = ring[m % D][i];
+            if constexpr (m + D < NM) load(m + D, ring[m % D]);
+            const T uo = raw[0] * irho_c;
+            T X = F.sx * uo, Y = F.sy * uo, P = F.ax * uo, Q = F.ay * uo;
+#pragma unroll
+            for (int f = 0; f < MF; ++f) {
+                T v = raw[f + 1] * F.sc[f];
+                if constexpr (GHOST) v = fma(gscale, raw[MF + 1 + f], v);
+                X = fma(F.nx[f], v, X);
+                Y = fma(F.ny[f], v, Y);
+                P = fma(-fabs(F.nx[f]), v, P);
+                Q = fma(-fabs(F.ny[f]), v, Q);
+            }
+            constexpr int s = pn::OpTable<N>::start[m];
+            constexpr int e = pn::OpTable<N>::start[m + 1];
+            apply_ops<N, s>(acc, X, Y, P, Q, Ws, std::make_integer_sequence<int, e - s>{});
+            __builtin_amdgcn_sched_barrier(0);
+        },
+        std::make_integer_sequence<int, NM>{});
+}
+
+// Fully unrolled step for degree N: acc holds all (N+1)^2 output moments of the lane's
+// cell; the packed coefficient table is staged in LDS (uniform addresses, broadcast reads).
+template <int N, int MF, typename T>
+__global__ __launch_bounds__(256, (pn_min_waves<N, T>())) void k_pn_fused(
+    const typename GeomOf<T>::type* __restrict__ geom, int32_t nc, int32_t ntiles,
+    const T* __restrict__ W, const T* __restrict__ sig, typename ArgsOf<T>::type a,
+    const T* __restrict__ u, T* __restrict__ out, uint32_t state_bytes, uint32_t inflow_bytes) {
+    constexpr int NM = pn::nmom(N);
+    constexpr int NW = pn::OpTable<N>::count;
+    constexpr uint32_t kPlane = kTile * sizeof(T);
+    __shared__ T Ws[NW];
+    for (int i = threadIdx.x; i < NW; i += blockDim.x) Ws[i] = W[i];
+    __syncthreads();
+
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = (int)(blk * 4 + (threadIdx.x >> 6));
+    const int c = tile * kTile + (int)(threadIdx.x & 63);
+    if (tile >= ntiles || c >= nc) return;
+
+    const auto rs = make_rsrc(u, state_bytes);
+    const auto g = geom[c];
+    const T irho_c = a.inv_rho ? a.inv_rho[c] : T(1);
+    const uint32_t own = tile_off<T>(c, NM);
+    PnFaces<MF, T> F;
+    pn_faces<MF>(g, a, c, NM, irho_c, F);
+
+    T acc[NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) acc[k] = T(0);
+    if (__builtin_amdgcn_ballot_w64(F.any_ghost) != 0) {
+        uint32_t goff[MF];
+#pragma unroll
+        for (int f = 0; f < MF; ++f)
+            goff[f] = F.ghost[f] >= 0 ? (uint32_t)F.ghost[f] * NM * (uint32_t)sizeof(T) : kNoGhost;
+        const auto ri = make_rsrc(a.inflow, inflow_bytes);
+        pn_fused_moments<true, N, MF, T>(acc, F, rs, ri, goff, (T)a.inflow_scale, own, irho_c, Ws);
+    } else {
+        const uint32_t goff[MF] = {};
+        pn_fused_moments<false, N, MF, T>(acc, F, rs, rs, goff, T(0), own, irho_c, Ws);
+    }
+
+    const PnUpdate<T, typename ArgsOf<T>::type> upd(a, (T)g.inv_area, c);
+    const auto ro = make_rsrc(out, state_bytes);
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+        const T uk = buf_ld<T>(rs, own, k * kPlane);
+        buf_st<T>(upd(uk, acc[k], sig[k], k == 0), ro, own, k * kPlane);
+    }
+}
+
+// Any degree: output moments in chunks of CH, the coefficients from the dense table
+// W[m][nmp][4] (zero outside the patterns and in the padding).
+template <int CH, int MF, typename T>
+__global__ __launch_bounds__(256) void k_pn_generic(const typename GeomOf<T>::type* __restrict__ geom,
+                                                    int32_t nc, int32_t ntiles, int32_t nm,
+                                                    int32_t nmp, const T* __restrict__ W,
+                                                    const T* __restrict__ sig,
+                                                    typename ArgsOf<T>::type a,
+                                                    const T* __restrict__ u, T* __restrict__ out,
+                                                    uint32_t state_bytes) {
+    const uint32_t kPlane = kTile * sizeof(T);
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = (int)(blk * 4 + (threadIdx.x >> 6));
+    const int c = tile * kTile + (int)(threadIdx.x & 63);
+    if (tile >= ntiles || c >= nc) return;
+
+    const auto rs = make_rsrc(u, state_bytes);
+    const auto ro = make_rsrc(out, state_bytes);
+    const auto g = geom[c];
+    const T irho_c = a.inv_rho ? a.inv_rho[c] : T(1);
+    const uint32_t own = tile_off<T>(c, nm);
+    PnFaces<MF, T> F;
+    pn_faces<MF>(g, a, c, nm, irho_c, F);
+    const PnUpdate<T, typename ArgsOf<T>::type> upd(a, (T)g.inv_area, c);
+
+    for (int k0 = 0; k0 < nm; k0 += CH) {
+        T acc[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) acc[j] = T(0);
+        for (int m = 0; m < nm; ++m) {
+            T X, Y, P, Q;
+            pn_gather<MF>(rs, F, a, own, (uint32_t)m * kPlane, m, nm, irho_c, X, Y, P, Q);
+            const T* w = W + ((size_t)m * nmp + k0) * 4;
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                acc[j] = fma(X, w[4 * j + 0], acc[j]);
+                acc[j] = fma(Y, w[4 * j + 1], acc[j]);
+                acc[j] = fma(P, w[4 * j + 2], acc[j]);
+                acc[j] = fma(Q, w[4 * j + 3], acc[j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int k = k0 + j;
+            if (k < nm) {
+                const T uk = buf_ld<T>(rs, own, (uint32_t)k * kPlane);
+                buf_st<T>(upd(uk, acc[j], sig[k], k == 0), ro, own, (uint32_t)k * kPlane);
+            }
+        }
+    }
+}
+
+// user [ncells][nm] rows <-> tiled internal layout (to_user = 0: into the tiled layout).
+template <typename T>
+__global__ __launch_bounds__(256) void k_pn_layout(const int64_t* __restrict__ to_user, int32_t nc,
+                                                   int32_t nm, int32_t dir, const T* __restrict__ in,
+                                                   T* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nc) return;
+    const int64_t i = to_user[k];
+    const int64_t t = (int64_t)(k >> 6) * nm * kTile + (k & 63);
+    for (int m = 0; m < nm; ++m) {
+        if (dir == 0)
+            out[t + (int64_t)m * kTile] = in[i * nm + m];
+        else
+            out[i * nm + m] = in[t + (int64_t)m * kTile];
+    }
+}
+
+template <typename T>
+uint32_t state_bytes(const snrt_mesh& m, int nm) {
+    return (uint32_t)(((m.nc + kTile - 1) / kTile) * (int64_t)nm * kTile * (int64_t)sizeof(T));
+}
+
+template <int N, int MF, typename T>
+hipError_t launch_fused_t(const snrt_mesh& m, const snrt_pn& p, const typename ArgsOf<T>::type& a,
+                          const T* W, const T* sig, const T* u, T* out, hipStream_t st) {
+    const int32_t ntiles = (int32_t)((m.nc + kTile - 1) / kTile);
+    const int blocks = (ntiles + 3) / 4;
+    using G = typename GeomOf<T>::type;
+    const G* geom;
+    if constexpr (sizeof(T) == 4) geom = m.geom32; else geom = m.geom64;
+    const uint32_t inflow_bytes =
+        a.inflow ? (uint32_t)(m.nbf * (int64_t)p.nm * (int64_t)sizeof(T)) : 0u;
+    hipLaunchKernelGGL((k_pn_fused<N, MF, T>), dim3(blocks), dim3(256), 0, st, geom,
+                       (int32_t)m.nc, ntiles, W, sig, a, u, out, state_bytes<T>(m, p.nm),
+                       inflow_bytes);
+    return hipGetLastError();
+}
+
+template <int MF, typename T, int N = 0>
+hipError_t dispatch_fused(const snrt_mesh& m, const snrt_pn& p,
+                          const typename ArgsOf<T>::type& a, const T* W, const T* sig,
+                          const T* u, T* out, hipStream_t st) {
+    if constexpr (N > pn::max_fused_degree<T>()) {
+        return hipErrorInvalidValue;
+    } else {
+        if (p.degree == N) return launch_fused_t<N, MF, T>(m, p, a, W, sig, u, out, st);
+        return dispatch_fused<MF, T, N + 1>(m, p, a, W, sig, u, out, st);
+    }
+}
+
+template <typename T>
+hipError_t launch_pn_t(const snrt_mesh& m, const snrt_pn& p, const typename ArgsOf<T>::type& a,
+                       const T* W, const T* sig, const T* u, T* out, hipStream_t st) {
+    if (m.nc == 0) return hipSuccess;
+    if (p.degree <= pn::max_fused_degree<T>()) {
+        return m.mf == 3 ? dispatch_fused<3, T>(m, p, a, W, sig, u, out, st)
+                         : dispatch_fused<4, T>(m, p, a, W, sig, u, out, st);
+    }
+    const int32_t ntiles = (int32_t)((m.nc + kTile - 1) / kTile);
+    const int blocks = (ntiles + 3) / 4;
+    constexpr int CH = sizeof(T) == 4 ? kPnChunk32 : kPnChunk64;
+    using G = typename GeomOf<T>::type;
+    const G* geom;
+    if constexpr (sizeof(T) == 4) geom = m.geom32; else geom = m.geom64;
+    if (m.mf == 3)
+        hipLaunchKernelGGL((k_pn_generic<CH, 3, T>), dim3(blocks), dim3(256), 0, st, geom,
+                           (int32_t)m.nc, ntiles, p.nm, p.nmp, W, sig, a, u, out,
+                           state_bytes<T>(m, p.nm));
+    else
+        hipLaunchKernelGGL((k_pn_generic<CH, 4, T>), dim3(blocks), dim3(256), 0, st, geom,
+                           (int32_t)m.nc, ntiles, p.nm, p.nmp, W, sig, a, u, out,
+                           state_bytes<T>(m, p.nm));
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_pn32(const snrt_mesh& m, const snrt_pn& p, const StepArgs32& a, const float* u,
+                       float* out, hipStream_t st) {
+    return launch_pn_t<float>(m, p, a, p.w32, p.sig32, u, out, st);
+}
+
+hipError_t launch_pn64(const snrt_mesh& m, const snrt_pn& p, const StepArgs64& a, const double* u,
+                       double* out, hipStream_t st) {
+    return launch_pn_t<double>(m, p, a, p.w64, p.sig64, u, out, st);
+}
+
+hipError_t launch_pn_layout(const snrt_mesh& m, int32_t nm, int to_user, int elem_bytes,
+                            const void* in, void* out, hipStream_t st) {
+    if (m.nc == 0) return hipSuccess;
+    const int blocks = (int)((m.nc + 255) / 256);
+    if (elem_bytes == 4)
+        hipLaunchKernelGGL(k_pn_layout<float>, dim3(blocks), dim3(256), 0, st, m.d_to_user,
+                           (int32_t)m.nc, nm, to_user, static_cast<const float*>(in),
+                           static_cast<float*>(out));
+    else
+        hipLaunchKernelGGL(k_pn_layout<double>, dim3(blocks), dim3(256), 0, st, m.d_to_user,
+                           (int32_t)m.nc, nm, to_user, static_cast<const double*>(in),
+                           static_cast<double*>(out));
+    return hipGetLastError();
+}
+
+}  // namespace snrt

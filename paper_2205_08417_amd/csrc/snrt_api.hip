@@ -16,45 +16,6 @@ namespace snrt {
 namespace {
 thread_local std::string g_last_error;
 
-bool is_finite(double x) { return std::isfinite(x); }
-
-template <typename T>
-snrt_status dev_alloc(T** p, size_t count, const char* what) {
-    *p = nullptr;
-    if (count == 0) return SNRT_OK;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
-    if (e != hipSuccess) {
-        *p = nullptr;
-        set_error(std::string("device allocation failed for ") + what + ": " +
-                  hipGetErrorString(e));
-        return e == hipErrorOutOfMemory ? SNRT_E_OOM : SNRT_E_HIP;
-    }
-    return SNRT_OK;
-}
-
-template <typename T>
-snrt_status upload(T* dst, const T* src, size_t count, const char* what) {
-    if (count == 0) return SNRT_OK;
-    hipError_t e = hipMemcpy(dst, src, count * sizeof(T), hipMemcpyHostToDevice);
-    return e == hipSuccess ? SNRT_OK : hip_fail(e, what);
-}
-
-void dev_free(void* p) {
-    if (p) (void)hipFree(p);
-}
-
-snrt_status check_device(int dev, const char* what) {
-    int cur = -1;
-    hipError_t e = hipGetDevice(&cur);
-    if (e != hipSuccess) return hip_fail(e, what);
-    if (cur != dev) {
-        set_error(std::string(what) + ": handle belongs to device " + std::to_string(dev) +
-                  " but device " + std::to_string(cur) + " is current");
-        return SNRT_E_ARG;
-    }
-    return SNRT_OK;
-}
-
 // Hilbert index of (x, y) on a 2^16 x 2^16 grid (the standard quadrant-rotation recursion).
 uint64_t hilbert_index(uint32_t x, uint32_t y) {
     const uint32_t n = 1u << 16;
@@ -73,13 +34,6 @@ uint64_t hilbert_index(uint32_t x, uint32_t y) {
     }
     return d;
 }
-
-bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
-    const auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
-    return pa < pb + bbytes && pb < pa + abytes;
-}
-
-bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 }  // namespace
 
@@ -100,6 +54,41 @@ const Tune& tune() {
 snrt_status hip_fail(hipError_t e, const char* what) {
     set_error(std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
     return SNRT_E_HIP;
+}
+
+// Real spherical harmonics m_l^k of the moment equations up to degree N at a direction given
+// in the paper's parametrisation (mu = z, phi = atan2(x, y)); out[l*l + l + k].  Built from
+// the normalised complex harmonics with associated Legendre functions (Condon-Shortley
+// phase) by the three-term recurrence in l: m_l^0 = Y_l^0, m_l^{+-k} = (-1)^k sqrt(2) times
+// the real / imaginary part of Y_l^k.
+void real_harmonics(int N, double x, double y, double z, double* out) {
+    const int W = N + 1;
+    std::vector<double> P((size_t)W * W, 0.0);
+    auto p = [&](int l, int k) -> double& { return P[(size_t)l * W + k]; };
+    const double mu = z;
+    const double s = std::sqrt(std::max(0.0, 1.0 - mu * mu));
+    const double phi = std::atan2(x, y);
+    p(0, 0) = 1.0;
+    for (int k = 1; k <= N; ++k) p(k, k) = -(2.0 * k - 1.0) * s * p(k - 1, k - 1);
+    for (int k = 0; k < N; ++k) p(k + 1, k) = (2.0 * k + 1.0) * mu * p(k, k);
+    for (int k = 0; k <= N; ++k)
+        for (int l = k + 2; l <= N; ++l)
+            p(l, k) = ((2.0 * l - 1.0) * mu * p(l - 1, k) - (l + k - 1.0) * p(l - 2, k)) / (l - k);
+    const double four_pi = 4.0 * 3.14159265358979323846;
+    for (int l = 0; l <= N; ++l) {
+        double ratio = 1.0;                       // (l-k)!/(l+k)!, built up as k grows
+        for (int k = 0; k <= l; ++k) {
+            if (k > 0) ratio /= (double)(l + k) * (double)(l - k + 1);
+            const double norm = std::sqrt((2.0 * l + 1.0) / four_pi * ratio);
+            if (k == 0) {
+                out[l * l + l] = norm * p(l, 0);
+            } else {
+                const double c = ((k & 1) ? -1.0 : 1.0) * std::sqrt(2.0) * norm * p(l, k);
+                out[l * l + l + k] = c * std::cos(k * phi);
+                out[l * l + l - k] = c * std::sin(k * phi);
+            }
+        }
+    }
 }
 
 }  // namespace snrt
@@ -453,41 +442,6 @@ snrt_status make_operand(GemmOperand& op, const std::vector<double>& x, int32_t 
     hipError_t e = launch_split_bf16(op.f32, op.hi, op.lo, K, N, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     return e == hipSuccess ? SNRT_OK : hip_fail(e, fn);
-}
-
-// Real spherical harmonics m_l^k of the moment equations up to degree N at a direction given
-// in the paper's parametrisation (mu = z, phi = atan2(x, y)); out[l*l + l + k].  Built from
-// the normalised complex harmonics with associated Legendre functions (Condon-Shortley
-// phase) by the three-term recurrence in l: m_l^0 = Y_l^0, m_l^{+-k} = (-1)^k sqrt(2) times
-// the real / imaginary part of Y_l^k.
-void real_harmonics(int N, double x, double y, double z, double* out) {
-    const int W = N + 1;
-    std::vector<double> P((size_t)W * W, 0.0);
-    auto p = [&](int l, int k) -> double& { return P[(size_t)l * W + k]; };
-    const double mu = z;
-    const double s = std::sqrt(std::max(0.0, 1.0 - mu * mu));
-    const double phi = std::atan2(x, y);
-    p(0, 0) = 1.0;
-    for (int k = 1; k <= N; ++k) p(k, k) = -(2.0 * k - 1.0) * s * p(k - 1, k - 1);
-    for (int k = 0; k < N; ++k) p(k + 1, k) = (2.0 * k + 1.0) * mu * p(k, k);
-    for (int k = 0; k <= N; ++k)
-        for (int l = k + 2; l <= N; ++l)
-            p(l, k) = ((2.0 * l - 1.0) * mu * p(l - 1, k) - (l + k - 1.0) * p(l - 2, k)) / (l - k);
-    const double four_pi = 4.0 * 3.14159265358979323846;
-    for (int l = 0; l <= N; ++l) {
-        double ratio = 1.0;                       // (l-k)!/(l+k)!, built up as k grows
-        for (int k = 0; k <= l; ++k) {
-            if (k > 0) ratio /= (double)(l + k) * (double)(l - k + 1);
-            const double norm = std::sqrt((2.0 * l + 1.0) / four_pi * ratio);
-            if (k == 0) {
-                out[l * l + l] = norm * p(l, 0);
-            } else {
-                const double c = ((k & 1) ? -1.0 : 1.0) * std::sqrt(2.0) * norm * p(l, k);
-                out[l * l + l + k] = c * std::cos(k * phi);
-                out[l * l + l - k] = c * std::sin(k * phi);
-            }
-        }
-    }
 }
 
 }  // namespace

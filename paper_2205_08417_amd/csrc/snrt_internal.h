@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -109,6 +110,25 @@ struct snrt_quad {
     std::vector<double> omega_host;        // [nq*3] unit directions (x, y, z)
 };
 
+// P_N system of degree N (Sec. 3.1 P_N closure, Sec. 4.3): the flux Jacobians, |A_x|,
+// |A_y| (host copies, FP64) and the step's coefficient tables on the device, one per
+// precision.  Degrees up to pn::max_fused_degree<T>() use the packed table of the unrolled
+// kernel (one value per structurally non-zero coefficient, halved, in pn::visit_ops order);
+// larger degrees the dense table [nm][nmp][4] (X, Y, P, Q coefficient of input moment m for
+// output k, halved, nmp = nm rounded up to a multiple of 16, the chunked kernel's step).
+struct snrt_pn {
+    int device = 0;
+    int32_t degree = 0;
+    int32_t nm = 0;
+    int32_t nmp = 0;
+    std::vector<double> ax, ay, ax_abs, ay_abs;   // [nm][nm]
+    std::vector<double> sig;                      // sigma_l(j) per moment
+    float* w32 = nullptr;
+    double* w64 = nullptr;
+    float* sig32 = nullptr;
+    double* sig64 = nullptr;
+};
+
 struct snrt_scatter {
     int device = 0;
     bool dense = false;
@@ -126,6 +146,56 @@ const Tune& tune();
 
 void set_error(const std::string& msg);
 snrt_status hip_fail(hipError_t e, const char* what);
+
+// ---- host helpers shared by the ABI translation units
+inline bool is_finite(double x) { return std::isfinite(x); }
+
+template <typename T>
+inline snrt_status dev_alloc(T** p, size_t count, const char* what) {
+    *p = nullptr;
+    if (count == 0) return SNRT_OK;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        set_error(std::string("device allocation failed for ") + what + ": " +
+                  hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? SNRT_E_OOM : SNRT_E_HIP;
+    }
+    return SNRT_OK;
+}
+
+template <typename T>
+inline snrt_status upload(T* dst, const T* src, size_t count, const char* what) {
+    if (count == 0) return SNRT_OK;
+    hipError_t e = hipMemcpy(dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, what);
+}
+
+inline void dev_free(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+inline snrt_status check_device(int dev, const char* what) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, what);
+    if (cur != dev) {
+        set_error(std::string(what) + ": handle belongs to device " + std::to_string(dev) +
+                  " but device " + std::to_string(cur) + " is current");
+        return SNRT_E_ARG;
+    }
+    return SNRT_OK;
+}
+
+inline bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
+    const auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return pa < pb + bbytes && pb < pa + abytes;
+}
+
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Real spherical harmonics m_j (j = l^2 + l + k, degree <= N) at the unit direction (x, y, z).
+void real_harmonics(int N, double x, double y, double z, double* out);
 
 // Kernel launchers (return hipGetLastError() after the launch).
 struct StepArgs32 {
@@ -193,6 +263,18 @@ hipError_t launch_dose_adjoint(const snrt_mesh& m, const snrt_quad& q, const flo
                                double coeff, const double* g_dose, float* lam, hipStream_t st);
 hipError_t launch_dose_density_grad(const snrt_mesh& m, const double* dose, const float* inv_rho,
                                     const double* g_dose, float* g_rho, hipStream_t st);
+
+// P_N step (sn_pn.hip): u_out = step(u_in) in the tiled moment layout; layout conversion
+// between the user's [ncells][nm] rows and the tiled internal layout.
+hipError_t launch_pn32(const snrt_mesh& m, const snrt_pn& p, const StepArgs32& a, const float* u,
+                       float* out, hipStream_t st);
+hipError_t launch_pn64(const snrt_mesh& m, const snrt_pn& p, const StepArgs64& a, const double* u,
+                       double* out, hipStream_t st);
+hipError_t launch_pn_layout(const snrt_mesh& m, int32_t nm, int to_user, int elem_bytes,
+                            const void* in, void* out, hipStream_t st);
+// chunk of output moments per pass of the generic (any degree) P_N kernel
+constexpr int kPnChunk32 = 16;
+constexpr int kPnChunk64 = 8;
 
 // XCD-aware mapping of a hardware block index to a logical block index: blocks are
 // dispatched round-robin over the XCDs, so give XCD x a contiguous range of logical blocks.

@@ -352,6 +352,16 @@ def cfl_dt(mesh: Mesh, omega: np.ndarray, cfl: float, rho: Optional[np.ndarray] 
     return float(cfl * np.min(mesh.area * r / out))
 
 
+def pn_cfl_dt(mesh: Mesh, cfl: float, rho: Optional[np.ndarray] = None) -> float:
+    """``dt = cfl * min_i A_i rho_i / sum_f (|n_x| + |n_y|)``: a step bound for the P_N
+    system, whose flux Jacobians have spectral radius below one."""
+    valid = mesh.face_nbr != INT32_MIN
+    s = np.sum(np.where(valid, np.abs(mesh.face_normal[..., 0]) + np.abs(mesh.face_normal[..., 1]),
+                        0.0), axis=1)
+    r = np.ones(mesh.ncells) if rho is None else rho
+    return float(cfl * np.min(mesh.area * r / s))
+
+
 # ----------------------------------------------------------------------------------------
 # CSD energy <-> pseudo-time for the synthetic stopping power S(E) = 2 E^-0.3 (Sec. 2)
 # ----------------------------------------------------------------------------------------
@@ -556,6 +566,23 @@ def build(name: str, **over) -> Problem:
     if kind == "csd":
         return csd_phantom(**spec)
     raise KeyError(kind)
+
+
+def pn_checkerboard(n_side: int = 316, degree: int = 5, seed: int = 1002, cfl: float = 0.5,
+                    nsteps: int = 1000) -> dict:
+    """The checkerboard lattice (mesh and materials of :func:`checkerboard`) for a P_N
+    solver of the given degree (Sec. 7.2 runs P_5): zero initial moments, vacuum boundary,
+    isotropic scattering.  316 x 316 points give the 198 450 triangles of the S_N case."""
+    P = checkerboard(n_side, 2, 2, seed, nsteps, cfl)
+    nm = (degree + 1) ** 2
+    return dict(name=f"checkerboard_p{degree}", mesh=P.mesh, degree=degree,
+                sigma_t=P.sigma_t, sigma_s=P.sigma_s, source=P.source,
+                u0=np.zeros((P.ncells, nm)), dt=pn_cfl_dt(P.mesh, cfl), nsteps=nsteps)
+
+
+def random_moments(nc: int, nm: int, seed: int) -> np.ndarray:
+    """Signed moments (standard normal, FP64), [nc][nm]."""
+    return np.random.default_rng(seed).standard_normal((nc, nm))
 
 
 def random_state(nc: int, nq: int, seed: int, decades: float = 6.0) -> np.ndarray:

@@ -47,6 +47,8 @@ EXPORTS = [
     "snrt_dose_accumulate", "snrt_dose_adjoint", "snrt_dose_density_grad", "snrt_permute",
     "snrt_mesh_set_face_midpoints", "snrt_step2_workspace_size", "snrt_step2", "snrt_step2_f64",
     "snrt_scatter_moments", "snrt_step_imex", "snrt_step_imex_f64",
+    "snrt_pn_operators", "snrt_pn_create", "snrt_pn_destroy", "snrt_pn_info",
+    "snrt_pn_state_elems", "snrt_pn_layout", "snrt_pn_step", "snrt_pn_step_f64",
 ]
 
 
@@ -123,6 +125,14 @@ def lib() -> ctypes.CDLL:
                              ctypes.c_size_t, _vp]),
         "snrt_step2_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp,
                                  ctypes.c_size_t, _vp]),
+        "snrt_pn_operators": (_st, [ctypes.c_int32, _dp, _dp, _dp, _dp]),
+        "snrt_pn_create": (_st, [ctypes.POINTER(_vp), ctypes.c_int32, _dp]),
+        "snrt_pn_destroy": (None, [_vp]),
+        "snrt_pn_info": (_st, [_vp, _ip, _ip]),
+        "snrt_pn_state_elems": (_st, [_vp, _vp, _lp]),
+        "snrt_pn_layout": (_st, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]),
+        "snrt_pn_step": (_st, [_vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp]),
+        "snrt_pn_step_f64": (_st, [_vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -364,3 +374,56 @@ def snrt_dose_density_grad(mesh, dose, inv_rho, g_dose, g_rho, stream=None) -> N
 def snrt_permute(mesh, to_user: int, src, dst, row_bytes: int, stream=None) -> None:
     _check("snrt_permute", lib().snrt_permute(mesh, int(to_user), _ptr(src), _ptr(dst),
                                               int(row_bytes), _stream(stream)))
+
+
+# ------------------------------------------------------------------------------ P_N solver
+
+def snrt_pn_operators(degree: int):
+    """Host-only: (A_x, A_y, |A_x|, |A_y|) of degree ``degree`` as [nm][nm] FP64 arrays."""
+    nm = (int(degree) + 1) ** 2
+    mats = [np.zeros((nm, nm)) for _ in range(4)]
+    _check("snrt_pn_operators",
+           lib().snrt_pn_operators(int(degree), *[m.ctypes.data_as(_dp) for m in mats]))
+    return tuple(mats)
+
+
+def snrt_pn_create(degree: int, sigma_l=None) -> int:
+    arr, p = _f64(sigma_l)
+    if arr is not None and arr.size < int(degree) + 1:
+        raise ValueError("sigma_l needs degree + 1 entries")
+    h = _vp()
+    _check("snrt_pn_create", lib().snrt_pn_create(ctypes.byref(h), int(degree), p))
+    return h.value
+
+
+def snrt_pn_destroy(pn: int) -> None:
+    lib().snrt_pn_destroy(pn)
+
+
+def snrt_pn_info(pn: int):
+    d = ctypes.c_int32()
+    n = ctypes.c_int32()
+    _check("snrt_pn_info", lib().snrt_pn_info(pn, ctypes.byref(d), ctypes.byref(n)))
+    return d.value, n.value
+
+
+def snrt_pn_state_elems(mesh: int, pn: int) -> int:
+    n = ctypes.c_int64()
+    _check("snrt_pn_state_elems", lib().snrt_pn_state_elems(mesh, pn, ctypes.byref(n)))
+    return n.value
+
+
+def snrt_pn_layout(mesh: int, pn: int, to_user: int, elem_bytes: int, src, dst,
+                   stream=None) -> None:
+    _check("snrt_pn_layout", lib().snrt_pn_layout(mesh, pn, int(to_user), int(elem_bytes),
+                                                  _ptr(src), _ptr(dst), _stream(stream)))
+
+
+def snrt_pn_step(mesh, pn, args: StepArgs, u_in, u_out, stream=None) -> None:
+    _check("snrt_pn_step", lib().snrt_pn_step(mesh, pn, ctypes.byref(args), _ptr(u_in),
+                                              _ptr(u_out), _stream(stream)))
+
+
+def snrt_pn_step_f64(mesh, pn, args: StepArgs, u_in, u_out, stream=None) -> None:
+    _check("snrt_pn_step_f64", lib().snrt_pn_step_f64(mesh, pn, ctypes.byref(args), _ptr(u_in),
+                                                      _ptr(u_out), _stream(stream)))

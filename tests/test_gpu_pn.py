@@ -1,0 +1,188 @@
+"""GPU parity of the P_N step (Sec. 3.1 P_N closure, Sec. 4.3 upwind flux) against the
+oracle's face-by-face formula.
+
+The kernels use the per-cell factorisation (A_x X + A_y Y + |A_x| P + |A_y| Q) / 2, so the two
+sides agree up to rounding: FP64 1e-12 and FP32 1e-5 relative L2 after the stated steps.
+Cases span the unrolled kernel (FP32 degrees <= 9, FP64 <= 2) and the chunked one (larger
+degrees), triangle (3 faces), quadrilateral (4) and padded meshes, every boundary mode,
+density, source, scattering moments and per-step scalars; every mesh has a ragged last
+tile of 64 cells.
+"""
+import numpy as np
+import pytest
+
+from _util import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2205_08417_amd import inputs as I  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2205_08417_amd import snrt
+    snrt.lib()
+
+
+def _case(mesh, degree, seed, rho=False, source=False, ghost=False, neumann=False,
+          sigma_l=None, scale=(1.0, 1.0)):
+    rng = np.random.default_rng(seed)
+    nc = mesh.ncells
+    nm = (degree + 1) ** 2
+    d = dict(mesh=mesh, degree=degree,
+             sigma_t=rng.uniform(0.5, 1.5, nc) * scale[0],
+             sigma_s=rng.uniform(0.1, 0.9, nc) * scale[1],
+             rho=rng.uniform(0.5, 2.0, nc) if rho else None,
+             source=rng.uniform(0.0, 1.0, nc) if source else None,
+             ghost=rng.standard_normal((max(mesh.nbfaces, 1), nm)) if ghost else None,
+             neumann=neumann, sigma_l=sigma_l)
+    d["dt"] = I.pn_cfl_dt(mesh, 0.5, d["rho"])
+    d["u0"] = I.random_moments(nc, nm, seed + 1)
+    return d
+
+
+def _oracle(d, nsteps, **kw):
+    from oracle import oracle as o
+    from oracle import pn
+    m = d["mesh"]
+    op = o.OracleProblem(face_nbr=m.face_nbr, face_normal=m.face_normal, area=m.area,
+                         omega=np.zeros((1, 3)), w=np.ones(1), sigma_t=d["sigma_t"],
+                         sigma_s=d["sigma_s"], rho=d["rho"], source=d["source"],
+                         inflow=d["ghost"], neumann=d["neumann"])
+    S = pn.PNSystem(d["degree"], d["sigma_l"])
+    return op, S, pn.pn_rollout(op, S, d["u0"], d["dt"], nsteps, **kw)
+
+
+def _solver(d):
+    from paper_2205_08417_amd.pn import PNSolver
+    return PNSolver(d["mesh"], d["degree"], d["sigma_t"], d["sigma_s"], d["dt"],
+                    sigma_l=d["sigma_l"], rho=d["rho"], source=d["source"], ghost=d["ghost"],
+                    neumann=d["neumann"])
+
+
+def _run(d, nsteps, dtype, **kw):
+    S = _solver(d)
+    u = S.rollout(S.to_tiled(d["u0"], dtype), nsteps, **kw)
+    out = S.to_user(u).cpu().numpy()
+    S.close()
+    return out
+
+
+def test_layout_round_trip():
+    from paper_2205_08417_amd import snrt
+    from paper_2205_08417_amd.pn import PNSolver
+    mesh = I.jittered_delaunay_mesh(15, 0.0, 1.0, seed=70)          # 392 cells: ragged tile
+    S = PNSolver(mesh, 3, np.ones(mesh.ncells), np.zeros(mesh.ncells), 0.01)
+    u = I.random_moments(mesh.ncells, 16, 71)
+    to_user = snrt.snrt_mesh_permutation(S.mesh)
+    for dt in (torch.float32, torch.float64):
+        t = S.to_tiled(u, dt)
+        assert t.numel() == (mesh.ncells + 63) // 64 * 64 * 16
+        ref = u.astype(np.float32) if dt == torch.float32 else u
+        assert np.array_equal(S.to_user(t).cpu().numpy(), ref)
+        # internal cell k, moment j at ((k / 64) * nm + j) * 64 + k % 64
+        th = t.cpu().numpy()
+        k = np.arange(mesh.ncells)
+        for j in (0, 5, 15):
+            assert np.array_equal(th[((k // 64) * 16 + j) * 64 + k % 64], ref[to_user, j])
+    S.close()
+
+
+MESHES = {
+    "tri": lambda: I.jittered_delaunay_mesh(14, 0.0, 1.0, seed=72),
+    "quad": lambda: I.quad_grid_mesh(19, 13),
+    "padded": lambda: I.pad_faces(I.jittered_delaunay_mesh(11, 0.0, 1.0, seed=73), 4),
+}
+
+
+@pytest.mark.parametrize("mesh_name", list(MESHES))
+@pytest.mark.parametrize("degree", [0, 1, 2, 3, 5, 7, 9, 10, 13])
+def test_pn_rollout_vs_oracle(mesh_name, degree):
+    mesh = MESHES[mesh_name]()
+    sl = I.hg_legendre_moments(0.7, degree)
+    d = _case(mesh, degree, seed=74 + degree, rho=True, source=True, ghost=True, sigma_l=sl)
+    kw = dict(alpha_t=1.1, alpha_s=0.9, inflow_scale=0.8)
+    _, _, ref = _oracle(d, 8, **kw)
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        err = rel_l2(_run(d, 8, dt, **kw), ref)
+        print(f"P{degree} {mesh_name} {dt}: {err:.2e}")
+        assert err <= tol
+
+
+@pytest.mark.parametrize("degree", [1, 5])
+def test_pn_neumann_and_vacuum(degree):
+    mesh = I.jittered_delaunay_mesh(13, 0.0, 1.0, seed=80)
+    for neumann in (True, False):
+        d = _case(mesh, degree, seed=81, neumann=neumann)
+        _, _, ref = _oracle(d, 10)
+        for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+            assert rel_l2(_run(d, 10, dt), ref) <= tol
+
+
+def test_pn_fp32_hundred_steps():
+    """The FP32 bar of the plain path: 1e-5 after 100 steps (P_5, source and density)."""
+    mesh = I.jittered_delaunay_mesh(20, 0.0, 1.0, seed=82)
+    d = _case(mesh, 5, seed=83, rho=True, source=True, ghost=True)
+    _, _, ref = _oracle(d, 100)
+    err = rel_l2(_run(d, 100, torch.float32), ref)
+    print(f"P5 FP32 100 steps: {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_pn_conserves_on_periodic_mesh():
+    """Without collisions, every moment's total is conserved (FP64 to rounding)."""
+    mesh = I.periodic_mesh(16)
+    d = _case(mesh, 3, seed=84, scale=(0.0, 0.0))
+    S = _solver(d)
+    u0 = S.to_tiled(d["u0"], torch.float64)
+    u = S.to_user(S.rollout(u0, 20)).cpu().numpy()
+    S.close()
+    tot0 = mesh.area @ d["u0"]
+    tot1 = mesh.area @ u
+    assert np.abs(tot1 - tot0).max() < 1e-12 * np.abs(d["u0"]).max() * mesh.area.sum()
+
+
+def test_full_size_checkerboard_p5_sampled():
+    """198 450 cells, P_5, the launch shape of the benchmark; one step from a random state,
+    300 sampled cells (including boundary cells) checked one by one."""
+    from oracle import oracle as o
+    from oracle import pn
+    w = I.pn_checkerboard()
+    mesh = w["mesh"]
+    u0 = I.random_moments(mesh.ncells, 36, 85)
+    from paper_2205_08417_amd.pn import PNSolver
+    S = PNSolver(mesh, 5, w["sigma_t"], w["sigma_s"], w["dt"], source=w["source"])
+    u = S.to_user(S.rollout(S.to_tiled(u0), 1)).cpu().numpy()
+    S.close()
+    rng = np.random.default_rng(2)
+    bnd = np.nonzero(np.any(mesh.face_nbr < 0, axis=1))[0]
+    cells = np.unique(np.concatenate([bnd[:100], rng.choice(mesh.ncells, 200, False)]))
+    op = o.OracleProblem(face_nbr=mesh.face_nbr, face_normal=mesh.face_normal, area=mesh.area,
+                         omega=np.zeros((1, 3)), w=np.ones(1), sigma_t=w["sigma_t"],
+                         sigma_s=w["sigma_s"], source=w["source"])
+    ref = pn.pn_step(op, pn.PNSystem(5), u0, w["dt"], cells=cells)
+    err = rel_l2(u[cells], ref)
+    print(f"P5 full-size sampled: {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_pn_errors():
+    from paper_2205_08417_amd import snrt
+    from paper_2205_08417_amd.pn import PNSolver
+    mesh = I.jittered_delaunay_mesh(8, 0.0, 1.0, seed=86)
+    S = PNSolver(mesh, 2, np.ones(mesh.ncells), np.zeros(mesh.ncells), 0.01)
+    u = S.to_tiled(I.random_moments(mesh.ncells, 9, 87))
+    with pytest.raises(snrt.SnrtError) as ei:
+        S.step(u, u)
+    assert ei.value.status == snrt.SNRT_E_ALIAS
+    with pytest.raises(snrt.SnrtError) as ei:
+        S.step(u, torch.empty_like(u), dt=float("nan"))
+    assert ei.value.status == snrt.SNRT_E_NONFINITE
+    with pytest.raises(snrt.SnrtError) as ei:
+        snrt.snrt_pn_create(31)
+    assert ei.value.status == snrt.SNRT_E_ARG
+    S.close()
