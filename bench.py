@@ -12,7 +12,7 @@ kernel (algorithmic bytes / measured kernel time vs 8 TB/s, and vs a measured de
 and the FP64 oracle timed on the host cores over a bounded sample of the same workload.
 Further sections time the other paths on their own workloads: adjoint/forward, the dense BF16
 hi+lo product (line source), the CSD dose step, moment-projected scattering, the
-second-order Heun step and the IMEX step.
+second-order Heun step, the IMEX step and the P_N solver step (P_5).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--graph] [--no-cpu-baseline]
 """
@@ -32,6 +32,7 @@ if ROOT not in sys.path:
 METRIC = "cell-ordinate updates/s per S_N step (FP32 vs mixed) + adjoint/forward ratio"
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, vendor figure
 BF16_PEAK_TFLOPS = 2500.0       # MI355X dense BF16 MFMA, vendor figure
+FP32_VECTOR_PEAK_TFLOPS = 157.3 # MI355X FP32 vector, vendor figure
 DENSE_WORKLOAD = "linesource_hg_s32"
 WORKLOAD = "checkerboard_s16"
 STEP_SOURCES = [os.path.join(ROOT, "paper_2205_08417_amd", "csrc", f)
@@ -312,6 +313,54 @@ def bench_imex(steps: int, warmup: int):
             "unit": "cell-ordinate updates/s", "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+def bench_pn(steps: int, warmup: int, degree: int = 5):
+    """P_N solver step (Sec. 4.3 flux with A^+/A^-) on the checkerboard mesh and materials:
+    198 450 cells x (degree+1)^2 moments, FP32, tiled moment layout.  Algorithmic bytes per
+    cell: the state in and out (8 B per moment), the 64-byte geometry record and sigma_t,
+    sigma_s, source (12 B).  Algorithmic FLOPs per cell: one FMA per structurally non-zero
+    entry of A_x, A_y, |A_x|, |A_y| plus the gather (per moment and face: a scale and four
+    FMAs; per moment: five products)."""
+    import numpy as np
+    import torch
+    from paper_2205_08417_amd import inputs as I
+    from paper_2205_08417_amd import snrt
+    from paper_2205_08417_amd.pn import PNSolver
+
+    w = I.pn_checkerboard(degree=degree)
+    mesh = w["mesh"]
+    S = PNSolver(mesh, degree, w["sigma_t"], w["sigma_s"], w["dt"], source=w["source"])
+    nm = S.nm
+    state = [S.to_tiled(w["u0"]), None]
+    state[1] = torch.empty_like(state[0])
+    args = S.args()
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        S.step(state[0], state[1], args)
+        state.reverse()
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    ms = timed(one_step, steps, stream)
+    S.close()
+    nc = mesh.ncells
+    alg = nc * (8 * nm + 64 + 12)
+    nnz = sum(int(np.count_nonzero(np.abs(a) > 1e-14)) for a in snrt.snrt_pn_operators(degree))
+    mf = mesh.face_nbr.shape[1]
+    flops = nc * (2 * nnz + nm * (5 + mf * 9))
+    achieved = alg / (ms * 1e-3) / 1e9
+    return {"workload": w["name"], "cells": nc, "moments": nm, "degree": degree,
+            "steps": steps, "ms_per_step": ms, "value": nc * nm / (ms * 1e-3),
+            "unit": "cell-moment updates/s", "precision": "fp32",
+            "kernel": f"k_pn_fused<{degree},{mf},float>" if degree <= 9 else
+            f"k_pn_generic<16,{mf},float>",
+            "algorithmic_bytes_per_step": alg, "achieved_gbs": achieved,
+            "hbm_frac": achieved / HBM_PEAK_GBS, "flops_per_step": flops,
+            "fp32_vector_tflops": flops / (ms * 1e-3) / 1e12,
+            "fp32_vector_frac": flops / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS}
+
+
 def bench_adjoint(nsteps: int = 400, ckpt: int = 20):
     """Checkerboard adjoint workload (51 842 cells x 256 ordinates, 400 steps, checkpoints
     every 20): forward rollout vs backward pass (segment recompute + adjoint steps) for
@@ -365,6 +414,8 @@ def main():
                     help="skip the adjoint/forward cost measurement")
     ap.add_argument("--no-second-order", action="store_true",
                     help="skip the second-order (Heun, reconstructed flux) measurement")
+    ap.add_argument("--no-pn", action="store_true",
+                    help="skip the P_N solver step measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of one state (for HBM counter scaling)")
     args = ap.parse_args()
@@ -464,6 +515,8 @@ def main():
     if not args.no_second_order:
         out["second_order"] = bench_second_order(min(args.steps, 200), 5)
         out["imex"] = bench_imex(min(args.steps, 200), 5)
+    if not args.no_pn:
+        out["pn"] = bench_pn(min(args.steps, 200), 5)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P)
     print(json.dumps(out), flush=True)

@@ -83,6 +83,28 @@ constexpr void visit_ops(int N, F&& f) {
         }
 }
 
+// Omega_x and Omega_y are both even under the z reflection, so A_x, A_y, |A_x| and |A_y|
+// all keep the z parity: the moment system of a 2-D problem splits into two independent
+// subsystems, the z-even and the z-odd moments (the diagonal scattering keeps them apart
+// too).
+constexpr int zpar(int j) { return mom(j).cls >> 2; }
+
+template <int N, int PZ>
+struct SubMoments {
+    static constexpr int count = [] {
+        int c = 0;
+        for (int j = 0; j < nmom(N); ++j) c += zpar(j) == PZ;
+        return c;
+    }();
+    static constexpr std::array<int, count> list = [] {
+        std::array<int, count> a{};
+        int c = 0;
+        for (int j = 0; j < nmom(N); ++j)
+            if (zpar(j) == PZ) a[c++] = j;
+        return a;
+    }();
+};
+
 template <int N>
 struct OpTable {
     static constexpr int NM = nmom(N);

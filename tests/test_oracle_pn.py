@@ -11,6 +11,8 @@ facts that do not come from the oracle itself:
 * degree 0: no transport, the closed-form collision update;
 * conservation of every moment and a stationary uniform state on a periodic mesh, and the
   non-increasing L2 energy of the upwind scheme;
+* the split of the 2-D system into z-even and z-odd moments that never meet (both
+  streaming directions are even under z -> -z);
 * the slab equivalence: on a grid whose state depends on x only, with zonal angular data
   about the x-axis, P_N with the characteristic upwind flux is exactly the 1-D S_{N+1}
   scheme with Gauss-Legendre ordinates (the eigenvectors of the x-zonal Jacobi matrix are
@@ -222,3 +224,32 @@ def _slab(N, axis, nsteps, neumann, seed):
 @pytest.mark.parametrize("neumann", [False, True])
 def test_slab_equivalence_with_gauss_sn(N, axis, neumann):
     assert _slab(N, axis, nsteps=15, neumann=neumann, seed=11 + N) < 1e-12
+
+
+def _zodd(N):
+    """Moments odd under z -> -z: (-1)^(l+|k|) = -1."""
+    return np.array([((l + abs(k)) % 2) == 1 for l in range(N + 1) for k in range(-l, l + 1)])
+
+
+@pytest.mark.parametrize("N", [2, 5])
+def test_z_parity_subsystems_decouple(N):
+    """Omega_x and Omega_y are even under z -> -z, so in 2-D the z-even and z-odd moments form
+    independent systems: zero z-odd data stays zero, and each half evolves on its own."""
+    mesh = I.jittered_delaunay_mesh(9, 0.0, 1.0, seed=20)
+    S = pn.PNSystem(N, I.hg_legendre_moments(0.5, N))
+    op = _op(mesh, S.nm, seed=21, rho=True, source=True, inflow=True)
+    odd = _zodd(N)
+    rng = np.random.default_rng(22)
+    u = rng.standard_normal((op.nc, S.nm))
+    ue = np.where(odd[None, :], 0.0, u)
+    uo = np.where(odd[None, :], u, 0.0)
+    opo = op.replace(inflow=np.where(odd[None, :], op.inflow, 0.0), source=None)
+    ope = op.replace(inflow=np.where(odd[None, :], 0.0, op.inflow))
+    full = pn.pn_step(op, S, u, 0.01)
+    even_only = pn.pn_step(ope, S, ue, 0.01)
+    odd_only = pn.pn_step(opo, S, uo, 0.01)
+    scale = np.abs(full).max()
+    # the quadrature and eigen-decomposition leave rounding-level entries outside the pattern
+    assert np.abs(even_only[:, odd]).max() < 1e-14 * scale
+    assert np.abs(odd_only[:, ~odd]).max() < 1e-14 * scale
+    assert np.abs(full - even_only - odd_only).max() < 1e-13 * np.abs(full).max()
