@@ -9,11 +9,17 @@
 // relative, is dropped).  The single-product mode keeps only A_hi B_hi.
 //
 // Tiling for v_mfma_f32_32x32x16_bf16 (64-lane wavefronts):
-//   block tile 256 (cells) x 256 (ordinates), 8 waves as 2 x 4, each wave 128 x 64 =
-//   4 x 2 MFMA tiles with FP32 accumulators.  K runs in chunks of 32 through two LDS
-//   stages with one barrier per chunk: after the barrier the block writes chunk k+1 into
-//   the idle stage, issues the global loads of chunk k+2 into registers, and multiplies
-//   chunk k out of the other stage.
+//   block tile BM (cells) x BN (ordinates), 8 waves as 2 x 4, each wave BM/2 x BN/4 =
+//   BM/64 x BN/128 MFMA tiles with FP32 accumulators.  The main launch uses 256 x 256; the
+//   rows of a mostly empty last round of blocks over the compute units go to a second
+//   launch with 64 x 128 or 64 x 256 tiles, so that round takes a fraction of the time (the
+//   per-element accumulation order, and so the result, does not depend on the tile shape).
+//   K runs in chunks of 32 through two LDS stages with one barrier per chunk: after the
+//   barrier the block writes chunk k+1 from registers into the idle stage, issues the global
+//   loads of chunk k+1+FD into the registers it freed, and multiplies chunk k out of the
+//   other stage.  FD = 1 for the full tiles, whose multiply covers the load latency; the
+//   small tiles multiply an eighth or a quarter as much per chunk and keep FD = 4 chunks in
+//   flight instead.
 //   A (Psi, FP32 rows) is split into hi/lo as it is written to LDS; X arrives pre-split
 //   and pre-tiled (plane[kc][n][kk] = part of X[kc*32 + kk][n]), so one chunk of a block's
 //   256 columns is a contiguous 16 KB run per half.  Every LDS plane is [256][32] bf16
@@ -25,6 +31,8 @@
 // MFMA operand layout (32x32x16): lane l supplies row (A) / column (B) l % 32 and the eight
 // K values (l / 32) * 8 + [0, 8); accumulator i of lane l is row (i/4)*8 + (l/32)*4 + i%4,
 // column l % 32.
+#include <algorithm>
+
 #include "snrt_internal.h"
 
 namespace snrt {
@@ -37,9 +45,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 256, BN = 256, BK = 32;
+constexpr int BK = 32;
 constexpr int kThreads = 512;
-constexpr int kPlane = BM * BK;          // bf16 elements of one LDS plane (16 KB)
+constexpr int kPlane = 256 * BK;         // bf16 elements of one LDS plane (16 KB)
 constexpr int kRsrcWord3 = 0x00020000;
 
 __device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
@@ -69,24 +77,30 @@ __device__ __forceinline__ void split4(f32x4 v, uint32_t (&hi)[2], uint32_t (&lo
 // position of 16-byte granule g in LDS row r
 __device__ __forceinline__ int swz(int r, int g) { return g ^ ((r >> 2) & 3); }
 
-template <bool THREE>
-__global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict__ A,
-                                                        const uint16_t* __restrict__ Bhi,
-                                                        const uint16_t* __restrict__ Blo,
-                                                        float* __restrict__ C, int64_t M,
-                                                        int32_t K, int32_t N)
+// One BM x BN block tile of C = A X; lb is the logical block index (row block major, column
+// blocks fastest) and lds the block's two stages of NP planes.
+template <bool THREE, int BM, int BN, int FD>
+__device__ __forceinline__ void gemm_block(const float* __restrict__ A,
+                                           const uint16_t* __restrict__ Bhi,
+                                           const uint16_t* __restrict__ Blo,
+                                           float* __restrict__ C, int64_t M, int32_t K,
+                                           int32_t N, int64_t lb, uint16_t* lds)
 {
+    static_assert(BM == 64 || BM == 128 || BM == 256, "block rows");
+    static_assert(BN == 128 || BN == 256, "block columns");
     constexpr int NP = THREE ? 4 : 2;    // planes per stage: A hi, B hi (, A lo, B lo)
-    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * NP * kPlane];
+    constexpr int IM = BM / 64;          // MFMA tiles per wave along M
+    constexpr int JN = BN / 128;         // MFMA tiles per wave along N
+    constexpr int AV = BM / 64;          // A float4 per thread per chunk
+    constexpr int BV = BN / 128;         // 16-byte B pieces per thread per chunk and half
 
     const int nN = N / BN;
-    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t m0 = (lb / nN) * BM;
     const int n0 = (int)(lb % nN) * BN;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int wm = (wave >> 2) * 128;    // wave tile origin inside the block tile
-    const int wn = (wave & 3) * 64;
+    const int wm = (wave >> 2) * (BM / 2);   // wave tile origin inside the block tile
+    const int wn = (wave & 3) * (BN / 4);
     const int nk = K / BK;
 
     // A rows as a buffer resource: rows past M read as zero
@@ -94,57 +108,59 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict_
     const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<float*>(A + m0 * K), 0, (int32_t)a_bytes, kRsrcWord3);
 
-    // global -> register staging of one chunk: A 256 x 32 floats = 2048 float4 (4 per
-    // thread); B 256 x 32 bf16 per half = 1024 16-byte pieces per half (2 per thread)
-    f32x4 ga[4];
-    u32x4 gbh[2], gbl[2];
-    auto fetch = [&](int kc) {
+    // global -> register staging of one chunk: A BM x 32 floats = BM * 8 float4 (BM / 64
+    // per thread); B BN x 32 bf16 per half = BN * 4 16-byte pieces per half (BN / 128 per
+    // thread).  FD register slots hold the chunks kc+1 .. kc+FD, chunk c in slot c % FD.
+    f32x4 ga[FD][AV];
+    u32x4 gbh[FD][BV], gbl[FD][BV];
+    auto fetch = [&](int kc, int slot) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < AV; ++e) {
             const int p = tid + e * kThreads;
             const int r = p >> 3, g4 = p & 7;
             i32x4 v = __builtin_amdgcn_raw_buffer_load_b128(
                 ra, (uint32_t)((r * K + kc * BK + g4 * 4) * 4), 0, 0);
-            ga[e] = __builtin_bit_cast(f32x4, v);
+            ga[slot][e] = __builtin_bit_cast(f32x4, v);
         }
         const size_t tile = ((size_t)kc * N + n0) * BK;
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
+        for (int e = 0; e < BV; ++e) {
             const int p = tid + e * kThreads;
-            gbh[e] = *reinterpret_cast<const u32x4*>(Bhi + tile + (size_t)p * 8);
-            if constexpr (THREE) gbl[e] = *reinterpret_cast<const u32x4*>(Blo + tile + (size_t)p * 8);
+            gbh[slot][e] = *reinterpret_cast<const u32x4*>(Bhi + tile + (size_t)p * 8);
+            if constexpr (THREE)
+                gbl[slot][e] = *reinterpret_cast<const u32x4*>(Blo + tile + (size_t)p * 8);
         }
     };
-    auto stash = [&](int s) {
+    auto stash = [&](int s, int slot) {
         uint16_t* Ah = lds + (s * NP + 0) * kPlane;
         uint16_t* Bh = lds + (s * NP + 1) * kPlane;
         uint16_t* Al = lds + (s * NP + 2) * kPlane;
         uint16_t* Bl = lds + (s * NP + 3) * kPlane;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < AV; ++e) {
             const int p = tid + e * kThreads;
             const int r = p >> 3, g4 = p & 7;
             const int o = r * BK + swz(r, g4 >> 1) * 8 + (g4 & 1) * 4;
             uint32_t hi[2], lo[2];
-            split4(ga[e], hi, lo);
+            split4(ga[slot][e], hi, lo);
             *reinterpret_cast<uint2*>(&Ah[o]) = make_uint2(hi[0], hi[1]);
             if constexpr (THREE) *reinterpret_cast<uint2*>(&Al[o]) = make_uint2(lo[0], lo[1]);
         }
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
+        for (int e = 0; e < BV; ++e) {
             const int p = tid + e * kThreads;
             const int n = p >> 2, g = p & 3;
             const int o = n * BK + swz(n, g) * 8;
-            *reinterpret_cast<u32x4*>(&Bh[o]) = gbh[e];
-            if constexpr (THREE) *reinterpret_cast<u32x4*>(&Bl[o]) = gbl[e];
+            *reinterpret_cast<u32x4*>(&Bh[o]) = gbh[slot][e];
+            if constexpr (THREE) *reinterpret_cast<u32x4*>(&Bl[o]) = gbl[slot][e];
         }
     };
 
-    f32x16 acc[4][2];
+    f32x16 acc[IM][JN];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < IM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < JN; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
@@ -155,52 +171,60 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict_
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) foff[ks] = fr * BK + swz(fr, ks * 2 + (lane >> 5)) * 8;
 
-    fetch(0);
-    stash(0);
-    if (nk > 1) fetch(1);
-    for (int kc = 0; kc < nk; ++kc) {
-        __syncthreads();                 // chunk kc staged; the idle stage is free again
-        const int s = kc & 1;
-        if (kc + 1 < nk) stash(s ^ 1);
-        if (kc + 2 < nk) fetch(kc + 2);
-        const uint16_t* Ah = lds + (s * NP + 0) * kPlane;
-        const uint16_t* Bh = lds + (s * NP + 1) * kPlane;
-        const uint16_t* Al = lds + (s * NP + 2) * kPlane;
-        const uint16_t* Bl = lds + (s * NP + 3) * kPlane;
+    fetch(0, 0);
+    stash(0, 0);
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            bf16x8 ah[4], al[4], bh[2], bl[2];
+    for (int d = 1; d <= FD; ++d)
+        if (d < nk) fetch(d, d % FD);
+    // the K loop, unrolled by FD so every register slot index is a constant
+    for (int kb = 0; kb < nk; kb += FD) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int o = (wn + j * 32) * BK + foff[ks];
-                bh[j] = *reinterpret_cast<const bf16x8*>(&Bh[o]);
-                if constexpr (THREE) bl[j] = *reinterpret_cast<const bf16x8*>(&Bl[o]);
-            }
+        for (int u = 0; u < FD; ++u) {
+            const int kc = kb + u;
+            if (kc >= nk) break;
+            __syncthreads();             // chunk kc staged; the idle stage is free again
+            const int s = kc & 1;
+            if (kc + 1 < nk) stash(s ^ 1, (u + 1) % FD);
+            if (kc + 1 + FD < nk) fetch(kc + 1 + FD, (u + 1) % FD);
+            const uint16_t* Ah = lds + (s * NP + 0) * kPlane;
+            const uint16_t* Bh = lds + (s * NP + 1) * kPlane;
+            const uint16_t* Al = lds + (s * NP + 2) * kPlane;
+            const uint16_t* Bl = lds + (s * NP + 3) * kPlane;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int o = (wm + i * 32) * BK + foff[ks];
-                ah[i] = *reinterpret_cast<const bf16x8*>(&Ah[o]);
-                if constexpr (THREE) al[i] = *reinterpret_cast<const bf16x8*>(&Al[o]);
-            }
+            for (int ks = 0; ks < 2; ++ks) {
+                bf16x8 ah[IM], al[IM], bh[JN], bl[JN];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-                    if constexpr (THREE) {
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-                    }
+                for (int j = 0; j < JN; ++j) {
+                    const int o = (wn + j * 32) * BK + foff[ks];
+                    bh[j] = *reinterpret_cast<const bf16x8*>(&Bh[o]);
+                    if constexpr (THREE) bl[j] = *reinterpret_cast<const bf16x8*>(&Bl[o]);
                 }
+#pragma unroll
+                for (int i = 0; i < IM; ++i) {
+                    const int o = (wm + i * 32) * BK + foff[ks];
+                    ah[i] = *reinterpret_cast<const bf16x8*>(&Ah[o]);
+                    if constexpr (THREE) al[i] = *reinterpret_cast<const bf16x8*>(&Al[o]);
+                }
+#pragma unroll
+                for (int i = 0; i < IM; ++i)
+#pragma unroll
+                    for (int j = 0; j < JN; ++j) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                        if constexpr (THREE) {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                        }
+                    }
+            }
         }
     }
 
     // epilogue: accumulator r of lane l is row (r/4)*8 + (l/32)*4 + r%4, column l%32; S is
     // consumed once by the step kernel, so it is streamed past the caches
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < IM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < JN; ++j) {
             const int col = n0 + wn + j * 32 + fr;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
@@ -208,6 +232,30 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict_
                 if (row < M) __builtin_nontemporal_store(acc[i][j][r], &C[row * N + col]);
             }
         }
+}
+
+// Blocks [0, nmain) are 256 x 256 tiles of the first M1 rows; blocks [nmain, grid) are
+// TM x TN tiles of the remaining rows (none when nmain == grid).  Blocks are dispatched in
+// order, so the small tiles fill the compute units as the full ones finish.
+template <bool THREE, int TM, int TN, int TFD>
+__global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict__ A,
+                                                        const uint16_t* __restrict__ Bhi,
+                                                        const uint16_t* __restrict__ Blo,
+                                                        float* __restrict__ C, int64_t M1,
+                                                        int64_t M, int32_t K, int32_t N,
+                                                        int64_t nmain)
+{
+    constexpr int NP = THREE ? 4 : 2;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * NP * kPlane];
+    const int64_t b = blockIdx.x;
+    if (b < nmain) {
+        gemm_block<THREE, 256, 256, 1>(A, Bhi, Blo, C, M1, K, N, xcd_remap(b, nmain), lds);
+    } else {
+        // nmain is a multiple of the XCD count, so the remap of the tail stays XCD-aware
+        const int64_t nt = (int64_t)gridDim.x - nmain;
+        gemm_block<THREE, TM, TN, TFD>(A + M1 * K, Bhi, Blo, C + M1 * N, M - M1, K, N,
+                                       xcd_remap(b - nmain, nt), lds);
+    }
 }
 
 // Tiled halves of X [K][N]: hi[(kc*N + n)*32 + kk] = bf16(X[kc*32 + kk][n]), lo = bf16(X - hi)
@@ -230,25 +278,64 @@ __global__ __launch_bounds__(256) void k_split(const float* __restrict__ B, uint
 
 hipError_t launch_split_bf16(const float* B, uint16_t* hi, uint16_t* lo, int32_t K, int32_t N,
                              hipStream_t st) {
-    if (K % BK != 0 || N % BN != 0) return hipErrorNotSupported;
+    if (K % BK != 0 || N % 256 != 0) return hipErrorNotSupported;
     const int64_t n = (int64_t)K * N;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_split, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, B, hi, lo, K, N);
     return hipGetLastError();
 }
 
+// Compute units of the current device (cached per device).
+int device_cu_count() {
+    static int cache[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cache[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n <= 0)
+            n = 256;
+        cache[dev] = n;
+    }
+    return cache[dev];
+}
+
+template <int TM, int TN>
+hipError_t launch_split(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
+                        int64_t M1, int64_t M, int32_t K, int32_t N, bool three,
+                        hipStream_t st) {
+    const int64_t nmain = ((M1 + 255) / 256) * (N / 256);
+    const int64_t ntail = ((M - M1 + TM - 1) / TM) * (N / TN);
+    const dim3 grid((unsigned)(nmain + ntail));
+    if (three)
+        hipLaunchKernelGGL((k_gemm_bf16<true, TM, TN, 4>), grid, dim3(kThreads), 0, st, A, Bhi,
+                           Blo, C, M1, M, K, N, nmain);
+    else
+        hipLaunchKernelGGL((k_gemm_bf16<false, TM, TN, 4>), grid, dim3(kThreads), 0, st, A, Bhi,
+                           Blo, C, M1, M, K, N, nmain);
+    return hipGetLastError();
+}
+
 hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
                             int64_t M, int32_t K, int32_t N, bool three_products, hipStream_t st) {
     if (M == 0) return hipSuccess;
-    if (K % BK != 0 || N % BN != 0 || K == 0) return hipErrorNotSupported;
-    const int64_t blocks = ((M + BM - 1) / BM) * (N / BN);
-    if (three_products)
-        hipLaunchKernelGGL(k_gemm_bf16<true>, dim3((unsigned)blocks), dim3(kThreads), 0, st, A,
-                           Bhi, Blo, C, M, K, N);
-    else
-        hipLaunchKernelGGL(k_gemm_bf16<false>, dim3((unsigned)blocks), dim3(kThreads), 0, st, A,
-                           Bhi, Blo, C, M, K, N);
-    return hipGetLastError();
+    if (K % BK != 0 || N % 256 != 0 || K == 0) return hipErrorNotSupported;
+    // One 256 x 256 block per compute unit and round (128 KB of LDS each).  When the last
+    // round would be mostly empty, its rows run as smaller blocks: 64 x 128 (an eighth of the
+    // work) if they then fill one round, else 64 x 256 (a quarter) if those fill one round;
+    // a small block takes about half the time of a full one (measured), so a fuller last
+    // round stays as it is.
+    const int64_t nN = N / 256;
+    const int64_t tiles = ((M + 255) / 256) * nN;
+    const int64_t cu = device_cu_count();
+    const int64_t rem = tiles % cu;
+    const bool eighth = tiles > cu && rem != 0 && rem * 8 <= cu && cu % kNumXcd == 0;
+    const bool quarter = !eighth && tiles > cu && rem != 0 && rem * 4 <= cu && cu % kNumXcd == 0;
+    if (!eighth && !quarter)
+        return launch_split<64, 256>(A, Bhi, Blo, C, M, M, K, N, three_products, st);
+    const int64_t rows1 = std::min<int64_t>(((tiles - rem) / nN) * 256, M);
+    if (eighth) return launch_split<64, 128>(A, Bhi, Blo, C, rows1, M, K, N, three_products, st);
+    return launch_split<64, 256>(A, Bhi, Blo, C, rows1, M, K, N, three_products, st);
 }
 
 }  // namespace snrt

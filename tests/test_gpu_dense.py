@@ -121,3 +121,32 @@ def test_bf16_requires_256_multiple():
         snrt.snrt_scatter_dense(q, K, snrt.SNRT_BF16X3)
     assert ei.value.status == snrt.SNRT_E_UNSUPPORTED
     snrt.snrt_quad_destroy(q)
+
+
+@pytest.mark.parametrize("three", [True, False])
+def test_bf16_product_with_partial_last_round(three):
+    """71 442 cells x 256 ordinates: 280 row tiles of 256 over the compute units leave a
+    partial last round, whose rows the library runs as 64-row blocks (ragged at the end).
+    Every row of the product S = Psi B is checked against FP64, the tail rows on their own."""
+    from paper_2205_08417_amd import snrt
+    from paper_2205_08417_amd.solver import Solver
+    mesh = I.jittered_delaunay_mesh(190, -1.5, 1.5, seed=61)
+    omega, w = I.product_quadrature(16, 16)
+    K = I.henyey_greenstein_kernel(omega, w, 0.8)
+    rng = np.random.default_rng(62)
+    psi = rng.uniform(0.1, 1.0, (mesh.ncells, 256))
+    P = I.Problem(name="product", mesh=mesh, omega=omega, w=w, K=K,
+                  sigma_t=np.ones(mesh.ncells), sigma_s=np.ones(mesh.ncells), rho=None,
+                  source=None, inflow=None, psi0=psi, dt=1e-3, nsteps=1)
+    S = Solver(P, precision="bf16x3" if three else "bf16x1")
+    x = S.to_internal(psi)
+    out = torch.empty_like(x)
+    snrt.snrt_scatter_apply(S.mesh, S.quad, S.scatter, x, out)
+    got = out.cpu().numpy().astype(np.float64)
+    ref = x.cpu().numpy().astype(np.float64) @ (w[:, None] * K.T)
+    S.close()
+    tol = 2e-5 if three else 1e-2
+    tail = 65536 if mesh.ncells > 65536 else 0
+    err, err_tail = rel_l2(got, ref), rel_l2(got[tail:], ref[tail:])
+    print(f"bf16 three={three}: all {err:.2e}, tail rows {err_tail:.2e}")
+    assert err <= tol and err_tail <= tol
