@@ -8,7 +8,8 @@
 //   Psi_i    = min_f min(1, (u_max - u_i)/d_f) if d_f > 0, min(1, (u_min - u_i)/d_f) if
 //              d_f < 0, 1 otherwise;  d_f = grad u_i . r_if,  u_max/u_min over u_i and every u_f
 //   G_i      = Psi_i grad u_i, stored as two rows per cell: [cell][x|y][nq].
-// k_flux2:
+// k_flux2 (one wavefront per cell; k_flux2p is the same update in the persistent,
+// pipelined form of the first-order step, used whenever the gradient fits 32-bit offsets):
 //   u~_i = u_i + G_i . r_if,  u~_f = u_f + G_j . r_jf (r_jf = 0 on boundary faces: the ghost is
 //   not reconstructed), flux = s > 0 ? s u~_i : s u~_f, and the first-order update formula;
 //   the final stage writes (psi_n + update) / 2.
@@ -200,6 +201,191 @@ __global__ __launch_bounds__(kStepBlock) void k_flux2(
     store_slice<V, EXACT>(out + c * nq, q0, nq, o);
 }
 
+// --------------------------------------------------------------- persistent stage update
+// The same update as k_flux2 in the persistent, XCD-partitioned, software-pipelined form of
+// the first-order step kernel: every wave sweeps a contiguous item range of its XCD, loading
+// the next cell's rows (own psi and G, each face's far-side psi and G) while it computes the
+// current one.  Requires the gradient array below 4 GiB.
+
+template <int V, int MF, bool DENSE, bool FINAL, typename T>
+struct Flux2Stage {
+    T p[V], gx[V], gy[V];
+    T up[MF][V], gxj[MF][V], gyj[MF][V];
+    T src[V], pn[V];
+    T ghost[MF];
+    T nx[MF], ny[MF], rox[MF], roy[MF], rfx[MF], rfy[MF];
+    T irho, keep, cflux, cscat, csrc;
+};
+
+template <typename T>
+struct Flux2Ctx {
+    __amdgpu_buffer_rsrc_t psi, G, inflow, out, S, pn;
+    uint32_t row_bytes;
+    const T* src_arr;
+    T src_mul, inflow_scale;
+    bool dirichlet, neumann;
+};
+
+template <int V, bool EXACT, int MF, bool RHO, bool DENSE, bool FINAL, typename T>
+__device__ __forceinline__ void flux2_load(Flux2Stage<V, MF, DENSE, FINAL, T>& d,
+                                           const NbrList<MF>& nb,
+                                           const typename GeomOf<T>::type* __restrict__ geom,
+                                           const typename ReconOf<T>::type* __restrict__ recon,
+                                           int32_t c, uint32_t cb, int32_t nq, int q0,
+                                           const typename ArgsOf<T>::type& a,
+                                           const Flux2Ctx<T>& x)
+{
+    const auto* g = cell_rec(geom, c);
+    const auto* rc = cell_rec(recon, c);
+    const uint32_t own = (uint32_t)c * x.row_bytes + cb;
+    const uint32_t gown = 2u * (uint32_t)c * x.row_bytes + cb;
+    buf_load_row<V, EXACT, T>(x.psi, own, q0, nq, d.p);
+    buf_load_row<V, EXACT, T>(x.G, gown, q0, nq, d.gx);
+    buf_load_row<V, EXACT, T>(x.G, gown + x.row_bytes, q0, nq, d.gy);
+    d.irho = RHO ? cell_val(a.inv_rho, c) : T(1);
+    const T bscale = x.dirichlet ? x.inflow_scale : (x.neumann ? d.irho : T(0));
+#pragma unroll
+    for (int f = 0; f < MF; ++f) {
+        const int32_t j = nb.j[f];
+        const bool bnd = j < 0;
+        const int32_t bidx = x.dirichlet ? -1 - j : c;
+        const uint32_t off = (uint32_t)(bnd ? bidx : j) * x.row_bytes + cb;
+        const T rho_j = RHO ? cell_val(a.inv_rho, bnd ? c : j) : T(1);
+        d.ghost[f] = bnd ? bscale : rho_j;
+        buf_load_row<V, EXACT, T>(bnd && x.dirichlet ? x.inflow : x.psi, off, q0, nq, d.up[f]);
+        // r_far is zero on boundary faces and unused slots: their own G rows are read and
+        // multiplied by zero
+        const uint32_t goff = 2u * (uint32_t)(bnd ? c : j) * x.row_bytes + cb;
+        buf_load_row<V, EXACT, T>(x.G, goff, q0, nq, d.gxj[f]);
+        buf_load_row<V, EXACT, T>(x.G, goff + x.row_bytes, q0, nq, d.gyj[f]);
+        d.nx[f] = g->n[f][0];
+        d.ny[f] = g->n[f][1];
+        d.rox[f] = rc->r_own[f][0];
+        d.roy[f] = rc->r_own[f][1];
+        d.rfx[f] = rc->r_far[f][0];
+        d.rfy[f] = rc->r_far[f][1];
+    }
+    if constexpr (DENSE) buf_load_row<V, EXACT, T>(x.S, own, q0, nq, d.src);
+    if constexpr (FINAL) buf_load_row<V, EXACT, T>(x.pn, own, q0, nq, d.pn);
+    d.keep = T(1) - a.dt * a.alpha_t * cell_val(a.sigma_t, c);
+    d.cflux = a.dt * g->inv_area;
+    d.cscat = a.dt * a.alpha_s * cell_val(a.sigma_s, c);
+    d.csrc = x.src_mul * cell_val(x.src_arr, c);
+}
+
+template <int V, bool EXACT, int MF, bool RHO, bool DENSE, bool FINAL, typename T>
+__device__ __forceinline__ void flux2_compute(const Flux2Stage<V, MF, DENSE, FINAL, T>& d,
+                                              const T (&ox)[V], const T (&oy)[V],
+                                              const T (&wi)[V], int32_t c, uint32_t cb,
+                                              int32_t nq, int q0, const Flux2Ctx<T>& x)
+{
+    T src[V];
+    if constexpr (DENSE) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) src[k] = d.src[k];
+    } else {
+        T part = T(0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) part += wi[k] * d.p[k];
+        const T phi = cell_sum(part);              // (1/4pi) sum_p w_p psi_p
+#pragma unroll
+        for (int k = 0; k < V; ++k) src[k] = phi;
+    }
+    T u[V], acc[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        u[k] = RHO ? d.p[k] * d.irho : d.p[k];
+        acc[k] = T(0);
+    }
+#pragma unroll
+    for (int f = 0; f < MF; ++f) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const T s = ox[k] * d.nx[f] + oy[k] * d.ny[f];
+            const T ui = u[k] + d.gx[k] * d.rox[f] + d.gy[k] * d.roy[f];
+            const T uj = d.up[f][k] * d.ghost[f] + d.gxj[f][k] * d.rfx[f] + d.gyj[f][k] * d.rfy[f];
+            acc[k] += (s > T(0)) ? s * ui : s * uj;
+        }
+    }
+    T o[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        o[k] = d.p[k] * d.keep - d.cflux * acc[k] + d.cscat * src[k] + d.csrc;
+        if constexpr (FINAL) o[k] = T(0.5) * (d.pn[k] + o[k]);
+    }
+    buf_store_row<V, EXACT, T, kAuxStream>(x.out, (uint32_t)c * x.row_bytes + cb, q0, nq, o);
+}
+
+template <int V, bool EXACT, int MF, bool RHO, bool DENSE, bool FINAL, typename T>
+__global__ __launch_bounds__(kStepBlock) void k_flux2p(
+    const typename GeomOf<T>::type* __restrict__ geom,
+    const typename ReconOf<T>::type* __restrict__ recon, int64_t nc, int32_t nq,
+    const T* __restrict__ tab, typename ArgsOf<T>::type a, const T* __restrict__ psi,
+    const T* __restrict__ G, const T* __restrict__ S, const T* __restrict__ psi_n,
+    T* __restrict__ out, int64_t items_per_xcd, uint32_t nbf, int32_t shift)
+{
+    const int x = blockIdx.x % kNumXcd;
+    const int kx = blockIdx.x / kNumXcd;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t stride = (int32_t)(gridDim.x / kNumXcd) * kCellsPerBlock;
+    const int64_t ni = nc << shift;
+    const int64_t xb = x * items_per_xcd;
+    if (xb >= ni) return;
+    const int32_t xend = (int32_t)(xb + items_per_xcd < ni ? xb + items_per_xcd : ni);
+    int32_t c = (int32_t)xb + kx * kCellsPerBlock + wave;
+    if (c >= xend) return;
+    const int q0 = lane * V;
+    const int32_t sh = shift;
+    const int chunk = c & ((1 << sh) - 1);
+    const uint32_t cb = (uint32_t)chunk * (uint32_t)(kWave * V * sizeof(T));
+
+    Flux2Ctx<T> cx;
+    cx.row_bytes = (uint32_t)nq * sizeof(T);
+    const uint32_t state_bytes = (uint32_t)nc * cx.row_bytes;
+    cx.psi = make_rsrc(psi, state_bytes);
+    cx.G = make_rsrc(G, 2u * state_bytes);
+    cx.out = make_rsrc(out, state_bytes);
+    cx.inflow = make_rsrc(a.inflow ? a.inflow : psi, a.inflow ? nbf * cx.row_bytes : 0u);
+    cx.S = make_rsrc(DENSE ? S : psi, DENSE ? state_bytes : 0u);
+    cx.pn = make_rsrc(FINAL ? psi_n : psi, FINAL ? state_bytes : 0u);
+    cx.src_arr = a.source ? a.source : a.sigma_t;
+    cx.src_mul = a.source ? a.dt : T(0);
+    cx.inflow_scale = a.inflow_scale;
+    cx.dirichlet = a.inflow != nullptr && !a.neumann;
+    cx.neumann = a.neumann != 0;
+    // prefetches address the clamped item min(i', xend-1) in [xbeg, xend): always in bounds
+    auto clampc = [xend, sh](int32_t cc) {
+        return uniform_cell((cc < xend ? cc : xend - 1) >> sh);
+    };
+
+    const int tq = chunk * kWave * V + q0;
+    T ox[V], oy[V], wi[V];
+    load_slice<V, EXACT>(tab, tq, nq, ox);
+    load_slice<V, EXACT>(tab + nq, tq, nq, oy);
+    load_slice<V, EXACT>(tab + 3 * nq, tq, nq, wi);
+
+    NbrList<MF> n0, n1, n2;
+    Flux2Stage<V, MF, DENSE, FINAL, T> sa, sb;
+    fwd_load_nbr<MF, T>(n0, geom, clampc(c));
+    flux2_load<V, EXACT, MF, RHO>(sa, n0, geom, recon, clampc(c), cb, nq, q0, a, cx);
+    fwd_load_nbr<MF, T>(n1, geom, clampc(c + stride));
+    for (;;) {
+        flux2_load<V, EXACT, MF, RHO>(sb, n1, geom, recon, clampc(c + stride), cb, nq, q0, a, cx);
+        fwd_load_nbr<MF, T>(n2, geom, clampc(c + 2 * stride));
+        flux2_compute<V, EXACT, MF, RHO>(sa, ox, oy, wi, clampc(c), cb, nq, q0, cx);
+        c += stride;
+        if (c >= xend) break;
+        n1 = n2;
+        flux2_load<V, EXACT, MF, RHO>(sa, n1, geom, recon, clampc(c + stride), cb, nq, q0, a, cx);
+        fwd_load_nbr<MF, T>(n2, geom, clampc(c + 2 * stride));
+        flux2_compute<V, EXACT, MF, RHO>(sb, ox, oy, wi, clampc(c), cb, nq, q0, cx);
+        c += stride;
+        if (c >= xend) break;
+        n1 = n2;
+    }
+}
+
 // Rows of 512 or 1024 ordinates split into 256-ordinate items when nothing couples the
 // ordinates of a cell inside the kernel (the gradient always, the update with dense
 // scattering); returns the chunk shift and the per-lane width through dispatch.
@@ -247,6 +433,8 @@ hipError_t launch_flux2_t(const snrt_mesh& m, const snrt_quad& q,
     const bool dense = S != nullptr, fin = psi_n != nullptr;
     const int shift = dense ? chunk_shift(q.nq) : 0;
     const bool rho = a.inv_rho != nullptr, mf4 = m.mf == 4;
+    // the persistent kernel addresses the gradient (two rows per cell) with 32-bit offsets
+    const bool persistent = 2 * m.nc * (int64_t)q.nq * (int64_t)sizeof(T) < (int64_t(1) << 32);
     return dispatch_v<T>(shift ? kWave * 4 : q.nq, [&](auto vc, auto ex) {
         constexpr int V = decltype(vc)::value;
         constexpr bool E = decltype(ex)::value;
@@ -255,9 +443,19 @@ hipError_t launch_flux2_t(const snrt_mesh& m, const snrt_quad& q,
             constexpr bool R = decltype(rcst)::value;
             constexpr bool D = decltype(dcst)::value;
             constexpr bool F = decltype(fcst)::value;
-            hipLaunchKernelGGL((k_flux2<V, E, MF, R, D, F, T>), dim3(item_blocks(m.nc, shift)),
-                               dim3(kStepBlock), 0, st, geom, recon, m.nc, q.nq, tab, a, psi, G,
-                               S, psi_n, out, (int32_t)shift);
+            if (persistent) {
+                static const int occ = resident_blocks(k_flux2p<V, E, MF, R, D, F, T>);
+                const StepShape sp = step_shape(m, m.nc << shift, shift ? kCellsPerBlock : 1, occ,
+                                                tune().flux2_blocks_per_cu);
+                hipLaunchKernelGGL((k_flux2p<V, E, MF, R, D, F, T>), dim3(sp.blocks),
+                                   dim3(kStepBlock), 0, st, geom, recon, m.nc, q.nq, tab, a, psi,
+                                   G, S, psi_n, out, sp.cells_per_xcd, (uint32_t)m.nbf,
+                                   (int32_t)shift);
+            } else {
+                hipLaunchKernelGGL((k_flux2<V, E, MF, R, D, F, T>), dim3(item_blocks(m.nc, shift)),
+                                   dim3(kStepBlock), 0, st, geom, recon, m.nc, q.nq, tab, a, psi,
+                                   G, S, psi_n, out, (int32_t)shift);
+            }
             return hipGetLastError();
         };
         using Tt = std::true_type;

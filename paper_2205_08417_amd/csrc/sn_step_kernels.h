@@ -644,8 +644,8 @@ struct StepShape {
 };
 
 inline StepShape step_shape(const snrt_mesh& m, int64_t items, int cpw,
-                            int resident_blocks_per_cu) {
-    int bpc = tune().step_blocks_per_cu;
+                            int resident_blocks_per_cu, int blocks_per_cu = 0) {
+    int bpc = blocks_per_cu > 0 ? blocks_per_cu : tune().step_blocks_per_cu;
     if (resident_blocks_per_cu > 0 && bpc > resident_blocks_per_cu) bpc = resident_blocks_per_cu;
     int64_t want = (items + (int64_t)kCellsPerBlock - 1) / (int64_t)kCellsPerBlock;
     int64_t cap = (int64_t)m.num_cu * bpc;

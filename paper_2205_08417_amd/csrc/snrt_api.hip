@@ -43,8 +43,10 @@ const Tune& tune() {
     static const Tune t = [] {
         Tune r;
         if (const char* e = std::getenv("SNRT_STEP_TUNE")) {
-            int bpc = 0;
-            if (std::sscanf(e, "%d", &bpc) == 1 && bpc >= 1 && bpc <= 64) r.step_blocks_per_cu = bpc;
+            int bpc = 0, bpc2 = 0;
+            const int n = std::sscanf(e, "%d,%d", &bpc, &bpc2);
+            if (n >= 1 && bpc >= 1 && bpc <= 64) r.step_blocks_per_cu = bpc;
+            if (n == 2 && bpc2 >= 1 && bpc2 <= 64) r.flux2_blocks_per_cu = bpc2;
         }
         return r;
     }();

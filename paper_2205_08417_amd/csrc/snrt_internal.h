@@ -138,9 +138,11 @@ struct snrt_scatter {
 namespace snrt {
 
 // Launch-shape knobs of the persistent kernels.  Defaults are the tuned values for MI355X;
-// SNRT_STEP_TUNE="<blocks per CU>" overrides them (read once per process).
+// SNRT_STEP_TUNE="<blocks per CU>[,<blocks per CU of the second-order update>]" overrides
+// them (read once per process).
 struct Tune {
     int step_blocks_per_cu = 3;
+    int flux2_blocks_per_cu = 2;   // its larger per-cell footprint favours a narrower sweep
 };
 const Tune& tune();
 
