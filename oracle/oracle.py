@@ -64,12 +64,14 @@ def lib():
         L.oracle_limited_gradient.restype = ctypes.c_int
         L.oracle_limited_gradient.argtypes = [ctypes.c_int64, ctypes.c_int32, _ip, _dp, _dp, _dp,
                                               _dp, ctypes.c_int32, _dp, _dp, ctypes.c_double,
-                                              ctypes.c_int32, _dp, _dp, _dp]
+                                              ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                              _dp, _dp, _dp]
         L.oracle_step2.restype = ctypes.c_int
         L.oracle_step2.argtypes = [ctypes.c_int64, ctypes.c_int32, _ip, _dp, _dp, _dp, _dp,
                                    ctypes.c_int32, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
                                    ctypes.c_double, ctypes.c_int32, ctypes.c_double,
-                                   ctypes.c_double, ctypes.c_double, _dp, _dp]
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                   ctypes.c_double, _dp, _dp]
         _lib = L
     return _lib
 
@@ -165,9 +167,18 @@ def adjoint_step(op: OracleProblem, psi_n: np.ndarray, lam_np1: np.ndarray, dt: 
     return out
 
 
-def limited_gradient(op: OracleProblem, psi: np.ndarray, inflow_scale: float = 1.0):
-    """Psi_i grad(u_i) per cell and ordinate (Green-Gauss + Barth-Jespersen, Sec. 4.2
-    second order schemes): returns (gx, gy), each [nc][nq]."""
+_LIMITERS = {"barth-jespersen": 0, "venkatakrishnan": 1}
+
+
+def limited_gradient(op: OracleProblem, psi: np.ndarray, inflow_scale: float = 1.0,
+                     limiter: str = "barth-jespersen", vk_k: float = 1.0):
+    """Psi_i grad(u_i) per cell and ordinate (Green-Gauss + the Barth-Jespersen or the
+    Venkatakrishnan limiter, Sec. 4.2 second order schemes): returns (gx, gy), each [nc][nq].
+
+    Venkatakrishnan (the limiter the section names next to Barth-Jespersen, in the form of
+    its cited paper): per face, with d2 = grad u_i . r_if and d1 = u_max - u_i (d2 > 0) or
+    u_min - u_i (d2 < 0), phi = ((d1^2 + eps^2) d2 + 2 d2^2 d1) / (d1^2 + 2 d2^2 + d1 d2 +
+    eps^2) / d2, Psi_i = min over faces; eps^2 = (vk_k sqrt(A_i))^3."""
     psi = _f64(psi).reshape(op.nc, op.nq)
     if op.face_mid is None or op.centroid is None:
         raise ValueError("the second-order scheme needs face midpoints and centroids")
@@ -176,16 +187,18 @@ def limited_gradient(op: OracleProblem, psi: np.ndarray, inflow_scale: float = 1
     rc = lib().oracle_limited_gradient(op.nc, op.mf, op.face_nbr.ctypes.data_as(_ip),
                                        _d(op.face_normal), _d(op.face_mid), _d(op.centroid),
                                        _d(op.area), op.nq, _d(op.rho), _d(op.inflow),
-                                       float(inflow_scale), int(op.neumann), _d(psi), _d(gx),
-                                       _d(gy))
+                                       float(inflow_scale), int(op.neumann), _LIMITERS[limiter],
+                                       float(vk_k), _d(psi), _d(gx), _d(gy))
     if rc != 0:
         raise ValueError("oracle_limited_gradient rejected its arguments")
     return gx, gy
 
 
 def step2(op: OracleProblem, psi: np.ndarray, dt: float, alpha_t: float = 1.0,
-          alpha_s: float = 1.0, inflow_scale: float = 1.0) -> np.ndarray:
-    """One Heun step of the second-order scheme (Sec. 4.2): (psi + L(L(psi))) / 2."""
+          alpha_s: float = 1.0, inflow_scale: float = 1.0, limiter: str = "barth-jespersen",
+          vk_k: float = 1.0) -> np.ndarray:
+    """One Heun step of the second-order scheme (Sec. 4.2): (psi + L(L(psi))) / 2, with the
+    limiter of :func:`limited_gradient`."""
     psi = _f64(psi).reshape(op.nc, op.nq)
     if op.face_mid is None or op.centroid is None:
         raise ValueError("the second-order scheme needs face midpoints and centroids")
@@ -194,7 +207,8 @@ def step2(op: OracleProblem, psi: np.ndarray, dt: float, alpha_t: float = 1.0,
                             _d(op.face_mid), _d(op.centroid), _d(op.area), op.nq, _d(op.omega),
                             _d(op.w), _d(op.K), _d(op.sigma_t), _d(op.sigma_s), _d(op.rho),
                             _d(op.source), _d(op.inflow), float(inflow_scale), int(op.neumann),
-                            float(dt), float(alpha_t), float(alpha_s), _d(psi), _d(out))
+                            float(dt), float(alpha_t), float(alpha_s), _LIMITERS[limiter],
+                            float(vk_k), _d(psi), _d(out))
     if rc != 0:
         raise ValueError(f"oracle_step2 failed ({rc})")
     return out

@@ -297,14 +297,16 @@ static double far_u(int64_t i, int32_t mf, const int32_t* face_nbr, int32_t f, i
 }
 
 /* Limited gradient Psi_i grad(u_i) of every cell and ordinate into gx, gy [nc][nq]. */
+/* limiter: 0 = Barth-Jespersen; 1 = Venkatakrishnan with eps^2 = (vk_k sqrt(A_i))^3 */
 int oracle_limited_gradient(int64_t nc, int32_t mf, const int32_t* face_nbr,
                             const double* face_normal, const double* face_mid,
                             const double* centroid, const double* area, int32_t nq,
                             const double* rho, const double* inflow, double inflow_scale,
-                            int32_t neumann, const double* psi, double* gx, double* gy)
+                            int32_t neumann, int32_t limiter, double vk_k, const double* psi,
+                            double* gx, double* gy)
 {
     if (nc < 0 || mf < 1 || nq < 1 || !face_nbr || !face_normal || !face_mid || !centroid ||
-        !area || !psi || !gx || !gy)
+        !area || !psi || !gx || !gy || (limiter != 0 && limiter != 1))
         return -1;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < nc; ++i) {
@@ -332,7 +334,14 @@ int oracle_limited_gradient(int64_t nc, int32_t mf, const int32_t* face_nbr,
                 if (u_j > gmax) gmax = u_j;
                 if (u_j < gmin) gmin = u_j;
             }
-            /* Barth-Jespersen: the smallest admissible scaling over the faces */
+            /* the smallest scaling over the faces: Barth-Jespersen admits at most 1 and the
+               increment up to the extreme; Venkatakrishnan replaces min(1, d1/d2) by a
+               smooth function of d1/d2 with the threshold eps^2 */
+            double eps2 = 0.0;
+            if (limiter == 1) {
+                double h = vk_k * sqrt(area[i]);
+                eps2 = h * h * h;
+            }
             double lim = 1.0;
             for (int32_t f = 0; f < mf; ++f) {
                 if (face_nbr[(size_t)i * mf + f] == ORACLE_UNUSED_FACE) continue;
@@ -341,11 +350,16 @@ int oracle_limited_gradient(int64_t nc, int32_t mf, const int32_t* face_nbr,
                 double ry = m[1] - centroid[(size_t)i * 2 + 1];
                 double d2 = ax * rx + ay * ry;
                 double t = 1.0;
-                if (d2 > 0.0)
-                    t = (gmax - u_i) / d2;
-                else if (d2 < 0.0)
-                    t = (gmin - u_i) / d2;
-                if (t > 1.0) t = 1.0;
+                if (d2 != 0.0) {
+                    double d1 = d2 > 0.0 ? gmax - u_i : gmin - u_i;
+                    if (limiter == 1) {
+                        t = ((d1 * d1 + eps2) * d2 + 2.0 * d2 * d2 * d1) /
+                            (d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2) / d2;
+                    } else {
+                        t = d1 / d2;
+                        if (t > 1.0) t = 1.0;
+                    }
+                }
                 if (t < lim) lim = t;
             }
             gx[(size_t)i * nq + q] = lim * ax;
@@ -369,11 +383,12 @@ static int stage2(int64_t nc, int32_t mf, const int32_t* face_nbr, const double*
                   const double* omega, const double* w, const double* K, const double* sigma_t,
                   const double* sigma_s, const double* rho, const double* source,
                   const double* inflow, double inflow_scale, int32_t neumann, double dt,
-                  double alpha_t, double alpha_s, const double* psi, double* out, double* gx,
-                  double* gy)
+                  double alpha_t, double alpha_s, int32_t limiter, double vk_k, const double* psi,
+                  double* out, double* gx, double* gy)
 {
     int rc = oracle_limited_gradient(nc, mf, face_nbr, face_normal, face_mid, centroid, area, nq,
-                                     rho, inflow, inflow_scale, neumann, psi, gx, gy);
+                                     rho, inflow, inflow_scale, neumann, limiter, vk_k, psi, gx,
+                                     gy);
     if (rc != 0) return rc;
     int failed = 0;
 #pragma omp parallel
@@ -443,8 +458,10 @@ int oracle_step2(int64_t nc, int32_t mf, const int32_t* face_nbr, const double* 
                  const double* omega, const double* w, const double* K, const double* sigma_t,
                  const double* sigma_s, const double* rho, const double* source,
                  const double* inflow, double inflow_scale, int32_t neumann, double dt,
-                 double alpha_t, double alpha_s, const double* psi_in, double* psi_out)
+                 double alpha_t, double alpha_s, int32_t limiter, double vk_k,
+                 const double* psi_in, double* psi_out)
 {
+    if (limiter != 0 && limiter != 1) return -1;
     if (nc < 0 || mf < 1 || nq < 1 || !face_nbr || !face_normal || !face_mid || !centroid ||
         !area || !omega || !w || !sigma_t || !sigma_s || !psi_in || !psi_out)
         return -1;
@@ -456,11 +473,11 @@ int oracle_step2(int64_t nc, int32_t mf, const int32_t* face_nbr, const double* 
     if (rc == 0)
         rc = stage2(nc, mf, face_nbr, face_normal, face_mid, centroid, area, nq, omega, w, K,
                     sigma_t, sigma_s, rho, source, inflow, inflow_scale, neumann, dt, alpha_t,
-                    alpha_s, psi_in, star, gx, gy);
+                    alpha_s, limiter, vk_k, psi_in, star, gx, gy);
     if (rc == 0)
         rc = stage2(nc, mf, face_nbr, face_normal, face_mid, centroid, area, nq, omega, w, K,
                     sigma_t, sigma_s, rho, source, inflow, inflow_scale, neumann, dt, alpha_t,
-                    alpha_s, star, psi_out, gx, gy);
+                    alpha_s, limiter, vk_k, star, psi_out, gx, gy);
     if (rc == 0)
         for (size_t k = 0; k < n; ++k) psi_out[k] = 0.5 * (psi_in[k] + psi_out[k]);
     free(star);

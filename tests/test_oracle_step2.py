@@ -174,7 +174,7 @@ def test_dense_isotropic_matrix_equals_isotropic_path():
     np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-15)
 
 
-def _advection_error(n, second, T=0.25, flip=False):
+def _advection_error(n, second, T=0.25, flip=False, limiter="barth-jespersen"):
     """Free streaming of a smooth profile on the unit torus; L1 error at the centroids."""
     mesh = I.periodic_mesh(n, diagonal_flip=flip)
     omega, w = I.product_quadrature(2, 4)
@@ -194,8 +194,55 @@ def _advection_error(n, second, T=0.25, flip=False):
     op = o.OracleProblem.from_problem(P)
     psi = P.psi0
     for _ in range(steps):
-        psi = o.step2(op, psi, dt) if second else o.step(op, psi, dt)
+        psi = o.step2(op, psi, dt, limiter=limiter) if second else o.step(op, psi, dt)
     return float(np.sum(mesh.area[:, None] * np.abs(psi - exact(T)))) / nq
+
+
+def _reconstruction_bounds_hold(op, psi, gx, gy, inflow_scale):
+    rho_v = op.rho if op.rho is not None else np.ones(op.nc)
+    u = psi / rho_v[:, None]
+    lo, hi = u.copy(), u.copy()
+    faces = []
+    for f in range(op.mf):
+        j = op.face_nbr[:, f]
+        fv = np.zeros_like(u)
+        fv[j >= 0] = u[j[j >= 0]]
+        fv[j < 0] = op.inflow[-1 - j[j < 0]] * inflow_scale
+        lo, hi = np.minimum(lo, fv), np.maximum(hi, fv)
+        r = op.face_mid[:, f] - op.centroid
+        faces.append(u + gx * r[:, :1] + gy * r[:, 1:])
+    tol = 1e-12 * np.maximum(np.abs(u), 1.0)
+    return all(np.all(rec >= lo - tol) and np.all(rec <= hi + tol) for rec in faces)
+
+
+def test_venkatakrishnan_limits():
+    """Venkatakrishnan (Sec. 4.2 names it beside Barth-Jespersen): with a vanishing threshold
+    eps its smooth limiter function stays below d1/d2, so reconstructions keep within the
+    neighbourhood extremes; with a huge threshold it leaves the Green-Gauss gradient (computed
+    independently here) untouched."""
+    mesh = I.jittered_delaunay_mesh(12, 0.0, 1.0, seed=5)
+    P = small_problem(mesh, seed=4, rho=True, inflow=True)
+    psi = np.random.default_rng(9).uniform(0.0, 1.0, (P.ncells, P.nq))
+    op = o.OracleProblem.from_problem(P)
+    gx, gy = o.limited_gradient(op, psi, 0.8, limiter="venkatakrishnan", vk_k=0.0)
+    assert _reconstruction_bounds_hold(op, psi, gx, gy, 0.8)
+    ux, uy = _unlimited_gradient(op, psi, 0.8)
+    assert np.any(np.abs(gx) < 0.99 * np.abs(ux))
+    gx, gy = o.limited_gradient(op, psi, 0.8, limiter="venkatakrishnan", vk_k=1e6)
+    np.testing.assert_allclose(gx, ux, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(gy, uy, rtol=1e-9, atol=1e-12)
+
+
+def test_venkatakrishnan_convergence():
+    """With eps^2 = (K h)^3, K = 1, the scheme with the Venkatakrishnan limiter is second order
+    on smooth data (its smooth limiter function scales slopes by less than 1 away from
+    extrema too, so its error is of the Barth-Jespersen size, not below it)."""
+    e_vk = [_advection_error(n, True, limiter="venkatakrishnan") for n in (24, 48, 96)]
+    e_bj = _advection_error(96, True)
+    p = np.log2(e_vk[1] / e_vk[2])
+    print(f"Venkatakrishnan errors {e_vk}, order {p:.2f}; Barth-Jespersen at 96: {e_bj}")
+    assert p > 1.8
+    assert e_vk[2] < 1.5 * e_bj
 
 
 def test_convergence_order():
