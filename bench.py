@@ -280,14 +280,18 @@ def bench_second_order(steps: int, warmup: int):
     args = S.args()
     stream = torch.cuda.current_stream()
 
-    def one_step():
-        S.step2(state[0], state[1], args)
-        state.reverse()
+    def run(limiter):
+        def one_step():
+            S.step2(state[0], state[1], args, limiter=limiter)
+            state.reverse()
 
-    for _ in range(warmup):
-        one_step()
-    torch.cuda.synchronize()
-    ms = timed(one_step, steps, stream)
+        for _ in range(warmup):
+            one_step()
+        torch.cuda.synchronize()
+        return timed(one_step, steps, stream)
+
+    ms = run("barth-jespersen")
+    ms_vk = run("venkatakrishnan")
     alg = P.ncells * (60 * P.nq + 2 * 2 * (64 + 64))
     S.close()
     return {"workload": WORKLOAD, "cells": P.ncells, "ordinates": P.nq,
@@ -295,7 +299,8 @@ def bench_second_order(steps: int, warmup: int):
             "steps": steps, "ms_per_step": ms, "value": P.ncells * P.nq / (ms * 1e-3),
             "unit": "cell-ordinate updates/s", "algorithmic_bytes_per_step": alg,
             "achieved_gbs": alg / (ms * 1e-3) / 1e9,
-            "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "venkatakrishnan_ms_per_step": ms_vk}
 
 
 def bench_imex(steps: int, warmup: int):

@@ -254,7 +254,8 @@ snrt_status snrt_step2_workspace_size(const snrt_mesh* mesh, const snrt_quad* qu
  * reconstructions of u = psi/rho on both sides of every face,
  *     u~_i = u_i + Psi_i grad(u_i) . r_if,   r_if = face midpoint - centroid_i,
  * grad(u_i) the Green-Gauss gradient from face averages (u_i + u_j)/2 (boundary faces use
- * the ghost value) and Psi_i the Barth-Jespersen limiter with the extremes of u over the
+ * the ghost value) and Psi_i the Barth-Jespersen limiter (snrt_step2_limited below offers
+ * Venkatakrishnan's as well) with the extremes of u over the
  * cell and its face neighbours and the increment grad(u_i) . r_if.  Ghost values are not
  * reconstructed.  Both stages use args (the same alpha_t, alpha_s, inflow_scale).
  * Requires snrt_mesh_set_face_midpoints (SNRT_E_ARG otherwise) and a workspace of
@@ -268,6 +269,36 @@ snrt_status snrt_step2_f64(const snrt_mesh* mesh, const snrt_quad* quad,
                            const snrt_scatter* scatter, const snrt_step_args_f64* args,
                            const double* psi_in, double* psi_out, void* ws, size_t ws_bytes,
                            void* stream);
+
+/* Slope limiter of the second-order step (Sec. 4.2 names Barth-Jespersen and
+ * Venkatakrishnan).  With d = grad(u_i) . r_if the unlimited increment at face f and
+ * d1 = u_max - u_i (d > 0) or u_min - u_i (d < 0), both limiters scale the gradient by
+ * Psi_i = min over the faces of phi(d1, d), phi = 1 where d = 0:
+ *   SNRT_LIMITER_BARTH_JESPERSEN:  phi = min(1, d1 / d)
+ *   SNRT_LIMITER_VENKATAKRISHNAN:  phi = (d1^2 + eps^2 + 2 d d1) / (d1^2 + 2 d^2 + d d1 + eps^2),
+ *                                  eps^2 = (k sqrt(A_i))^3
+ * The Venkatakrishnan form is smooth in the data.  With k = 0 it keeps every reconstructed
+ * value inside the neighbourhood range (phi <= d1 / d) though phi itself may exceed 1
+ * slightly; a larger k limits less wherever the variation is small against eps. */
+#define SNRT_LIMITER_BARTH_JESPERSEN 0
+#define SNRT_LIMITER_VENKATAKRISHNAN 1
+typedef struct snrt_limiter {
+    int32_t kind;       /* SNRT_LIMITER_* */
+    int32_t reserved;   /* 0 */
+    double k;           /* Venkatakrishnan's K >= 0 (length-scale factor); ignored otherwise */
+} snrt_limiter;
+
+/* snrt_step2 / snrt_step2_f64 with the limiter chosen by lim (NULL = Barth-Jespersen, which
+ * is what snrt_step2 uses).  SNRT_E_ARG for an unknown kind, a non-zero reserved field or a
+ * k that is negative or not finite; everything else as snrt_step2. */
+snrt_status snrt_step2_limited(const snrt_mesh* mesh, const snrt_quad* quad,
+                               const snrt_scatter* scatter, const snrt_step_args* args,
+                               const snrt_limiter* lim, const float* psi_in, float* psi_out,
+                               void* ws, size_t ws_bytes, void* stream);
+snrt_status snrt_step2_limited_f64(const snrt_mesh* mesh, const snrt_quad* quad,
+                                   const snrt_scatter* scatter, const snrt_step_args_f64* args,
+                                   const snrt_limiter* lim, const double* psi_in,
+                                   double* psi_out, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- reductions */
 

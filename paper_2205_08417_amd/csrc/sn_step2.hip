@@ -5,8 +5,11 @@
 //
 // k_grad2 (one wavefront per cell or per 256-ordinate chunk of a cell, lane = V ordinates):
 //   grad u_i = 1/A_i sum_f (u_i + u_f)/2 n_if          (u_f: neighbour value or ghost value)
-//   Psi_i    = min_f min(1, (u_max - u_i)/d_f) if d_f > 0, min(1, (u_min - u_i)/d_f) if
-//              d_f < 0, 1 otherwise;  d_f = grad u_i . r_if,  u_max/u_min over u_i and every u_f
+//   Psi_i    = min_f phi(d1_f, d_f), d_f = grad u_i . r_if, d1_f = u_max - u_i if d_f > 0,
+//              u_min - u_i if d_f < 0 (u_max/u_min over u_i and every u_f), phi = 1 at d_f = 0;
+//              Barth-Jespersen: phi = min(1, d1/d);  Venkatakrishnan:
+//              phi = (d1^2 + eps^2 + 2 d d1) / (d1^2 + 2 d^2 + d d1 + eps^2),
+//              eps^2 = (K sqrt(A_i))^3 (the d-divided form of the smooth limiter)
 //   G_i      = Psi_i grad u_i, stored as two rows per cell: [cell][x|y][nq].
 // k_flux2 (one wavefront per cell; k_flux2p is the same update in the persistent,
 // pipelined form of the first-order step, used whenever the gradient fits 32-bit offsets):
@@ -45,11 +48,12 @@ __device__ __forceinline__ FaceSource<T> face_source(int32_t j, int64_t c, T irh
     return {psi + c * nq, a.neumann ? irho : T(0)};
 }
 
-template <int V, bool EXACT, int MF, bool RHO, typename T>
+template <int V, bool EXACT, int MF, bool RHO, int LIM, typename T>
 __global__ __launch_bounds__(kStepBlock) void k_grad2(
     const typename GeomOf<T>::type* __restrict__ geom,
     const typename ReconOf<T>::type* __restrict__ recon, int64_t nc, int32_t nq,
-    typename ArgsOf<T>::type a, const T* __restrict__ psi, T* __restrict__ G, int32_t shift)
+    typename ArgsOf<T>::type a, const T* __restrict__ psi, T* __restrict__ G, int32_t shift,
+    T vk_k)
 {
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -94,18 +98,27 @@ __global__ __launch_bounds__(kStepBlock) void k_grad2(
         gy[k] *= g.inv_area;
         lim[k] = T(1);
     }
+    T eps2 = T(0);
+    if constexpr (LIM == SNRT_LIMITER_VENKATAKRISHNAN) {
+        const T h = vk_k * sqrt(T(1) / g.inv_area);
+        eps2 = h * h * h;
+    }
 #pragma unroll
     for (int f = 0; f < MF; ++f) {
         const T rx = rc.r_own[f][0], ry = rc.r_own[f][1];
 #pragma unroll
         for (int k = 0; k < V; ++k) {
             const T d2 = gx[k] * rx + gy[k] * ry;
+            const T d1 = d2 > T(0) ? umax[k] - u[k] : umin[k] - u[k];
             T t = T(1);
-            if (d2 > T(0))
-                t = (umax[k] - u[k]) / d2;
-            else if (d2 < T(0))
-                t = (umin[k] - u[k]) / d2;
-            t = t < T(1) ? t : T(1);
+            if constexpr (LIM == SNRT_LIMITER_VENKATAKRISHNAN) {
+                // d1 d2 >= 0, so the denominator is at least 2 d2^2 > 0 whenever d2 != 0
+                const T d11 = d1 * d1 + eps2;
+                if (d2 != T(0)) t = (d11 + T(2) * d2 * d1) / (d11 + T(2) * d2 * d2 + d1 * d2);
+            } else {
+                if (d2 != T(0)) t = d1 / d2;
+                t = t < T(1) ? t : T(1);
+            }
             lim[k] = t < lim[k] ? t : lim[k];
         }
     }
@@ -397,28 +410,34 @@ inline unsigned item_blocks(int64_t nc, int shift) {
 
 template <typename T>
 hipError_t launch_grad2_t(const snrt_mesh& m, const snrt_quad& q,
-                          const typename ArgsOf<T>::type& a, const T* psi, T* G,
-                          const typename GeomOf<T>::type* geom,
+                          const typename ArgsOf<T>::type& a, const Limiter& lim, const T* psi,
+                          T* G, const typename GeomOf<T>::type* geom,
                           const typename ReconOf<T>::type* recon, hipStream_t st)
 {
     if (m.nc == 0) return hipSuccess;
     const int shift = chunk_shift(q.nq);
     const bool rho = a.inv_rho != nullptr, mf4 = m.mf == 4;
+    const bool vk = lim.kind == SNRT_LIMITER_VENKATAKRISHNAN;
     return dispatch_v<T>(shift ? kWave * 4 : q.nq, [&](auto vc, auto ex) {
         constexpr int V = decltype(vc)::value;
         constexpr bool E = decltype(ex)::value;
-        auto go = [&](auto mfc, auto rcst) {
+        auto go = [&](auto mfc, auto rcst, auto lc) {
             constexpr int MF = decltype(mfc)::value;
             constexpr bool R = decltype(rcst)::value;
-            hipLaunchKernelGGL((k_grad2<V, E, MF, R, T>), dim3(item_blocks(m.nc, shift)),
+            constexpr int L = decltype(lc)::value;
+            hipLaunchKernelGGL((k_grad2<V, E, MF, R, L, T>), dim3(item_blocks(m.nc, shift)),
                                dim3(kStepBlock), 0, st, geom, recon, m.nc, q.nq, a, psi, G,
-                               (int32_t)shift);
+                               (int32_t)shift, (T)lim.k);
             return hipGetLastError();
+        };
+        auto by_lim = [&](auto mfc, auto rcst) {
+            return vk ? go(mfc, rcst, std::integral_constant<int, SNRT_LIMITER_VENKATAKRISHNAN>{})
+                      : go(mfc, rcst, std::integral_constant<int, SNRT_LIMITER_BARTH_JESPERSEN>{});
         };
         using I3 = std::integral_constant<int, 3>;
         using I4 = std::integral_constant<int, 4>;
-        if (mf4) return rho ? go(I4{}, std::true_type{}) : go(I4{}, std::false_type{});
-        return rho ? go(I3{}, std::true_type{}) : go(I3{}, std::false_type{});
+        if (mf4) return rho ? by_lim(I4{}, std::true_type{}) : by_lim(I4{}, std::false_type{});
+        return rho ? by_lim(I3{}, std::true_type{}) : by_lim(I3{}, std::false_type{});
     });
 }
 
@@ -477,13 +496,13 @@ hipError_t launch_flux2_t(const snrt_mesh& m, const snrt_quad& q,
 }  // namespace
 
 hipError_t launch_grad2_32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
-                           const float* psi, float* G, hipStream_t st) {
-    return launch_grad2_t<float>(m, q, a, psi, G, m.geom32, m.recon32, st);
+                           const Limiter& lim, const float* psi, float* G, hipStream_t st) {
+    return launch_grad2_t<float>(m, q, a, lim, psi, G, m.geom32, m.recon32, st);
 }
 
 hipError_t launch_grad2_64(const snrt_mesh& m, const snrt_quad& q, const StepArgs64& a,
-                           const double* psi, double* G, hipStream_t st) {
-    return launch_grad2_t<double>(m, q, a, psi, G, m.geom64, m.recon64, st);
+                           const Limiter& lim, const double* psi, double* G, hipStream_t st) {
+    return launch_grad2_t<double>(m, q, a, lim, psi, G, m.geom64, m.recon64, st);
 }
 
 hipError_t launch_flux2_32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,

@@ -796,9 +796,21 @@ namespace {
 // Heun step of the second-order scheme on the workspace [star | G (two planes) | S].
 template <typename T, typename ArgsT>
 snrt_status step2_common(const char* fn, const snrt_mesh* m, const snrt_quad* q,
-                         const snrt_scatter* sc, const ArgsT* a, const T* psi_in, T* psi_out,
-                         void* ws, size_t ws_bytes, void* stream) {
+                         const snrt_scatter* sc, const ArgsT* a, const snrt_limiter* lim_in,
+                         const T* psi_in, T* psi_out, void* ws, size_t ws_bytes, void* stream) {
     SNRT_TRY(check_step_common(fn, m, q, sc, a, sizeof(T), psi_in, psi_out, ws, ws_bytes));
+    Limiter lim;
+    if (lim_in) {
+        SNRT_REQUIRE(lim_in->kind == SNRT_LIMITER_BARTH_JESPERSEN ||
+                         lim_in->kind == SNRT_LIMITER_VENKATAKRISHNAN,
+                     SNRT_E_ARG, std::string(fn) + ": unknown limiter kind");
+        SNRT_REQUIRE(lim_in->reserved == 0, SNRT_E_ARG,
+                     std::string(fn) + ": limiter.reserved must be 0");
+        SNRT_REQUIRE(is_finite(lim_in->k) && lim_in->k >= 0.0, SNRT_E_ARG,
+                     std::string(fn) + ": limiter k must be finite and >= 0");
+        lim.kind = lim_in->kind;
+        lim.k = lim_in->k;
+    }
     if (m->nc == 0) return SNRT_OK;
     SNRT_REQUIRE(m->recon32 && m->recon64, SNRT_E_ARG,
                  std::string(fn) + ": call snrt_mesh_set_face_midpoints first");
@@ -820,14 +832,14 @@ snrt_status step2_common(const char* fn, const snrt_mesh* m, const snrt_quad* q,
     for (int stage = 0; stage < 2 && e == hipSuccess; ++stage) {
         if constexpr (sizeof(T) == 4) {
             const StepArgs32 a32 = to32(a);
-            e = launch_grad2_32(*m, *q, a32, in[stage], G, st);
+            e = launch_grad2_32(*m, *q, a32, lim, in[stage], G, st);
             if (e == hipSuccess && S) e = scatter_product32(sc, in[stage], S, m->nc, false, U, st);
             if (e == hipSuccess)
                 e = launch_flux2_32(*m, *q, a32, in[stage], G, S, stage ? psi_in : nullptr,
                                     outp[stage], st);
         } else {
             const StepArgs64 a64 = to64(a);
-            e = launch_grad2_64(*m, *q, a64, in[stage], G, st);
+            e = launch_grad2_64(*m, *q, a64, lim, in[stage], G, st);
             if (e == hipSuccess && S) e = scatter_product64(sc, in[stage], S, m->nc, false, U, st);
             if (e == hipSuccess)
                 e = launch_flux2_64(*m, *q, a64, in[stage], G, S, stage ? psi_in : nullptr,
@@ -845,15 +857,34 @@ snrt_status snrt_step2(const snrt_mesh* m, const snrt_quad* q, const snrt_scatte
                        const snrt_step_args* a, const float* psi_in, float* psi_out, void* ws,
                        size_t ws_bytes, void* stream) {
     g_last_error.clear();
-    return step2_common<float>("snrt_step2", m, q, sc, a, psi_in, psi_out, ws, ws_bytes, stream);
+    return step2_common<float>("snrt_step2", m, q, sc, a, nullptr, psi_in, psi_out, ws,
+                               ws_bytes, stream);
 }
 
 snrt_status snrt_step2_f64(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
                            const snrt_step_args_f64* a, const double* psi_in, double* psi_out,
                            void* ws, size_t ws_bytes, void* stream) {
     g_last_error.clear();
-    return step2_common<double>("snrt_step2_f64", m, q, sc, a, psi_in, psi_out, ws, ws_bytes,
-                                stream);
+    return step2_common<double>("snrt_step2_f64", m, q, sc, a, nullptr, psi_in, psi_out, ws,
+                                ws_bytes, stream);
+}
+
+snrt_status snrt_step2_limited(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
+                               const snrt_step_args* a, const snrt_limiter* lim,
+                               const float* psi_in, float* psi_out, void* ws, size_t ws_bytes,
+                               void* stream) {
+    g_last_error.clear();
+    return step2_common<float>("snrt_step2_limited", m, q, sc, a, lim, psi_in, psi_out, ws,
+                               ws_bytes, stream);
+}
+
+snrt_status snrt_step2_limited_f64(const snrt_mesh* m, const snrt_quad* q,
+                                   const snrt_scatter* sc, const snrt_step_args_f64* a,
+                                   const snrt_limiter* lim, const double* psi_in,
+                                   double* psi_out, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    return step2_common<double>("snrt_step2_limited_f64", m, q, sc, a, lim, psi_in, psi_out,
+                                ws, ws_bytes, stream);
 }
 
 snrt_status snrt_step_imex(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,

@@ -242,10 +242,14 @@ hipError_t launch_imex64(const snrt_mesh& m, const snrt_quad& q, const StepArgs6
 
 // Second-order scheme (sn_step2.hip): limited gradient of a stage input and the stage
 // update with reconstructed face values; final = true writes (psi_n + stage) / 2.
+struct Limiter {
+    int32_t kind = SNRT_LIMITER_BARTH_JESPERSEN;
+    double k = 0.0;    // Venkatakrishnan's K (eps^2 = (K sqrt(A_i))^3)
+};
 hipError_t launch_grad2_32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
-                           const float* psi, float* G, hipStream_t st);
+                           const Limiter& lim, const float* psi, float* G, hipStream_t st);
 hipError_t launch_grad2_64(const snrt_mesh& m, const snrt_quad& q, const StepArgs64& a,
-                           const double* psi, double* G, hipStream_t st);
+                           const Limiter& lim, const double* psi, double* G, hipStream_t st);
 hipError_t launch_flux2_32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
                            const float* psi, const float* G, const float* S,
                            const float* psi_n, float* out, hipStream_t st);

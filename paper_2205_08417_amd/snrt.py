@@ -46,6 +46,7 @@ EXPORTS = [
     "snrt_step_adjoint_f64", "snrt_scatter_apply", "snrt_mass", "snrt_scalar_flux",
     "snrt_dose_accumulate", "snrt_dose_adjoint", "snrt_dose_density_grad", "snrt_permute",
     "snrt_mesh_set_face_midpoints", "snrt_step2_workspace_size", "snrt_step2", "snrt_step2_f64",
+    "snrt_step2_limited", "snrt_step2_limited_f64",
     "snrt_scatter_moments", "snrt_step_imex", "snrt_step_imex_f64",
     "snrt_pn_operators", "snrt_pn_create", "snrt_pn_destroy", "snrt_pn_info",
     "snrt_pn_state_elems", "snrt_pn_layout", "snrt_pn_step", "snrt_pn_step_f64",
@@ -56,6 +57,25 @@ class SnrtError(RuntimeError):
     def __init__(self, fn: str, status: int, msg: str):
         super().__init__(f"{fn} failed with status {status}: {msg}")
         self.status = status
+
+
+SNRT_LIMITER_BARTH_JESPERSEN = 0
+SNRT_LIMITER_VENKATAKRISHNAN = 1
+LIMITERS = {"barth-jespersen": SNRT_LIMITER_BARTH_JESPERSEN,
+            "venkatakrishnan": SNRT_LIMITER_VENKATAKRISHNAN}
+
+
+class Limiter(ctypes.Structure):
+    """``snrt_limiter``: the second-order step's slope limiter and Venkatakrishnan's K."""
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("k", ctypes.c_double)]
+
+
+def limiter(kind="barth-jespersen", k: float = 1.0) -> Limiter:
+    if isinstance(kind, str):
+        if kind not in LIMITERS:
+            raise ValueError(f"unknown limiter {kind!r}; expected one of {sorted(LIMITERS)}")
+        kind = LIMITERS[kind]
+    return Limiter(int(kind), 0, float(k))
 
 
 class StepArgs(ctypes.Structure):
@@ -125,6 +145,12 @@ def lib() -> ctypes.CDLL:
                              ctypes.c_size_t, _vp]),
         "snrt_step2_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp,
                                  ctypes.c_size_t, _vp]),
+        "snrt_step2_limited": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs),
+                                     ctypes.POINTER(Limiter), _vp, _vp, _vp, ctypes.c_size_t,
+                                     _vp]),
+        "snrt_step2_limited_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs),
+                                         ctypes.POINTER(Limiter), _vp, _vp, _vp,
+                                         ctypes.c_size_t, _vp]),
         "snrt_pn_operators": (_st, [ctypes.c_int32, _dp, _dp, _dp, _dp]),
         "snrt_pn_create": (_st, [ctypes.POINTER(_vp), ctypes.c_int32, _dp]),
         "snrt_pn_destroy": (None, [_vp]),
@@ -298,6 +324,23 @@ def snrt_step2_f64(mesh, quad, scatter, args: StepArgs, psi_in, psi_out, ws=None
     _check("snrt_step2_f64", lib().snrt_step2_f64(mesh, quad, scatter, ctypes.byref(args),
                                                   _ptr(psi_in), _ptr(psi_out), _ptr(ws),
                                                   int(ws_bytes), _stream(stream)))
+
+
+def snrt_step2_limited(mesh, quad, scatter, args: StepArgs, lim: Optional[Limiter], psi_in,
+                       psi_out, ws=None, ws_bytes=0, stream=None) -> None:
+    _check("snrt_step2_limited",
+           lib().snrt_step2_limited(mesh, quad, scatter, ctypes.byref(args),
+                                    None if lim is None else ctypes.byref(lim), _ptr(psi_in),
+                                    _ptr(psi_out), _ptr(ws), int(ws_bytes), _stream(stream)))
+
+
+def snrt_step2_limited_f64(mesh, quad, scatter, args: StepArgs, lim: Optional[Limiter], psi_in,
+                           psi_out, ws=None, ws_bytes=0, stream=None) -> None:
+    _check("snrt_step2_limited_f64",
+           lib().snrt_step2_limited_f64(mesh, quad, scatter, ctypes.byref(args),
+                                        None if lim is None else ctypes.byref(lim), _ptr(psi_in),
+                                        _ptr(psi_out), _ptr(ws), int(ws_bytes),
+                                        _stream(stream)))
 
 
 def snrt_workspace_size(mesh: int, quad: int, scatter: int) -> int:

@@ -134,19 +134,20 @@ class Solver:
         snrt.snrt_step_imex_f64(self.mesh, self.quad, self.scatter, args or self.args(**kw),
                                 psi_in, psi_out)
 
-    def step2(self, psi_in, psi_out, args=None, **kw):
-        """One Heun step of the second-order scheme (limited linear reconstruction)."""
+    def step2(self, psi_in, psi_out, args=None, limiter="barth-jespersen", vk_k=1.0, **kw):
+        """One Heun step of the second-order scheme (limited linear reconstruction);
+        ``limiter`` is "barth-jespersen" or "venkatakrishnan" (with its K = ``vk_k``)."""
         ws, n = self._ws2(False)
-        snrt.snrt_step2(self.mesh, self.quad, self.scatter, args or self.args(**kw), psi_in,
-                        psi_out, ws, n)
+        snrt.snrt_step2_limited(self.mesh, self.quad, self.scatter, args or self.args(**kw),
+                                snrt.limiter(limiter, vk_k), psi_in, psi_out, ws, n)
 
-    def step2_f64(self, psi_in, psi_out, args=None, **kw):
+    def step2_f64(self, psi_in, psi_out, args=None, limiter="barth-jespersen", vk_k=1.0, **kw):
         if self.mats64 is None:
             self.mats64 = self._materials(torch.float64)
         kw["fp64"] = True
         ws, n = self._ws2(True)
-        snrt.snrt_step2_f64(self.mesh, self.quad, self.scatter, args or self.args(**kw), psi_in,
-                            psi_out, ws, n)
+        snrt.snrt_step2_limited_f64(self.mesh, self.quad, self.scatter, args or self.args(**kw),
+                                    snrt.limiter(limiter, vk_k), psi_in, psi_out, ws, n)
 
     def adjoint_step(self, psi_n, lam_np1, lam_n, g_sigma_t=None, g_sigma_s=None, g_rho=None,
                      args=None, **kw):
@@ -168,10 +169,12 @@ class Solver:
                 alpha_s: Optional[Sequence[float]] = None,
                 inflow_scale: Optional[Sequence[float]] = None,
                 dose_coeff: Optional[Sequence[float]] = None,
-                dose: Optional[torch.Tensor] = None, order: int = 1, imex: bool = False):
+                dose: Optional[torch.Tensor] = None, order: int = 1, imex: bool = False,
+                limiter: str = "barth-jespersen", vk_k: float = 1.0):
         """Advance ``nsteps`` explicit steps (ping-pong buffers).  Returns ``(psi, dose)``;
         the dose (FP64, internal order) adds ``dose_coeff[n]`` times the density-weighted
-        scalar flux of the state entering step n."""
+        scalar flux of the state entering step n.  ``limiter`` and ``vk_k`` choose the slope
+        limiter of the second-order scheme (``order=2``)."""
         a = psi0.clone()
         b = torch.empty_like(a)
         if dose_coeff is not None and dose is None:
@@ -183,7 +186,10 @@ class Solver:
             step = lambda m, q, sc, args, a, b, ws_, n_, st: fn(m, q, sc, args, a, b, st)  # noqa
             ws, ws_bytes = None, 0
         elif order == 2:
-            step = snrt.snrt_step2_f64 if fp64 else snrt.snrt_step2
+            fn2 = snrt.snrt_step2_limited_f64 if fp64 else snrt.snrt_step2_limited
+            lim = snrt.limiter(limiter, vk_k)
+            step = lambda m, q, sc, args, a, b, ws_, n_, st: fn2(m, q, sc, args, lim, a, b,  # noqa
+                                                                  ws_, n_, st)
             w2, ws_bytes = self._ws2(fp64)
             ws = w2.data_ptr()
         elif order == 1:
