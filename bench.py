@@ -74,10 +74,23 @@ def cpu_baseline(P, budget_s: float = 12.0):
     for _ in range(n):
         psi = o.step(op, psi, P.dt)
     el = time.perf_counter() - t0
-    return {"value": P.ncells * P.nq * n / el, "unit": "cell-ordinate updates/s",
-            "cores": o.num_threads(), "kind": "oracle",
-            "sample": f"{n} FP64 oracle steps of the full {WORKLOAD} workload "
-                      f"({P.ncells} cells x {P.nq} ordinates), {el:.1f} s wall"}
+    out = {"value": P.ncells * P.nq * n / el, "unit": "cell-ordinate updates/s",
+           "cores": o.num_threads(), "kind": "oracle",
+           "sample": f"{n} FP64 oracle steps of the full {WORKLOAD} workload "
+                     f"({P.ncells} cells x {P.nq} ordinates), {el:.1f} s wall"}
+    # the same oracle on one host thread, over a shorter sample
+    prev = o.set_num_threads(1)
+    try:
+        n1 = max(1, min(n, int(0.25 * budget_s / max(el / n, 1e-6) / out["cores"])))
+        t0 = time.perf_counter()
+        for _ in range(n1):
+            psi = o.step(op, psi, P.dt)
+        el1 = time.perf_counter() - t0
+    finally:
+        o.set_num_threads(prev)
+    out["single_thread"] = {"value": P.ncells * P.nq * n1 / el1, "cores": 1,
+                            "sample": f"{n1} steps, {el1:.1f} s wall"}
+    return out
 
 
 def timed(fn, n, stream):

@@ -44,6 +44,8 @@ def lib():
         L = ctypes.CDLL(_LIB)
         L.oracle_version.restype = ctypes.c_int
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         L.oracle_step.restype = ctypes.c_int
         L.oracle_step.argtypes = [ctypes.c_int64, ctypes.c_int32, _ip, _dp, _dp, ctypes.c_int32,
                                   _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_double,
@@ -297,6 +299,11 @@ def rollout_gradient(op: OracleProblem, psi0, dt: float, nsteps: int,
 def num_threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> int:
+    """Sets the OpenMP thread count of the oracle's parallel loops; returns the previous."""
+    return int(lib().oracle_set_num_threads(int(n)))
 
 
 def rel_l2(x, ref) -> float:

@@ -57,6 +57,18 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Sets the thread count of the following parallel loops (n >= 1); returns the previous one. */
+int oracle_set_num_threads(int n)
+{
+    int prev = oracle_num_threads();
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+    return prev;
+}
+
 /* Scattering source of cell c at ordinate q: sum_p k(Omega_q.Omega_p) w_p psi_cp (eq. SNEqns). */
 static double scatter_source(int32_t nq, const double* w, const double* K, const double* psi_c, int32_t q)
 {

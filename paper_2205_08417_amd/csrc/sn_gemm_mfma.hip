@@ -21,11 +21,15 @@
 //   small tiles multiply an eighth or a quarter as much per chunk and keep FD = 4 chunks in
 //   flight instead.
 //   A (Psi, FP32 rows) is split into hi/lo as it is written to LDS; X arrives pre-split
-//   and pre-tiled (plane[kc][n][kk] = part of X[kc*32 + kk][n]), so one chunk of a block's
-//   256 columns is a contiguous 16 KB run per half.  Every LDS plane is [256][32] bf16
-//   (64-byte rows) with the 16-byte granule g of row r stored at position g ^ ((r>>2)&3):
-//   the fragment reads of 16 consecutive rows and the stores of 4 consecutive rows then
-//   fall on distinct banks without padding.
+//   and pre-tiled in the LDS plane order (row (kc, n) holds X[kc*32 + kk][n], kk < 32), so
+//   one chunk of a block's 256 columns is a contiguous 16 KB run per half, copied to LDS
+//   unchanged.  Every LDS plane is [256][32] bf16 (64-byte rows) with the 16-byte granule
+//   g of row r stored at position g ^ ((r>>2)&3): the fragment reads of 16 consecutive rows
+//   and the stores of 4 consecutive rows then fall on distinct banks without padding.
+//   The two waves that share a SIMD run a chunk in different orders (split-then-multiply
+//   and half-multiply, split, half-multiply), so one's VALU split overlaps the other's
+//   matrix products; without it both split right after the barrier and the matrix core
+//   idles (7 % of the product time, measured).
 //   Consecutive logical blocks share an A row block (its N tiles) and the XCD-aware block
 //   order keeps them on one XCD, so A is fetched from HBM about once.
 // MFMA operand layout (32x32x16): lane l supplies row (A) / column (B) l % 32 and the eight
@@ -79,7 +83,7 @@ __device__ __forceinline__ int swz(int r, int g) { return g ^ ((r >> 2) & 3); }
 
 // One BM x BN block tile of C = A X; lb is the logical block index (row block major, column
 // blocks fastest) and lds the block's two stages of NP planes.
-template <bool THREE, int BM, int BN, int FD>
+template <bool THREE, int BM, int BN, int FD, bool STAGGER>
 __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
                                            const uint16_t* __restrict__ Bhi,
                                            const uint16_t* __restrict__ Blo,
@@ -148,11 +152,9 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
         }
 #pragma unroll
         for (int e = 0; e < BV; ++e) {
-            const int p = tid + e * kThreads;
-            const int n = p >> 2, g = p & 3;
-            const int o = n * BK + swz(n, g) * 8;
-            *reinterpret_cast<u32x4*>(&Bh[o]) = gbh[slot][e];
-            if constexpr (THREE) *reinterpret_cast<u32x4*>(&Bl[o]) = gbl[slot][e];
+            const int p = tid + e * kThreads;    // X is stored in the plane's order
+            *reinterpret_cast<u32x4*>(&Bh[p * 8]) = gbh[slot][e];
+            if constexpr (THREE) *reinterpret_cast<u32x4*>(&Bl[p * 8]) = gbl[slot][e];
         }
     };
 
@@ -176,45 +178,64 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
 #pragma unroll
     for (int d = 1; d <= FD; ++d)
         if (d < nk) fetch(d, d % FD);
+    // Waves w and w + 4 share a SIMD.  With STAGGER the second group multiplies the first
+    // half of a chunk before staging the next one, so that one wave's hi/lo split (VALU)
+    // runs beside the other's matrix products instead of both idling the matrix core
+    // right after the barrier.  The products of every accumulator keep their order.
+    const bool late = STAGGER && __builtin_amdgcn_readfirstlane(tid >> 8) != 0;
+
+    auto read_frags = [&](int s, int ks, bf16x8 (&ah)[IM], bf16x8 (&al)[IM], bf16x8 (&bh)[JN],
+                          bf16x8 (&bl)[JN]) {
+        const uint16_t* Ah = lds + (s * NP + 0) * kPlane;
+        const uint16_t* Bh = lds + (s * NP + 1) * kPlane;
+        const uint16_t* Al = lds + (s * NP + 2) * kPlane;
+        const uint16_t* Bl = lds + (s * NP + 3) * kPlane;
+#pragma unroll
+        for (int j = 0; j < JN; ++j) {
+            const int o = (wn + j * 32) * BK + foff[ks];
+            bh[j] = *reinterpret_cast<const bf16x8*>(&Bh[o]);
+            if constexpr (THREE) bl[j] = *reinterpret_cast<const bf16x8*>(&Bl[o]);
+        }
+#pragma unroll
+        for (int i = 0; i < IM; ++i) {
+            const int o = (wm + i * 32) * BK + foff[ks];
+            ah[i] = *reinterpret_cast<const bf16x8*>(&Ah[o]);
+            if constexpr (THREE) al[i] = *reinterpret_cast<const bf16x8*>(&Al[o]);
+        }
+    };
+    auto multiply = [&](const bf16x8 (&ah)[IM], const bf16x8 (&al)[IM], const bf16x8 (&bh)[JN],
+                        const bf16x8 (&bl)[JN]) {
+#pragma unroll
+        for (int i = 0; i < IM; ++i)
+#pragma unroll
+            for (int j = 0; j < JN; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                if constexpr (THREE) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                }
+            }
+    };
+
     // the K loop, unrolled by FD so every register slot index is a constant
     for (int kb = 0; kb < nk; kb += FD) {
 #pragma unroll
         for (int u = 0; u < FD; ++u) {
             const int kc = kb + u;
             if (kc >= nk) break;
-            __syncthreads();             // chunk kc staged; the idle stage is free again
             const int s = kc & 1;
-            if (kc + 1 < nk) stash(s ^ 1, (u + 1) % FD);
-            if (kc + 1 + FD < nk) fetch(kc + 1 + FD, (u + 1) % FD);
-            const uint16_t* Ah = lds + (s * NP + 0) * kPlane;
-            const uint16_t* Bh = lds + (s * NP + 1) * kPlane;
-            const uint16_t* Al = lds + (s * NP + 2) * kPlane;
-            const uint16_t* Bl = lds + (s * NP + 3) * kPlane;
+            __syncthreads();             // chunk kc staged; the idle stage is free again
+            auto prepare = [&]() {
+                if (kc + 1 < nk) stash(s ^ 1, (u + 1) % FD);
+                if (kc + 1 + FD < nk) fetch(kc + 1 + FD, (u + 1) % FD);
+            };
+            if (!late) prepare();
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
+                if (late && ks == 1) prepare();
                 bf16x8 ah[IM], al[IM], bh[JN], bl[JN];
-#pragma unroll
-                for (int j = 0; j < JN; ++j) {
-                    const int o = (wn + j * 32) * BK + foff[ks];
-                    bh[j] = *reinterpret_cast<const bf16x8*>(&Bh[o]);
-                    if constexpr (THREE) bl[j] = *reinterpret_cast<const bf16x8*>(&Bl[o]);
-                }
-#pragma unroll
-                for (int i = 0; i < IM; ++i) {
-                    const int o = (wm + i * 32) * BK + foff[ks];
-                    ah[i] = *reinterpret_cast<const bf16x8*>(&Ah[o]);
-                    if constexpr (THREE) al[i] = *reinterpret_cast<const bf16x8*>(&Al[o]);
-                }
-#pragma unroll
-                for (int i = 0; i < IM; ++i)
-#pragma unroll
-                    for (int j = 0; j < JN; ++j) {
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-                        if constexpr (THREE) {
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-                        }
-                    }
+                read_frags(s, ks, ah, al, bh, bl);
+                multiply(ah, al, bh, bl);
             }
         }
     }
@@ -237,7 +258,7 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
 // Blocks [0, nmain) are 256 x 256 tiles of the first M1 rows; blocks [nmain, grid) are
 // TM x TN tiles of the remaining rows (none when nmain == grid).  Blocks are dispatched in
 // order, so the small tiles fill the compute units as the full ones finish.
-template <bool THREE, int TM, int TN, int TFD>
+template <bool THREE, int TM, int TN, int TFD, bool STAGGER>
 __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict__ A,
                                                         const uint16_t* __restrict__ Bhi,
                                                         const uint16_t* __restrict__ Blo,
@@ -249,25 +270,29 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict_
     __shared__ __attribute__((aligned(16))) uint16_t lds[2 * NP * kPlane];
     const int64_t b = blockIdx.x;
     if (b < nmain) {
-        gemm_block<THREE, 256, 256, 1>(A, Bhi, Blo, C, M1, K, N, xcd_remap(b, nmain), lds);
+        gemm_block<THREE, 256, 256, 1, STAGGER>(A, Bhi, Blo, C, M1, K, N, xcd_remap(b, nmain),
+                                                lds);
     } else {
         // nmain is a multiple of the XCD count, so the remap of the tail stays XCD-aware
         const int64_t nt = (int64_t)gridDim.x - nmain;
-        gemm_block<THREE, TM, TN, TFD>(A + M1 * K, Bhi, Blo, C + M1 * N, M - M1, K, N,
-                                       xcd_remap(b - nmain, nt), lds);
+        gemm_block<THREE, TM, TN, TFD, STAGGER>(A + M1 * K, Bhi, Blo, C + M1 * N, M - M1, K, N,
+                                                xcd_remap(b - nmain, nt), lds);
     }
 }
 
-// Tiled halves of X [K][N]: hi[(kc*N + n)*32 + kk] = bf16(X[kc*32 + kk][n]), lo = bf16(X - hi)
+// Tiled halves of X [K][N] in the LDS plane order: the 64-byte row (kc, n) holds
+// X[kc*32 + kk][n], kk = 0..31, as four 16-byte granules with granule g at position
+// g ^ ((n >> 2) & 3); hi = bf16(X), lo = bf16(X - hi).
 __global__ __launch_bounds__(256) void k_split(const float* __restrict__ B, uint16_t* __restrict__ hi,
                                                uint16_t* __restrict__ lo, int32_t K, int32_t N)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= (int64_t)K * N) return;
-    const int kk = (int)(i % BK);
+    const int pos = (int)(i % BK);
     const int64_t t = i / BK;
     const int n = (int)(t % N);
     const int kc = (int)(t / N);
+    const int kk = swz(n, pos >> 3) * 8 + (pos & 7);
     const float x = B[(int64_t)(kc * BK + kk) * N + n];
     const uint32_t h = bf16_rne_bits(x);
     hi[i] = (uint16_t)h;
@@ -307,13 +332,17 @@ hipError_t launch_split(const float* A, const uint16_t* Bhi, const uint16_t* Blo
     const int64_t nmain = ((M1 + 255) / 256) * (N / 256);
     const int64_t ntail = ((M - M1 + TM - 1) / TM) * (N / TN);
     const dim3 grid((unsigned)(nmain + ntail));
-    if (three)
-        hipLaunchKernelGGL((k_gemm_bf16<true, TM, TN, 4>), grid, dim3(kThreads), 0, st, A, Bhi,
-                           Blo, C, M1, M, K, N, nmain);
-    else
-        hipLaunchKernelGGL((k_gemm_bf16<false, TM, TN, 4>), grid, dim3(kThreads), 0, st, A, Bhi,
-                           Blo, C, M1, M, K, N, nmain);
-    return hipGetLastError();
+    auto go = [&](auto three_c, auto stagger_c) {
+        constexpr bool T3 = decltype(three_c)::value, SG = decltype(stagger_c)::value;
+        hipLaunchKernelGGL((k_gemm_bf16<T3, TM, TN, 4, SG>), grid, dim3(kThreads), 0, st, A,
+                           Bhi, Blo, C, M1, M, K, N, nmain);
+        return hipGetLastError();
+    };
+    auto by_stagger = [&](auto three_c) {
+        return tune().gemm_stagger ? go(three_c, std::true_type{})
+                                   : go(three_c, std::false_type{});
+    };
+    return three ? by_stagger(std::true_type{}) : by_stagger(std::false_type{});
 }
 
 hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,

@@ -48,6 +48,7 @@ const Tune& tune() {
             if (n >= 1 && bpc >= 1 && bpc <= 64) r.step_blocks_per_cu = bpc;
             if (n == 2 && bpc2 >= 1 && bpc2 <= 64) r.flux2_blocks_per_cu = bpc2;
         }
+        if (const char* e = std::getenv("SNRT_GEMM_STAGGER")) r.gemm_stagger = std::atoi(e) != 0;
         return r;
     }();
     return t;
