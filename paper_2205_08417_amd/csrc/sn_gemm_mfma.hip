@@ -1,7 +1,7 @@
 // Scattering products C = A X on the CDNA4 matrix cores: the dense kernel S = Psi B of
 // eq. SNEqns (B[p][q] = w_p K[q][p], K = N = nq) and the two skinny products of the
 // moment-projected form O Sigma M of eq. SNEqns2 (K or N = the padded moment count).
-// A is [M][K] FP32 row-major, C is [M][N] FP32; K % 32 == 0 and N % 256 == 0.
+// A is [M][K] FP32 row-major, C is [M][N] FP32; K % 32 == 0 and N % 128 == 0.
 //
 // Split precision: every FP32 operand x is written as hi + lo with hi = bf16(x) and
 // lo = bf16(x - hi) (round to nearest even; x - hi is exact in FP32), and the product is
@@ -258,7 +258,7 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
 // Blocks [0, nmain) are 256 x 256 tiles of the first M1 rows; blocks [nmain, grid) are
 // TM x TN tiles of the remaining rows (none when nmain == grid).  Blocks are dispatched in
 // order, so the small tiles fill the compute units as the full ones finish.
-template <bool THREE, int TM, int TN, int TFD, bool STAGGER>
+template <bool THREE, int MBN, int TM, int TN, int TFD, bool STAGGER>
 __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict__ A,
                                                         const uint16_t* __restrict__ Bhi,
                                                         const uint16_t* __restrict__ Blo,
@@ -270,8 +270,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict_
     __shared__ __attribute__((aligned(16))) uint16_t lds[2 * NP * kPlane];
     const int64_t b = blockIdx.x;
     if (b < nmain) {
-        gemm_block<THREE, 256, 256, 1, STAGGER>(A, Bhi, Blo, C, M1, K, N, xcd_remap(b, nmain),
-                                                lds);
+        // 256 x 256 tiles keep one chunk in flight (their multiply covers the load latency
+        // and their accumulators leave no room for more); 256 x 128 tiles keep two
+        gemm_block<THREE, 256, MBN, MBN == 256 ? 1 : 2, STAGGER>(A, Bhi, Blo, C, M1, K, N,
+                                                                xcd_remap(b, nmain), lds);
     } else {
         // nmain is a multiple of the XCD count, so the remap of the tail stays XCD-aware
         const int64_t nt = (int64_t)gridDim.x - nmain;
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(256) void k_split(const float* __restrict__ B, uint
 
 hipError_t launch_split_bf16(const float* B, uint16_t* hi, uint16_t* lo, int32_t K, int32_t N,
                              hipStream_t st) {
-    if (K % BK != 0 || N % 256 != 0) return hipErrorNotSupported;
+    if (K % BK != 0 || N % 128 != 0) return hipErrorNotSupported;
     const int64_t n = (int64_t)K * N;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_split, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, B, hi, lo, K, N);
@@ -325,17 +327,17 @@ int device_cu_count() {
     return cache[dev];
 }
 
-template <int TM, int TN>
+template <int MBN, int TM, int TN>
 hipError_t launch_split(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
                         int64_t M1, int64_t M, int32_t K, int32_t N, bool three,
                         hipStream_t st) {
-    const int64_t nmain = ((M1 + 255) / 256) * (N / 256);
+    const int64_t nmain = ((M1 + 255) / 256) * (N / MBN);
     const int64_t ntail = ((M - M1 + TM - 1) / TM) * (N / TN);
     const dim3 grid((unsigned)(nmain + ntail));
     auto go = [&](auto three_c, auto stagger_c) {
         constexpr bool T3 = decltype(three_c)::value, SG = decltype(stagger_c)::value;
-        hipLaunchKernelGGL((k_gemm_bf16<T3, TM, TN, 4, SG>), grid, dim3(kThreads), 0, st, A,
-                           Bhi, Blo, C, M1, M, K, N, nmain);
+        hipLaunchKernelGGL((k_gemm_bf16<T3, MBN, TM, TN, 4, SG>), grid, dim3(kThreads), 0, st,
+                           A, Bhi, Blo, C, M1, M, K, N, nmain);
         return hipGetLastError();
     };
     auto by_stagger = [&](auto three_c) {
@@ -348,23 +350,32 @@ hipError_t launch_split(const float* A, const uint16_t* Bhi, const uint16_t* Blo
 hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
                             int64_t M, int32_t K, int32_t N, bool three_products, hipStream_t st) {
     if (M == 0) return hipSuccess;
-    if (K % BK != 0 || N % 256 != 0 || K == 0) return hipErrorNotSupported;
-    // One 256 x 256 block per compute unit and round (128 KB of LDS each).  When the last
-    // round would be mostly empty, its rows run as smaller blocks: 64 x 128 (an eighth of the
-    // work) if they then fill one round, else 64 x 256 (a quarter) if those fill one round;
-    // a small block takes about half the time of a full one (measured), so a fuller last
-    // round stays as it is.
-    const int64_t nN = N / 256;
+    if (K % BK != 0 || N % 128 != 0 || K == 0) return hipErrorNotSupported;
+    // One 256 x 256 block (256 x 128 when N is an odd multiple of 128) per compute unit and
+    // round (128 KB of LDS each).  When the last round would be mostly empty, its rows run
+    // as smaller blocks: 64 x 128 (an eighth of a 256 x 256 block) if they then fill one
+    // round, else 64 x 256 (a quarter) if those fill one round; a small block takes about
+    // half the time of a full one (measured), so a fuller last round stays as it is.  With
+    // 256 x 128 blocks only the quarter (64 x 128) applies.
+    const bool wide = N % 256 == 0;
+    const int64_t nN = wide ? N / 256 : N / 128;
     const int64_t tiles = ((M + 255) / 256) * nN;
     const int64_t cu = device_cu_count();
     const int64_t rem = tiles % cu;
-    const bool eighth = tiles > cu && rem != 0 && rem * 8 <= cu && cu % kNumXcd == 0;
-    const bool quarter = !eighth && tiles > cu && rem != 0 && rem * 4 <= cu && cu % kNumXcd == 0;
-    if (!eighth && !quarter)
-        return launch_split<64, 256>(A, Bhi, Blo, C, M, M, K, N, three_products, st);
+    const bool level = tiles > cu && rem != 0 && cu % kNumXcd == 0;
+    const bool eighth = wide && level && rem * 8 <= cu;
+    const bool quarter = !eighth && level && rem * 4 <= cu;
     const int64_t rows1 = std::min<int64_t>(((tiles - rem) / nN) * 256, M);
-    if (eighth) return launch_split<64, 128>(A, Bhi, Blo, C, rows1, M, K, N, three_products, st);
-    return launch_split<64, 256>(A, Bhi, Blo, C, rows1, M, K, N, three_products, st);
+    if (!wide) {
+        if (quarter)
+            return launch_split<128, 64, 128>(A, Bhi, Blo, C, rows1, M, K, N, three_products, st);
+        return launch_split<128, 64, 128>(A, Bhi, Blo, C, M, M, K, N, three_products, st);
+    }
+    if (eighth)
+        return launch_split<256, 64, 128>(A, Bhi, Blo, C, rows1, M, K, N, three_products, st);
+    if (quarter)
+        return launch_split<256, 64, 256>(A, Bhi, Blo, C, rows1, M, K, N, three_products, st);
+    return launch_split<256, 64, 256>(A, Bhi, Blo, C, M, M, K, N, three_products, st);
 }
 
 }  // namespace snrt
