@@ -130,10 +130,11 @@ snrt_status snrt_scatter_moments(snrt_scatter** out, const snrt_quad* quad, int3
                                  const double* sigma_l, snrt_precision precision);
 void snrt_scatter_destroy(snrt_scatter* scatter);
 
-/* Bytes of device workspace snrt_step / snrt_step_adjoint need for this combination
- * (0 for isotropic scattering; one [ncells][nq] FP64-sized buffer for a dense kernel, plus
- * [ncells][moments, padded] for the moment form; the size serves both the FP32 and the FP64
- * entry points). */
+/* Bytes of device workspace that serve every step entry point for this combination:
+ * snrt_step / snrt_step_adjoint (FP32 and FP64) need one [ncells][nq] buffer for a dense
+ * kernel, plus [ncells][moments, padded] for the moment form, and none for isotropic
+ * scattering; snrt_step_dose needs that product buffer (FP32) plus one double per cell and
+ * 256-ordinate row chunk of the dense step (one per cell otherwise). */
 snrt_status snrt_workspace_size(const snrt_mesh* mesh, const snrt_quad* quad,
                                 const snrt_scatter* scatter, size_t* bytes);
 
@@ -174,10 +175,24 @@ typedef struct {
 } snrt_step_args_f64;
 
 /* One explicit Euler S_N step, FP32: psi_out = step(psi_in).  ws: device workspace of at
- * least snrt_workspace_size bytes (may be NULL when that size is 0). */
+ * least snrt_workspace_size bytes (may be NULL for isotropic scattering). */
 snrt_status snrt_step(const snrt_mesh* mesh, const snrt_quad* quad, const snrt_scatter* scatter,
                       const snrt_step_args* args, const float* psi_in, float* psi_out,
                       void* ws, size_t ws_bytes, void* stream);
+
+/* snrt_dose_accumulate(psi_in, args->inv_rho, coeff, dose) followed by snrt_step, with the
+ * dose sum taken from the rows the step kernel reads anyway (Sec. 2 pseudo-time dose, left
+ * endpoint) instead of a second pass over psi_in:
+ *     dose[i] += coeff * inv_rho[i] * sum_q w_q psi_in[i][q]   (FP64; inv_rho NULL = 1)
+ * psi_out is bitwise the output of snrt_step; the dose agrees with snrt_dose_accumulate to
+ * FP64 rounding (the sum is formed per 256-ordinate row chunk of the dense step, then the
+ * chunks are added in order; deterministic).  ws: at least snrt_workspace_size bytes,
+ * 16-byte aligned.  dose must not overlap the states or the workspace (SNRT_E_ALIAS);
+ * SNRT_E_NONFINITE for a non-finite coeff. */
+snrt_status snrt_step_dose(const snrt_mesh* mesh, const snrt_quad* quad,
+                           const snrt_scatter* scatter, const snrt_step_args* args,
+                           const float* psi_in, float* psi_out, double coeff, double* dose,
+                           void* ws, size_t ws_bytes, void* stream);
 
 /* The same step in FP64 throughout (parity template of the FP32 kernels).  Dense scattering
  * runs as an FP64 product regardless of the scatter handle's precision. */

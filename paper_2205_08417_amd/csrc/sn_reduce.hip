@@ -125,6 +125,20 @@ __global__ __launch_bounds__(kStepBlock) void k_dose(const float* __restrict__ p
     });
 }
 
+// dose[c] += coeff * inv_rho[c] * sum_k part[c * nch + k]: the fused step's per-item sums
+// of the state entering the step, folded in a fixed order (one thread per cell)
+__global__ __launch_bounds__(256) void k_dose_fold(const double* __restrict__ part, int32_t nch,
+                                                   const float* __restrict__ inv_rho,
+                                                   double coeff, int64_t nc,
+                                                   double* __restrict__ dose)
+{
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= nc) return;
+    double s = 0.0;
+    for (int32_t k = 0; k < nch; ++k) s += part[c * nch + k];
+    dose[c] += coeff * (inv_rho ? (double)inv_rho[c] : 1.0) * s;
+}
+
 // out[k] = in[src(k)] row copy in 4-byte words; to_user: out[perm[k]] = in[k]
 __global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ in,
                                                  uint32_t* __restrict__ out,
@@ -234,6 +248,14 @@ hipError_t launch_dose(const snrt_mesh& m, const snrt_quad& q, const float* psi,
                            q.tab64 + 2 * (int64_t)q.nq, inv_rho, coeff, m.nc, q.nq, dose);
         return hipGetLastError();
     });
+}
+
+hipError_t launch_dose_fold(const snrt_mesh& m, const double* part, int32_t nch,
+                            const float* inv_rho, double coeff, double* dose, hipStream_t st) {
+    if (m.nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dose_fold, dim3((unsigned)((m.nc + 255) / 256)), dim3(256), 0, st, part,
+                       nch, inv_rho, coeff, m.nc, dose);
+    return hipGetLastError();
 }
 
 hipError_t launch_permute(const snrt_mesh& m, int to_user, const void* in, void* out,

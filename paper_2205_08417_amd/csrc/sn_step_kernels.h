@@ -290,6 +290,7 @@ struct FwdCtx {
     const T *src_arr;
     T src_mul, inflow_scale;
     bool dirichlet, neumann;
+    double* dpart;    // FP64 sum_q w_q psi_q of each work item (the fused dose), or unused
 };
 
 template <int MF, typename T>
@@ -340,12 +341,21 @@ __device__ __forceinline__ void fwd_load_stage(FwdStage<V, MF, DENSE, T>& d, con
 }
 
 template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T, int SA = kAuxStream,
-          bool IMEX = false>
+          bool IMEX = false, bool DOSE = false>
 __device__ __forceinline__ void fwd_compute(const FwdStage<V, MF, DENSE, T>& d, const T (&ox)[V],
                                             const T (&oy)[V], const T (&wi)[V], int32_t c,
                                             uint32_t cb, int32_t nq, int q0, const FwdCtx<T>& x,
-                                            T w4 = T(0))
+                                            T w4 = T(0), const double* wd = nullptr,
+                                            int32_t item = 0)
 {
+    if constexpr (DOSE) {
+        // the dose of the state entering the step: FP64 weighted sum of this item's slice
+        double sd = 0.0;
+#pragma unroll
+        for (int k = 0; k < V; ++k) sd += wd[k] * (double)d.p[k];
+        sd = wave_sum(sd);
+        if (q0 == 0) x.dpart[item] = sd;
+    }
     if constexpr (IMEX) {
         // (a - c K~) psi' = b, K~ = w/(4 pi) (isotropic): with B = sum_q (w_q/4pi) b_q and
         // W = sum_q w_q/(4 pi), the scalar flux of psi' is B / (a - c W) times 4 pi, so
@@ -414,12 +424,12 @@ __device__ __forceinline__ void fwd_compute(const FwdStage<V, MF, DENSE, T>& d, 
     buf_store_row<V, EXACT, T, SA>(x.out, (uint32_t)c * x.row_bytes + cb, q0, nq, o);
 }
 
-template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T, bool IMEX = false>
-__global__ __launch_bounds__(kStepBlock) void k_step(
+template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T, bool IMEX, bool DOSE>
+__device__ __forceinline__ void step_sweep(
     const typename GeomOf<T>::type* __restrict__ geom, int64_t nc, int32_t nq,
-    const T* __restrict__ tab, typename ArgsOf<T>::type a, const T* __restrict__ psi_in,
+    const T* __restrict__ tab, const typename ArgsOf<T>::type& a, const T* __restrict__ psi_in,
     T* __restrict__ psi_out, const T* __restrict__ S, int64_t items_per_xcd, uint32_t nbf,
-    int32_t shift)
+    int32_t shift, const double* __restrict__ wq, double* __restrict__ dpart)
 {
     // Work items: with dense scattering no ordinate couples to another inside the step, so
     // a row may be cut into 2^shift chunks of 64*V ordinates, one item each (item i is chunk
@@ -458,6 +468,7 @@ __global__ __launch_bounds__(kStepBlock) void k_step(
     cx.inflow_scale = a.inflow_scale;
     cx.dirichlet = a.inflow != nullptr && !a.neumann;
     cx.neumann = a.neumann != 0;
+    cx.dpart = dpart;
     // prefetches address the clamped item min(i', xend-1) in [xbeg, xend): always in bounds
     auto clampc = [xend, sh](int32_t cc) {
         return uniform_cell((cc < xend ? cc : xend - 1) >> sh);
@@ -475,6 +486,11 @@ __global__ __launch_bounds__(kStepBlock) void k_step(
         for (int k = 0; k < V; ++k) part += wi[k];
         w4 = cell_sum(part);
     }
+    double wd[DOSE ? V : 1];                    // FP64 weights w_q of the fused dose
+    if constexpr (DOSE) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) wd[k] = (EXACT || tq + k < nq) ? wq[tq + k] : 0.0;
+    }
 
     NbrList<MF> n0, n1, n2;
     FwdStage<V, MF, DENSE, T> sa, sb;
@@ -486,20 +502,46 @@ __global__ __launch_bounds__(kStepBlock) void k_step(
         fwd_load_stage<V, EXACT, MF, RHO, DENSE>(sb, n1, geom, clampc(c + stride), cb, nq, q0,
                                                  a, cx);
         fwd_load_nbr<MF, T>(n2, geom, clampc(c + 2 * stride));
-        fwd_compute<V, EXACT, MF, RHO, DENSE, T, kAuxStream, IMEX>(sa, ox, oy, wi, clampc(c), cb,
-                                                                  nq, q0, cx, w4);
+        fwd_compute<V, EXACT, MF, RHO, DENSE, T, kAuxStream, IMEX, DOSE>(
+            sa, ox, oy, wi, clampc(c), cb, nq, q0, cx, w4, wd, c);
         c += stride;
         if (c >= xend) break;
         n1 = n2;
         fwd_load_stage<V, EXACT, MF, RHO, DENSE>(sa, n1, geom, clampc(c + stride), cb, nq, q0,
                                                  a, cx);
         fwd_load_nbr<MF, T>(n2, geom, clampc(c + 2 * stride));
-        fwd_compute<V, EXACT, MF, RHO, DENSE, T, kAuxStream, IMEX>(sb, ox, oy, wi, clampc(c), cb,
-                                                                  nq, q0, cx, w4);
+        fwd_compute<V, EXACT, MF, RHO, DENSE, T, kAuxStream, IMEX, DOSE>(
+            sb, ox, oy, wi, clampc(c), cb, nq, q0, cx, w4, wd, c);
         c += stride;
         if (c >= xend) break;
         n1 = n2;
     }
+}
+
+template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T, bool IMEX = false>
+__global__ __launch_bounds__(kStepBlock) void k_step(
+    const typename GeomOf<T>::type* __restrict__ geom, int64_t nc, int32_t nq,
+    const T* __restrict__ tab, typename ArgsOf<T>::type a, const T* __restrict__ psi_in,
+    T* __restrict__ psi_out, const T* __restrict__ S, int64_t items_per_xcd, uint32_t nbf,
+    int32_t shift)
+{
+    step_sweep<V, EXACT, MF, RHO, DENSE, T, IMEX, false>(geom, nc, nq, tab, a, psi_in, psi_out,
+                                                         S, items_per_xcd, nbf, shift, nullptr,
+                                                         nullptr);
+}
+
+// The step with the dose of its input fused: each work item (a row, or one 2^-shift chunk
+// of it) also writes dpart[item] = sum_q w_q psi_q over its ordinates in FP64.
+template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T>
+__global__ __launch_bounds__(kStepBlock) void k_step_dose(
+    const typename GeomOf<T>::type* __restrict__ geom, int64_t nc, int32_t nq,
+    const T* __restrict__ tab, typename ArgsOf<T>::type a, const T* __restrict__ psi_in,
+    T* __restrict__ psi_out, const T* __restrict__ S, int64_t items_per_xcd, uint32_t nbf,
+    int32_t shift, const double* __restrict__ wq, double* __restrict__ dpart)
+{
+    step_sweep<V, EXACT, MF, RHO, DENSE, T, false, true>(geom, nc, nq, tab, a, psi_in, psi_out,
+                                                         S, items_per_xcd, nbf, shift, wq,
+                                                         dpart);
 }
 
 // --------------------------------------------------------------------------- adjoint step
@@ -670,8 +712,20 @@ int resident_blocks(K kernel) {
 template <typename T, int V, bool E, int MF, bool RHO, bool DENSE, bool IMEX = false>
 hipError_t launch_fwd(const typename GeomOf<T>::type* geom, const snrt_mesh& m, const T* tab,
                       int32_t nq, const typename ArgsOf<T>::type& a, const T* psi_in,
-                      T* psi_out, const T* S, int shift, hipStream_t st)
+                      T* psi_out, const T* S, int shift, hipStream_t st,
+                      const double* wq = nullptr, double* dpart = nullptr)
 {
+    if (dpart) {
+        if constexpr (!IMEX) {
+            static const int occ = resident_blocks(k_step_dose<V, E, MF, RHO, DENSE, T>);
+            const StepShape sh = step_shape(m, m.nc << shift, shift ? kCellsPerBlock : 1, occ);
+            hipLaunchKernelGGL((k_step_dose<V, E, MF, RHO, DENSE, T>), dim3(sh.blocks),
+                               dim3(kStepBlock), 0, st, geom, m.nc, nq, tab, a, psi_in, psi_out,
+                               S, sh.cells_per_xcd, (uint32_t)m.nbf, (int32_t)shift, wq, dpart);
+            return hipGetLastError();
+        }
+        return hipErrorNotSupported;
+    }
     static const int occ = resident_blocks(k_step<V, E, MF, RHO, DENSE, T, IMEX>);
     const StepShape sh = step_shape(m, m.nc << shift, shift ? kCellsPerBlock : 1, occ);
     hipLaunchKernelGGL((k_step<V, E, MF, RHO, DENSE, T, IMEX>), dim3(sh.blocks), dim3(kStepBlock),
@@ -715,7 +769,8 @@ hipError_t launch_imex_t(const typename GeomOf<T>::type* geom, const snrt_mesh& 
 template <typename T>
 hipError_t launch_step_t(const typename GeomOf<T>::type* geom, const snrt_mesh& m,
                          const T* tab, int32_t nq, const typename ArgsOf<T>::type& a,
-                         const T* psi_in, T* psi_out, const T* S, hipStream_t st)
+                         const T* psi_in, T* psi_out, const T* S, hipStream_t st,
+                         const double* wq = nullptr, double* dpart = nullptr)
 {
     if (m.nc == 0) return hipSuccess;
     const bool rho = a.inv_rho != nullptr, dense = S != nullptr, mf4 = m.mf == 4;
@@ -728,7 +783,7 @@ hipError_t launch_step_t(const typename GeomOf<T>::type* geom, const snrt_mesh& 
             constexpr bool R = decltype(rc)::value;
             constexpr bool D = decltype(dc)::value;
             return launch_fwd<T, V, E, MF, R, D>(geom, m, tab, nq, a, psi_in, psi_out, S,
-                                                 shift, st);
+                                                 shift, st, wq, dpart);
         };
         using I3 = std::integral_constant<int, 3>;
         using I4 = std::integral_constant<int, 4>;

@@ -561,6 +561,16 @@ size_t product_ws_elems(const snrt_scatter* sc, int64_t nc) {
     return (size_t)nc * (size_t)(sc->B.nq + (sc->B.chain == 2 ? sc->B.mid : 0));
 }
 
+// snrt_step_dose: the FP32 product workspace, then (16-byte aligned) one FP64 partial sum
+// per work item of the step ([nc][items per row]).
+size_t dose_ws_offset(const snrt_mesh* m, const snrt_scatter* sc) {
+    return (product_ws_elems(sc, m->nc) * sizeof(float) + 15) / 16 * 16;
+}
+size_t dose_ws_bytes(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc) {
+    return dose_ws_offset(m, sc) +
+           (size_t)m->nc * step_items_per_row(*q, sc->dense) * sizeof(double);
+}
+
 }  // namespace
 
 extern "C" {
@@ -570,7 +580,7 @@ snrt_status snrt_workspace_size(const snrt_mesh* m, const snrt_quad* q, const sn
     g_last_error.clear();
     SNRT_REQUIRE(m && q && sc && bytes, SNRT_E_ARG, "snrt_workspace_size: NULL argument");
     SNRT_REQUIRE(sc->B.nq == q->nq, SNRT_E_SHAPE, "snrt_workspace_size: scatter/quad nq differ");
-    *bytes = product_ws_elems(sc, m->nc) * sizeof(double);
+    *bytes = std::max(product_ws_elems(sc, m->nc) * sizeof(double), dose_ws_bytes(m, q, sc));
     return SNRT_OK;
 }
 
@@ -717,6 +727,42 @@ snrt_status snrt_step(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter
     }
     hipError_t e = launch_step32(*m, *q, to32(a), psi_in, psi_out, S, st);
     return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_step: launch");
+}
+
+snrt_status snrt_step_dose(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
+                           const snrt_step_args* a, const float* psi_in, float* psi_out,
+                           double coeff, double* dose, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    const char* fn = "snrt_step_dose";
+    SNRT_TRY(check_step_common(fn, m, q, sc, a, sizeof(float), psi_in, psi_out, ws, ws_bytes));
+    SNRT_REQUIRE(is_finite(coeff), SNRT_E_NONFINITE, "snrt_step_dose: non-finite coeff");
+    if (m->nc == 0) return SNRT_OK;
+    SNRT_REQUIRE(dose, SNRT_E_ARG, "snrt_step_dose: NULL dose");
+    const size_t need = dose_ws_bytes(m, q, sc);
+    SNRT_REQUIRE(ws && ws_bytes >= need, SNRT_E_ARG,
+                 "snrt_step_dose: needs a workspace of " + std::to_string(need) + " bytes");
+    SNRT_REQUIRE(aligned16(ws), SNRT_E_ARG, "snrt_step_dose: workspace must be 16-byte aligned");
+    const size_t row = (size_t)m->nc * q->nq * sizeof(float), db = (size_t)m->nc * sizeof(double);
+    SNRT_REQUIRE(!ranges_overlap(ws, need, psi_in, row) && !ranges_overlap(ws, need, psi_out, row),
+                 SNRT_E_ALIAS, "snrt_step_dose: workspace aliases a state array");
+    SNRT_REQUIRE(!ranges_overlap(dose, db, psi_in, row) && !ranges_overlap(dose, db, psi_out, row) &&
+                     !ranges_overlap(dose, db, ws, need),
+                 SNRT_E_ALIAS, "snrt_step_dose: dose aliases a state array or the workspace");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const float* S = nullptr;
+    if (sc->dense) {
+        float* Sbuf = static_cast<float*>(ws);
+        hipError_t e = scatter_product32(sc, psi_in, Sbuf, m->nc, false,
+                                         Sbuf + (size_t)m->nc * q->nq, st);
+        if (e != hipSuccess) return hip_fail(e, "snrt_step_dose: scattering product");
+        S = Sbuf;
+    }
+    double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + dose_ws_offset(m, sc));
+    hipError_t e = launch_step32(*m, *q, to32(a), psi_in, psi_out, S, st, part);
+    if (e == hipSuccess)
+        e = launch_dose_fold(*m, part, step_items_per_row(*q, sc->dense), a->inv_rho, coeff,
+                             dose, st);
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_step_dose: launch");
 }
 
 snrt_status snrt_step_f64(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,

@@ -212,8 +212,14 @@ struct StepArgs64 {
     int32_t neumann;
 };
 
+// dose_part: with the fused dose, the [nc * items per row] FP64 weighted sums of psi_in
 hipError_t launch_step32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
-                         const float* psi_in, float* psi_out, const float* S, hipStream_t st);
+                         const float* psi_in, float* psi_out, const float* S, hipStream_t st,
+                         double* dose_part = nullptr);
+// work items per state row of the FP32 step (row chunks of the dense step)
+int32_t step_items_per_row(const snrt_quad& q, bool dense);
+hipError_t launch_dose_fold(const snrt_mesh& m, const double* part, int32_t nch,
+                            const float* inv_rho, double coeff, double* dose, hipStream_t st);
 hipError_t launch_step64(const snrt_mesh& m, const snrt_quad& q, const StepArgs64& a,
                          const double* psi_in, double* psi_out, const double* S, hipStream_t st);
 hipError_t launch_adjoint32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,

@@ -46,7 +46,7 @@ EXPORTS = [
     "snrt_step_adjoint_f64", "snrt_scatter_apply", "snrt_mass", "snrt_scalar_flux",
     "snrt_dose_accumulate", "snrt_dose_adjoint", "snrt_dose_density_grad", "snrt_permute",
     "snrt_mesh_set_face_midpoints", "snrt_step2_workspace_size", "snrt_step2", "snrt_step2_f64",
-    "snrt_step2_limited", "snrt_step2_limited_f64",
+    "snrt_step2_limited", "snrt_step2_limited_f64", "snrt_step_dose",
     "snrt_scatter_moments", "snrt_step_imex", "snrt_step_imex_f64",
     "snrt_pn_operators", "snrt_pn_create", "snrt_pn_destroy", "snrt_pn_info",
     "snrt_pn_state_elems", "snrt_pn_layout", "snrt_pn_step", "snrt_pn_step_f64",
@@ -145,6 +145,8 @@ def lib() -> ctypes.CDLL:
                              ctypes.c_size_t, _vp]),
         "snrt_step2_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp,
                                  ctypes.c_size_t, _vp]),
+        "snrt_step_dose": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp,
+                                 ctypes.c_double, _vp, _vp, ctypes.c_size_t, _vp]),
         "snrt_step2_limited": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs),
                                      ctypes.POINTER(Limiter), _vp, _vp, _vp, ctypes.c_size_t,
                                      _vp]),
@@ -324,6 +326,14 @@ def snrt_step2_f64(mesh, quad, scatter, args: StepArgs, psi_in, psi_out, ws=None
     _check("snrt_step2_f64", lib().snrt_step2_f64(mesh, quad, scatter, ctypes.byref(args),
                                                   _ptr(psi_in), _ptr(psi_out), _ptr(ws),
                                                   int(ws_bytes), _stream(stream)))
+
+
+def snrt_step_dose(mesh, quad, scatter, args: StepArgs, psi_in, psi_out, coeff: float, dose,
+                   ws=None, ws_bytes=0, stream=None) -> None:
+    _check("snrt_step_dose",
+           lib().snrt_step_dose(mesh, quad, scatter, ctypes.byref(args), _ptr(psi_in),
+                                _ptr(psi_out), float(coeff), _ptr(dose), _ptr(ws), int(ws_bytes),
+                                _stream(stream)))
 
 
 def snrt_step2_limited(mesh, quad, scatter, args: StepArgs, lim: Optional[Limiter], psi_in,

@@ -175,10 +175,13 @@ class Solver:
         the dose (FP64, internal order) adds ``dose_coeff[n]`` times the density-weighted
         scalar flux of the state entering step n.  ``limiter`` and ``vk_k`` choose the slope
         limiter of the second-order scheme (``order=2``)."""
+        if fp64 and dose_coeff is not None:
+            raise ValueError("the dose accumulation runs on FP32 states")
         a = psi0.clone()
         b = torch.empty_like(a)
         if dose_coeff is not None and dose is None:
             dose = torch.zeros(self.nc, dtype=torch.float64, device=self.device)
+        fused_dose = order == 1 and not imex
         if fp64 and self.mats64 is None:
             self.mats64 = self._materials(torch.float64)
         if imex:
@@ -209,10 +212,16 @@ class Solver:
             if key not in cache:
                 cache[key] = self.args(alpha_t=key[0], alpha_s=key[1], inflow_scale=key[2],
                                        fp64=fp64)
-            if dose_coeff is not None:
-                snrt.snrt_dose_accumulate(self.mesh, self.quad, pa, self.mats32["inv_rho"],
-                                          float(dose_coeff[n]), dose, stream)
-            step(self.mesh, self.quad, self.scatter, cache[key], pa, pb, ws, ws_bytes, stream)
+            if dose_coeff is not None and fused_dose:
+                # the dose of the state entering the step, from the rows the step reads
+                snrt.snrt_step_dose(self.mesh, self.quad, self.scatter, cache[key], pa, pb,
+                                    float(dose_coeff[n]), dose, ws, ws_bytes, stream)
+            else:
+                if dose_coeff is not None:
+                    snrt.snrt_dose_accumulate(self.mesh, self.quad, pa, self.mats32["inv_rho"],
+                                              float(dose_coeff[n]), dose, stream)
+                step(self.mesh, self.quad, self.scatter, cache[key], pa, pb, ws, ws_bytes,
+                     stream)
             pa, pb = pb, pa
         return (a if pa == a.data_ptr() else b), dose
 
@@ -311,9 +320,10 @@ class SNRollout(torch.autograd.Function):
                 dst.copy_(a if pa == a.data_ptr() else b)
                 ckpts.append(dst)
             if dose is not None:
-                snrt.snrt_dose_accumulate(S.mesh, S.quad, pa, inv_rho, float(dose_coeff[n]),
-                                          dose, stream)
-            stepper(S.mesh, S.quad, S.scatter, args(n), pa, pb, ws, S.ws_bytes, stream)
+                snrt.snrt_step_dose(S.mesh, S.quad, S.scatter, args(n), pa, pb,
+                                    float(dose_coeff[n]), dose, ws, S.ws_bytes, stream)
+            else:
+                stepper(S.mesh, S.quad, S.scatter, args(n), pa, pb, ws, S.ws_bytes, stream)
             pa, pb = pb, pa
         a = a if pa == a.data_ptr() else b
         ctx.S, ctx.fp64, ctx.nsteps, ctx.K = S, fp64, nsteps, ckpt_every
