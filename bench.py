@@ -399,7 +399,7 @@ def bench_pn(steps: int, warmup: int, degree: int = 5):
     return {"workload": w["name"], "cells": nc, "moments": nm, "degree": degree,
             "steps": steps, "ms_per_step": ms, "value": nc * nm / (ms * 1e-3),
             "unit": "cell-moment updates/s", "precision": "fp32",
-            "kernel": f"k_pn_fused<{degree},{mf},float>" if degree <= 9 else
+            "kernel": f"k_pn_fused<{degree},{mf},float>" if degree <= 9 or degree == 13 else
             f"k_pn_generic<16,{mf},float>",
             "algorithmic_bytes_per_step": alg, "achieved_gbs": achieved,
             "hbm_frac": achieved / HBM_PEAK_GBS, "flops_per_step": flops,
@@ -564,6 +564,8 @@ def main():
         out["imex"] = bench_imex(min(args.steps, 200), 5)
     if not args.no_pn:
         out["pn"] = bench_pn(min(args.steps, 200), 5)
+        # the degree of the paper's CSD P_N runs (Sec. 7), same mesh and materials
+        out["pn_degree13"] = bench_pn(min(args.steps, 50), 3, degree=13)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P)
     print(json.dumps(out), flush=True)

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsnrt.so")
-SOURCES = ["snrt_api.hip", "sn_step_f32.hip", "sn_step_f64.hip", "sn_adjoint.hip",
+# the longest compile (the unrolled P_N kernel of degree 13) first, so the pool starts it early
+SOURCES = ["sn_pn13.hip", "snrt_api.hip", "sn_step_f32.hip", "sn_step_f64.hip", "sn_adjoint.hip",
            "sn_reduce.hip", "sn_gemm_simple.hip", "sn_gemm_mfma.hip", "sn_step2.hip",
            "sn_step_imex.hip", "sn_pn.hip", "snrt_pn_api.hip"]
 ARCH = os.environ.get("SNRT_OFFLOAD_ARCH", "gfx950")
@@ -24,6 +25,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # the compile-time operator tables of the larger P_N degrees (pn_pattern.h)
+          "-fconstexpr-steps=500000000",
           "-I", os.path.join(ROOT, "include")]
 
 

@@ -22,11 +22,16 @@ namespace snrt {
 namespace pn {
 
 constexpr int kMaxDegree = 30;        // largest P_N degree the library accepts
-constexpr int kMaxFusedDegree = 9;    // degrees with a fully unrolled FP32 step kernel
+constexpr int kMaxFusedDegree = 9;    // degrees 0..9 have a fully unrolled FP32 step kernel
+constexpr int kFusedHighDegree = 13;  // and degree 13 (the CSD degree of Sec. 7) as well
 constexpr int kMaxFusedDegree64 = 2;  // the same for FP64 (its accumulators take twice the
                                       // registers; larger degrees use the chunked kernel)
 template <typename T>
 constexpr int max_fused_degree() { return sizeof(T) == 4 ? kMaxFusedDegree : kMaxFusedDegree64; }
+template <typename T>
+constexpr bool has_fused_kernel(int N) {
+    return N <= max_fused_degree<T>() || (sizeof(T) == 4 && N == kFusedHighDegree);
+}
 
 constexpr int nmom(int N) { return (N + 1) * (N + 1); }
 

@@ -112,9 +112,9 @@ struct snrt_quad {
 
 // P_N system of degree N (Sec. 3.1 P_N closure, Sec. 4.3): the flux Jacobians, |A_x|,
 // |A_y| (host copies, FP64) and the step's coefficient tables on the device, one per
-// precision.  Degrees up to pn::max_fused_degree<T>() use the packed table of the unrolled
-// kernel (one value per structurally non-zero coefficient, halved, in pn::visit_ops order);
-// larger degrees the dense table [nm][nmp][4] (X, Y, P, Q coefficient of input moment m for
+// precision.  Degrees with an unrolled kernel (pn::has_fused_kernel<T>) use the packed
+// table of that kernel (one value per structurally non-zero coefficient, halved, in
+// pn::visit_ops order); the other degrees the dense table [nm][nmp][4] (X, Y, P, Q coefficient of input moment m for
 // output k, halved, nmp = nm rounded up to a multiple of 16, the chunked kernel's step).
 struct snrt_pn {
     int device = 0;
@@ -279,6 +279,9 @@ hipError_t launch_dose_density_grad(const snrt_mesh& m, const double* dose, cons
 
 // P_N step (sn_pn.hip): u_out = step(u_in) in the tiled moment layout; layout conversion
 // between the user's [ncells][nm] rows and the tiled internal layout.
+// the unrolled FP32 kernel of degree pn::kFusedHighDegree (sn_pn13.hip)
+hipError_t launch_pn_fused_high32(const snrt_mesh& m, const snrt_pn& p, const StepArgs32& a,
+                                  const float* u, float* out, hipStream_t st);
 hipError_t launch_pn32(const snrt_mesh& m, const snrt_pn& p, const StepArgs32& a, const float* u,
                        float* out, hipStream_t st);
 hipError_t launch_pn64(const snrt_mesh& m, const snrt_pn& p, const StepArgs64& a, const double* u,

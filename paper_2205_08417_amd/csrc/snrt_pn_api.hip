@@ -265,8 +265,8 @@ snrt_status snrt_pn_create(snrt_pn** out, int32_t degree, const double* sigma_l)
         }
         return tab;
     };
-    const std::vector<double> t32d = table(N <= pn::max_fused_degree<float>());
-    const std::vector<double> tab = table(N <= pn::max_fused_degree<double>());
+    const std::vector<double> t32d = table(pn::has_fused_kernel<float>(N));
+    const std::vector<double> tab = table(pn::has_fused_kernel<double>(N));
     std::vector<float> tab32(t32d.begin(), t32d.end());
     std::vector<float> sig32(p->sig.begin(), p->sig.end());
     hipError_t e = hipGetDevice(&p->device);
