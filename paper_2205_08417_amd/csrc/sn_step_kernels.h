@@ -546,6 +546,8 @@ __global__ __launch_bounds__(kStepBlock) void k_step_dose(
 
 // --------------------------------------------------------------------------- adjoint step
 
+// Adjoint for wide rows (more than 32 bytes of each row per lane, where the pipelined form
+// below would hold two stages of them in registers): one wavefront per cell.
 template <int V, bool EXACT, bool DENSE, typename T>
 __global__ __launch_bounds__(kStepBlock) void k_adjoint(
     const typename GeomOf<T>::type* __restrict__ geom, int64_t nc, int32_t mf, int32_t nq,
@@ -652,6 +654,183 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint(
     if (g_r) {
         const T s = wave_sum(part_r);
         if (lane == 0) g_r[c] += a.dt * irho * irho * s;
+    }
+}
+
+// The adjoint step in the persistent, XCD-partitioned, pipelined form of the forward
+// sweep: stage B loads the next cell's rows (own lambda and psi, each face's lambda, the
+// neighbours' 1/A, the dense G row) while stage C computes this one.  Faces are branch-free:
+// interior faces (and the zero-normal self-faces of unused slots) read the neighbour's
+// lambda with its 1/A, boundary faces the cell's own row with weight 0; a Neumann boundary
+// face passes both flux signs (its ghost is the cell's own value).
+template <int V, int MF, bool DENSE, typename T>
+struct AdjStage {
+    T l[V], p[V];
+    T ln[MF][V];
+    T g[DENSE ? V : 1];
+    T ia_n[MF], nx[MF], ny[MF];
+    bool all_signs[MF];
+    T ia, irho, keep, cscat;
+};
+
+template <typename T>
+struct AdjCtx {
+    __amdgpu_buffer_rsrc_t lam, psi, out, G;
+    uint32_t row_bytes;
+    bool neumann;
+};
+
+template <int V, bool EXACT, int MF, bool DENSE, typename T>
+__device__ __forceinline__ void adj_load_stage(AdjStage<V, MF, DENSE, T>& d,
+                                               const NbrList<MF>& nb,
+                                               const typename GeomOf<T>::type* __restrict__ geom,
+                                               int32_t c, int32_t nq, int q0,
+                                               const typename ArgsOf<T>::type& a,
+                                               const AdjCtx<T>& x)
+{
+    const auto* g = cell_rec(geom, c);
+    const uint32_t own = (uint32_t)c * x.row_bytes;
+    buf_load_row<V, EXACT, T>(x.lam, own, q0, nq, d.l);
+    buf_load_row<V, EXACT, T>(x.psi, own, q0, nq, d.p);
+#pragma unroll
+    for (int f = 0; f < MF; ++f) {
+        const int32_t j = nb.j[f];
+        const bool interior = j >= 0;
+        const int32_t src = uniform_cell(interior ? j : c);
+        buf_load_row<V, EXACT, T>(x.lam, (uint32_t)src * x.row_bytes, q0, nq, d.ln[f]);
+        d.ia_n[f] = interior ? cell_rec(geom, src)->inv_area : T(0);
+        d.all_signs[f] = !interior && x.neumann;
+        d.nx[f] = g->n[f][0];
+        d.ny[f] = g->n[f][1];
+    }
+    if constexpr (DENSE) buf_load_row<V, EXACT, T>(x.G, own, q0, nq, d.g);
+    d.ia = g->inv_area;
+    d.irho = a.inv_rho ? cell_val(a.inv_rho, c) : T(1);
+    d.keep = T(1) - a.dt * a.alpha_t * cell_val(a.sigma_t, c);
+    d.cscat = a.dt * a.alpha_s * cell_val(a.sigma_s, c);
+}
+
+template <int V, bool EXACT, int MF, bool DENSE, typename T>
+__device__ __forceinline__ void adj_compute(const AdjStage<V, MF, DENSE, T>& d, const T (&ox)[V],
+                                            const T (&oy)[V], const T (&wi)[V], int32_t c,
+                                            int32_t nq, int q0, int lane,
+                                            const typename ArgsOf<T>::type& a,
+                                            const AdjCtx<T>& x, T* __restrict__ g_t,
+                                            T* __restrict__ g_s, T* __restrict__ g_r)
+{
+    T xs[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) xs[j] = T(0);
+#pragma unroll
+    for (int f = 0; f < MF; ++f) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const T s = ox[j] * d.nx[f] + oy[j] * d.ny[f];
+            const T dd = d.l[j] * d.ia - d.ln[f][j] * d.ia_n[f];
+            xs[j] += (s > T(0) || d.all_signs[f]) ? s * dd : T(0);
+        }
+    }
+    const T cstream = a.dt * d.irho;
+    T src[V];
+    T part_s;                                     // per-lane part of sum_q l_q S_q
+    if constexpr (DENSE) {
+        part_s = T(0);
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            src[j] = d.g[j];                      // (Lambda B^T)_cq
+            part_s += d.p[j] * src[j];
+        }
+    } else {
+        T pl = T(0), pw = T(0);
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            pl += d.l[j];
+            pw += wi[j] * d.p[j];
+        }
+        const T lsum = wave_sum(pl);
+        const T scell = wave_sum(pw);             // isotropic S of the cell
+#pragma unroll
+        for (int j = 0; j < V; ++j) src[j] = wi[j] * lsum;
+        part_s = (lane == 0) ? scell * lsum : T(0);
+    }
+    T o[V];
+    T part_t = T(0), part_r = T(0);
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        o[j] = d.l[j] * d.keep - cstream * xs[j] + d.cscat * src[j];
+        part_t += d.l[j] * d.p[j];
+        part_r += d.p[j] * xs[j];
+    }
+    buf_store_row<V, EXACT, T, kAuxStream>(x.out, (uint32_t)c * x.row_bytes, q0, nq, o);
+    if (g_t) {
+        const T s = wave_sum(part_t);
+        if (lane == 0) g_t[c] += -a.dt * a.alpha_t * s;
+    }
+    if (g_s) {
+        const T s = wave_sum(part_s);
+        if (lane == 0) g_s[c] += a.dt * a.alpha_s * s;
+    }
+    if (g_r) {
+        const T s = wave_sum(part_r);
+        if (lane == 0) g_r[c] += a.dt * d.irho * d.irho * s;
+    }
+}
+
+template <int V, bool EXACT, int MF, bool DENSE, typename T>
+__global__ __launch_bounds__(kStepBlock) void k_adjoint_p(
+    const typename GeomOf<T>::type* __restrict__ geom, int64_t nc, int32_t nq,
+    const T* __restrict__ tab, typename ArgsOf<T>::type a, const T* __restrict__ psi_n,
+    const T* __restrict__ lam_np1, T* __restrict__ lam_n, T* __restrict__ g_t,
+    T* __restrict__ g_s, T* __restrict__ g_r, const T* __restrict__ G, int64_t items_per_xcd)
+{
+    const int x = blockIdx.x % kNumXcd;
+    const int kx = blockIdx.x / kNumXcd;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t stride = (int32_t)(gridDim.x / kNumXcd) * kCellsPerBlock;
+    const int64_t xb = x * items_per_xcd;
+    if (xb >= nc) return;
+    const int32_t xend = (int32_t)(xb + items_per_xcd < nc ? xb + items_per_xcd : nc);
+    int32_t c = (int32_t)xb + kx * kCellsPerBlock + wave;
+    if (c >= xend) return;
+    const int q0 = lane * V;
+
+    AdjCtx<T> cx;
+    cx.row_bytes = (uint32_t)nq * sizeof(T);
+    const uint32_t state_bytes = (uint32_t)nc * cx.row_bytes;
+    cx.lam = make_rsrc(lam_np1, state_bytes);
+    cx.psi = make_rsrc(psi_n, state_bytes);
+    cx.out = make_rsrc(lam_n, state_bytes);
+    cx.G = make_rsrc(DENSE ? G : lam_np1, DENSE ? state_bytes : 0u);
+    cx.neumann = a.neumann != 0;
+    // prefetches address the clamped cell min(c', xend-1): always in bounds
+    auto clampc = [xend](int32_t cc) { return uniform_cell(cc < xend ? cc : xend - 1); };
+
+    T ox[V], oy[V], wi[V];
+    load_slice<V, EXACT>(tab, q0, nq, ox);
+    load_slice<V, EXACT>(tab + nq, q0, nq, oy);
+    load_slice<V, EXACT>(tab + 3 * nq, q0, nq, wi);
+
+    NbrList<MF> n0, n1, n2;
+    AdjStage<V, MF, DENSE, T> sa, sb;
+    fwd_load_nbr<MF, T>(n0, geom, clampc(c));
+    adj_load_stage<V, EXACT, MF, DENSE>(sa, n0, geom, clampc(c), nq, q0, a, cx);
+    fwd_load_nbr<MF, T>(n1, geom, clampc(c + stride));
+    for (;;) {
+        adj_load_stage<V, EXACT, MF, DENSE>(sb, n1, geom, clampc(c + stride), nq, q0, a, cx);
+        fwd_load_nbr<MF, T>(n2, geom, clampc(c + 2 * stride));
+        adj_compute<V, EXACT, MF, DENSE>(sa, ox, oy, wi, clampc(c), nq, q0, lane, a, cx, g_t,
+                                         g_s, g_r);
+        c += stride;
+        if (c >= xend) break;
+        n1 = n2;
+        adj_load_stage<V, EXACT, MF, DENSE>(sa, n1, geom, clampc(c + stride), nq, q0, a, cx);
+        fwd_load_nbr<MF, T>(n2, geom, clampc(c + 2 * stride));
+        adj_compute<V, EXACT, MF, DENSE>(sb, ox, oy, wi, clampc(c), nq, q0, lane, a, cx, g_t,
+                                         g_s, g_r);
+        c += stride;
+        if (c >= xend) break;
+        n1 = n2;
     }
 }
 
@@ -798,10 +977,6 @@ hipError_t launch_step_t(const typename GeomOf<T>::type* geom, const snrt_mesh& 
     });
 }
 
-inline unsigned step_blocks(int64_t nc) {
-    return (unsigned)((nc + kCellsPerBlock - 1) / kCellsPerBlock);
-}
-
 template <typename T>
 hipError_t launch_adjoint_t(const typename GeomOf<T>::type* geom, const snrt_mesh& m,
                             const T* tab, int32_t nq, const typename ArgsOf<T>::type& a,
@@ -812,15 +987,33 @@ hipError_t launch_adjoint_t(const typename GeomOf<T>::type* geom, const snrt_mes
     return dispatch_v<T>(nq, [&](auto vc, auto ex) {
         constexpr int V = decltype(vc)::value;
         constexpr bool E = decltype(ex)::value;
-        if (G)
-            hipLaunchKernelGGL((k_adjoint<V, E, true, T>), dim3(step_blocks(m.nc)),
-                               dim3(kStepBlock), 0, st, geom, m.nc, m.mf, nq, tab, a, psi_n,
-                               lam_np1, lam_n, g_t, g_s, g_r, G);
-        else
-            hipLaunchKernelGGL((k_adjoint<V, E, false, T>), dim3(step_blocks(m.nc)),
-                               dim3(kStepBlock), 0, st, geom, m.nc, m.mf, nq, tab, a, psi_n,
-                               lam_np1, lam_n, g_t, g_s, g_r, G);
-        return hipGetLastError();
+        if constexpr (V * sizeof(T) > 32) {
+            const unsigned blocks = (unsigned)((m.nc + kCellsPerBlock - 1) / kCellsPerBlock);
+            if (G)
+                hipLaunchKernelGGL((k_adjoint<V, E, true, T>), dim3(blocks), dim3(kStepBlock), 0,
+                                   st, geom, m.nc, m.mf, nq, tab, a, psi_n, lam_np1, lam_n, g_t,
+                                   g_s, g_r, G);
+            else
+                hipLaunchKernelGGL((k_adjoint<V, E, false, T>), dim3(blocks), dim3(kStepBlock),
+                                   0, st, geom, m.nc, m.mf, nq, tab, a, psi_n, lam_np1, lam_n,
+                                   g_t, g_s, g_r, G);
+            return hipGetLastError();
+        } else {
+            auto go = [&](auto mfc, auto dc) {
+                constexpr int MF = decltype(mfc)::value;
+                constexpr bool D = decltype(dc)::value;
+                static const int occ = resident_blocks(k_adjoint_p<V, E, MF, D, T>);
+                const StepShape sh = step_shape(m, m.nc, 1, occ, tune().adjoint_blocks_per_cu);
+                hipLaunchKernelGGL((k_adjoint_p<V, E, MF, D, T>), dim3(sh.blocks),
+                                   dim3(kStepBlock), 0, st, geom, m.nc, nq, tab, a, psi_n,
+                                   lam_np1, lam_n, g_t, g_s, g_r, G, sh.cells_per_xcd);
+                return hipGetLastError();
+            };
+            using I3 = std::integral_constant<int, 3>;
+            using I4 = std::integral_constant<int, 4>;
+            if (m.mf == 4) return G ? go(I4{}, std::true_type{}) : go(I4{}, std::false_type{});
+            return G ? go(I3{}, std::true_type{}) : go(I3{}, std::false_type{});
+        }
     });
 }
 

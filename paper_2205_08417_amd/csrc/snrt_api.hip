@@ -43,10 +43,11 @@ const Tune& tune() {
     static const Tune t = [] {
         Tune r;
         if (const char* e = std::getenv("SNRT_STEP_TUNE")) {
-            int bpc = 0, bpc2 = 0;
-            const int n = std::sscanf(e, "%d,%d", &bpc, &bpc2);
+            int bpc = 0, bpc2 = 0, bpc3 = 0;
+            const int n = std::sscanf(e, "%d,%d,%d", &bpc, &bpc2, &bpc3);
             if (n >= 1 && bpc >= 1 && bpc <= 64) r.step_blocks_per_cu = bpc;
-            if (n == 2 && bpc2 >= 1 && bpc2 <= 64) r.flux2_blocks_per_cu = bpc2;
+            if (n >= 2 && bpc2 >= 1 && bpc2 <= 64) r.flux2_blocks_per_cu = bpc2;
+            if (n >= 3 && bpc3 >= 1 && bpc3 <= 64) r.adjoint_blocks_per_cu = bpc3;
         }
         if (const char* e = std::getenv("SNRT_GEMM_STAGGER")) r.gemm_stagger = std::atoi(e) != 0;
         return r;

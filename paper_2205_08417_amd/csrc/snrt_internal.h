@@ -143,6 +143,7 @@ namespace snrt {
 struct Tune {
     int step_blocks_per_cu = 3;
     int flux2_blocks_per_cu = 2;   // its larger per-cell footprint favours a narrower sweep
+    int adjoint_blocks_per_cu = 7; // the adjoint's smaller workloads favour a wide grid
     bool gemm_stagger = true;      // staggered split/product phases in the BF16 product
 };
 const Tune& tune();
