@@ -671,6 +671,7 @@ struct AdjStage {
     T ia_n[MF], nx[MF], ny[MF];
     bool all_signs[MF];
     T ia, irho, keep, cscat;
+    T gt0, gs0, gr0;                // the gradient accumulators' values before this step
 };
 
 template <typename T>
@@ -678,6 +679,7 @@ struct AdjCtx {
     __amdgpu_buffer_rsrc_t lam, psi, out, G;
     uint32_t row_bytes;
     bool neumann;
+    T *g_t, *g_s, *g_r;
 };
 
 template <int V, bool EXACT, int MF, bool DENSE, typename T>
@@ -708,6 +710,11 @@ __device__ __forceinline__ void adj_load_stage(AdjStage<V, MF, DENSE, T>& d,
     d.irho = a.inv_rho ? cell_val(a.inv_rho, c) : T(1);
     d.keep = T(1) - a.dt * a.alpha_t * cell_val(a.sigma_t, c);
     d.cscat = a.dt * a.alpha_s * cell_val(a.sigma_s, c);
+    // each cell's accumulators are updated once per launch (by this wavefront), so their
+    // old values can be fetched a stage ahead instead of stalling the update on the load
+    d.gt0 = x.g_t ? cell_val(x.g_t, c) : T(0);
+    d.gs0 = x.g_s ? cell_val(x.g_s, c) : T(0);
+    d.gr0 = x.g_r ? cell_val(x.g_r, c) : T(0);
 }
 
 template <int V, bool EXACT, int MF, bool DENSE, typename T>
@@ -715,8 +722,7 @@ __device__ __forceinline__ void adj_compute(const AdjStage<V, MF, DENSE, T>& d, 
                                             const T (&oy)[V], const T (&wi)[V], int32_t c,
                                             int32_t nq, int q0, int lane,
                                             const typename ArgsOf<T>::type& a,
-                                            const AdjCtx<T>& x, T* __restrict__ g_t,
-                                            T* __restrict__ g_s, T* __restrict__ g_r)
+                                            const AdjCtx<T>& x)
 {
     T xs[V];
 #pragma unroll
@@ -747,8 +753,8 @@ __device__ __forceinline__ void adj_compute(const AdjStage<V, MF, DENSE, T>& d, 
             pl += d.l[j];
             pw += wi[j] * d.p[j];
         }
-        const T lsum = wave_sum(pl);
-        const T scell = wave_sum(pw);             // isotropic S of the cell
+        const T lsum = cell_sum(pl);
+        const T scell = cell_sum(pw);             // isotropic S of the cell
 #pragma unroll
         for (int j = 0; j < V; ++j) src[j] = wi[j] * lsum;
         part_s = (lane == 0) ? scell * lsum : T(0);
@@ -762,17 +768,17 @@ __device__ __forceinline__ void adj_compute(const AdjStage<V, MF, DENSE, T>& d, 
         part_r += d.p[j] * xs[j];
     }
     buf_store_row<V, EXACT, T, kAuxStream>(x.out, (uint32_t)c * x.row_bytes, q0, nq, o);
-    if (g_t) {
-        const T s = wave_sum(part_t);
-        if (lane == 0) g_t[c] += -a.dt * a.alpha_t * s;
+    if (x.g_t) {
+        const T s = cell_sum(part_t);
+        if (lane == 0) x.g_t[c] = d.gt0 + -a.dt * a.alpha_t * s;
     }
-    if (g_s) {
-        const T s = wave_sum(part_s);
-        if (lane == 0) g_s[c] += a.dt * a.alpha_s * s;
+    if (x.g_s) {
+        const T s = cell_sum(part_s);
+        if (lane == 0) x.g_s[c] = d.gs0 + a.dt * a.alpha_s * s;
     }
-    if (g_r) {
-        const T s = wave_sum(part_r);
-        if (lane == 0) g_r[c] += a.dt * d.irho * d.irho * s;
+    if (x.g_r) {
+        const T s = cell_sum(part_r);
+        if (lane == 0) x.g_r[c] = d.gr0 + a.dt * d.irho * d.irho * s;
     }
 }
 
@@ -803,6 +809,9 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint_p(
     cx.out = make_rsrc(lam_n, state_bytes);
     cx.G = make_rsrc(DENSE ? G : lam_np1, DENSE ? state_bytes : 0u);
     cx.neumann = a.neumann != 0;
+    cx.g_t = g_t;
+    cx.g_s = g_s;
+    cx.g_r = g_r;
     // prefetches address the clamped cell min(c', xend-1): always in bounds
     auto clampc = [xend](int32_t cc) { return uniform_cell(cc < xend ? cc : xend - 1); };
 
@@ -819,15 +828,13 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint_p(
     for (;;) {
         adj_load_stage<V, EXACT, MF, DENSE>(sb, n1, geom, clampc(c + stride), nq, q0, a, cx);
         fwd_load_nbr<MF, T>(n2, geom, clampc(c + 2 * stride));
-        adj_compute<V, EXACT, MF, DENSE>(sa, ox, oy, wi, clampc(c), nq, q0, lane, a, cx, g_t,
-                                         g_s, g_r);
+        adj_compute<V, EXACT, MF, DENSE>(sa, ox, oy, wi, clampc(c), nq, q0, lane, a, cx);
         c += stride;
         if (c >= xend) break;
         n1 = n2;
         adj_load_stage<V, EXACT, MF, DENSE>(sa, n1, geom, clampc(c + stride), nq, q0, a, cx);
         fwd_load_nbr<MF, T>(n2, geom, clampc(c + 2 * stride));
-        adj_compute<V, EXACT, MF, DENSE>(sb, ox, oy, wi, clampc(c), nq, q0, lane, a, cx, g_t,
-                                         g_s, g_r);
+        adj_compute<V, EXACT, MF, DENSE>(sb, ox, oy, wi, clampc(c), nq, q0, lane, a, cx);
         c += stride;
         if (c >= xend) break;
         n1 = n2;

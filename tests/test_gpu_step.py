@@ -274,6 +274,18 @@ def test_empty_mesh():
     out = torch.full((1,), 7.0, dtype=torch.float64, device="cuda")
     snrt.snrt_mass(mesh, quad, e, out)
     assert out.item() == 0.0
+    # every other step kind is a no-op on zero cells as well
+    ed = torch.empty(0, dtype=torch.float64, device="cuda")
+    snrt.snrt_step_dose(mesh, quad, sc, args, e, e, 0.5, ed)
+    snrt.snrt_dose_accumulate(mesh, quad, e, None, 0.5, ed)
+    snrt.snrt_step_imex(mesh, quad, sc, args, e, e)
+    snrt.snrt_step_adjoint(mesh, quad, sc, args, e, e, e, e, e, None)
+    snrt.snrt_step2_limited(mesh, quad, sc, args, snrt.limiter("venkatakrishnan", 0.5), e, e)
+    pn = snrt.snrt_pn_create(3)
+    assert snrt.snrt_pn_state_elems(mesh, pn) == 0
+    snrt.snrt_pn_step(mesh, pn, args, e, e)
+    snrt.snrt_pn_destroy(pn)
+    torch.cuda.synchronize()
     for fn, h in ((snrt.snrt_scatter_destroy, sc), (snrt.snrt_quad_destroy, quad),
                   (snrt.snrt_mesh_destroy, mesh)):
         fn(h)
