@@ -52,7 +52,7 @@ typedef enum {
     SNRT_E_ARG = -1,          /* null / out-of-range argument */
     SNRT_E_SHAPE = -2,        /* sizes disagree between handles or with the arrays */
     SNRT_E_ALIAS = -3,        /* an output aliases an input */
-    SNRT_E_UNSUPPORTED = -4,  /* valid request this build does not implement */
+    SNRT_E_UNSUPPORTED = -4,  /* valid request the library does not implement */
     SNRT_E_HIP = -5,          /* HIP runtime error (text in snrt_last_error) */
     SNRT_E_OOM = -6,          /* device allocation failed */
     SNRT_E_NONFINITE = -7     /* NaN/Inf in a scalar argument */

@@ -1,7 +1,7 @@
 """FP64 CPU oracle of the explicit S_N step (and of the P_N step in ``oracle.pn``) -- TEST
 INFRASTRUCTURE.
 
-Only ``tests/``, the graft entry point's ``smoke()`` and the ``cpu_baseline`` leg of
+Only ``tests/``, ``smoke()`` in ``__graft_entry__.py`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The product path (``paper_2205_08417_amd``) never
 imports, links or calls it, and the oracle never imports the product: the two share only
 the seeded input generators, which hold none of the method's arithmetic.

@@ -2,7 +2,7 @@
  * sn_oracle.c -- plain FP64 CPU reference of the explicit S_N step.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links or calls this file: it is
- * used by tests/, by the smoke check of the graft entry point and by the CPU-baseline leg of
+ * used by tests/, by smoke() in __graft_entry__.py and by the CPU-baseline leg of
  * bench.py.  It shares no code, header or constant with the HIP library.
  *
  * What it computes (KiT-RT, arXiv 2205.08417):
