@@ -150,11 +150,27 @@ def bench_dense(steps, warmup: int):
     final = product_rate(S, state[0])
     dense = product_rate(S, torch.rand_like(state[0]))
     S.close()
+    # the same step with the FP32 scattering product (vector FMA kernel), 20 steps from the
+    # initial state: the FP32 side of the FP32-vs-mixed comparison
+    S32 = Solver(P, precision="fp32")
+    args32 = S32.args()
+    st32 = [S32.initial_state(), None]
+    st32[1] = torch.empty_like(st32[0])
+
+    def step32():
+        S32.step(st32[0], st32[1], args32)
+        st32.reverse()
+
+    step32()
+    torch.cuda.synchronize()
+    ms_fp32 = timed(step32, 20, stream)
+    S32.close()
     return {"workload": DENSE_WORKLOAD, "cells": P.ncells, "ordinates": P.nq,
             "scattering": "Henyey-Greenstein g=0.9, dense, column-normalised",
             "precision": "bf16x3 (hi+lo split, FP32 accumulate)", "steps": nsteps,
             "value": P.ncells * P.nq / (ms_step * 1e-3), "unit": "cell-ordinate updates/s",
             "ms_per_step": ms_step,
+            "fp32_product_ms_per_step": ms_fp32,
             "scatter_product": final, "scatter_product_dense_random_state": dense}
 
 
