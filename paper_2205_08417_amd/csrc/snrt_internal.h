@@ -137,9 +137,10 @@ struct snrt_scatter {
 
 namespace snrt {
 
-// Launch-shape knobs of the persistent kernels.  Defaults are the tuned values for MI355X;
-// SNRT_STEP_TUNE="<blocks per CU>[,<blocks per CU of the second-order update>]" overrides
-// them (read once per process).
+// Launch-shape knobs of the persistent kernels and the BF16 product.  Defaults are the tuned
+// values for MI355X.  SNRT_STEP_TUNE="<step>[,<second-order update>[,<adjoint>]]" overrides
+// the blocks per CU of the three persistent sweeps, SNRT_GEMM_STAGGER=0 turns the staggered
+// chunk order of the product off (both read once per process).
 struct Tune {
     int step_blocks_per_cu = 3;
     int flux2_blocks_per_cu = 2;   // its larger per-cell footprint favours a narrower sweep
