@@ -33,6 +33,7 @@ METRIC = "cell-ordinate updates/s per S_N step (FP32 vs mixed) + adjoint/forward
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, vendor figure
 BF16_PEAK_TFLOPS = 2500.0       # MI355X dense BF16 MFMA, vendor figure
 FP32_VECTOR_PEAK_TFLOPS = 157.3 # MI355X FP32 vector, vendor figure
+FP32_MFMA_PEAK_TFLOPS = 157.3   # MI355X dense FP32 MFMA, vendor figure
 DENSE_WORKLOAD = "linesource_hg_s32"
 WORKLOAD = "checkerboard_s16"
 STEP_SOURCES = [os.path.join(ROOT, "paper_2205_08417_amd", "csrc", f)
@@ -105,18 +106,21 @@ def timed(fn, n, stream):
     return start.elapsed_time(end) / n
 
 
-def product_rate(S, psi, reps: int = 10):
-    """Executed TFLOP/s of the BF16 hi+lo scattering product (three products) on state psi."""
+def product_rate(S, psi, reps: int = 10, passes: int = 3, kernel: str = "k_gemm_bf16",
+                 peak: float = None):
+    """Executed TFLOP/s of the scattering product on state psi: the BF16 hi+lo product
+    (three passes, against the BF16 MFMA peak) or the FP32 one (one pass, FP32 MFMA peak)."""
     import torch
     from paper_2205_08417_amd import snrt
+    peak = BF16_PEAK_TFLOPS if peak is None else peak
     sbuf = torch.empty_like(psi)
     stream = torch.cuda.current_stream()
     snrt.snrt_scatter_apply(S.mesh, S.quad, S.scatter, psi, sbuf)
     torch.cuda.synchronize()
     ms = timed(lambda: snrt.snrt_scatter_apply(S.mesh, S.quad, S.scatter, psi, sbuf), reps, stream)
-    tflops = 3 * 2.0 * S.nc * S.nq * S.nq / (ms * 1e-3) / 1e12
-    return {"kernel": "k_gemm_bf16", "ms": ms, "executed_tflops": tflops,
-            "peak_tflops": BF16_PEAK_TFLOPS, "mfma_utilization": tflops / BF16_PEAK_TFLOPS}
+    tflops = passes * 2.0 * S.nc * S.nq * S.nq / (ms * 1e-3) / 1e12
+    return {"kernel": kernel, "ms": ms, "executed_tflops": tflops,
+            "peak_tflops": peak, "mfma_utilization": tflops / peak}
 
 
 def bench_dense(steps, warmup: int):
@@ -164,13 +168,15 @@ def bench_dense(steps, warmup: int):
     step32()
     torch.cuda.synchronize()
     ms_fp32 = timed(step32, 20, stream)
+    fp32_product = product_rate(S32, st32[0], passes=1, kernel="k_gemm_f32",
+                                peak=FP32_MFMA_PEAK_TFLOPS)
     S32.close()
     return {"workload": DENSE_WORKLOAD, "cells": P.ncells, "ordinates": P.nq,
             "scattering": "Henyey-Greenstein g=0.9, dense, column-normalised",
             "precision": "bf16x3 (hi+lo split, FP32 accumulate)", "steps": nsteps,
             "value": P.ncells * P.nq / (ms_step * 1e-3), "unit": "cell-ordinate updates/s",
             "ms_per_step": ms_step,
-            "fp32_product_ms_per_step": ms_fp32,
+            "fp32_product_ms_per_step": ms_fp32, "fp32_scatter_product": fp32_product,
             "scatter_product": final, "scatter_product_dense_random_state": dense}
 
 

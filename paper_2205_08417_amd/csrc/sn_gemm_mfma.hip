@@ -282,6 +282,176 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict_
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// FP32 product on the matrix cores (v_mfma_f32_32x32x2_f32): the FP32 precision mode.  Same
+// block structure as the BF16 kernel (8 waves as 2 x 4, 32 x 32 MFMA tiles, K in chunks of
+// 32 through two LDS stages), with FP32 planes [rows][32] and no operand split.  One MFMA
+// takes two k values per row (lanes 0-31 and 32-63); lane half h carries k = 16h + s at
+// step s, so each lane's 16 k values of a chunk are contiguous and one 16-byte LDS read feeds
+// four steps (the accumulation order differs from a sequential k sum only by rounding).
+// Planes store the 16-byte granule g of row r at position g ^ ((r >> 1) & 7): 16
+// consecutive rows then cover the 256 bytes of LDS banks once.
+__device__ __forceinline__ int swz8(int r, int g) { return g ^ ((r >> 1) & 7); }
+
+typedef float f32x16v __attribute__((ext_vector_type(16)));
+
+template <int BM, int BN, int FD>
+__device__ __forceinline__ void gemm_block_f32(const float* __restrict__ A,
+                                               const float* __restrict__ Bt,
+                                               float* __restrict__ C, int64_t M, int32_t K,
+                                               int32_t N, int64_t lb, float* lds)
+{
+    static_assert(BM == 64 || BM == 128 || BM == 256, "block rows");
+    static_assert(BN == 128 || BN == 256, "block columns");
+    constexpr int IM = BM / 64, JN = BN / 128;
+    constexpr int AV = BM / 64;                 // A float4 per thread per chunk
+    constexpr int BVf = BN / 64;                // B float4 per thread per chunk
+    constexpr int kPlaneF = 256 * BK;           // floats of one plane (32 KB)
+
+    const int nN = N / BN;
+    const int64_t m0 = (lb / nN) * BM;
+    const int n0 = (int)(lb % nN) * BN;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = (wave >> 2) * (BM / 2);
+    const int wn = (wave & 3) * (BN / 4);
+    const int nk = K / BK;
+
+    const uint32_t a_bytes = (uint32_t)((M - m0 < BM ? M - m0 : BM) * (int64_t)K * 4);
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(A + m0 * K), 0, (int32_t)a_bytes, kRsrcWord3);
+
+    f32x4 ga[FD][AV], gb[FD][BVf];
+    auto fetch = [&](int kc, int slot) {
+#pragma unroll
+        for (int e = 0; e < AV; ++e) {
+            const int p = tid + e * kThreads;
+            const int r = p >> 3, g = p & 7;
+            i32x4 v = __builtin_amdgcn_raw_buffer_load_b128(
+                ra, (uint32_t)((r * K + kc * BK + g * 4) * 4), 0, 0);
+            ga[slot][e] = __builtin_bit_cast(f32x4, v);
+        }
+        const size_t tile = ((size_t)kc * N + n0) * BK;
+#pragma unroll
+        for (int e = 0; e < BVf; ++e) {
+            const int p = tid + e * kThreads;
+            gb[slot][e] = *reinterpret_cast<const f32x4*>(Bt + tile + (size_t)p * 4);
+        }
+    };
+    auto stash = [&](int s, int slot) {
+        float* Ap = lds + (s * 2 + 0) * kPlaneF;
+        float* Bp = lds + (s * 2 + 1) * kPlaneF;
+#pragma unroll
+        for (int e = 0; e < AV; ++e) {
+            const int p = tid + e * kThreads;
+            const int r = p >> 3, g = p & 7;
+            *reinterpret_cast<f32x4*>(&Ap[r * BK + swz8(r, g) * 4]) = ga[slot][e];
+        }
+#pragma unroll
+        for (int e = 0; e < BVf; ++e) {
+            const int p = tid + e * kThreads;    // X is stored in the plane's order
+            *reinterpret_cast<f32x4*>(&Bp[p * 4]) = gb[slot][e];
+        }
+    };
+
+    f32x16v acc[IM][JN];
+#pragma unroll
+    for (int i = 0; i < IM; ++i)
+#pragma unroll
+        for (int j = 0; j < JN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    const int fr = lane & 31, half = lane >> 5;
+    fetch(0, 0);
+    stash(0, 0);
+#pragma unroll
+    for (int d = 1; d <= FD; ++d)
+        if (d < nk) fetch(d, d % FD);
+    for (int kb = 0; kb < nk; kb += FD) {
+#pragma unroll
+        for (int u = 0; u < FD; ++u) {
+            const int kc = kb + u;
+            if (kc >= nk) break;
+            const int s = kc & 1;
+            __syncthreads();             // chunk kc staged; the idle stage is free again
+            if (kc + 1 < nk) stash(s ^ 1, (u + 1) % FD);
+            if (kc + 1 + FD < nk) fetch(kc + 1 + FD, (u + 1) % FD);
+            const float* Ap = lds + (s * 2 + 0) * kPlaneF;
+            const float* Bp = lds + (s * 2 + 1) * kPlaneF;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int g = 4 * half + t;      // this lane's k = 16 half + 4 t + [0, 4)
+                f32x4 a[IM], b[JN];
+#pragma unroll
+                for (int i = 0; i < IM; ++i) {
+                    const int r = wm + i * 32 + fr;
+                    a[i] = *reinterpret_cast<const f32x4*>(&Ap[r * BK + swz8(r, g) * 4]);
+                }
+#pragma unroll
+                for (int j = 0; j < JN; ++j) {
+                    const int n = wn + j * 32 + fr;
+                    b[j] = *reinterpret_cast<const f32x4*>(&Bp[n * BK + swz8(n, g) * 4]);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int i = 0; i < IM; ++i)
+#pragma unroll
+                        for (int j = 0; j < JN; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][q], b[j][q],
+                                                                             acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+
+#pragma unroll
+    for (int i = 0; i < IM; ++i)
+#pragma unroll
+        for (int j = 0; j < JN; ++j) {
+            const int col = n0 + wn + j * 32 + fr;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = m0 + wm + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                if (row < M) __builtin_nontemporal_store(acc[i][j][r], &C[row * N + col]);
+            }
+        }
+}
+
+template <int MBN, int TM, int TN, int TFD>
+__global__ __launch_bounds__(kThreads) void k_gemm_f32(const float* __restrict__ A,
+                                                       const float* __restrict__ Bt,
+                                                       float* __restrict__ C, int64_t M1,
+                                                       int64_t M, int32_t K, int32_t N,
+                                                       int64_t nmain)
+{
+    __shared__ __attribute__((aligned(16))) float lds[2 * 2 * 256 * BK];
+    const int64_t b = blockIdx.x;
+    if (b < nmain) {
+        gemm_block_f32<256, MBN, MBN == 256 ? 1 : 2>(A, Bt, C, M1, K, N, xcd_remap(b, nmain),
+                                                     lds);
+    } else {
+        const int64_t nt = (int64_t)gridDim.x - nmain;
+        gemm_block_f32<TM, TN, TFD>(A + M1 * K, Bt, C + M1 * N, M - M1, K, N,
+                                    xcd_remap(b - nmain, nt), lds);
+    }
+}
+
+// X [K][N] FP32 in the FP32 plane order: the 128-byte row (kc, n) holds X[kc*32 + k][n],
+// k = 0..31, as eight 16-byte granules with granule g at position g ^ ((n >> 1) & 7).
+__global__ __launch_bounds__(256) void k_tile_f32(const float* __restrict__ B,
+                                                  float* __restrict__ out, int32_t K, int32_t N)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)K * N) return;
+    const int pos = (int)(i % BK);
+    const int64_t t = i / BK;
+    const int n = (int)(t % N);
+    const int kc = (int)(t / N);
+    const int k = swz8(n, pos >> 2) * 4 + (pos & 3);
+    out[i] = B[(int64_t)(kc * BK + k) * N + n];
+}
+
 // Tiled halves of X [K][N] in the LDS plane order: the 64-byte row (kc, n) holds
 // X[kc*32 + kk][n], kk = 0..31, as four 16-byte granules with granule g at position
 // g ^ ((n >> 2) & 3); hi = bf16(X), lo = bf16(X - hi).
@@ -302,6 +472,15 @@ __global__ __launch_bounds__(256) void k_split(const float* __restrict__ B, uint
 }
 
 }  // namespace
+
+hipError_t launch_tile_f32(const float* B, float* out, int32_t K, int32_t N, hipStream_t st) {
+    if (K % BK != 0 || N % 128 != 0) return hipErrorNotSupported;
+    const int64_t n = (int64_t)K * N;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, B, out,
+                       K, N);
+    return hipGetLastError();
+}
 
 hipError_t launch_split_bf16(const float* B, uint16_t* hi, uint16_t* lo, int32_t K, int32_t N,
                              hipStream_t st) {
@@ -376,6 +555,38 @@ hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t*
     if (quarter)
         return launch_split<256, 64, 256>(A, Bhi, Blo, C, rows1, M, K, N, three_products, st);
     return launch_split<256, 64, 256>(A, Bhi, Blo, C, M, M, K, N, three_products, st);
+}
+
+template <int MBN, int TM, int TN>
+hipError_t launch_f32_split(const float* A, const float* Bt, float* C, int64_t M1, int64_t M,
+                            int32_t K, int32_t N, hipStream_t st) {
+    const int64_t nmain = ((M1 + 255) / 256) * (N / MBN);
+    const int64_t ntail = ((M - M1 + TM - 1) / TM) * (N / TN);
+    hipLaunchKernelGGL((k_gemm_f32<MBN, TM, TN, 4>), dim3((unsigned)(nmain + ntail)),
+                       dim3(kThreads), 0, st, A, Bt, C, M1, M, K, N, nmain);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_f32mfma(const float* A, const float* Bt, float* C, int64_t M, int32_t K,
+                               int32_t N, hipStream_t st) {
+    if (M == 0) return hipSuccess;
+    if (K % BK != 0 || N % 128 != 0 || K == 0) return hipErrorNotSupported;
+    // the same block shapes and last-round policy as the BF16 product
+    const bool wide = N % 256 == 0;
+    const int64_t nN = wide ? N / 256 : N / 128;
+    const int64_t tiles = ((M + 255) / 256) * nN;
+    const int64_t cu = device_cu_count();
+    const int64_t rem = tiles % cu;
+    const bool level = tiles > cu && rem != 0 && cu % kNumXcd == 0;
+    const bool eighth = wide && level && rem * 8 <= cu;
+    const bool quarter = !eighth && level && rem * 4 <= cu;
+    const int64_t rows1 = std::min<int64_t>(((tiles - rem) / nN) * 256, M);
+    if (!wide)
+        return quarter ? launch_f32_split<128, 64, 128>(A, Bt, C, rows1, M, K, N, st)
+                       : launch_f32_split<128, 64, 128>(A, Bt, C, M, M, K, N, st);
+    if (eighth) return launch_f32_split<256, 64, 128>(A, Bt, C, rows1, M, K, N, st);
+    if (quarter) return launch_f32_split<256, 64, 256>(A, Bt, C, rows1, M, K, N, st);
+    return launch_f32_split<256, 64, 256>(A, Bt, C, M, M, K, N, st);
 }
 
 }  // namespace snrt

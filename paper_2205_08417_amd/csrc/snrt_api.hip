@@ -406,6 +406,7 @@ void snrt_scatter_destroy(snrt_scatter* sc) {
             dev_free(ops[i].f64);
             dev_free(ops[i].hi);
             dev_free(ops[i].lo);
+            dev_free(ops[i].t32);
         }
     delete sc;
 }
@@ -439,7 +440,14 @@ snrt_status make_operand(GemmOperand& op, const std::vector<double>& x, int32_t 
         (s = upload(op.f32, x32.data(), n, fn)) != SNRT_OK ||
         (s = upload(op.f64, x.data(), n, fn)) != SNRT_OK)
         return s;
-    if (precision == SNRT_FP32) return SNRT_OK;
+    if (precision == SNRT_FP32) {
+        // the matrix-core FP32 product where its shape constraints hold
+        if (K % 32 != 0 || N % 128 != 0 || K == 0) return SNRT_OK;
+        if ((s = dev_alloc(&op.t32, n, "scattering operand (FP32 tiled)")) != SNRT_OK) return s;
+        hipError_t e = launch_tile_f32(op.f32, op.t32, K, N, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        return e == hipSuccess ? SNRT_OK : hip_fail(e, fn);
+    }
     if ((s = dev_alloc(&op.hi, n, "scattering operand (BF16 hi)")) != SNRT_OK ||
         (s = dev_alloc(&op.lo, n, "scattering operand (BF16 lo)")) != SNRT_OK)
         return s;
@@ -683,7 +691,8 @@ hipError_t scatter_product32(const snrt_scatter* sc, const float* A, float* C, i
         float* out = (i == B.chain - 1) ? C : scratch;
         const GemmOperand& op = ops[i];
         if (B.precision == SNRT_FP32)
-            e = launch_gemm32(in, op.f32, out, M, op.K, op.N, st);
+            e = op.t32 ? launch_gemm_f32mfma(in, op.t32, out, M, op.K, op.N, st)
+                       : launch_gemm32(in, op.f32, out, M, op.K, op.N, st);
         else
             e = launch_gemm_bf16(in, op.hi, op.lo, out, M, op.K, op.N,
                                  B.precision == SNRT_BF16X3, st);

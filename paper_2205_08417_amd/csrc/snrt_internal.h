@@ -62,6 +62,7 @@ struct GemmOperand {
     double* f64 = nullptr;
     uint16_t* hi = nullptr;
     uint16_t* lo = nullptr;
+    float* t32 = nullptr;     // FP32 in the MFMA kernel's tiled order (FP32 mode, if shaped)
 };
 
 // The scattering product as a chain of right operands, forward (S = Psi X0 [X1]) and adjoint
@@ -242,6 +243,10 @@ hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t*
 // Re-layout of an FP32 [K][N] matrix into the BF16 hi/lo operand format of the MFMA GEMM.
 hipError_t launch_split_bf16(const float* B, uint16_t* hi, uint16_t* lo, int32_t K, int32_t N,
                              hipStream_t st);
+// The FP32 product on the matrix cores (K % 32 == 0, N % 128 == 0) and its operand layout.
+hipError_t launch_gemm_f32mfma(const float* A, const float* Bt, float* C, int64_t M, int32_t K,
+                               int32_t N, hipStream_t st);
+hipError_t launch_tile_f32(const float* B, float* out, int32_t K, int32_t N, hipStream_t st);
 
 // IMEX step with the isotropic collision operator taken implicitly (sn_step_imex.hip).
 hipError_t launch_imex32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
