@@ -61,20 +61,22 @@ def measured_traffic():
     return d.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(P, budget_s: float = 12.0):
+def cpu_baseline(P, budget_s: float = 36.0):
     """Oracle (FP64, OpenMP over cells) on the same mesh and quadrature: as many steps from
-    the workload's initial state as fit the time budget (at least 2)."""
+    the workload's initial state as fit the time budget (at least 2, at most 1000 in all).
+    Also returns the oracle's state and its step count, for the parity figure."""
     from oracle import oracle as o
     op = o.OracleProblem.from_problem(P)
     psi = P.psi0
     t0 = time.perf_counter()
     psi = o.step(op, psi, P.dt)
     t1 = time.perf_counter() - t0
-    n = max(2, min(1000, int(budget_s / max(t1, 1e-6))))
+    n = max(2, min(999, int(budget_s / max(t1, 1e-6))))
     t0 = time.perf_counter()
     for _ in range(n):
         psi = o.step(op, psi, P.dt)
     el = time.perf_counter() - t0
+    reference = (n + 1, psi)
     out = {"value": P.ncells * P.nq * n / el, "unit": "cell-ordinate updates/s",
            "cores": o.num_threads(), "kind": "oracle",
            "sample": f"{n} FP64 oracle steps of the full {WORKLOAD} workload "
@@ -91,7 +93,7 @@ def cpu_baseline(P, budget_s: float = 12.0):
         o.set_num_threads(prev)
     out["single_thread"] = {"value": P.ncells * P.nq * n1 / el1, "cores": 1,
                             "sample": f"{n1} steps, {el1:.1f} s wall"}
-    return out
+    return out, reference
 
 
 def timed(fn, n, stream):
@@ -589,7 +591,17 @@ def main():
         # the degree of the paper's CSD P_N runs (Sec. 7), same mesh and materials
         out["pn_degree13"] = bench_pn(min(args.steps, 50), 3, degree=13)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(P)
+        out["cpu_baseline"], (nref, ref) = cpu_baseline(P)
+        # the FP32 path against the oracle after the same number of steps from the
+        # workload's initial state
+        import numpy as np
+        Sp = Solver(P)
+        psi_g, _ = Sp.rollout(Sp.initial_state(), nref)
+        got = Sp.to_user(psi_g).cpu().numpy().astype(np.float64)
+        Sp.close()
+        out["parity_vs_oracle"] = {
+            "workload": WORKLOAD, "steps": nref, "dtype": "f32",
+            "rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
     print(json.dumps(out), flush=True)
 
 
