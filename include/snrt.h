@@ -59,7 +59,9 @@ typedef enum {
 } snrt_status;
 
 typedef enum {
-    SNRT_FP32 = 0,    /* dense scattering product in FP32 */
+    SNRT_FP32 = 0,    /* dense scattering product in FP32 (on the matrix cores when the
+                         product's inner dimension is a multiple of 32 and its outer one a
+                         multiple of 128; FP32 vector FMAs otherwise) */
     SNRT_BF16X3 = 1,  /* BF16 MFMA, hi+lo split of both operands, three products, FP32 accumulate */
     SNRT_BF16X1 = 2   /* BF16 MFMA, single product (fast, ~1e-3 relative) */
 } snrt_precision;
