@@ -372,11 +372,31 @@ __device__ __forceinline__ void pn_fused_tile(const typename GeomOf<T>::type* __
 // its even wavefronts take a tile's z-even moments, the odd ones its z-odd moments (the
 // two subsystems never meet), so each wavefront runs about half of the moment loop.  The
 // packed coefficient table is read with scalar loads (uniform addresses, one per wavefront).
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// Degrees whose packed table (43 KB at degree 13) overflows the scalar cache read it from
+// an LDS copy made once per block instead (measured: degree 13 0.264 -> 0.201 ms per step on
+// 198 450 cells; degrees 7-9, whose tables of 6-12 KB the scalar cache holds, ran 7-9 %
+// slower from LDS).
+template <int N, typename T>
+constexpr bool pn_table_in_lds() { return sizeof(T) == 4 && N > pn::kMaxFusedDegree; }
+
 template <int N, int MF, typename T>
 __global__ __launch_bounds__(256, (pn_min_waves<N, MF, T>())) void k_pn_fused(
     const typename GeomOf<T>::type* __restrict__ geom, int32_t nc, int32_t ntiles,
-    const T* __restrict__ W, const T* __restrict__ sig, typename ArgsOf<T>::type a,
+    const T* __restrict__ Wg, const T* __restrict__ sig, typename ArgsOf<T>::type a,
     const T* __restrict__ u, T* __restrict__ out, uint32_t state_bytes, uint32_t inflow_bytes) {
+    const T* W = Wg;
+    if constexpr (pn_table_in_lds<N, T>()) {
+        constexpr int NW = pn::OpTable<N>::count;
+        __shared__ __attribute__((aligned(16))) T Wl[(NW + 3) / 4 * 4];
+        // 16-byte pieces, then the last NW % 4 values one by one (no read past the table)
+        for (int i = (int)threadIdx.x; i < NW / 4; i += 256)
+            reinterpret_cast<f32x4_t*>(Wl)[i] = reinterpret_cast<const f32x4_t*>(Wg)[i];
+        if ((int)threadIdx.x < NW % 4) Wl[NW / 4 * 4 + threadIdx.x] = Wg[NW / 4 * 4 + threadIdx.x];
+        __syncthreads();                  // before any wavefront of the block may leave
+        W = Wl;
+    }
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int tile = (int)(blk * 2 + (threadIdx.x >> 7));
     const int c = tile * kTile + (int)(threadIdx.x & 63);
