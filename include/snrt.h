@@ -408,6 +408,15 @@ snrt_status snrt_pn_step_f64(const snrt_mesh* mesh, const snrt_pn* pn,
 snrt_status snrt_permute(const snrt_mesh* mesh, int32_t to_user, const void* in, void* out,
                          int64_t row_bytes, void* stream);
 
+/* ---------------------------------------------------------------- measurement helper */
+
+/* Not part of the method: copies `bytes` bytes from src to dst (device pointers, 16-byte
+ * aligned, disjoint; bytes a non-negative multiple of 16) in one launch on `stream`, with
+ * 16-byte nontemporal loads and stores.  Its rate on a state-sized buffer is the attainable
+ * HBM read+write bandwidth that the step kernels are compared with.  SNRT_E_ARG for a bad
+ * size, a NULL or misaligned pointer (bytes > 0); SNRT_E_ALIAS if the ranges overlap. */
+snrt_status snrt_stream_copy(const void* src, void* dst, int64_t bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

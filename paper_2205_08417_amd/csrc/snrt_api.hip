@@ -1068,4 +1068,20 @@ snrt_status snrt_permute(const snrt_mesh* m, int32_t to_user, const void* in, vo
     return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_permute: launch");
 }
 
+// ------------------------------------------------------------------- measurement helper
+
+snrt_status snrt_stream_copy(const void* src, void* dst, int64_t bytes, void* stream) {
+    g_last_error.clear();
+    SNRT_REQUIRE(bytes >= 0 && bytes % 16 == 0, SNRT_E_ARG,
+                 "snrt_stream_copy: bytes must be a non-negative multiple of 16");
+    if (bytes == 0) return SNRT_OK;
+    SNRT_REQUIRE(src && dst, SNRT_E_ARG, "snrt_stream_copy: NULL array");
+    SNRT_REQUIRE(((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15u) == 0,
+                 SNRT_E_ARG, "snrt_stream_copy: arrays must be 16-byte aligned");
+    SNRT_REQUIRE(!ranges_overlap(src, (size_t)bytes, dst, (size_t)bytes), SNRT_E_ALIAS,
+                 "snrt_stream_copy: dst overlaps src");
+    hipError_t e = launch_stream_copy(src, dst, bytes, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_stream_copy: launch");
+}
+
 }  // extern "C"

@@ -223,6 +223,8 @@ hipError_t launch_step32(const snrt_mesh& m, const snrt_quad& q, const StepArgs3
 int32_t step_items_per_row(const snrt_quad& q, bool dense);
 hipError_t launch_dose_fold(const snrt_mesh& m, const double* part, int32_t nch,
                             const float* inv_rho, double coeff, double* dose, hipStream_t st);
+// nontemporal device copy of bytes / 16 16-byte vectors (bandwidth measurement)
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);
 hipError_t launch_step64(const snrt_mesh& m, const snrt_quad& q, const StepArgs64& a,
                          const double* psi_in, double* psi_out, const double* S, hipStream_t st);
 hipError_t launch_adjoint32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,

@@ -50,6 +50,7 @@ EXPORTS = [
     "snrt_scatter_moments", "snrt_step_imex", "snrt_step_imex_f64",
     "snrt_pn_operators", "snrt_pn_create", "snrt_pn_destroy", "snrt_pn_info",
     "snrt_pn_state_elems", "snrt_pn_layout", "snrt_pn_step", "snrt_pn_step_f64",
+    "snrt_stream_copy",
 ]
 
 
@@ -134,6 +135,7 @@ def lib() -> ctypes.CDLL:
         "snrt_dose_adjoint": (_st, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
         "snrt_dose_density_grad": (_st, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "snrt_permute": (_st, [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int64, _vp]),
+        "snrt_stream_copy": (_st, [_vp, _vp, ctypes.c_int64, _vp]),
         "snrt_mesh_set_face_midpoints": (_st, [_vp, _dp]),
         "snrt_step_imex": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp]),
         "snrt_step_imex_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp]),
@@ -427,6 +429,12 @@ def snrt_dose_density_grad(mesh, dose, inv_rho, g_dose, g_rho, stream=None) -> N
 def snrt_permute(mesh, to_user: int, src, dst, row_bytes: int, stream=None) -> None:
     _check("snrt_permute", lib().snrt_permute(mesh, int(to_user), _ptr(src), _ptr(dst),
                                               int(row_bytes), _stream(stream)))
+
+
+def snrt_stream_copy(src, dst, nbytes: int, stream=None) -> None:
+    """Measurement helper: nontemporal device copy of ``nbytes`` bytes from ``src`` to ``dst``."""
+    _check("snrt_stream_copy", lib().snrt_stream_copy(_ptr(src), _ptr(dst), int(nbytes),
+                                                      _stream(stream)))
 
 
 # ------------------------------------------------------------------------------ P_N solver
