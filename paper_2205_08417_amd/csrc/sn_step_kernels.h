@@ -331,7 +331,7 @@ __device__ __forceinline__ void fwd_load_stage(FwdStage<V, MF, DENSE, T>& d, con
         d.nx[f] = g->n[f][0];
         d.ny[f] = g->n[f][1];
     }
-    if constexpr (DENSE) buf_load_row<V, EXACT>(x.S, own, q0, nq, d.src);
+    if constexpr (DENSE) buf_load_row<V, EXACT, T, kAuxStream>(x.S, own, q0, nq, d.src);
     const T st_c = cell_val(a.sigma_t, c);
     d.keep = T(1) - a.dt * a.alpha_t * st_c;
     d.imex_a = T(1) + a.dt * a.alpha_t * st_c;
