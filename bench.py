@@ -288,9 +288,11 @@ def bench_csd(steps, warmup: int):
 
 def bench_moments(steps, warmup: int, degree: int = 8):
     """Moment-projected scattering (eq. SNEqns2) on the HG line source (100 352 cells x
-    1024 ordinates), HG g=0.9 to degree 8 (81 moments, padded to 256 for the MFMA kernel),
+    1024 ordinates), HG g=0.9 to degree 8 (81 moments, padded to 128 for the MFMA kernel),
     BF16 hi+lo: the step rate over the whole 200-step run (steps=None) against the
-    dense-kernel step of the same workload."""
+    dense-kernel step of the same workload; then the same number of IMEX steps (implicit
+    moment-form collisions: collision-free step, two products with the per-cell diagonal
+    between them, combine)."""
     import torch
     from paper_2205_08417_amd import inputs as I
     from paper_2205_08417_amd.solver import Solver
@@ -313,6 +315,17 @@ def bench_moments(steps, warmup: int, degree: int = 8):
     state[0] = S.initial_state()
     torch.cuda.synchronize()
     ms = timed(one_step, steps, stream)
+
+    def one_imex():
+        S.step_imex(state[0], state[1], args)
+        state.reverse()
+
+    state[0] = S.initial_state()
+    for _ in range(min(warmup, 5)):
+        one_imex()
+    state[0] = S.initial_state()
+    torch.cuda.synchronize()
+    ms_imex = timed(one_imex, steps, stream)
     nm = (degree + 1) ** 2
     mid = ((nm + 127) // 128) * 128                      # the library's BF16 padding
     executed = 3 * 2 * 2.0 * P.ncells * P.nq * mid       # two products, three BF16 passes
@@ -323,7 +336,7 @@ def bench_moments(steps, warmup: int, degree: int = 8):
             "precision": "bf16x3", "steps": steps, "ms_per_step": ms,
             "value": P.ncells * P.nq / (ms * 1e-3), "unit": "cell-ordinate updates/s",
             "moment_dimension_padded": mid, "product_flops_executed": executed,
-            "product_flops_useful": useful}
+            "product_flops_useful": useful, "imex_ms_per_step": ms_imex}
 
 
 def bench_second_order(steps: int, warmup: int):

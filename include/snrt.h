@@ -249,6 +249,29 @@ snrt_status snrt_step_imex_f64(const snrt_mesh* mesh, const snrt_quad* quad,
                                const snrt_scatter* scatter, const snrt_step_args_f64* args,
                                const double* psi_in, double* psi_out, void* stream);
 
+/* IMEX step as above with moment-projected scattering S(psi) = O Sigma M psi (eq. SNEqns2,
+ * scatter from snrt_scatter_moments).  Per cell, with a = 1 + dt alpha_t sigma_t and
+ * b = dt alpha_s sigma_s, the system (a I - b O Sigma M) psi' = r has, when the quadrature
+ * integrates the products of the harmonics exactly (M O = I), the solution
+ *     psi' = (r + O D M r) / a,   D = diag(b Sigma_l / (a - b Sigma_l)),
+ * computed as the collision-free explicit step r (written to psi_out), the two moment
+ * products with the per-cell diagonal between them, and (r + S) / a in place.  Requires
+ * a - b Sigma_l != 0 for every moment (always true for sigma_s <= sigma_t, alpha_s <= alpha_t
+ * and |Sigma_l| <= 1).  Returns SNRT_E_UNSUPPORTED for other scatter handles and when
+ * max |M O - I| > 1e-10 (the product rule integrates degree-N harmonics exactly when it has
+ * more than N polar and more than 2N azimuthal nodes; the check is skipped, and the call
+ * refused, when (N+1)^4 nq exceeds 2e8).  Workspace: snrt_workspace_size of the handle,
+ * 16-byte aligned, disjoint from the states; the products run in the handle's precision. */
+snrt_status snrt_step_imex_moments(const snrt_mesh* mesh, const snrt_quad* quad,
+                                   const snrt_scatter* scatter, const snrt_step_args* args,
+                                   const float* psi_in, float* psi_out, void* workspace,
+                                   size_t workspace_bytes, void* stream);
+snrt_status snrt_step_imex_moments_f64(const snrt_mesh* mesh, const snrt_quad* quad,
+                                       const snrt_scatter* scatter,
+                                       const snrt_step_args_f64* args, const double* psi_in,
+                                       double* psi_out, void* workspace, size_t workspace_bytes,
+                                       void* stream);
+
 /* ---------------------------------------------------------------- second-order step */
 
 /* Face-slot midpoints for the second-order scheme (Sec. 4.2, second order finite volume

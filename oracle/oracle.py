@@ -319,7 +319,8 @@ def rel_l2(x, ref) -> float:
 # ----------------------------------------------------------------------------------------
 
 def step_imex(op: OracleProblem, psi: np.ndarray, dt: float, alpha_t: float = 1.0,
-              alpha_s: float = 1.0, inflow_scale: float = 1.0) -> np.ndarray:
+              alpha_s: float = 1.0, inflow_scale: float = 1.0,
+              cells: Optional[np.ndarray] = None) -> np.ndarray:
     """(I - dt R_i) psi_i^{n+1} = psi_i^n - dt/A_i sum_j F_up + dt q_i per cell, with the
     linear collision operator R_i psi = -alpha_t sigma_t,i psi + alpha_s sigma_s,i S(psi)
     (S the scattering source of eq. SNEqns) taken implicitly and the source q explicitly.
@@ -327,17 +328,20 @@ def step_imex(op: OracleProblem, psi: np.ndarray, dt: float, alpha_t: float = 1.
     The right-hand side is the explicit step with the collision term switched off; the
     per-cell system (a I - c K~) psi = b, a = 1 + dt alpha_t sigma_t, c = dt alpha_s sigma_s,
     K~[q][p] = K[q][p] w_p (K = 1/(4 pi) when isotropic), is solved with numpy's LU solver.
+    ``cells``: only those cells' rows, in that order.
     """
     zero = np.zeros(op.nc)
-    b = step(op.replace(sigma_t=zero, sigma_s=zero), psi, dt, alpha_t, alpha_s, inflow_scale)
+    b = step(op.replace(sigma_t=zero, sigma_s=zero), psi, dt, alpha_t, alpha_s, inflow_scale,
+             cells=cells)
     K = op.K if op.K is not None else np.full((op.nq, op.nq), 1.0 / (4.0 * np.pi))
     Kw = K * op.w[None, :]
-    a = 1.0 + dt * alpha_t * op.sigma_t
-    c = dt * alpha_s * op.sigma_s
+    idx = np.arange(op.nc) if cells is None else np.asarray(cells, dtype=np.int64)
+    a = 1.0 + dt * alpha_t * op.sigma_t[idx]
+    c = dt * alpha_s * op.sigma_s[idx]
     out = np.empty_like(b)
     eye = np.eye(op.nq)
-    for start in range(0, op.nc, 256):                     # batches of cells
-        sl = slice(start, min(op.nc, start + 256))
+    for start in range(0, b.shape[0], 256):                # batches of cells
+        sl = slice(start, min(b.shape[0], start + 256))
         A = a[sl, None, None] * eye[None] - c[sl, None, None] * Kw[None]
         out[sl] = np.linalg.solve(A, b[sl][..., None])[..., 0]
     return out

@@ -9,4 +9,10 @@ hipError_t launch_step64(const snrt_mesh& m, const snrt_quad& q, const StepArgs6
     return launch_step_t<double>(m.geom64, m, q.tab64, q.nq, a, psi_in, psi_out, S, st);
 }
 
+hipError_t launch_free_step64(const snrt_mesh& m, const snrt_quad& q, const StepArgs64& a,
+                              const double* psi_in, double* psi_out, hipStream_t st) {
+    return launch_step_t<double>(m.geom64, m, q.tab64, q.nq, a, psi_in, psi_out, nullptr, st,
+                                 nullptr, nullptr, true);
+}
+
 }  // namespace snrt

@@ -461,7 +461,8 @@ __device__ __forceinline__ void step_sweep(
     cx.psi = make_rsrc(psi_in, state_bytes);
     cx.out = make_rsrc(psi_out, state_bytes);
     cx.inflow = make_rsrc(a.inflow ? a.inflow : psi_in, a.inflow ? nbf * cx.row_bytes : 0u);
-    cx.S = make_rsrc(DENSE ? S : psi_in, DENSE ? state_bytes : 0u);
+    // no S (a chunked step without scattering): an empty resource, whose loads return 0
+    cx.S = make_rsrc(DENSE && S ? S : psi_in, DENSE && S ? state_bytes : 0u);
     // optional per-cell source: read a valid array and scale by 0 when there is none
     cx.src_arr = a.source ? a.source : a.sigma_t;
     cx.src_mul = a.source ? a.dt : T(0);
@@ -956,10 +957,13 @@ template <typename T>
 hipError_t launch_step_t(const typename GeomOf<T>::type* geom, const snrt_mesh& m,
                          const T* tab, int32_t nq, const typename ArgsOf<T>::type& a,
                          const T* psi_in, T* psi_out, const T* S, hipStream_t st,
-                         const double* wq = nullptr, double* dpart = nullptr)
+                         const double* wq = nullptr, double* dpart = nullptr,
+                         bool chunk_rows = false)
 {
     if (m.nc == 0) return hipSuccess;
-    const bool rho = a.inv_rho != nullptr, dense = S != nullptr, mf4 = m.mf == 4;
+    // chunk_rows without S: the chunked (dense-row) kernel with a zero scattering source, for
+    // steps that need no in-row reduction
+    const bool rho = a.inv_rho != nullptr, dense = S != nullptr || chunk_rows, mf4 = m.mf == 4;
     const int shift = dense ? dense_chunk_shift(nq) : 0;
     return dispatch_v<T>(shift ? kWave * 4 : nq, [&](auto vc, auto ex) {
         constexpr int V = decltype(vc)::value;

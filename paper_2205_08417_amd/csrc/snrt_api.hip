@@ -408,6 +408,8 @@ void snrt_scatter_destroy(snrt_scatter* sc) {
             dev_free(ops[i].lo);
             dev_free(ops[i].t32);
         }
+    dev_free(sc->B.msig32);
+    dev_free(sc->B.msig64);
     delete sc;
 }
 
@@ -524,9 +526,18 @@ snrt_status snrt_scatter_moments(snrt_scatter** out, const snrt_quad* q, int32_t
     std::vector<double> mt((size_t)nq * mid, 0.0), ot((size_t)mid * nq, 0.0);
     std::vector<double> mtT((size_t)mid * nq, 0.0), otT((size_t)nq * mid, 0.0);
     std::vector<double> m(nm);
+    // Gram matrix G = M O of the harmonics under the quadrature (the identity when the rule
+    // integrates their products exactly); skipped as too costly above ~2e8 terms
+    const bool gram = (double)nm * nm * nq <= 2e8;
+    std::vector<double> G(gram ? (size_t)nm * nm : 0, 0.0);
     for (int32_t qq = 0; qq < nq; ++qq) {
         const double* o = q->omega_host.data() + (size_t)qq * 3;
         real_harmonics(degree, o[0], o[1], o[2], m.data());
+        if (gram)
+            for (int j = 0; j < nm; ++j) {
+                const double wj = q->w_host[qq] * m[j];
+                for (int k = 0; k < nm; ++k) G[(size_t)j * nm + k] += wj * m[k];
+            }
         for (int l = 0; l <= degree; ++l)
             for (int j = l * l; j < (l + 1) * (l + 1); ++j) {
                 const double a = q->w_host[qq] * m[j];
@@ -546,9 +557,24 @@ snrt_status snrt_scatter_moments(snrt_scatter** out, const snrt_quad* q, int32_t
     B.chain = 2;
     B.mid = mid;
     B.degree = degree;
+    B.mo_err = gram ? 0.0 : HUGE_VAL;
+    for (int j = 0; gram && j < nm; ++j)
+        for (int k = 0; k < nm; ++k)
+            B.mo_err = std::max(B.mo_err, std::fabs(G[(size_t)j * nm + k] - (j == k ? 1.0 : 0.0)));
+    std::vector<double> msig(mid, 0.0);
+    std::vector<float> msig32(mid, 0.0f);
+    for (int l = 0; l <= degree; ++l)
+        for (int j = l * l; j < (l + 1) * (l + 1); ++j) {
+            msig[j] = sigma_l[l];
+            msig32[j] = (float)sigma_l[l];
+        }
     snrt_status s = SNRT_OK;
     const char* fn = "snrt_scatter_moments: upload";
-    if ((s = make_operand(B.fwd[0], mt, nq, mid, precision, fn)) != SNRT_OK ||
+    if ((s = dev_alloc(&B.msig32, (size_t)mid, "moment diagonal")) != SNRT_OK ||
+        (s = dev_alloc(&B.msig64, (size_t)mid, "moment diagonal")) != SNRT_OK ||
+        (s = upload(B.msig32, msig32.data(), (size_t)mid, fn)) != SNRT_OK ||
+        (s = upload(B.msig64, msig.data(), (size_t)mid, fn)) != SNRT_OK ||
+        (s = make_operand(B.fwd[0], mt, nq, mid, precision, fn)) != SNRT_OK ||
         (s = make_operand(B.fwd[1], ot, mid, nq, precision, fn)) != SNRT_OK ||
         (s = make_operand(B.adj[0], otT, nq, mid, precision, fn)) != SNRT_OK ||
         (s = make_operand(B.adj[1], mtT, mid, nq, precision, fn)) != SNRT_OK) {
@@ -681,6 +707,15 @@ StepArgs64 to64(const snrt_step_args_f64* a) {
 // S = Psi B (forward) or G = Lambda B^T (adjoint) into the workspace, FP32 state
 // C = A X0 [X1] (forward) or A X0^T-side chain (adjoint); scratch holds the moments between
 // the two products of the moment form ([M][mid]).
+// out = in X for one right operand of the chain, in the handle's precision
+hipError_t product32(const DenseB& B, const GemmOperand& op, const float* in, float* out,
+                     int64_t M, hipStream_t st) {
+    if (B.precision == SNRT_FP32)
+        return op.t32 ? launch_gemm_f32mfma(in, op.t32, out, M, op.K, op.N, st)
+                      : launch_gemm32(in, op.f32, out, M, op.K, op.N, st);
+    return launch_gemm_bf16(in, op.hi, op.lo, out, M, op.K, op.N, B.precision == SNRT_BF16X3, st);
+}
+
 hipError_t scatter_product32(const snrt_scatter* sc, const float* A, float* C, int64_t M,
                              bool transpose, float* scratch, hipStream_t st) {
     const DenseB& B = sc->B;
@@ -689,13 +724,7 @@ hipError_t scatter_product32(const snrt_scatter* sc, const float* A, float* C, i
     hipError_t e = hipSuccess;
     for (int i = 0; i < B.chain && e == hipSuccess; ++i) {
         float* out = (i == B.chain - 1) ? C : scratch;
-        const GemmOperand& op = ops[i];
-        if (B.precision == SNRT_FP32)
-            e = op.t32 ? launch_gemm_f32mfma(in, op.t32, out, M, op.K, op.N, st)
-                       : launch_gemm32(in, op.f32, out, M, op.K, op.N, st);
-        else
-            e = launch_gemm_bf16(in, op.hi, op.lo, out, M, op.K, op.N,
-                                 B.precision == SNRT_BF16X3, st);
+        e = product32(B, ops[i], in, out, M, st);
         in = out;
     }
     return e;
@@ -971,6 +1000,80 @@ snrt_status snrt_step_imex_f64(const snrt_mesh* m, const snrt_quad* q, const snr
     if (m->nc == 0) return SNRT_OK;
     hipError_t e = launch_imex64(*m, *q, to64(a), psi_in, psi_out, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_step_imex_f64: launch");
+}
+
+}  // extern "C"
+
+namespace {
+
+// Largest |M O - I| for which the moment-form IMEX inverse is taken as exact.
+constexpr double kMomentGramTol = 1e-10;
+
+// IMEX with moment-projected scattering: r = the collision-free explicit step (into psi_out),
+// U = M r, U *= b / (a - b Sigma), S = (Sigma O) U, psi_out = (r + S) / a.
+template <typename T, typename ArgsT>
+snrt_status imex_moments_common(const char* fn, const snrt_mesh* m, const snrt_quad* q,
+                                const snrt_scatter* sc, const ArgsT* a, const T* psi_in,
+                                T* psi_out, void* ws, size_t ws_bytes, void* stream) {
+    SNRT_REQUIRE(sc, SNRT_E_ARG, std::string(fn) + ": NULL scatter handle");
+    SNRT_REQUIRE(sc->dense && sc->B.chain == 2, SNRT_E_UNSUPPORTED,
+                 std::string(fn) + ": needs a moment-form scatter handle (snrt_scatter_moments)");
+    SNRT_REQUIRE(sc->B.mo_err <= kMomentGramTol, SNRT_E_UNSUPPORTED,
+                 std::string(fn) + ": the quadrature does not integrate the harmonics' products "
+                                   "exactly (M O != I), so the closed-form inverse does not hold");
+    SNRT_TRY(check_step_common(fn, m, q, sc, a, sizeof(T), psi_in, psi_out, ws, ws_bytes));
+    if (m->nc == 0) return SNRT_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const DenseB& B = sc->B;
+    T* S = static_cast<T*>(ws);
+    T* U = S + (size_t)m->nc * q->nq;
+    hipError_t e;
+    if constexpr (sizeof(T) == 4) {
+        const StepArgs32 a32 = to32(a);
+        StepArgs32 free_flight = a32;
+        free_flight.alpha_t = 0.0f;
+        free_flight.alpha_s = 0.0f;
+        e = launch_free_step32(*m, *q, free_flight, psi_in, psi_out, st);
+        if (e == hipSuccess) e = product32(B, B.fwd[0], psi_out, U, m->nc, st);
+        if (e == hipSuccess) e = launch_imex_moment_scale32(a32, U, B.msig32, m->nc, B.mid, st);
+        if (e == hipSuccess) e = product32(B, B.fwd[1], U, S, m->nc, st);
+        if (e == hipSuccess) e = launch_imex_combine32(a32, psi_out, S, m->nc, q->nq, st);
+    } else {
+        const StepArgs64 a64 = to64(a);
+        StepArgs64 free_flight = a64;
+        free_flight.alpha_t = 0.0;
+        free_flight.alpha_s = 0.0;
+        e = launch_free_step64(*m, *q, free_flight, psi_in, psi_out, st);
+        if (e == hipSuccess)
+            e = launch_gemm64(psi_out, B.fwd[0].f64, U, m->nc, B.fwd[0].K, B.fwd[0].N, st);
+        if (e == hipSuccess) e = launch_imex_moment_scale64(a64, U, B.msig64, m->nc, B.mid, st);
+        if (e == hipSuccess)
+            e = launch_gemm64(U, B.fwd[1].f64, S, m->nc, B.fwd[1].K, B.fwd[1].N, st);
+        if (e == hipSuccess) e = launch_imex_combine64(a64, psi_out, S, m->nc, q->nq, st);
+    }
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, (std::string(fn) + ": launch").c_str());
+}
+
+}  // namespace
+
+extern "C" {
+
+snrt_status snrt_step_imex_moments(const snrt_mesh* m, const snrt_quad* q,
+                                   const snrt_scatter* sc, const snrt_step_args* a,
+                                   const float* psi_in, float* psi_out, void* ws,
+                                   size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    return imex_moments_common<float>("snrt_step_imex_moments", m, q, sc, a, psi_in, psi_out,
+                                      ws, ws_bytes, stream);
+}
+
+snrt_status snrt_step_imex_moments_f64(const snrt_mesh* m, const snrt_quad* q,
+                                       const snrt_scatter* sc, const snrt_step_args_f64* a,
+                                       const double* psi_in, double* psi_out, void* ws,
+                                       size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    return imex_moments_common<double>("snrt_step_imex_moments_f64", m, q, sc, a, psi_in,
+                                       psi_out, ws, ws_bytes, stream);
 }
 
 snrt_status snrt_scatter_apply(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,

@@ -77,6 +77,11 @@ struct DenseB {
     int32_t chain = 1;
     int32_t mid = 0;
     int32_t degree = -1;          // moment degree N (chain 2)
+    // moment form: Sigma per moment index ([mid], zero past the (N+1)^2 moments) and
+    // max |M O - I| over the moments (how exactly the quadrature integrates their products)
+    float* msig32 = nullptr;
+    double* msig64 = nullptr;
+    double mo_err = 0.0;
     GemmOperand fwd[2], adj[2];
 };
 
@@ -227,6 +232,12 @@ hipError_t launch_dose_fold(const snrt_mesh& m, const double* part, int32_t nch,
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);
 hipError_t launch_step64(const snrt_mesh& m, const snrt_quad& q, const StepArgs64& a,
                          const double* psi_in, double* psi_out, const double* S, hipStream_t st);
+// the step without scattering through the row-chunked kernel (no in-row reduction); with
+// alpha_t = alpha_s = 0 it is the collision-free step of the IMEX splitting
+hipError_t launch_free_step32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
+                              const float* psi_in, float* psi_out, hipStream_t st);
+hipError_t launch_free_step64(const snrt_mesh& m, const snrt_quad& q, const StepArgs64& a,
+                              const double* psi_in, double* psi_out, hipStream_t st);
 hipError_t launch_adjoint32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
                             const float* psi_n, const float* lam_np1, float* lam_n,
                             float* g_t, float* g_s, float* g_r, const float* G, hipStream_t st);
@@ -255,6 +266,15 @@ hipError_t launch_imex32(const snrt_mesh& m, const snrt_quad& q, const StepArgs3
                          const float* psi_in, float* psi_out, hipStream_t st);
 hipError_t launch_imex64(const snrt_mesh& m, const snrt_quad& q, const StepArgs64& a,
                          const double* psi_in, double* psi_out, hipStream_t st);
+// moment-form IMEX: U[c][j] *= b_c / (a_c - b_c Sigma_j), then psi[c][q] = (psi + S) / a_c
+hipError_t launch_imex_moment_scale32(const StepArgs32& a, float* U, const float* msig,
+                                      int64_t nc, int32_t mid, hipStream_t st);
+hipError_t launch_imex_moment_scale64(const StepArgs64& a, double* U, const double* msig,
+                                      int64_t nc, int32_t mid, hipStream_t st);
+hipError_t launch_imex_combine32(const StepArgs32& a, float* psi, const float* S, int64_t nc,
+                                 int32_t nq, hipStream_t st);
+hipError_t launch_imex_combine64(const StepArgs64& a, double* psi, const double* S, int64_t nc,
+                                 int32_t nq, hipStream_t st);
 
 // Second-order scheme (sn_step2.hip): limited gradient of a stage input and the stage
 // update with reconstructed face values; final = true writes (psi_n + stage) / 2.

@@ -50,7 +50,7 @@ EXPORTS = [
     "snrt_scatter_moments", "snrt_step_imex", "snrt_step_imex_f64",
     "snrt_pn_operators", "snrt_pn_create", "snrt_pn_destroy", "snrt_pn_info",
     "snrt_pn_state_elems", "snrt_pn_layout", "snrt_pn_step", "snrt_pn_step_f64",
-    "snrt_stream_copy",
+    "snrt_stream_copy", "snrt_step_imex_moments", "snrt_step_imex_moments_f64",
 ]
 
 
@@ -139,6 +139,10 @@ def lib() -> ctypes.CDLL:
         "snrt_mesh_set_face_midpoints": (_st, [_vp, _dp]),
         "snrt_step_imex": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp]),
         "snrt_step_imex_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp]),
+        "snrt_step_imex_moments": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp,
+                                         _vp, ctypes.c_size_t, _vp]),
+        "snrt_step_imex_moments_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp,
+                                             _vp, ctypes.c_size_t, _vp]),
         "snrt_scatter_moments": (_st, [ctypes.POINTER(_vp), _vp, ctypes.c_int32, _dp,
                                        ctypes.c_int]),
         "snrt_step2_workspace_size": (_st, [_vp, _vp, _vp, ctypes.c_int32,
@@ -307,6 +311,21 @@ def snrt_step_imex_f64(mesh, quad, scatter, args: StepArgs, psi_in, psi_out,
     _check("snrt_step_imex_f64", lib().snrt_step_imex_f64(mesh, quad, scatter, ctypes.byref(args),
                                                           _ptr(psi_in), _ptr(psi_out),
                                                           _stream(stream)))
+
+
+def snrt_step_imex_moments(mesh, quad, scatter, args: StepArgs, psi_in, psi_out, ws,
+                           ws_bytes: int, stream=None) -> None:
+    _check("snrt_step_imex_moments",
+           lib().snrt_step_imex_moments(mesh, quad, scatter, ctypes.byref(args), _ptr(psi_in),
+                                        _ptr(psi_out), _ptr(ws), int(ws_bytes), _stream(stream)))
+
+
+def snrt_step_imex_moments_f64(mesh, quad, scatter, args: StepArgs, psi_in, psi_out, ws,
+                               ws_bytes: int, stream=None) -> None:
+    _check("snrt_step_imex_moments_f64",
+           lib().snrt_step_imex_moments_f64(mesh, quad, scatter, ctypes.byref(args),
+                                            _ptr(psi_in), _ptr(psi_out), _ptr(ws),
+                                            int(ws_bytes), _stream(stream)))
 
 
 def snrt_step2_workspace_size(mesh: int, quad: int, scatter: int, fp64: bool = False) -> int:

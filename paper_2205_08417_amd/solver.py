@@ -45,6 +45,7 @@ class Solver:
             self.mesh = snrt.snrt_mesh_create(m.face_nbr, m.face_normal, m.area, m.centroid,
                                               m.nbfaces, flags)
             self.quad = snrt.snrt_quad_create(P.omega, P.w)
+            self.is_moments = moments is not None
             if moments is not None:
                 # moment-projected scattering O Sigma M (eq. SNEqns2) with Legendre moments
                 self.scatter = snrt.snrt_scatter_moments(self.quad, moments, _PREC[precision])
@@ -123,16 +124,25 @@ class Solver:
         return self.ws2[fp64]
 
     def step_imex(self, psi_in, psi_out, args=None, **kw):
-        """One IMEX step: implicit isotropic collision, explicit streaming and source."""
-        snrt.snrt_step_imex(self.mesh, self.quad, self.scatter, args or self.args(**kw), psi_in,
-                            psi_out)
+        """One IMEX step: implicit collision (isotropic, or moment-projected scattering),
+        explicit streaming and source."""
+        args = args or self.args(**kw)
+        if self.is_moments:
+            snrt.snrt_step_imex_moments(self.mesh, self.quad, self.scatter, args, psi_in,
+                                        psi_out, self.ws, self.ws_bytes)
+        else:
+            snrt.snrt_step_imex(self.mesh, self.quad, self.scatter, args, psi_in, psi_out)
 
     def step_imex_f64(self, psi_in, psi_out, args=None, **kw):
         if self.mats64 is None:
             self.mats64 = self._materials(torch.float64)
         kw["fp64"] = True
-        snrt.snrt_step_imex_f64(self.mesh, self.quad, self.scatter, args or self.args(**kw),
-                                psi_in, psi_out)
+        args = args or self.args(**kw)
+        if self.is_moments:
+            snrt.snrt_step_imex_moments_f64(self.mesh, self.quad, self.scatter, args, psi_in,
+                                            psi_out, self.ws, self.ws_bytes)
+        else:
+            snrt.snrt_step_imex_f64(self.mesh, self.quad, self.scatter, args, psi_in, psi_out)
 
     def step2(self, psi_in, psi_out, args=None, limiter="barth-jespersen", vk_k=1.0, **kw):
         """One Heun step of the second-order scheme (limited linear reconstruction);
@@ -184,7 +194,11 @@ class Solver:
         fused_dose = order == 1 and not imex
         if fp64 and self.mats64 is None:
             self.mats64 = self._materials(torch.float64)
-        if imex:
+        if imex and self.is_moments:
+            step = snrt.snrt_step_imex_moments_f64 if fp64 else snrt.snrt_step_imex_moments
+            ws = self.ws.data_ptr()
+            ws_bytes = self.ws_bytes
+        elif imex:
             fn = snrt.snrt_step_imex_f64 if fp64 else snrt.snrt_step_imex
             step = lambda m, q, sc, args, a, b, ws_, n_, st: fn(m, q, sc, args, a, b, st)  # noqa
             ws, ws_bytes = None, 0

@@ -100,3 +100,141 @@ def test_imex_rejects_dense_scattering():
         S.step_imex(a, torch.empty_like(a))
     assert ei.value.status == snrt.SNRT_E_UNSUPPORTED
     S.close()
+
+
+# ---------------------------------------------------------------- moment-form IMEX
+
+def _moment_problem(npol, naz, seed, stiff=1.0, **kw):
+    omega, w = I.product_quadrature(npol, naz)
+    P = small_problem(I.jittered_delaunay_mesh(12, 0.0, 1.0, seed=seed), omega_w=(omega, w),
+                      seed=seed, scatter=(0.5, 1.0), **kw)
+    sig_t = P.sigma_t * stiff
+    return dataclasses.replace(P, sigma_t=sig_t, sigma_s=0.9 * sig_t)
+
+
+def _oracle_moment_imex(P, sig, nsteps, **kw):
+    from oracle import moments as mo
+    from oracle import oracle as o
+    op = o.OracleProblem.from_problem(P, K=mo.moment_kernel(P.omega, P.w, sig))
+    psi = P.psi0
+    for _ in range(nsteps):
+        psi = o.step_imex(op, psi, P.dt, **kw)
+    return psi
+
+
+@pytest.mark.parametrize("npol,naz,N,precision,stiff,tol", [
+    (8, 8, 3, "fp32", 1.0, 1e-5), (8, 8, 3, "fp32", 300.0, 1e-5),
+    (16, 32, 8, "fp32", 1.0, 1e-5), (16, 32, 8, "bf16x3", 1.0, 1e-4),
+    (16, 32, 8, "bf16x3", 300.0, 1e-4)])
+def test_imex_moments_rollout(npol, naz, N, precision, stiff, tol):
+    """10 IMEX steps with moment-projected HG scattering against the oracle's per-cell LU
+    solve; densities, source and inflow on; stiff = 300 is far past the explicit limit."""
+    P = _moment_problem(npol, naz, 61 + N, stiff, rho=True, source=True, inflow=True)
+    sig = I.hg_legendre_moments(0.8, N)
+    ref = _oracle_moment_imex(P, sig, 10)
+    S = _solver(P, precision=precision, moments=sig, fp64=True)
+    psi, _ = S.rollout(S.initial_state(), 10, imex=True)
+    err = rel_l2(S.to_user(psi).cpu().numpy(), ref)
+    print(f"imex moments N={N} nq={npol * naz} {precision} stiff={stiff}: {err:.2e}")
+    assert err <= tol
+    if precision == "fp32":
+        psi64, _ = S.rollout(S.initial_state(torch.float64), 10, fp64=True, imex=True)
+        err64 = rel_l2(S.to_user(psi64).cpu().numpy(), ref)
+        print(f"  fp64: {err64:.2e}")
+        assert err64 <= 1e-12
+    S.close()
+
+
+def test_imex_moments_step_arguments_vs_oracle():
+    """One step with alpha_t, alpha_s, inflow scale != 1 (FP64 template and FP32)."""
+    P = _moment_problem(8, 8, 67, 20.0, rho=True, source=True, inflow=True)
+    sig = I.hg_legendre_moments(0.6, 3)
+    kw = dict(alpha_t=1.3, alpha_s=0.6, inflow_scale=0.7)
+    ref = _oracle_moment_imex(P, sig, 1, **kw)
+    S = _solver(P, precision="fp32", moments=sig, fp64=True)
+    for fp64, tol in ((True, 1e-12), (False, 1e-5)):
+        a = S.initial_state(torch.float64 if fp64 else torch.float32)
+        b = torch.empty_like(a)
+        (S.step_imex_f64 if fp64 else S.step_imex)(a, b, **kw)
+        err = rel_l2(S.to_user(b).cpu().numpy(), ref)
+        print(f"imex moments args fp64={fp64}: {err:.2e}")
+        assert err <= tol
+    S.close()
+
+
+def test_imex_moments_degree0_equals_isotropic_imex():
+    """sigma_0 = 1 alone is the isotropic kernel 1/(4 pi): the moment-form IMEX must give the
+    closed-form isotropic IMEX (FP64, to rounding)."""
+    P = _moment_problem(8, 8, 71, 50.0, rho=True, source=True, inflow=True)
+    Sm = _solver(P, precision="fp32", moments=[1.0], fp64=True)
+    Si = _solver(P, fp64=True)
+    pm, _ = Sm.rollout(Sm.initial_state(torch.float64), 5, fp64=True, imex=True)
+    pi, _ = Si.rollout(Si.initial_state(torch.float64), 5, fp64=True, imex=True)
+    err = rel_l2(Sm.to_user(pm).cpu().numpy(), Si.to_user(pi).cpu().numpy())
+    print(f"imex degree 0 vs isotropic: {err:.2e}")
+    assert err <= 1e-13
+    Sm.close()
+    Si.close()
+
+
+def test_full_size_line_source_imex_moments_sampled():
+    """100 352 cells x 1024 ordinates (32 x 32, exact to degree 15), HG g=0.9 to degree 8,
+    BF16 hi+lo, cross sections x 5000 (dt sigma = 4.7, beyond the explicit collision limit; the
+    streaming part keeps its CFL step): one IMEX step from the pulse, sampled cells against
+    the oracle's LU solve one by one."""
+    P = I.build("linesource_hg_s32")
+    P = dataclasses.replace(P, sigma_t=5000.0 * P.sigma_t, sigma_s=5000.0 * P.sigma_s)
+    sig = I.hg_legendre_moments(0.9, 8)
+    from oracle import moments as mo
+    from oracle import oracle as o
+    S = _solver(P, precision="bf16x3", moments=sig)
+    a = S.initial_state()
+    b = torch.empty_like(a)
+    dt = P.dt
+    S.step_imex(a, b)
+    out = S.to_user(b).cpu().numpy()
+    S.close()
+    rng = np.random.default_rng(3)
+    hot = np.nonzero(np.sum(P.mesh.centroid ** 2, axis=1) < 0.01)[0]
+    cells = np.unique(np.concatenate([hot[:40], rng.choice(P.ncells, 40, False)]))
+    op = o.OracleProblem.from_problem(P, K=mo.moment_kernel(P.omega, P.w, sig))
+    ref = o.step_imex(op, P.psi0, dt, cells=cells)
+    err = rel_l2(out[cells], ref)
+    print(f"imex moments full-size sampled: {err:.2e}")
+    assert err <= 1e-4
+
+
+def test_imex_moments_rejections():
+    from paper_2205_08417_amd import snrt
+    # 16 azimuthal nodes do not integrate degree-8 products exactly (cos 16 phi aliases)
+    P = _moment_problem(16, 16, 73)
+    S = _solver(P, precision="fp32", moments=I.hg_legendre_moments(0.8, 8))
+    a = S.initial_state()
+    with pytest.raises(snrt.SnrtError) as ei:
+        S.step_imex(a, torch.empty_like(a))
+    assert ei.value.status == snrt.SNRT_E_UNSUPPORTED
+    S.close()
+    # isotropic and dense handles are not moment handles
+    P = _moment_problem(8, 8, 74)
+    for kw in ({}, {"precision": "fp32"}):
+        Q = dataclasses.replace(P, K=I.henyey_greenstein_kernel(P.omega, P.w, 0.5)) if kw else P
+        S = _solver(Q, **kw)
+        a = S.initial_state()
+        ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+        with pytest.raises(snrt.SnrtError) as ei:
+            snrt.snrt_step_imex_moments(S.mesh, S.quad, S.scatter, S.args(), a,
+                                        torch.empty_like(a), ws, ws.numel())
+        assert ei.value.status == snrt.SNRT_E_UNSUPPORTED
+        S.close()
+    # workspace too small, aliasing the state
+    S = _solver(P, precision="fp32", moments=[1.0, 0.5])
+    a = S.initial_state()
+    b = torch.empty_like(a)
+    with pytest.raises(snrt.SnrtError) as ei:
+        snrt.snrt_step_imex_moments(S.mesh, S.quad, S.scatter, S.args(), a, b, S.ws,
+                                    S.ws_bytes // 4 - 16)
+    assert ei.value.status == snrt.SNRT_E_ARG
+    with pytest.raises(snrt.SnrtError) as ei:
+        snrt.snrt_step_imex_moments(S.mesh, S.quad, S.scatter, S.args(), a, b, a, S.ws_bytes)
+    assert ei.value.status in (snrt.SNRT_E_ALIAS, snrt.SNRT_E_ARG)
+    S.close()

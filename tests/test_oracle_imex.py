@@ -94,3 +94,35 @@ def test_dense_kernel_system():
     S = (out * w[None, :]) @ K.T
     res = (1 + dt * P.sigma_t)[:, None] * out - (dt * P.sigma_s)[:, None] * S - b
     assert np.abs(res).max() <= 1e-12 * np.abs(b).max()
+
+
+def test_moment_kernel_harmonic_eigenstate():
+    """Moment-projected scattering (eq. SNEqns2): when the quadrature integrates products of
+    the harmonics exactly, K~ O[:, j] = sigma_l(j) O[:, j].  A uniform state psi = O[:, j] on
+    a torus streams to itself (the face normals of a closed cell sum to zero), so the IMEX
+    step gives psi / (a - c sigma_l(j)) per cell, a = 1 + dt sigma_t, c = dt sigma_s: a
+    closed form the oracle's LU solve does not use.  8 x 8 ordinates, degree 3 (exact:
+    8 polar nodes > 3, 8 azimuthal > 6)."""
+    from oracle import moments as mo
+    omega, w = I.product_quadrature(8, 8)
+    N = 3
+    sig_l = np.array([1.0, 0.7, -0.4, 0.25])
+    O, M = mo.moment_matrices(omega, w, N)
+    np.testing.assert_allclose(M @ O, np.eye((N + 1) ** 2), atol=1e-12)
+    K = mo.moment_kernel(omega, w, sig_l)
+    mesh = I.periodic_mesh(5)
+    base = small_problem(mesh, omega_w=(omega, w), K=K, seed=7)
+    rng = np.random.default_rng(7)
+    sig_t = rng.uniform(1.0, 30.0, base.ncells)
+    sig_s = sig_t * rng.uniform(0.2, 1.0, base.ncells)
+    dt = 3 * base.dt
+    a = 1 + dt * sig_t
+    c = dt * sig_s
+    for j in (0, 2, 5, 13):
+        l = int(np.floor(np.sqrt(j)))
+        psi0 = np.tile(O[:, j], (base.ncells, 1))
+        P = dataclasses.replace(base, sigma_t=sig_t, sigma_s=sig_s, psi0=psi0,
+                                source=np.zeros(base.ncells))
+        out = o.step_imex(o.OracleProblem.from_problem(P), psi0, dt)
+        want = psi0 / (a - c * sig_l[l])[:, None]
+        np.testing.assert_allclose(out, want, rtol=1e-10, atol=1e-12 * np.abs(psi0).max())
