@@ -104,10 +104,10 @@ def test_imex_rejects_dense_scattering():
 
 # ---------------------------------------------------------------- moment-form IMEX
 
-def _moment_problem(npol, naz, seed, stiff=1.0, **kw):
+def _moment_problem(npol, naz, seed, stiff=1.0, mesh=None, **kw):
     omega, w = I.product_quadrature(npol, naz)
-    P = small_problem(I.jittered_delaunay_mesh(12, 0.0, 1.0, seed=seed), omega_w=(omega, w),
-                      seed=seed, scatter=(0.5, 1.0), **kw)
+    mesh = mesh if mesh is not None else I.jittered_delaunay_mesh(12, 0.0, 1.0, seed=seed)
+    P = small_problem(mesh, omega_w=(omega, w), seed=seed, scatter=(0.5, 1.0), **kw)
     sig_t = P.sigma_t * stiff
     return dataclasses.replace(P, sigma_t=sig_t, sigma_s=0.9 * sig_t)
 
@@ -160,6 +160,23 @@ def test_imex_moments_step_arguments_vs_oracle():
         print(f"imex moments args fp64={fp64}: {err:.2e}")
         assert err <= tol
     S.close()
+
+
+def test_imex_moments_quad_mesh():
+    """Quadrilateral cells (four face slots) with densities, inflow and source, 16 x 32
+    ordinates to degree 8: FP64 template and BF16 hi+lo products, 5 steps."""
+    P = _moment_problem(16, 32, 69, 30.0, mesh=I.quad_grid_mesh(10, 7), rho=True,
+                        source=True, inflow=True)
+    sig = I.hg_legendre_moments(0.7, 8)
+    ref = _oracle_moment_imex(P, sig, 5)
+    for precision, fp64, tol in (("fp32", True, 1e-12), ("bf16x3", False, 1e-4)):
+        S = _solver(P, precision=precision, moments=sig, fp64=fp64)
+        psi, _ = S.rollout(S.initial_state(torch.float64 if fp64 else torch.float32), 5,
+                           fp64=fp64, imex=True)
+        err = rel_l2(S.to_user(psi).cpu().numpy(), ref)
+        print(f"imex moments quads {precision} fp64={fp64}: {err:.2e}")
+        assert err <= tol
+        S.close()
 
 
 def test_imex_moments_degree0_equals_isotropic_imex():
