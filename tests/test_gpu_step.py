@@ -281,6 +281,10 @@ def test_empty_mesh():
     snrt.snrt_step_imex(mesh, quad, sc, args, e, e)
     snrt.snrt_step_adjoint(mesh, quad, sc, args, e, e, e, e, e, None)
     snrt.snrt_step2_limited(mesh, quad, sc, args, snrt.limiter("venkatakrishnan", 0.5), e, e)
+    scm = snrt.snrt_scatter_moments(quad, [1.0, 0.5, 0.25], snrt.SNRT_FP32)
+    snrt.snrt_step_imex_moments(mesh, quad, scm, args, e, e, None, 0)
+    snrt.snrt_scatter_destroy(scm)
+    snrt.snrt_stream_copy(None, None, 0)
     pn = snrt.snrt_pn_create(3)
     assert snrt.snrt_pn_state_elems(mesh, pn) == 0
     snrt.snrt_pn_step(mesh, pn, args, e, e)
