@@ -255,3 +255,24 @@ def test_imex_moments_rejections():
         snrt.snrt_step_imex_moments(S.mesh, S.quad, S.scatter, S.args(), a, b, a, S.ws_bytes)
     assert ei.value.status in (snrt.SNRT_E_ALIAS, snrt.SNRT_E_ARG)
     S.close()
+
+
+def test_imex_moments_neumann_boundary():
+    """Neumann faces (ghost = the cell's own u) in the collision-free part, moment-form
+    implicit collisions, densities on: one step, FP64 template and FP32."""
+    from oracle import moments as mo
+    from oracle import oracle as o
+    from paper_2205_08417_amd import snrt
+    P = _moment_problem(8, 8, 75, 40.0, rho=True, source=True)
+    sig = I.hg_legendre_moments(0.75, 3)
+    op = o.OracleProblem.from_problem(P, K=mo.moment_kernel(P.omega, P.w, sig), neumann=True)
+    ref = o.step_imex(op, P.psi0, P.dt)
+    S = _solver(P, precision="fp32", moments=sig, fp64=True)
+    for fp64, tol in ((True, 1e-12), (False, 1e-5)):
+        a = S.initial_state(torch.float64 if fp64 else torch.float32)
+        b = torch.empty_like(a)
+        (S.step_imex_f64 if fp64 else S.step_imex)(a, b, boundary=snrt.SNRT_BC_NEUMANN)
+        err = rel_l2(S.to_user(b).cpu().numpy(), ref)
+        print(f"imex moments neumann fp64={fp64}: {err:.2e}")
+        assert err <= tol
+    S.close()
