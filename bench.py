@@ -155,7 +155,27 @@ def bench_dense(steps, warmup: int):
     ms_step = timed(one_step, nsteps, stream)
     final = product_rate(S, state[0])
     dense = product_rate(S, torch.rand_like(state[0]))
+    ref_state = state[0].clone()
     S.close()
+    # the two-product mode (the kernel split hi+lo, the state in BF16): the same whole run,
+    # and its final state against the three-product one
+    S2 = Solver(P, precision="bf16x2")
+    args2 = S2.args()
+    st2 = [S2.initial_state(), None]
+    st2[1] = torch.empty_like(st2[0])
+
+    def step2():
+        S2.step(st2[0], st2[1], args2)
+        st2.reverse()
+
+    for _ in range(min(warmup, 5)):
+        step2()
+    st2[0] = S2.initial_state()
+    torch.cuda.synchronize()
+    ms_x2 = timed(step2, nsteps, stream)
+    x2_diff = float(torch.linalg.vector_norm((st2[0] - ref_state).double()) /
+                    torch.linalg.vector_norm(ref_state.double()))
+    S2.close()
     # the same step with the FP32 scattering product (vector FMA kernel), 20 steps from the
     # initial state: the FP32 side of the FP32-vs-mixed comparison
     S32 = Solver(P, precision="fp32")
@@ -179,7 +199,9 @@ def bench_dense(steps, warmup: int):
             "value": P.ncells * P.nq / (ms_step * 1e-3), "unit": "cell-ordinate updates/s",
             "ms_per_step": ms_step,
             "fp32_product_ms_per_step": ms_fp32, "fp32_scatter_product": fp32_product,
-            "scatter_product": final, "scatter_product_dense_random_state": dense}
+            "scatter_product": final, "scatter_product_dense_random_state": dense,
+            "bf16x2": {"ms_per_step": ms_x2, "steps": nsteps,
+                       "rel_l2_vs_bf16x3_final_state": x2_diff}}
 
 
 def library_gemm_ceiling(M: int, nq: int, reps: int = 10):

@@ -63,7 +63,10 @@ typedef enum {
                          product's inner dimension is a multiple of 32 and its outer one a
                          multiple of 128; FP32 vector FMAs otherwise) */
     SNRT_BF16X3 = 1,  /* BF16 MFMA, hi+lo split of both operands, three products, FP32 accumulate */
-    SNRT_BF16X1 = 2   /* BF16 MFMA, single product (fast, ~1e-3 relative) */
+    SNRT_BF16X1 = 2,  /* BF16 MFMA, single product (fast, ~1e-3 relative) */
+    SNRT_BF16X2 = 3   /* BF16 MFMA, two products: the scattering operand split hi+lo, the
+                         state rounded to BF16 once (its rounding errors are independent
+                         across ordinates and average in the sum); FP32 accumulate */
 } snrt_precision;
 
 /* mesh flags */

@@ -83,7 +83,7 @@ __device__ __forceinline__ int swz(int r, int g) { return g ^ ((r >> 2) & 3); }
 
 // One BM x BN block tile of C = A X; lb is the logical block index (row block major, column
 // blocks fastest) and lds the block's two stages of NP planes.
-template <bool THREE, int BM, int BN, int FD, bool STAGGER>
+template <int P, int BM, int BN, int FD, bool STAGGER>
 __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
                                            const uint16_t* __restrict__ Bhi,
                                            const uint16_t* __restrict__ Blo,
@@ -92,7 +92,11 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
 {
     static_assert(BM == 64 || BM == 128 || BM == 256, "block rows");
     static_assert(BN == 128 || BN == 256, "block columns");
-    constexpr int NP = THREE ? 4 : 2;    // planes per stage: A hi, B hi (, A lo, B lo)
+    // P products: A_hi B_hi (+ A_hi B_lo (+ A_lo B_hi)); planes per stage: A hi, B hi, then
+    // A lo, B lo (P = 3) or B lo (P = 2)
+    static_assert(P >= 1 && P <= 3, "products");
+    constexpr int NP = P == 3 ? 4 : P == 2 ? 3 : 2;
+    constexpr int PL_AL = 2, PL_BL = P == 3 ? 3 : 2;
     constexpr int IM = BM / 64;          // MFMA tiles per wave along M
     constexpr int JN = BN / 128;         // MFMA tiles per wave along N
     constexpr int AV = BM / 64;          // A float4 per thread per chunk
@@ -131,15 +135,15 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
         for (int e = 0; e < BV; ++e) {
             const int p = tid + e * kThreads;
             gbh[slot][e] = *reinterpret_cast<const u32x4*>(Bhi + tile + (size_t)p * 8);
-            if constexpr (THREE)
+            if constexpr (P >= 2)
                 gbl[slot][e] = *reinterpret_cast<const u32x4*>(Blo + tile + (size_t)p * 8);
         }
     };
     auto stash = [&](int s, int slot) {
         uint16_t* Ah = lds + (s * NP + 0) * kPlane;
         uint16_t* Bh = lds + (s * NP + 1) * kPlane;
-        uint16_t* Al = lds + (s * NP + 2) * kPlane;
-        uint16_t* Bl = lds + (s * NP + 3) * kPlane;
+        uint16_t* Al = lds + (s * NP + PL_AL) * kPlane;
+        uint16_t* Bl = lds + (s * NP + PL_BL) * kPlane;
 #pragma unroll
         for (int e = 0; e < AV; ++e) {
             const int p = tid + e * kThreads;
@@ -148,13 +152,13 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
             uint32_t hi[2], lo[2];
             split4(ga[slot][e], hi, lo);
             *reinterpret_cast<uint2*>(&Ah[o]) = make_uint2(hi[0], hi[1]);
-            if constexpr (THREE) *reinterpret_cast<uint2*>(&Al[o]) = make_uint2(lo[0], lo[1]);
+            if constexpr (P == 3) *reinterpret_cast<uint2*>(&Al[o]) = make_uint2(lo[0], lo[1]);
         }
 #pragma unroll
         for (int e = 0; e < BV; ++e) {
             const int p = tid + e * kThreads;    // X is stored in the plane's order
             *reinterpret_cast<u32x4*>(&Bh[p * 8]) = gbh[slot][e];
-            if constexpr (THREE) *reinterpret_cast<u32x4*>(&Bl[p * 8]) = gbl[slot][e];
+            if constexpr (P >= 2) *reinterpret_cast<u32x4*>(&Bl[p * 8]) = gbl[slot][e];
         }
     };
 
@@ -188,19 +192,19 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
                           bf16x8 (&bl)[JN]) {
         const uint16_t* Ah = lds + (s * NP + 0) * kPlane;
         const uint16_t* Bh = lds + (s * NP + 1) * kPlane;
-        const uint16_t* Al = lds + (s * NP + 2) * kPlane;
-        const uint16_t* Bl = lds + (s * NP + 3) * kPlane;
+        const uint16_t* Al = lds + (s * NP + PL_AL) * kPlane;
+        const uint16_t* Bl = lds + (s * NP + PL_BL) * kPlane;
 #pragma unroll
         for (int j = 0; j < JN; ++j) {
             const int o = (wn + j * 32) * BK + foff[ks];
             bh[j] = *reinterpret_cast<const bf16x8*>(&Bh[o]);
-            if constexpr (THREE) bl[j] = *reinterpret_cast<const bf16x8*>(&Bl[o]);
+            if constexpr (P >= 2) bl[j] = *reinterpret_cast<const bf16x8*>(&Bl[o]);
         }
 #pragma unroll
         for (int i = 0; i < IM; ++i) {
             const int o = (wm + i * 32) * BK + foff[ks];
             ah[i] = *reinterpret_cast<const bf16x8*>(&Ah[o]);
-            if constexpr (THREE) al[i] = *reinterpret_cast<const bf16x8*>(&Al[o]);
+            if constexpr (P == 3) al[i] = *reinterpret_cast<const bf16x8*>(&Al[o]);
         }
     };
     auto multiply = [&](const bf16x8 (&ah)[IM], const bf16x8 (&al)[IM], const bf16x8 (&bh)[JN],
@@ -210,10 +214,10 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
 #pragma unroll
             for (int j = 0; j < JN; ++j) {
                 acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-                if constexpr (THREE) {
+                if constexpr (P >= 2)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                if constexpr (P == 3)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-                }
             }
     };
 
@@ -258,7 +262,7 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
 // Blocks [0, nmain) are 256 x 256 tiles of the first M1 rows; blocks [nmain, grid) are
 // TM x TN tiles of the remaining rows (none when nmain == grid).  Blocks are dispatched in
 // order, so the small tiles fill the compute units as the full ones finish.
-template <bool THREE, int MBN, int TM, int TN, int TFD, bool STAGGER>
+template <int P, int MBN, int TM, int TN, int TFD, bool STAGGER>
 __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict__ A,
                                                         const uint16_t* __restrict__ Bhi,
                                                         const uint16_t* __restrict__ Blo,
@@ -266,18 +270,18 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict_
                                                         int64_t M, int32_t K, int32_t N,
                                                         int64_t nmain)
 {
-    constexpr int NP = THREE ? 4 : 2;
+    constexpr int NP = P == 3 ? 4 : P == 2 ? 3 : 2;
     __shared__ __attribute__((aligned(16))) uint16_t lds[2 * NP * kPlane];
     const int64_t b = blockIdx.x;
     if (b < nmain) {
         // 256 x 256 tiles keep one chunk in flight (their multiply covers the load latency
         // and their accumulators leave no room for more); 256 x 128 tiles keep two
-        gemm_block<THREE, 256, MBN, MBN == 256 ? 1 : 2, STAGGER>(A, Bhi, Blo, C, M1, K, N,
+        gemm_block<P, 256, MBN, MBN == 256 ? 1 : 2, STAGGER>(A, Bhi, Blo, C, M1, K, N,
                                                                 xcd_remap(b, nmain), lds);
     } else {
         // nmain is a multiple of the XCD count, so the remap of the tail stays XCD-aware
         const int64_t nt = (int64_t)gridDim.x - nmain;
-        gemm_block<THREE, TM, TN, TFD, STAGGER>(A + M1 * K, Bhi, Blo, C + M1 * N, M - M1, K, N,
+        gemm_block<P, TM, TN, TFD, STAGGER>(A + M1 * K, Bhi, Blo, C + M1 * N, M - M1, K, N,
                                                 xcd_remap(b - nmain, nt), lds);
     }
 }
@@ -508,27 +512,31 @@ int device_cu_count() {
 
 template <int MBN, int TM, int TN>
 hipError_t launch_split(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
-                        int64_t M1, int64_t M, int32_t K, int32_t N, bool three,
+                        int64_t M1, int64_t M, int32_t K, int32_t N, int products,
                         hipStream_t st) {
     const int64_t nmain = ((M1 + 255) / 256) * (N / MBN);
     const int64_t ntail = ((M - M1 + TM - 1) / TM) * (N / TN);
     const dim3 grid((unsigned)(nmain + ntail));
-    auto go = [&](auto three_c, auto stagger_c) {
-        constexpr bool T3 = decltype(three_c)::value, SG = decltype(stagger_c)::value;
-        hipLaunchKernelGGL((k_gemm_bf16<T3, MBN, TM, TN, 4, SG>), grid, dim3(kThreads), 0, st,
+    auto go = [&](auto p_c, auto stagger_c) {
+        constexpr int PP = decltype(p_c)::value;
+        constexpr bool SG = decltype(stagger_c)::value;
+        hipLaunchKernelGGL((k_gemm_bf16<PP, MBN, TM, TN, 4, SG>), grid, dim3(kThreads), 0, st,
                            A, Bhi, Blo, C, M1, M, K, N, nmain);
         return hipGetLastError();
     };
-    auto by_stagger = [&](auto three_c) {
-        return tune().gemm_stagger ? go(three_c, std::true_type{})
-                                   : go(three_c, std::false_type{});
+    auto by_stagger = [&](auto p_c) {
+        return tune().gemm_stagger ? go(p_c, std::true_type{})
+                                   : go(p_c, std::false_type{});
     };
-    return three ? by_stagger(std::true_type{}) : by_stagger(std::false_type{});
+    if (products == 3) return by_stagger(std::integral_constant<int, 3>{});
+    if (products == 2) return by_stagger(std::integral_constant<int, 2>{});
+    return by_stagger(std::integral_constant<int, 1>{});
 }
 
 hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
-                            int64_t M, int32_t K, int32_t N, bool three_products, hipStream_t st) {
+                            int64_t M, int32_t K, int32_t N, int products, hipStream_t st) {
     if (M == 0) return hipSuccess;
+    if (products < 1 || products > 3) return hipErrorInvalidValue;
     if (K % BK != 0 || N % 128 != 0 || K == 0) return hipErrorNotSupported;
     // One 256 x 256 block (256 x 128 when N is an odd multiple of 128) per compute unit and
     // round (128 KB of LDS each).  When the last round would be mostly empty, its rows run
@@ -547,14 +555,14 @@ hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t*
     const int64_t rows1 = std::min<int64_t>(((tiles - rem) / nN) * 256, M);
     if (!wide) {
         if (quarter)
-            return launch_split<128, 64, 128>(A, Bhi, Blo, C, rows1, M, K, N, three_products, st);
-        return launch_split<128, 64, 128>(A, Bhi, Blo, C, M, M, K, N, three_products, st);
+            return launch_split<128, 64, 128>(A, Bhi, Blo, C, rows1, M, K, N, products, st);
+        return launch_split<128, 64, 128>(A, Bhi, Blo, C, M, M, K, N, products, st);
     }
     if (eighth)
-        return launch_split<256, 64, 128>(A, Bhi, Blo, C, rows1, M, K, N, three_products, st);
+        return launch_split<256, 64, 128>(A, Bhi, Blo, C, rows1, M, K, N, products, st);
     if (quarter)
-        return launch_split<256, 64, 256>(A, Bhi, Blo, C, rows1, M, K, N, three_products, st);
-    return launch_split<256, 64, 256>(A, Bhi, Blo, C, M, M, K, N, three_products, st);
+        return launch_split<256, 64, 256>(A, Bhi, Blo, C, rows1, M, K, N, products, st);
+    return launch_split<256, 64, 256>(A, Bhi, Blo, C, M, M, K, N, products, st);
 }
 
 template <int MBN, int TM, int TN>

@@ -467,7 +467,8 @@ snrt_status snrt_scatter_dense(snrt_scatter** out, const snrt_quad* q, const dou
     g_last_error.clear();
     SNRT_REQUIRE(out && q && K, SNRT_E_ARG, "snrt_scatter_dense: NULL argument");
     *out = nullptr;
-    SNRT_REQUIRE(precision == SNRT_FP32 || precision == SNRT_BF16X3 || precision == SNRT_BF16X1,
+    SNRT_REQUIRE(precision == SNRT_FP32 || precision == SNRT_BF16X3 || precision == SNRT_BF16X1 ||
+                     precision == SNRT_BF16X2,
                  SNRT_E_ARG, "snrt_scatter_dense: unknown precision");
     const int32_t nq = q->nq;
     if (precision != SNRT_FP32) {
@@ -506,7 +507,8 @@ snrt_status snrt_scatter_moments(snrt_scatter** out, const snrt_quad* q, int32_t
     g_last_error.clear();
     SNRT_REQUIRE(out && q && sigma_l, SNRT_E_ARG, "snrt_scatter_moments: NULL argument");
     *out = nullptr;
-    SNRT_REQUIRE(precision == SNRT_FP32 || precision == SNRT_BF16X3 || precision == SNRT_BF16X1,
+    SNRT_REQUIRE(precision == SNRT_FP32 || precision == SNRT_BF16X3 || precision == SNRT_BF16X1 ||
+                     precision == SNRT_BF16X2,
                  SNRT_E_ARG, "snrt_scatter_moments: unknown precision");
     SNRT_REQUIRE(degree >= 0 && degree <= 30, SNRT_E_ARG,
                  "snrt_scatter_moments: degree must be in [0, 30]");
@@ -713,7 +715,8 @@ hipError_t product32(const DenseB& B, const GemmOperand& op, const float* in, fl
     if (B.precision == SNRT_FP32)
         return op.t32 ? launch_gemm_f32mfma(in, op.t32, out, M, op.K, op.N, st)
                       : launch_gemm32(in, op.f32, out, M, op.K, op.N, st);
-    return launch_gemm_bf16(in, op.hi, op.lo, out, M, op.K, op.N, B.precision == SNRT_BF16X3, st);
+    const int products = B.precision == SNRT_BF16X3 ? 3 : B.precision == SNRT_BF16X2 ? 2 : 1;
+    return launch_gemm_bf16(in, op.hi, op.lo, out, M, op.K, op.N, products, st);
 }
 
 hipError_t scatter_product32(const snrt_scatter* sc, const float* A, float* C, int64_t M,

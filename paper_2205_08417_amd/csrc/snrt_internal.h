@@ -253,7 +253,7 @@ hipError_t launch_gemm32(const float* A, const float* B, float* C, int64_t M, in
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int64_t M, int32_t K,
                          int32_t N, hipStream_t st);
 hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
-                            int64_t M, int32_t K, int32_t N, bool three_products, hipStream_t st);
+                            int64_t M, int32_t K, int32_t N, int products, hipStream_t st);
 // Re-layout of an FP32 [K][N] matrix into the BF16 hi/lo operand format of the MFMA GEMM.
 hipError_t launch_split_bf16(const float* B, uint16_t* hi, uint16_t* lo, int32_t K, int32_t N,
                              hipStream_t st);

@@ -30,6 +30,7 @@ SNRT_E_NONFINITE = -7
 SNRT_FP32 = 0
 SNRT_BF16X3 = 1
 SNRT_BF16X1 = 2
+SNRT_BF16X2 = 3
 
 SNRT_REORDER_HILBERT = 0
 SNRT_NO_REORDER = 1

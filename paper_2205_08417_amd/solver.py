@@ -15,7 +15,8 @@ import torch
 from . import snrt
 from .inputs import Problem
 
-_PREC = {"fp32": snrt.SNRT_FP32, "bf16x3": snrt.SNRT_BF16X3, "bf16x1": snrt.SNRT_BF16X1}
+_PREC = {"fp32": snrt.SNRT_FP32, "bf16x3": snrt.SNRT_BF16X3, "bf16x2": snrt.SNRT_BF16X2,
+         "bf16x1": snrt.SNRT_BF16X1}
 
 
 def _require_gpu():
@@ -26,7 +27,8 @@ def _require_gpu():
 class Solver:
     """Device-resident S_N problem: mesh / quadrature / scattering handles and materials.
 
-    ``precision`` selects the dense scattering product (``fp32``, ``bf16x3``, ``bf16x1``);
+    ``precision`` selects the dense scattering product (``fp32``, ``bf16x3``, ``bf16x2``,
+    ``bf16x1``);
     isotropic problems ignore it.  ``moments`` (Legendre moments sigma_0..sigma_N of the
     scattering kernel) selects the moment-projected scattering O Sigma M instead of ``P.K``.  ``fp64`` additionally uploads FP64 copies of the
     materials for the FP64 parity template (:meth:`step_f64`).
