@@ -95,9 +95,9 @@ def _detector_weights(P):
     return (region * P.mesh.area)[:, None] * P.w[None, :]
 
 
-def _gpu_gradients(P, nsteps, ckpt, fp64=False, rho=False):
+def _gpu_gradients(P, nsteps, ckpt, fp64=False, rho=False, precision="fp32"):
     from paper_2205_08417_amd.solver import differentiable_rollout
-    S = _solver(P, fp64=fp64)
+    S = _solver(P, fp64=fp64, precision=precision)
     dt = torch.float64 if fp64 else torch.float32
     psi0 = S.to_internal(P.psi0, dt).requires_grad_(True)
     st = S.cells_to_internal(P.sigma_t, dt).requires_grad_(True)
@@ -143,6 +143,26 @@ def test_rollout_gradients_density_dense_fp32_vs_oracle():
         err = rel_l2(g[k], ref[k])
         print(f"dense gradient {k}: rel-L2 vs oracle adjoint = {err:.2e}")
         assert err <= 1e-4, k
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16x2"])
+def test_rollout_gradients_density_dense_bf16_vs_oracle(precision):
+    """The dense case above with the BF16 products (forward and transposed adjoint product),
+    held to the same 1e-4 gradient bar.  Measured: three products 3e-7 to 8e-7; two products
+    (state and adjoint state rounded to BF16 before the product) 2e-6 to 6.7e-5."""
+    from oracle import oracle as o
+    omega, w = I.product_quadrature(16, 16)
+    K = I.henyey_greenstein_kernel(omega, w, 0.8)
+    P = small_problem(I.jittered_delaunay_mesh(12, 0.0, 1.0, seed=41), omega_w=(omega, w), K=K,
+                      rho=True, seed=41, source=True, inflow=True, nsteps=25)
+    ref = o.rollout_gradient(o.OracleProblem.from_problem(P), P.psi0, P.dt, 25,
+                             dJ_dpsiN=_detector_weights(P))
+    g = _gpu_gradients(P, 25, 7, rho=True, precision=precision)
+    tol = 1e-4
+    for k in ("sigma_t", "sigma_s", "rho", "psi0"):
+        err = rel_l2(g[k], ref[k])
+        print(f"dense {precision} gradient {k}: rel-L2 vs oracle adjoint = {err:.2e}")
+        assert err <= tol, k
 
 
 def test_checkpoint_interval_is_bitwise_invisible():
