@@ -1,6 +1,7 @@
-// IMEX step (Sec. 4.2): implicit isotropic collision, explicit streaming and source.  The
+// IMEX step (Sec. 4.2): implicit collision, explicit streaming and source.  Isotropic: the
 // same persistent kernel as the explicit step with the closed-form per-cell solve of
-// (a I - c K~) psi' = b for the rank-one isotropic kernel K~ = w / (4 pi).
+// (a I - c K~) psi' = b for the rank-one isotropic kernel K~ = w / (4 pi).  Moment-projected
+// scattering: the per-cell diagonal and the final combine around the two moment products.
 #include "sn_step_kernels.h"
 
 namespace snrt {

@@ -706,9 +706,6 @@ StepArgs64 to64(const snrt_step_args_f64* a) {
     return r;
 }
 
-// S = Psi B (forward) or G = Lambda B^T (adjoint) into the workspace, FP32 state
-// C = A X0 [X1] (forward) or A X0^T-side chain (adjoint); scratch holds the moments between
-// the two products of the moment form ([M][mid]).
 // out = in X for one right operand of the chain, in the handle's precision
 hipError_t product32(const DenseB& B, const GemmOperand& op, const float* in, float* out,
                      int64_t M, hipStream_t st) {
@@ -719,6 +716,9 @@ hipError_t product32(const DenseB& B, const GemmOperand& op, const float* in, fl
     return launch_gemm_bf16(in, op.hi, op.lo, out, M, op.K, op.N, products, st);
 }
 
+// S = Psi B (forward) or G = Lambda B^T (adjoint) into the workspace, FP32 state
+// C = A X0 [X1] (forward) or A X0^T-side chain (adjoint); scratch holds the moments between
+// the two products of the moment form ([M][mid]).
 hipError_t scatter_product32(const snrt_scatter* sc, const float* A, float* C, int64_t M,
                              bool transpose, float* scratch, hipStream_t st) {
     const DenseB& B = sc->B;
