@@ -295,7 +295,33 @@ def bench_csd(steps, warmup: int):
     ms_step = run(fused_step)
     final = product_rate(S, state[0])
     dense = product_rate(S, torch.rand_like(state[0]))
+    dose_ref = dose.clone()
     S.close()
+    # the two-product mode over the same energy run: its dose against the three-product dose
+    S2 = Solver(P, precision="bf16x2")
+    args2 = [S2.args(inflow_scale=float(isc[n])) for n in range(nsteps)]
+    st2 = [S2.initial_state(), None]
+    st2[1] = torch.empty_like(st2[0])
+    dose2 = torch.zeros(S2.nc, dtype=torch.float64, device="cuda")
+
+    def fused_step2():
+        n = counter[0]
+        snrt.snrt_step_dose(S2.mesh, S2.quad, S2.scatter, args2[n], st2[0], st2[1],
+                            float(coeff[n]), dose2, S2.ws, S2.ws_bytes)
+        st2.reverse()
+        counter[0] = n + 1
+
+    counter[0] = 0
+    for _ in range(min(warmup, 5, nsteps)):
+        fused_step2()
+    counter[0] = 0
+    st2[0] = S2.initial_state()
+    dose2.zero_()
+    torch.cuda.synchronize()
+    ms_x2 = timed(fused_step2, nsteps, stream)
+    dose_diff = float(torch.linalg.vector_norm(dose2 - dose_ref) /
+                      torch.linalg.vector_norm(dose_ref))
+    S2.close()
     return {"workload": "csd_phantom_s512", "cells": P.ncells, "ordinates": P.nq,
             "scattering": "Henyey-Greenstein g=0.95, dense, column-normalised",
             "precision": "bf16x3 (hi+lo split, FP32 accumulate)", "steps": nsteps,
@@ -305,7 +331,8 @@ def bench_csd(steps, warmup: int):
             "note": "a step = scattering product + flux/update kernel with the dose of its "
                     "input fused (snrt_step_dose)",
             "ms_per_step_separate_dose_pass": ms_separate,
-            "scatter_product": final, "scatter_product_dense_random_state": dense}
+            "scatter_product": final, "scatter_product_dense_random_state": dense,
+            "bf16x2": {"ms_per_step": ms_x2, "dose_rel_l2_vs_bf16x3": dose_diff}}
 
 
 def bench_moments(steps, warmup: int, degree: int = 8):
