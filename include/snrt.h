@@ -275,6 +275,75 @@ snrt_status snrt_step_imex_moments_f64(const snrt_mesh* mesh, const snrt_quad* q
                                        double* psi_out, void* workspace, size_t workspace_bytes,
                                        void* stream);
 
+/* ---------------------------------------------------------------- rollouts */
+
+/* Per-step scalars of a multi-step call (the explicit time or energy loop of Alg. "Execution
+ * of the solver", one Runge-Kutta stage per step).  HOST arrays of nsteps doubles, each may
+ * be NULL (then the value in the step arguments serves every step):
+ *   alpha_t, alpha_s, inflow_scale  replace the fields of the same name for step n
+ *   dose_coeff                      the dose coefficient of step n (Sec. 2 pseudo-time dose,
+ *                                   left endpoint; see snrt_step_dose) */
+typedef struct {
+    const double* alpha_t;
+    const double* alpha_s;
+    const double* inflow_scale;
+    const double* dose_coeff;
+} snrt_schedule;
+
+/* nsteps explicit steps psi^{n+1} = step_n(psi^n), n = 0..nsteps-1, issued from the library on
+ * one stream (snrt_step with the step-n arguments; snrt_step_dose when dose is not NULL).
+ *   psi    device [ncells][nq]: psi^0 on entry, psi^nsteps on return
+ *   tmp    device [ncells][nq] scratch state, disjoint from psi
+ *   ckpt   NULL, or device [ceil(nsteps/ckpt_every)][ncells][nq], disjoint from psi and tmp:
+ *          on return ckpt[k] holds psi^(k*ckpt_every).  The step before a checkpointed state
+ *          writes it into its slot directly (no copies beyond one of psi^0).
+ *   dose   NULL, or device [ncells] FP64, accumulated (+=) with sched->dose_coeff[n] before
+ *          step n (requires sched->dose_coeff)
+ *   ws     as for snrt_step / snrt_step_dose (snrt_workspace_size bytes)
+ * States are bitwise those of nsteps separate snrt_step calls.  Errors: those of the step
+ * entry points, SNRT_E_ARG (nsteps < 0, ckpt_every < 1 with checkpoints, NULL buffers,
+ * dose without dose_coeff), SNRT_E_ALIAS (overlapping buffers).  Host arrays of the
+ * schedule are read during the call only; the call returns once every step is enqueued. */
+snrt_status snrt_rollout(const snrt_mesh* mesh, const snrt_quad* quad, const snrt_scatter* scatter,
+                         const snrt_step_args* args, const snrt_schedule* sched, int64_t nsteps,
+                         float* psi, float* tmp, float* ckpt, int32_t ckpt_every, double* dose,
+                         void* ws, size_t ws_bytes, void* stream);
+snrt_status snrt_rollout_f64(const snrt_mesh* mesh, const snrt_quad* quad,
+                             const snrt_scatter* scatter, const snrt_step_args_f64* args,
+                             const snrt_schedule* sched, int64_t nsteps, double* psi, double* tmp,
+                             double* ckpt, int32_t ckpt_every, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/* Reverse pass over a rollout made by snrt_rollout with checkpoints (same args, sched,
+ * nsteps and ckpt_every): for each checkpoint segment, last first, the segment's states are
+ * recomputed from its checkpoint into seg and walked backwards with snrt_step_adjoint:
+ *     lam^N = lam (on entry),  lam^n = T_n^T lam^{n+1} (+ the dose term below),
+ * with the gradient contributions of every step added to g_sigma_t, g_sigma_s, g_rho (device
+ * [ncells], each may be NULL; g_rho needs args->inv_rho).
+ *   ckpt    device, the checkpoints snrt_rollout wrote
+ *   seg     device [ckpt_every - 1][ncells][nq] scratch (may be NULL when ckpt_every == 1)
+ *   lam     device [ncells][nq]: dJ/dpsi^N on entry, dJ/dpsi^0 on return
+ *   tmp     device [ncells][nq] scratch
+ *   g_dose  NULL, or device [ncells] FP64 dJ/dD for a functional of the rollout's dose:
+ *           after the adjoint of step n, snrt_dose_adjoint(args->inv_rho,
+ *           sched->dose_coeff[n], g_dose) is applied to lam^n.  The explicit density term of
+ *           the dose is left to snrt_dose_density_grad.
+ * lam, tmp, seg and ckpt must be disjoint (SNRT_E_ALIAS).  Recomputed states are bitwise the
+ * forward ones (the kernels are deterministic), so the result does not depend on ckpt_every. */
+snrt_status snrt_rollout_adjoint(const snrt_mesh* mesh, const snrt_quad* quad,
+                                 const snrt_scatter* scatter, const snrt_step_args* args,
+                                 const snrt_schedule* sched, int64_t nsteps, const float* ckpt,
+                                 int32_t ckpt_every, float* seg, float* lam, float* tmp,
+                                 float* g_sigma_t, float* g_sigma_s, float* g_rho,
+                                 const double* g_dose, void* ws, size_t ws_bytes, void* stream);
+snrt_status snrt_rollout_adjoint_f64(const snrt_mesh* mesh, const snrt_quad* quad,
+                                     const snrt_scatter* scatter, const snrt_step_args_f64* args,
+                                     const snrt_schedule* sched, int64_t nsteps,
+                                     const double* ckpt, int32_t ckpt_every, double* seg,
+                                     double* lam, double* tmp, double* g_sigma_t,
+                                     double* g_sigma_s, double* g_rho, void* ws, size_t ws_bytes,
+                                     void* stream);
+
 /* ---------------------------------------------------------------- second-order step */
 
 /* Face-slot midpoints for the second-order scheme (Sec. 4.2, second order finite volume

@@ -268,7 +268,8 @@ def rollout(op: OracleProblem, psi0, dt: float, nsteps: int, alpha_t=None, alpha
 
 def rollout_gradient(op: OracleProblem, psi0, dt: float, nsteps: int,
                      dJ_dpsiN: Optional[np.ndarray] = None, dJ_ddose: Optional[np.ndarray] = None,
-                     alpha_t=None, alpha_s=None, inflow_scale=None, dose_coeff=None):
+                     alpha_t=None, alpha_s=None, inflow_scale=None, dose_coeff=None,
+                     ckpt_every: Optional[int] = None):
     """Reverse pass of :func:`rollout` for a functional J(psi^N, D) that is linear in its
     arguments with the given partial derivatives.  Returns a dict with ``psi0``,
     ``sigma_t``, ``sigma_s`` and (when ``op.rho`` is given) ``rho`` gradients.
@@ -276,21 +277,59 @@ def rollout_gradient(op: OracleProblem, psi0, dt: float, nsteps: int,
     Recurrence: lam^N = dJ/dpsi^N; lam^n = T_n^T lam^{n+1} + dJ/dpsi^n, where the dose term
     of step n gives dJ/dpsi^n_iq = coeff_n w_q (dJ/dD_i) / rho_i, and the explicit density
     derivative of D_i = (1/rho_i) sum_n coeff_n phi_i^n is -D_i/rho_i (dJ/dD_i).
+
+    ``ckpt_every``: None keeps every state psi^n of the forward pass; an integer K keeps only
+    psi^{kK} and, walking the segments backwards, steps each one forward again from its
+    stored state before the adjoint steps need it (the memory of a long run is then about
+    (N/K + K) states instead of N).  The states, and so the result, are the same either way.
     """
-    _, dose, states = rollout(op, psi0, dt, nsteps, alpha_t, alpha_s, inflow_scale, dose_coeff,
-                              keep_states=True)
     nc, nq = op.nc, op.nq
+
+    def scalars(n):
+        return (1.0 if alpha_t is None else float(alpha_t[n]),
+                1.0 if alpha_s is None else float(alpha_s[n]),
+                1.0 if inflow_scale is None else float(inflow_scale[n]))
+
+    if ckpt_every is None:
+        _, dose, states = rollout(op, psi0, dt, nsteps, alpha_t, alpha_s, inflow_scale,
+                                  dose_coeff, keep_states=True)
+        K = max(nsteps, 1)
+        kept = {0: None}
+    else:
+        if ckpt_every < 1:
+            raise ValueError("ckpt_every must be >= 1")
+        K = int(ckpt_every)
+        # forward pass keeping psi^n for n = 0, K, 2K, ... (and the dose)
+        psi = _f64(psi0).reshape(nc, nq).copy()
+        dose = np.zeros(nc) if dose_coeff is not None else None
+        kept = {}
+        for n in range(nsteps):
+            at, as_, isc = scalars(n)
+            if n % K == 0:
+                kept[n] = psi
+            if dose is not None:
+                dose_accumulate(op, psi, float(dose_coeff[n]), dose)
+            psi = step(op, psi, dt, at, as_, isc)
+        states = None
     lam = np.zeros((nc, nq)) if dJ_dpsiN is None else _f64(dJ_dpsiN).reshape(nc, nq).copy()
     g_t = np.zeros(nc)
     g_s = np.zeros(nc)
     g_r = np.zeros(nc) if op.rho is not None else None
     rho = op.rho if op.rho is not None else np.ones(nc)
-    for n in range(nsteps - 1, -1, -1):
-        at = 1.0 if alpha_t is None else float(alpha_t[n])
-        as_ = 1.0 if alpha_s is None else float(alpha_s[n])
-        lam = adjoint_step(op, states[n], lam, dt, at, as_, g_t, g_s, g_r)
-        if dJ_ddose is not None and dose_coeff is not None:
-            lam += float(dose_coeff[n]) * op.w[None, :] * (dJ_ddose / rho)[:, None]
+    for n0 in sorted(kept, reverse=True):
+        n1 = min(n0 + K, nsteps)
+        if states is None:
+            seg = [kept[n0]]
+            for n in range(n0, n1 - 1):
+                at, as_, isc = scalars(n)
+                seg.append(step(op, seg[-1], dt, at, as_, isc))
+        else:
+            seg = states[n0:n1]
+        for n in range(n1 - 1, n0 - 1, -1):
+            at, as_, _ = scalars(n)
+            lam = adjoint_step(op, seg[n - n0], lam, dt, at, as_, g_t, g_s, g_r)
+            if dJ_ddose is not None and dose_coeff is not None:
+                lam += float(dose_coeff[n]) * op.w[None, :] * (dJ_ddose / rho)[:, None]
     if g_r is not None and dJ_ddose is not None and dose is not None:
         g_r += -dose / rho * dJ_ddose
     return {"psi0": lam, "sigma_t": g_t, "sigma_s": g_s, "rho": g_r, "dose": dose}

@@ -52,6 +52,7 @@ EXPORTS = [
     "snrt_pn_operators", "snrt_pn_create", "snrt_pn_destroy", "snrt_pn_info",
     "snrt_pn_state_elems", "snrt_pn_layout", "snrt_pn_step", "snrt_pn_step_f64",
     "snrt_stream_copy", "snrt_step_imex_moments", "snrt_step_imex_moments_f64",
+    "snrt_rollout", "snrt_rollout_f64", "snrt_rollout_adjoint", "snrt_rollout_adjoint_f64",
 ]
 
 
@@ -87,6 +88,22 @@ class StepArgs(ctypes.Structure):
                 ("inflow", ctypes.c_void_p), ("inflow_scale", ctypes.c_double),
                 ("dt", ctypes.c_double), ("alpha_t", ctypes.c_double),
                 ("alpha_s", ctypes.c_double), ("boundary", ctypes.c_int32)]
+
+
+class Schedule(ctypes.Structure):
+    """``snrt_schedule``: per-step host arrays (FP64, each may be NULL) of a rollout."""
+    _fields_ = [("alpha_t", ctypes.c_void_p), ("alpha_s", ctypes.c_void_p),
+                ("inflow_scale", ctypes.c_void_p), ("dose_coeff", ctypes.c_void_p)]
+
+
+def schedule(alpha_t=None, alpha_s=None, inflow_scale=None, dose_coeff=None):
+    """A :class:`Schedule` over FP64 copies of the given sequences; the copies are kept on
+    the returned object so they outlive the call that reads them."""
+    keep = [None if v is None else np.ascontiguousarray(v, dtype=np.float64)
+            for v in (alpha_t, alpha_s, inflow_scale, dose_coeff)]
+    sch = Schedule(*[None if k is None else k.ctypes.data for k in keep])
+    sch._keep = keep
+    return sch
 
 
 _vp = ctypes.c_void_p
@@ -160,6 +177,20 @@ def lib() -> ctypes.CDLL:
         "snrt_step2_limited_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs),
                                          ctypes.POINTER(Limiter), _vp, _vp, _vp,
                                          ctypes.c_size_t, _vp]),
+        "snrt_rollout": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), ctypes.POINTER(Schedule),
+                               ctypes.c_int64, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp,
+                               ctypes.c_size_t, _vp]),
+        "snrt_rollout_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs),
+                                   ctypes.POINTER(Schedule), ctypes.c_int64, _vp, _vp, _vp,
+                                   ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
+        "snrt_rollout_adjoint": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs),
+                                       ctypes.POINTER(Schedule), ctypes.c_int64, _vp,
+                                       ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                       ctypes.c_size_t, _vp]),
+        "snrt_rollout_adjoint_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs),
+                                           ctypes.POINTER(Schedule), ctypes.c_int64, _vp,
+                                           ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                           ctypes.c_size_t, _vp]),
         "snrt_pn_operators": (_st, [ctypes.c_int32, _dp, _dp, _dp, _dp]),
         "snrt_pn_create": (_st, [ctypes.POINTER(_vp), ctypes.c_int32, _dp]),
         "snrt_pn_destroy": (None, [_vp]),
@@ -455,6 +486,52 @@ def snrt_stream_copy(src, dst, nbytes: int, stream=None) -> None:
     """Measurement helper: nontemporal device copy of ``nbytes`` bytes from ``src`` to ``dst``."""
     _check("snrt_stream_copy", lib().snrt_stream_copy(_ptr(src), _ptr(dst), int(nbytes),
                                                       _stream(stream)))
+
+
+def snrt_rollout(mesh, quad, scatter, args: StepArgs, sched: Optional[Schedule], nsteps: int,
+                 psi, tmp, ckpt=None, ckpt_every: int = 1, dose=None, ws=None, ws_bytes=0,
+                 stream=None) -> None:
+    _check("snrt_rollout",
+           lib().snrt_rollout(mesh, quad, scatter, ctypes.byref(args),
+                              None if sched is None else ctypes.byref(sched), int(nsteps),
+                              _ptr(psi), _ptr(tmp), _ptr(ckpt), int(ckpt_every), _ptr(dose),
+                              _ptr(ws), int(ws_bytes), _stream(stream)))
+
+
+def snrt_rollout_f64(mesh, quad, scatter, args: StepArgs, sched: Optional[Schedule],
+                     nsteps: int, psi, tmp, ckpt=None, ckpt_every: int = 1, ws=None, ws_bytes=0,
+                     stream=None) -> None:
+    _check("snrt_rollout_f64",
+           lib().snrt_rollout_f64(mesh, quad, scatter, ctypes.byref(args),
+                                  None if sched is None else ctypes.byref(sched), int(nsteps),
+                                  _ptr(psi), _ptr(tmp), _ptr(ckpt), int(ckpt_every), _ptr(ws),
+                                  int(ws_bytes), _stream(stream)))
+
+
+def snrt_rollout_adjoint(mesh, quad, scatter, args: StepArgs, sched: Optional[Schedule],
+                         nsteps: int, ckpt, ckpt_every: int, seg, lam, tmp, g_sigma_t=None,
+                         g_sigma_s=None, g_rho=None, g_dose=None, ws=None, ws_bytes=0,
+                         stream=None) -> None:
+    _check("snrt_rollout_adjoint",
+           lib().snrt_rollout_adjoint(mesh, quad, scatter, ctypes.byref(args),
+                                      None if sched is None else ctypes.byref(sched),
+                                      int(nsteps), _ptr(ckpt), int(ckpt_every), _ptr(seg),
+                                      _ptr(lam), _ptr(tmp), _ptr(g_sigma_t), _ptr(g_sigma_s),
+                                      _ptr(g_rho), _ptr(g_dose), _ptr(ws), int(ws_bytes),
+                                      _stream(stream)))
+
+
+def snrt_rollout_adjoint_f64(mesh, quad, scatter, args: StepArgs, sched: Optional[Schedule],
+                             nsteps: int, ckpt, ckpt_every: int, seg, lam, tmp, g_sigma_t=None,
+                             g_sigma_s=None, g_rho=None, ws=None, ws_bytes=0,
+                             stream=None) -> None:
+    _check("snrt_rollout_adjoint_f64",
+           lib().snrt_rollout_adjoint_f64(mesh, quad, scatter, ctypes.byref(args),
+                                          None if sched is None else ctypes.byref(sched),
+                                          int(nsteps), _ptr(ckpt), int(ckpt_every), _ptr(seg),
+                                          _ptr(lam), _ptr(tmp), _ptr(g_sigma_t),
+                                          _ptr(g_sigma_s), _ptr(g_rho), _ptr(ws), int(ws_bytes),
+                                          _stream(stream)))
 
 
 # ------------------------------------------------------------------------------ P_N solver

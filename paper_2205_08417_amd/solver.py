@@ -193,7 +193,6 @@ class Solver:
         b = torch.empty_like(a)
         if dose_coeff is not None and dose is None:
             dose = torch.zeros(self.nc, dtype=torch.float64, device=self.device)
-        fused_dose = order == 1 and not imex
         if fp64 and self.mats64 is None:
             self.mats64 = self._materials(torch.float64)
         if imex and self.is_moments:
@@ -219,6 +218,18 @@ class Solver:
             raise ValueError("order is 1 (explicit Euler, first-order flux) or 2 (Heun, "
                              "limited linear reconstruction)")
         stream = torch.cuda.current_stream().cuda_stream
+        if order == 1 and not imex:
+            # the whole explicit Euler loop in one library call (snrt_rollout)
+            sched = snrt.schedule(alpha_t, alpha_s, inflow_scale, dose_coeff)
+            base = self.args(fp64=fp64)
+            if fp64:
+                snrt.snrt_rollout_f64(self.mesh, self.quad, self.scatter, base, sched, nsteps,
+                                      a, b, None, 1, ws, ws_bytes, stream)
+            else:
+                snrt.snrt_rollout(self.mesh, self.quad, self.scatter, base, sched, nsteps, a, b,
+                                  None, 1, dose if dose_coeff is not None else None, ws,
+                                  ws_bytes, stream)
+            return a, dose
         pa, pb = a.data_ptr(), b.data_ptr()
         cache = {}
         for n in range(nsteps):
@@ -228,16 +239,10 @@ class Solver:
             if key not in cache:
                 cache[key] = self.args(alpha_t=key[0], alpha_s=key[1], inflow_scale=key[2],
                                        fp64=fp64)
-            if dose_coeff is not None and fused_dose:
-                # the dose of the state entering the step, from the rows the step reads
-                snrt.snrt_step_dose(self.mesh, self.quad, self.scatter, cache[key], pa, pb,
-                                    float(dose_coeff[n]), dose, ws, ws_bytes, stream)
-            else:
-                if dose_coeff is not None:
-                    snrt.snrt_dose_accumulate(self.mesh, self.quad, pa, self.mats32["inv_rho"],
-                                              float(dose_coeff[n]), dose, stream)
-                step(self.mesh, self.quad, self.scatter, cache[key], pa, pb, ws, ws_bytes,
-                     stream)
+            if dose_coeff is not None:
+                snrt.snrt_dose_accumulate(self.mesh, self.quad, pa, self.mats32["inv_rho"],
+                                          float(dose_coeff[n]), dose, stream)
+            step(self.mesh, self.quad, self.scatter, cache[key], pa, pb, ws, ws_bytes, stream)
             pa, pb = pb, pa
         return (a if pa == a.data_ptr() else b), dose
 
@@ -280,9 +285,10 @@ class SNRollout(torch.autograd.Function):
 
     Inputs (device tensors, internal cell order): ``psi0`` [nc, nq] (FP32, or FP64 for the
     parity template), per-cell ``sigma_t``, ``sigma_s`` and optional density ``rho``.  The
-    forward pass keeps the state every ``ckpt_every`` steps; the backward pass recomputes
-    each segment from its checkpoint (bit-identical: the kernels are deterministic) and walks
-    it backwards with the library's adjoint step:
+    forward pass (one ``snrt_rollout`` call) keeps the state every ``ckpt_every`` steps; the
+    backward pass (one ``snrt_rollout_adjoint`` call) recomputes each segment from its
+    checkpoint (bit-identical: the kernels are deterministic) and walks it backwards with the
+    library's adjoint step:
 
         lam^N = dJ/dpsi^N,  lam^n = T_n^T lam^{n+1} + dJ/dpsi^n,
         dJ/dsigma_t, dJ/dsigma_s, dJ/drho accumulated by the adjoint kernel per step.
@@ -299,53 +305,41 @@ class SNRollout(torch.autograd.Function):
         fp64 = psi0.dtype == torch.float64
         if fp64 and dose_coeff is not None:
             raise ValueError("the dose accumulation runs on FP32 states")
-        at, as_, isc = (_seq(alpha_t, nsteps), _seq(alpha_s, nsteps), _seq(inflow_scale, nsteps))
+        if ckpt_every < 1:
+            raise ValueError("ckpt_every must be >= 1")
         inv_rho = None if rho is None else torch.reciprocal(rho.detach()).contiguous()
         st, ss = sigma_t.detach().contiguous(), sigma_s.detach().contiguous()
         M = S.mats64 if fp64 else S.mats32
         if M is None:
             S.mats64 = S._materials(torch.float64)
             M = S.mats64
-
-        cache = {}
-
-        def args(n):
-            # one argument record per distinct (alpha_t, alpha_s, inflow_scale)
-            key = (at[n], as_[n], isc[n])
-            if key not in cache:
-                cache[key] = snrt.step_args(st, ss, S.P.dt, inv_rho=inv_rho, source=M["source"],
-                                            inflow=M["inflow"], inflow_scale=isc[n],
-                                            alpha_t=at[n], alpha_s=as_[n])
-            return cache[key]
-
-        stepper = snrt.snrt_step_f64 if fp64 else snrt.snrt_step
+        # the step arguments over the differentiable materials; the per-step scalars come
+        # from the schedule
+        base = snrt.step_args(st, ss, S.P.dt, inv_rho=inv_rho, source=M["source"],
+                              inflow=M["inflow"])
+        sched = snrt.schedule(_seq(alpha_t, nsteps), _seq(alpha_s, nsteps),
+                              _seq(inflow_scale, nsteps),
+                              None if dose_coeff is None else _seq(dose_coeff, nsteps))
         stream = torch.cuda.current_stream().cuda_stream
         ws = S.ws.data_ptr() if S.ws is not None else None
         a = psi0.detach().contiguous().clone()
         b = torch.empty_like(a)
-        pa, pb = a.data_ptr(), b.data_ptr()
         dose = (torch.zeros(S.nc, dtype=torch.float64, device=a.device)
                 if dose_coeff is not None else None)
-        # one allocation holds every checkpoint (no allocator traffic inside the time loop)
+        # one allocation holds every checkpoint; the library's rollout writes each
+        # checkpointed state into its slot directly
         n_ck = (nsteps + ckpt_every - 1) // ckpt_every
         ck_store = torch.empty((max(n_ck, 1),) + tuple(a.shape), dtype=a.dtype, device=a.device)
-        ckpts = []
-        for n in range(nsteps):
-            if n % ckpt_every == 0:
-                dst = ck_store[len(ckpts)]
-                dst.copy_(a if pa == a.data_ptr() else b)
-                ckpts.append(dst)
-            if dose is not None:
-                snrt.snrt_step_dose(S.mesh, S.quad, S.scatter, args(n), pa, pb,
-                                    float(dose_coeff[n]), dose, ws, S.ws_bytes, stream)
-            else:
-                stepper(S.mesh, S.quad, S.scatter, args(n), pa, pb, ws, S.ws_bytes, stream)
-            pa, pb = pb, pa
-        a = a if pa == a.data_ptr() else b
+        if fp64:
+            snrt.snrt_rollout_f64(S.mesh, S.quad, S.scatter, base, sched, nsteps, a, b, ck_store,
+                                  ckpt_every, ws, S.ws_bytes, stream)
+        else:
+            snrt.snrt_rollout(S.mesh, S.quad, S.scatter, base, sched, nsteps, a, b, ck_store,
+                              ckpt_every, dose, ws, S.ws_bytes, stream)
         ctx.S, ctx.fp64, ctx.nsteps, ctx.K = S, fp64, nsteps, ckpt_every
-        ctx.args, ctx.ckpts, ctx.dose_coeff = args, ckpts, dose_coeff
+        ctx.base, ctx.sched, ctx.ck_store = base, sched, ck_store
         ctx.stream, ctx.ws = stream, ws
-        ctx.has_rho = rho is not None
+        ctx.has_rho, ctx.has_dose = rho is not None, dose_coeff is not None
         ctx.save_for_backward(st, ss, inv_rho if inv_rho is not None else st,
                               dose if dose is not None else st)
         if dose is not None:
@@ -358,43 +352,29 @@ class SNRollout(torch.autograd.Function):
         st, ss, inv_rho, dose = ctx.saved_tensors
         if not ctx.has_rho:
             inv_rho = None
-        if ctx.dose_coeff is None:
+        if not ctx.has_dose:
             dose = None
         dt = torch.float64 if fp64 else torch.float32
         dev = st.device
         lam = (torch.zeros((S.nc, S.nq), dtype=dt, device=dev) if g_psi is None
                else g_psi.to(dt).contiguous().clone())
-        lam_new = torch.empty_like(lam)
+        tmp = torch.empty_like(lam)
         g_t = torch.zeros(S.nc, dtype=dt, device=dev)
         g_s = torch.zeros(S.nc, dtype=dt, device=dev)
         g_r = torch.zeros(S.nc, dtype=dt, device=dev) if inv_rho is not None else None
         gd = None if (g_dose is None or dose is None) else g_dose.to(torch.float64).contiguous()
-        stepper = snrt.snrt_step_f64 if fp64 else snrt.snrt_step
-        adjoint = snrt.snrt_step_adjoint_f64 if fp64 else snrt.snrt_step_adjoint
-        stream, ws = ctx.stream, ctx.ws
-        seg = torch.empty((K,) + tuple(lam.shape), dtype=lam.dtype, device=lam.device)
-        seg_ptr = [seg[i].data_ptr() for i in range(K)]
-        pl, pn = lam.data_ptr(), lam_new.data_ptr()
-        gtp, gsp = g_t.data_ptr(), g_s.data_ptr()
-        grp = g_r.data_ptr() if g_r is not None else None
-        for k in range(len(ctx.ckpts) - 1, -1, -1):
-            n0 = k * K
-            L = min(K, N - n0)
-            states = [ctx.ckpts[k].data_ptr()] + seg_ptr[1:L]
-            for i in range(L - 1):                          # recompute the segment
-                stepper(S.mesh, S.quad, S.scatter, ctx.args(n0 + i), states[i], states[i + 1],
-                        ws, S.ws_bytes, stream)
-            for i in range(L - 1, -1, -1):
-                n = n0 + i
-                adjoint(S.mesh, S.quad, S.scatter, ctx.args(n), states[i], pl, pn, gtp, gsp, grp,
-                        ws, S.ws_bytes, stream)
-                if gd is not None:
-                    snrt.snrt_dose_adjoint(S.mesh, S.quad, inv_rho, float(ctx.dose_coeff[n]), gd,
-                                           pn, stream)
-                pl, pn = pn, pl
-        lam = lam if pl == lam.data_ptr() else lam_new
+        seg = (torch.empty((K - 1,) + tuple(lam.shape), dtype=lam.dtype, device=dev)
+               if K > 1 else None)
+        if fp64:
+            snrt.snrt_rollout_adjoint_f64(S.mesh, S.quad, S.scatter, ctx.base, ctx.sched, N,
+                                          ctx.ck_store, K, seg, lam, tmp, g_t, g_s, g_r, ctx.ws,
+                                          S.ws_bytes, ctx.stream)
+        else:
+            snrt.snrt_rollout_adjoint(S.mesh, S.quad, S.scatter, ctx.base, ctx.sched, N,
+                                      ctx.ck_store, K, seg, lam, tmp, g_t, g_s, g_r, gd, ctx.ws,
+                                      S.ws_bytes, ctx.stream)
         if gd is not None and g_r is not None:
-            snrt.snrt_dose_density_grad(S.mesh, dose, inv_rho, gd, g_r)
+            snrt.snrt_dose_density_grad(S.mesh, dose, inv_rho, gd, g_r, ctx.stream)
         return (lam, g_t, g_s, g_r, None, None, None, None, None, None, None)
 
 

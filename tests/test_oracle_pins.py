@@ -388,3 +388,52 @@ def test_dose_gradient_central_fd(oracle_lib):
         jm = J(op.replace(rho=r))
         np.testing.assert_allclose(g["rho"][c], (jp - jm) / (2 * h), rtol=1e-6,
                                    atol=1e-7 * np.max(np.abs(g["rho"])))
+
+
+def test_checkpointed_reverse_pass_matches_stored_states_and_fd(oracle_lib):
+    """The reverse pass that keeps every K-th state and steps each segment forward again
+    returns bitwise the gradients of the one that keeps every state (the FP64 steps are
+    deterministic), for K dividing N or not, and those gradients agree with FP64 central
+    differences of the dose functional with per-step coefficients."""
+    o = oracle_lib
+    m = I.jittered_delaunay_mesh(8, 0.0, 1.0, seed=23)
+    omega, w = I.product_quadrature(4, 4)
+    K = I.henyey_greenstein_kernel(omega, w, 0.6)
+    nc, nq = m.ncells, w.size
+    rng = np.random.default_rng(23)
+    rho = rng.uniform(0.3, 2.0, nc)
+    top = np.abs(m.bface_mid[:, 1] - 1.0) < 1e-12
+    inflow = np.where(top[:, None], 1.0, 0.0) * np.exp(-(omega[:, 1] + 1) ** 2)[None, :]
+    op = _op_from_mesh(o, m, omega, w, sigma_t=rng.uniform(0.5, 1.5, nc),
+                       sigma_s=rng.uniform(0.2, 1.0, nc), K=K, rho=rho,
+                       inflow=np.ascontiguousarray(inflow))
+    nsteps = 17
+    dt = I.cfl_dt(m, omega, 0.5, rho)
+    at = np.linspace(1.0, 1.4, nsteps)
+    isc = np.linspace(2.0, 1.0, nsteps)
+    coeff = dt * np.linspace(1.0, 3.0, nsteps)
+    dJdD = m.area * rng.standard_normal(nc)
+    kw = dict(dJ_ddose=dJdD, alpha_t=at, alpha_s=at, inflow_scale=isc, dose_coeff=coeff)
+    psi0 = np.zeros((nc, nq))
+    ref = o.rollout_gradient(op, psi0, dt, nsteps, **kw)
+    for K in (1, 4, 17, 40):
+        g = o.rollout_gradient(op, psi0, dt, nsteps, ckpt_every=K, **kw)
+        for k in ("psi0", "sigma_t", "sigma_s", "rho", "dose"):
+            assert np.array_equal(g[k], ref[k]), (K, k)
+
+    def J(opp):
+        _, dose, _ = o.rollout(opp, psi0, dt, nsteps, alpha_t=at, alpha_s=at,
+                               inflow_scale=isc, dose_coeff=coeff)
+        return np.sum(dJdD * dose)
+
+    g = o.rollout_gradient(op, psi0, dt, nsteps, ckpt_every=5, **kw)
+    for attr in ("sigma_t", "rho"):
+        for c in rng.choice(nc, 4, replace=False):
+            h = 1e-6 * max(abs(getattr(op, attr)[c]), 1.0)
+            arr = getattr(op, attr).copy()
+            arr[c] += h
+            jp = J(op.replace(**{attr: arr}))
+            arr[c] -= 2 * h
+            jm = J(op.replace(**{attr: arr}))
+            np.testing.assert_allclose(g[attr][c], (jp - jm) / (2 * h), rtol=1e-6,
+                                       atol=1e-7 * np.max(np.abs(g[attr])))
