@@ -199,6 +199,22 @@ snrt_status snrt_step_dose(const snrt_mesh* mesh, const snrt_quad* quad,
                            const float* psi_in, float* psi_out, double coeff, double* dose,
                            void* ws, size_t ws_bytes, void* stream);
 
+/* snrt_step_dose for callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid allocation): the same step and dose with isotropic
+ * scattering, bitwise the results of snrt_step_dose, but the step's FP64 per-cell dose
+ * partials live in a static device array of the library (8 MiB per device, held until the
+ * process ends) instead of a workspace.  Needs no workspace and allocates nothing.
+ * Limits and errors: at most 1048576 cells (SNRT_E_UNSUPPORTED above); dense and moment
+ * scatter handles need the product workspace and are refused (SNRT_E_UNSUPPORTED; use
+ * snrt_step_dose); otherwise the errors of snrt_step_dose.  Every call on a device shares
+ * that device's array: calls that overlap in time on one device (other streams or threads)
+ * race and must be serialised by the caller.  Nothing needs clearing between calls (each
+ * call writes every partial it reads). */
+snrt_status snrt_step_dose_noalloc(const snrt_mesh* mesh, const snrt_quad* quad,
+                                   const snrt_scatter* scatter, const snrt_step_args* args,
+                                   const float* psi_in, float* psi_out, double coeff,
+                                   double* dose, void* stream);
+
 /* The same step in FP64 throughout (parity template of the FP32 kernels).  Dense scattering
  * runs as an FP64 product regardless of the scatter handle's precision. */
 snrt_status snrt_step_f64(const snrt_mesh* mesh, const snrt_quad* quad,

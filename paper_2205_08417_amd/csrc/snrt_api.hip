@@ -749,6 +749,18 @@ hipError_t scatter_product64(const snrt_scatter* sc, const double* A, double* C,
 
 }  // namespace
 
+namespace snrt {
+
+snrt_status check_step32(const char* fn, const snrt_mesh* m, const snrt_quad* q,
+                         const snrt_scatter* sc, const snrt_step_args* a, const float* in,
+                         float* out, void* ws, size_t ws_bytes) {
+    return check_step_common(fn, m, q, sc, a, sizeof(float), in, out, ws, ws_bytes);
+}
+
+StepArgs32 step_args32(const snrt_step_args* a) { return to32(a); }
+
+}  // namespace snrt
+
 extern "C" {
 
 snrt_status snrt_step(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,

@@ -221,6 +221,13 @@ struct StepArgs64 {
     int32_t neumann;
 };
 
+// Argument checks of the FP32 step entry points (handles, devices, scalars, sizes, alignment,
+// aliasing, the dense product's workspace) and the conversion of their arguments.
+snrt_status check_step32(const char* fn, const snrt_mesh* m, const snrt_quad* q,
+                         const snrt_scatter* sc, const snrt_step_args* a, const float* in,
+                         float* out, void* ws, size_t ws_bytes);
+StepArgs32 step_args32(const snrt_step_args* a);
+
 // dose_part: with the fused dose, the [nc * items per row] FP64 weighted sums of psi_in
 hipError_t launch_step32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
                          const float* psi_in, float* psi_out, const float* S, hipStream_t st,

@@ -53,6 +53,7 @@ EXPORTS = [
     "snrt_pn_state_elems", "snrt_pn_layout", "snrt_pn_step", "snrt_pn_step_f64",
     "snrt_stream_copy", "snrt_step_imex_moments", "snrt_step_imex_moments_f64",
     "snrt_rollout", "snrt_rollout_f64", "snrt_rollout_adjoint", "snrt_rollout_adjoint_f64",
+    "snrt_step_dose_noalloc",
 ]
 
 
@@ -171,6 +172,8 @@ def lib() -> ctypes.CDLL:
                                  ctypes.c_size_t, _vp]),
         "snrt_step_dose": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp,
                                  ctypes.c_double, _vp, _vp, ctypes.c_size_t, _vp]),
+        "snrt_step_dose_noalloc": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp,
+                                         ctypes.c_double, _vp, _vp]),
         "snrt_step2_limited": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs),
                                      ctypes.POINTER(Limiter), _vp, _vp, _vp, ctypes.c_size_t,
                                      _vp]),
@@ -387,6 +390,14 @@ def snrt_step_dose(mesh, quad, scatter, args: StepArgs, psi_in, psi_out, coeff: 
            lib().snrt_step_dose(mesh, quad, scatter, ctypes.byref(args), _ptr(psi_in),
                                 _ptr(psi_out), float(coeff), _ptr(dose), _ptr(ws), int(ws_bytes),
                                 _stream(stream)))
+
+
+def snrt_step_dose_noalloc(mesh, quad, scatter, args: StepArgs, psi_in, psi_out, coeff: float,
+                           dose, stream=None) -> None:
+    _check("snrt_step_dose_noalloc",
+           lib().snrt_step_dose_noalloc(mesh, quad, scatter, ctypes.byref(args), _ptr(psi_in),
+                                        _ptr(psi_out), float(coeff), _ptr(dose),
+                                        _stream(stream)))
 
 
 def snrt_step2_limited(mesh, quad, scatter, args: StepArgs, lim: Optional[Limiter], psi_in,
