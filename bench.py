@@ -117,9 +117,11 @@ def product_rate(S, psi, reps: int = 10, passes: int = 3, kernel: str = "k_gemm_
     peak = BF16_PEAK_TFLOPS if peak is None else peak
     sbuf = torch.empty_like(psi)
     stream = torch.cuda.current_stream()
-    snrt.snrt_scatter_apply(S.mesh, S.quad, S.scatter, psi, sbuf)
+    apply = lambda: snrt.snrt_scatter_apply(S.mesh, S.quad, S.scatter, psi, sbuf, 0, S.ws,  # noqa
+                                            S.ws_bytes)
+    apply()
     torch.cuda.synchronize()
-    ms = timed(lambda: snrt.snrt_scatter_apply(S.mesh, S.quad, S.scatter, psi, sbuf), reps, stream)
+    ms = timed(apply, reps, stream)
     tflops = passes * 2.0 * S.nc * S.nq * S.nq / (ms * 1e-3) / 1e12
     return {"kernel": kernel, "ms": ms, "executed_tflops": tflops,
             "peak_tflops": peak, "mfma_utilization": tflops / peak}

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SNRT_ABI_VERSION 1
+#define SNRT_ABI_VERSION 2
 
 typedef enum {
     SNRT_OK = 0,
@@ -64,9 +64,16 @@ typedef enum {
                          multiple of 128; FP32 vector FMAs otherwise) */
     SNRT_BF16X3 = 1,  /* BF16 MFMA, hi+lo split of both operands, three products, FP32 accumulate */
     SNRT_BF16X1 = 2,  /* BF16 MFMA, single product (fast, ~1e-3 relative) */
-    SNRT_BF16X2 = 3   /* BF16 MFMA, two products: the scattering operand split hi+lo, the
+    SNRT_BF16X2 = 3,  /* BF16 MFMA, two products: the scattering operand split hi+lo, the
                          state rounded to BF16 once (its rounding errors are independent
                          across ordinates and average in the sum); FP32 accumulate */
+    SNRT_FP16X3 = 4   /* FP16 MFMA, hi+lo split of both operands, three products, FP32
+                         accumulate.  FP16 has 11 significant bits but a narrow exponent
+                         range, so every state row is scaled by its own power of two (its
+                         largest magnitude into [2^13, 2^14)) and the operand by one power of
+                         two before the split; the product's rows are scaled back exactly.
+                         The row scales come from a pass over the state into the workspace
+                         (4 bytes per cell). */
 } snrt_precision;
 
 /* mesh flags */
@@ -116,8 +123,9 @@ void snrt_quad_destroy(snrt_quad* quad);
  * snrt_scatter_isotropic: K = 1/(4 pi) (Sigma_t = Sigma_{s,0} convention of Sec. 2), reduced
  *   per cell without forming K.
  * snrt_scatter_dense: K host [nq*nq] row-major (K[q*nq+p]), applied as a GEMM
- *   S = Psi B with B[p][q] = w_p K[q][p], at the given precision.  BF16 modes need
- *   nq % 256 == 0 (SNRT_E_UNSUPPORTED otherwise). */
+ *   S = Psi B with B[p][q] = w_p K[q][p], at the given precision.  The BF16 and FP16 modes
+ *   need nq % 32 == 0 (SNRT_E_UNSUPPORTED otherwise); their operand is zero-padded to a
+ *   multiple of 128 columns. */
 snrt_status snrt_scatter_isotropic(snrt_scatter** out, const snrt_quad* quad);
 snrt_status snrt_scatter_dense(snrt_scatter** out, const snrt_quad* quad, const double* K,
                                snrt_precision precision);
@@ -128,9 +136,9 @@ snrt_status snrt_scatter_dense(snrt_scatter** out, const snrt_quad* quad, const 
  * kernel's Legendre moments 2 pi int P_l(mu) k(mu) dmu, repeated on the 2l+1 moments of degree
  * l (sigma_0 = 1 conserves particles; Henyey-Greenstein: g^l).  Equivalent to the dense
  * kernel K[q][p] = sum_j m_j(Omega_q) sigma_l(j) m_j(Omega_p), applied as two products through
- * the moments.  0 <= degree <= 30.  BF16 modes need nq % 256 == 0 and pad the moment count
- * with zeros to a multiple of 128.  Steps with this handle need snrt_workspace_size bytes;
- * snrt_scatter_apply does not accept it (SNRT_E_UNSUPPORTED). */
+ * the moments.  0 <= degree <= 30.  The BF16 and FP16 modes need nq % 32 == 0 and pad the
+ * moment count with zeros to a multiple of 128.  Steps with this handle need
+ * snrt_workspace_size bytes. */
 snrt_status snrt_scatter_moments(snrt_scatter** out, const snrt_quad* quad, int32_t degree,
                                  const double* sigma_l, snrt_precision precision);
 void snrt_scatter_destroy(snrt_scatter* scatter);
@@ -243,14 +251,18 @@ snrt_status snrt_step_adjoint_f64(const snrt_mesh* mesh, const snrt_quad* quad,
                                   double* g_sigma_t, double* g_sigma_s, double* g_rho,
                                   void* ws, size_t ws_bytes, void* stream);
 
-/* The dense scattering product alone (the S term of eq. SNEqns without the update):
+/* The scattering product alone (the S term of eq. SNEqns without the update):
  *   transpose = 0:  S[c][q] = sum_p K[q][p] w_p psi[c][p]          (S = Psi B)
  *   transpose = 1:  S[c][p] = w_p sum_q K[q][p] psi[c][q]          (Lambda B^T, adjoint side)
- * psi, S: device [ncells][nq] FP32, S must not alias psi.  Only for dense scatter handles
- * (SNRT_E_UNSUPPORTED for isotropic). */
+ * with K the dense kernel, or the kernel of the moment form (eq. SNEqns2).  psi, S: device
+ * [ncells][nq] FP32, S must not alias psi.  ws: device workspace of at least
+ * snrt_workspace_size bytes, 16-byte aligned and disjoint from psi and S (it holds the
+ * moments between the two products of the moment form and the row scales of the FP16 mode;
+ * may be NULL for a dense kernel in the FP32 or BF16 modes).  Only for dense and moment
+ * scatter handles (SNRT_E_UNSUPPORTED for isotropic). */
 snrt_status snrt_scatter_apply(const snrt_mesh* mesh, const snrt_quad* quad,
                                const snrt_scatter* scatter, const float* psi, float* S,
-                               int32_t transpose, void* stream);
+                               int32_t transpose, void* ws, size_t ws_bytes, void* stream);
 
 /* IMEX step (Sec. 4.2): the linear collision operator R psi = -alpha_t sigma_t psi +
  * alpha_s sigma_s S(psi) is taken implicitly, streaming and the source explicitly:
@@ -332,26 +344,33 @@ snrt_status snrt_rollout_f64(const snrt_mesh* mesh, const snrt_quad* quad,
 
 /* Reverse pass over a rollout made by snrt_rollout with checkpoints (same args, sched,
  * nsteps and ckpt_every): for each checkpoint segment, last first, the segment's states are
- * recomputed from its checkpoint into seg and walked backwards with snrt_step_adjoint:
+ * recomputed from its checkpoint into seg and walked backwards with the transposed step of
+ * snrt_step_adjoint:
  *     lam^N = lam (on entry),  lam^n = T_n^T lam^{n+1} (+ the dose term below),
  * with the gradient contributions of every step added to g_sigma_t, g_sigma_s, g_rho (device
- * [ncells], each may be NULL; g_rho needs args->inv_rho).
+ * [ncells] FP64, accumulated (+=), each may be NULL; g_rho needs args->inv_rho).  The
+ * accumulators are FP64 because a long run adds many small contributions of one sign to
+ * each cell: an FP32 accumulator loses about half an ulp per addition the same way every
+ * time, a drift of order nsteps * 2^-25 relative.
  *   ckpt    device, the checkpoints snrt_rollout wrote
  *   seg     device [ckpt_every - 1][ncells][nq] scratch (may be NULL when ckpt_every == 1)
  *   lam     device [ncells][nq]: dJ/dpsi^N on entry, dJ/dpsi^0 on return
  *   tmp     device [ncells][nq] scratch
  *   g_dose  NULL, or device [ncells] FP64 dJ/dD for a functional of the rollout's dose:
- *           after the adjoint of step n, snrt_dose_adjoint(args->inv_rho,
- *           sched->dose_coeff[n], g_dose) is applied to lam^n.  The explicit density term of
- *           the dose is left to snrt_dose_density_grad.
+ *           after the transposed step n, snrt_dose_adjoint(args->inv_rho,
+ *           sched->dose_coeff[n], g_dose) is applied to lam^n
+ *   dose    NULL, or the rollout's dose (device [ncells] FP64): with g_dose and g_rho, the
+ *           explicit density derivative -dose_i inv_rho_i g_dose_i is added to g_rho last
  * lam, tmp, seg and ckpt must be disjoint (SNRT_E_ALIAS).  Recomputed states are bitwise the
  * forward ones (the kernels are deterministic), so the result does not depend on ckpt_every. */
 snrt_status snrt_rollout_adjoint(const snrt_mesh* mesh, const snrt_quad* quad,
                                  const snrt_scatter* scatter, const snrt_step_args* args,
                                  const snrt_schedule* sched, int64_t nsteps, const float* ckpt,
                                  int32_t ckpt_every, float* seg, float* lam, float* tmp,
-                                 float* g_sigma_t, float* g_sigma_s, float* g_rho,
-                                 const double* g_dose, void* ws, size_t ws_bytes, void* stream);
+                                 double* g_sigma_t, double* g_sigma_s, double* g_rho,
+                                 const double* g_dose, const double* dose, void* ws,
+                                 size_t ws_bytes, void* stream);
+/* The FP64 parity template of the reverse pass (no dose terms). */
 snrt_status snrt_rollout_adjoint_f64(const snrt_mesh* mesh, const snrt_quad* quad,
                                      const snrt_scatter* scatter, const snrt_step_args_f64* args,
                                      const snrt_schedule* sched, int64_t nsteps,

@@ -1,12 +1,23 @@
 // Scattering products C = A X on the CDNA4 matrix cores: the dense kernel S = Psi B of
 // eq. SNEqns (B[p][q] = w_p K[q][p], K = N = nq) and the two skinny products of the
 // moment-projected form O Sigma M of eq. SNEqns2 (K or N = the padded moment count).
-// A is [M][K] FP32 row-major, C is [M][N] FP32; K % 32 == 0 and N % 128 == 0.
+// A is [M][K] FP32 row-major, C is [M][ldc] FP32; K % 32 == 0.  The right operand is stored
+// with its N columns zero-padded to a multiple of 128 (the tile width); only the first ldc
+// columns of each tile row are written.
 //
 // Split precision: every FP32 operand x is written as hi + lo with hi = bf16(x) and
 // lo = bf16(x - hi) (round to nearest even; x - hi is exact in FP32), and the product is
 // accumulated in FP32 as  A_hi B_hi + A_hi B_lo + A_lo B_hi  (the lo*lo term, below 2^-16
 // relative, is dropped).  The single-product mode keeps only A_hi B_hi.
+//
+// FP16 variant (three products, v_mfma_f32_32x32x16_f16): FP16 carries 11 significant bits
+// (hi + lo: 22) but only 5 exponent bits, so both operands are scaled by powers of two into
+// its range first (exact): every row r of A by 2^e_r with e_r chosen so that the row's largest
+// magnitude lands in [2^13, 2^14) (a pre-pass over A writes e_r), and X by one 2^e_B so that
+// its largest magnitude lands there too.  The epilogue multiplies each accumulator row by
+// 2^-(e_r + e_B), which undoes the scaling exactly.  Entries far below their row's largest
+// (below ~2^-16 of it) lose the lo part's precision gradually; their share of a dot product
+// is of that order.
 //
 // Tiling for v_mfma_f32_32x32x16_bf16 (64-lane wavefronts):
 //   block tile BM (cells) x BN (ordinates), 8 waves as 2 x 4, each wave BM/2 x BN/4 =
@@ -36,6 +47,7 @@
 // K values (l / 32) * 8 + [0, 8); accumulator i of lane l is row (i/4)*8 + (l/32)*4 + i%4,
 // column l % 32.
 #include <algorithm>
+#include <type_traits>
 
 #include "snrt_internal.h"
 
@@ -44,6 +56,7 @@ namespace snrt {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
@@ -78,18 +91,42 @@ __device__ __forceinline__ void split4(f32x4 v, uint32_t (&hi)[2], uint32_t (&lo
     lo[1] = l[2] | (l[3] << 16);
 }
 
+// FP16 hi/lo split of four floats scaled by 2^e (exact scaling; round to nearest even), packed
+// as four halves each (two 32-bit words per half)
+__device__ __forceinline__ uint16_t f16_bits(_Float16 h) { return __builtin_bit_cast(uint16_t, h); }
+
+__device__ __forceinline__ void split4_f16(f32x4 v, int e, uint32_t (&hi)[2], uint32_t (&lo)[2]) {
+    uint32_t h[4], l[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float x = __builtin_ldexpf(v[i], e);
+        const _Float16 xh = (_Float16)x;
+        h[i] = f16_bits(xh);
+        l[i] = f16_bits((_Float16)(x - (float)xh));
+    }
+    hi[0] = h[0] | (h[1] << 16);
+    hi[1] = h[2] | (h[3] << 16);
+    lo[0] = l[0] | (l[1] << 16);
+    lo[1] = l[2] | (l[3] << 16);
+}
+
 // position of 16-byte granule g in LDS row r
 __device__ __forceinline__ int swz(int r, int g) { return g ^ ((r >> 2) & 3); }
 
 // One BM x BN block tile of C = A X; lb is the logical block index (row block major, column
-// blocks fastest) and lds the block's two stages of NP planes.
-template <int P, int BM, int BN, int FD, bool STAGGER>
+// blocks fastest) and lds the block's two stages of NP planes.  N is the padded width of X
+// (a multiple of BN), ldc <= N the row length of C.  F16: FP16 operands with the row
+// exponents rexp[M] of A and the exponent eb of X (see the file comment); BF16 otherwise.
+template <int P, int BM, int BN, int FD, bool STAGGER, bool F16 = false>
 __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
                                            const uint16_t* __restrict__ Bhi,
                                            const uint16_t* __restrict__ Blo,
                                            float* __restrict__ C, int64_t M, int32_t K,
-                                           int32_t N, int64_t lb, uint16_t* lds)
+                                           int32_t N, int32_t ldc,
+                                           const int32_t* __restrict__ rexp, int32_t eb,
+                                           int64_t lb, uint16_t* lds)
 {
+    using Frag = typename std::conditional<F16, f16x8, bf16x8>::type;
     static_assert(BM == 64 || BM == 128 || BM == 256, "block rows");
     static_assert(BN == 128 || BN == 256, "block columns");
     // P products: A_hi B_hi (+ A_hi B_lo (+ A_lo B_hi)); planes per stage: A hi, B hi, then
@@ -121,6 +158,14 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
     // thread).  FD register slots hold the chunks kc+1 .. kc+FD, chunk c in slot c % FD.
     f32x4 ga[FD][AV];
     u32x4 gbh[FD][BV], gbl[FD][BV];
+    // FP16: the exponent of each A row this thread stages (fixed over the K loop; rows past M
+    // read as zero and take exponent 0)
+    int ea[AV];
+#pragma unroll
+    for (int e = 0; e < AV; ++e) {
+        const int64_t r = m0 + ((tid + e * kThreads) >> 3);
+        ea[e] = (F16 && r < M) ? rexp[r] : 0;
+    }
     auto fetch = [&](int kc, int slot) {
 #pragma unroll
         for (int e = 0; e < AV; ++e) {
@@ -150,7 +195,10 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
             const int r = p >> 3, g4 = p & 7;
             const int o = r * BK + swz(r, g4 >> 1) * 8 + (g4 & 1) * 4;
             uint32_t hi[2], lo[2];
-            split4(ga[slot][e], hi, lo);
+            if constexpr (F16)
+                split4_f16(ga[slot][e], ea[e], hi, lo);
+            else
+                split4(ga[slot][e], hi, lo);
             *reinterpret_cast<uint2*>(&Ah[o]) = make_uint2(hi[0], hi[1]);
             if constexpr (P == 3) *reinterpret_cast<uint2*>(&Al[o]) = make_uint2(lo[0], lo[1]);
         }
@@ -188,8 +236,8 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
     // right after the barrier.  The products of every accumulator keep their order.
     const bool late = STAGGER && __builtin_amdgcn_readfirstlane(tid >> 8) != 0;
 
-    auto read_frags = [&](int s, int ks, bf16x8 (&ah)[IM], bf16x8 (&al)[IM], bf16x8 (&bh)[JN],
-                          bf16x8 (&bl)[JN]) {
+    auto read_frags = [&](int s, int ks, Frag (&ah)[IM], Frag (&al)[IM], Frag (&bh)[JN],
+                          Frag (&bl)[JN]) {
         const uint16_t* Ah = lds + (s * NP + 0) * kPlane;
         const uint16_t* Bh = lds + (s * NP + 1) * kPlane;
         const uint16_t* Al = lds + (s * NP + PL_AL) * kPlane;
@@ -197,27 +245,31 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
 #pragma unroll
         for (int j = 0; j < JN; ++j) {
             const int o = (wn + j * 32) * BK + foff[ks];
-            bh[j] = *reinterpret_cast<const bf16x8*>(&Bh[o]);
-            if constexpr (P >= 2) bl[j] = *reinterpret_cast<const bf16x8*>(&Bl[o]);
+            bh[j] = *reinterpret_cast<const Frag*>(&Bh[o]);
+            if constexpr (P >= 2) bl[j] = *reinterpret_cast<const Frag*>(&Bl[o]);
         }
 #pragma unroll
         for (int i = 0; i < IM; ++i) {
             const int o = (wm + i * 32) * BK + foff[ks];
-            ah[i] = *reinterpret_cast<const bf16x8*>(&Ah[o]);
-            if constexpr (P == 3) al[i] = *reinterpret_cast<const bf16x8*>(&Al[o]);
+            ah[i] = *reinterpret_cast<const Frag*>(&Ah[o]);
+            if constexpr (P == 3) al[i] = *reinterpret_cast<const Frag*>(&Al[o]);
         }
     };
-    auto multiply = [&](const bf16x8 (&ah)[IM], const bf16x8 (&al)[IM], const bf16x8 (&bh)[JN],
-                        const bf16x8 (&bl)[JN]) {
+    auto mfma = [](const Frag& a, const Frag& b, const f32x16& c) -> f32x16 {
+        if constexpr (F16)
+            return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+        else
+            return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    };
+    auto multiply = [&](const Frag (&ah)[IM], const Frag (&al)[IM], const Frag (&bh)[JN],
+                        const Frag (&bl)[JN]) {
 #pragma unroll
         for (int i = 0; i < IM; ++i)
 #pragma unroll
             for (int j = 0; j < JN; ++j) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-                if constexpr (P >= 2)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                if constexpr (P == 3)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = mfma(ah[i], bh[j], acc[i][j]);
+                if constexpr (P >= 2) acc[i][j] = mfma(ah[i], bl[j], acc[i][j]);
+                if constexpr (P == 3) acc[i][j] = mfma(al[i], bh[j], acc[i][j]);
             }
     };
 
@@ -237,7 +289,7 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
                 if (late && ks == 1) prepare();
-                bf16x8 ah[IM], al[IM], bh[JN], bl[JN];
+                Frag ah[IM], al[IM], bh[JN], bl[JN];
                 read_frags(s, ks, ah, al, bh, bl);
                 multiply(ah, al, bh, bl);
             }
@@ -245,30 +297,41 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
     }
 
     // epilogue: accumulator r of lane l is row (r/4)*8 + (l/32)*4 + r%4, column l%32; S is
-    // consumed once by the step kernel, so it is streamed past the caches
+    // consumed once by the step kernel, so it is streamed past the caches.  Columns past ldc
+    // (the zero padding of X) are not stored.
 #pragma unroll
-    for (int i = 0; i < IM; ++i)
+    for (int i = 0; i < IM; ++i) {
+        // FP16: the exponent that undoes the scaling of each of this lane's 16 rows
+        int eu[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t row = m0 + wm + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+            eu[r] = (F16 && row < M) ? -(rexp[row] + eb) : 0;
+        }
 #pragma unroll
         for (int j = 0; j < JN; ++j) {
             const int col = n0 + wn + j * 32 + fr;
+            if (col >= ldc) continue;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int64_t row = m0 + wm + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-                if (row < M) __builtin_nontemporal_store(acc[i][j][r], &C[row * N + col]);
+                const float v = F16 ? __builtin_ldexpf(acc[i][j][r], eu[r]) : acc[i][j][r];
+                if (row < M) __builtin_nontemporal_store(v, &C[row * ldc + col]);
             }
         }
+    }
 }
 
 // Blocks [0, nmain) are 256 x 256 tiles of the first M1 rows; blocks [nmain, grid) are
 // TM x TN tiles of the remaining rows (none when nmain == grid).  Blocks are dispatched in
 // order, so the small tiles fill the compute units as the full ones finish.
-template <int P, int MBN, int TM, int TN, int TFD, bool STAGGER>
-__global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict__ A,
-                                                        const uint16_t* __restrict__ Bhi,
-                                                        const uint16_t* __restrict__ Blo,
-                                                        float* __restrict__ C, int64_t M1,
-                                                        int64_t M, int32_t K, int32_t N,
-                                                        int64_t nmain)
+template <bool F16, int P, int MBN, int TM, int TN, int TFD, bool STAGGER>
+__device__ __forceinline__ void gemm_grid(const float* __restrict__ A,
+                                          const uint16_t* __restrict__ Bhi,
+                                          const uint16_t* __restrict__ Blo, float* __restrict__ C,
+                                          int64_t M1, int64_t M, int32_t K, int32_t N,
+                                          int32_t ldc, const int32_t* __restrict__ rexp,
+                                          int32_t eb, int64_t nmain)
 {
     constexpr int NP = P == 3 ? 4 : P == 2 ? 3 : 2;
     __shared__ __attribute__((aligned(16))) uint16_t lds[2 * NP * kPlane];
@@ -276,13 +339,69 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict_
     if (b < nmain) {
         // 256 x 256 tiles keep one chunk in flight (their multiply covers the load latency
         // and their accumulators leave no room for more); 256 x 128 tiles keep two
-        gemm_block<P, 256, MBN, MBN == 256 ? 1 : 2, STAGGER>(A, Bhi, Blo, C, M1, K, N,
-                                                                xcd_remap(b, nmain), lds);
+        gemm_block<P, 256, MBN, MBN == 256 ? 1 : 2, STAGGER, F16>(
+            A, Bhi, Blo, C, M1, K, N, ldc, rexp, eb, xcd_remap(b, nmain), lds);
     } else {
         // nmain is a multiple of the XCD count, so the remap of the tail stays XCD-aware
         const int64_t nt = (int64_t)gridDim.x - nmain;
-        gemm_block<P, TM, TN, TFD, STAGGER>(A + M1 * K, Bhi, Blo, C + M1 * N, M - M1, K, N,
-                                                xcd_remap(b - nmain, nt), lds);
+        gemm_block<P, TM, TN, TFD, STAGGER, F16>(A + M1 * K, Bhi, Blo, C + M1 * ldc, M - M1, K,
+                                                 N, ldc, F16 ? rexp + M1 : rexp, eb,
+                                                 xcd_remap(b - nmain, nt), lds);
+    }
+}
+
+template <int P, int MBN, int TM, int TN, int TFD, bool STAGGER>
+__global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict__ A,
+                                                        const uint16_t* __restrict__ Bhi,
+                                                        const uint16_t* __restrict__ Blo,
+                                                        float* __restrict__ C, int64_t M1,
+                                                        int64_t M, int32_t K, int32_t N,
+                                                        int32_t ldc, int64_t nmain)
+{
+    gemm_grid<false, P, MBN, TM, TN, TFD, STAGGER>(A, Bhi, Blo, C, M1, M, K, N, ldc, nullptr, 0,
+                                                   nmain);
+}
+
+// The FP16 hi+lo product (three products) with per-row exponents rexp of A and exponent eb
+// of X.
+template <int MBN, int TM, int TN, int TFD, bool STAGGER>
+__global__ __launch_bounds__(kThreads) void k_gemm_f16(const float* __restrict__ A,
+                                                       const uint16_t* __restrict__ Bhi,
+                                                       const uint16_t* __restrict__ Blo,
+                                                       float* __restrict__ C, int64_t M1,
+                                                       int64_t M, int32_t K, int32_t N,
+                                                       int32_t ldc,
+                                                       const int32_t* __restrict__ rexp,
+                                                       int32_t eb, int64_t nmain)
+{
+    gemm_grid<true, 3, MBN, TM, TN, TFD, STAGGER>(A, Bhi, Blo, C, M1, M, K, N, ldc, rexp, eb,
+                                                  nmain);
+}
+
+// Row exponents of A [M][K] for the FP16 product: e_r with max_k |A[r][k]| * 2^e_r in
+// [2^13, 2^14) (frexp of the row maximum m = f 2^E, f in [0.5, 1): e_r = 14 - E); 0 for a row
+// of zeros or with a non-finite entry.  One wavefront per row, K % 4 == 0.
+__global__ __launch_bounds__(256) void k_row_exp_f16(const float* __restrict__ A, int64_t M,
+                                                     int32_t K, int32_t* __restrict__ rexp)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < M; r += nw) {
+        const f32x4* row = reinterpret_cast<const f32x4*>(A + r * K);
+        float mx = 0.0f;
+        for (int k = lane; k < K / 4; k += 64) {
+            const f32x4 v = row[k];
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))));
+            // a NaN anywhere makes the row's exponent 0 (fmaxf would drop it)
+            if (v[0] != v[0] || v[1] != v[1] || v[2] != v[2] || v[3] != v[3]) mx = INFINITY;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+        if (lane == 0) {
+            int E = 0;
+            (void)__builtin_frexpf(mx, &E);
+            rexp[r] = (mx > 0.0f && mx < INFINITY) ? 14 - E : 0;
+        }
     }
 }
 
@@ -475,7 +594,36 @@ __global__ __launch_bounds__(256) void k_split(const float* __restrict__ B, uint
     lo[i] = (uint16_t)bf16_rne_bits(x - bf16_to_f32(h));
 }
 
+// FP16 halves of X [K][N] scaled by 2^eb, in the same tiled plane order as k_split.
+__global__ __launch_bounds__(256) void k_split_f16(const float* __restrict__ B,
+                                                   uint16_t* __restrict__ hi,
+                                                   uint16_t* __restrict__ lo, int32_t K, int32_t N,
+                                                   int32_t eb)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)K * N) return;
+    const int pos = (int)(i % BK);
+    const int64_t t = i / BK;
+    const int n = (int)(t % N);
+    const int kc = (int)(t / N);
+    const int kk = swz(n, pos >> 3) * 8 + (pos & 7);
+    const float x = __builtin_ldexpf(B[(int64_t)(kc * BK + kk) * N + n], eb);
+    const _Float16 h = (_Float16)x;
+    hi[i] = f16_bits(h);
+    lo[i] = f16_bits((_Float16)(x - (float)h));
+}
+
 }  // namespace
+
+hipError_t launch_split_f16(const float* B, uint16_t* hi, uint16_t* lo, int32_t K, int32_t N,
+                            int32_t eb, hipStream_t st) {
+    if (K % BK != 0 || N % 128 != 0) return hipErrorNotSupported;
+    const int64_t n = (int64_t)K * N;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_split_f16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, B, hi,
+                       lo, K, N, eb);
+    return hipGetLastError();
+}
 
 hipError_t launch_tile_f32(const float* B, float* out, int32_t K, int32_t N, hipStream_t st) {
     if (K % BK != 0 || N % 128 != 0) return hipErrorNotSupported;
@@ -510,18 +658,23 @@ int device_cu_count() {
     return cache[dev];
 }
 
+// products 1..3: BF16; 0: the FP16 three-product form (rexp, eb).
 template <int MBN, int TM, int TN>
 hipError_t launch_split(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
-                        int64_t M1, int64_t M, int32_t K, int32_t N, int products,
-                        hipStream_t st) {
+                        int64_t M1, int64_t M, int32_t K, int32_t N, int32_t ldc, int products,
+                        const int32_t* rexp, int32_t eb, hipStream_t st) {
     const int64_t nmain = ((M1 + 255) / 256) * (N / MBN);
     const int64_t ntail = ((M - M1 + TM - 1) / TM) * (N / TN);
     const dim3 grid((unsigned)(nmain + ntail));
     auto go = [&](auto p_c, auto stagger_c) {
         constexpr int PP = decltype(p_c)::value;
         constexpr bool SG = decltype(stagger_c)::value;
-        hipLaunchKernelGGL((k_gemm_bf16<PP, MBN, TM, TN, 4, SG>), grid, dim3(kThreads), 0, st,
-                           A, Bhi, Blo, C, M1, M, K, N, nmain);
+        if constexpr (PP == 0)
+            hipLaunchKernelGGL((k_gemm_f16<MBN, TM, TN, 4, SG>), grid, dim3(kThreads), 0, st, A,
+                               Bhi, Blo, C, M1, M, K, N, ldc, rexp, eb, nmain);
+        else
+            hipLaunchKernelGGL((k_gemm_bf16<PP, MBN, TM, TN, 4, SG>), grid, dim3(kThreads), 0,
+                               st, A, Bhi, Blo, C, M1, M, K, N, ldc, nmain);
         return hipGetLastError();
     };
     // the staggered phases pay on the square products of the dense kernel (4-5 % measured);
@@ -530,16 +683,20 @@ hipError_t launch_split(const float* A, const uint16_t* Bhi, const uint16_t* Blo
     auto by_stagger = [&](auto p_c) {
         return stagger ? go(p_c, std::true_type{}) : go(p_c, std::false_type{});
     };
+    if (products == 0) return by_stagger(std::integral_constant<int, 0>{});
     if (products == 3) return by_stagger(std::integral_constant<int, 3>{});
     if (products == 2) return by_stagger(std::integral_constant<int, 2>{});
     return by_stagger(std::integral_constant<int, 1>{});
 }
 
-hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
-                            int64_t M, int32_t K, int32_t N, int products, hipStream_t st) {
+// The shape policy of both low-precision products (products 1..3: BF16; 0: FP16 x3).
+hipError_t launch_gemm_lp(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
+                          int64_t M, int32_t K, int32_t N, int32_t ldc, int products,
+                          const int32_t* rexp, int32_t eb, hipStream_t st) {
     if (M == 0) return hipSuccess;
-    if (products < 1 || products > 3) return hipErrorInvalidValue;
-    if (K % BK != 0 || N % 128 != 0 || K == 0) return hipErrorNotSupported;
+    if (products < 0 || products > 3) return hipErrorInvalidValue;
+    if (K % BK != 0 || N % 128 != 0 || K == 0 || ldc <= 0 || ldc > N)
+        return hipErrorNotSupported;
     // One 256 x 256 block (256 x 128 when N is an odd multiple of 128) per compute unit and
     // round (128 KB of LDS each).  When the last round would be mostly empty, its rows run
     // as smaller blocks: 64 x 128 (an eighth of a 256 x 256 block) if they then fill one
@@ -557,14 +714,38 @@ hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t*
     const int64_t rows1 = std::min<int64_t>(((tiles - rem) / nN) * 256, M);
     if (!wide) {
         if (quarter)
-            return launch_split<128, 64, 128>(A, Bhi, Blo, C, rows1, M, K, N, products, st);
-        return launch_split<128, 64, 128>(A, Bhi, Blo, C, M, M, K, N, products, st);
+            return launch_split<128, 64, 128>(A, Bhi, Blo, C, rows1, M, K, N, ldc, products,
+                                              rexp, eb, st);
+        return launch_split<128, 64, 128>(A, Bhi, Blo, C, M, M, K, N, ldc, products, rexp, eb,
+                                          st);
     }
     if (eighth)
-        return launch_split<256, 64, 128>(A, Bhi, Blo, C, rows1, M, K, N, products, st);
+        return launch_split<256, 64, 128>(A, Bhi, Blo, C, rows1, M, K, N, ldc, products, rexp,
+                                          eb, st);
     if (quarter)
-        return launch_split<256, 64, 256>(A, Bhi, Blo, C, rows1, M, K, N, products, st);
-    return launch_split<256, 64, 256>(A, Bhi, Blo, C, M, M, K, N, products, st);
+        return launch_split<256, 64, 256>(A, Bhi, Blo, C, rows1, M, K, N, ldc, products, rexp,
+                                          eb, st);
+    return launch_split<256, 64, 256>(A, Bhi, Blo, C, M, M, K, N, ldc, products, rexp, eb, st);
+}
+
+hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
+                            int64_t M, int32_t K, int32_t N, int32_t ldc, int products,
+                            hipStream_t st) {
+    if (products < 1 || products > 3) return hipErrorInvalidValue;
+    return launch_gemm_lp(A, Bhi, Blo, C, M, K, N, ldc, products, nullptr, 0, st);
+}
+
+hipError_t launch_gemm_f16x3(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
+                             int64_t M, int32_t K, int32_t N, int32_t ldc, int32_t* rexp,
+                             int32_t eb, hipStream_t st) {
+    if (M == 0) return hipSuccess;
+    if (!rexp || K % BK != 0 || K == 0) return hipErrorNotSupported;
+    const int64_t want = (M + 3) / 4;
+    const unsigned nb = (unsigned)std::min<int64_t>(want, (int64_t)device_cu_count() * 8);
+    hipLaunchKernelGGL(k_row_exp_f16, dim3(nb), dim3(256), 0, st, A, M, K, rexp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_gemm_lp(A, Bhi, Blo, C, M, K, N, ldc, 0, rexp, eb, st);
 }
 
 template <int MBN, int TM, int TN>

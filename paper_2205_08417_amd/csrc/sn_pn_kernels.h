@@ -155,7 +155,9 @@ __device__ __forceinline__ void for_each_index(F&& f, std::integer_sequence<int,
     (f(std::integral_constant<int, I>{}), ...);
 }
 
-// Cell update: u' = u (1 - dt a_t s_t + dt a_s s_s sigma_l(k)) - dt/A flux_k (+ source on m_0).
+// Cell update: u' = u + u (dt a_s s_s sigma_l(k) - dt a_t s_t) - dt/A flux_k (+ source on m_0);
+// the collision factor is applied as u + u (...) so that rounding 1 + (...) to the working
+// precision (an error that would repeat on every step) never scales the state.
 template <typename T, typename A>
 struct PnUpdate {
     T dtA, c1, c2, q0;
@@ -166,7 +168,7 @@ struct PnUpdate {
         q0 = a.source ? (T)a.dt * a.source[c] * (T)kSqrt4Pi : T(0);
     }
     __device__ __forceinline__ T operator()(T uk, T flux, T sig, bool first) const {
-        T v = uk * (T(1) - c1 + c2 * sig) - dtA * flux;
+        T v = (uk + uk * (c2 * sig - c1)) - dtA * flux;
         return first ? v + q0 : v;
     }
 };
@@ -291,8 +293,8 @@ __device__ __forceinline__ void pn_fused_moments(T (&acc)[pn::nmom(N)], const Pn
                         Q = fma(gc[f][3], gv, Q);
                     }
                 }
-                // the collision term of moment m: u_m (1 - dt a_t s_t + dt a_s s_s sigma_l(m))
-                acc[m] = fma(fma(c2, sig[m], T(1) - c1), uo, acc[m]);
+                // the collision term of moment m: u_m + u_m (dt a_s s_s sigma_l(m) - dt a_t s_t)
+                acc[m] = fma(fma(c2, sig[m], -c1), uo, acc[m] + uo);
                 constexpr int s = pn::OpTable<N>::start[m];
                 constexpr int e = pn::OpTable<N>::start[m + 1];
                 apply_ops<N, s>(acc, X, Y, P, Q, W, std::make_integer_sequence<int, e - s>{});

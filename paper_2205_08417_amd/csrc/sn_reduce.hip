@@ -189,6 +189,16 @@ __global__ __launch_bounds__(256) void k_dose_density_grad(const double* __restr
     g_rho[c] = (float)((double)g_rho[c] - dose[c] * (inv_rho ? (double)inv_rho[c] : 1.0) * g_dose[c]);
 }
 
+__global__ __launch_bounds__(256) void k_dose_density_grad64(const double* __restrict__ dose,
+                                                             const float* __restrict__ inv_rho,
+                                                             const double* __restrict__ g_dose,
+                                                             double* __restrict__ g_rho, int64_t nc)
+{
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= nc) return;
+    g_rho[c] -= dose[c] * (inv_rho ? (double)inv_rho[c] : 1.0) * g_dose[c];
+}
+
 inline unsigned blocks_for(int64_t nc) {
     return (unsigned)((nc + kCellsPerBlock - 1) / kCellsPerBlock);
 }
@@ -308,6 +318,15 @@ hipError_t launch_dose_density_grad(const snrt_mesh& m, const double* dose, cons
     if (m.nc == 0) return hipSuccess;
     hipLaunchKernelGGL(k_dose_density_grad, dim3((unsigned)((m.nc + 255) / 256)), dim3(256), 0, st,
                        dose, inv_rho, g_dose, g_rho, m.nc);
+    return hipGetLastError();
+}
+
+hipError_t launch_dose_density_grad64(const snrt_mesh& m, const double* dose,
+                                      const float* inv_rho, const double* g_dose, double* g_rho,
+                                      hipStream_t st) {
+    if (m.nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dose_density_grad64, dim3((unsigned)((m.nc + 255) / 256)), dim3(256), 0,
+                       st, dose, inv_rho, g_dose, g_rho, m.nc);
     return hipGetLastError();
 }
 

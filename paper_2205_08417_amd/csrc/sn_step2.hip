@@ -198,13 +198,13 @@ __global__ __launch_bounds__(kStepBlock) void k_flux2(
         }
     }
 
-    const T keep = T(1) - a.dt * a.alpha_t * a.sigma_t[c];
+    const T cabs = a.dt * a.alpha_t * a.sigma_t[c];   // absorption as p - cabs p
     const T cflux = a.dt * g.inv_area;
     const T cscat = a.dt * a.alpha_s * a.sigma_s[c];
     const T csrc = a.source ? a.dt * a.source[c] : T(0);
     T o[V];
 #pragma unroll
-    for (int k = 0; k < V; ++k) o[k] = p[k] * keep - cflux * acc[k] + cscat * src[k] + csrc;
+    for (int k = 0; k < V; ++k) o[k] = (p[k] - cabs * p[k]) - cflux * acc[k] + cscat * src[k] + csrc;
     if constexpr (FINAL) {
         T pn[V];
         load_slice<V, EXACT>(psi_n + c * nq, q0, nq, pn);
@@ -227,7 +227,7 @@ struct Flux2Stage {
     T src[V], pn[V];
     T ghost[MF];
     T nx[MF], ny[MF], rox[MF], roy[MF], rfx[MF], rfy[MF];
-    T irho, keep, cflux, cscat, csrc;
+    T irho, cabs, cflux, cscat, csrc;
 };
 
 template <typename T>
@@ -280,7 +280,7 @@ __device__ __forceinline__ void flux2_load(Flux2Stage<V, MF, DENSE, FINAL, T>& d
     }
     if constexpr (DENSE) buf_load_row<V, EXACT, T>(x.S, own, q0, nq, d.src);
     if constexpr (FINAL) buf_load_row<V, EXACT, T>(x.pn, own, q0, nq, d.pn);
-    d.keep = T(1) - a.dt * a.alpha_t * cell_val(a.sigma_t, c);
+    d.cabs = a.dt * a.alpha_t * cell_val(a.sigma_t, c);
     d.cflux = a.dt * g->inv_area;
     d.cscat = a.dt * a.alpha_s * cell_val(a.sigma_s, c);
     d.csrc = x.src_mul * cell_val(x.src_arr, c);
@@ -323,7 +323,7 @@ __device__ __forceinline__ void flux2_compute(const Flux2Stage<V, MF, DENSE, FIN
     T o[V];
 #pragma unroll
     for (int k = 0; k < V; ++k) {
-        o[k] = d.p[k] * d.keep - d.cflux * acc[k] + d.cscat * src[k] + d.csrc;
+        o[k] = (d.p[k] - d.cabs * d.p[k]) - d.cflux * acc[k] + d.cscat * src[k] + d.csrc;
         if constexpr (FINAL) o[k] = T(0.5) * (d.pn[k] + o[k]);
     }
     buf_store_row<V, EXACT, T, kAuxStream>(x.out, (uint32_t)c * x.row_bytes + cb, q0, nq, o);

@@ -36,16 +36,22 @@ __global__ __launch_bounds__(256) void k_imex_moment_scale(T* __restrict__ U,
     }
 }
 
-// psi <- (r + S) / a_i in place: r is the collision-free explicit step, S = O D M r.
+// psi <- (r + S) / a_i in place: r is the collision-free explicit step, S = O D M r.  With
+// c = dt alpha_t sigma_t the division by a_i = 1 + c is taken as x - x c / (1 + c), so that the
+// rounding of 1 + c (half an ulp of 1, the same on every step) does not scale the state.
 template <typename T>
 __global__ __launch_bounds__(256) void k_imex_combine(T* __restrict__ psi, const T* __restrict__ S,
                                                       const T* __restrict__ sigma_t, T dt,
                                                       T alpha_t, int64_t nc, int32_t nq) {
     for (int64_t c = blockIdx.x; c < nc; c += gridDim.x) {
-        const T inv_a = T(1) / (T(1) + dt * alpha_t * sigma_t[c]);
+        const T cabs = dt * alpha_t * sigma_t[c];
+        const T y = cabs / (T(1) + cabs);
         T* row = psi + c * nq;
         const T* srow = S + c * nq;
-        for (int32_t q = (int32_t)threadIdx.x; q < nq; q += 256) row[q] = (row[q] + srow[q]) * inv_a;
+        for (int32_t q = (int32_t)threadIdx.x; q < nq; q += 256) {
+            const T x = row[q] + srow[q];
+            row[q] = x - x * y;
+        }
     }
 }
 
@@ -57,12 +63,14 @@ __global__ __launch_bounds__(256) void k_imex_combine4(f32x4* __restrict__ psi,
                                                        float dt, float alpha_t, int64_t nc,
                                                        int32_t nq4) {
     for (int64_t c = blockIdx.x; c < nc; c += gridDim.x) {
-        const float inv_a = 1.0f / (1.0f + dt * alpha_t * sigma_t[c]);
+        const float cabs = dt * alpha_t * sigma_t[c];
+        const float y = cabs / (1.0f + cabs);
         f32x4* row = psi + c * nq4;
         const f32x4* srow = S + c * nq4;
-        for (int32_t q = (int32_t)threadIdx.x; q < nq4; q += 256)
-            __builtin_nontemporal_store((row[q] + __builtin_nontemporal_load(&srow[q])) * inv_a,
-                                        &row[q]);
+        for (int32_t q = (int32_t)threadIdx.x; q < nq4; q += 256) {
+            const f32x4 x = row[q] + __builtin_nontemporal_load(&srow[q]);
+            __builtin_nontemporal_store(x - x * y, &row[q]);
+        }
     }
 }
 

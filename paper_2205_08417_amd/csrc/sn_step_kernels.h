@@ -8,12 +8,18 @@
 // cell's own row; dense scattering reads the GEMM result S = Psi B.
 //
 // Forward (Sec. 4.2, eq. upwind1stOrder2; eq. SNEqns / BoltzmannCSDTrafo):
-//   psi'_q = psi_q (1 - dt a_t sig_t) - dt/A sum_f s_fq u_up + dt a_s sig_s S_q + dt q_src,
+//   psi'_q = psi_q - dt a_t sig_t psi_q - dt/A sum_f s_fq u_up + dt a_s sig_s S_q + dt q_src,
 //   s_fq = Omega_q . n_f, u_up = own u if s_fq > 0 else neighbour u / boundary ghost.
 // Adjoint (exact transpose of the linear part; a downwind gather):
-//   lam_q = l_q (1 - dt a_t sig_t) - dt/rho sum_{f: s>0} s (l_q/A - l_nbr,q/A_nbr)
+//   lam_q = l_q - dt a_t sig_t l_q - dt/rho sum_{f: s>0} s (l_q/A - l_nbr,q/A_nbr)
 //           + dt a_s sig_s (B^T-side scattering),
 // plus per-cell gradient sums, one wavefront reduction each.
+//
+// The absorption is applied as psi - (dt a_t sig_t) psi, never as psi (1 - dt a_t sig_t): the
+// factor 1 - dt a_t sig_t rounded to the working precision carries an absolute error of up
+// to half an ulp of 1 that would repeat identically on every step and compound over a long
+// run (about nsteps * 3e-8 relative in FP32), while the small coefficient itself keeps full
+// relative precision.  Implicit collisions divide by 1 + c the same way, as r - r c/(1 + c).
 #pragma once
 
 #include <type_traits>
@@ -278,8 +284,7 @@ struct FwdStage {
     T src[V];
     T ghost[MF];
     T nx[MF], ny[MF];
-    T irho, keep, cflux, cscat, csrc;
-    T imex_a;                       // 1 + dt alpha_t sigma_t (implicit collision only)
+    T irho, cabs, cflux, cscat, csrc;   // cabs = dt alpha_t sigma_t
 };
 
 // Buffer resources and scalars of one launch.
@@ -333,8 +338,7 @@ __device__ __forceinline__ void fwd_load_stage(FwdStage<V, MF, DENSE, T>& d, con
     }
     if constexpr (DENSE) buf_load_row<V, EXACT, T, kAuxStream>(x.S, own, q0, nq, d.src);
     const T st_c = cell_val(a.sigma_t, c);
-    d.keep = T(1) - a.dt * a.alpha_t * st_c;
-    d.imex_a = T(1) + a.dt * a.alpha_t * st_c;
+    d.cabs = a.dt * a.alpha_t * st_c;
     d.cflux = a.dt * g->inv_area;
     d.cscat = a.dt * a.alpha_s * cell_val(a.sigma_s, c);
     d.csrc = x.src_mul * cell_val(x.src_arr, c);
@@ -359,7 +363,8 @@ __device__ __forceinline__ void fwd_compute(const FwdStage<V, MF, DENSE, T>& d, 
     if constexpr (IMEX) {
         // (a - c K~) psi' = b, K~ = w/(4 pi) (isotropic): with B = sum_q (w_q/4pi) b_q and
         // W = sum_q w_q/(4 pi), the scalar flux of psi' is B / (a - c W) times 4 pi, so
-        // psi'_q = (b_q + c B / (a - c W)) / a  (Sherman-Morrison on the rank-one kernel)
+        // psi'_q = (b_q + c B / (a - c W)) / a  (Sherman-Morrison on the rank-one kernel),
+        // a = 1 + cabs; the final division is taken as r - r y, y = cabs / (1 + cabs)
         T u[V], acc[V];
 #pragma unroll
         for (int k = 0; k < V; ++k) {
@@ -383,10 +388,14 @@ __device__ __forceinline__ void fwd_compute(const FwdStage<V, MF, DENSE, T>& d, 
             part += wi[k] * b[k];
         }
         const T B = cell_sum(part);
-        const T phi4 = B / (d.imex_a - d.cscat * w4);
+        const T phi4 = B / (T(1) + (d.cabs - d.cscat * w4));
+        const T y = d.cabs / (T(1) + d.cabs);
         T o[V];
 #pragma unroll
-        for (int k = 0; k < V; ++k) o[k] = (b[k] + d.cscat * phi4) / d.imex_a;
+        for (int k = 0; k < V; ++k) {
+            const T r = b[k] + d.cscat * phi4;
+            o[k] = r - r * y;
+        }
         buf_store_row<V, EXACT, T, SA>(x.out, (uint32_t)c * x.row_bytes + cb, q0, nq, o);
         return;
     }
@@ -420,7 +429,7 @@ __device__ __forceinline__ void fwd_compute(const FwdStage<V, MF, DENSE, T>& d, 
     T o[V];
 #pragma unroll
     for (int k = 0; k < V; ++k)
-        o[k] = d.p[k] * d.keep - d.cflux * acc[k] + d.cscat * src[k] + d.csrc;
+        o[k] = (d.p[k] - d.cabs * d.p[k]) - d.cflux * acc[k] + d.cscat * src[k] + d.csrc;
     buf_store_row<V, EXACT, T, SA>(x.out, (uint32_t)c * x.row_bytes + cb, q0, nq, o);
 }
 
@@ -548,13 +557,14 @@ __global__ __launch_bounds__(kStepBlock) void k_step_dose(
 // --------------------------------------------------------------------------- adjoint step
 
 // Adjoint for wide rows (more than 32 bytes of each row per lane, where the pipelined form
-// below would hold two stages of them in registers): one wavefront per cell.
-template <int V, bool EXACT, bool DENSE, typename T>
+// below would hold two stages of them in registers): one wavefront per cell.  GT is the type
+// of the gradient accumulators (T, or double so that long runs accumulate in FP64).
+template <int V, bool EXACT, bool DENSE, typename T, typename GT = T>
 __global__ __launch_bounds__(kStepBlock) void k_adjoint(
     const typename GeomOf<T>::type* __restrict__ geom, int64_t nc, int32_t mf, int32_t nq,
     const T* __restrict__ tab, typename ArgsOf<T>::type a, const T* __restrict__ psi_n,
-    const T* __restrict__ lam_np1, T* __restrict__ lam_n, T* __restrict__ g_t,
-    T* __restrict__ g_s, T* __restrict__ g_r, const T* __restrict__ G)
+    const T* __restrict__ lam_np1, T* __restrict__ lam_n, GT* __restrict__ g_t,
+    GT* __restrict__ g_s, GT* __restrict__ g_r, const T* __restrict__ G)
 {
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -609,7 +619,7 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint(
     }
 
     const T irho = a.inv_rho ? a.inv_rho[c] : T(1);
-    const T keep = T(1) - a.dt * a.alpha_t * a.sigma_t[c];
+    const T cabs = a.dt * a.alpha_t * a.sigma_t[c];
     const T cscat = a.dt * a.alpha_s * a.sigma_s[c];
     const T cstream = a.dt * irho;
 
@@ -638,7 +648,7 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint(
     T part_t = T(0), part_r = T(0);
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-        o[j] = l[j] * keep - cstream * x[j] + cscat * src[j];
+        o[j] = (l[j] - cabs * l[j]) - cstream * x[j] + cscat * src[j];
         part_t += l[j] * p[j];
         part_r += p[j] * x[j];
     }
@@ -646,15 +656,15 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint(
 
     if (g_t) {
         const T s = wave_sum(part_t);
-        if (lane == 0) g_t[c] += -a.dt * a.alpha_t * s;
+        if (lane == 0) g_t[c] += (GT)(-a.dt * a.alpha_t * s);
     }
     if (g_s) {
         const T s = wave_sum(part_s);
-        if (lane == 0) g_s[c] += a.dt * a.alpha_s * s;
+        if (lane == 0) g_s[c] += (GT)(a.dt * a.alpha_s * s);
     }
     if (g_r) {
         const T s = wave_sum(part_r);
-        if (lane == 0) g_r[c] += a.dt * irho * irho * s;
+        if (lane == 0) g_r[c] += (GT)(a.dt * irho * irho * s);
     }
 }
 
@@ -664,32 +674,32 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint(
 // interior faces (and the zero-normal self-faces of unused slots) read the neighbour's
 // lambda with its 1/A, boundary faces the cell's own row with weight 0; a Neumann boundary
 // face passes both flux signs (its ghost is the cell's own value).
-template <int V, int MF, bool DENSE, typename T>
+template <int V, int MF, bool DENSE, typename T, typename GT>
 struct AdjStage {
     T l[V], p[V];
     T ln[MF][V];
     T g[DENSE ? V : 1];
     T ia_n[MF], nx[MF], ny[MF];
     bool all_signs[MF];
-    T ia, irho, keep, cscat;
-    T gt0, gs0, gr0;                // the gradient accumulators' values before this step
+    T ia, irho, cabs, cscat;
+    GT gt0, gs0, gr0;               // the gradient accumulators' values before this step
 };
 
-template <typename T>
+template <typename T, typename GT>
 struct AdjCtx {
     __amdgpu_buffer_rsrc_t lam, psi, out, G;
     uint32_t row_bytes;
     bool neumann;
-    T *g_t, *g_s, *g_r;
+    GT *g_t, *g_s, *g_r;
 };
 
-template <int V, bool EXACT, int MF, bool DENSE, typename T>
-__device__ __forceinline__ void adj_load_stage(AdjStage<V, MF, DENSE, T>& d,
+template <int V, bool EXACT, int MF, bool DENSE, typename T, typename GT>
+__device__ __forceinline__ void adj_load_stage(AdjStage<V, MF, DENSE, T, GT>& d,
                                                const NbrList<MF>& nb,
                                                const typename GeomOf<T>::type* __restrict__ geom,
                                                int32_t c, int32_t nq, int q0,
                                                const typename ArgsOf<T>::type& a,
-                                               const AdjCtx<T>& x)
+                                               const AdjCtx<T, GT>& x)
 {
     const auto* g = cell_rec(geom, c);
     const uint32_t own = (uint32_t)c * x.row_bytes;
@@ -709,21 +719,21 @@ __device__ __forceinline__ void adj_load_stage(AdjStage<V, MF, DENSE, T>& d,
     if constexpr (DENSE) buf_load_row<V, EXACT, T>(x.G, own, q0, nq, d.g);
     d.ia = g->inv_area;
     d.irho = a.inv_rho ? cell_val(a.inv_rho, c) : T(1);
-    d.keep = T(1) - a.dt * a.alpha_t * cell_val(a.sigma_t, c);
+    d.cabs = a.dt * a.alpha_t * cell_val(a.sigma_t, c);
     d.cscat = a.dt * a.alpha_s * cell_val(a.sigma_s, c);
     // each cell's accumulators are updated once per launch (by this wavefront), so their
     // old values can be fetched a stage ahead instead of stalling the update on the load
-    d.gt0 = x.g_t ? cell_val(x.g_t, c) : T(0);
-    d.gs0 = x.g_s ? cell_val(x.g_s, c) : T(0);
-    d.gr0 = x.g_r ? cell_val(x.g_r, c) : T(0);
+    d.gt0 = x.g_t ? cell_val(x.g_t, c) : GT(0);
+    d.gs0 = x.g_s ? cell_val(x.g_s, c) : GT(0);
+    d.gr0 = x.g_r ? cell_val(x.g_r, c) : GT(0);
 }
 
-template <int V, bool EXACT, int MF, bool DENSE, typename T>
-__device__ __forceinline__ void adj_compute(const AdjStage<V, MF, DENSE, T>& d, const T (&ox)[V],
-                                            const T (&oy)[V], const T (&wi)[V], int32_t c,
-                                            int32_t nq, int q0, int lane,
-                                            const typename ArgsOf<T>::type& a,
-                                            const AdjCtx<T>& x)
+template <int V, bool EXACT, int MF, bool DENSE, typename T, typename GT>
+__device__ __forceinline__ void adj_compute(const AdjStage<V, MF, DENSE, T, GT>& d,
+                                            const T (&ox)[V], const T (&oy)[V],
+                                            const T (&wi)[V], int32_t c, int32_t nq, int q0,
+                                            int lane, const typename ArgsOf<T>::type& a,
+                                            const AdjCtx<T, GT>& x)
 {
     T xs[V];
 #pragma unroll
@@ -764,31 +774,31 @@ __device__ __forceinline__ void adj_compute(const AdjStage<V, MF, DENSE, T>& d, 
     T part_t = T(0), part_r = T(0);
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-        o[j] = d.l[j] * d.keep - cstream * xs[j] + d.cscat * src[j];
+        o[j] = (d.l[j] - d.cabs * d.l[j]) - cstream * xs[j] + d.cscat * src[j];
         part_t += d.l[j] * d.p[j];
         part_r += d.p[j] * xs[j];
     }
     buf_store_row<V, EXACT, T, kAuxStream>(x.out, (uint32_t)c * x.row_bytes, q0, nq, o);
     if (x.g_t) {
         const T s = cell_sum(part_t);
-        if (lane == 0) x.g_t[c] = d.gt0 + -a.dt * a.alpha_t * s;
+        if (lane == 0) x.g_t[c] = d.gt0 + (GT)(-a.dt * a.alpha_t * s);
     }
     if (x.g_s) {
         const T s = cell_sum(part_s);
-        if (lane == 0) x.g_s[c] = d.gs0 + a.dt * a.alpha_s * s;
+        if (lane == 0) x.g_s[c] = d.gs0 + (GT)(a.dt * a.alpha_s * s);
     }
     if (x.g_r) {
         const T s = cell_sum(part_r);
-        if (lane == 0) x.g_r[c] = d.gr0 + a.dt * d.irho * d.irho * s;
+        if (lane == 0) x.g_r[c] = d.gr0 + (GT)(a.dt * d.irho * d.irho * s);
     }
 }
 
-template <int V, bool EXACT, int MF, bool DENSE, typename T>
+template <int V, bool EXACT, int MF, bool DENSE, typename T, typename GT = T>
 __global__ __launch_bounds__(kStepBlock) void k_adjoint_p(
     const typename GeomOf<T>::type* __restrict__ geom, int64_t nc, int32_t nq,
     const T* __restrict__ tab, typename ArgsOf<T>::type a, const T* __restrict__ psi_n,
-    const T* __restrict__ lam_np1, T* __restrict__ lam_n, T* __restrict__ g_t,
-    T* __restrict__ g_s, T* __restrict__ g_r, const T* __restrict__ G, int64_t items_per_xcd)
+    const T* __restrict__ lam_np1, T* __restrict__ lam_n, GT* __restrict__ g_t,
+    GT* __restrict__ g_s, GT* __restrict__ g_r, const T* __restrict__ G, int64_t items_per_xcd)
 {
     const int x = blockIdx.x % kNumXcd;
     const int kx = blockIdx.x / kNumXcd;
@@ -802,7 +812,7 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint_p(
     if (c >= xend) return;
     const int q0 = lane * V;
 
-    AdjCtx<T> cx;
+    AdjCtx<T, GT> cx;
     cx.row_bytes = (uint32_t)nq * sizeof(T);
     const uint32_t state_bytes = (uint32_t)nc * cx.row_bytes;
     cx.lam = make_rsrc(lam_np1, state_bytes);
@@ -822,7 +832,7 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint_p(
     load_slice<V, EXACT>(tab + 3 * nq, q0, nq, wi);
 
     NbrList<MF> n0, n1, n2;
-    AdjStage<V, MF, DENSE, T> sa, sb;
+    AdjStage<V, MF, DENSE, T, GT> sa, sb;
     fwd_load_nbr<MF, T>(n0, geom, clampc(c));
     adj_load_stage<V, EXACT, MF, DENSE>(sa, n0, geom, clampc(c), nq, q0, a, cx);
     fwd_load_nbr<MF, T>(n1, geom, clampc(c + stride));
@@ -988,11 +998,11 @@ hipError_t launch_step_t(const typename GeomOf<T>::type* geom, const snrt_mesh& 
     });
 }
 
-template <typename T>
+template <typename T, typename GT = T>
 hipError_t launch_adjoint_t(const typename GeomOf<T>::type* geom, const snrt_mesh& m,
                             const T* tab, int32_t nq, const typename ArgsOf<T>::type& a,
-                            const T* psi_n, const T* lam_np1, T* lam_n, T* g_t, T* g_s, T* g_r,
-                            const T* G, hipStream_t st)
+                            const T* psi_n, const T* lam_np1, T* lam_n, GT* g_t, GT* g_s,
+                            GT* g_r, const T* G, hipStream_t st)
 {
     if (m.nc == 0) return hipSuccess;
     return dispatch_v<T>(nq, [&](auto vc, auto ex) {
@@ -1001,21 +1011,21 @@ hipError_t launch_adjoint_t(const typename GeomOf<T>::type* geom, const snrt_mes
         if constexpr (V * sizeof(T) > 32) {
             const unsigned blocks = (unsigned)((m.nc + kCellsPerBlock - 1) / kCellsPerBlock);
             if (G)
-                hipLaunchKernelGGL((k_adjoint<V, E, true, T>), dim3(blocks), dim3(kStepBlock), 0,
-                                   st, geom, m.nc, m.mf, nq, tab, a, psi_n, lam_np1, lam_n, g_t,
-                                   g_s, g_r, G);
+                hipLaunchKernelGGL((k_adjoint<V, E, true, T, GT>), dim3(blocks),
+                                   dim3(kStepBlock), 0, st, geom, m.nc, m.mf, nq, tab, a, psi_n,
+                                   lam_np1, lam_n, g_t, g_s, g_r, G);
             else
-                hipLaunchKernelGGL((k_adjoint<V, E, false, T>), dim3(blocks), dim3(kStepBlock),
-                                   0, st, geom, m.nc, m.mf, nq, tab, a, psi_n, lam_np1, lam_n,
-                                   g_t, g_s, g_r, G);
+                hipLaunchKernelGGL((k_adjoint<V, E, false, T, GT>), dim3(blocks),
+                                   dim3(kStepBlock), 0, st, geom, m.nc, m.mf, nq, tab, a, psi_n,
+                                   lam_np1, lam_n, g_t, g_s, g_r, G);
             return hipGetLastError();
         } else {
             auto go = [&](auto mfc, auto dc) {
                 constexpr int MF = decltype(mfc)::value;
                 constexpr bool D = decltype(dc)::value;
-                static const int occ = resident_blocks(k_adjoint_p<V, E, MF, D, T>);
+                static const int occ = resident_blocks(k_adjoint_p<V, E, MF, D, T, GT>);
                 const StepShape sh = step_shape(m, m.nc, 1, occ, tune().adjoint_blocks_per_cu);
-                hipLaunchKernelGGL((k_adjoint_p<V, E, MF, D, T>), dim3(sh.blocks),
+                hipLaunchKernelGGL((k_adjoint_p<V, E, MF, D, T, GT>), dim3(sh.blocks),
                                    dim3(kStepBlock), 0, st, geom, m.nc, nq, tab, a, psi_n,
                                    lam_np1, lam_n, g_t, g_s, g_r, G, sh.cells_per_xcd);
                 return hipGetLastError();

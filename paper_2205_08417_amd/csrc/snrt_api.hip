@@ -7,6 +7,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "snrt_internal.h"
@@ -428,12 +429,21 @@ snrt_status snrt_scatter_isotropic(snrt_scatter** out, const snrt_quad* q) {
 
 namespace {
 
-// Upload X [K][N] (host FP64) in FP64, FP32 and, for the BF16 modes, as tiled hi/lo parts.
+bool low_precision(snrt_precision p) {
+    return p == SNRT_BF16X3 || p == SNRT_BF16X2 || p == SNRT_BF16X1 || p == SNRT_FP16X3;
+}
+
+bool known_precision(snrt_precision p) { return p == SNRT_FP32 || low_precision(p); }
+
+// Upload X [K][N] (host FP64) in FP64, FP32 and, for the BF16 / FP16 modes, as tiled hi/lo
+// parts over N padded with zero columns to a multiple of 128 (FP16: of X * 2^eb, with eb
+// putting max |X| into [2^13, 2^14)).
 snrt_status make_operand(GemmOperand& op, const std::vector<double>& x, int32_t K, int32_t N,
                          snrt_precision precision, const char* fn) {
     const size_t n = (size_t)K * N;
     op.K = K;
     op.N = N;
+    op.Np = ((N + 127) / 128) * 128;
     std::vector<float> x32(n);
     for (size_t i = 0; i < n; ++i) x32[i] = (float)x[i];
     snrt_status s = SNRT_OK;
@@ -450,11 +460,33 @@ snrt_status make_operand(GemmOperand& op, const std::vector<double>& x, int32_t 
         if (e == hipSuccess) e = hipDeviceSynchronize();
         return e == hipSuccess ? SNRT_OK : hip_fail(e, fn);
     }
-    if ((s = dev_alloc(&op.hi, n, "scattering operand (BF16 hi)")) != SNRT_OK ||
-        (s = dev_alloc(&op.lo, n, "scattering operand (BF16 lo)")) != SNRT_OK)
+    const size_t np = (size_t)K * op.Np;
+    std::vector<float> xp(np, 0.0f);
+    double mx = 0.0;
+    for (int32_t k = 0; k < K; ++k)
+        for (int32_t j = 0; j < N; ++j) {
+            xp[(size_t)k * op.Np + j] = x32[(size_t)k * N + j];
+            mx = std::max(mx, std::fabs(x[(size_t)k * N + j]));
+        }
+    if (precision == SNRT_FP16X3 && mx > 0.0) {
+        int E = 0;
+        (void)std::frexp((double)(float)mx, &E);
+        op.eb = 14 - E;
+    }
+    float* staged = nullptr;
+    if ((s = dev_alloc(&op.hi, np, "scattering operand (hi)")) != SNRT_OK ||
+        (s = dev_alloc(&op.lo, np, "scattering operand (lo)")) != SNRT_OK ||
+        (s = dev_alloc(&staged, np, "scattering operand (staging)")) != SNRT_OK)
         return s;
-    hipError_t e = launch_split_bf16(op.f32, op.hi, op.lo, K, N, nullptr);
+    if ((s = upload(staged, xp.data(), np, fn)) != SNRT_OK) {
+        dev_free(staged);
+        return s;
+    }
+    hipError_t e = precision == SNRT_FP16X3
+                       ? launch_split_f16(staged, op.hi, op.lo, K, op.Np, op.eb, nullptr)
+                       : launch_split_bf16(staged, op.hi, op.lo, K, op.Np, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
+    dev_free(staged);
     return e == hipSuccess ? SNRT_OK : hip_fail(e, fn);
 }
 
@@ -467,13 +499,11 @@ snrt_status snrt_scatter_dense(snrt_scatter** out, const snrt_quad* q, const dou
     g_last_error.clear();
     SNRT_REQUIRE(out && q && K, SNRT_E_ARG, "snrt_scatter_dense: NULL argument");
     *out = nullptr;
-    SNRT_REQUIRE(precision == SNRT_FP32 || precision == SNRT_BF16X3 || precision == SNRT_BF16X1 ||
-                     precision == SNRT_BF16X2,
-                 SNRT_E_ARG, "snrt_scatter_dense: unknown precision");
+    SNRT_REQUIRE(known_precision(precision), SNRT_E_ARG, "snrt_scatter_dense: unknown precision");
     const int32_t nq = q->nq;
-    if (precision != SNRT_FP32) {
-        SNRT_REQUIRE(nq % 256 == 0, SNRT_E_UNSUPPORTED,
-                     "snrt_scatter_dense: BF16 modes need nq % 256 == 0");
+    if (low_precision(precision)) {
+        SNRT_REQUIRE(nq % 32 == 0, SNRT_E_UNSUPPORTED,
+                     "snrt_scatter_dense: the BF16 and FP16 modes need nq % 32 == 0");
     }
     SNRT_TRY(check_device(q->device, "snrt_scatter_dense"));
     const size_t n2 = (size_t)nq * nq;
@@ -507,22 +537,21 @@ snrt_status snrt_scatter_moments(snrt_scatter** out, const snrt_quad* q, int32_t
     g_last_error.clear();
     SNRT_REQUIRE(out && q && sigma_l, SNRT_E_ARG, "snrt_scatter_moments: NULL argument");
     *out = nullptr;
-    SNRT_REQUIRE(precision == SNRT_FP32 || precision == SNRT_BF16X3 || precision == SNRT_BF16X1 ||
-                     precision == SNRT_BF16X2,
-                 SNRT_E_ARG, "snrt_scatter_moments: unknown precision");
+    SNRT_REQUIRE(known_precision(precision), SNRT_E_ARG,
+                 "snrt_scatter_moments: unknown precision");
     SNRT_REQUIRE(degree >= 0 && degree <= 30, SNRT_E_ARG,
                  "snrt_scatter_moments: degree must be in [0, 30]");
     const int32_t nq = q->nq;
-    if (precision != SNRT_FP32) {
-        SNRT_REQUIRE(nq % 256 == 0, SNRT_E_UNSUPPORTED,
-                     "snrt_scatter_moments: BF16 modes need nq % 256 == 0");
+    if (low_precision(precision)) {
+        SNRT_REQUIRE(nq % 32 == 0, SNRT_E_UNSUPPORTED,
+                     "snrt_scatter_moments: the BF16 and FP16 modes need nq % 32 == 0");
     }
     for (int l = 0; l <= degree; ++l)
         SNRT_REQUIRE(is_finite(sigma_l[l]), SNRT_E_ARG,
                      "snrt_scatter_moments: non-finite Legendre moment");
     SNRT_TRY(check_device(q->device, "snrt_scatter_moments"));
     const int32_t nm = (degree + 1) * (degree + 1);
-    // the BF16 product takes inner and outer widths in multiples of 128
+    // the low-precision products take the moments (inner and outer width) in multiples of 128
     const int32_t mid = precision == SNRT_FP32 ? nm : ((nm + 127) / 128) * 128;
     // Mt[q][j] = w_q m_j(Omega_q), Ot[j][q] = sigma_l(j) m_j(Omega_q); zero past nm
     std::vector<double> mt((size_t)nq * mid, 0.0), ot((size_t)mid * nq, 0.0);
@@ -591,11 +620,13 @@ snrt_status snrt_scatter_moments(snrt_scatter** out, const snrt_quad* q, int32_t
 
 namespace {
 
-// Elements of the scattering product's workspace: S [nc][nq] and, for the moment form, the
-// moments U [nc][mid] between its two products.
+// Elements (4 or 8 bytes) of the scattering product's workspace: S [nc][nq], for the moment
+// form the moments U [nc][mid] between its two products, and for the FP16 mode the row
+// exponents [nc] (int32) of each product's left operand.
 size_t product_ws_elems(const snrt_scatter* sc, int64_t nc) {
     if (!sc->dense) return 0;
-    return (size_t)nc * (size_t)(sc->B.nq + (sc->B.chain == 2 ? sc->B.mid : 0));
+    return (size_t)nc * (size_t)(sc->B.nq + (sc->B.chain == 2 ? sc->B.mid : 0) +
+                                 (sc->B.precision == SNRT_FP16X3 ? 1 : 0));
 }
 
 // snrt_step_dose: the FP32 product workspace, then (16-byte aligned) one FP64 partial sum
@@ -706,28 +737,38 @@ StepArgs64 to64(const snrt_step_args_f64* a) {
     return r;
 }
 
-// out = in X for one right operand of the chain, in the handle's precision
+// out = in X for one right operand of the chain, in the handle's precision; rexp: [M] int32
+// scratch for the FP16 mode's row exponents
 hipError_t product32(const DenseB& B, const GemmOperand& op, const float* in, float* out,
-                     int64_t M, hipStream_t st) {
+                     int64_t M, int32_t* rexp, hipStream_t st) {
     if (B.precision == SNRT_FP32)
         return op.t32 ? launch_gemm_f32mfma(in, op.t32, out, M, op.K, op.N, st)
                       : launch_gemm32(in, op.f32, out, M, op.K, op.N, st);
+    if (B.precision == SNRT_FP16X3)
+        return launch_gemm_f16x3(in, op.hi, op.lo, out, M, op.K, op.Np, op.N, rexp, op.eb, st);
     const int products = B.precision == SNRT_BF16X3 ? 3 : B.precision == SNRT_BF16X2 ? 2 : 1;
-    return launch_gemm_bf16(in, op.hi, op.lo, out, M, op.K, op.N, products, st);
+    return launch_gemm_bf16(in, op.hi, op.lo, out, M, op.K, op.Np, op.N, products, st);
+}
+
+// The FP16 row exponents in the product workspace: after the moments of the moment form.
+int32_t* ws_rexp(const DenseB& B, float* after_S, int64_t M) {
+    return reinterpret_cast<int32_t*>(after_S + (B.chain == 2 ? (size_t)M * B.mid : 0));
 }
 
 // S = Psi B (forward) or G = Lambda B^T (adjoint) into the workspace, FP32 state
-// C = A X0 [X1] (forward) or A X0^T-side chain (adjoint); scratch holds the moments between
-// the two products of the moment form ([M][mid]).
+// C = A X0 [X1] (forward) or A X0^T-side chain (adjoint); after_S is the workspace past the
+// [M][nq] product: the moments between the two products of the moment form ([M][mid]), then
+// the FP16 row exponents ([M]).
 hipError_t scatter_product32(const snrt_scatter* sc, const float* A, float* C, int64_t M,
-                             bool transpose, float* scratch, hipStream_t st) {
+                             bool transpose, float* after_S, hipStream_t st) {
     const DenseB& B = sc->B;
     const GemmOperand* ops = transpose ? B.adj : B.fwd;
+    int32_t* rexp = after_S ? ws_rexp(B, after_S, M) : nullptr;
     const float* in = A;
     hipError_t e = hipSuccess;
     for (int i = 0; i < B.chain && e == hipSuccess; ++i) {
-        float* out = (i == B.chain - 1) ? C : scratch;
-        e = product32(B, ops[i], in, out, M, st);
+        float* out = (i == B.chain - 1) ? C : after_S;
+        e = product32(B, ops[i], in, out, M, rexp, st);
         in = out;
     }
     return e;
@@ -758,6 +799,45 @@ snrt_status check_step32(const char* fn, const snrt_mesh* m, const snrt_quad* q,
 }
 
 StepArgs32 step_args32(const snrt_step_args* a) { return to32(a); }
+
+// The FP32 adjoint step with gradient accumulators of type GT (float: snrt_step_adjoint;
+// double: the reverse pass of long rollouts).
+template <typename GT>
+snrt_status step_adjoint32_t(const char* fn, const snrt_mesh* m, const snrt_quad* q,
+                             const snrt_scatter* sc, const snrt_step_args* a,
+                             const float* psi_n, const float* lam_np1, float* lam_n, GT* g_t,
+                             GT* g_s, GT* g_r, void* ws, size_t ws_bytes, void* stream) {
+    SNRT_TRY(check_step_common(fn, m, q, sc, a, sizeof(float), lam_np1, lam_n, ws, ws_bytes));
+    if (m->nc == 0) return SNRT_OK;
+    SNRT_REQUIRE(psi_n && aligned16(psi_n), SNRT_E_ARG,
+                 std::string(fn) + ": psi_n NULL or misaligned");
+    const size_t bytes = (size_t)m->nc * q->nq * sizeof(float);
+    SNRT_REQUIRE(!ranges_overlap(psi_n, bytes, lam_n, bytes), SNRT_E_ALIAS,
+                 std::string(fn) + ": lam_n aliases psi_n");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const float* G = nullptr;
+    if (sc->dense) {
+        float* Gbuf = static_cast<float*>(ws);
+        hipError_t e = scatter_product32(sc, lam_np1, Gbuf, m->nc, true,
+                                         Gbuf + (size_t)m->nc * q->nq, st);
+        if (e != hipSuccess) return hip_fail(e, (std::string(fn) + ": scattering product").c_str());
+        G = Gbuf;
+    }
+    hipError_t e;
+    if constexpr (std::is_same<GT, double>::value)
+        e = launch_adjoint32_acc64(*m, *q, to32(a), psi_n, lam_np1, lam_n, g_t, g_s, g_r, G, st);
+    else
+        e = launch_adjoint32(*m, *q, to32(a), psi_n, lam_np1, lam_n, g_t, g_s, g_r, G, st);
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, (std::string(fn) + ": launch").c_str());
+}
+
+snrt_status step_adjoint32_acc64(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
+                                 const snrt_step_args* a, const float* psi_n,
+                                 const float* lam_np1, float* lam_n, double* g_t, double* g_s,
+                                 double* g_r, void* ws, size_t ws_bytes, void* stream) {
+    return step_adjoint32_t<double>("snrt_rollout_adjoint", m, q, sc, a, psi_n, lam_np1, lam_n,
+                                    g_t, g_s, g_r, ws, ws_bytes, stream);
+}
 
 }  // namespace snrt
 
@@ -844,25 +924,8 @@ snrt_status snrt_step_adjoint(const snrt_mesh* m, const snrt_quad* q, const snrt
                               float* lam_n, float* g_t, float* g_s, float* g_r, void* ws,
                               size_t ws_bytes, void* stream) {
     g_last_error.clear();
-    SNRT_TRY(check_step_common("snrt_step_adjoint", m, q, sc, a, sizeof(float), lam_np1, lam_n,
-                               ws, ws_bytes));
-    if (m->nc == 0) return SNRT_OK;
-    SNRT_REQUIRE(psi_n && aligned16(psi_n), SNRT_E_ARG,
-                 "snrt_step_adjoint: psi_n NULL or misaligned");
-    const size_t bytes = (size_t)m->nc * q->nq * sizeof(float);
-    SNRT_REQUIRE(!ranges_overlap(psi_n, bytes, lam_n, bytes), SNRT_E_ALIAS,
-                 "snrt_step_adjoint: lam_n aliases psi_n");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const float* G = nullptr;
-    if (sc->dense) {
-        float* Gbuf = static_cast<float*>(ws);
-        hipError_t e = scatter_product32(sc, lam_np1, Gbuf, m->nc, true,
-                                         Gbuf + (size_t)m->nc * q->nq, st);
-        if (e != hipSuccess) return hip_fail(e, "snrt_step_adjoint: scattering product");
-        G = Gbuf;
-    }
-    hipError_t e = launch_adjoint32(*m, *q, to32(a), psi_n, lam_np1, lam_n, g_t, g_s, g_r, G, st);
-    return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_step_adjoint: launch");
+    return step_adjoint32_t<float>("snrt_step_adjoint", m, q, sc, a, psi_n, lam_np1, lam_n, g_t,
+                                   g_s, g_r, ws, ws_bytes, stream);
 }
 
 snrt_status snrt_step_adjoint_f64(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
@@ -1049,9 +1112,10 @@ snrt_status imex_moments_common(const char* fn, const snrt_mesh* m, const snrt_q
         free_flight.alpha_t = 0.0f;
         free_flight.alpha_s = 0.0f;
         e = launch_free_step32(*m, *q, free_flight, psi_in, psi_out, st);
-        if (e == hipSuccess) e = product32(B, B.fwd[0], psi_out, U, m->nc, st);
+        int32_t* rexp = ws_rexp(B, U, m->nc);
+        if (e == hipSuccess) e = product32(B, B.fwd[0], psi_out, U, m->nc, rexp, st);
         if (e == hipSuccess) e = launch_imex_moment_scale32(a32, U, B.msig32, m->nc, B.mid, st);
-        if (e == hipSuccess) e = product32(B, B.fwd[1], U, S, m->nc, st);
+        if (e == hipSuccess) e = product32(B, B.fwd[1], U, S, m->nc, rexp, st);
         if (e == hipSuccess) e = launch_imex_combine32(a32, psi_out, S, m->nc, q->nq, st);
     } else {
         const StepArgs64 a64 = to64(a);
@@ -1092,12 +1156,12 @@ snrt_status snrt_step_imex_moments_f64(const snrt_mesh* m, const snrt_quad* q,
 }
 
 snrt_status snrt_scatter_apply(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
-                               const float* psi, float* S, int32_t transpose, void* stream) {
+                               const float* psi, float* S, int32_t transpose, void* ws,
+                               size_t ws_bytes, void* stream) {
     g_last_error.clear();
     SNRT_REQUIRE(m && q && sc, SNRT_E_ARG, "snrt_scatter_apply: NULL handle");
-    SNRT_REQUIRE(sc->dense, SNRT_E_UNSUPPORTED, "snrt_scatter_apply: needs a dense scatter handle");
-    SNRT_REQUIRE(sc->B.chain == 1, SNRT_E_UNSUPPORTED,
-                 "snrt_scatter_apply: the moment form needs a workspace; use the step entry points");
+    SNRT_REQUIRE(sc->dense, SNRT_E_UNSUPPORTED,
+                 "snrt_scatter_apply: needs a dense or moment scatter handle");
     SNRT_REQUIRE(sc->B.nq == q->nq, SNRT_E_SHAPE, "snrt_scatter_apply: scatter/quad nq differ");
     SNRT_REQUIRE(transpose == 0 || transpose == 1, SNRT_E_ARG, "snrt_scatter_apply: transpose is 0 or 1");
     SNRT_TRY(check_device(m->device, "snrt_scatter_apply"));
@@ -1106,7 +1170,18 @@ snrt_status snrt_scatter_apply(const snrt_mesh* m, const snrt_quad* q, const snr
                  "snrt_scatter_apply: NULL or misaligned array");
     const size_t bytes = (size_t)m->nc * q->nq * sizeof(float);
     SNRT_REQUIRE(!ranges_overlap(psi, bytes, S, bytes), SNRT_E_ALIAS, "snrt_scatter_apply: S aliases psi");
-    hipError_t e = scatter_product32(sc, psi, S, m->nc, transpose != 0, nullptr,
+    // the workspace past the product itself: moments and FP16 row exponents
+    const size_t need = (product_ws_elems(sc, m->nc) - (size_t)m->nc * q->nq) * sizeof(float);
+    float* after = nullptr;
+    if (need > 0) {
+        SNRT_REQUIRE(ws && ws_bytes >= need && aligned16(ws), SNRT_E_ARG,
+                     "snrt_scatter_apply: this handle needs a 16-byte aligned workspace of " +
+                         std::to_string(need) + " bytes");
+        SNRT_REQUIRE(!ranges_overlap(ws, need, psi, bytes) && !ranges_overlap(ws, need, S, bytes),
+                     SNRT_E_ALIAS, "snrt_scatter_apply: workspace aliases psi or S");
+        after = static_cast<float*>(ws);
+    }
+    hipError_t e = scatter_product32(sc, psi, S, m->nc, transpose != 0, after,
                                      static_cast<hipStream_t>(stream));
     return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_scatter_apply: launch");
 }

@@ -54,10 +54,13 @@ struct alignas(64) CellRecon64 {
 static_assert(sizeof(CellRecon64) == 128, "two cache lines per cell");
 
 // Right operand X [K][N] of a scattering product C = A X on the device, in every precision
-// the products use: FP32 and FP64 row-major, and BF16 hi/lo parts tiled by K chunks of 32
-// ([K/32][N][32]) for the MFMA kernel.
+// the products use: FP32 and FP64 row-major, and the BF16 or FP16 hi/lo parts for the MFMA
+// kernel, with the columns zero-padded to Np (a multiple of 128) and tiled by K chunks of 32
+// ([K/32][Np][32]); the FP16 parts hold X * 2^eb.
 struct GemmOperand {
     int32_t K = 0, N = 0;
+    int32_t Np = 0;           // padded width of the hi/lo parts
+    int32_t eb = 0;           // FP16 scale exponent of X
     float* f32 = nullptr;
     double* f64 = nullptr;
     uint16_t* hi = nullptr;
@@ -227,6 +230,12 @@ snrt_status check_step32(const char* fn, const snrt_mesh* m, const snrt_quad* q,
                          const snrt_scatter* sc, const snrt_step_args* a, const float* in,
                          float* out, void* ws, size_t ws_bytes);
 StepArgs32 step_args32(const snrt_step_args* a);
+// snrt_step_adjoint with the gradient contributions added to FP64 accumulators (the reverse
+// pass of long rollouts, where FP32 accumulators would drift by rounding).
+snrt_status step_adjoint32_acc64(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
+                                 const snrt_step_args* a, const float* psi_n,
+                                 const float* lam_np1, float* lam_n, double* g_t, double* g_s,
+                                 double* g_r, void* ws, size_t ws_bytes, void* stream);
 
 // dose_part: with the fused dose, the [nc * items per row] FP64 weighted sums of psi_in
 hipError_t launch_step32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
@@ -249,6 +258,11 @@ hipError_t launch_free_step64(const snrt_mesh& m, const snrt_quad& q, const Step
 hipError_t launch_adjoint32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
                             const float* psi_n, const float* lam_np1, float* lam_n,
                             float* g_t, float* g_s, float* g_r, const float* G, hipStream_t st);
+// the FP32 adjoint adding its gradient contributions to FP64 accumulators
+hipError_t launch_adjoint32_acc64(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
+                                  const float* psi_n, const float* lam_np1, float* lam_n,
+                                  double* g_t, double* g_s, double* g_r, const float* G,
+                                  hipStream_t st);
 hipError_t launch_adjoint64(const snrt_mesh& m, const snrt_quad& q, const StepArgs64& a,
                             const double* psi_n, const double* lam_np1, double* lam_n,
                             double* g_t, double* g_s, double* g_r, const double* G,
@@ -259,11 +273,21 @@ hipError_t launch_gemm32(const float* A, const float* B, float* C, int64_t M, in
                          int32_t N, hipStream_t st);
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int64_t M, int32_t K,
                          int32_t N, hipStream_t st);
+// Low-precision products on the matrix cores: X in the hi/lo tiled format with N padded
+// columns (N % 128 == 0, K % 32 == 0); C is [M][ldc], ldc <= N.  The FP16 form first writes
+// the row exponents of A to rexp [M] (device scratch) and scales X's part by 2^-eb.
 hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
-                            int64_t M, int32_t K, int32_t N, int products, hipStream_t st);
-// Re-layout of an FP32 [K][N] matrix into the BF16 hi/lo operand format of the MFMA GEMM.
+                            int64_t M, int32_t K, int32_t N, int32_t ldc, int products,
+                            hipStream_t st);
+hipError_t launch_gemm_f16x3(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
+                             int64_t M, int32_t K, int32_t N, int32_t ldc, int32_t* rexp,
+                             int32_t eb, hipStream_t st);
+// Re-layout of an FP32 [K][N] matrix (N % 128 == 0) into the BF16 hi/lo operand format of the
+// MFMA GEMM, and into the FP16 format of X * 2^eb.
 hipError_t launch_split_bf16(const float* B, uint16_t* hi, uint16_t* lo, int32_t K, int32_t N,
                              hipStream_t st);
+hipError_t launch_split_f16(const float* B, uint16_t* hi, uint16_t* lo, int32_t K, int32_t N,
+                            int32_t eb, hipStream_t st);
 // The FP32 product on the matrix cores (K % 32 == 0, N % 128 == 0) and its operand layout.
 hipError_t launch_gemm_f32mfma(const float* A, const float* Bt, float* C, int64_t M, int32_t K,
                                int32_t N, hipStream_t st);
@@ -313,6 +337,9 @@ hipError_t launch_dose_adjoint(const snrt_mesh& m, const snrt_quad& q, const flo
                                double coeff, const double* g_dose, float* lam, hipStream_t st);
 hipError_t launch_dose_density_grad(const snrt_mesh& m, const double* dose, const float* inv_rho,
                                     const double* g_dose, float* g_rho, hipStream_t st);
+hipError_t launch_dose_density_grad64(const snrt_mesh& m, const double* dose,
+                                      const float* inv_rho, const double* g_dose, double* g_rho,
+                                      hipStream_t st);
 
 // P_N step (sn_pn.hip): u_out = step(u_in) in the tiled moment layout; layout conversion
 // between the user's [ncells][nm] rows and the tiled internal layout.

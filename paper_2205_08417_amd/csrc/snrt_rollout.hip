@@ -6,6 +6,7 @@
 // with one Runge-Kutta stage (explicit Euler).
 #include <algorithm>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "snrt_internal.h"
@@ -30,10 +31,12 @@ template <> struct Api<float> {
                             void* st) {
         return snrt_step(m, q, sc, a, in, out, ws, wsb, st);
     }
+    // gradients accumulate in FP64 across the steps of a reverse pass
     static snrt_status adjoint(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
                                const Args* a, const float* psi, const float* l1, float* l0,
-                               float* gt, float* gs, float* gr, void* ws, size_t wsb, void* st) {
-        return snrt_step_adjoint(m, q, sc, a, psi, l1, l0, gt, gs, gr, ws, wsb, st);
+                               double* gt, double* gs, double* gr, void* ws, size_t wsb,
+                               void* st) {
+        return step_adjoint32_acc64(m, q, sc, a, psi, l1, l0, gt, gs, gr, ws, wsb, st);
     }
 };
 template <> struct Api<double> {
@@ -124,9 +127,9 @@ template <typename T>
 snrt_status rollout_adjoint_t(const char* fn, const snrt_mesh* m, const snrt_quad* q,
                               const snrt_scatter* sc, const typename Api<T>::Args* a,
                               const snrt_schedule* sched, int64_t nsteps, const T* ckpt,
-                              int32_t ckpt_every, T* seg, T* lam, T* tmp, T* g_t, T* g_s,
-                              T* g_r, const double* g_dose, void* ws, size_t ws_bytes,
-                              void* stream) {
+                              int32_t ckpt_every, T* seg, T* lam, T* tmp, double* g_t,
+                              double* g_s, double* g_r, const double* g_dose,
+                              const double* dose, void* ws, size_t ws_bytes, void* stream) {
     SNRT_REQUIRE(m && q && sc && a, SNRT_E_ARG, std::string(fn) + ": NULL handle or args");
     SNRT_REQUIRE(nsteps >= 0, SNRT_E_ARG, std::string(fn) + ": nsteps < 0");
     SNRT_REQUIRE(ckpt_every >= 1, SNRT_E_ARG, std::string(fn) + ": ckpt_every must be >= 1");
@@ -175,6 +178,13 @@ snrt_status rollout_adjoint_t(const char* fn, const snrt_mesh* m, const snrt_qua
         }
     }
     if (s == SNRT_OK) s = copy_state(lam, pl, bytes, st, fn);
+    if constexpr (std::is_same<T, float>::value) {
+        // the explicit density derivative of the dose, -D_i (1/rho_i) dJ/dD_i
+        if (s == SNRT_OK && g_dose && dose && g_r) {
+            hipError_t e = launch_dose_density_grad64(*m, dose, a->inv_rho, g_dose, g_r, st);
+            if (e != hipSuccess) s = hip_fail(e, fn);
+        }
+    }
     return s;
 }
 
@@ -203,13 +213,13 @@ snrt_status snrt_rollout_f64(const snrt_mesh* m, const snrt_quad* q, const snrt_
 snrt_status snrt_rollout_adjoint(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
                                  const snrt_step_args* a, const snrt_schedule* sched,
                                  int64_t nsteps, const float* ckpt, int32_t ckpt_every,
-                                 float* seg, float* lam, float* tmp, float* g_sigma_t,
-                                 float* g_sigma_s, float* g_rho, const double* g_dose, void* ws,
-                                 size_t ws_bytes, void* stream) {
+                                 float* seg, float* lam, float* tmp, double* g_sigma_t,
+                                 double* g_sigma_s, double* g_rho, const double* g_dose,
+                                 const double* dose, void* ws, size_t ws_bytes, void* stream) {
     set_error("");
     return rollout_adjoint_t<float>("snrt_rollout_adjoint", m, q, sc, a, sched, nsteps, ckpt,
                                     ckpt_every, seg, lam, tmp, g_sigma_t, g_sigma_s, g_rho,
-                                    g_dose, ws, ws_bytes, stream);
+                                    g_dose, dose, ws, ws_bytes, stream);
 }
 
 snrt_status snrt_rollout_adjoint_f64(const snrt_mesh* m, const snrt_quad* q,
@@ -222,7 +232,7 @@ snrt_status snrt_rollout_adjoint_f64(const snrt_mesh* m, const snrt_quad* q,
     set_error("");
     return rollout_adjoint_t<double>("snrt_rollout_adjoint_f64", m, q, sc, a, sched, nsteps, ckpt,
                                      ckpt_every, seg, lam, tmp, g_sigma_t, g_sigma_s, g_rho,
-                                     nullptr, ws, ws_bytes, stream);
+                                     nullptr, nullptr, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -31,6 +31,7 @@ SNRT_FP32 = 0
 SNRT_BF16X3 = 1
 SNRT_BF16X1 = 2
 SNRT_BF16X2 = 3
+SNRT_FP16X3 = 4
 
 SNRT_REORDER_HILBERT = 0
 SNRT_NO_REORDER = 1
@@ -147,7 +148,8 @@ def lib() -> ctypes.CDLL:
                                     _vp, _vp, _vp, ctypes.c_size_t, _vp]),
         "snrt_step_adjoint_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp,
                                         _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
-        "snrt_scatter_apply": (_st, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp]),
+        "snrt_scatter_apply": (_st, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp,
+                                     ctypes.c_size_t, _vp]),
         "snrt_mass": (_st, [_vp, _vp, _vp, _vp, _vp]),
         "snrt_scalar_flux": (_st, [_vp, _vp, _vp, _vp, _vp]),
         "snrt_dose_accumulate": (_st, [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp]),
@@ -189,7 +191,7 @@ def lib() -> ctypes.CDLL:
         "snrt_rollout_adjoint": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs),
                                        ctypes.POINTER(Schedule), ctypes.c_int64, _vp,
                                        ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                                       ctypes.c_size_t, _vp]),
+                                       _vp, ctypes.c_size_t, _vp]),
         "snrt_rollout_adjoint_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs),
                                            ctypes.POINTER(Schedule), ctypes.c_int64, _vp,
                                            ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -457,9 +459,11 @@ def snrt_step_adjoint_f64(mesh, quad, scatter, args: StepArgs, psi_n, lam_np1, l
                                        _stream(stream)))
 
 
-def snrt_scatter_apply(mesh, quad, scatter, psi, S, transpose=0, stream=None) -> None:
+def snrt_scatter_apply(mesh, quad, scatter, psi, S, transpose=0, ws=None, ws_bytes=0,
+                       stream=None) -> None:
     _check("snrt_scatter_apply", lib().snrt_scatter_apply(mesh, quad, scatter, _ptr(psi), _ptr(S),
-                                                          int(transpose), _stream(stream)))
+                                                          int(transpose), _ptr(ws),
+                                                          int(ws_bytes), _stream(stream)))
 
 
 def snrt_mass(mesh, quad, psi, out_dev, stream=None) -> None:
@@ -521,15 +525,15 @@ def snrt_rollout_f64(mesh, quad, scatter, args: StepArgs, sched: Optional[Schedu
 
 def snrt_rollout_adjoint(mesh, quad, scatter, args: StepArgs, sched: Optional[Schedule],
                          nsteps: int, ckpt, ckpt_every: int, seg, lam, tmp, g_sigma_t=None,
-                         g_sigma_s=None, g_rho=None, g_dose=None, ws=None, ws_bytes=0,
-                         stream=None) -> None:
+                         g_sigma_s=None, g_rho=None, g_dose=None, dose=None, ws=None,
+                         ws_bytes=0, stream=None) -> None:
     _check("snrt_rollout_adjoint",
            lib().snrt_rollout_adjoint(mesh, quad, scatter, ctypes.byref(args),
                                       None if sched is None else ctypes.byref(sched),
                                       int(nsteps), _ptr(ckpt), int(ckpt_every), _ptr(seg),
                                       _ptr(lam), _ptr(tmp), _ptr(g_sigma_t), _ptr(g_sigma_s),
-                                      _ptr(g_rho), _ptr(g_dose), _ptr(ws), int(ws_bytes),
-                                      _stream(stream)))
+                                      _ptr(g_rho), _ptr(g_dose), _ptr(dose), _ptr(ws),
+                                      int(ws_bytes), _stream(stream)))
 
 
 def snrt_rollout_adjoint_f64(mesh, quad, scatter, args: StepArgs, sched: Optional[Schedule],

@@ -16,7 +16,7 @@ from . import snrt
 from .inputs import Problem
 
 _PREC = {"fp32": snrt.SNRT_FP32, "bf16x3": snrt.SNRT_BF16X3, "bf16x2": snrt.SNRT_BF16X2,
-         "bf16x1": snrt.SNRT_BF16X1}
+         "bf16x1": snrt.SNRT_BF16X1, "fp16x3": snrt.SNRT_FP16X3}
 
 
 def _require_gpu():
@@ -28,8 +28,7 @@ class Solver:
     """Device-resident S_N problem: mesh / quadrature / scattering handles and materials.
 
     ``precision`` selects the dense scattering product (``fp32``, ``bf16x3``, ``bf16x2``,
-    ``bf16x1``);
-    isotropic problems ignore it.  ``moments`` (Legendre moments sigma_0..sigma_N of the
+    ``bf16x1``, ``fp16x3``); isotropic problems ignore it.  ``moments`` (Legendre moments sigma_0..sigma_N of the
     scattering kernel) selects the moment-projected scattering O Sigma M instead of ``P.K``.  ``fp64`` additionally uploads FP64 copies of the
     materials for the FP64 parity template (:meth:`step_f64`).
     """
@@ -359,9 +358,11 @@ class SNRollout(torch.autograd.Function):
         lam = (torch.zeros((S.nc, S.nq), dtype=dt, device=dev) if g_psi is None
                else g_psi.to(dt).contiguous().clone())
         tmp = torch.empty_like(lam)
-        g_t = torch.zeros(S.nc, dtype=dt, device=dev)
-        g_s = torch.zeros(S.nc, dtype=dt, device=dev)
-        g_r = torch.zeros(S.nc, dtype=dt, device=dev) if inv_rho is not None else None
+        # the reverse pass accumulates the gradients in FP64 (one small contribution per step)
+        f64 = torch.float64
+        g_t = torch.zeros(S.nc, dtype=f64, device=dev)
+        g_s = torch.zeros(S.nc, dtype=f64, device=dev)
+        g_r = torch.zeros(S.nc, dtype=f64, device=dev) if inv_rho is not None else None
         gd = None if (g_dose is None or dose is None) else g_dose.to(torch.float64).contiguous()
         seg = (torch.empty((K - 1,) + tuple(lam.shape), dtype=lam.dtype, device=dev)
                if K > 1 else None)
@@ -371,10 +372,11 @@ class SNRollout(torch.autograd.Function):
                                           S.ws_bytes, ctx.stream)
         else:
             snrt.snrt_rollout_adjoint(S.mesh, S.quad, S.scatter, ctx.base, ctx.sched, N,
-                                      ctx.ck_store, K, seg, lam, tmp, g_t, g_s, g_r, gd, ctx.ws,
-                                      S.ws_bytes, ctx.stream)
-        if gd is not None and g_r is not None:
-            snrt.snrt_dose_density_grad(S.mesh, dose, inv_rho, gd, g_r, ctx.stream)
+                                      ctx.ck_store, K, seg, lam, tmp, g_t, g_s, g_r, gd, dose,
+                                      ctx.ws, S.ws_bytes, ctx.stream)
+        g_t, g_s = g_t.to(st.dtype), g_s.to(ss.dtype)
+        if g_r is not None:
+            g_r = g_r.to(inv_rho.dtype)
         return (lam, g_t, g_s, g_r, None, None, None, None, None, None, None)
 
 

@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol(L):
 
 
 def test_abi_version(L):
-    assert snrt.snrt_abi_version() == 1
+    assert snrt.snrt_abi_version() == 2
 
 
 def test_rejects_null_and_bad_sizes_before_device_use(L):

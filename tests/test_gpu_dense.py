@@ -42,7 +42,7 @@ def _oracle(P, nsteps):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16x3", 1e-3), ("bf16x2", 1e-3),
-                                           ("bf16x1", 1e-2)])
+                                           ("bf16x1", 1e-2), ("fp16x3", 1e-4)])
 def test_hg_linesource_256_ordinates(precision, tol):
     """HG g=0.9 line source, 30x30 points (1 682 cells, two ragged 128-cell tiles), 16x16
     ordinates, 40 steps."""
@@ -53,7 +53,7 @@ def test_hg_linesource_256_ordinates(precision, tol):
     assert err <= tol
 
 
-@pytest.mark.parametrize("precision,tol", [("bf16x3", 1e-5), ("bf16x2", 1e-4)])
+@pytest.mark.parametrize("precision,tol", [("bf16x3", 1e-5), ("bf16x2", 1e-4), ("fp16x3", 1e-6)])
 def test_bf16_512_ordinates_rough_state(precision, tol):
     """16x32 = 512 ordinates (two N tiles), a state spanning 6 decades, one step."""
     P = I.build("csd_phantom_s512", n_side=14, nsteps=1)
@@ -64,7 +64,7 @@ def test_bf16_512_ordinates_rough_state(precision, tol):
     assert err <= tol
 
 
-@pytest.mark.parametrize("precision", ["bf16x3", "bf16x2"])
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16x2", "fp16x3"])
 def test_bf16_full_size_linesource_sampled(precision):
     """Full HG line source (100 352 cells x 1024 ordinates) in the benchmark's launch shape:
     one step from the seeded pulse, sampled cells checked one by one."""
@@ -115,18 +115,22 @@ def test_bf16x3_full_size_csd_sampled():
     assert derr <= 1e-6
 
 
-def test_bf16_requires_256_multiple():
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3"])
+def test_low_precision_requires_32_multiple(precision):
+    """The product runs K in chunks of 32: 6 x 8 = 48 ordinates are refused."""
     from paper_2205_08417_amd import snrt
-    omega, w = I.product_quadrature(8, 8)
+    from paper_2205_08417_amd.solver import _PREC
+    omega, w = I.product_quadrature(6, 8)
     K = I.henyey_greenstein_kernel(omega, w, 0.5)
     q = snrt.snrt_quad_create(omega, w)
     with pytest.raises(snrt.SnrtError) as ei:
-        snrt.snrt_scatter_dense(q, K, snrt.SNRT_BF16X3)
+        snrt.snrt_scatter_dense(q, K, _PREC[precision])
     assert ei.value.status == snrt.SNRT_E_UNSUPPORTED
     snrt.snrt_quad_destroy(q)
 
 
-@pytest.mark.parametrize("precision,tol", [("bf16x3", 2e-5), ("bf16x2", 2e-3), ("bf16x1", 1e-2)])
+@pytest.mark.parametrize("precision,tol", [("bf16x3", 2e-5), ("bf16x2", 2e-3), ("bf16x1", 1e-2),
+                                           ("fp16x3", 1e-6)])
 def test_bf16_product_with_partial_last_round(precision, tol):
     """71 442 cells x 256 ordinates: 280 row tiles of 256 over the compute units leave a
     partial last round, whose rows the library runs as 64-row blocks (ragged at the end).
@@ -144,7 +148,7 @@ def test_bf16_product_with_partial_last_round(precision, tol):
     S = Solver(P, precision=precision)
     x = S.to_internal(psi)
     out = torch.empty_like(x)
-    snrt.snrt_scatter_apply(S.mesh, S.quad, S.scatter, x, out)
+    snrt.snrt_scatter_apply(S.mesh, S.quad, S.scatter, x, out, 0, S.ws, S.ws_bytes)
     got = out.cpu().numpy().astype(np.float64)
     ref = x.cpu().numpy().astype(np.float64) @ (w[:, None] * K.T)
     S.close()
@@ -152,3 +156,24 @@ def test_bf16_product_with_partial_last_round(precision, tol):
     err, err_tail = rel_l2(got, ref), rel_l2(got[tail:], ref[tail:])
     print(f"{precision}: all {err:.2e}, tail rows {err_tail:.2e}")
     assert err <= tol and err_tail <= tol
+
+
+@pytest.mark.parametrize("npol,naz", [(8, 8), (4, 24), (5, 32)])
+@pytest.mark.parametrize("precision,tol", [("bf16x3", 1e-5), ("bf16x2", 2e-4), ("fp16x3", 1e-6)])
+def test_low_precision_products_on_padded_widths(npol, naz, precision, tol):
+    """Ordinate counts that are multiples of 32 but not of 128 (64, 96, 160): the product's
+    operand is zero-padded to the next 128 columns and only nq are written.  One step from a
+    state spanning 6 decades (the FP16 mode's per-row scaling), every element against the
+    oracle, on 17 x 17 points (512 cells: two full 256-row tiles)."""
+    from _util import small_problem
+    omega, w = I.product_quadrature(npol, naz)
+    K = I.henyey_greenstein_kernel(omega, w, 0.9)
+    P = small_problem(I.jittered_delaunay_mesh(17, 0.0, 1.0, seed=81), omega_w=(omega, w), K=K,
+                      rho=True, seed=81, scatter=(0.5, 1.0), nsteps=1)
+    P = dataclasses.replace(P, psi0=I.random_state(P.ncells, P.nq, seed=82))
+    ref = _oracle(P, 1)
+    got = _run(P, 1, precision)
+    err = rel_l2(got, ref)
+    worst = float(np.max(np.abs(got - ref) / (np.abs(ref) + 1e-30)))
+    print(f"{precision} nq={P.nq}: rel-L2 {err:.2e}, worst element relative {worst:.2e}")
+    assert err <= tol

@@ -9,6 +9,10 @@
   the oracle's reverse pass, and central differences of the full 400-step workload on 20
   seeded cells per cross section (FP64 template for the differences).
 - The mixed-precision products over 200 steps at 1024 ordinates against the oracle.
+- The reduced CSD dose workload over its whole energy range (5 000 cells, 64 ordinates,
+  15 812 steps, checkpoints every 20) with the mixed-precision products: dose and the
+  gradient of the target-minus-organ dose functional w.r.t. density against the oracle's
+  values stored by tests/golden/make_csd_reduced_gradient.py.
 
 Element-wise bounds are |x - ref| <= rtol |ref| + atol with atol a small fraction of the
 largest |ref| (the floor covers entries that are sums of terms of both signs); the worst
@@ -239,7 +243,7 @@ def linesource_1024():
 
 
 @pytest.mark.parametrize("precision,tol", [("bf16x3", 1e-4), ("bf16x2", 1e-3),
-                                           ("fp32", 1e-5)])
+                                           ("fp16x3", 1e-4), ("fp32", 1e-5)])
 def test_mixed_precision_1024_ordinates_200_steps(linesource_1024, precision, tol):
     """Error of the whole 200-step run at 1024 ordinates against the FP64 oracle: rel-L2 and
     max|err| / max|ref| within the product's bound (hi+lo BF16 at 1e-3, the three-product
@@ -253,3 +257,43 @@ def test_mixed_precision_1024_ordinates_200_steps(linesource_1024, precision, to
     mx = float(np.max(np.abs(out - ref)) / np.max(np.abs(ref)))
     print(f"{precision} 1024 ordinates, 200 steps: rel-L2 {err:.2e}, max-abs/max-ref {mx:.2e}")
     assert err <= tol and mx <= tol
+
+
+# ------------------------------------------------------------------ CSD dose gradient
+
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3", "fp32"])
+def test_csd_reduced_dose_gradient_full_energy_range(precision):
+    """The reduced CSD workload from 20 MeV to 0.1 MeV: GPU dose (FP64 accumulation) and
+    the density gradient of J = sum_T A D - sum_O A D through the differentiable rollout
+    (checkpoints every 20 steps, the mixed-precision product forward and transposed) against
+    the oracle's reverse pass: dose rel-L2 <= 1e-4, gradient rel-L2 <= 1e-4 and element-wise
+    within 1e-3 relative above a floor of 1e-4 max|g|."""
+    import importlib.util
+    import os
+    from paper_2205_08417_amd.solver import differentiable_rollout
+    here = os.path.dirname(os.path.abspath(__file__))
+    spec = importlib.util.spec_from_file_location(
+        "make_csd", os.path.join(here, "golden", "make_csd_reduced_gradient.py"))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    P = gen.problem()
+    ref = np.load(os.path.join(here, "golden", "csd_reduced_gradient.npz"))
+    assert str(ref["digest"]) == gen.input_digest(P), "inputs differ from the stored run"
+    n = P.nsteps
+    print(f"CSD reduced: {P.ncells} x {P.nq}, {n} steps, {precision}", flush=True)
+    S = _solver(P, precision=precision)
+    psi0 = S.initial_state()
+    r = S.cells_to_internal(P.rho).requires_grad_(True)
+    psiN, dose = differentiable_rollout(S, psi0, n, rho=r, ckpt_every=20,
+                                        inflow_scale=np.asarray(P.meta["inflow_scale"]),
+                                        dose_coeff=np.asarray(P.meta["dose_coeff"]))
+    w_d = S.cells_to_internal(gen.functional_weights(P), torch.float64)
+    J = torch.sum(w_d * dose)
+    J.backward()
+    d = _cells_user(S, dose.detach())
+    g = _cells_user(S, r.grad)
+    S.close()
+    e_d, e_g = rel_l2(d, ref["dose"]), rel_l2(g, ref["g_rho"])
+    print(f"{precision}: dose rel-L2 {e_d:.2e}, density gradient rel-L2 {e_g:.2e}")
+    assert e_d <= 1e-4 and e_g <= 1e-4
+    check_elementwise(f"{precision} density gradient", g, ref["g_rho"], 1e-3, 1e-4)

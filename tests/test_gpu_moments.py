@@ -128,12 +128,29 @@ def test_full_size_line_source_moments_sampled():
     assert err <= 1e-4
 
 
-def test_scatter_apply_rejects_the_moment_form():
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-6), ("bf16x3", 1e-5), ("fp16x3", 1e-6)])
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_scatter_apply_moment_form(precision, tol, transpose):
+    """snrt_scatter_apply of the moment form (with its workspace) against the equivalent
+    dense kernel built by the oracle's own harmonics; the transposed product too.  A
+    workspace is required."""
+    from oracle import moments as mo
     from paper_2205_08417_amd import snrt
     P = _problem(16, 16, seed=43)
-    S = _solver(P, moments=[1.0, 0.5])
-    psi = S.initial_state()
+    sig = I.hg_legendre_moments(0.8, 6)
+    S = _solver(P, moments=sig, precision=precision)
+    rng = np.random.default_rng(44)
+    x = torch.tensor(rng.uniform(0.0, 1.0, (P.ncells, P.nq)), dtype=torch.float32, device="cuda")
+    out = torch.empty_like(x)
     with pytest.raises(snrt.SnrtError) as ei:
-        snrt.snrt_scatter_apply(S.mesh, S.quad, S.scatter, psi, torch.empty_like(psi))
-    assert ei.value.status == snrt.SNRT_E_UNSUPPORTED
+        snrt.snrt_scatter_apply(S.mesh, S.quad, S.scatter, x, out, transpose)
+    assert ei.value.status == snrt.SNRT_E_ARG
+    snrt.snrt_scatter_apply(S.mesh, S.quad, S.scatter, x, out, transpose, S.ws, S.ws_bytes)
+    Kd = mo.moment_kernel(P.omega, P.w, sig)
+    B = P.w[:, None] * Kd.T                      # S = Psi B, B[p][q] = w_p K[q][p]
+    xs = x.cpu().numpy().astype(np.float64)
+    ref = xs @ (B if transpose == 0 else B.T)
+    err = rel_l2(out.cpu().numpy(), ref)
+    print(f"moment-form product {precision} transpose={transpose}: {err:.2e}")
+    assert err <= tol
     S.close()
