@@ -78,7 +78,7 @@ def cpu_baseline(P, budget_s: float = 36.0):
     el = time.perf_counter() - t0
     reference = (n + 1, psi)
     out = {"value": P.ncells * P.nq * n / el, "unit": "cell-ordinate updates/s",
-           "cores": o.num_threads(), "kind": "oracle",
+           "cores": o.num_threads(), "cpu_model": host_cpu_model(), "kind": "oracle",
            "sample": f"{n} FP64 oracle steps of the full {WORKLOAD} workload "
                      f"({P.ncells} cells x {P.nq} ordinates), {el:.1f} s wall"}
     # the same oracle on one host thread, over a shorter sample
@@ -94,6 +94,48 @@ def cpu_baseline(P, budget_s: float = 36.0):
     out["single_thread"] = {"value": P.ncells * P.nq * n1 / el1, "cores": 1,
                             "sample": f"{n1} steps, {el1:.1f} s wall"}
     return out, reference
+
+
+def host_cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo; empty if unavailable)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
+def sample_cells(nc: int, n: int = 256, seed: int = 0):
+    import numpy as np
+    return np.sort(np.random.default_rng(seed).choice(nc, min(n, nc), replace=False))
+
+
+def oracle_error(got_rows, ref_rows, what: str) -> dict:
+    """Error of GPU rows against the oracle's rows for the same cells and input state."""
+    import numpy as np
+    got = np.asarray(got_rows, dtype=np.float64)
+    ref = np.asarray(ref_rows, dtype=np.float64)
+    nr = float(np.linalg.norm(ref))
+    return {"rel_l2": float(np.linalg.norm(got - ref)) / (nr if nr > 0 else 1.0),
+            "max_abs_over_max_ref": float(np.max(np.abs(got - ref)) /
+                                          max(float(np.max(np.abs(ref))), 1e-300)),
+            "check": what}
+
+
+def step_vs_oracle(S, psi, oracle_fn, n: int = 256, seed: int = 0,
+                   step=None, what: str = "one step") -> dict:
+    """One more step of the GPU path from the section's final state ``psi`` (internal order)
+    against the FP64 oracle's step from the same state, on ``n`` seeded cells."""
+    import torch
+    out = torch.empty_like(psi)
+    (step or S.step)(psi, out)
+    cells = sample_cells(S.nc, n, seed)
+    got = S.to_user(out).cpu().numpy()[cells]
+    start = S.to_user(psi).cpu().numpy().astype("float64")
+    ref = oracle_fn(start, cells)
+    return oracle_error(got, ref, f"{what} from the final state, {cells.size} seeded cells")
 
 
 def timed(fn, n, stream):
@@ -128,82 +170,82 @@ def product_rate(S, psi, reps: int = 10, passes: int = 3, kernel: str = "k_gemm_
 
 
 def bench_dense(steps, warmup: int):
-    """Anisotropic HG line source (100 352 cells x 1024 ordinates) with the BF16 hi+lo MFMA
-    scattering product.  The whole 200-step run is timed from the initial pulse (steps=None;
-    warm-up steps run on a separate copy first): early states are mostly exact zeros, on
-    which the matrix cores draw less power and clock higher, so a window of early steps
-    alone would flatter the rate.  The product's MFMA utilisation is measured on the run's
-    final state and, for comparison, on a dense random state."""
+    """Anisotropic HG line source (100 352 cells x 1024 ordinates) with the scattering product
+    in each mixed precision (BF16 hi+lo in three and two products, FP16 hi+lo in three) and
+    in FP32.  Each low-precision run is timed over the whole 200-step workload from the
+    initial pulse (steps=None; warm-up steps run on a separate copy first): early states are
+    mostly exact zeros, on which the matrix cores draw less power and clock higher, so a
+    window of early steps alone would flatter the rate.  The products' MFMA utilisation is
+    measured on the run's final state and on a dense random state; every precision's final
+    state then takes one more step whose sampled cells are checked against the FP64 oracle."""
     import torch
+    from oracle import oracle as o
     from paper_2205_08417_amd import inputs as I
     from paper_2205_08417_amd.solver import Solver
 
     P = I.build(DENSE_WORKLOAD)
     nsteps = P.nsteps if steps is None else steps
-    S = Solver(P, precision="bf16x3")
-    args = S.args()
+    op = o.OracleProblem.from_problem(P)
     stream = torch.cuda.current_stream()
-    state = [S.initial_state(), None]
-    state[1] = torch.empty_like(state[0])
 
-    def one_step():
-        S.step(state[0], state[1], args)
-        state.reverse()
+    def whole_run(precision, nrun, warm):
+        S = Solver(P, precision=precision)
+        args = S.args()
+        st = [S.initial_state(), None]
+        st[1] = torch.empty_like(st[0])
 
-    for _ in range(warmup):
-        one_step()
-    state[0] = S.initial_state()
-    torch.cuda.synchronize()
-    ms_step = timed(one_step, nsteps, stream)
-    final = product_rate(S, state[0])
-    dense = product_rate(S, torch.rand_like(state[0]))
-    ref_state = state[0].clone()
-    S.close()
-    # the two-product mode (the kernel split hi+lo, the state in BF16): the same whole run,
-    # and its final state against the three-product one
-    S2 = Solver(P, precision="bf16x2")
-    args2 = S2.args()
-    st2 = [S2.initial_state(), None]
-    st2[1] = torch.empty_like(st2[0])
+        def one_step():
+            S.step(st[0], st[1], args)
+            st.reverse()
 
-    def step2():
-        S2.step(st2[0], st2[1], args2)
-        st2.reverse()
+        for _ in range(warm):
+            one_step()
+        st[0] = S.initial_state()
+        torch.cuda.synchronize()
+        return S, st[0], timed(one_step, nrun, stream)
 
-    for _ in range(min(warmup, 5)):
-        step2()
-    st2[0] = S2.initial_state()
-    torch.cuda.synchronize()
-    ms_x2 = timed(step2, nsteps, stream)
-    x2_diff = float(torch.linalg.vector_norm((st2[0] - ref_state).double()) /
-                    torch.linalg.vector_norm(ref_state.double()))
-    S2.close()
-    # the same step with the FP32 scattering product (vector FMA kernel), 20 steps from the
+    def oracle_rows(start, cells):
+        return o.step(op, start, P.dt, cells=cells)
+
+    out = {"workload": DENSE_WORKLOAD, "cells": P.ncells, "ordinates": P.nq,
+           "scattering": "Henyey-Greenstein g=0.9, dense, column-normalised", "steps": nsteps,
+           "unit": "cell-ordinate updates/s"}
+    finals = {}
+    for precision, label in (("bf16x3", "BF16 hi+lo, three products"),
+                             ("bf16x2", "BF16, operand hi+lo and state once: two products"),
+                             ("fp16x3", "FP16 hi+lo with per-row power-of-2 scaling, three "
+                                        "products")):
+        S, final, ms = whole_run(precision, nsteps, warmup if precision == "bf16x3" else 3)
+        passes = 2 if precision == "bf16x2" else 3
+        sec = {"precision": label, "ms_per_step": ms, "steps": nsteps,
+               "value": P.ncells * P.nq / (ms * 1e-3),
+               "scatter_product": product_rate(S, final, passes=passes,
+                                               kernel="k_gemm_f16" if precision == "fp16x3"
+                                               else "k_gemm_bf16"),
+               "scatter_product_dense_random_state":
+                   product_rate(S, torch.rand_like(final), passes=passes,
+                                kernel="k_gemm_f16" if precision == "fp16x3" else "k_gemm_bf16"),
+               "vs_oracle": step_vs_oracle(S, final, oracle_rows)}
+        finals[precision] = final.clone()
+        S.close()
+        out[precision] = sec
+    for k in ("bf16x2", "fp16x3"):
+        out[k]["rel_l2_vs_bf16x3_final_state"] = float(
+            torch.linalg.vector_norm((finals[k] - finals["bf16x3"]).double()) /
+            torch.linalg.vector_norm(finals["bf16x3"].double()))
+    # the headline figures of the section: the three-product BF16 run
+    out.update({"precision": "bf16x3 (hi+lo split, FP32 accumulate)",
+                "value": out["bf16x3"]["value"], "ms_per_step": out["bf16x3"]["ms_per_step"],
+                "rel_l2_vs_oracle": out["bf16x3"]["vs_oracle"]["rel_l2"]})
+    # the same step with the FP32 scattering product (on the matrix cores), 20 steps from the
     # initial state: the FP32 side of the FP32-vs-mixed comparison
-    S32 = Solver(P, precision="fp32")
-    args32 = S32.args()
-    st32 = [S32.initial_state(), None]
-    st32[1] = torch.empty_like(st32[0])
-
-    def step32():
-        S32.step(st32[0], st32[1], args32)
-        st32.reverse()
-
-    step32()
-    torch.cuda.synchronize()
-    ms_fp32 = timed(step32, 20, stream)
-    fp32_product = product_rate(S32, st32[0], passes=1, kernel="k_gemm_f32",
-                                peak=FP32_MFMA_PEAK_TFLOPS)
+    S32, final32, ms32 = whole_run("fp32", 20, 1)
+    out["fp32"] = {"ms_per_step": ms32, "steps": 20,
+                   "scatter_product": product_rate(S32, final32, passes=1, kernel="k_gemm_f32",
+                                                   peak=FP32_MFMA_PEAK_TFLOPS),
+                   "vs_oracle": step_vs_oracle(S32, final32, oracle_rows)}
     S32.close()
-    return {"workload": DENSE_WORKLOAD, "cells": P.ncells, "ordinates": P.nq,
-            "scattering": "Henyey-Greenstein g=0.9, dense, column-normalised",
-            "precision": "bf16x3 (hi+lo split, FP32 accumulate)", "steps": nsteps,
-            "value": P.ncells * P.nq / (ms_step * 1e-3), "unit": "cell-ordinate updates/s",
-            "ms_per_step": ms_step,
-            "fp32_product_ms_per_step": ms_fp32, "fp32_scatter_product": fp32_product,
-            "scatter_product": final, "scatter_product_dense_random_state": dense,
-            "bf16x2": {"ms_per_step": ms_x2, "steps": nsteps,
-                       "rel_l2_vs_bf16x3_final_state": x2_diff}}
+    return out
 
 
 def library_gemm_ceiling(M: int, nq: int, reps: int = 10):
@@ -298,6 +340,13 @@ def bench_csd(steps, warmup: int):
     final = product_rate(S, state[0])
     dense = product_rate(S, torch.rand_like(state[0]))
     dose_ref = dose.clone()
+    from oracle import oracle as o
+    op = o.OracleProblem.from_problem(P)
+    last = nsteps - 1
+    vs_oracle = step_vs_oracle(
+        S, state[0], lambda start, cells: o.step(op, start, P.dt, inflow_scale=float(isc[last]),
+                                                 cells=cells),
+        step=lambda a_, b_: S.step(a_, b_, args[last]))
     S.close()
     # the two-product mode over the same energy run: its dose against the three-product dose
     S2 = Solver(P, precision="bf16x2")
@@ -324,6 +373,25 @@ def bench_csd(steps, warmup: int):
     dose_diff = float(torch.linalg.vector_norm(dose2 - dose_ref) /
                       torch.linalg.vector_norm(dose_ref))
     S2.close()
+    # the FP16 three-product mode over the same run
+    S3 = Solver(P, precision="fp16x3")
+    args3 = [S3.args(inflow_scale=float(isc[n])) for n in range(nsteps)]
+    st3 = [S3.initial_state(), torch.empty_like(state[0])]
+    dose3 = torch.zeros(S3.nc, dtype=torch.float64, device="cuda")
+
+    def fused_step3():
+        n = counter[0]
+        snrt.snrt_step_dose(S3.mesh, S3.quad, S3.scatter, args3[n], st3[0], st3[1],
+                            float(coeff[n]), dose3, S3.ws, S3.ws_bytes)
+        st3.reverse()
+        counter[0] = n + 1
+
+    counter[0] = 0
+    torch.cuda.synchronize()
+    ms_x3f16 = timed(fused_step3, nsteps, stream)
+    dose_diff16 = float(torch.linalg.vector_norm(dose3 - dose_ref) /
+                        torch.linalg.vector_norm(dose_ref))
+    S3.close()
     return {"workload": "csd_phantom_s512", "cells": P.ncells, "ordinates": P.nq,
             "scattering": "Henyey-Greenstein g=0.95, dense, column-normalised",
             "precision": "bf16x3 (hi+lo split, FP32 accumulate)", "steps": nsteps,
@@ -334,7 +402,58 @@ def bench_csd(steps, warmup: int):
                     "input fused (snrt_step_dose)",
             "ms_per_step_separate_dose_pass": ms_separate,
             "scatter_product": final, "scatter_product_dense_random_state": dense,
-            "bf16x2": {"ms_per_step": ms_x2, "dose_rel_l2_vs_bf16x3": dose_diff}}
+            "vs_oracle": vs_oracle, "rel_l2_vs_oracle": vs_oracle["rel_l2"],
+            "bf16x2": {"ms_per_step": ms_x2, "dose_rel_l2_vs_bf16x3": dose_diff},
+            "fp16x3": {"ms_per_step": ms_x3f16, "dose_rel_l2_vs_bf16x3": dose_diff16}}
+
+
+def bench_dose_gradient(nsteps: int = 500, ckpt: int = 20):
+    """Gradient of the target-minus-organ dose functional w.r.t. the per-cell density on
+    the full CSD phantom (299 538 cells x 512 ordinates, the first 500 energy steps, BF16 hi+lo
+    products, checkpoints every 20): the differentiable rollout's forward pass (steps with the
+    fused dose) against its backward pass (segment recompute, transposed steps with the
+    transposed product, the dose's adjoint terms), each one library call."""
+    import numpy as np
+    import torch
+    from paper_2205_08417_amd import inputs as I
+    from paper_2205_08417_amd.solver import Solver, differentiable_rollout
+
+    P = I.build("csd_phantom_s512")
+    n = min(nsteps, P.nsteps)
+    S = Solver(P, precision="bf16x3")
+    isc = np.asarray(P.meta["inflow_scale"][:n])
+    coeff = np.asarray(P.meta["dose_coeff"][:n])
+    T = P.meta["target"].astype(float)
+    O = P.meta["organ"].astype(float)
+    wd = S.cells_to_internal(P.mesh.area * (T - O), torch.float64)
+    r = S.cells_to_internal(P.rho).requires_grad_(True)
+    psi0 = S.initial_state()
+    stream = torch.cuda.current_stream()
+
+    def one_pass():
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        _, dose = differentiable_rollout(S, psi0, n, rho=r, ckpt_every=ckpt, inflow_scale=isc,
+                                         dose_coeff=coeff)
+        ev[1].record(stream)
+        J = torch.sum(wd * dose)
+        ev[2].record(stream)
+        J.backward()
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        r.grad = None
+        return ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
+
+    one_pass()
+    fwd, bwd = one_pass()
+    S.close()
+    return {"workload": "csd_phantom_s512", "cells": P.ncells, "ordinates": P.nq, "steps": n,
+            "checkpoint_every": ckpt, "precision": "bf16x3",
+            "functional": "sum_T A D - sum_O A D, gradient w.r.t. per-cell density",
+            "forward_ms": fwd, "backward_ms": bwd, "adjoint_forward_ratio": bwd / fwd,
+            "parity": "the same path on the reduced CSD workload over the whole energy range "
+                      "is checked against the oracle in tests/test_gpu_fullsize.py"}
 
 
 def bench_moments(steps, warmup: int, degree: int = 8):
@@ -377,6 +496,14 @@ def bench_moments(steps, warmup: int, degree: int = 8):
     state[0] = S.initial_state()
     torch.cuda.synchronize()
     ms_imex = timed(one_imex, steps, stream)
+    from oracle import moments as mo
+    from oracle import oracle as o
+    op = o.OracleProblem.from_problem(P, K=mo.moment_kernel(P.omega, P.w, sig))
+    vs_oracle = step_vs_oracle(S, state[0], lambda st_, c: o.step(op, st_, P.dt, cells=c))
+    vs_oracle_imex = step_vs_oracle(S, state[0],
+                                    lambda st_, c: o.step_imex(op, st_, P.dt, cells=c), n=64,
+                                    step=lambda a_, b_: S.step_imex(a_, b_, args),
+                                    what="one IMEX step")
     nm = (degree + 1) ** 2
     mid = ((nm + 127) // 128) * 128                      # the library's BF16 padding
     executed = 3 * 2 * 2.0 * P.ncells * P.nq * mid       # two products, three BF16 passes
@@ -387,7 +514,9 @@ def bench_moments(steps, warmup: int, degree: int = 8):
             "precision": "bf16x3", "steps": steps, "ms_per_step": ms,
             "value": P.ncells * P.nq / (ms * 1e-3), "unit": "cell-ordinate updates/s",
             "moment_dimension_padded": mid, "product_flops_executed": executed,
-            "product_flops_useful": useful, "imex_ms_per_step": ms_imex}
+            "product_flops_useful": useful, "imex_ms_per_step": ms_imex,
+            "vs_oracle": vs_oracle, "rel_l2_vs_oracle": vs_oracle["rel_l2"],
+            "imex_vs_oracle": vs_oracle_imex}
 
 
 def bench_second_order(steps: int, warmup: int):
@@ -422,6 +551,12 @@ def bench_second_order(steps: int, warmup: int):
     ms = run("barth-jespersen")
     ms_vk = run("venkatakrishnan")
     alg = P.ncells * (60 * P.nq + 2 * 2 * (64 + 64))
+    from oracle import oracle as o
+    op = o.OracleProblem.from_problem(P)
+    # the oracle's Heun step is taken over the whole state (it has no cell selection)
+    vs_oracle = step_vs_oracle(S, state[0], lambda st_, c: o.step2(op, st_, P.dt)[c],
+                               step=lambda a_, b_: S.step2(a_, b_, args),
+                               what="one Heun step (Barth-Jespersen)")
     S.close()
     return {"workload": WORKLOAD, "cells": P.ncells, "ordinates": P.nq,
             "scheme": "second order: Green-Gauss + Barth-Jespersen reconstruction, Heun",
@@ -429,7 +564,8 @@ def bench_second_order(steps: int, warmup: int):
             "unit": "cell-ordinate updates/s", "algorithmic_bytes_per_step": alg,
             "achieved_gbs": alg / (ms * 1e-3) / 1e9,
             "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "venkatakrishnan_ms_per_step": ms_vk}
+            "venkatakrishnan_ms_per_step": ms_vk, "vs_oracle": vs_oracle,
+            "rel_l2_vs_oracle": vs_oracle["rel_l2"]}
 
 
 def bench_imex(steps: int, warmup: int):
@@ -455,10 +591,16 @@ def bench_imex(steps: int, warmup: int):
     torch.cuda.synchronize()
     ms = timed(one_step, steps, stream)
     alg = P.ncells * (8 * P.nq + 64)
+    from oracle import oracle as o
+    op = o.OracleProblem.from_problem(P)
+    vs_oracle = step_vs_oracle(S, state[0], lambda st_, c: o.step_imex(op, st_, P.dt, cells=c),
+                               n=128, step=lambda a_, b_: S.step_imex(a_, b_, args),
+                               what="one IMEX step")
     S.close()
     return {"workload": WORKLOAD, "scheme": "IMEX: implicit isotropic collision", "steps": steps,
             "ms_per_step": ms, "value": P.ncells * P.nq / (ms * 1e-3),
-            "unit": "cell-ordinate updates/s", "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            "unit": "cell-ordinate updates/s", "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "vs_oracle": vs_oracle, "rel_l2_vs_oracle": vs_oracle["rel_l2"]}
 
 
 def bench_pn(steps: int, warmup: int, degree: int = 5):
@@ -491,6 +633,19 @@ def bench_pn(steps: int, warmup: int, degree: int = 5):
         one_step()
     torch.cuda.synchronize()
     ms = timed(one_step, steps, stream)
+    from oracle import oracle as o
+    from oracle import pn as opn
+    op = o.OracleProblem(mesh.face_nbr, mesh.face_normal, mesh.area, np.zeros((1, 3)),
+                         np.ones(1), w["sigma_t"], w["sigma_s"], source=w["source"])
+    system = opn.PNSystem(degree)
+    final = state[0]
+    nxt = torch.empty_like(final)
+    S.step(final, nxt, args)
+    cells = sample_cells(mesh.ncells, 256)
+    got = S.to_user(nxt).cpu().numpy()[cells]
+    start = S.to_user(final).cpu().numpy().astype(np.float64)
+    vs_oracle = oracle_error(got, opn.pn_step(op, system, start, w["dt"], cells=cells),
+                             f"one step from the final state, {cells.size} seeded cells")
     S.close()
     nc = mesh.ncells
     alg = nc * (8 * nm + 64 + 12)
@@ -506,7 +661,8 @@ def bench_pn(steps: int, warmup: int, degree: int = 5):
             "algorithmic_bytes_per_step": alg, "achieved_gbs": achieved,
             "hbm_frac": achieved / HBM_PEAK_GBS, "flops_per_step": flops,
             "fp32_vector_tflops": flops / (ms * 1e-3) / 1e12,
-            "fp32_vector_frac": flops / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS}
+            "fp32_vector_frac": flops / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+            "vs_oracle": vs_oracle, "rel_l2_vs_oracle": vs_oracle["rel_l2"]}
 
 
 def bench_adjoint(nsteps: int = 400, ckpt: int = 20):
@@ -644,6 +800,9 @@ def main():
         return x, y
 
     stream = torch.cuda.current_stream()
+    # the timed steps start from the developed state after the workload's 1000 steps (one
+    # library call), not from the empty initial state
+    a, _ = S.rollout(a, P.nsteps)
     a, b = run(args.warmup, a, b)
     torch.cuda.synchronize()
     K = args.steps
@@ -679,7 +838,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": WORKLOAD, "cells": P.ncells, "ordinates": P.nq,
                    "scattering": "isotropic", "precision": "fp32", "mesh": "seeded jittered "
-                   "Delaunay 316x316 points on [0,7]^2", "graph": bool(args.graph)},
+                   "Delaunay 316x316 points on [0,7]^2", "graph": bool(args.graph),
+                   "timed_from": f"the state after {P.nsteps} steps from the initial state "
+                                 f"plus {args.warmup} warm-up steps"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_step<4,true,3,false,false,float,false>",
@@ -694,10 +855,14 @@ def main():
         out["adjoint"] = bench_adjoint()
     if not args.no_dense:
         out["mixed_precision"] = bench_dense(args.dense_steps, 5)
+        print("# mixed precision done", file=sys.stderr, flush=True)
         out["mixed_precision"]["hipblaslt_bf16_single_product_tflops_random"] = \
             library_gemm_ceiling(out["mixed_precision"]["cells"],
                                  out["mixed_precision"]["ordinates"])
         out["csd_dose"] = bench_csd(args.dense_steps, 5)
+        print("# csd dose done", file=sys.stderr, flush=True)
+        out["csd_dose_gradient"] = bench_dose_gradient()
+        print("# csd dose gradient done", file=sys.stderr, flush=True)
         out["moments"] = bench_moments(args.dense_steps, 5)
     if not args.no_second_order:
         out["second_order"] = bench_second_order(min(args.steps, 200), 5)
