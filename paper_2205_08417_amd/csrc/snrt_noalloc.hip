@@ -35,8 +35,16 @@ snrt_status scratch_address(int dev, double** out) {
     }
     std::lock_guard<std::mutex> lock(g_scratch_mu);
     if (!g_scratch_ptr[dev]) {
+        // each device holds its own copy of the array: look it up with that device current
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
         void* p = nullptr;
-        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur >= 0 && cur != dev) {
+            hipError_t r = hipSetDevice(cur);
+            if (e == hipSuccess) e = r;
+        }
         if (e != hipSuccess || !p)
             return snrt::hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
                                   "snrt_step_dose_noalloc: scratch address");
