@@ -143,6 +143,21 @@ snrt_status snrt_scatter_moments(snrt_scatter** out, const snrt_quad* quad, int3
                                  const double* sigma_l, snrt_precision precision);
 void snrt_scatter_destroy(snrt_scatter* scatter);
 
+/* Implicit form of a dense kernel, for the IMEX step with dense scattering (Sec. 4.2 with
+ * the scattering operator of eq. SNEqns; snrt_step_imex_dense).  Set-up call on a handle
+ * from snrt_scatter_dense: decomposes A = K W (A[q][p] = K[q][p] w_p) once, in FP64 on the
+ * host, as A = V diag(lam) V^-1 and stores V^-1, V diag(lam) and lam on the device in the
+ * handle's precision.  The decomposition goes through the symmetric matrix
+ * R^{1/2} A R^{-1/2} for a positive diagonal R with R A symmetric, which exists when K is a
+ * symmetric kernel times a positive diagonal (a symmetric kernel with normalised columns,
+ * e.g. Henyey-Greenstein; the isotropic kernel as a dense matrix); other kernels return
+ * SNRT_E_UNSUPPORTED, as does a decomposition whose residual |A y - V lam V^-1 y| exceeds
+ * 1e-10 |A| |y| on seeded probes.  Cost O(nq^3) on one host thread (about a second at
+ * nq = 1024), device memory 2 more nq x nq operands.  Idempotent; afterwards
+ * snrt_workspace_size includes the implicit solve's workspace.  SNRT_E_UNSUPPORTED for
+ * isotropic and moment-form handles. */
+snrt_status snrt_scatter_prepare_implicit(snrt_scatter* scatter);
+
 /* Bytes of device workspace that serve every step entry point for this combination:
  * snrt_step / snrt_step_adjoint (FP32 and FP64) need one [ncells][nq] buffer for a dense
  * kernel, plus [ncells][moments, padded] for the moment form, and none for isotropic
@@ -267,7 +282,8 @@ snrt_status snrt_scatter_apply(const snrt_mesh* mesh, const snrt_quad* quad,
 /* IMEX step (Sec. 4.2): the linear collision operator R psi = -alpha_t sigma_t psi +
  * alpha_s sigma_s S(psi) is taken implicitly, streaming and the source explicitly:
  *     (I - dt R_i) psi_out_i = psi_in_i - dt/A_i sum_f F_up(psi_in) + dt q_i.
- * Isotropic scattering only (SNRT_E_UNSUPPORTED for dense or moment handles): the per-cell
+ * Isotropic scattering only (SNRT_E_UNSUPPORTED for dense or moment handles; they have
+ * snrt_step_imex_dense and snrt_step_imex_moments): the per-cell
  * system has the closed-form solution
  *     psi'_q = (b_q + c B / (a - c W)) / a,  a = 1 + dt alpha_t sigma_t, c = dt alpha_s sigma_s,
  *     B = sum_q w_q b_q / (4 pi),  W = sum_q w_q / (4 pi),
@@ -302,6 +318,28 @@ snrt_status snrt_step_imex_moments_f64(const snrt_mesh* mesh, const snrt_quad* q
                                        const snrt_step_args_f64* args, const double* psi_in,
                                        double* psi_out, void* workspace, size_t workspace_bytes,
                                        void* stream);
+
+/* IMEX step as above with a dense scattering kernel (handle from snrt_scatter_dense, after
+ * snrt_scatter_prepare_implicit; SNRT_E_UNSUPPORTED without it).  Per cell, with
+ * a = 1 + dt alpha_t sigma_t and b = dt alpha_s sigma_s, the system (a I - b K W) psi' = r
+ * has the solution
+ *     psi' = (r + V D V^-1 r) / a,   D = diag(b lam_j / (a - b lam_j)),
+ * with K W = V diag(lam) V^-1 from the set-up call: the collision-free explicit step r
+ * (written to psi_out), the products with V^-1 and V diag(lam) with the per-cell diagonal
+ * between them, and (r + S) / a in place.  Requires a - b lam_j != 0 (true for sigma_s <=
+ * sigma_t and alpha_s <= alpha_t when the kernel conserves particles, |lam_j| <= 1).
+ * Workspace: snrt_workspace_size of the prepared handle (2 nq values per cell, plus one
+ * int32 per cell in the FP16 mode), 16-byte aligned, disjoint from the states; the products
+ * run in the handle's precision. */
+snrt_status snrt_step_imex_dense(const snrt_mesh* mesh, const snrt_quad* quad,
+                                 const snrt_scatter* scatter, const snrt_step_args* args,
+                                 const float* psi_in, float* psi_out, void* workspace,
+                                 size_t workspace_bytes, void* stream);
+snrt_status snrt_step_imex_dense_f64(const snrt_mesh* mesh, const snrt_quad* quad,
+                                     const snrt_scatter* scatter,
+                                     const snrt_step_args_f64* args, const double* psi_in,
+                                     double* psi_out, void* workspace, size_t workspace_bytes,
+                                     void* stream);
 
 /* ---------------------------------------------------------------- rollouts */
 

@@ -401,7 +401,7 @@ snrt_status snrt_quad_create(snrt_quad** out, int32_t nq, const double* omega, c
 
 void snrt_scatter_destroy(snrt_scatter* sc) {
     if (!sc) return;
-    for (GemmOperand* ops : {sc->B.fwd, sc->B.adj})
+    for (GemmOperand* ops : {sc->B.fwd, sc->B.adj, sc->B.imp})
         for (int i = 0; i < 2; ++i) {
             dev_free(ops[i].f32);
             dev_free(ops[i].f64);
@@ -411,6 +411,8 @@ void snrt_scatter_destroy(snrt_scatter* sc) {
         }
     dev_free(sc->B.msig32);
     dev_free(sc->B.msig64);
+    dev_free(sc->B.lam32);
+    dev_free(sc->B.lam64);
     delete sc;
 }
 
@@ -616,6 +618,54 @@ snrt_status snrt_scatter_moments(snrt_scatter** out, const snrt_quad* q, int32_t
     return SNRT_OK;
 }
 
+snrt_status snrt_scatter_prepare_implicit(snrt_scatter* sc) {
+    g_last_error.clear();
+    const char* fn = "snrt_scatter_prepare_implicit";
+    SNRT_REQUIRE(sc, SNRT_E_ARG, std::string(fn) + ": NULL scatter handle");
+    SNRT_REQUIRE(sc->dense && sc->B.chain == 1, SNRT_E_UNSUPPORTED,
+                 std::string(fn) + ": needs a dense scatter handle (snrt_scatter_dense); "
+                 "isotropic and moment-form handles have their own implicit solves");
+    DenseB& B = sc->B;
+    if (B.implicit) return SNRT_OK;
+    SNRT_TRY(check_device(sc->device, fn));
+    const int32_t n = B.nq;
+    const size_t n2 = (size_t)n * n;
+    // the forward operand holds X[p][q] = w_p K[q][p] = A[q][p]
+    std::vector<double> X(n2), A(n2);
+    hipError_t e = hipMemcpy(X.data(), B.fwd[0].f64, n2 * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, fn);
+    for (int32_t p = 0; p < n; ++p)
+        for (int32_t q = 0; q < n; ++q) A[(size_t)q * n + p] = X[(size_t)p * n + q];
+    std::vector<double> lam, x0, x1;
+    double resid = 0.0;
+    SNRT_TRY(implicit_form(n, A, lam, x0, x1, &resid));
+    std::vector<float> lam32(lam.begin(), lam.end());
+    snrt_status s = SNRT_OK;
+    if ((s = dev_alloc(&B.lam32, (size_t)n, "implicit eigenvalues")) != SNRT_OK ||
+        (s = dev_alloc(&B.lam64, (size_t)n, "implicit eigenvalues")) != SNRT_OK ||
+        (s = upload(B.lam32, lam32.data(), (size_t)n, fn)) != SNRT_OK ||
+        (s = upload(B.lam64, lam.data(), (size_t)n, fn)) != SNRT_OK ||
+        (s = make_operand(B.imp[0], x0, n, n, B.precision, fn)) != SNRT_OK ||
+        (s = make_operand(B.imp[1], x1, n, n, B.precision, fn)) != SNRT_OK) {
+        for (GemmOperand& op : B.imp) {
+            dev_free(op.f32);
+            dev_free(op.f64);
+            dev_free(op.hi);
+            dev_free(op.lo);
+            dev_free(op.t32);
+            op = GemmOperand();
+        }
+        dev_free(B.lam32);
+        dev_free(B.lam64);
+        B.lam32 = nullptr;
+        B.lam64 = nullptr;
+        return s;
+    }
+    B.imp_resid = resid;
+    B.implicit = true;
+    return SNRT_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -627,6 +677,13 @@ size_t product_ws_elems(const snrt_scatter* sc, int64_t nc) {
     if (!sc->dense) return 0;
     return (size_t)nc * (size_t)(sc->B.nq + (sc->B.chain == 2 ? sc->B.mid : 0) +
                                  (sc->B.precision == SNRT_FP16X3 ? 1 : 0));
+}
+
+// The IMEX step with a dense kernel's implicit form: the right-hand side's modes U [nc][nq]
+// after S [nc][nq], then the FP16 row exponents.
+size_t implicit_ws_elems(const snrt_scatter* sc, int64_t nc) {
+    if (!sc->dense || !sc->B.implicit) return 0;
+    return (size_t)nc * (size_t)(2 * sc->B.nq + (sc->B.precision == SNRT_FP16X3 ? 1 : 0));
 }
 
 // snrt_step_dose: the FP32 product workspace, then (16-byte aligned) one FP64 partial sum
@@ -648,7 +705,8 @@ snrt_status snrt_workspace_size(const snrt_mesh* m, const snrt_quad* q, const sn
     g_last_error.clear();
     SNRT_REQUIRE(m && q && sc && bytes, SNRT_E_ARG, "snrt_workspace_size: NULL argument");
     SNRT_REQUIRE(sc->B.nq == q->nq, SNRT_E_SHAPE, "snrt_workspace_size: scatter/quad nq differ");
-    *bytes = std::max(product_ws_elems(sc, m->nc) * sizeof(double), dose_ws_bytes(m, q, sc));
+    *bytes = std::max({product_ws_elems(sc, m->nc) * sizeof(double), dose_ws_bytes(m, q, sc),
+                       implicit_ws_elems(sc, m->nc) * sizeof(double)});
     return SNRT_OK;
 }
 
@@ -1058,7 +1116,8 @@ snrt_status snrt_step_imex(const snrt_mesh* m, const snrt_quad* q, const snrt_sc
     g_last_error.clear();
     SNRT_REQUIRE(sc, SNRT_E_ARG, "snrt_step_imex: NULL scatter handle");
     SNRT_REQUIRE(!sc->dense, SNRT_E_UNSUPPORTED,
-                 "snrt_step_imex: only isotropic scattering has the closed-form implicit solve");
+                 "snrt_step_imex: only isotropic scattering has the closed-form implicit solve "
+                 "(dense kernels: snrt_step_imex_dense; moment form: snrt_step_imex_moments)");
     SNRT_TRY(check_step_common("snrt_step_imex", m, q, sc, a, sizeof(float), psi_in, psi_out,
                                nullptr, 0));
     if (m->nc == 0) return SNRT_OK;
@@ -1072,7 +1131,9 @@ snrt_status snrt_step_imex_f64(const snrt_mesh* m, const snrt_quad* q, const snr
     g_last_error.clear();
     SNRT_REQUIRE(sc, SNRT_E_ARG, "snrt_step_imex_f64: NULL scatter handle");
     SNRT_REQUIRE(!sc->dense, SNRT_E_UNSUPPORTED,
-                 "snrt_step_imex_f64: only isotropic scattering has the closed-form implicit solve");
+                 "snrt_step_imex_f64: only isotropic scattering has the closed-form implicit "
+                 "solve (dense kernels: snrt_step_imex_dense_f64; moment form: "
+                 "snrt_step_imex_moments_f64)");
     SNRT_TRY(check_step_common("snrt_step_imex_f64", m, q, sc, a, sizeof(double), psi_in,
                                psi_out, nullptr, 0));
     if (m->nc == 0) return SNRT_OK;
@@ -1087,8 +1148,44 @@ namespace {
 // Largest |M O - I| for which the moment-form IMEX inverse is taken as exact.
 constexpr double kMomentGramTol = 1e-10;
 
-// IMEX with moment-projected scattering: r = the collision-free explicit step (into psi_out),
-// U = M r, U *= b / (a - b Sigma), S = (Sigma O) U, psi_out = (r + S) / a.
+// The IMEX solve in mode space, shared by the moment form and a dense kernel's implicit
+// form: r = the collision-free explicit step (into psi_out), U = r X0, U_j *= b / (a - b
+// sig_j), S = U X1, psi_out = (r + S) / a.  S [nc][nq] and U [nc][mid] in the workspace,
+// rexp [nc] the FP16 row exponents (FP32 state only).
+template <typename T, typename ArgsT>
+hipError_t imex_modes(const snrt_mesh* m, const snrt_quad* q, const DenseB& B,
+                      const GemmOperand* ops, const float* sig32, const double* sig64,
+                      int32_t mid, const ArgsT* a, const T* psi_in, T* psi_out, T* S, T* U,
+                      int32_t* rexp, hipStream_t st) {
+    hipError_t e;
+    if constexpr (sizeof(T) == 4) {
+        const StepArgs32 a32 = to32(a);
+        StepArgs32 free_flight = a32;
+        free_flight.alpha_t = 0.0f;
+        free_flight.alpha_s = 0.0f;
+        e = launch_free_step32(*m, *q, free_flight, psi_in, psi_out, st);
+        if (e == hipSuccess) e = product32(B, ops[0], psi_out, U, m->nc, rexp, st);
+        if (e == hipSuccess) e = launch_imex_moment_scale32(a32, U, sig32, m->nc, mid, st);
+        if (e == hipSuccess) e = product32(B, ops[1], U, S, m->nc, rexp, st);
+        if (e == hipSuccess) e = launch_imex_combine32(a32, psi_out, S, m->nc, q->nq, st);
+    } else {
+        const StepArgs64 a64 = to64(a);
+        StepArgs64 free_flight = a64;
+        free_flight.alpha_t = 0.0;
+        free_flight.alpha_s = 0.0;
+        e = launch_free_step64(*m, *q, free_flight, psi_in, psi_out, st);
+        if (e == hipSuccess)
+            e = launch_gemm64(psi_out, ops[0].f64, U, m->nc, ops[0].K, ops[0].N, st);
+        if (e == hipSuccess) e = launch_imex_moment_scale64(a64, U, sig64, m->nc, mid, st);
+        if (e == hipSuccess)
+            e = launch_gemm64(U, ops[1].f64, S, m->nc, ops[1].K, ops[1].N, st);
+        if (e == hipSuccess) e = launch_imex_combine64(a64, psi_out, S, m->nc, q->nq, st);
+    }
+    return e;
+}
+
+// IMEX with moment-projected scattering: with M O = I the per-cell inverse of a I - b O Sigma M
+// is (1/a) [I + O diag(b Sigma / (a - b Sigma)) M].
 template <typename T, typename ArgsT>
 snrt_status imex_moments_common(const char* fn, const snrt_mesh* m, const snrt_quad* q,
                                 const snrt_scatter* sc, const ArgsT* a, const T* psi_in,
@@ -1101,35 +1198,45 @@ snrt_status imex_moments_common(const char* fn, const snrt_mesh* m, const snrt_q
                                    "exactly (M O != I), so the closed-form inverse does not hold");
     SNRT_TRY(check_step_common(fn, m, q, sc, a, sizeof(T), psi_in, psi_out, ws, ws_bytes));
     if (m->nc == 0) return SNRT_OK;
-    hipStream_t st = static_cast<hipStream_t>(stream);
     const DenseB& B = sc->B;
     T* S = static_cast<T*>(ws);
     T* U = S + (size_t)m->nc * q->nq;
-    hipError_t e;
-    if constexpr (sizeof(T) == 4) {
-        const StepArgs32 a32 = to32(a);
-        StepArgs32 free_flight = a32;
-        free_flight.alpha_t = 0.0f;
-        free_flight.alpha_s = 0.0f;
-        e = launch_free_step32(*m, *q, free_flight, psi_in, psi_out, st);
-        int32_t* rexp = ws_rexp(B, U, m->nc);
-        if (e == hipSuccess) e = product32(B, B.fwd[0], psi_out, U, m->nc, rexp, st);
-        if (e == hipSuccess) e = launch_imex_moment_scale32(a32, U, B.msig32, m->nc, B.mid, st);
-        if (e == hipSuccess) e = product32(B, B.fwd[1], U, S, m->nc, rexp, st);
-        if (e == hipSuccess) e = launch_imex_combine32(a32, psi_out, S, m->nc, q->nq, st);
-    } else {
-        const StepArgs64 a64 = to64(a);
-        StepArgs64 free_flight = a64;
-        free_flight.alpha_t = 0.0;
-        free_flight.alpha_s = 0.0;
-        e = launch_free_step64(*m, *q, free_flight, psi_in, psi_out, st);
-        if (e == hipSuccess)
-            e = launch_gemm64(psi_out, B.fwd[0].f64, U, m->nc, B.fwd[0].K, B.fwd[0].N, st);
-        if (e == hipSuccess) e = launch_imex_moment_scale64(a64, U, B.msig64, m->nc, B.mid, st);
-        if (e == hipSuccess)
-            e = launch_gemm64(U, B.fwd[1].f64, S, m->nc, B.fwd[1].K, B.fwd[1].N, st);
-        if (e == hipSuccess) e = launch_imex_combine64(a64, psi_out, S, m->nc, q->nq, st);
-    }
+    int32_t* rexp = nullptr;
+    if constexpr (sizeof(T) == 4) rexp = ws_rexp(B, U, m->nc);
+    hipError_t e = imex_modes<T>(m, q, B, B.fwd, B.msig32, B.msig64, B.mid, a, psi_in, psi_out,
+                                 S, U, rexp, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SNRT_OK : hip_fail(e, (std::string(fn) + ": launch").c_str());
+}
+
+// IMEX with a dense kernel (implicit form from snrt_scatter_prepare_implicit): K W =
+// V diag(lam) V^-1, so the per-cell inverse is (1/a) [I + V diag(b lam / (a - b lam)) V^-1].
+template <typename T, typename ArgsT>
+snrt_status imex_dense_common(const char* fn, const snrt_mesh* m, const snrt_quad* q,
+                              const snrt_scatter* sc, const ArgsT* a, const T* psi_in,
+                              T* psi_out, void* ws, size_t ws_bytes, void* stream) {
+    SNRT_REQUIRE(sc, SNRT_E_ARG, std::string(fn) + ": NULL scatter handle");
+    SNRT_REQUIRE(sc->dense && sc->B.chain == 1, SNRT_E_UNSUPPORTED,
+                 std::string(fn) + ": needs a dense scatter handle (snrt_scatter_dense)");
+    SNRT_REQUIRE(sc->B.implicit, SNRT_E_UNSUPPORTED,
+                 std::string(fn) + ": the handle has no implicit form "
+                                   "(call snrt_scatter_prepare_implicit first)");
+    SNRT_TRY(check_step_common(fn, m, q, sc, a, sizeof(T), psi_in, psi_out, ws, ws_bytes));
+    if (m->nc == 0) return SNRT_OK;
+    const size_t need = implicit_ws_elems(sc, m->nc) * sizeof(T);
+    const size_t bytes = (size_t)m->nc * q->nq * sizeof(T);
+    SNRT_REQUIRE(ws_bytes >= need, SNRT_E_ARG,
+                 std::string(fn) + ": the implicit solve needs a workspace of " +
+                     std::to_string(need) + " bytes (snrt_workspace_size after "
+                     "snrt_scatter_prepare_implicit)");
+    SNRT_REQUIRE(!ranges_overlap(ws, need, psi_in, bytes) && !ranges_overlap(ws, need, psi_out, bytes),
+                 SNRT_E_ALIAS, std::string(fn) + ": workspace aliases a state array");
+    const DenseB& B = sc->B;
+    T* S = static_cast<T*>(ws);
+    T* U = S + (size_t)m->nc * q->nq;
+    int32_t* rexp = reinterpret_cast<int32_t*>(U + (size_t)m->nc * q->nq);
+    hipError_t e = imex_modes<T>(m, q, B, B.imp, B.lam32, B.lam64, B.nq, a, psi_in, psi_out, S,
+                                 U, sizeof(T) == 4 ? rexp : nullptr,
+                                 static_cast<hipStream_t>(stream));
     return e == hipSuccess ? SNRT_OK : hip_fail(e, (std::string(fn) + ": launch").c_str());
 }
 
@@ -1153,6 +1260,23 @@ snrt_status snrt_step_imex_moments_f64(const snrt_mesh* m, const snrt_quad* q,
     g_last_error.clear();
     return imex_moments_common<double>("snrt_step_imex_moments_f64", m, q, sc, a, psi_in,
                                        psi_out, ws, ws_bytes, stream);
+}
+
+snrt_status snrt_step_imex_dense(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
+                                 const snrt_step_args* a, const float* psi_in, float* psi_out,
+                                 void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    return imex_dense_common<float>("snrt_step_imex_dense", m, q, sc, a, psi_in, psi_out, ws,
+                                    ws_bytes, stream);
+}
+
+snrt_status snrt_step_imex_dense_f64(const snrt_mesh* m, const snrt_quad* q,
+                                     const snrt_scatter* sc, const snrt_step_args_f64* a,
+                                     const double* psi_in, double* psi_out, void* ws,
+                                     size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    return imex_dense_common<double>("snrt_step_imex_dense_f64", m, q, sc, a, psi_in, psi_out,
+                                     ws, ws_bytes, stream);
 }
 
 snrt_status snrt_scatter_apply(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,

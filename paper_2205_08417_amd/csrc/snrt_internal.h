@@ -87,7 +87,22 @@ struct DenseB {
     double* msig64 = nullptr;
     double mo_err = 0.0;
     GemmOperand fwd[2], adj[2];
+    // implicit form of a dense kernel (chain 1; snrt_scatter_prepare_implicit): K W =
+    // V diag(lam) V^-1 as the operands imp[0] = V^-1 as [nq][nq] (x0[q][j] = V^-1[j][q]) and
+    // imp[1] = (V diag(lam))^T (x1[j][q] = lam_j V[q][j]), with lam on the device
+    bool implicit = false;
+    GemmOperand imp[2];
+    float* lam32 = nullptr;
+    double* lam64 = nullptr;
+    double imp_resid = 0.0;
 };
+
+// The eigendecomposition behind the implicit form (host, FP64): A [n][n] row-major with
+// A[q][p] = K[q][p] w_p; fills lam [n] and the two product operands x0, x1 [n][n].  Returns
+// SNRT_E_UNSUPPORTED (with the reason set) when A is not diagonally similar to a symmetric
+// matrix or the decomposition fails its residual check.
+snrt_status implicit_form(int n, const std::vector<double>& A, std::vector<double>& lam,
+                          std::vector<double>& x0, std::vector<double>& x1, double* resid);
 
 }  // namespace snrt
 

@@ -54,7 +54,8 @@ EXPORTS = [
     "snrt_pn_state_elems", "snrt_pn_layout", "snrt_pn_step", "snrt_pn_step_f64",
     "snrt_stream_copy", "snrt_step_imex_moments", "snrt_step_imex_moments_f64",
     "snrt_rollout", "snrt_rollout_f64", "snrt_rollout_adjoint", "snrt_rollout_adjoint_f64",
-    "snrt_step_dose_noalloc",
+    "snrt_step_dose_noalloc", "snrt_scatter_prepare_implicit", "snrt_step_imex_dense",
+    "snrt_step_imex_dense_f64",
 ]
 
 
@@ -166,6 +167,11 @@ def lib() -> ctypes.CDLL:
                                              _vp, ctypes.c_size_t, _vp]),
         "snrt_scatter_moments": (_st, [ctypes.POINTER(_vp), _vp, ctypes.c_int32, _dp,
                                        ctypes.c_int]),
+        "snrt_scatter_prepare_implicit": (_st, [_vp]),
+        "snrt_step_imex_dense": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp,
+                                       _vp, ctypes.c_size_t, _vp]),
+        "snrt_step_imex_dense_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp,
+                                           _vp, ctypes.c_size_t, _vp]),
         "snrt_step2_workspace_size": (_st, [_vp, _vp, _vp, ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_size_t)]),
         "snrt_step2": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp, _vp,
@@ -363,6 +369,25 @@ def snrt_step_imex_moments_f64(mesh, quad, scatter, args: StepArgs, psi_in, psi_
            lib().snrt_step_imex_moments_f64(mesh, quad, scatter, ctypes.byref(args),
                                             _ptr(psi_in), _ptr(psi_out), _ptr(ws),
                                             int(ws_bytes), _stream(stream)))
+
+
+def snrt_scatter_prepare_implicit(scatter: int) -> None:
+    _check("snrt_scatter_prepare_implicit", lib().snrt_scatter_prepare_implicit(scatter))
+
+
+def snrt_step_imex_dense(mesh, quad, scatter, args: StepArgs, psi_in, psi_out, ws,
+                         ws_bytes: int, stream=None) -> None:
+    _check("snrt_step_imex_dense",
+           lib().snrt_step_imex_dense(mesh, quad, scatter, ctypes.byref(args), _ptr(psi_in),
+                                      _ptr(psi_out), _ptr(ws), int(ws_bytes), _stream(stream)))
+
+
+def snrt_step_imex_dense_f64(mesh, quad, scatter, args: StepArgs, psi_in, psi_out, ws,
+                             ws_bytes: int, stream=None) -> None:
+    _check("snrt_step_imex_dense_f64",
+           lib().snrt_step_imex_dense_f64(mesh, quad, scatter, ctypes.byref(args), _ptr(psi_in),
+                                          _ptr(psi_out), _ptr(ws), int(ws_bytes),
+                                          _stream(stream)))
 
 
 def snrt_step2_workspace_size(mesh: int, quad: int, scatter: int, fp64: bool = False) -> int:

@@ -124,26 +124,48 @@ class Solver:
             self.ws2[fp64] = (torch.empty(max(n, 16), dtype=torch.uint8, device=self.device), n)
         return self.ws2[fp64]
 
-    def step_imex(self, psi_in, psi_out, args=None, **kw):
-        """One IMEX step: implicit collision (isotropic, or moment-projected scattering),
-        explicit streaming and source."""
-        args = args or self.args(**kw)
+    @property
+    def is_dense(self) -> bool:
+        return self.P.K is not None and not self.is_moments
+
+    def prepare_implicit(self):
+        """Set up the dense kernel's implicit form (snrt_scatter_prepare_implicit, once) and
+        grow the workspace to what the dense IMEX step needs."""
+        if getattr(self, "_implicit_ready", False):
+            return
+        with torch.cuda.device(self.device):
+            snrt.snrt_scatter_prepare_implicit(self.scatter)
+            n = snrt.snrt_workspace_size(self.mesh, self.quad, self.scatter)
+        if n > self.ws_bytes:
+            self.ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+            self.ws_bytes = n
+        self._implicit_ready = True
+
+    def _imex_fn(self, fp64: bool):
+        """The IMEX entry point for this scattering form, as fn(mesh, quad, scatter, args,
+        psi_in, psi_out, ws, ws_bytes, stream)."""
         if self.is_moments:
-            snrt.snrt_step_imex_moments(self.mesh, self.quad, self.scatter, args, psi_in,
-                                        psi_out, self.ws, self.ws_bytes)
-        else:
-            snrt.snrt_step_imex(self.mesh, self.quad, self.scatter, args, psi_in, psi_out)
+            return snrt.snrt_step_imex_moments_f64 if fp64 else snrt.snrt_step_imex_moments
+        if self.is_dense:
+            self.prepare_implicit()
+            return snrt.snrt_step_imex_dense_f64 if fp64 else snrt.snrt_step_imex_dense
+        fn = snrt.snrt_step_imex_f64 if fp64 else snrt.snrt_step_imex
+        return lambda m, q, sc, args, a, b, ws_, n_, st=None: fn(m, q, sc, args, a, b, st)
+
+    def step_imex(self, psi_in, psi_out, args=None, **kw):
+        """One IMEX step: implicit collision (isotropic, dense or moment-projected
+        scattering), explicit streaming and source."""
+        args = args or self.args(**kw)
+        fn = self._imex_fn(False)
+        fn(self.mesh, self.quad, self.scatter, args, psi_in, psi_out, self.ws, self.ws_bytes)
 
     def step_imex_f64(self, psi_in, psi_out, args=None, **kw):
         if self.mats64 is None:
             self.mats64 = self._materials(torch.float64)
         kw["fp64"] = True
         args = args or self.args(**kw)
-        if self.is_moments:
-            snrt.snrt_step_imex_moments_f64(self.mesh, self.quad, self.scatter, args, psi_in,
-                                            psi_out, self.ws, self.ws_bytes)
-        else:
-            snrt.snrt_step_imex_f64(self.mesh, self.quad, self.scatter, args, psi_in, psi_out)
+        fn = self._imex_fn(True)
+        fn(self.mesh, self.quad, self.scatter, args, psi_in, psi_out, self.ws, self.ws_bytes)
 
     def step2(self, psi_in, psi_out, args=None, limiter="barth-jespersen", vk_k=1.0, **kw):
         """One Heun step of the second-order scheme (limited linear reconstruction);
@@ -194,14 +216,10 @@ class Solver:
             dose = torch.zeros(self.nc, dtype=torch.float64, device=self.device)
         if fp64 and self.mats64 is None:
             self.mats64 = self._materials(torch.float64)
-        if imex and self.is_moments:
-            step = snrt.snrt_step_imex_moments_f64 if fp64 else snrt.snrt_step_imex_moments
-            ws = self.ws.data_ptr()
+        if imex:
+            step = self._imex_fn(fp64)
+            ws = self.ws.data_ptr() if self.ws is not None else None
             ws_bytes = self.ws_bytes
-        elif imex:
-            fn = snrt.snrt_step_imex_f64 if fp64 else snrt.snrt_step_imex
-            step = lambda m, q, sc, args, a, b, ws_, n_, st: fn(m, q, sc, args, a, b, st)  # noqa
-            ws, ws_bytes = None, 0
         elif order == 2:
             fn2 = snrt.snrt_step2_limited_f64 if fp64 else snrt.snrt_step2_limited
             lim = snrt.limiter(limiter, vk_k)

@@ -1,6 +1,8 @@
-"""GPU parity of the IMEX step (implicit isotropic collision) against the oracle's
-``step_imex``, which solves each cell's linear system with LU (the kernel uses the closed
-form).  Tolerances: FP64 template 1e-12, FP32 1e-5.
+"""GPU parity of the IMEX step (implicit collision) against the oracle's ``step_imex``, which
+solves each cell's linear system with LU: isotropic scattering (closed form in the kernel),
+dense kernels (one eigendecomposition of K W shared by all cells, two products per step)
+and the moment form.  Tolerances: FP64 template 1e-12, FP32 1e-5, BF16/FP16 hi+lo 1e-4,
+BF16 two products 1e-3.
 """
 import dataclasses
 
@@ -89,6 +91,8 @@ def test_imex_full_size_checkerboard():
 
 
 def test_imex_rejects_dense_scattering():
+    """The isotropic entry point refuses a dense handle; the dense one needs the implicit
+    form first."""
     from paper_2205_08417_amd import snrt
     omega, w = I.product_quadrature(4, 8)
     K = I.henyey_greenstein_kernel(omega, w, 0.5)
@@ -96,9 +100,156 @@ def test_imex_rejects_dense_scattering():
                       seed=54)
     S = _solver(P)
     a = S.initial_state()
+    b = torch.empty_like(a)
     with pytest.raises(snrt.SnrtError) as ei:
-        S.step_imex(a, torch.empty_like(a))
+        snrt.snrt_step_imex(S.mesh, S.quad, S.scatter, S.args(), a, b)
     assert ei.value.status == snrt.SNRT_E_UNSUPPORTED
+    with pytest.raises(snrt.SnrtError) as ei:
+        snrt.snrt_step_imex_dense(S.mesh, S.quad, S.scatter, S.args(), a, b, S.ws, S.ws_bytes)
+    assert ei.value.status == snrt.SNRT_E_UNSUPPORTED
+    S.close()
+
+
+# ---------------------------------------------------------------- dense-kernel IMEX
+
+def _dense_problem(npol, naz, g, seed, stiff=1.0, mesh=None, **kw):
+    omega, w = I.product_quadrature(npol, naz)
+    mesh = mesh if mesh is not None else I.jittered_delaunay_mesh(12, 0.0, 1.0, seed=seed)
+    P = small_problem(mesh, omega_w=(omega, w), seed=seed, scatter=(0.5, 1.0),
+                      K=I.henyey_greenstein_kernel(omega, w, g), **kw)
+    sig_t = P.sigma_t * stiff
+    return dataclasses.replace(P, sigma_t=sig_t, sigma_s=0.9 * sig_t)
+
+
+@pytest.mark.parametrize("npol,naz,g,precision,stiff,tol", [
+    (4, 8, 0.5, "fp32", 1.0, 1e-5), (4, 8, 0.5, "fp32", 300.0, 1e-5),
+    (8, 8, 0.9, "fp32", 30.0, 1e-5), (8, 8, 0.9, "bf16x3", 1.0, 1e-4),
+    (8, 8, 0.9, "bf16x3", 300.0, 1e-4), (8, 12, 0.8, "fp16x3", 300.0, 1e-4),
+    (8, 12, 0.8, "bf16x2", 30.0, 1e-3)])
+def test_imex_dense_rollout(npol, naz, g, precision, stiff, tol):
+    """10 IMEX steps with a dense HG kernel (densities, source, inflow) against the oracle's
+    per-cell LU solves; stiff = 300 puts dt sigma far past the explicit collision limit.
+    The FP64 template runs beside the FP32-state path of the fp32 cases."""
+    P = _dense_problem(npol, naz, g, 61, stiff, rho=True, source=True, inflow=True)
+    ref = _oracle_imex(P, 10)
+    runs = [(False, tol)] + ([(True, 1e-12)] if precision == "fp32" else [])
+    for fp64, t in runs:
+        S = _solver(P, precision=precision, fp64=fp64)
+        psi, _ = S.rollout(S.initial_state(torch.float64 if fp64 else torch.float32), 10,
+                           fp64=fp64, imex=True)
+        out = S.to_user(psi).cpu().numpy()
+        err = rel_l2(out, ref)
+        emax = float(np.max(np.abs(out - ref)) / np.max(np.abs(ref)))
+        print(f"imex dense {npol}x{naz} g={g} {precision} stiff={stiff} fp64={fp64}: "
+              f"{err:.2e} (max {emax:.2e})")
+        assert err <= t and emax <= 10 * t
+        S.close()
+
+
+def test_imex_dense_step_arguments_and_neumann():
+    """Per-step scalars and Neumann faces, one step, FP64 template and FP32."""
+    from oracle import oracle as o
+    from paper_2205_08417_amd import snrt
+    for boundary, neumann in ((snrt.SNRT_BC_DIRICHLET, False), (snrt.SNRT_BC_NEUMANN, True)):
+        P = _dense_problem(8, 8, 0.7, 62, 40.0, rho=True, source=True, inflow=True,
+                           mesh=I.quad_grid_mesh(9, 7))
+        op = o.OracleProblem.from_problem(P, neumann=neumann)
+        ref = o.step_imex(op, P.psi0, P.dt, alpha_t=1.3, alpha_s=0.6, inflow_scale=0.7)
+        S = _solver(P, precision="fp32", fp64=True)
+        for fp64, tol in ((True, 1e-12), (False, 1e-5)):
+            a = S.initial_state(torch.float64 if fp64 else torch.float32)
+            b = torch.empty_like(a)
+            (S.step_imex_f64 if fp64 else S.step_imex)(a, b, alpha_t=1.3, alpha_s=0.6,
+                                                        inflow_scale=0.7, boundary=boundary)
+            err = rel_l2(S.to_user(b).cpu().numpy(), ref)
+            print(f"imex dense neumann={neumann} fp64={fp64}: {err:.2e}")
+            assert err <= tol
+        S.close()
+
+
+def test_imex_dense_isotropic_kernel_equals_isotropic_imex():
+    """The isotropic kernel as a dense matrix (rank one, eigenvalues 1 and 0) gives the
+    closed-form isotropic IMEX step."""
+    P = _dense_problem(4, 8, 0.0, 63, 50.0, rho=True, source=True, inflow=True)
+    Pd = dataclasses.replace(P, K=np.full((P.nq, P.nq), 1.0 / (4.0 * np.pi)))
+    Pi = dataclasses.replace(P, K=None)
+    outs = []
+    for Q in (Pd, Pi):
+        S = _solver(Q, precision="fp32", fp64=True)
+        a = S.initial_state(torch.float64)
+        b = torch.empty_like(a)
+        S.step_imex_f64(a, b)
+        outs.append(S.to_user(b).cpu().numpy())
+        S.close()
+    err = rel_l2(outs[0], outs[1])
+    print(f"imex dense isotropic vs closed form: {err:.2e}")
+    assert err <= 1e-13
+
+
+def test_imex_dense_prepare_rejections():
+    from paper_2205_08417_amd import snrt
+    omega, w = I.product_quadrature(4, 8)
+    rng = np.random.default_rng(64)
+    mesh = I.jittered_delaunay_mesh(6, 0.0, 1.0, seed=64)
+    # a positive kernel with no symmetrising diagonal
+    P = small_problem(mesh, omega_w=(omega, w), seed=64, K=rng.uniform(0.5, 1.5, (32, 32)))
+    S = _solver(P)
+    with pytest.raises(snrt.SnrtError) as ei:
+        snrt.snrt_scatter_prepare_implicit(S.scatter)
+    assert ei.value.status == snrt.SNRT_E_UNSUPPORTED
+    S.close()
+    # isotropic and moment-form handles have their own implicit solves
+    P = small_problem(mesh, omega_w=(omega, w), seed=64)
+    for kw in ({}, {"moments": [1.0, 0.5]}):
+        S = _solver(P, **kw)
+        with pytest.raises(snrt.SnrtError) as ei:
+            snrt.snrt_scatter_prepare_implicit(S.scatter)
+        assert ei.value.status == snrt.SNRT_E_UNSUPPORTED
+        S.close()
+    # workspace sized before the implicit form, or aliasing the state
+    P = small_problem(mesh, omega_w=(omega, w), seed=64,
+                      K=I.henyey_greenstein_kernel(omega, w, 0.6))
+    S = _solver(P, precision="bf16x3")
+    n_explicit = S.ws_bytes
+    S.prepare_implicit()
+    S.prepare_implicit()                                  # idempotent
+    assert S.ws_bytes >= n_explicit
+    a = S.initial_state()
+    b = torch.empty_like(a)
+    need = P.ncells * 2 * P.nq * 4
+    with pytest.raises(snrt.SnrtError) as ei:
+        snrt.snrt_step_imex_dense(S.mesh, S.quad, S.scatter, S.args(), a, b, S.ws, need - 16)
+    assert ei.value.status == snrt.SNRT_E_ARG
+    with pytest.raises(snrt.SnrtError) as ei:
+        snrt.snrt_step_imex_dense(S.mesh, S.quad, S.scatter, S.args(), a, b, a, S.ws_bytes)
+    assert ei.value.status in (snrt.SNRT_E_ALIAS, snrt.SNRT_E_ARG)
+    snrt.snrt_step_imex_dense(S.mesh, S.quad, S.scatter, S.args(), a, b, S.ws, need)
+    S.close()
+
+
+def test_full_size_line_source_imex_dense_sampled():
+    """100 352 cells x 1024 ordinates, dense HG g=0.9, BF16 hi+lo, cross sections x 5000
+    (dt sigma = 4.7): one IMEX step from the pulse, then one more from a rough state,
+    sampled cells against the oracle's LU solve one by one."""
+    from oracle import oracle as o
+    P = I.build("linesource_hg_s32")
+    P = dataclasses.replace(P, sigma_t=5000.0 * P.sigma_t, sigma_s=5000.0 * P.sigma_s)
+    S = _solver(P, precision="bf16x3")
+    rng = np.random.default_rng(5)
+    hot = np.nonzero(np.sum(P.mesh.centroid ** 2, axis=1) < 0.01)[0]
+    cells = np.unique(np.concatenate([hot[:24], rng.choice(P.ncells, 24, False)]))
+    op = o.OracleProblem.from_problem(P)
+    rough = I.random_state(P.ncells, P.nq, seed=65, decades=3)
+    for name, start in (("pulse", P.psi0), ("rough", rough)):
+        a = S.to_internal(start)
+        b = torch.empty_like(a)
+        S.step_imex(a, b)
+        out = S.to_user(b).cpu().numpy()[cells]
+        ref = o.step_imex(op, start, P.dt, cells=cells)
+        err = rel_l2(out, ref)
+        emax = float(np.max(np.abs(out - ref)) / np.max(np.abs(ref)))
+        print(f"imex dense full-size {name}: {err:.2e} (max {emax:.2e})")
+        assert err <= 1e-4 and emax <= 1e-3
     S.close()
 
 
