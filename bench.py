@@ -245,7 +245,46 @@ def bench_dense(steps, warmup: int):
                                                    peak=FP32_MFMA_PEAK_TFLOPS),
                    "vs_oracle": step_vs_oracle(S32, final32, oracle_rows)}
     S32.close()
+    out["imex_dense"] = bench_imex_dense(P, op, nsteps, warmup)
     return out
+
+
+def bench_imex_dense(P, op, nsteps: int, warmup: int):
+    """IMEX steps with the dense HG kernel (implicit collisions through the kernel's
+    eigendecomposition: collision-free step, product with V^-1, per-cell diagonal, product
+    with V diag(lam), combine), BF16 hi+lo, over the whole run from the initial pulse; the
+    one-time host set-up is timed on its own."""
+    import time
+    import torch
+    from oracle import oracle as o
+    from paper_2205_08417_amd.solver import Solver
+
+    S = Solver(P, precision="bf16x3")
+    t0 = time.perf_counter()
+    S.prepare_implicit()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    args = S.args()
+    st = [S.initial_state(), None]
+    st[1] = torch.empty_like(st[0])
+
+    def one_step():
+        S.step_imex(st[0], st[1], args)
+        st.reverse()
+
+    for _ in range(min(warmup, 3)):
+        one_step()
+    st[0] = S.initial_state()
+    torch.cuda.synchronize()
+    ms = timed(one_step, nsteps, torch.cuda.current_stream())
+    vs = step_vs_oracle(S, st[0], lambda start, c: o.step_imex(op, start, P.dt, cells=c), n=32,
+                        step=lambda a_, b_: S.step_imex(a_, b_, args), what="one IMEX step")
+    S.close()
+    return {"precision": "bf16x3", "steps": nsteps, "ms_per_step": ms,
+            "value": P.ncells * P.nq / (ms * 1e-3), "setup_s": setup_s,
+            "note": "implicit HG collisions through one eigendecomposition of K W (host FP64, "
+                    "set-up), two nq x nq products per step",
+            "vs_oracle": vs, "rel_l2_vs_oracle": vs["rel_l2"]}
 
 
 def library_gemm_ceiling(M: int, nq: int, reps: int = 10):
