@@ -137,7 +137,7 @@ snrt_status snrt_scatter_dense(snrt_scatter** out, const snrt_quad* quad, const 
  * l (sigma_0 = 1 conserves particles; Henyey-Greenstein: g^l).  Equivalent to the dense
  * kernel K[q][p] = sum_j m_j(Omega_q) sigma_l(j) m_j(Omega_p), applied as two products through
  * the moments.  0 <= degree <= 30.  The BF16 and FP16 modes need nq % 32 == 0 and pad the
- * moment count with zeros to a multiple of 128.  Steps with this handle need
+ * moment count with zeros to a multiple of 32.  Steps with this handle need
  * snrt_workspace_size bytes. */
 snrt_status snrt_scatter_moments(snrt_scatter** out, const snrt_quad* quad, int32_t degree,
                                  const double* sigma_l, snrt_precision precision);

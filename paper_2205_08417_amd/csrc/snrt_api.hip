@@ -553,8 +553,10 @@ snrt_status snrt_scatter_moments(snrt_scatter** out, const snrt_quad* q, int32_t
                      "snrt_scatter_moments: non-finite Legendre moment");
     SNRT_TRY(check_device(q->device, "snrt_scatter_moments"));
     const int32_t nm = (degree + 1) * (degree + 1);
-    // the low-precision products take the moments (inner and outer width) in multiples of 128
-    const int32_t mid = precision == SNRT_FP32 ? nm : ((nm + 127) / 128) * 128;
+    // the low-precision products take their inner width in chunks of 32: the moments are
+    // padded with zeros to a multiple of 32 (their outer width is padded to the tile width
+    // inside the operand, and only the mid real columns are written)
+    const int32_t mid = precision == SNRT_FP32 ? nm : ((nm + 31) / 32) * 32;
     // Mt[q][j] = w_q m_j(Omega_q), Ot[j][q] = sigma_l(j) m_j(Omega_q); zero past nm
     std::vector<double> mt((size_t)nq * mid, 0.0), ot((size_t)mid * nq, 0.0);
     std::vector<double> mtT((size_t)mid * nq, 0.0), otT((size_t)nq * mid, 0.0);

@@ -73,8 +73,8 @@ struct GemmOperand {
 //   dense kernel (chain 1):  X0 = B, B[p][q] = w_p K[q][p];  adjoint X0 = B^T;
 //   moments (chain 2, eq. SNEqns2):  X0 = M^T [nq][mid] (w_q m_j(Omega_q)), X1 = (Sigma O)^T
 //   [mid][nq] (sigma_l(j) m_j(Omega_q)); adjoint X0 = X1^T, X1 = X0^T.  mid = the moment
-//   count (N+1)^2, padded with zero columns to a multiple of 128 for the BF16 MFMA
-//   kernel (unpadded in FP32).
+//   count (N+1)^2, padded with zero columns to a multiple of 32 (the K chunk) for the BF16
+//   and FP16 MFMA kernels (unpadded in FP32).
 struct DenseB {
     int32_t nq = 0;
     snrt_precision precision = SNRT_FP32;
