@@ -113,6 +113,98 @@ __device__ __forceinline__ void split4_f16(f32x4 v, int e, uint32_t (&hi)[2], ui
 // position of 16-byte granule g in LDS row r
 __device__ __forceinline__ int swz(int r, int g) { return g ^ ((r >> 2) & 3); }
 
+// Per-row scalars of the epilogue modes (GemmEpi): kScale a and b, kCombine y in pa.
+__device__ __forceinline__ void epi_row(const GemmEpi& epi, int64_t row, float& pa, float& pb) {
+    pa = pb = 0.0f;
+    if (epi.mode == GemmEpi::kScale) {
+        pa = 1.0f + epi.dt * epi.alpha_t * epi.sigma_t[row];
+        pb = epi.dt * epi.alpha_s * epi.sigma_s[row];
+    } else if (epi.mode == GemmEpi::kCombine) {
+        const float cabs = epi.dt * epi.alpha_t * epi.sigma_t[row];
+        pa = cabs / (1.0f + cabs);
+    }
+}
+
+// One accumulated element v through epilogue mode MODE; old is C's previous value (kCombine).
+template <int MODE>
+__device__ __forceinline__ float epi_val(float v, float old, float pa, float pb, float sg) {
+    if constexpr (MODE == GemmEpi::kScale) return v * (pb / (pa - pb * sg));
+    if constexpr (MODE == GemmEpi::kCombine) {
+        const float x = old + v;
+        return x - x * pa;
+    }
+    return v;
+}
+
+// The epilogue of one wave's IM x JN accumulator tiles (32 x 32 each; accumulator r of lane l
+// is row row0 + (r/4)*8 + (l/32)*4 + r%4 of the tile, column col0 + l%32).  C is written
+// with the streaming bit (read once, by the next kernel or here).  kCombine first loads the
+// tile row's previous values, all of them before any store, so the loads overlap.  eu:
+// per-row exponents that undo the FP16 scaling (0 otherwise).
+template <int MODE, int IM, int JN, typename Acc, typename RowOf, typename ExpOf>
+__device__ __forceinline__ void epilogue_tiles(const GemmEpi& epi, Acc (&acc)[IM][JN],
+                                               float* __restrict__ C, int64_t M, int32_t ldc,
+                                               int col0, int lane, RowOf row_of, ExpOf exp_of) {
+#pragma unroll
+    for (int i = 0; i < IM; ++i) {
+        int eu[16];
+        float pa[16], pb[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t row = row_of(i, r);
+            eu[r] = exp_of(row);
+            pa[r] = pb[r] = 0.0f;
+            if constexpr (MODE != GemmEpi::kStore)
+                if (row < M) epi_row(epi, row, pa[r], pb[r]);
+        }
+        float old[JN][16];
+#pragma unroll
+        for (int j = 0; j < JN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                old[j][r] = 0.0f;
+                if constexpr (MODE == GemmEpi::kCombine) {
+                    const int col = col0 + j * 32 + (lane & 31);
+                    const int64_t row = row_of(i, r);
+                    if (col < ldc && row < M) old[j][r] = C[row * ldc + col];
+                }
+            }
+#pragma unroll
+        for (int j = 0; j < JN; ++j) {
+            const int col = col0 + j * 32 + (lane & 31);
+            if (col >= ldc) continue;
+            const float sg = MODE == GemmEpi::kScale ? epi.sig[col] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = row_of(i, r);
+                const float v = eu[r] != 0 ? __builtin_ldexpf(acc[i][j][r], eu[r]) : acc[i][j][r];
+                if (row < M)
+                    __builtin_nontemporal_store(epi_val<MODE>(v, old[j][r], pa[r], pb[r], sg),
+                                                &C[row * ldc + col]);
+            }
+        }
+    }
+}
+
+template <int IM, int JN, typename Acc, typename RowOf, typename ExpOf>
+__device__ __forceinline__ void epilogue_any(const GemmEpi& epi, Acc (&acc)[IM][JN],
+                                             float* __restrict__ C, int64_t M, int32_t ldc,
+                                             int col0, int lane, RowOf row_of, ExpOf exp_of) {
+    if (epi.mode == GemmEpi::kScale)
+        epilogue_tiles<GemmEpi::kScale>(epi, acc, C, M, ldc, col0, lane, row_of, exp_of);
+    else if (epi.mode == GemmEpi::kCombine)
+        epilogue_tiles<GemmEpi::kCombine>(epi, acc, C, M, ldc, col0, lane, row_of, exp_of);
+    else
+        epilogue_tiles<GemmEpi::kStore>(epi, acc, C, M, ldc, col0, lane, row_of, exp_of);
+}
+
+// The epilogue's per-row arrays for rows that start at row0 of the full product.
+__device__ __forceinline__ GemmEpi epi_rows_from(GemmEpi e, int64_t row0) {
+    if (e.sigma_t) e.sigma_t += row0;
+    if (e.sigma_s) e.sigma_s += row0;
+    return e;
+}
+
 // One BM x BN block tile of C = A X; lb is the logical block index (row block major, column
 // blocks fastest) and lds the block's two stages of NP planes.  N is the padded width of X
 // (a multiple of BN), ldc <= N the row length of C.  F16: FP16 operands with the row
@@ -124,7 +216,7 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
                                            float* __restrict__ C, int64_t M, int32_t K,
                                            int32_t N, int32_t ldc,
                                            const int32_t* __restrict__ rexp, int32_t eb,
-                                           int64_t lb, uint16_t* lds)
+                                           int64_t lb, uint16_t* lds, const GemmEpi& epi)
 {
     using Frag = typename std::conditional<F16, f16x8, bf16x8>::type;
     static_assert(BM == 64 || BM == 128 || BM == 256, "block rows");
@@ -296,30 +388,13 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A,
         }
     }
 
-    // epilogue: accumulator r of lane l is row (r/4)*8 + (l/32)*4 + r%4, column l%32; S is
-    // consumed once by the step kernel, so it is streamed past the caches.  Columns past ldc
-    // (the zero padding of X) are not stored.
-#pragma unroll
-    for (int i = 0; i < IM; ++i) {
-        // FP16: the exponent that undoes the scaling of each of this lane's 16 rows
-        int eu[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int64_t row = m0 + wm + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-            eu[r] = (F16 && row < M) ? -(rexp[row] + eb) : 0;
-        }
-#pragma unroll
-        for (int j = 0; j < JN; ++j) {
-            const int col = n0 + wn + j * 32 + fr;
-            if (col >= ldc) continue;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t row = m0 + wm + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-                const float v = F16 ? __builtin_ldexpf(acc[i][j][r], eu[r]) : acc[i][j][r];
-                if (row < M) __builtin_nontemporal_store(v, &C[row * ldc + col]);
-            }
-        }
-    }
+    // epilogue: columns past ldc (the zero padding of X) are not stored; FP16 rows are
+    // scaled back by 2^-(e_r + e_B) first
+    auto row_of = [&](int i, int r) -> int64_t {
+        return m0 + wm + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+    };
+    auto exp_of = [&](int64_t row) -> int { return (F16 && row < M) ? -(rexp[row] + eb) : 0; };
+    epilogue_any<IM, JN>(epi, acc, C, M, ldc, n0 + wn, lane, row_of, exp_of);
 }
 
 // Blocks [0, nmain) are 256 x 256 tiles of the first M1 rows; blocks [nmain, grid) are
@@ -331,7 +406,7 @@ __device__ __forceinline__ void gemm_grid(const float* __restrict__ A,
                                           const uint16_t* __restrict__ Blo, float* __restrict__ C,
                                           int64_t M1, int64_t M, int32_t K, int32_t N,
                                           int32_t ldc, const int32_t* __restrict__ rexp,
-                                          int32_t eb, int64_t nmain)
+                                          int32_t eb, int64_t nmain, const GemmEpi& epi)
 {
     constexpr int NP = P == 3 ? 4 : P == 2 ? 3 : 2;
     __shared__ __attribute__((aligned(16))) uint16_t lds[2 * NP * kPlane];
@@ -340,13 +415,14 @@ __device__ __forceinline__ void gemm_grid(const float* __restrict__ A,
         // 256 x 256 tiles keep one chunk in flight (their multiply covers the load latency
         // and their accumulators leave no room for more); 256 x 128 tiles keep two
         gemm_block<P, 256, MBN, MBN == 256 ? 1 : 2, STAGGER, F16>(
-            A, Bhi, Blo, C, M1, K, N, ldc, rexp, eb, xcd_remap(b, nmain), lds);
+            A, Bhi, Blo, C, M1, K, N, ldc, rexp, eb, xcd_remap(b, nmain), lds, epi);
     } else {
         // nmain is a multiple of the XCD count, so the remap of the tail stays XCD-aware
         const int64_t nt = (int64_t)gridDim.x - nmain;
         gemm_block<P, TM, TN, TFD, STAGGER, F16>(A + M1 * K, Bhi, Blo, C + M1 * ldc, M - M1, K,
                                                  N, ldc, F16 ? rexp + M1 : rexp, eb,
-                                                 xcd_remap(b - nmain, nt), lds);
+                                                 xcd_remap(b - nmain, nt), lds,
+                                                 epi_rows_from(epi, M1));
     }
 }
 
@@ -356,10 +432,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const float* __restrict_
                                                         const uint16_t* __restrict__ Blo,
                                                         float* __restrict__ C, int64_t M1,
                                                         int64_t M, int32_t K, int32_t N,
-                                                        int32_t ldc, int64_t nmain)
+                                                        int32_t ldc, int64_t nmain,
+                                                        GemmEpi epi)
 {
     gemm_grid<false, P, MBN, TM, TN, TFD, STAGGER>(A, Bhi, Blo, C, M1, M, K, N, ldc, nullptr, 0,
-                                                   nmain);
+                                                   nmain, epi);
 }
 
 // The FP16 hi+lo product (three products) with per-row exponents rexp of A and exponent eb
@@ -372,10 +449,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f16(const float* __restrict__
                                                        int64_t M, int32_t K, int32_t N,
                                                        int32_t ldc,
                                                        const int32_t* __restrict__ rexp,
-                                                       int32_t eb, int64_t nmain)
+                                                       int32_t eb, int64_t nmain, GemmEpi epi)
 {
     gemm_grid<true, 3, MBN, TM, TN, TFD, STAGGER>(A, Bhi, Blo, C, M1, M, K, N, ldc, rexp, eb,
-                                                  nmain);
+                                                  nmain, epi);
 }
 
 // Row exponents of A [M][K] for the FP16 product: e_r with max_k |A[r][k]| * 2^e_r in
@@ -422,7 +499,8 @@ template <int BM, int BN, int FD>
 __device__ __forceinline__ void gemm_block_f32(const float* __restrict__ A,
                                                const float* __restrict__ Bt,
                                                float* __restrict__ C, int64_t M, int32_t K,
-                                               int32_t N, int64_t lb, float* lds)
+                                               int32_t N, int64_t lb, float* lds,
+                                               const GemmEpi& epi)
 {
     static_assert(BM == 64 || BM == 128 || BM == 256, "block rows");
     static_assert(BN == 128 || BN == 256, "block columns");
@@ -528,17 +606,12 @@ __device__ __forceinline__ void gemm_block_f32(const float* __restrict__ A,
         }
     }
 
-#pragma unroll
-    for (int i = 0; i < IM; ++i)
-#pragma unroll
-        for (int j = 0; j < JN; ++j) {
-            const int col = n0 + wn + j * 32 + fr;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t row = m0 + wm + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-                if (row < M) __builtin_nontemporal_store(acc[i][j][r], &C[row * N + col]);
-            }
-        }
+    auto row_of = [&](int i, int r) -> int64_t {
+        return m0 + wm + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+    };
+    auto exp_of = [](int64_t) -> int { return 0; };
+    (void)fr;
+    epilogue_any<IM, JN>(epi, acc, C, M, N, n0 + wn, lane, row_of, exp_of);
 }
 
 template <int MBN, int TM, int TN, int TFD>
@@ -546,17 +619,17 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(const float* __restrict__
                                                        const float* __restrict__ Bt,
                                                        float* __restrict__ C, int64_t M1,
                                                        int64_t M, int32_t K, int32_t N,
-                                                       int64_t nmain)
+                                                       int64_t nmain, GemmEpi epi)
 {
     __shared__ __attribute__((aligned(16))) float lds[2 * 2 * 256 * BK];
     const int64_t b = blockIdx.x;
     if (b < nmain) {
         gemm_block_f32<256, MBN, MBN == 256 ? 1 : 2>(A, Bt, C, M1, K, N, xcd_remap(b, nmain),
-                                                     lds);
+                                                     lds, epi);
     } else {
         const int64_t nt = (int64_t)gridDim.x - nmain;
         gemm_block_f32<TM, TN, TFD>(A + M1 * K, Bt, C + M1 * N, M - M1, K, N,
-                                    xcd_remap(b - nmain, nt), lds);
+                                    xcd_remap(b - nmain, nt), lds, epi_rows_from(epi, M1));
     }
 }
 
@@ -662,7 +735,7 @@ int device_cu_count() {
 template <int MBN, int TM, int TN>
 hipError_t launch_split(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
                         int64_t M1, int64_t M, int32_t K, int32_t N, int32_t ldc, int products,
-                        const int32_t* rexp, int32_t eb, hipStream_t st) {
+                        const int32_t* rexp, int32_t eb, hipStream_t st, const GemmEpi& epi) {
     const int64_t nmain = ((M1 + 255) / 256) * (N / MBN);
     const int64_t ntail = ((M - M1 + TM - 1) / TM) * (N / TN);
     const dim3 grid((unsigned)(nmain + ntail));
@@ -671,10 +744,10 @@ hipError_t launch_split(const float* A, const uint16_t* Bhi, const uint16_t* Blo
         constexpr bool SG = decltype(stagger_c)::value;
         if constexpr (PP == 0)
             hipLaunchKernelGGL((k_gemm_f16<MBN, TM, TN, 4, SG>), grid, dim3(kThreads), 0, st, A,
-                               Bhi, Blo, C, M1, M, K, N, ldc, rexp, eb, nmain);
+                               Bhi, Blo, C, M1, M, K, N, ldc, rexp, eb, nmain, epi);
         else
             hipLaunchKernelGGL((k_gemm_bf16<PP, MBN, TM, TN, 4, SG>), grid, dim3(kThreads), 0,
-                               st, A, Bhi, Blo, C, M1, M, K, N, ldc, nmain);
+                               st, A, Bhi, Blo, C, M1, M, K, N, ldc, nmain, epi);
         return hipGetLastError();
     };
     // the staggered phases pay on the square products of the dense kernel (4-5 % measured);
@@ -692,7 +765,7 @@ hipError_t launch_split(const float* A, const uint16_t* Bhi, const uint16_t* Blo
 // The shape policy of both low-precision products (products 1..3: BF16; 0: FP16 x3).
 hipError_t launch_gemm_lp(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
                           int64_t M, int32_t K, int32_t N, int32_t ldc, int products,
-                          const int32_t* rexp, int32_t eb, hipStream_t st) {
+                          const int32_t* rexp, int32_t eb, hipStream_t st, const GemmEpi& epi) {
     if (M == 0) return hipSuccess;
     if (products < 0 || products > 3) return hipErrorInvalidValue;
     if (K % BK != 0 || N % 128 != 0 || K == 0 || ldc <= 0 || ldc > N)
@@ -715,29 +788,30 @@ hipError_t launch_gemm_lp(const float* A, const uint16_t* Bhi, const uint16_t* B
     if (!wide) {
         if (quarter)
             return launch_split<128, 64, 128>(A, Bhi, Blo, C, rows1, M, K, N, ldc, products,
-                                              rexp, eb, st);
+                                              rexp, eb, st, epi);
         return launch_split<128, 64, 128>(A, Bhi, Blo, C, M, M, K, N, ldc, products, rexp, eb,
-                                          st);
+                                          st, epi);
     }
     if (eighth)
         return launch_split<256, 64, 128>(A, Bhi, Blo, C, rows1, M, K, N, ldc, products, rexp,
-                                          eb, st);
+                                          eb, st, epi);
     if (quarter)
         return launch_split<256, 64, 256>(A, Bhi, Blo, C, rows1, M, K, N, ldc, products, rexp,
-                                          eb, st);
-    return launch_split<256, 64, 256>(A, Bhi, Blo, C, M, M, K, N, ldc, products, rexp, eb, st);
+                                          eb, st, epi);
+    return launch_split<256, 64, 256>(A, Bhi, Blo, C, M, M, K, N, ldc, products, rexp, eb, st,
+                                      epi);
 }
 
 hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
                             int64_t M, int32_t K, int32_t N, int32_t ldc, int products,
-                            hipStream_t st) {
+                            hipStream_t st, const GemmEpi& epi) {
     if (products < 1 || products > 3) return hipErrorInvalidValue;
-    return launch_gemm_lp(A, Bhi, Blo, C, M, K, N, ldc, products, nullptr, 0, st);
+    return launch_gemm_lp(A, Bhi, Blo, C, M, K, N, ldc, products, nullptr, 0, st, epi);
 }
 
 hipError_t launch_gemm_f16x3(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
                              int64_t M, int32_t K, int32_t N, int32_t ldc, int32_t* rexp,
-                             int32_t eb, hipStream_t st) {
+                             int32_t eb, hipStream_t st, const GemmEpi& epi) {
     if (M == 0) return hipSuccess;
     if (!rexp || K % BK != 0 || K == 0) return hipErrorNotSupported;
     const int64_t want = (M + 3) / 4;
@@ -745,21 +819,21 @@ hipError_t launch_gemm_f16x3(const float* A, const uint16_t* Bhi, const uint16_t
     hipLaunchKernelGGL(k_row_exp_f16, dim3(nb), dim3(256), 0, st, A, M, K, rexp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_gemm_lp(A, Bhi, Blo, C, M, K, N, ldc, 0, rexp, eb, st);
+    return launch_gemm_lp(A, Bhi, Blo, C, M, K, N, ldc, 0, rexp, eb, st, epi);
 }
 
 template <int MBN, int TM, int TN>
 hipError_t launch_f32_split(const float* A, const float* Bt, float* C, int64_t M1, int64_t M,
-                            int32_t K, int32_t N, hipStream_t st) {
+                            int32_t K, int32_t N, hipStream_t st, const GemmEpi& epi) {
     const int64_t nmain = ((M1 + 255) / 256) * (N / MBN);
     const int64_t ntail = ((M - M1 + TM - 1) / TM) * (N / TN);
     hipLaunchKernelGGL((k_gemm_f32<MBN, TM, TN, 4>), dim3((unsigned)(nmain + ntail)),
-                       dim3(kThreads), 0, st, A, Bt, C, M1, M, K, N, nmain);
+                       dim3(kThreads), 0, st, A, Bt, C, M1, M, K, N, nmain, epi);
     return hipGetLastError();
 }
 
 hipError_t launch_gemm_f32mfma(const float* A, const float* Bt, float* C, int64_t M, int32_t K,
-                               int32_t N, hipStream_t st) {
+                               int32_t N, hipStream_t st, const GemmEpi& epi) {
     if (M == 0) return hipSuccess;
     if (K % BK != 0 || N % 128 != 0 || K == 0) return hipErrorNotSupported;
     // the same block shapes and last-round policy as the BF16 product
@@ -773,11 +847,11 @@ hipError_t launch_gemm_f32mfma(const float* A, const float* Bt, float* C, int64_
     const bool quarter = !eighth && level && rem * 4 <= cu;
     const int64_t rows1 = std::min<int64_t>(((tiles - rem) / nN) * 256, M);
     if (!wide)
-        return quarter ? launch_f32_split<128, 64, 128>(A, Bt, C, rows1, M, K, N, st)
-                       : launch_f32_split<128, 64, 128>(A, Bt, C, M, M, K, N, st);
-    if (eighth) return launch_f32_split<256, 64, 128>(A, Bt, C, rows1, M, K, N, st);
-    if (quarter) return launch_f32_split<256, 64, 256>(A, Bt, C, rows1, M, K, N, st);
-    return launch_f32_split<256, 64, 256>(A, Bt, C, M, M, K, N, st);
+        return quarter ? launch_f32_split<128, 64, 128>(A, Bt, C, rows1, M, K, N, st, epi)
+                       : launch_f32_split<128, 64, 128>(A, Bt, C, M, M, K, N, st, epi);
+    if (eighth) return launch_f32_split<256, 64, 128>(A, Bt, C, rows1, M, K, N, st, epi);
+    if (quarter) return launch_f32_split<256, 64, 256>(A, Bt, C, rows1, M, K, N, st, epi);
+    return launch_f32_split<256, 64, 256>(A, Bt, C, M, M, K, N, st, epi);
 }
 
 }  // namespace snrt

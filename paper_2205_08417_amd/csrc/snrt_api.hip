@@ -51,6 +51,7 @@ const Tune& tune() {
             if (n >= 3 && bpc3 >= 1 && bpc3 <= 64) r.adjoint_blocks_per_cu = bpc3;
         }
         if (const char* e = std::getenv("SNRT_GEMM_STAGGER")) r.gemm_stagger = std::atoi(e) != 0;
+        if (const char* e = std::getenv("SNRT_GEMM_EPILOGUE")) r.gemm_epilogue = std::atoi(e) != 0;
         return r;
     }();
     return t;
@@ -797,17 +798,27 @@ StepArgs64 to64(const snrt_step_args_f64* a) {
     return r;
 }
 
+// Whether product32 runs this operand on a matrix-core kernel, which applies the epilogue
+// modes of GemmEpi (the vector FP32 kernel of odd shapes only stores).
+bool product_fuses_epi(const DenseB& B, const GemmOperand& op) {
+    if (!tune().gemm_epilogue) return false;
+    return B.precision != SNRT_FP32 || op.t32 != nullptr;
+}
+
 // out = in X for one right operand of the chain, in the handle's precision; rexp: [M] int32
-// scratch for the FP16 mode's row exponents
+// scratch for the FP16 mode's row exponents; epi: what happens to each element on the way
+// out (product_fuses_epi must hold for any mode but kStore)
 hipError_t product32(const DenseB& B, const GemmOperand& op, const float* in, float* out,
-                     int64_t M, int32_t* rexp, hipStream_t st) {
+                     int64_t M, int32_t* rexp, hipStream_t st, const GemmEpi& epi = GemmEpi()) {
+    if (epi.mode != GemmEpi::kStore && !product_fuses_epi(B, op)) return hipErrorNotSupported;
     if (B.precision == SNRT_FP32)
-        return op.t32 ? launch_gemm_f32mfma(in, op.t32, out, M, op.K, op.N, st)
+        return op.t32 ? launch_gemm_f32mfma(in, op.t32, out, M, op.K, op.N, st, epi)
                       : launch_gemm32(in, op.f32, out, M, op.K, op.N, st);
     if (B.precision == SNRT_FP16X3)
-        return launch_gemm_f16x3(in, op.hi, op.lo, out, M, op.K, op.Np, op.N, rexp, op.eb, st);
+        return launch_gemm_f16x3(in, op.hi, op.lo, out, M, op.K, op.Np, op.N, rexp, op.eb, st,
+                                 epi);
     const int products = B.precision == SNRT_BF16X3 ? 3 : B.precision == SNRT_BF16X2 ? 2 : 1;
-    return launch_gemm_bf16(in, op.hi, op.lo, out, M, op.K, op.Np, op.N, products, st);
+    return launch_gemm_bf16(in, op.hi, op.lo, out, M, op.K, op.Np, op.N, products, st, epi);
 }
 
 // The FP16 row exponents in the product workspace: after the moments of the moment form.
@@ -1166,10 +1177,35 @@ hipError_t imex_modes(const snrt_mesh* m, const snrt_quad* q, const DenseB& B,
         free_flight.alpha_t = 0.0f;
         free_flight.alpha_s = 0.0f;
         e = launch_free_step32(*m, *q, free_flight, psi_in, psi_out, st);
-        if (e == hipSuccess) e = product32(B, ops[0], psi_out, U, m->nc, rexp, st);
-        if (e == hipSuccess) e = launch_imex_moment_scale32(a32, U, sig32, m->nc, mid, st);
-        if (e == hipSuccess) e = product32(B, ops[1], U, S, m->nc, rexp, st);
-        if (e == hipSuccess) e = launch_imex_combine32(a32, psi_out, S, m->nc, q->nq, st);
+        // the per-cell diagonal and the final combine ride on the two products' epilogues
+        // where the matrix-core kernels run them (S then stays unused), else separate passes
+        GemmEpi scale;
+        scale.mode = GemmEpi::kScale;
+        scale.sigma_t = a32.sigma_t;
+        scale.sigma_s = a32.sigma_s;
+        scale.sig = sig32;
+        scale.dt = a32.dt;
+        scale.alpha_t = a32.alpha_t;
+        scale.alpha_s = a32.alpha_s;
+        GemmEpi combine = scale;
+        combine.mode = GemmEpi::kCombine;
+        combine.sig = nullptr;
+        if (e == hipSuccess) {
+            if (product_fuses_epi(B, ops[0])) {
+                e = product32(B, ops[0], psi_out, U, m->nc, rexp, st, scale);
+            } else {
+                e = product32(B, ops[0], psi_out, U, m->nc, rexp, st);
+                if (e == hipSuccess) e = launch_imex_moment_scale32(a32, U, sig32, m->nc, mid, st);
+            }
+        }
+        if (e == hipSuccess) {
+            if (product_fuses_epi(B, ops[1])) {
+                e = product32(B, ops[1], U, psi_out, m->nc, rexp, st, combine);
+            } else {
+                e = product32(B, ops[1], U, S, m->nc, rexp, st);
+                if (e == hipSuccess) e = launch_imex_combine32(a32, psi_out, S, m->nc, q->nq, st);
+            }
+        }
     } else {
         const StepArgs64 a64 = to64(a);
         StepArgs64 free_flight = a64;

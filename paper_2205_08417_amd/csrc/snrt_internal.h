@@ -165,12 +165,14 @@ namespace snrt {
 // Launch-shape knobs of the persistent kernels and the BF16 product.  Defaults are the tuned
 // values for MI355X.  SNRT_STEP_TUNE="<step>[,<second-order update>[,<adjoint>]]" overrides
 // the blocks per CU of the three persistent sweeps, SNRT_GEMM_STAGGER=0 turns the staggered
-// chunk order of the product off (both read once per process).
+// chunk order of the product off, SNRT_GEMM_EPILOGUE=0 the IMEX steps in the products'
+// epilogues (separate passes instead; all read once per process).
 struct Tune {
     int step_blocks_per_cu = 3;
     int flux2_blocks_per_cu = 2;   // its larger per-cell footprint favours a narrower sweep
     int adjoint_blocks_per_cu = 7; // the adjoint's smaller workloads favour a wide grid
     bool gemm_stagger = true;      // staggered split/product phases in the BF16 product
+    bool gemm_epilogue = true;     // IMEX per-cell steps in the products' epilogues
 };
 const Tune& tune();
 
@@ -288,15 +290,31 @@ hipError_t launch_gemm32(const float* A, const float* B, float* C, int64_t M, in
                          int32_t N, hipStream_t st);
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int64_t M, int32_t K,
                          int32_t N, hipStream_t st);
+// What the matrix-core products do with each accumulated element v = (A X)[row][col] (row a
+// cell): store it (kStore), or apply the two per-cell steps of the mode-space IMEX solve on
+// the way out (IMEX step of Sec. 4.2), with a = 1 + dt alpha_t sigma_t[row] and
+// b = dt alpha_s sigma_s[row]:
+//   kScale:    C = v * (b / (a - b sig[col]))      the per-cell diagonal on the moments
+//   kCombine:  x = C + v, C = x - x y,  y = (a - 1) / a   (C holds the collision-free step)
+// Both evaluate exactly the expressions of the separate passes in sn_step_imex.hip.
+struct GemmEpi {
+    enum : int32_t { kStore = 0, kScale = 1, kCombine = 2 };
+    int32_t mode = kStore;
+    const float* sigma_t = nullptr;
+    const float* sigma_s = nullptr;
+    const float* sig = nullptr;
+    float dt = 0.0f, alpha_t = 0.0f, alpha_s = 0.0f;
+};
+
 // Low-precision products on the matrix cores: X in the hi/lo tiled format with N padded
 // columns (N % 128 == 0, K % 32 == 0); C is [M][ldc], ldc <= N.  The FP16 form first writes
 // the row exponents of A to rexp [M] (device scratch) and scales X's part by 2^-eb.
 hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
                             int64_t M, int32_t K, int32_t N, int32_t ldc, int products,
-                            hipStream_t st);
+                            hipStream_t st, const GemmEpi& epi = GemmEpi());
 hipError_t launch_gemm_f16x3(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
                              int64_t M, int32_t K, int32_t N, int32_t ldc, int32_t* rexp,
-                             int32_t eb, hipStream_t st);
+                             int32_t eb, hipStream_t st, const GemmEpi& epi = GemmEpi());
 // Re-layout of an FP32 [K][N] matrix (N % 128 == 0) into the BF16 hi/lo operand format of the
 // MFMA GEMM, and into the FP16 format of X * 2^eb.
 hipError_t launch_split_bf16(const float* B, uint16_t* hi, uint16_t* lo, int32_t K, int32_t N,
@@ -305,7 +323,7 @@ hipError_t launch_split_f16(const float* B, uint16_t* hi, uint16_t* lo, int32_t 
                             int32_t eb, hipStream_t st);
 // The FP32 product on the matrix cores (K % 32 == 0, N % 128 == 0) and its operand layout.
 hipError_t launch_gemm_f32mfma(const float* A, const float* Bt, float* C, int64_t M, int32_t K,
-                               int32_t N, hipStream_t st);
+                               int32_t N, hipStream_t st, const GemmEpi& epi = GemmEpi());
 hipError_t launch_tile_f32(const float* B, float* out, int32_t K, int32_t N, hipStream_t st);
 
 // IMEX step with the isotropic collision operator taken implicitly (sn_step_imex.hip).
