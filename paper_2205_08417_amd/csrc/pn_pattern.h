@@ -110,6 +110,64 @@ struct SubMoments {
     }();
 };
 
+// The z-parity-PZ moments ordered by reflection class for the matrix-core step: the four
+// classes of that parity (local class lc = x parity * 2 + y parity) one after the other,
+// largest first (equal sizes in class order), each in increasing moment order.  Inside a
+// class, |A_x| and |A_y| are dense: with the class's moments as both inputs and outputs in
+// this order, the class block is a product of the class's coefficient matrix with the
+// stacked P and Q aggregates of its inputs.
+template <int N, int PZ>
+struct ClassOrder {
+    static constexpr int NM = nmom(N);
+    static constexpr std::array<int, 4> size = [] {
+        std::array<int, 4> c{};
+        for (int j = 0; j < NM; ++j)
+            if (zpar(j) == PZ) ++c[mom(j).cls & 3];
+        return c;
+    }();
+    // classes by decreasing size (stable)
+    static constexpr std::array<int, 4> order = [] {
+        std::array<int, 4> o{0, 1, 2, 3};
+        for (int a = 0; a < 4; ++a)
+            for (int b = a + 1; b < 4; ++b)
+                if (size[o[b]] > size[o[a]] || (size[o[b]] == size[o[a]] && o[b] < o[a])) {
+                    const int t = o[a];
+                    o[a] = o[b];
+                    o[b] = t;
+                }
+        return o;
+    }();
+    static constexpr int count = size[0] + size[1] + size[2] + size[3];
+    static constexpr std::array<int, count> list = [] {
+        std::array<int, count> l{};
+        int c = 0;
+        for (int q = 0; q < 4; ++q)
+            for (int j = 0; j < NM; ++j)
+                if (zpar(j) == PZ && (mom(j).cls & 3) == order[q]) l[c++] = j;
+        return l;
+    }();
+    // position of moment j inside its class (its row and column in the class block)
+    static constexpr std::array<int, NM> local = [] {
+        std::array<int, NM> t{};
+        std::array<int, 4> used{};
+        for (int j = 0; j < NM; ++j) {
+            t[j] = -1;
+            if (zpar(j) == PZ) t[j] = used[mom(j).cls & 3]++;
+        }
+        return t;
+    }();
+    // moment at position t of local class lc (-1 past the class)
+    static constexpr int at(int lc, int t) {
+        int c = 0;
+        for (int j = 0; j < NM; ++j)
+            if (zpar(j) == PZ && (mom(j).cls & 3) == lc) {
+                if (c == t) return j;
+                ++c;
+            }
+        return -1;
+    }
+};
+
 template <int N>
 struct OpTable {
     static constexpr int NM = nmom(N);
@@ -139,6 +197,28 @@ struct OpTable {
         for (int m = 1; m <= NM; ++m)
             if (s[m] < s[m - 1]) s[m] = s[m - 1];
         return s;
+    }();
+};
+
+// The A_x and A_y coefficients (kinds X, Y) of OpTable<N> as a table of their own, in
+// OpTable order: sidx[i] is the position of op i (-1 for the |A_x|, |A_y| kinds).
+template <int N>
+struct SparseOps {
+    static constexpr int nops = OpTable<N>::count;
+    static constexpr std::array<int, nops> sidx = [] {
+        std::array<int, nops> a{};
+        int c = 0;
+        for (int i = 0; i < nops; ++i) {
+            const int kind = OpTable<N>::ops[i].kind;
+            a[i] = (kind == kOpX || kind == kOpY) ? c++ : -1;
+        }
+        return a;
+    }();
+    static constexpr int count = [] {
+        int c = 0;
+        for (int i = 0; i < nops; ++i)
+            c += OpTable<N>::ops[i].kind == kOpX || OpTable<N>::ops[i].kind == kOpY;
+        return c;
     }();
 };
 

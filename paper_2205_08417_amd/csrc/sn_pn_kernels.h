@@ -430,6 +430,332 @@ hipError_t launch_fused_t(const snrt_mesh& m, const snrt_pn& p, const typename A
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- matrix-core form
+//
+// Inside each reflection class |A_x| and |A_y| are dense (pn_pattern.h), and their part of
+// the flux, sum over the class's inputs m of |A_x|[k][m] P_m + |A_y|[k][m] Q_m into every
+// output k of the class, is 85 % of the coefficient applications at degree 13.  The
+// matrix-core step runs the moment loop class by class (pn::ClassOrder), keeps the sparse
+// A_x X and A_y Y coefficients, the collision term and the gathers on the vector unit, and
+// stages each input's P and Q in LDS (a row per cell, P in columns 0-31, Q in 32-63).  After
+// a class's last input the class block D = W_c [P; Q] (W_c: 32 outputs x 64 stacked inputs,
+// zero-padded) runs as 4 K steps of v_mfma_f32_32x32x16_f16 per 32-cell half, in FP16 hi+lo
+// with three products (hi hi, hi lo, lo hi) as the scattering product does: each cell's
+// staged values are scaled by 2^e_c (their largest magnitude into [2^13, 2^14)), the
+// coefficients by a per-class 2^e_W prepared on the host, and the accumulators scaled back
+// exactly.  The accumulators hold rows = outputs, columns = cells; one v_permlane32_swap per
+// register pair turns the two halves into lane-per-cell rows that are added to the vector
+// accumulators.
+typedef _Float16 f16x8_pn __attribute__((ext_vector_type(8)));
+typedef float f32x16_pn __attribute__((ext_vector_type(16)));
+
+constexpr int kPnStageRow = 68;                      // floats per staged cell row (64 + 4)
+constexpr int kPnStageWave = kTile * kPnStageRow;    // floats per wavefront
+
+template <int N, int IDX>
+__device__ __forceinline__ void apply_sparse_op(float (&acc)[pn::nmom(N)], float X, float Y,
+                                                const float* __restrict__ Ws) {
+    constexpr pn::Op op = pn::OpTable<N>::ops[IDX];
+    constexpr int si = pn::SparseOps<N>::sidx[IDX];
+    if constexpr (si >= 0) acc[op.k] = fma(op.kind == pn::kOpX ? X : Y, Ws[si], acc[op.k]);
+}
+
+template <int N, int S, int... I>
+__device__ __forceinline__ void apply_sparse_ops(float (&acc)[pn::nmom(N)], float X, float Y,
+                                                 const float* __restrict__ Ws,
+                                                 std::integer_sequence<int, I...>) {
+    (apply_sparse_op<N, S + I>(acc, X, Y, Ws), ...);
+}
+
+__device__ __forceinline__ float f32_of(uint32_t u) { return __builtin_bit_cast(float, u); }
+__device__ __forceinline__ uint32_t u32_of(float f) { return __builtin_bit_cast(uint32_t, f); }
+
+// The class block of class position Q (pn::ClassOrder<N, PZ>::order[Q]) from the staged rows
+// stage (this wavefront's 64 rows), added to acc.  mx: the largest staged magnitude of the
+// lane's cell (reset here).  wa: the coefficient operands [class][K step][hi, lo][lane][8]
+// (FP16 bits), wae: the class exponents e_W.
+template <int N, int PZ, int Q>
+__device__ __forceinline__ void pn_class_block(float (&acc)[pn::nmom(N)], float& mx,
+                                               const float* stage,
+                                               const uint16_t* __restrict__ wa,
+                                               const int32_t* __restrict__ wae, int lane) {
+    using CO = pn::ClassOrder<N, PZ>;
+    constexpr int lc = CO::order[Q];
+    constexpr int n = CO::size[lc];
+    static_assert(n <= 32, "one 32-row block per class");
+    int E = 0;
+    (void)__builtin_frexpf(mx, &E);
+    const int e = (mx > 0.0f && mx < INFINITY) ? 14 - E : 0;
+    mx = 0.0f;
+    // lanes l and l + 32 of half h hold cell 32 h + l % 32
+    const auto es = __builtin_amdgcn_permlane32_swap((uint32_t)e, (uint32_t)e, false, false);
+    const int eh[2] = {(int)es[0], (int)es[1]};
+    const int ew = wae[PZ * 4 + lc];
+    const uint16_t* a = wa + (size_t)(PZ * 4 + lc) * 4 * 2 * kWave * 8;
+    f32x16_pn C[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) C[h][r] = 0.0f;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const f16x8_pn ahi = *reinterpret_cast<const f16x8_pn*>(a + ((s * 2 + 0) * kWave + lane) * 8);
+        const f16x8_pn alo = *reinterpret_cast<const f16x8_pn*>(a + ((s * 2 + 1) * kWave + lane) * 8);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float* row = stage + (32 * h + (lane & 31)) * kPnStageRow + 16 * s + 8 * (lane >> 5);
+            const f32x4 v0 = *reinterpret_cast<const f32x4*>(row);
+            const f32x4 v1 = *reinterpret_cast<const f32x4*>(row + 4);
+            f16x8_pn bhi, blo;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float x = __builtin_ldexpf(i < 4 ? v0[i] : v1[i - 4], eh[h]);
+                const _Float16 xh = (_Float16)x;
+                bhi[i] = xh;
+                blo[i] = (_Float16)(x - (float)xh);
+            }
+            C[h] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, bhi, C[h], 0, 0, 0);
+            C[h] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, blo, C[h], 0, 0, 0);
+            C[h] = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, bhi, C[h], 0, 0, 0);
+        }
+    }
+    // accumulator r of lane l: row (r/4)*8 + (l/32)*4 + r%4, column (cell of the half) l%32
+    for_each_index(
+        [&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            constexpr int i0 = (r / 4) * 8 + (r % 4), i1 = i0 + 4;
+            if constexpr (i0 < n) {
+                constexpr int k0 = CO::at(lc, i0);
+                constexpr int k1 = i1 < n ? CO::at(lc, i1) : 0;
+                const float c0 = __builtin_ldexpf(C[0][r], -(eh[0] + ew));
+                const float c1 = __builtin_ldexpf(C[1][r], -(eh[1] + ew));
+                const auto sw = __builtin_amdgcn_permlane32_swap(u32_of(c0), u32_of(c1), false, false);
+                acc[k0] += f32_of(sw[0]);
+                if constexpr (i1 < n) acc[k1] += f32_of(sw[1]);
+            }
+        },
+        std::make_integer_sequence<int, 16>{});
+}
+
+// The moment loop of one z-parity subsystem in class order, with the load pipeline of
+// pn_fused_moments; the class blocks run after each class's last input.
+template <bool GHOST, int N, int PZ, int MF>
+__device__ __forceinline__ void pn_mfma_moments(float (&acc)[pn::nmom(N)],
+                                                const PnFaces<MF, float>& F,
+                                                __amdgpu_buffer_rsrc_t rs,
+                                                __amdgpu_buffer_rsrc_t ri,
+                                                const uint32_t (&goff)[MF], float gscale,
+                                                uint32_t own, float irho_c, float mdt, float c1,
+                                                float c2, const float* __restrict__ Ws,
+                                                const float* __restrict__ sig, float* stage,
+                                                const uint16_t* __restrict__ wa,
+                                                const int32_t* __restrict__ wae, int lane) {
+    using T = float;
+    using CO = pn::ClassOrder<N, PZ>;
+    constexpr int NS = CO::count;
+    constexpr int D = NS < kPnPrefetch ? NS : (GHOST ? kPnPrefetch / 2 : kPnPrefetch);
+    constexpr int O = 1;
+    constexpr int L = O + (GHOST ? 2 * MF : MF);
+    constexpr uint32_t kPlane = kTile * sizeof(T);
+    auto load_faces = [&](int m, T (&raw)[L]) {
+#pragma unroll
+        for (int f = 0; f < MF; ++f) raw[O + f] = buf_ld<T>(rs, F.off[f], (uint32_t)m * kPlane);
+        if constexpr (GHOST) {
+#pragma unroll
+            for (int f = 0; f < MF; ++f)
+                raw[O + MF + f] = buf_ld<T>(ri, goff[f], (uint32_t)m * (uint32_t)sizeof(T));
+        }
+    };
+    const T oc[4] = {mdt * F.sx * irho_c, mdt * F.sy * irho_c, mdt * F.ax * irho_c,
+                     mdt * F.ay * irho_c};
+    T fc[MF][4], gc[MF][4];
+#pragma unroll
+    for (int f = 0; f < MF; ++f) {
+        fc[f][0] = mdt * F.cx[f];
+        fc[f][1] = mdt * F.cy[f];
+        fc[f][2] = mdt * F.cp[f];
+        fc[f][3] = mdt * F.cq[f];
+        gc[f][0] = mdt * F.nx[f] * gscale;
+        gc[f][1] = mdt * F.ny[f] * gscale;
+        gc[f][2] = -mdt * fabs(F.nx[f]) * gscale;
+        gc[f][3] = -mdt * fabs(F.ny[f]) * gscale;
+    }
+    float* srow = stage + lane * kPnStageRow;
+    T mx = T(0);
+    T ring[D][L];
+    for_each_index(
+        [&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int m = CO::list[i];
+            ring[i][0] = buf_ld<T>(rs, own, (uint32_t)m * kPlane);
+            load_faces(m, ring[i]);
+        },
+        std::make_integer_sequence<int, D>{});
+
+    for_each_index(
+        [&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int m = CO::list[i];
+            T raw[L];
+#pragma unroll
+            for (int r = 0; r < L; ++r) raw[r] = ring[i % D][r];
+            if constexpr (i + D < NS) {
+                constexpr int mn = CO::list[i + D];
+                ring[i % D][0] = buf_ld<T>(rs, own, (uint32_t)mn * kPlane);
+                load_faces(mn, ring[i % D]);
+            }
+            const T uo = raw[0];
+            T X = oc[0] * uo, Y = oc[1] * uo, P = oc[2] * uo, Q = oc[3] * uo;
+#pragma unroll
+            for (int f = 0; f < MF; ++f) {
+                const T v = raw[O + f];
+                X = fma(fc[f][0], v, X);
+                Y = fma(fc[f][1], v, Y);
+                P = fma(fc[f][2], v, P);
+                Q = fma(fc[f][3], v, Q);
+                if constexpr (GHOST) {
+                    const T gv = raw[O + MF + f];
+                    X = fma(gc[f][0], gv, X);
+                    Y = fma(gc[f][1], gv, Y);
+                    P = fma(gc[f][2], gv, P);
+                    Q = fma(gc[f][3], gv, Q);
+                }
+            }
+            acc[m] = fma(fma(c2, sig[m], -c1), uo, acc[m] + uo);
+            constexpr int s = pn::OpTable<N>::start[m];
+            constexpr int e = pn::OpTable<N>::start[m + 1];
+            apply_sparse_ops<N, s>(acc, X, Y, Ws, std::make_integer_sequence<int, e - s>{});
+            // stage P and Q of this input in its class column
+            constexpr int t = CO::local[m];
+            srow[t] = P;
+            srow[32 + t] = Q;
+            mx = fmaxf(mx, fmaxf(fabsf(P), fabsf(Q)));
+            __builtin_amdgcn_sched_barrier(0);
+            // after the last input of class position q: its class block
+            constexpr int q = (i < CO::size[CO::order[0]]) ? 0
+                              : (i < CO::size[CO::order[0]] + CO::size[CO::order[1]]) ? 1
+                              : (i < CO::size[CO::order[0]] + CO::size[CO::order[1]] +
+                                         CO::size[CO::order[2]]) ? 2 : 3;
+            constexpr int endq = CO::size[CO::order[0]] + (q >= 1 ? CO::size[CO::order[1]] : 0) +
+                                 (q >= 2 ? CO::size[CO::order[2]] : 0) +
+                                 (q >= 3 ? CO::size[CO::order[3]] : 0);
+            if constexpr (i + 1 == endq) {
+                pn_class_block<N, PZ, q>(acc, mx, stage, wa, wae, lane);
+                // a smaller next class leaves this class's values in its padding columns:
+                // clear them (the class blocks read all 32 columns of P and of Q)
+                if constexpr (q < 3) {
+                    constexpr int nn = CO::size[CO::order[q + 1]], nc = CO::size[CO::order[q]];
+#pragma unroll
+                    for (int z = nn; z < nc; ++z) {
+                        srow[z] = 0.0f;
+                        srow[32 + z] = 0.0f;
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        },
+        std::make_integer_sequence<int, NS>{});
+}
+
+template <int N, int PZ, int MF>
+__device__ __forceinline__ void pn_mfma_tile(const CellGeom32* __restrict__ geom, int c, bool live,
+                                             const float* __restrict__ Ws,
+                                             const float* __restrict__ sig, const StepArgs32& a,
+                                             const float* __restrict__ u, float* __restrict__ out,
+                                             uint32_t state_bytes, uint32_t inflow_bytes,
+                                             float* stage, const uint16_t* __restrict__ wa,
+                                             const int32_t* __restrict__ wae, int lane) {
+    using T = float;
+    using CO = pn::ClassOrder<N, PZ>;
+    constexpr int NM = pn::nmom(N);
+    constexpr uint32_t kPlane = kTile * sizeof(T);
+    const auto rs = make_rsrc(u, state_bytes);
+    const uint32_t own = tile_off<T>(c, NM);
+    const auto g = geom[c];
+    const T irho_c = a.inv_rho ? a.inv_rho[c] : T(1);
+    PnFaces<MF, T> F;
+    pn_faces<MF>(g, a, c, NM, irho_c, F);
+    const T mdt = -a.dt * g.inv_area;
+    const T c1 = a.dt * a.alpha_t * a.sigma_t[c];
+    const T c2 = a.dt * a.alpha_s * a.sigma_s[c];
+    T acc[NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) acc[k] = T(0);
+    if (__builtin_amdgcn_ballot_w64(F.any_ghost) != 0) {
+        uint32_t goff[MF];
+#pragma unroll
+        for (int f = 0; f < MF; ++f)
+            goff[f] = F.ghost[f] >= 0 ? (uint32_t)F.ghost[f] * NM * (uint32_t)sizeof(T) : kNoGhost;
+        const auto ri = make_rsrc(a.inflow, inflow_bytes);
+        pn_mfma_moments<true, N, PZ, MF>(acc, F, rs, ri, goff, a.inflow_scale, own,
+                                         irho_c, mdt, c1, c2, Ws, sig, stage, wa, wae, lane);
+    } else {
+        const uint32_t goff[MF] = {};
+        pn_mfma_moments<false, N, PZ, MF>(acc, F, rs, rs, goff, 0.0f, own, irho_c, mdt,
+                                          c1, c2, Ws, sig, stage, wa, wae, lane);
+    }
+    if constexpr (PZ == 0) {
+        if (a.source) acc[0] += a.dt * a.source[c] * (T)kSqrt4Pi;
+    }
+    if (!live) return;
+    const auto ro = make_rsrc(out, state_bytes);
+    for_each_index(
+        [&](auto ic) {
+            constexpr int m = CO::list[decltype(ic)::value];
+            buf_st<T>(acc[m], ro, own, m * kPlane);
+        },
+        std::make_integer_sequence<int, CO::count>{});
+}
+
+// Matrix-core step of degree N (FP32 state): two tiles per block, even wavefronts the z-even
+// subsystem, odd ones the z-odd.  Every lane of a wavefront takes part in the matrix products
+// (their operands span the wavefront), so lanes past the last cell run a copy of the last
+// cell and only skip the stores.
+template <int N, int MF>
+__global__ __launch_bounds__(256, 2) void k_pn_mfma(const CellGeom32* __restrict__ geom,
+                                                    int32_t nc, int32_t ntiles,
+                                                    const float* __restrict__ Ws,
+                                                    const float* __restrict__ sig, StepArgs32 a,
+                                                    const float* __restrict__ u,
+                                                    float* __restrict__ out, uint32_t state_bytes,
+                                                    uint32_t inflow_bytes,
+                                                    const uint16_t* __restrict__ wa,
+                                                    const int32_t* __restrict__ wae) {
+    __shared__ __attribute__((aligned(16))) float stage_all[4 * kPnStageWave];
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = (int)(blk * 2 + (threadIdx.x >> 7));
+    if (tile >= ntiles) return;
+    const int wave = (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    float* stage = stage_all + wave * kPnStageWave;
+    float* srow = stage + lane * kPnStageRow;
+#pragma unroll
+    for (int i = 0; i < kPnStageRow; i += 4)
+        *reinterpret_cast<f32x4*>(srow + i) = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int cl = tile * kTile + lane;
+    const bool live = cl < nc;
+    const int c = live ? cl : nc - 1;
+    if ((wave & 1) == 0)
+        pn_mfma_tile<N, 0, MF>(geom, c, live, Ws, sig, a, u, out, state_bytes, inflow_bytes,
+                               stage, wa, wae, lane);
+    else
+        pn_mfma_tile<N, 1, MF>(geom, c, live, Ws, sig, a, u, out, state_bytes, inflow_bytes,
+                               stage, wa, wae, lane);
+}
+
+template <int N, int MF>
+hipError_t launch_mfma_t(const snrt_mesh& m, const snrt_pn& p, const StepArgs32& a,
+                         const float* u, float* out, hipStream_t st) {
+    const int32_t ntiles = (int32_t)((m.nc + kTile - 1) / kTile);
+    const int blocks = (ntiles + 1) / 2;
+    const uint32_t inflow_bytes =
+        a.inflow ? (uint32_t)(m.nbf * (int64_t)p.nm * (int64_t)sizeof(float)) : 0u;
+    hipLaunchKernelGGL((k_pn_mfma<N, MF>), dim3(blocks), dim3(256), 0, st, m.geom32,
+                       (int32_t)m.nc, ntiles, p.wsp32, p.sig32, a, u, out,
+                       state_bytes<float>(m, p.nm), inflow_bytes, p.wa16, p.wae);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 }  // namespace snrt

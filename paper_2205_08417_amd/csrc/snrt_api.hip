@@ -52,6 +52,7 @@ const Tune& tune() {
         }
         if (const char* e = std::getenv("SNRT_GEMM_STAGGER")) r.gemm_stagger = std::atoi(e) != 0;
         if (const char* e = std::getenv("SNRT_GEMM_EPILOGUE")) r.gemm_epilogue = std::atoi(e) != 0;
+        if (const char* e = std::getenv("SNRT_PN_MFMA")) r.pn_mfma = std::atoi(e) != 0;
         return r;
     }();
     return t;

@@ -152,6 +152,12 @@ struct snrt_pn {
     double* w64 = nullptr;
     float* sig32 = nullptr;
     double* sig64 = nullptr;
+    // the matrix-core step of degree pn::kFusedHighDegree: the A_x, A_y coefficients
+    // (pn::SparseOps order), the class blocks' FP16 hi/lo operands [z parity][class][K step]
+    // [hi, lo][lane][8] and their exponents [z parity][class]
+    float* wsp32 = nullptr;
+    uint16_t* wa16 = nullptr;
+    int32_t* wae = nullptr;
 };
 
 struct snrt_scatter {
@@ -166,13 +172,15 @@ namespace snrt {
 // values for MI355X.  SNRT_STEP_TUNE="<step>[,<second-order update>[,<adjoint>]]" overrides
 // the blocks per CU of the three persistent sweeps, SNRT_GEMM_STAGGER=0 turns the staggered
 // chunk order of the product off, SNRT_GEMM_EPILOGUE=0 the IMEX steps in the products'
-// epilogues (separate passes instead; all read once per process).
+// epilogues (separate passes instead), SNRT_PN_MFMA=0 the matrix-core class blocks of the
+// degree-13 P_N step (all read once per process).
 struct Tune {
     int step_blocks_per_cu = 3;
     int flux2_blocks_per_cu = 2;   // its larger per-cell footprint favours a narrower sweep
     int adjoint_blocks_per_cu = 7; // the adjoint's smaller workloads favour a wide grid
     bool gemm_stagger = true;      // staggered split/product phases in the BF16 product
     bool gemm_epilogue = true;     // IMEX per-cell steps in the products' epilogues
+    bool pn_mfma = true;           // matrix-core class blocks in the degree-13 P_N step
 };
 const Tune& tune();
 

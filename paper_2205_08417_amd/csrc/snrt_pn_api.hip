@@ -217,6 +217,9 @@ void snrt_pn_destroy(snrt_pn* p) {
     dev_free(p->w64);
     dev_free(p->sig32);
     dev_free(p->sig64);
+    dev_free(p->wsp32);
+    dev_free(p->wa16);
+    dev_free(p->wae);
     delete p;
 }
 
@@ -265,6 +268,57 @@ snrt_status snrt_pn_create(snrt_pn** out, int32_t degree, const double* sigma_l)
         }
         return tab;
     };
+    // the matrix-core step's tables (degree 13): sparse A_x / A_y coefficients, then per
+    // (z parity, class) the 32 x 64 class block W[i][k] (k < 32: |A_x| on input k of the
+    // class, k >= 32: |A_y| on input k - 32; halved, zero past the class), scaled by 2^e_W
+    // (largest magnitude into [2^13, 2^14)) and split into FP16 hi + lo, in the lane order of
+    // the 32x32x16 products' left operand (lane l: row l % 32, k = 16 s + 8 (l / 32) + [0, 8))
+    std::vector<float> wsp;
+    std::vector<uint16_t> wa16;
+    std::vector<int32_t> wae;
+    if (N == pn::kFusedHighDegree) {
+        constexpr int NH = pn::kFusedHighDegree;
+        using SO = pn::SparseOps<NH>;
+        wsp.assign(SO::count, 0.0f);
+        int idx = 0;
+        pn::visit_ops(N, [&](int m, int k, int kind) {
+            const int si = SO::sidx[idx++];
+            if (si >= 0) wsp[si] = (float)(0.5 * (*mats[kind])[(size_t)k * nm + m]);
+        });
+        wa16.assign((size_t)2 * 4 * 4 * 2 * 64 * 8, 0);
+        wae.assign(8, 0);
+        for (int pz = 0; pz < 2; ++pz)
+            for (int lc = 0; lc < 4; ++lc) {
+                const int n = pz == 0 ? pn::ClassOrder<NH, 0>::size[lc] : pn::ClassOrder<NH, 1>::size[lc];
+                auto at = [&](int t) {
+                    return pz == 0 ? pn::ClassOrder<NH, 0>::at(lc, t) : pn::ClassOrder<NH, 1>::at(lc, t);
+                };
+                std::vector<float> W(32 * 64, 0.0f);
+                float wmax = 0.0f;
+                for (int i = 0; i < n; ++i)
+                    for (int t = 0; t < n; ++t) {
+                        const size_t ki = (size_t)at(i) * nm + at(t);
+                        W[i * 64 + t] = (float)(0.5 * p->ax_abs[ki]);
+                        W[i * 64 + 32 + t] = (float)(0.5 * p->ay_abs[ki]);
+                        wmax = std::max({wmax, std::fabs(W[i * 64 + t]), std::fabs(W[i * 64 + 32 + t])});
+                    }
+                int E = 0;
+                (void)std::frexp(wmax, &E);
+                const int ew = wmax > 0.0f ? 14 - E : 0;
+                wae[pz * 4 + lc] = ew;
+                for (int st = 0; st < 4; ++st)
+                    for (int lane = 0; lane < 64; ++lane)
+                        for (int e = 0; e < 8; ++e) {
+                            const int i = lane % 32, k = 16 * st + 8 * (lane / 32) + e;
+                            const float x = std::ldexp(W[i * 64 + k], ew);
+                            const _Float16 hi = (_Float16)x;
+                            const _Float16 lo = (_Float16)(x - (float)hi);
+                            const size_t base = ((((size_t)(pz * 4 + lc) * 4 + st) * 2) * 64 + lane) * 8 + e;
+                            wa16[base] = __builtin_bit_cast(uint16_t, hi);
+                            wa16[base + 64 * 8] = __builtin_bit_cast(uint16_t, lo);
+                        }
+            }
+    }
     const std::vector<double> t32d = table(pn::has_fused_kernel<float>(N));
     const std::vector<double> tab = table(pn::has_fused_kernel<double>(N));
     std::vector<float> tab32(t32d.begin(), t32d.end());
@@ -281,7 +335,13 @@ snrt_status snrt_pn_create(snrt_pn** out, int32_t degree, const double* sigma_l)
         (s = upload(p->w32, tab32.data(), tab32.size(), "snrt_pn_create: upload")) != SNRT_OK ||
         (s = upload(p->w64, tab.data(), tab.size(), "snrt_pn_create: upload")) != SNRT_OK ||
         (s = upload(p->sig32, sig32.data(), (size_t)nm, "snrt_pn_create: upload")) != SNRT_OK ||
-        (s = upload(p->sig64, p->sig.data(), (size_t)nm, "snrt_pn_create: upload")) != SNRT_OK) {
+        (s = upload(p->sig64, p->sig.data(), (size_t)nm, "snrt_pn_create: upload")) != SNRT_OK ||
+        (s = dev_alloc(&p->wsp32, wsp.size(), "P_N sparse coefficients")) != SNRT_OK ||
+        (s = upload(p->wsp32, wsp.data(), wsp.size(), "snrt_pn_create: upload")) != SNRT_OK ||
+        (s = dev_alloc(&p->wa16, wa16.size(), "P_N class blocks")) != SNRT_OK ||
+        (s = upload(p->wa16, wa16.data(), wa16.size(), "snrt_pn_create: upload")) != SNRT_OK ||
+        (s = dev_alloc(&p->wae, wae.size(), "P_N class exponents")) != SNRT_OK ||
+        (s = upload(p->wae, wae.data(), wae.size(), "snrt_pn_create: upload")) != SNRT_OK) {
         snrt_pn_destroy(p);
         return s;
     }
