@@ -696,7 +696,9 @@ def bench_pn(steps: int, warmup: int, degree: int = 5):
     return {"workload": w["name"], "cells": nc, "moments": nm, "degree": degree,
             "steps": steps, "ms_per_step": ms, "value": nc * nm / (ms * 1e-3),
             "unit": "cell-moment updates/s", "precision": "fp32",
-            "kernel": f"k_pn_fused<{degree},{mf},float>" if degree <= 9 or degree == 13 else
+            "kernel": (f"k_pn_mfma<{degree},{mf}> (class blocks |A_x| P + |A_y| Q as FP16 "
+                       "hi+lo matrix-core products, the rest FP32 vector FMAs)")
+            if degree == 13 else f"k_pn_fused<{degree},{mf},float>" if degree <= 9 else
             f"k_pn_generic<16,{mf},float>",
             "algorithmic_bytes_per_step": alg, "achieved_gbs": achieved,
             "hbm_frac": achieved / HBM_PEAK_GBS, "flops_per_step": flops,
