@@ -189,3 +189,43 @@ def test_pn_errors():
         snrt.snrt_pn_create(31)
     assert ei.value.status == snrt.SNRT_E_ARG
     S.close()
+
+
+def test_pn13_vector_kernel_in_a_fresh_process():
+    """The all-vector degree-13 kernel (SNRT_PN_MFMA=0, read once per process) against the
+    oracle on a triangle and a quadrilateral mesh with ghosts, densities and a source: run in
+    a child process, compared here."""
+    import os
+    import subprocess
+    import sys
+    import tempfile
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cases = {"tri": (I.jittered_delaunay_mesh(14, 0.0, 1.0, seed=72), 87),
+             "quad": (I.quad_grid_mesh(19, 13), 88)}
+    script = (
+        "import sys, numpy as np, torch\n"
+        f"sys.path.insert(0, {root!r}); sys.path.insert(0, {os.path.join(root, 'tests')!r})\n"
+        "from paper_2205_08417_amd import inputs as I\n"
+        "import test_gpu_pn as T\n"
+        "name, out = sys.argv[1], sys.argv[2]\n"
+        "mesh = I.jittered_delaunay_mesh(14, 0.0, 1.0, seed=72) if name == 'tri' "
+        "else I.quad_grid_mesh(19, 13)\n"
+        "seed = 87 if name == 'tri' else 88\n"
+        "d = T._case(mesh, 13, seed=seed, rho=True, source=True, ghost=True, "
+        "sigma_l=I.hg_legendre_moments(0.7, 13))\n"
+        "np.save(out, T._run(d, 6, torch.float32))\n")
+    env = dict(os.environ, SNRT_PN_MFMA="0")
+    for name, (mesh, seed) in cases.items():
+        with tempfile.TemporaryDirectory() as tmp:
+            out = os.path.join(tmp, "u.npy")
+            print(f"child: P13 vector kernel, {name} mesh", flush=True)
+            r = subprocess.run([sys.executable, "-c", script, name, out], env=env,
+                               capture_output=True, text=True, timeout=300)
+            assert r.returncode == 0, r.stderr[-2000:]
+            got = np.load(out)
+        d = _case(mesh, 13, seed=seed, rho=True, source=True, ghost=True,
+                  sigma_l=I.hg_legendre_moments(0.7, 13))
+        _, _, ref = _oracle(d, 6)
+        err = rel_l2(got, ref)
+        print(f"P13 vector kernel {name}: {err:.2e}")
+        assert err <= 1e-5
