@@ -63,8 +63,7 @@ __device__ __forceinline__ void for_each_phi(const float* __restrict__ psi,
         if (cn < nc) rp.load(psi, cn, nxt);
         visit(c, rp.sum(cur));
         if (cn >= nc) break;
-#pragma unroll
-        for (int k = 0; k < V; ++k) cur[k] = nxt[k];
+        __builtin_memcpy(cur, nxt, sizeof(cur));
         c = cn;
     }
 }

@@ -480,7 +480,7 @@ __device__ __forceinline__ void step_sweep(
     cx.neumann = a.neumann != 0;
     cx.dpart = dpart;
     // prefetches address the clamped item min(i', xend-1) in [xbeg, xend): always in bounds
-    auto clampc = [xend, sh](int32_t cc) {
+    auto clampc = [&](int32_t cc) {
         return uniform_cell((cc < xend ? cc : xend - 1) >> sh);
     };
 
