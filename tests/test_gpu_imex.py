@@ -427,3 +427,53 @@ def test_imex_moments_neumann_boundary():
         print(f"imex moments neumann fp64={fp64}: {err:.2e}")
         assert err <= tol
     S.close()
+
+
+def test_imex_separate_passes_in_a_fresh_process():
+    """SNRT_GEMM_EPILOGUE=0 (read once per process) runs the per-cell diagonal and the final
+    combine of the mode-space IMEX solve as separate passes instead of in the products'
+    epilogues: the moment form and the dense kernel, BF16 hi+lo, in a child process, against
+    the oracle here."""
+    import os
+    import subprocess
+    import sys
+    import tempfile
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    script = (
+        "import sys, numpy as np, torch, dataclasses\n"
+        f"sys.path.insert(0, {root!r}); sys.path.insert(0, {os.path.join(root, 'tests')!r})\n"
+        "from paper_2205_08417_amd import inputs as I\n"
+        "import test_gpu_imex as T\n"
+        "kind, out = sys.argv[1], sys.argv[2]\n"
+        "if kind == 'moments':\n"
+        "    P = T._moment_problem(8, 8, 93, 30.0, rho=True, source=True, inflow=True)\n"
+        "    S = T._solver(P, precision='bf16x3', moments=I.hg_legendre_moments(0.8, 3))\n"
+        "else:\n"
+        "    P = T._dense_problem(8, 8, 0.8, 94, 30.0, rho=True, source=True, inflow=True)\n"
+        "    S = T._solver(P, precision='bf16x3')\n"
+        "psi, _ = S.rollout(S.initial_state(), 5, imex=True)\n"
+        "np.save(out, S.to_user(psi).cpu().numpy())\n")
+    env = dict(os.environ, SNRT_GEMM_EPILOGUE="0")
+    from oracle import moments as mo
+    from oracle import oracle as o
+    for kind in ("moments", "dense"):
+        with tempfile.TemporaryDirectory() as tmp:
+            out = os.path.join(tmp, "psi.npy")
+            print(f"child: separate IMEX passes, {kind}", flush=True)
+            r = subprocess.run([sys.executable, "-c", script, kind, out], env=env,
+                               capture_output=True, text=True, timeout=300)
+            assert r.returncode == 0, r.stderr[-2000:]
+            got = np.load(out)
+        if kind == "moments":
+            P = _moment_problem(8, 8, 93, 30.0, rho=True, source=True, inflow=True)
+            op = o.OracleProblem.from_problem(
+                P, K=mo.moment_kernel(P.omega, P.w, I.hg_legendre_moments(0.8, 3)))
+        else:
+            P = _dense_problem(8, 8, 0.8, 94, 30.0, rho=True, source=True, inflow=True)
+            op = o.OracleProblem.from_problem(P)
+        ref = P.psi0
+        for _ in range(5):
+            ref = o.step_imex(op, ref, P.dt)
+        err = rel_l2(got, ref)
+        print(f"separate IMEX passes {kind}: {err:.2e}")
+        assert err <= 1e-4
