@@ -158,6 +158,16 @@ void snrt_scatter_destroy(snrt_scatter* scatter);
  * isotropic and moment-form handles. */
 snrt_status snrt_scatter_prepare_implicit(snrt_scatter* scatter);
 
+/* The host computation behind snrt_scatter_prepare_implicit, without a device: for
+ * A [n][n] (host, row-major, A[q][p] = K[q][p] w_p) it returns the eigenvalues lam [n] and
+ * the two operands of the mode-space solve, x0 [n][n] with x0[q][j] = V^-1[j][q] and
+ * x1 [n][n] with x1[j][q] = lam_j V[q][j], where A = V diag(lam) V^-1 (all host, FP64,
+ * caller-allocated).  resid (may be NULL) receives the probe residual.  Errors as for
+ * snrt_scatter_prepare_implicit (SNRT_E_UNSUPPORTED when A is not diagonally similar to a
+ * symmetric matrix); SNRT_E_ARG for NULL arrays or n < 1. */
+snrt_status snrt_kernel_modes(int32_t n, const double* A, double* lam, double* x0, double* x1,
+                              double* resid);
+
 /* Bytes of device workspace that serve every step entry point for this combination:
  * snrt_step / snrt_step_adjoint (FP32 and FP64) need one [ncells][nq] buffer for a dense
  * kernel, plus [ncells][moments, padded] for the moment form, and none for isotropic

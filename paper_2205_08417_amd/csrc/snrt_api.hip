@@ -642,7 +642,7 @@ snrt_status snrt_scatter_prepare_implicit(snrt_scatter* sc) {
         for (int32_t q = 0; q < n; ++q) A[(size_t)q * n + p] = X[(size_t)p * n + q];
     std::vector<double> lam, x0, x1;
     double resid = 0.0;
-    SNRT_TRY(implicit_form(n, A, lam, x0, x1, &resid));
+    SNRT_TRY(implicit_form(n, A, lam, x0, x1, &resid, "snrt_scatter_prepare_implicit"));
     std::vector<float> lam32(lam.begin(), lam.end());
     snrt_status s = SNRT_OK;
     if ((s = dev_alloc(&B.lam32, (size_t)n, "implicit eigenvalues")) != SNRT_OK ||

@@ -157,8 +157,8 @@ bool tridiagonal_qr(int n, std::vector<double>& d, std::vector<double>& e,
 }  // namespace
 
 snrt_status implicit_form(int n, const std::vector<double>& A, std::vector<double>& lam,
-                          std::vector<double>& x0, std::vector<double>& x1, double* resid) {
-    const char* fn = "snrt_scatter_prepare_implicit";
+                          std::vector<double>& x0, std::vector<double>& x1, double* resid,
+                          const char* fn) {
     // positive r with diag(r) A symmetric: r_p = r_q A[q][p] / A[p][q] along the nonzero
     // pattern, one root per connected component
     std::vector<double> r(n, 0.0);
@@ -256,3 +256,27 @@ snrt_status implicit_form(int n, const std::vector<double>& A, std::vector<doubl
 }
 
 }  // namespace snrt
+
+extern "C" snrt_status snrt_kernel_modes(int32_t n, const double* A, double* lam, double* x0,
+                                         double* x1, double* resid) {
+    snrt::set_error("");
+    if (n < 1 || !A || !lam || !x0 || !x1) {
+        snrt::set_error("snrt_kernel_modes: NULL array or n < 1");
+        return SNRT_E_ARG;
+    }
+    const size_t n2 = (size_t)n * n;
+    for (size_t i = 0; i < n2; ++i)
+        if (!std::isfinite(A[i])) {
+            snrt::set_error("snrt_kernel_modes: non-finite entry");
+            return SNRT_E_ARG;
+        }
+    std::vector<double> a(A, A + n2), l, v0, v1;
+    double r = 0.0;
+    const snrt_status s = snrt::implicit_form(n, a, l, v0, v1, &r, "snrt_kernel_modes");
+    if (resid) *resid = r;
+    if (s != SNRT_OK) return s;
+    std::copy(l.begin(), l.end(), lam);
+    std::copy(v0.begin(), v0.end(), x0);
+    std::copy(v1.begin(), v1.end(), x1);
+    return SNRT_OK;
+}

@@ -102,7 +102,8 @@ struct DenseB {
 // SNRT_E_UNSUPPORTED (with the reason set) when A is not diagonally similar to a symmetric
 // matrix or the decomposition fails its residual check.
 snrt_status implicit_form(int n, const std::vector<double>& A, std::vector<double>& lam,
-                          std::vector<double>& x0, std::vector<double>& x1, double* resid);
+                          std::vector<double>& x0, std::vector<double>& x1, double* resid,
+                          const char* fn);  // fn: the entry point named in error messages
 
 }  // namespace snrt
 

@@ -55,7 +55,7 @@ EXPORTS = [
     "snrt_stream_copy", "snrt_step_imex_moments", "snrt_step_imex_moments_f64",
     "snrt_rollout", "snrt_rollout_f64", "snrt_rollout_adjoint", "snrt_rollout_adjoint_f64",
     "snrt_step_dose_noalloc", "snrt_scatter_prepare_implicit", "snrt_step_imex_dense",
-    "snrt_step_imex_dense_f64",
+    "snrt_step_imex_dense_f64", "snrt_kernel_modes",
 ]
 
 
@@ -168,6 +168,7 @@ def lib() -> ctypes.CDLL:
         "snrt_scatter_moments": (_st, [ctypes.POINTER(_vp), _vp, ctypes.c_int32, _dp,
                                        ctypes.c_int]),
         "snrt_scatter_prepare_implicit": (_st, [_vp]),
+        "snrt_kernel_modes": (_st, [ctypes.c_int32, _dp, _dp, _dp, _dp, _dp]),
         "snrt_step_imex_dense": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp,
                                        _vp, ctypes.c_size_t, _vp]),
         "snrt_step_imex_dense_f64": (_st, [_vp, _vp, _vp, ctypes.POINTER(StepArgs), _vp, _vp,
@@ -575,6 +576,21 @@ def snrt_rollout_adjoint_f64(mesh, quad, scatter, args: StepArgs, sched: Optiona
 
 
 # ------------------------------------------------------------------------------ P_N solver
+
+def snrt_kernel_modes(A):
+    """Host-only: (lam, x0, x1, resid) of A = K W (see include/snrt.h)."""
+    a = np.ascontiguousarray(A, dtype=np.float64)
+    n = a.shape[0]
+    lam = np.zeros(n)
+    x0 = np.zeros((n, n))
+    x1 = np.zeros((n, n))
+    r = ctypes.c_double()
+    _check("snrt_kernel_modes",
+           lib().snrt_kernel_modes(int(n), a.ctypes.data_as(_dp), lam.ctypes.data_as(_dp),
+                                   x0.ctypes.data_as(_dp), x1.ctypes.data_as(_dp),
+                                   ctypes.byref(r)))
+    return lam, x0, x1, float(r.value)
+
 
 def snrt_pn_operators(degree: int):
     """Host-only: (A_x, A_y, |A_x|, |A_y|) of degree ``degree`` as [nm][nm] FP64 arrays."""
