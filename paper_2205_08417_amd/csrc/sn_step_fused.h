@@ -1,0 +1,286 @@
+// The explicit dense S_N step in one launch: the scattering product's block tiles run the
+// transport update on their own cells and ordinates (kernel templates; instantiated by
+// sn_step_fused.hip and sn_step_fused_rho.hip).
+//
+// The explicit step of Sec. 4.2 with dense scattering (eq. SNEqns) needs the scattering
+// source S = Psi B only at the cell and ordinate it updates.  When a block of the product
+// finishes its K loop, its accumulators hold S for a tile of cells x ordinates.  Instead of
+// writing the tile out for a second kernel to read back, the block stages it in LDS (the K
+// loop's operand planes are free by then) and updates those cells and ordinates itself:
+// the own row, the neighbour rows, the boundary ghosts and the cell records come from
+// memory as in the step kernel, S from LDS, and the new rows go to psi_out.  The update
+// arithmetic is the step kernel's own (fwd_load_stage / fwd_compute) on the same operand
+// values, so the result equals the two-launch step bit for bit; the S round trip through
+// memory (write and read of M x nq floats) disappears.
+//
+// A tile of 256 cells x 256 ordinates needs 256 KB of FP32 S, twice the LDS the block holds,
+// so it runs as two slabs of 256 cells x 128 ordinates: slab s holds, of every wave's two
+// 32-column accumulator blocks, block s.  Each wave writes the accumulators of the slab
+// (half of its own), then all eight waves update the slab's cells, one cell per wave at a
+// time with the step kernel's load pipeline (neighbour lists two cells ahead, rows one cell
+// ahead); only half of the accumulators stay live meanwhile.  Lane l owns V = slab width / 64
+// consecutive ordinates of the slab; the update is elementwise in the ordinate, so which
+// lane owns which ordinate does not change the result.  The LDS rows are stored with their
+// 128-byte halves swapped on every other group of 4 rows, so the accumulator writes of the
+// two half-waves (rows r and r + 4) fall on different banks.
+#pragma once
+
+#include "sn_gemm_core.h"
+#include "sn_step_kernels.h"
+
+namespace snrt {
+namespace fused {
+
+constexpr int kSlabFloats = 32768;   // 128 KB of LDS for the S slab
+
+__device__ __forceinline__ int slab_swz(int row) { return ((row >> 2) & 1) << 5; }
+
+template <int P, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (P < N) {
+        f(std::integral_constant<int, P>{});
+        static_for<P + 1, N>(f);
+    }
+}
+
+constexpr int kAhead = 2;            // cells whose rows are in flight ahead of the update
+
+// The update of one block tile: acc holds S for rows m0 + [0, BM) of a sub-product whose
+// row 0 is cell row0 (M rows in all), columns n0 + [0, BN); exp_of undoes the FP16 row
+// scaling.
+template <int BM, int BN, bool RHO, int D, int IM, int JN, typename Acc, typename ExpOf>
+__device__ __forceinline__ void step_tile(Acc (&acc)[IM][JN], const gemm::TileInfo& t,
+                                          int64_t row0, int64_t M, ExpOf exp_of,
+                                          float* __restrict__ sl, const StepEpi& se)
+{
+    constexpr int NS = BM * BN <= kSlabFloats ? 1 : 2;      // column slabs
+    constexpr int W = BN / NS;                              // slab width
+    constexpr int JS = JN / NS;                             // accumulator blocks per slab
+    constexpr int V = W / 64;                               // ordinates per lane
+    static_assert(BM * W <= kSlabFloats && JN % NS == 0 && W >= 64, "slab shape");
+    constexpr int MF = 3;
+    const int lane = t.lane;
+    const int wave = __builtin_amdgcn_readfirstlane(t.wave);
+    const int w4 = wave & 3;                                // the wave's column group
+    const int64_t trows = M - t.m0 < BM ? M - t.m0 : BM;    // rows of this tile (> 0)
+    const int nrow = (int)trows;
+
+    FwdCtx<float> cx;
+    cx.row_bytes = (uint32_t)se.nq * (uint32_t)sizeof(float);
+    const uint32_t state_bytes = (uint32_t)se.nc * cx.row_bytes;
+    cx.psi = make_rsrc(se.psi_in, state_bytes);
+    cx.out = make_rsrc(se.psi_out, state_bytes);
+    cx.inflow = make_rsrc(se.a.inflow ? se.a.inflow : se.psi_in,
+                          se.a.inflow ? se.nbf * cx.row_bytes : 0u);
+    cx.S = make_rsrc(se.psi_in, 0u);                           // S comes from LDS
+    cx.src_arr = se.a.source ? se.a.source : se.a.sigma_t;
+    cx.src_mul = se.a.source ? se.a.dt : 0.0f;
+    cx.inflow_scale = se.a.inflow_scale;
+    cx.dirichlet = se.a.inflow != nullptr && !se.a.neumann;
+    cx.neumann = se.a.neumann != 0;
+    cx.dpart = nullptr;
+    const uint32_t cb = (uint32_t)t.n0 * (uint32_t)sizeof(float);
+    const int64_t base = row0 + t.m0;
+    // loads run ahead on clamped rows (always in the tile); only rows < nrow are stored
+    auto cell = [&](int k) { return uniform_cell((int32_t)(base + (k < nrow ? k : nrow - 1))); };
+
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        __syncthreads();              // the K loop's planes, or the previous slab, are done
+        // this wave's blocks of the slab: j = jj * NS + s, at slab column (w4 * JS + jj) * 32
+#pragma unroll
+        for (int i = 0; i < IM; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int lr = t.wm + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                const int e = exp_of(t.m0 + lr);
+#pragma unroll
+                for (int jj = 0; jj < JS; ++jj) {
+                    const int j = jj * NS + s;
+                    const int lc = (w4 * JS + jj) * 32 + (lane & 31);
+                    const float v = e != 0 ? __builtin_ldexpf(acc[i][j][r], e) : acc[i][j][r];
+                    sl[lr * W + (lc ^ slab_swz(lr))] = v;
+                }
+            }
+        __syncthreads();
+        if (wave >= nrow) continue;
+        // lane l: slab columns [V l, V l + V), block b = V l / 32 of the slab order, i.e.
+        // tile columns (b / JS) * BN/4 + 32 ((b % JS) NS + s) + (V l) % 32 + [0, V)
+        const int e0 = lane * V;
+        const int blk = e0 >> 5;
+        const int q0 = (blk / JS) * (BN / 4) + 32 * ((blk % JS) * NS + s) + (e0 & 31);
+        float ox[V], oy[V], wi[V];
+        load_slice<V, true>(se.tab, t.n0 + q0, se.nq, ox);
+        load_slice<V, true>(se.tab + se.nq, t.n0 + q0, se.nq, oy);
+#pragma unroll
+        for (int k = 0; k < V; ++k) wi[k] = 0.0f;              // unused by the dense update
+        auto src_of = [&](FwdStage<V, MF, true, float>& d, int k) {
+            const float* p = sl + k * W + (e0 ^ slab_swz(k));
+#pragma unroll
+            for (int v = 0; v < V; ++v) d.src[v] = p[v];
+        };
+        // The wave's cells of the slab are k = wave + 8 n, n < U <= 32.  Everything a cell's
+        // update needs besides its rows (neighbours, normals, ghost scales, coefficients) is
+        // loaded up front, cell n in lane n, and read back with readlane: the loop then holds
+        // no scalar loads, whose wait would also cover the LDS read of S, and the row loads of
+        // a cell depend on no other load.  The rows run D cells ahead of the update, through
+        // D + 1 stage slots (cell n in slot n % (D + 1)).  The values are formed exactly as
+        // fwd_load_stage forms them.
+        const int U = (nrow - wave + 7) / 8;
+        int32_t lj[MF];
+        float lg[MF], lnx[MF], lny[MF];
+        float lirho, lcabs, lcflux, lcscat, lsrcv;
+        {
+            const int kk = wave + 8 * (lane < 32 ? lane : 31);
+            const int32_t c = (int32_t)(base + (kk < nrow ? kk : nrow - 1));
+            const CellGeom32* g = se.geom + c;
+            lirho = RHO ? se.a.inv_rho[c] : 1.0f;
+            const float bscale = cx.dirichlet ? cx.inflow_scale : (cx.neumann ? lirho : 0.0f);
+#pragma unroll
+            for (int f = 0; f < MF; ++f) {
+                const int32_t j = g->nbr[f];
+                const bool bnd = j < 0;
+                lj[f] = j;
+                const float rho_j = RHO ? se.a.inv_rho[bnd ? c : j] : 1.0f;
+                lg[f] = bnd ? bscale : rho_j;
+                lnx[f] = g->n[f][0];
+                lny[f] = g->n[f][1];
+            }
+            lcabs = se.a.dt * se.a.alpha_t * se.a.sigma_t[c];
+            lcflux = se.a.dt * g->inv_area;
+            lcscat = se.a.dt * se.a.alpha_s * se.a.sigma_s[c];
+            lsrcv = cx.src_arr[c];
+        }
+        auto rl = [](float v, int l) {
+            return __builtin_bit_cast(float,
+                                      __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+        };
+        FwdStage<V, MF, true, float> st[D + 1];
+        // prefetches past the wave's last cell take lane min(n, 31), some cell of the tile:
+        // in bounds, and never updated
+        auto fetch = [&](auto slot_c, int n) {
+            constexpr int SL = decltype(slot_c)::value;
+            FwdStage<V, MF, true, float>& d = st[SL];
+            const int ln = n < 31 ? n : 31;
+            const int32_t c = cell(wave + 8 * n);
+            buf_load_row<V, true, float>(cx.psi, (uint32_t)c * cx.row_bytes + cb, q0, se.nq,
+                                         d.p);
+#pragma unroll
+            for (int f = 0; f < MF; ++f) {
+                const int32_t j = __builtin_amdgcn_readlane(lj[f], ln);
+                const bool bnd = j < 0;
+                const int32_t bidx = cx.dirichlet ? -1 - j : c;
+                const uint32_t off = (uint32_t)(bnd ? bidx : j) * cx.row_bytes + cb;
+                buf_load_row<V, true, float>(bnd && cx.dirichlet ? cx.inflow : cx.psi, off, q0,
+                                             se.nq, d.up[f]);
+            }
+        };
+        // the scalars of cell n (n < U) into its slot, just before its update
+        auto scalars = [&](FwdStage<V, MF, true, float>& d, int n) {
+#pragma unroll
+            for (int f = 0; f < MF; ++f) {
+                d.ghost[f] = rl(lg[f], n);
+                d.nx[f] = rl(lnx[f], n);
+                d.ny[f] = rl(lny[f], n);
+            }
+            d.irho = rl(lirho, n);
+            d.cabs = rl(lcabs, n);
+            d.cflux = rl(lcflux, n);
+            d.cscat = rl(lcscat, n);
+            d.srcv = rl(lsrcv, n);
+        };
+        auto update = [&](auto slot_c, int n) {
+            constexpr int SL = decltype(slot_c)::value;
+            const int k = wave + 8 * n;
+            scalars(st[SL], n);
+            src_of(st[SL], k);
+            fwd_compute<V, true, MF, RHO, true, float>(st[SL], ox, oy, wi, cell(k), cb, se.nq,
+                                                       q0, cx);
+        };
+        static_for<0, D>([&](auto d_c) { fetch(d_c, decltype(d_c)::value); });
+        for (int n = 0; n < U; n += D + 1) {
+            static_for<0, D + 1>([&](auto p_c) {
+                constexpr int P = decltype(p_c)::value;
+                if (n + P < U) {
+                    fetch(std::integral_constant<int, (P + D) % (D + 1)>{}, n + P + D);
+                    update(p_c, n + P);
+                }
+            });
+        }
+    }
+}
+
+// Blocks [0, nmain) are 256 x 256 tiles of the first M1 rows, blocks [nmain, grid) TM x TN
+// tiles of the rest (the block order and last-round policy of the plain product).
+template <bool F16, int P, int TM, int TN, bool STAGGER, bool RHO>
+__global__ __launch_bounds__(gemm::kThreads) void k_gemm_step(
+    const float* __restrict__ A, const uint16_t* __restrict__ Bhi,
+    const uint16_t* __restrict__ Blo, int64_t M1, int64_t M, int32_t K, int32_t N,
+    const int32_t* __restrict__ rexp, int32_t eb, int64_t nmain, StepEpi se)
+{
+    constexpr int NP = P == 3 ? 4 : P == 2 ? 3 : 2;
+    constexpr int kPlanes = 2 * NP * gemm::kPlane;
+    constexpr int kU16 = kPlanes > 2 * kSlabFloats ? kPlanes : 2 * kSlabFloats;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[kU16];
+    float* sl = reinterpret_cast<float*>(lds);
+    const int64_t b = blockIdx.x;
+    if (b < nmain) {
+        gemm::gemm_block<P, 256, 256, 1, STAGGER, F16>(
+            A, Bhi, Blo, M1, K, N, rexp, eb, xcd_remap(b, nmain), lds,
+            [&](auto& acc, const gemm::TileInfo& t, auto, auto exp_of) {
+                step_tile<256, 256, RHO, kAhead>(acc, t, 0, M1, exp_of, sl, se);
+            });
+    } else {
+        const int64_t nt = (int64_t)gridDim.x - nmain;
+        gemm::gemm_block<P, TM, TN, 4, STAGGER, F16>(
+            A + M1 * K, Bhi, Blo, M - M1, K, N, F16 ? rexp + M1 : rexp, eb,
+            xcd_remap(b - nmain, nt), lds,
+            [&](auto& acc, const gemm::TileInfo& t, auto, auto exp_of) {
+                step_tile<TM, TN, RHO, kAhead>(acc, t, M1, M - M1, exp_of, sl, se);
+            });
+    }
+}
+
+template <bool RHO>
+hipError_t launch_gemm_step_t(const float* A, const uint16_t* Bhi, const uint16_t* Blo,
+                              int64_t M, int32_t K, int32_t N, int products,
+                              const int32_t* rexp, int32_t eb, const StepEpi& se,
+                              hipStream_t st)
+{
+    if (M == 0) return hipSuccess;
+    if (products < 0 || products > 3) return hipErrorInvalidValue;
+    if (K % 32 != 0 || K == 0 || N % 256 != 0 || N != se.nq || M != se.nc ||
+        (products == 0 && !rexp))
+        return hipErrorNotSupported;
+    const GemmPlan p = gemm_plan(M, N);
+    if (p.mbn != 256) return hipErrorNotSupported;
+    const int64_t nmain = ((p.rows1 + 255) / 256) * (N / 256);
+    const int64_t ntail = ((M - p.rows1 + p.tm - 1) / p.tm) * (N / p.tn);
+    const dim3 grid((unsigned)(nmain + ntail));
+    const bool stagger = tune().gemm_stagger && K >= 256 && N >= 256;
+    auto go = [&](auto p_c, auto tn_c, auto sg_c) {
+        constexpr int PP = decltype(p_c)::value;
+        constexpr int TN = decltype(tn_c)::value;
+        constexpr bool SG = decltype(sg_c)::value;
+        hipLaunchKernelGGL((k_gemm_step<PP == 0, PP == 0 ? 3 : PP, 64, TN, SG, RHO>), grid,
+                           dim3(gemm::kThreads), 0, st, A, Bhi, Blo, p.rows1, M, K, N, rexp, eb,
+                           nmain, se);
+        return hipGetLastError();
+    };
+    auto by_tn = [&](auto p_c, auto sg_c) {
+        return p.tn == 128 ? go(p_c, std::integral_constant<int, 128>{}, sg_c)
+                           : go(p_c, std::integral_constant<int, 256>{}, sg_c);
+    };
+    auto by_sg = [&](auto p_c) {
+        return stagger ? by_tn(p_c, std::true_type{}) : by_tn(p_c, std::false_type{});
+    };
+    switch (products) {
+        case 0: return by_sg(std::integral_constant<int, 0>{});
+        case 3: return by_sg(std::integral_constant<int, 3>{});
+        case 2: return by_sg(std::integral_constant<int, 2>{});
+        default: return by_sg(std::integral_constant<int, 1>{});
+    }
+}
+
+}  // namespace fused
+}  // namespace snrt

@@ -272,6 +272,14 @@ __device__ __forceinline__ int32_t uniform_cell(int32_t c) {
     return __builtin_amdgcn_readfirstlane(c);
 }
 
+template <typename T>
+__device__ __forceinline__ T fma_t(T a, T b, T c) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_fmaf(a, b, c);
+    else
+        return __builtin_fma(a, b, c);
+}
+
 template <int MF>
 struct NbrList {
     int32_t j[MF];
@@ -284,7 +292,7 @@ struct FwdStage {
     T src[V];
     T ghost[MF];
     T nx[MF], ny[MF];
-    T irho, cabs, cflux, cscat, csrc;   // cabs = dt alpha_t sigma_t
+    T irho, cabs, cflux, cscat, srcv;   // cabs = dt alpha_t sigma_t; srcv: the cell's source
 };
 
 // Buffer resources and scalars of one launch.
@@ -308,8 +316,10 @@ __device__ __forceinline__ void fwd_load_nbr(NbrList<MF>& nb,
     for (int f = 0; f < MF; ++f) nb.j[f] = g->nbr[f];
 }
 
+// LOAD_S: read the scattering source row of a dense step from x.S (a caller that holds the
+// source elsewhere fills d.src itself).
 template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T, int LA_OWN = kAuxDefault,
-          int LA_NBR = kAuxDefault>
+          int LA_NBR = kAuxDefault, bool LOAD_S = DENSE>
 __device__ __forceinline__ void fwd_load_stage(FwdStage<V, MF, DENSE, T>& d, const NbrList<MF>& nb,
                                                const typename GeomOf<T>::type* __restrict__ geom,
                                                int32_t c, uint32_t cb, int32_t nq, int q0,
@@ -336,12 +346,12 @@ __device__ __forceinline__ void fwd_load_stage(FwdStage<V, MF, DENSE, T>& d, con
         d.nx[f] = g->n[f][0];
         d.ny[f] = g->n[f][1];
     }
-    if constexpr (DENSE) buf_load_row<V, EXACT, T, kAuxStream>(x.S, own, q0, nq, d.src);
+    if constexpr (DENSE && LOAD_S) buf_load_row<V, EXACT, T, kAuxStream>(x.S, own, q0, nq, d.src);
     const T st_c = cell_val(a.sigma_t, c);
     d.cabs = a.dt * a.alpha_t * st_c;
     d.cflux = a.dt * g->inv_area;
     d.cscat = a.dt * a.alpha_s * cell_val(a.sigma_s, c);
-    d.csrc = x.src_mul * cell_val(x.src_arr, c);
+    d.srcv = cell_val(x.src_arr, c);
 }
 
 template <int V, bool EXACT, int MF, bool RHO, bool DENSE, typename T, int SA = kAuxStream,
@@ -384,7 +394,7 @@ __device__ __forceinline__ void fwd_compute(const FwdStage<V, MF, DENSE, T>& d, 
         T part = T(0);
 #pragma unroll
         for (int k = 0; k < V; ++k) {
-            b[k] = d.p[k] - d.cflux * acc[k] + d.csrc;
+            b[k] = d.p[k] - d.cflux * acc[k] + x.src_mul * d.srcv;
             part += wi[k] * b[k];
         }
         const T B = cell_sum(part);
@@ -417,19 +427,41 @@ __device__ __forceinline__ void fwd_compute(const FwdStage<V, MF, DENSE, T>& d, 
         u[k] = RHO ? d.p[k] * d.irho : d.p[k];
         acc[k] = T(0);
     }
+    T o[V];
+    if constexpr (DENSE) {
+        // Dense scattering: every rounding step spelled out as an explicit FMA.  The compiler
+        // contracts a product into a sum only when both sit in one basic block, which depends
+        // on the caller's loop structure; written out, the step kernel and the product tiles
+        // of the one-launch dense step (which inline this update in different loops) compute
+        // the same bits.  The forms are the ones the compiler picks for the step kernel.
 #pragma unroll
-    for (int f = 0; f < MF; ++f) {
+        for (int f = 0; f < MF; ++f) {
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const T s = fma_t(d.nx[f], ox[k], d.ny[f] * oy[k]);
+                acc[k] = fma_t(s, s > T(0) ? u[k] : d.up[f][k] * d.ghost[f], acc[k]);
+            }
+        }
 #pragma unroll
         for (int k = 0; k < V; ++k) {
-            const T s = ox[k] * d.nx[f] + oy[k] * d.ny[f];
-            const T ub = d.up[f][k] * d.ghost[f];
-            acc[k] += (s > T(0)) ? s * u[k] : s * ub;
+            const T v = fma_t(-d.cflux, acc[k], fma_t(-d.p[k], d.cabs, d.p[k]));
+            o[k] = fma_t(x.src_mul, d.srcv, fma_t(d.cscat, src[k], v));
         }
-    }
-    T o[V];
+    } else {
 #pragma unroll
-    for (int k = 0; k < V; ++k)
-        o[k] = (d.p[k] - d.cabs * d.p[k]) - d.cflux * acc[k] + d.cscat * src[k] + d.csrc;
+        for (int f = 0; f < MF; ++f) {
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const T s = ox[k] * d.nx[f] + oy[k] * d.ny[f];
+                const T ub = d.up[f][k] * d.ghost[f];
+                acc[k] += (s > T(0)) ? s * u[k] : s * ub;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            o[k] = (d.p[k] - d.cabs * d.p[k]) - d.cflux * acc[k] + d.cscat * src[k] +
+                   x.src_mul * d.srcv;
+    }
     buf_store_row<V, EXACT, T, SA>(x.out, (uint32_t)c * x.row_bytes + cb, q0, nq, o);
 }
 

@@ -53,6 +53,7 @@ const Tune& tune() {
         if (const char* e = std::getenv("SNRT_GEMM_STAGGER")) r.gemm_stagger = std::atoi(e) != 0;
         if (const char* e = std::getenv("SNRT_GEMM_EPILOGUE")) r.gemm_epilogue = std::atoi(e) != 0;
         if (const char* e = std::getenv("SNRT_PN_MFMA")) r.pn_mfma = std::atoi(e) != 0;
+        if (const char* e = std::getenv("SNRT_STEP_FUSED")) r.step_fused = std::atoi(e) != 0;
         return r;
     }();
     return t;
@@ -846,6 +847,41 @@ hipError_t scatter_product32(const snrt_scatter* sc, const float* A, float* C, i
     return e;
 }
 
+// Whether the explicit dense step runs as one launch (the product's last factor with the
+// transport update in its epilogue): low-precision products, triangles, nq % 256 == 0.
+bool step_fusable(const snrt_mesh& m, const snrt_quad& q, const DenseB& B) {
+    if (!tune().step_fused || B.precision == SNRT_FP32 || m.mf != 3 || q.nq % 256 != 0)
+        return false;
+    const GemmOperand& last = B.fwd[B.chain - 1];
+    return last.N == q.nq && last.Np == q.nq && last.K % 32 == 0 && last.hi != nullptr;
+}
+
+// The fused dense step: the moment form first writes the moments to after_S (as the
+// two-launch step does); the FP16 mode writes the row exponents of the last product's left
+// operand, then one launch forms S tile by tile and updates psi_out from it.
+hipError_t fused_dense_step(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
+                            const DenseB& B, const float* psi_in, float* psi_out,
+                            float* after_S, hipStream_t st) {
+    int32_t* rexp = ws_rexp(B, after_S, m.nc);
+    const float* A = psi_in;
+    hipError_t e = hipSuccess;
+    if (B.chain == 2) {
+        e = product32(B, B.fwd[0], psi_in, after_S, m.nc, rexp, st);
+        A = after_S;
+    }
+    const GemmOperand& op = B.fwd[B.chain - 1];
+    const int products = B.precision == SNRT_FP16X3 ? 0
+                         : B.precision == SNRT_BF16X3 ? 3
+                         : B.precision == SNRT_BF16X2 ? 2 : 1;
+    if (e == hipSuccess && products == 0) e = launch_row_exp_f16(A, m.nc, op.K, rexp, st);
+    if (e != hipSuccess) return e;
+    const StepEpi se{m.geom32, q.tab32, a, psi_in, psi_out, m.nc, q.nq, (uint32_t)m.nbf};
+    return a.inv_rho ? launch_gemm_step_rho(A, op.hi, op.lo, m.nc, op.K, op.Np, products, rexp,
+                                            op.eb, se, st)
+                     : launch_gemm_step(A, op.hi, op.lo, m.nc, op.K, op.Np, products, rexp,
+                                        op.eb, se, st);
+}
+
 hipError_t scatter_product64(const snrt_scatter* sc, const double* A, double* C, int64_t M,
                              bool transpose, double* scratch, hipStream_t st) {
     const DenseB& B = sc->B;
@@ -926,8 +962,13 @@ snrt_status snrt_step(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter
     const float* S = nullptr;
     if (sc->dense) {
         float* Sbuf = static_cast<float*>(ws);
-        hipError_t e = scatter_product32(sc, psi_in, Sbuf, m->nc, false,
-                                         Sbuf + (size_t)m->nc * q->nq, st);
+        float* after = Sbuf + (size_t)m->nc * q->nq;
+        if (step_fusable(*m, *q, sc->B)) {
+            const hipError_t e = fused_dense_step(*m, *q, to32(a), sc->B, psi_in, psi_out,
+                                                  after, st);
+            return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_step: fused dense step");
+        }
+        hipError_t e = scatter_product32(sc, psi_in, Sbuf, m->nc, false, after, st);
         if (e != hipSuccess) return hip_fail(e, "snrt_step: scattering product");
         S = Sbuf;
     }

@@ -182,6 +182,7 @@ struct Tune {
     bool gemm_stagger = true;      // staggered split/product phases in the BF16 product
     bool gemm_epilogue = true;     // IMEX per-cell steps in the products' epilogues
     bool pn_mfma = true;           // matrix-core class blocks in the degree-13 P_N step
+    bool step_fused = true;        // dense step: the update in the product's epilogue
 };
 const Tune& tune();
 
@@ -324,6 +325,42 @@ hipError_t launch_gemm_bf16(const float* A, const uint16_t* Bhi, const uint16_t*
 hipError_t launch_gemm_f16x3(const float* A, const uint16_t* Bhi, const uint16_t* Blo, float* C,
                              int64_t M, int32_t K, int32_t N, int32_t ldc, int32_t* rexp,
                              int32_t eb, hipStream_t st, const GemmEpi& epi = GemmEpi());
+// Block shapes of the low-precision products for M rows and N (padded) columns: mbn-wide
+// 256-row tiles for the first rows1 rows, tm x tn tiles for the rest (none when rows1 == M).
+struct GemmPlan {
+    int mbn = 256, tm = 64, tn = 256;
+    int64_t rows1 = 0;
+};
+GemmPlan gemm_plan(int64_t M, int32_t N);
+// Row exponents of A [M][K] for the FP16 product into rexp [M] (K % 4 == 0).
+hipError_t launch_row_exp_f16(const float* A, int64_t M, int32_t K, int32_t* rexp,
+                              hipStream_t st);
+
+// The explicit dense step with the scattering product's last factor and the transport update
+// in one launch (sn_step_fused.h): S = A X stays in the product's tiles, each tile updates its
+// cells and ordinates from psi_in into psi_out.  A is the product's left operand (psi_in for
+// a dense kernel, the moments for the moment form), X its operand in the hi/lo format with
+// N = nq columns, N % 256 == 0, K % 32 == 0; triangles only; products as launch_gemm_lp
+// (1..3 BF16, 0 FP16 with rexp already written).  The result equals launch_step32's on the
+// stored product bit for bit.
+struct StepEpi {
+    const CellGeom32* geom;
+    const float* tab;         // ordinate table [4][nq]
+    StepArgs32 a;
+    const float* psi_in;
+    float* psi_out;
+    int64_t nc;
+    int32_t nq;
+    uint32_t nbf;
+};
+hipError_t launch_gemm_step(const float* A, const uint16_t* Bhi, const uint16_t* Blo, int64_t M,
+                            int32_t K, int32_t N, int products, const int32_t* rexp, int32_t eb,
+                            const StepEpi& se, hipStream_t st);
+hipError_t launch_gemm_step_rho(const float* A, const uint16_t* Bhi, const uint16_t* Blo,
+                                int64_t M, int32_t K, int32_t N, int products,
+                                const int32_t* rexp, int32_t eb, const StepEpi& se,
+                                hipStream_t st);
+
 // Re-layout of an FP32 [K][N] matrix (N % 128 == 0) into the BF16 hi/lo operand format of the
 // MFMA GEMM, and into the FP16 format of X * 2^eb.
 hipError_t launch_split_bf16(const float* B, uint16_t* hi, uint16_t* lo, int32_t K, int32_t N,
