@@ -48,7 +48,8 @@ constexpr int kAhead = 2;            // cells whose rows are in flight ahead of 
 // The update of one block tile: acc holds S for rows m0 + [0, BM) of a sub-product whose
 // row 0 is cell row0 (M rows in all), columns n0 + [0, BN); exp_of undoes the FP16 row
 // scaling.
-template <int BM, int BN, bool RHO, int D, int IM, int JN, typename Acc, typename ExpOf>
+template <int BM, int BN, bool RHO, bool DOSE, int D, int IM, int JN, typename Acc,
+          typename ExpOf>
 __device__ __forceinline__ void step_tile(Acc (&acc)[IM][JN], const gemm::TileInfo& t,
                                           int64_t row0, int64_t M, ExpOf exp_of,
                                           float* __restrict__ sl, const StepEpi& se)
@@ -114,6 +115,15 @@ __device__ __forceinline__ void step_tile(Acc (&acc)[IM][JN], const gemm::TileIn
         load_slice<V, true>(se.tab + se.nq, t.n0 + q0, se.nq, oy);
 #pragma unroll
         for (int k = 0; k < V; ++k) wi[k] = 0.0f;              // unused by the dense update
+        // the fused dose: FP64 weights of the lane's ordinates, and the piece of the row this
+        // slab (or half-wave, for a 256-wide slab) sums: 128 ordinates each, (n0 / 128) + h
+        double wd[DOSE ? V : 1];
+        if constexpr (DOSE) {
+#pragma unroll
+            for (int k = 0; k < V; ++k) wd[k] = se.wq[t.n0 + q0 + k];
+        }
+        const int npieces = se.nq >> 7;
+        const int piece = (t.n0 >> 7) + (NS == 2 ? s : (W == 256 ? (lane >> 5) : 0));
         auto src_of = [&](FwdStage<V, MF, true, float>& d, int k) {
             const float* p = sl + k * W + (e0 ^ slab_swz(k));
 #pragma unroll
@@ -196,6 +206,17 @@ __device__ __forceinline__ void step_tile(Acc (&acc)[IM][JN], const gemm::TileIn
             src_of(st[SL], k);
             fwd_compute<V, true, MF, RHO, true, float>(st[SL], ox, oy, wi, cell(k), cb, se.nq,
                                                        q0, cx);
+            if constexpr (DOSE) {
+                double sd = 0.0;
+#pragma unroll
+                for (int v = 0; v < V; ++v) sd += wd[v] * (double)st[SL].p[v];
+                // sum over the lanes of the piece: the whole wave, or each half of it
+#pragma unroll
+                for (int off = (W == 256 ? 16 : 32); off >= 1; off >>= 1)
+                    sd += __shfl_xor(sd, off, kWave);
+                if ((lane & (W == 256 ? 31 : 63)) == 0)
+                    se.dpart[(int64_t)cell(k) * npieces + piece] = sd;
+            }
         };
         static_for<0, D>([&](auto d_c) { fetch(d_c, decltype(d_c)::value); });
         for (int n = 0; n < U; n += D + 1) {
@@ -212,7 +233,7 @@ __device__ __forceinline__ void step_tile(Acc (&acc)[IM][JN], const gemm::TileIn
 
 // Blocks [0, nmain) are 256 x 256 tiles of the first M1 rows, blocks [nmain, grid) TM x TN
 // tiles of the rest (the block order and last-round policy of the plain product).
-template <bool F16, int P, int TM, int TN, bool STAGGER, bool RHO>
+template <bool F16, int P, int TM, int TN, bool STAGGER, bool RHO, bool DOSE>
 __global__ __launch_bounds__(gemm::kThreads) void k_gemm_step(
     const float* __restrict__ A, const uint16_t* __restrict__ Bhi,
     const uint16_t* __restrict__ Blo, int64_t M1, int64_t M, int32_t K, int32_t N,
@@ -228,7 +249,7 @@ __global__ __launch_bounds__(gemm::kThreads) void k_gemm_step(
         gemm::gemm_block<P, 256, 256, 1, STAGGER, F16>(
             A, Bhi, Blo, M1, K, N, rexp, eb, xcd_remap(b, nmain), lds,
             [&](auto& acc, const gemm::TileInfo& t, auto, auto exp_of) {
-                step_tile<256, 256, RHO, kAhead>(acc, t, 0, M1, exp_of, sl, se);
+                step_tile<256, 256, RHO, DOSE, kAhead>(acc, t, 0, M1, exp_of, sl, se);
             });
     } else {
         const int64_t nt = (int64_t)gridDim.x - nmain;
@@ -236,12 +257,12 @@ __global__ __launch_bounds__(gemm::kThreads) void k_gemm_step(
             A + M1 * K, Bhi, Blo, M - M1, K, N, F16 ? rexp + M1 : rexp, eb,
             xcd_remap(b - nmain, nt), lds,
             [&](auto& acc, const gemm::TileInfo& t, auto, auto exp_of) {
-                step_tile<TM, TN, RHO, kAhead>(acc, t, M1, M - M1, exp_of, sl, se);
+                step_tile<TM, TN, RHO, DOSE, kAhead>(acc, t, M1, M - M1, exp_of, sl, se);
             });
     }
 }
 
-template <bool RHO>
+template <bool RHO, bool DOSE>
 hipError_t launch_gemm_step_t(const float* A, const uint16_t* Bhi, const uint16_t* Blo,
                               int64_t M, int32_t K, int32_t N, int products,
                               const int32_t* rexp, int32_t eb, const StepEpi& se,
@@ -250,7 +271,8 @@ hipError_t launch_gemm_step_t(const float* A, const uint16_t* Bhi, const uint16_
     if (M == 0) return hipSuccess;
     if (products < 0 || products > 3) return hipErrorInvalidValue;
     if (K % 32 != 0 || K == 0 || N % 256 != 0 || N != se.nq || M != se.nc ||
-        (products == 0 && !rexp))
+        (products == 0 && !rexp) || RHO != (se.a.inv_rho != nullptr) ||
+        DOSE != (se.dpart != nullptr) || (DOSE && !se.wq))
         return hipErrorNotSupported;
     const GemmPlan p = gemm_plan(M, N);
     if (p.mbn != 256) return hipErrorNotSupported;
@@ -262,7 +284,7 @@ hipError_t launch_gemm_step_t(const float* A, const uint16_t* Bhi, const uint16_
         constexpr int PP = decltype(p_c)::value;
         constexpr int TN = decltype(tn_c)::value;
         constexpr bool SG = decltype(sg_c)::value;
-        hipLaunchKernelGGL((k_gemm_step<PP == 0, PP == 0 ? 3 : PP, 64, TN, SG, RHO>), grid,
+        hipLaunchKernelGGL((k_gemm_step<PP == 0, PP == 0 ? 3 : PP, 64, TN, SG, RHO, DOSE>), grid,
                            dim3(gemm::kThreads), 0, st, A, Bhi, Blo, p.rows1, M, K, N, rexp, eb,
                            nmain, se);
         return hipGetLastError();

@@ -1,13 +1,13 @@
-// The fused dense step without densities (see sn_step_fused.h).
+// The one-launch dense step (kernel templates in sn_step_fused.h).
 #include "sn_step_fused.h"
 
 namespace snrt {
+namespace fused {
 
-hipError_t launch_gemm_step(const float* A, const uint16_t* Bhi, const uint16_t* Blo, int64_t M,
-                            int32_t K, int32_t N, int products, const int32_t* rexp, int32_t eb,
-                            const StepEpi& se, hipStream_t st) {
-    if (se.a.inv_rho) return hipErrorInvalidValue;
-    return fused::launch_gemm_step_t<false>(A, Bhi, Blo, M, K, N, products, rexp, eb, se, st);
-}
+template hipError_t launch_gemm_step_t<false, false>(const float*, const uint16_t*,
+                                                  const uint16_t*, int64_t, int32_t, int32_t,
+                                                  int, const int32_t*, int32_t, const StepEpi&,
+                                                  hipStream_t);
 
+}  // namespace fused
 }  // namespace snrt

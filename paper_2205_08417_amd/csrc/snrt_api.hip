@@ -696,9 +696,14 @@ size_t implicit_ws_elems(const snrt_scatter* sc, int64_t nc) {
 size_t dose_ws_offset(const snrt_mesh* m, const snrt_scatter* sc) {
     return (product_ws_elems(sc, m->nc) * sizeof(float) + 15) / 16 * 16;
 }
+// FP64 dose partials per row: one per work item of the step kernel, or one per 128-ordinate
+// piece for the one-launch dense step (whichever is more).
+int32_t dose_pieces(const snrt_quad* q, const snrt_scatter* sc) {
+    const int32_t items = step_items_per_row(*q, sc->dense);
+    return sc->dense && q->nq % 256 == 0 ? std::max(items, q->nq / 128) : items;
+}
 size_t dose_ws_bytes(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc) {
-    return dose_ws_offset(m, sc) +
-           (size_t)m->nc * step_items_per_row(*q, sc->dense) * sizeof(double);
+    return dose_ws_offset(m, sc) + (size_t)m->nc * dose_pieces(q, sc) * sizeof(double);
 }
 
 }  // namespace
@@ -861,7 +866,7 @@ bool step_fusable(const snrt_mesh& m, const snrt_quad& q, const DenseB& B) {
 // operand, then one launch forms S tile by tile and updates psi_out from it.
 hipError_t fused_dense_step(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
                             const DenseB& B, const float* psi_in, float* psi_out,
-                            float* after_S, hipStream_t st) {
+                            float* after_S, hipStream_t st, double* dpart = nullptr) {
     int32_t* rexp = ws_rexp(B, after_S, m.nc);
     const float* A = psi_in;
     hipError_t e = hipSuccess;
@@ -875,11 +880,9 @@ hipError_t fused_dense_step(const snrt_mesh& m, const snrt_quad& q, const StepAr
                          : B.precision == SNRT_BF16X2 ? 2 : 1;
     if (e == hipSuccess && products == 0) e = launch_row_exp_f16(A, m.nc, op.K, rexp, st);
     if (e != hipSuccess) return e;
-    const StepEpi se{m.geom32, q.tab32, a, psi_in, psi_out, m.nc, q.nq, (uint32_t)m.nbf};
-    return a.inv_rho ? launch_gemm_step_rho(A, op.hi, op.lo, m.nc, op.K, op.Np, products, rexp,
-                                            op.eb, se, st)
-                     : launch_gemm_step(A, op.hi, op.lo, m.nc, op.K, op.Np, products, rexp,
-                                        op.eb, se, st);
+    const StepEpi se{m.geom32, q.tab32, a, psi_in, psi_out, m.nc, q.nq, (uint32_t)m.nbf,
+                     q.tab64 + 2 * (int64_t)q.nq, dpart};
+    return launch_gemm_step(A, op.hi, op.lo, m.nc, op.K, op.Np, products, rexp, op.eb, se, st);
 }
 
 hipError_t scatter_product64(const snrt_scatter* sc, const double* A, double* C, int64_t M,
@@ -996,15 +999,22 @@ snrt_status snrt_step_dose(const snrt_mesh* m, const snrt_quad* q, const snrt_sc
                      !ranges_overlap(dose, db, ws, need),
                  SNRT_E_ALIAS, "snrt_step_dose: dose aliases a state array or the workspace");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + dose_ws_offset(m, sc));
     const float* S = nullptr;
     if (sc->dense) {
         float* Sbuf = static_cast<float*>(ws);
-        hipError_t e = scatter_product32(sc, psi_in, Sbuf, m->nc, false,
-                                         Sbuf + (size_t)m->nc * q->nq, st);
+        float* after = Sbuf + (size_t)m->nc * q->nq;
+        if (step_fusable(*m, *q, sc->B)) {
+            hipError_t e = fused_dense_step(*m, *q, to32(a), sc->B, psi_in, psi_out, after, st,
+                                            part);
+            if (e == hipSuccess)
+                e = launch_dose_fold(*m, part, q->nq / 128, a->inv_rho, coeff, dose, st);
+            return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_step_dose: fused dense step");
+        }
+        hipError_t e = scatter_product32(sc, psi_in, Sbuf, m->nc, false, after, st);
         if (e != hipSuccess) return hip_fail(e, "snrt_step_dose: scattering product");
         S = Sbuf;
     }
-    double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + dose_ws_offset(m, sc));
     hipError_t e = launch_step32(*m, *q, to32(a), psi_in, psi_out, S, st, part);
     if (e == hipSuccess)
         e = launch_dose_fold(*m, part, step_items_per_row(*q, sc->dense), a->inv_rho, coeff,

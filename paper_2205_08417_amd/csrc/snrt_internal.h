@@ -343,6 +343,9 @@ hipError_t launch_row_exp_f16(const float* A, int64_t M, int32_t K, int32_t* rex
 // N = nq columns, N % 256 == 0, K % 32 == 0; triangles only; products as launch_gemm_lp
 // (1..3 BF16, 0 FP16 with rexp already written).  The result equals launch_step32's on the
 // stored product bit for bit.
+// With dpart set, each tile also writes the FP64 sums sum_q w_q psi_in[c][q] (wq: FP64
+// weights [nq]) over 128-ordinate pieces of the row: dpart[c * (nq / 128) + piece], for
+// k_dose_fold (the fused dose of snrt_step_dose).
 struct StepEpi {
     const CellGeom32* geom;
     const float* tab;         // ordinate table [4][nq]
@@ -352,14 +355,31 @@ struct StepEpi {
     int64_t nc;
     int32_t nq;
     uint32_t nbf;
+    const double* wq;
+    double* dpart;
 };
-hipError_t launch_gemm_step(const float* A, const uint16_t* Bhi, const uint16_t* Blo, int64_t M,
-                            int32_t K, int32_t N, int products, const int32_t* rexp, int32_t eb,
-                            const StepEpi& se, hipStream_t st);
-hipError_t launch_gemm_step_rho(const float* A, const uint16_t* Bhi, const uint16_t* Blo,
-                                int64_t M, int32_t K, int32_t N, int products,
-                                const int32_t* rexp, int32_t eb, const StepEpi& se,
-                                hipStream_t st);
+namespace fused {
+template <bool RHO, bool DOSE>
+hipError_t launch_gemm_step_t(const float* A, const uint16_t* Bhi, const uint16_t* Blo,
+                              int64_t M, int32_t K, int32_t N, int products,
+                              const int32_t* rexp, int32_t eb, const StepEpi& se,
+                              hipStream_t st);
+}  // namespace fused
+inline hipError_t launch_gemm_step(const float* A, const uint16_t* Bhi, const uint16_t* Blo,
+                                   int64_t M, int32_t K, int32_t N, int products,
+                                   const int32_t* rexp, int32_t eb, const StepEpi& se,
+                                   hipStream_t st) {
+    const bool rho = se.a.inv_rho != nullptr, dose = se.dpart != nullptr;
+    if (rho)
+        return dose ? fused::launch_gemm_step_t<true, true>(A, Bhi, Blo, M, K, N, products,
+                                                            rexp, eb, se, st)
+                    : fused::launch_gemm_step_t<true, false>(A, Bhi, Blo, M, K, N, products,
+                                                             rexp, eb, se, st);
+    return dose ? fused::launch_gemm_step_t<false, true>(A, Bhi, Blo, M, K, N, products, rexp,
+                                                         eb, se, st)
+                : fused::launch_gemm_step_t<false, false>(A, Bhi, Blo, M, K, N, products, rexp,
+                                                          eb, se, st);
+}
 
 // Re-layout of an FP32 [K][N] matrix (N % 128 == 0) into the BF16 hi/lo operand format of the
 // MFMA GEMM, and into the FP16 format of X * 2^eb.

@@ -1,16 +1,16 @@
 """GPU tests of the one-launch dense step: the low-precision scattering product whose tiles
 run the transport update (Sec. 4.2 explicit step, eq. SNEqns / SNEqns2) on the cells and
-ordinates they hold, instead of writing S for a second kernel.
+ordinates they hold, instead of writing S for a second kernel; with the dose of the input
+state (Sec. 2) fused as well for snrt_step_dose.
 
-snrt_step takes this path for triangles with nq % 256 == 0 and a BF16 / FP16 product;
-snrt_step_dose keeps the two launches (product, then the step kernel with the dose), and
-its state is the plain step's bit for bit.  So in one process the fused state can be held
-against the two-launch state exactly, and against the FP64 oracle to the product's
+snrt_step and snrt_step_dose take this path for triangles with nq % 256 == 0 and a BF16 /
+FP16 product.  A child process with SNRT_STEP_FUSED=0 (read once per process) computes the
+same steps with two launches (the product, then the step kernel); the states must agree
+bit for bit, the doses to FP64 rounding, and both with the FP64 oracle to the product's
 precision.  The launch shapes cover full 256 x 256 tiles with a ragged last row tile, the
 last-round 64 x 128 and 64 x 256 tiles of larger meshes, a single cell, 256 / 512 / 1024
 ordinates, densities, sources, Dirichlet inflow, Neumann and vacuum boundaries, and the
-moment form (moments, then the fused second product).  A child process with
-SNRT_STEP_FUSED=0 runs the same rollout with the two launches throughout.
+moment form (moments, then the fused second product).
 """
 import os
 import subprocess
@@ -99,63 +99,116 @@ def _oracle_problem(P, kw, neumann):
 
 CASES = ["single-cell", "256-ragged", "512-neumann", "1024-vacuum", "256-eighth",
          "256-quarter", "moments-256", "moments-512"]
+PRECISIONS = ["bf16x3", "bf16x2", "bf16x1", "fp16x3"]
 
 
-@pytest.mark.parametrize("precision", ["bf16x3", "bf16x2", "bf16x1", "fp16x3"])
-@pytest.mark.parametrize("name", CASES)
-def test_fused_step_equals_two_launch_step_and_oracle(name, precision):
-    from oracle import oracle as o
+def _skip(name, precision):
+    return name in ("256-eighth", "256-quarter") and precision not in ("bf16x3", "fp16x3")
+
+
+def _one_step(name, precision):
+    """The step and the dose of every cell (user order) through snrt_step and snrt_step_dose,
+    in whichever form this process runs the dense step."""
     from paper_2205_08417_amd import snrt
     from paper_2205_08417_amd.solver import Solver
-    if name in ("256-eighth", "256-quarter") and precision not in ("bf16x3", "fp16x3"):
-        pytest.skip("the last-round tile shapes are covered by two precisions")
     P, kw, bc = _case(name, 17)
-    boundary = {"dirichlet": snrt.SNRT_BC_DIRICHLET, "neumann": snrt.SNRT_BC_NEUMANN,
-                "vacuum": snrt.SNRT_BC_DIRICHLET}[bc]
-    if bc == "vacuum":
-        assert P.inflow is None
+    boundary = snrt.SNRT_BC_NEUMANN if bc == "neumann" else snrt.SNRT_BC_DIRICHLET
     S = Solver(P, precision=precision, **kw)
-    rows1, tail = _plan(S.nc, S.nq)
-    print(f"{name} {precision}: {S.nc} cells x {S.nq} ordinates, 256-row tiles up to row "
+    args = S.args(alpha_t=1.1, alpha_s=0.9, inflow_scale=0.6, boundary=boundary)
+    psi = S.initial_state()
+    out = torch.empty_like(psi)
+    out_d = torch.empty_like(psi)
+    dose = torch.full((S.nc,), 0.25, dtype=torch.float64, device="cuda")
+    snrt.snrt_step(S.mesh, S.quad, S.scatter, args, psi, out, S.ws, S.ws_bytes)
+    snrt.snrt_step_dose(S.mesh, S.quad, S.scatter, args, psi, out_d, 0.37, dose, S.ws,
+                        S.ws_bytes)
+    torch.cuda.synchronize()
+    res = (S.to_user(out).cpu().numpy(), S.to_user(out_d).cpu().numpy(),
+           S.to_user(dose.reshape(-1, 1)).cpu().numpy().ravel(), S.perm.copy(), S.nc, S.nq)
+    S.close()
+    return P, kw, bc, res
+
+
+@pytest.fixture(scope="module")
+def two_launch():
+    """Every case's step and dose from a child process that runs the two launches."""
+    script = (
+        "import sys, numpy as np\n"
+        f"sys.path.insert(0, {ROOT!r}); sys.path.insert(0, {os.path.join(ROOT, 'tests')!r})\n"
+        "import test_gpu_step_fused as T\n"
+        "out = sys.argv[1]\n"
+        "for name in T.CASES:\n"
+        "    for prec in T.PRECISIONS:\n"
+        "        if T._skip(name, prec):\n"
+        "            continue\n"
+        "        print(f'two-launch {name} {prec}', flush=True)\n"
+        "        _, _, _, r = T._one_step(name, prec)\n"
+        "        np.save(f'{out}/{name}-{prec}-step.npy', r[0])\n"
+        "        np.save(f'{out}/{name}-{prec}-dose-step.npy', r[1])\n"
+        "        np.save(f'{out}/{name}-{prec}-dose.npy', r[2])\n")
+    env = dict(os.environ, SNRT_STEP_FUSED="0")
+    with tempfile.TemporaryDirectory() as tmp:
+        print("child: two-launch steps of every case", flush=True)
+        r = subprocess.run([sys.executable, "-c", script, tmp], env=env, capture_output=True,
+                           text=True, timeout=600)
+        assert r.returncode == 0, r.stderr[-3000:]
+        yield tmp
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("name", CASES)
+def test_fused_step_equals_two_launch_step_and_oracle(two_launch, name, precision):
+    from oracle import oracle as o
+    if _skip(name, precision):
+        pytest.skip("the last-round tile shapes are covered by two precisions")
+    P, kw, bc, (out, out_d, dose, perm, nc, nq) = _one_step(name, precision)
+    rows1, tail = _plan(nc, nq)
+    print(f"{name} {precision}: {nc} cells x {nq} ordinates, 256-row tiles up to row "
           f"{rows1}, last-round tiles {'64x%d' % tail if tail else 'none'}", flush=True)
     if name == "256-eighth":
         assert tail == 128
     if name == "256-quarter":
         assert tail == 256
-    args = S.args(alpha_t=1.1, alpha_s=0.9, inflow_scale=0.6, boundary=boundary)
-    psi = S.initial_state()
-    out = torch.empty_like(psi)
-    ref = torch.empty_like(psi)
-    dose = torch.zeros(S.nc, dtype=torch.float64, device="cuda")
-    snrt.snrt_step(S.mesh, S.quad, S.scatter, args, psi, out, S.ws, S.ws_bytes)
-    snrt.snrt_step_dose(S.mesh, S.quad, S.scatter, args, psi, ref, 1.0, dose, S.ws, S.ws_bytes)
-    torch.cuda.synchronize()
-    if not torch.equal(out, ref):
-        diff = (out - ref).abs()
-        bad = (diff > 0).nonzero()
-        print(f"  differing elements {bad.shape[0]} of {out.numel()}, max |diff| "
-              f"{float(diff.max()):.3e} (max |ref| {float(ref.abs().max()):.3e}); first "
-              f"(row, col): {bad[:8].tolist()}", flush=True)
-    assert torch.equal(out, ref), "the one-launch step must equal the two-launch step"
+    ref = np.load(os.path.join(two_launch, f"{name}-{precision}-step.npy"))
+    ref_d = np.load(os.path.join(two_launch, f"{name}-{precision}-dose-step.npy"))
+    ref_dose = np.load(os.path.join(two_launch, f"{name}-{precision}-dose.npy"))
+    for got, want, what in ((out, ref, "snrt_step"), (out_d, ref_d, "snrt_step_dose")):
+        if not np.array_equal(got, want):
+            bad = np.argwhere(got != want)
+            print(f"  {what}: {bad.shape[0]} elements differ, max "
+                  f"{np.abs(got - want).max():.3e}; first {bad[:6].tolist()}", flush=True)
+        assert np.array_equal(got, want), f"{what}: one launch must equal two launches"
+    assert np.array_equal(out, out_d)
+    derr = float(np.max(np.abs(dose - ref_dose)) / np.max(np.abs(ref_dose)))
+    print(f"  dose vs two-launch dose: {derr:.2e}")
+    assert derr <= 1e-14
     # the oracle on sampled cells: every row of a small mesh, else cells of the full tiles
     # and of the last-round tiles (internal order: the last rows)
-    got = S.to_user(out).cpu().numpy()
-    if S.nc <= 4000:
-        cells = np.arange(S.nc)
+    if nc <= 4000:
+        cells = np.arange(nc)
     else:
         rng = np.random.default_rng(3)
-        inner = S.perm[rng.choice(min(rows1, S.nc), 80, replace=False)]
-        last = S.perm[rows1 + rng.choice(S.nc - rows1, 80, replace=False)] if rows1 < S.nc \
-            else S.perm[-80:]
-        cells = np.unique(np.concatenate([inner, last, S.perm[-1:]]))
+        inner = perm[rng.choice(min(rows1, nc), 80, replace=False)]
+        last = perm[rows1 + rng.choice(nc - rows1, 80, replace=False)] if rows1 < nc \
+            else perm[-80:]
+        cells = np.unique(np.concatenate([inner, last, perm[-1:]]))
     op = _oracle_problem(P, kw, bc == "neumann")
     want = o.step(op, P.psi0, P.dt, 1.1, 0.9, 0.6, cells=cells)
-    err = rel_l2(got[cells], want)
-    worst = float(np.max(np.abs(got[cells] - want)) / np.max(np.abs(want)))
+    err = rel_l2(out[cells], want)
+    worst = float(np.max(np.abs(out[cells] - want)) / np.max(np.abs(want)))
     print(f"  vs oracle on {cells.size} cells: rel-L2 {err:.2e}, max {worst:.2e}")
     assert err <= TOL[precision]
     assert worst <= 10 * TOL[precision]
-    S.close()
+    # the dose of the input state against the oracle's (FP32 copies of psi and 1/rho, as on
+    # the device)
+    op32 = _oracle_problem(P, kw, bc == "neumann")
+    if P.rho is not None:
+        op32 = op32.replace(rho=1.0 / (1.0 / P.rho).astype(np.float32).astype(np.float64))
+    psi32 = P.psi0.astype(np.float32).astype(np.float64)
+    dref = o.dose_accumulate(op32, psi32, 0.37, np.full(nc, 0.25))
+    dose_err = rel_l2(dose, dref)
+    print(f"  dose vs oracle: {dose_err:.2e}")
+    assert dose_err <= 1e-12
 
 
 def test_fused_rollout_equals_two_launch_rollout_in_a_fresh_process():
