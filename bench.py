@@ -169,6 +169,14 @@ def product_rate(S, psi, reps: int = 10, passes: int = 3, kernel: str = "k_gemm_
             "peak_tflops": peak, "mfma_utilization": tflops / peak}
 
 
+def step_form() -> str:
+    """How the library runs an explicit dense step (SNRT_STEP_FUSED, read once per process)."""
+    if os.environ.get("SNRT_STEP_FUSED", "1") == "0":
+        return "two launches: scattering product into the workspace, then k_step"
+    return ("one launch: k_gemm_step, the scattering product whose tiles run the update of "
+            "their cells and ordinates (triangles, nq % 256 == 0, BF16/FP16 products)")
+
+
 def bench_dense(steps, warmup: int):
     """Anisotropic HG line source (100 352 cells x 1024 ordinates) with the scattering product
     in each mixed precision (BF16 hi+lo in three and two products, FP16 hi+lo in three) and
@@ -209,7 +217,7 @@ def bench_dense(steps, warmup: int):
 
     out = {"workload": DENSE_WORKLOAD, "cells": P.ncells, "ordinates": P.nq,
            "scattering": "Henyey-Greenstein g=0.9, dense, column-normalised", "steps": nsteps,
-           "unit": "cell-ordinate updates/s"}
+           "unit": "cell-ordinate updates/s", "step_form": step_form()}
     finals = {}
     for precision, label in (("bf16x3", "BF16 hi+lo, three products"),
                              ("bf16x2", "BF16, operand hi+lo and state once: two products"),
@@ -437,8 +445,9 @@ def bench_csd(steps, warmup: int):
             "energy_MeV": [float(P.meta["energy"][0]), float(P.meta["energy"][nsteps - 1])],
             "value": P.ncells * P.nq / (ms_step * 1e-3), "unit": "cell-ordinate updates/s",
             "ms_per_step": ms_step,
-            "note": "a step = scattering product + flux/update kernel with the dose of its "
-                    "input fused (snrt_step_dose)",
+            "note": "a step = snrt_step_dose: the scattering product, the flux/update and the "
+                    "dose of the step's input, then the fold of the dose partials",
+            "step_form": step_form(),
             "ms_per_step_separate_dose_pass": ms_separate,
             "scatter_product": final, "scatter_product_dense_random_state": dense,
             "vs_oracle": vs_oracle, "rel_l2_vs_oracle": vs_oracle["rel_l2"],
@@ -551,7 +560,7 @@ def bench_moments(steps, warmup: int, degree: int = 8):
     S.close()
     return {"workload": DENSE_WORKLOAD, "cells": P.ncells, "ordinates": P.nq,
             "scattering": f"moment-projected O Sigma M, HG g=0.9, degree {degree} ({nm} moments)",
-            "precision": "bf16x3", "steps": steps, "ms_per_step": ms,
+            "precision": "bf16x3", "steps": steps, "ms_per_step": ms, "step_form": step_form(),
             "value": P.ncells * P.nq / (ms * 1e-3), "unit": "cell-ordinate updates/s",
             "moment_dimension_padded": mid, "product_flops_executed": executed,
             "product_flops_useful": useful, "imex_ms_per_step": ms_imex,

@@ -364,6 +364,16 @@ hipError_t launch_gemm_step_t(const float* A, const uint16_t* Bhi, const uint16_
                               int64_t M, int32_t K, int32_t N, int products,
                               const int32_t* rexp, int32_t eb, const StepEpi& se,
                               hipStream_t st);
+// each form is instantiated in a translation unit of its own (sn_step_fused*.hip)
+#define SNRT_FUSED_STEP_EXTERN(R, D)                                                          \
+    extern template hipError_t launch_gemm_step_t<R, D>(                                      \
+        const float*, const uint16_t*, const uint16_t*, int64_t, int32_t, int32_t, int,        \
+        const int32_t*, int32_t, const StepEpi&, hipStream_t);
+SNRT_FUSED_STEP_EXTERN(false, false)
+SNRT_FUSED_STEP_EXTERN(true, false)
+SNRT_FUSED_STEP_EXTERN(false, true)
+SNRT_FUSED_STEP_EXTERN(true, true)
+#undef SNRT_FUSED_STEP_EXTERN
 }  // namespace fused
 inline hipError_t launch_gemm_step(const float* A, const uint16_t* Bhi, const uint16_t* Blo,
                                    int64_t M, int32_t K, int32_t N, int products,
