@@ -31,7 +31,10 @@
 namespace snrt {
 namespace fused {
 
-constexpr int kSlabFloats = 32768;   // 128 KB of LDS for the S slab
+constexpr int kSlabFloats = 32768;   // 128 KB: the column slabs and the last-round tiles
+constexpr bool kRowSlabs = true;     // 256 x 256 tiles as two row slabs (see step_tile)
+constexpr int kRowSplit = 160;       // rows of the first row slab
+constexpr int kSlabFloatsMax = 40960;  // 160 KB, all the LDS a compute unit has
 
 __device__ __forceinline__ int slab_swz(int row) { return ((row >> 2) & 1) << 5; }
 
@@ -54,17 +57,22 @@ __device__ __forceinline__ void step_tile(Acc (&acc)[IM][JN], const gemm::TileIn
                                           int64_t row0, int64_t M, ExpOf exp_of,
                                           float* __restrict__ sl, const StepEpi& se)
 {
-    constexpr int NS = BM * BN <= kSlabFloats ? 1 : 2;      // column slabs
-    constexpr int W = BN / NS;                              // slab width
-    constexpr int JS = JN / NS;                             // accumulator blocks per slab
+    // A tile larger than the LDS slab runs as two slabs: with kRowSlabs, rows [0, kRowSplit)
+    // and [kRowSplit, BM) at the full width (V = 4: the rows of 160 cells fill the 160 KB of
+    // LDS); otherwise the interleaved column halves described above (V = 2).
+    constexpr int NS = BM * BN <= kSlabFloats ? 1 : 2;
+    constexpr bool RS = kRowSlabs && NS == 2;
+    constexpr int W = RS ? BN : BN / NS;                    // slab width
+    constexpr int JS = RS ? JN : JN / NS;                   // accumulator blocks per slab
     constexpr int V = W / 64;                               // ordinates per lane
-    static_assert(BM * W <= kSlabFloats && JN % NS == 0 && W >= 64, "slab shape");
+    static_assert(RS ? kRowSplit * W <= kSlabFloatsMax && kRowSplit % 32 == 0
+                     : BM * W <= kSlabFloats && JN % NS == 0, "slab shape");
+    static_assert(W >= 64, "slab width");
     constexpr int MF = 3;
     const int lane = t.lane;
     const int wave = __builtin_amdgcn_readfirstlane(t.wave);
     const int w4 = wave & 3;                                // the wave's column group
     const int64_t trows = M - t.m0 < BM ? M - t.m0 : BM;    // rows of this tile (> 0)
-    const int nrow = (int)trows;
 
     FwdCtx<float> cx;
     cx.row_bytes = (uint32_t)se.nq * (uint32_t)sizeof(float);
@@ -82,34 +90,44 @@ __device__ __forceinline__ void step_tile(Acc (&acc)[IM][JN], const gemm::TileIn
     cx.dpart = nullptr;
     const uint32_t cb = (uint32_t)t.n0 * (uint32_t)sizeof(float);
     const int64_t base = row0 + t.m0;
-    // loads run ahead on clamped rows (always in the tile); only rows < nrow are stored
-    auto cell = [&](int k) { return uniform_cell((int32_t)(base + (k < nrow ? k : nrow - 1))); };
 
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
+        // the slab's tile rows [rs, re)
+        const int rs = RS && s == 1 ? kRowSplit : 0;
+        const int re = RS && s == 0 ? kRowSplit : BM;
         __syncthreads();              // the K loop's planes, or the previous slab, are done
-        // this wave's blocks of the slab: j = jj * NS + s, at slab column (w4 * JS + jj) * 32
+        // this wave's blocks of the slab: column slabs hold blocks j = jj * NS + s at slab
+        // column (w4 * JS + jj) * 32; row slabs every block of the rows they hold
 #pragma unroll
-        for (int i = 0; i < IM; ++i)
+        for (int i = 0; i < IM; ++i) {
+            if (RS && (t.wm + i * 32 < rs || t.wm + i * 32 >= re)) continue;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int lr = t.wm + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                const int sr = lr - rs;
                 const int e = exp_of(t.m0 + lr);
 #pragma unroll
                 for (int jj = 0; jj < JS; ++jj) {
-                    const int j = jj * NS + s;
+                    const int j = RS ? jj : jj * NS + s;
                     const int lc = (w4 * JS + jj) * 32 + (lane & 31);
                     const float v = e != 0 ? __builtin_ldexpf(acc[i][j][r], e) : acc[i][j][r];
-                    sl[lr * W + (lc ^ slab_swz(lr))] = v;
+                    sl[sr * W + (lc ^ slab_swz(sr))] = v;
                 }
             }
+        }
         __syncthreads();
+        const int nrow = (trows < re ? (int)trows : re) - rs;   // rows of the slab in M
         if (wave >= nrow) continue;
+        // loads run ahead on clamped rows (always in the slab); only rows < nrow are stored
+        auto cell = [&](int k) {
+            return uniform_cell((int32_t)(base + rs + (k < nrow ? k : nrow - 1)));
+        };
         // lane l: slab columns [V l, V l + V), block b = V l / 32 of the slab order, i.e.
         // tile columns (b / JS) * BN/4 + 32 ((b % JS) NS + s) + (V l) % 32 + [0, V)
         const int e0 = lane * V;
         const int blk = e0 >> 5;
-        const int q0 = (blk / JS) * (BN / 4) + 32 * ((blk % JS) * NS + s) + (e0 & 31);
+        const int q0 = RS ? e0 : (blk / JS) * (BN / 4) + 32 * ((blk % JS) * NS + s) + (e0 & 31);
         float ox[V], oy[V], wi[V];
         load_slice<V, true>(se.tab, t.n0 + q0, se.nq, ox);
         load_slice<V, true>(se.tab + se.nq, t.n0 + q0, se.nq, oy);
@@ -123,7 +141,7 @@ __device__ __forceinline__ void step_tile(Acc (&acc)[IM][JN], const gemm::TileIn
             for (int k = 0; k < V; ++k) wd[k] = se.wq[t.n0 + q0 + k];
         }
         const int npieces = se.nq >> 7;
-        const int piece = (t.n0 >> 7) + (NS == 2 ? s : (W == 256 ? (lane >> 5) : 0));
+        const int piece = (t.n0 >> 7) + (W == 256 ? (lane >> 5) : (NS == 2 ? s : 0));
         auto src_of = [&](FwdStage<V, MF, true, float>& d, int k) {
             const float* p = sl + k * W + (e0 ^ slab_swz(k));
 #pragma unroll
@@ -142,7 +160,7 @@ __device__ __forceinline__ void step_tile(Acc (&acc)[IM][JN], const gemm::TileIn
         float lirho, lcabs, lcflux, lcscat, lsrcv;
         {
             const int kk = wave + 8 * (lane < 32 ? lane : 31);
-            const int32_t c = (int32_t)(base + (kk < nrow ? kk : nrow - 1));
+            const int32_t c = (int32_t)(base + rs + (kk < nrow ? kk : nrow - 1));
             const CellGeom32* g = se.geom + c;
             lirho = RHO ? se.a.inv_rho[c] : 1.0f;
             const float bscale = cx.dirichlet ? cx.inflow_scale : (cx.neumann ? lirho : 0.0f);
@@ -241,7 +259,8 @@ __global__ __launch_bounds__(gemm::kThreads) void k_gemm_step(
 {
     constexpr int NP = P == 3 ? 4 : P == 2 ? 3 : 2;
     constexpr int kPlanes = 2 * NP * gemm::kPlane;
-    constexpr int kU16 = kPlanes > 2 * kSlabFloats ? kPlanes : 2 * kSlabFloats;
+    constexpr int kSlab = kRowSlabs ? kRowSplit * 256 : kSlabFloats;
+    constexpr int kU16 = kPlanes > 2 * kSlab ? kPlanes : 2 * kSlab;
     __shared__ __attribute__((aligned(16))) uint16_t lds[kU16];
     float* sl = reinterpret_cast<float*>(lds);
     const int64_t b = blockIdx.x;
