@@ -303,9 +303,6 @@ hipError_t launch_gemm_step_t(const float* A, const uint16_t* Bhi, const uint16_
         constexpr int PP = decltype(p_c)::value;
         constexpr int TN = decltype(tn_c)::value;
         constexpr bool SG = decltype(sg_c)::value;
-        // the FP16 product runs with densities or the dose in two launches (the library's
-        // choice: this form needs more scalar registers than the kernel has)
-        if constexpr (PP == 0 && (RHO || DOSE)) return hipErrorNotSupported;
         hipLaunchKernelGGL((k_gemm_step<PP == 0, PP == 0 ? 3 : PP, 64, TN, SG, RHO, DOSE>), grid,
                            dim3(gemm::kThreads), 0, st, A, Bhi, Blo, p.rows1, M, K, N, rexp, eb,
                            nmain, se);

@@ -853,14 +853,10 @@ hipError_t scatter_product32(const snrt_scatter* sc, const float* A, float* C, i
 }
 
 // Whether the explicit dense step runs as one launch (the product's last factor with the
-// transport update in its epilogue): low-precision products, triangles, nq % 256 == 0.  The
-// FP16 product with densities or the fused dose keeps two launches: its one-launch form
-// holds more scalar registers than the kernel has and measured slower (CSD workload).
-bool step_fusable(const snrt_mesh& m, const snrt_quad& q, const DenseB& B, bool rho,
-                  bool dose) {
+// transport update in its epilogue): low-precision products, triangles, nq % 256 == 0.
+bool step_fusable(const snrt_mesh& m, const snrt_quad& q, const DenseB& B) {
     if (!tune().step_fused || B.precision == SNRT_FP32 || m.mf != 3 || q.nq % 256 != 0)
         return false;
-    if (B.precision == SNRT_FP16X3 && (rho || dose)) return false;
     const GemmOperand& last = B.fwd[B.chain - 1];
     return last.N == q.nq && last.Np == q.nq && last.K % 32 == 0 && last.hi != nullptr;
 }
@@ -970,7 +966,7 @@ snrt_status snrt_step(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter
     if (sc->dense) {
         float* Sbuf = static_cast<float*>(ws);
         float* after = Sbuf + (size_t)m->nc * q->nq;
-        if (step_fusable(*m, *q, sc->B, a->inv_rho != nullptr, false)) {
+        if (step_fusable(*m, *q, sc->B)) {
             const hipError_t e = fused_dense_step(*m, *q, to32(a), sc->B, psi_in, psi_out,
                                                   after, st);
             return e == hipSuccess ? SNRT_OK : hip_fail(e, "snrt_step: fused dense step");
@@ -1008,7 +1004,7 @@ snrt_status snrt_step_dose(const snrt_mesh* m, const snrt_quad* q, const snrt_sc
     if (sc->dense) {
         float* Sbuf = static_cast<float*>(ws);
         float* after = Sbuf + (size_t)m->nc * q->nq;
-        if (step_fusable(*m, *q, sc->B, a->inv_rho != nullptr, true)) {
+        if (step_fusable(*m, *q, sc->B)) {
             hipError_t e = fused_dense_step(*m, *q, to32(a), sc->B, psi_in, psi_out, after, st,
                                             part);
             if (e == hipSuccess)

@@ -3,9 +3,8 @@ run the transport update (Sec. 4.2 explicit step, eq. SNEqns / SNEqns2) on the c
 ordinates they hold, instead of writing S for a second kernel; with the dose of the input
 state (Sec. 2) fused as well for snrt_step_dose.
 
-snrt_step and snrt_step_dose take this path for triangles with nq % 256 == 0 and a BF16
-product, or an FP16 product without densities and dose (the FP16 cases with either keep two
-launches; they still run here, against the same references).  A child process with SNRT_STEP_FUSED=0 (read once per process) computes the
+snrt_step and snrt_step_dose take this path for triangles with nq % 256 == 0 and a BF16 /
+FP16 product.  A child process with SNRT_STEP_FUSED=0 (read once per process) computes the
 same steps with two launches (the product, then the step kernel); the states must agree
 bit for bit, the doses to FP64 rounding, and both with the FP64 oracle to the product's
 precision.  The launch shapes cover full 256 x 256 tiles with a ragged last row tile, the
