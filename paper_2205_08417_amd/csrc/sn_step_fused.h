@@ -48,6 +48,34 @@ __device__ __forceinline__ void static_for(F&& f) {
 
 constexpr int kAhead = 2;            // cells whose rows are in flight ahead of the update
 
+// This wave's accumulators of slab s (tile rows [rs, re)) into the LDS slab sl: column
+// slabs hold blocks j = jj * NS + s at slab column (w4 * JS + jj) * 32; row slabs every block
+// of the rows they hold.  exp_of undoes the FP16 row scaling.
+template <bool RS, int NS, int W, int JS, int IM, int JN, typename Acc, typename ExpOf>
+__device__ __forceinline__ void slab_store(Acc (&acc)[IM][JN], const gemm::TileInfo& t, int s,
+                                           int rs, int re, ExpOf exp_of,
+                                           float* __restrict__ sl) {
+    const int lane = t.lane;
+    const int w4 = __builtin_amdgcn_readfirstlane(t.wave) & 3;
+#pragma unroll
+    for (int i = 0; i < IM; ++i) {
+        if (RS && (t.wm + i * 32 < rs || t.wm + i * 32 >= re)) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int lr = t.wm + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+            const int sr = lr - rs;
+            const int e = exp_of(t.m0 + lr);
+#pragma unroll
+            for (int jj = 0; jj < JS; ++jj) {
+                const int j = RS ? jj : jj * NS + s;
+                const int lc = (w4 * JS + jj) * 32 + (lane & 31);
+                const float v = e != 0 ? __builtin_ldexpf(acc[i][j][r], e) : acc[i][j][r];
+                sl[sr * W + (lc ^ slab_swz(sr))] = v;
+            }
+        }
+    }
+}
+
 // The update of one block tile: acc holds S for rows m0 + [0, BM) of a sub-product whose
 // row 0 is cell row0 (M rows in all), columns n0 + [0, BN); exp_of undoes the FP16 row
 // scaling.
@@ -71,7 +99,6 @@ __device__ __forceinline__ void step_tile(Acc (&acc)[IM][JN], const gemm::TileIn
     constexpr int MF = 3;
     const int lane = t.lane;
     const int wave = __builtin_amdgcn_readfirstlane(t.wave);
-    const int w4 = wave & 3;                                // the wave's column group
     const int64_t trows = M - t.m0 < BM ? M - t.m0 : BM;    // rows of this tile (> 0)
 
     FwdCtx<float> cx;
@@ -97,25 +124,7 @@ __device__ __forceinline__ void step_tile(Acc (&acc)[IM][JN], const gemm::TileIn
         const int rs = RS && s == 1 ? kRowSplit : 0;
         const int re = RS && s == 0 ? kRowSplit : BM;
         __syncthreads();              // the K loop's planes, or the previous slab, are done
-        // this wave's blocks of the slab: column slabs hold blocks j = jj * NS + s at slab
-        // column (w4 * JS + jj) * 32; row slabs every block of the rows they hold
-#pragma unroll
-        for (int i = 0; i < IM; ++i) {
-            if (RS && (t.wm + i * 32 < rs || t.wm + i * 32 >= re)) continue;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int lr = t.wm + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-                const int sr = lr - rs;
-                const int e = exp_of(t.m0 + lr);
-#pragma unroll
-                for (int jj = 0; jj < JS; ++jj) {
-                    const int j = RS ? jj : jj * NS + s;
-                    const int lc = (w4 * JS + jj) * 32 + (lane & 31);
-                    const float v = e != 0 ? __builtin_ldexpf(acc[i][j][r], e) : acc[i][j][r];
-                    sl[sr * W + (lc ^ slab_swz(sr))] = v;
-                }
-            }
-        }
+        slab_store<RS, NS, W, JS>(acc, t, s, rs, re, exp_of, sl);
         __syncthreads();
         const int nrow = (trows < re ? (int)trows : re) - rs;   // rows of the slab in M
         if (wave >= nrow) continue;
@@ -306,6 +315,152 @@ hipError_t launch_gemm_step_t(const float* A, const uint16_t* Bhi, const uint16_
         hipLaunchKernelGGL((k_gemm_step<PP == 0, PP == 0 ? 3 : PP, 64, TN, SG, RHO, DOSE>), grid,
                            dim3(gemm::kThreads), 0, st, A, Bhi, Blo, p.rows1, M, K, N, rexp, eb,
                            nmain, se);
+        return hipGetLastError();
+    };
+    auto by_tn = [&](auto p_c, auto sg_c) {
+        return p.tn == 128 ? go(p_c, std::integral_constant<int, 128>{}, sg_c)
+                           : go(p_c, std::integral_constant<int, 256>{}, sg_c);
+    };
+    auto by_sg = [&](auto p_c) {
+        return stagger ? by_tn(p_c, std::true_type{}) : by_tn(p_c, std::false_type{});
+    };
+    switch (products) {
+        case 0: return by_sg(std::integral_constant<int, 0>{});
+        case 3: return by_sg(std::integral_constant<int, 3>{});
+        case 2: return by_sg(std::integral_constant<int, 2>{});
+        default: return by_sg(std::integral_constant<int, 1>{});
+    }
+}
+
+// The last factor of the mode-space IMEX solve (IMEX step of Sec. 4.2) in the same tile
+// form: acc holds S for its cells and ordinates, out holds the collision-free step r, and
+// each element becomes x - x y with x = r + S and y = c / (1 + c), c = dt alpha_t sigma_t of
+// the cell (the kCombine epilogue's arithmetic), written over r.  Rows run at full width
+// through the row slabs with V = 4 ordinates per lane; y of the wave's cells sits in lanes.
+template <int BM, int BN, int D, int IM, int JN, typename Acc, typename ExpOf>
+__device__ __forceinline__ void combine_tile(Acc (&acc)[IM][JN], const gemm::TileInfo& t,
+                                             int64_t row0, int64_t M, ExpOf exp_of,
+                                             float* __restrict__ sl, const CombineEpi& ce)
+{
+    constexpr int NS = BM * BN <= kSlabFloats ? 1 : 2;
+    static_assert(kRowSlabs || NS == 1, "the combine runs on row slabs");
+    constexpr bool RS = NS == 2;
+    constexpr int W = BN, V = W / 64;
+    const int lane = t.lane;
+    const int wave = __builtin_amdgcn_readfirstlane(t.wave);
+    const int64_t trows = M - t.m0 < BM ? M - t.m0 : BM;
+    const uint32_t row_bytes = (uint32_t)ce.nq * (uint32_t)sizeof(float);
+    const __amdgpu_buffer_rsrc_t out = make_rsrc(ce.out, (uint32_t)ce.nc * row_bytes);
+    const uint32_t cb = (uint32_t)t.n0 * (uint32_t)sizeof(float);
+    const int64_t base = row0 + t.m0;
+    const int q0 = lane * V;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int rs = RS && s == 1 ? kRowSplit : 0;
+        const int re = RS && s == 0 ? kRowSplit : BM;
+        __syncthreads();
+        slab_store<RS, NS, W, JN>(acc, t, s, rs, re, exp_of, sl);
+        __syncthreads();
+        const int nrow = (trows < re ? (int)trows : re) - rs;
+        if (wave >= nrow) continue;
+        auto cell = [&](int k) {
+            return uniform_cell((int32_t)(base + rs + (k < nrow ? k : nrow - 1)));
+        };
+        const int U = (nrow - wave + 7) / 8;                    // <= kRowSplit / 8 <= 32
+        float ly;                                               // y of the wave's cell n
+        {
+            const int kk = wave + 8 * (lane < 32 ? lane : 31);
+            const int32_t c = (int32_t)(base + rs + (kk < nrow ? kk : nrow - 1));
+            const float cabs = ce.dt * ce.alpha_t * ce.sigma_t[c];
+            ly = cabs / (1.0f + cabs);
+        }
+        float st[D + 1][V];
+        auto fetch = [&](auto slot_c, int n) {
+            constexpr int SL = decltype(slot_c)::value;
+            buf_load_row<V, true, float>(out, (uint32_t)cell(wave + 8 * n) * row_bytes + cb, q0,
+                                         ce.nq, st[SL]);
+        };
+        auto update = [&](auto slot_c, int n) {
+            constexpr int SL = decltype(slot_c)::value;
+            const int k = wave + 8 * n;
+            const float y = __builtin_bit_cast(
+                float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, ly), n));
+            const float* p = sl + k * W + (q0 ^ slab_swz(k));
+            float o[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const float x = st[SL][v] + p[v];
+                o[v] = __builtin_fmaf(-x, y, x);
+            }
+            buf_store_row<V, true, float, kAuxStream>(out, (uint32_t)cell(k) * row_bytes + cb,
+                                                      q0, ce.nq, o);
+        };
+        static_for<0, D>([&](auto d_c) { fetch(d_c, decltype(d_c)::value); });
+        for (int n = 0; n < U; n += D + 1) {
+            static_for<0, D + 1>([&](auto p_c) {
+                constexpr int P = decltype(p_c)::value;
+                if (n + P < U) {
+                    fetch(std::integral_constant<int, (P + D) % (D + 1)>{}, n + P + D);
+                    update(p_c, n + P);
+                }
+            });
+        }
+    }
+}
+
+template <bool F16, int P, int TM, int TN, bool STAGGER>
+__global__ __launch_bounds__(gemm::kThreads) void k_gemm_combine(
+    const float* __restrict__ A, const uint16_t* __restrict__ Bhi,
+    const uint16_t* __restrict__ Blo, int64_t M1, int64_t M, int32_t K, int32_t N,
+    const int32_t* __restrict__ rexp, int32_t eb, int64_t nmain, CombineEpi ce)
+{
+    constexpr int NP = P == 3 ? 4 : P == 2 ? 3 : 2;
+    constexpr int kPlanes = 2 * NP * gemm::kPlane;
+    constexpr int kSlab = kRowSlabs ? kRowSplit * 256 : kSlabFloats;
+    constexpr int kU16 = kPlanes > 2 * kSlab ? kPlanes : 2 * kSlab;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[kU16];
+    float* sl = reinterpret_cast<float*>(lds);
+    const int64_t b = blockIdx.x;
+    if (b < nmain) {
+        gemm::gemm_block<P, 256, 256, 1, STAGGER, F16>(
+            A, Bhi, Blo, M1, K, N, rexp, eb, xcd_remap(b, nmain), lds,
+            [&](auto& acc, const gemm::TileInfo& t, auto, auto exp_of) {
+                combine_tile<256, 256, kAhead>(acc, t, 0, M1, exp_of, sl, ce);
+            });
+    } else {
+        const int64_t nt = (int64_t)gridDim.x - nmain;
+        gemm::gemm_block<P, TM, TN, 4, STAGGER, F16>(
+            A + M1 * K, Bhi, Blo, M - M1, K, N, F16 ? rexp + M1 : rexp, eb,
+            xcd_remap(b - nmain, nt), lds,
+            [&](auto& acc, const gemm::TileInfo& t, auto, auto exp_of) {
+                combine_tile<TM, TN, kAhead>(acc, t, M1, M - M1, exp_of, sl, ce);
+            });
+    }
+}
+
+inline hipError_t launch_gemm_combine_impl(const float* A, const uint16_t* Bhi,
+                                           const uint16_t* Blo, int64_t M, int32_t K,
+                                           int32_t N, int products, const int32_t* rexp,
+                                           int32_t eb, const CombineEpi& ce, hipStream_t st)
+{
+    if (M == 0) return hipSuccess;
+    if (products < 0 || products > 3) return hipErrorInvalidValue;
+    if (K % 32 != 0 || K == 0 || N % 256 != 0 || N != ce.nq || M != ce.nc ||
+        (products == 0 && !rexp))
+        return hipErrorNotSupported;
+    const GemmPlan p = gemm_plan(M, N);
+    if (p.mbn != 256) return hipErrorNotSupported;
+    const int64_t nmain = ((p.rows1 + 255) / 256) * (N / 256);
+    const int64_t ntail = ((M - p.rows1 + p.tm - 1) / p.tm) * (N / p.tn);
+    const dim3 grid((unsigned)(nmain + ntail));
+    const bool stagger = tune().gemm_stagger && K >= 256 && N >= 256;
+    auto go = [&](auto p_c, auto tn_c, auto sg_c) {
+        constexpr int PP = decltype(p_c)::value;
+        constexpr int TN = decltype(tn_c)::value;
+        constexpr bool SG = decltype(sg_c)::value;
+        hipLaunchKernelGGL((k_gemm_combine<PP == 0, PP == 0 ? 3 : PP, 64, TN, SG>), grid,
+                           dim3(gemm::kThreads), 0, st, A, Bhi, Blo, p.rows1, M, K, N, rexp, eb,
+                           nmain, ce);
         return hipGetLastError();
     };
     auto by_tn = [&](auto p_c, auto sg_c) {

@@ -1251,7 +1251,19 @@ hipError_t imex_modes(const snrt_mesh* m, const snrt_quad* q, const DenseB& B,
             }
         }
         if (e == hipSuccess) {
-            if (product_fuses_epi(B, ops[1])) {
+            const GemmOperand& o1 = ops[1];
+            if (product_fuses_epi(B, o1) && B.precision != SNRT_FP32 && o1.hi &&
+                o1.N == q->nq && o1.Np == q->nq && q->nq % 256 == 0) {
+                // the combine on the product's tiles staged in LDS, full rows per wave
+                const int products = B.precision == SNRT_FP16X3 ? 0
+                                     : B.precision == SNRT_BF16X3 ? 3
+                                     : B.precision == SNRT_BF16X2 ? 2 : 1;
+                if (products == 0) e = launch_row_exp_f16(U, m->nc, o1.K, rexp, st);
+                const CombineEpi ce{a32.sigma_t, a32.dt, a32.alpha_t, psi_out, m->nc, q->nq};
+                if (e == hipSuccess)
+                    e = launch_gemm_combine(U, o1.hi, o1.lo, m->nc, o1.K, o1.Np, products, rexp,
+                                            o1.eb, ce, st);
+            } else if (product_fuses_epi(B, o1)) {
                 e = product32(B, ops[1], U, psi_out, m->nc, rexp, st, combine);
             } else {
                 e = product32(B, ops[1], U, S, m->nc, rexp, st);

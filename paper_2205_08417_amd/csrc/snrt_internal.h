@@ -358,6 +358,21 @@ struct StepEpi {
     const double* wq;
     double* dpart;
 };
+// The mode-space IMEX combine in the same one-launch form (the last product of
+// snrt_step_imex_dense / _moments): out [nc][nq] holds the collision-free step r and
+// receives x - x y, x = r + (A X)[c][q], y = c / (1 + c), c = dt alpha_t sigma_t[c].
+struct CombineEpi {
+    const float* sigma_t;
+    float dt, alpha_t;
+    float* out;
+    int64_t nc;
+    int32_t nq;
+};
+hipError_t launch_gemm_combine(const float* A, const uint16_t* Bhi, const uint16_t* Blo,
+                               int64_t M, int32_t K, int32_t N, int products,
+                               const int32_t* rexp, int32_t eb, const CombineEpi& ce,
+                               hipStream_t st);
+
 namespace fused {
 template <bool RHO, bool DOSE>
 hipError_t launch_gemm_step_t(const float* A, const uint16_t* Bhi, const uint16_t* Blo,
