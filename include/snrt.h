@@ -213,7 +213,11 @@ typedef struct {
 } snrt_step_args_f64;
 
 /* One explicit Euler S_N step, FP32: psi_out = step(psi_in).  ws: device workspace of at
- * least snrt_workspace_size bytes (may be NULL for isotropic scattering). */
+ * least snrt_workspace_size bytes (may be NULL for isotropic scattering).  With a dense or
+ * moment-form scatter handle in a BF16 / FP16 precision, triangles and nq % 256 == 0 the step
+ * runs as one launch: the scattering product's tiles update their cells and ordinates, and
+ * S = Psi B never reaches the workspace (the environment variable SNRT_STEP_FUSED=0, read
+ * once per process, selects the product-then-step form; both give the same bits). */
 snrt_status snrt_step(const snrt_mesh* mesh, const snrt_quad* quad, const snrt_scatter* scatter,
                       const snrt_step_args* args, const float* psi_in, float* psi_out,
                       void* ws, size_t ws_bytes, void* stream);
@@ -223,8 +227,9 @@ snrt_status snrt_step(const snrt_mesh* mesh, const snrt_quad* quad, const snrt_s
  * endpoint) instead of a second pass over psi_in:
  *     dose[i] += coeff * inv_rho[i] * sum_q w_q psi_in[i][q]   (FP64; inv_rho NULL = 1)
  * psi_out is bitwise the output of snrt_step; the dose agrees with snrt_dose_accumulate to
- * FP64 rounding (the sum is formed per 256-ordinate row chunk of the dense step, then the
- * chunks are added in order; deterministic).  ws: at least snrt_workspace_size bytes,
+ * FP64 rounding (the sum is formed per row piece of the dense step: 128 ordinates in the
+ * one-launch form, 256 in the two-launch form; then the pieces are added in order;
+ * deterministic).  ws: at least snrt_workspace_size bytes,
  * 16-byte aligned.  dose must not overlap the states or the workspace (SNRT_E_ALIAS);
  * SNRT_E_NONFINITE for a non-finite coeff. */
 snrt_status snrt_step_dose(const snrt_mesh* mesh, const snrt_quad* quad,
