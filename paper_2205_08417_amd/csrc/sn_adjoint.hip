@@ -14,9 +14,9 @@ hipError_t launch_adjoint32(const snrt_mesh& m, const snrt_quad& q, const StepAr
 hipError_t launch_adjoint32_acc64(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
                                   const float* psi_n, const float* lam_np1, float* lam_n,
                                   double* g_t, double* g_s, double* g_r, const float* G,
-                                  hipStream_t st) {
+                                  hipStream_t st, const DoseAdj& da) {
     return launch_adjoint_t<float, double>(m.geom32, m, q.tab32, q.nq, a, psi_n, lam_np1, lam_n,
-                                           g_t, g_s, g_r, G, st);
+                                           g_t, g_s, g_r, G, st, da);
 }
 
 hipError_t launch_adjoint64(const snrt_mesh& m, const snrt_quad& q, const StepArgs64& a,

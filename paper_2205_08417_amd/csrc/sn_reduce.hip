@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kStepBlock) void k_dose_adjoint(const double* __res
         float r[V];
         load_slice<V, EXACT>(row, q0, nq, r);
 #pragma unroll
-        for (int k = 0; k < V; ++k) r[k] = (float)((double)r[k] + g * wv[k]);
+        for (int k = 0; k < V; ++k) r[k] = (float)__builtin_fma(g, wv[k], (double)r[k]);
         store_slice<V, EXACT>(row, q0, nq, r, false);
     }
 }

@@ -591,12 +591,27 @@ __global__ __launch_bounds__(kStepBlock) void k_step_dose(
 // Adjoint for wide rows (more than 32 bytes of each row per lane, where the pipelined form
 // below would hold two stages of them in registers): one wavefront per cell.  GT is the type
 // of the gradient accumulators (T, or double so that long runs accumulate in FP64).
-template <int V, bool EXACT, bool DENSE, typename T, typename GT = T>
+// lam_q += coeff (1/rho_c) g_dose[c] w_q in FP64 on an output row of the transposed step (the
+// dose functional's term of the reverse rollout, snrt_dose_adjoint's arithmetic).
+template <int V, bool EXACT>
+__device__ __forceinline__ void dose_adjoint_row(float (&o)[V], const DoseAdj& da,
+                                                 const float* __restrict__ inv_rho, int32_t c,
+                                                 int q0, int32_t nq) {
+    const double g = da.coeff * (inv_rho ? (double)inv_rho[c] : 1.0) * da.g_dose[c];
+    double wv[V];
+    load_slice<V, EXACT>(da.w, q0, nq, wv);
+#pragma unroll
+    for (int k = 0; k < V; ++k) o[k] = (float)__builtin_fma(g, wv[k], (double)o[k]);
+}
+
+// DA: the dose functional's term (dose_adjoint_row) on the output rows (FP32 state, FP64
+// gradients only)
+template <int V, bool EXACT, bool DENSE, typename T, typename GT = T, bool DA = false>
 __global__ __launch_bounds__(kStepBlock) void k_adjoint(
     const typename GeomOf<T>::type* __restrict__ geom, int64_t nc, int32_t mf, int32_t nq,
     const T* __restrict__ tab, typename ArgsOf<T>::type a, const T* __restrict__ psi_n,
     const T* __restrict__ lam_np1, T* __restrict__ lam_n, GT* __restrict__ g_t,
-    GT* __restrict__ g_s, GT* __restrict__ g_r, const T* __restrict__ G)
+    GT* __restrict__ g_s, GT* __restrict__ g_r, const T* __restrict__ G, DoseAdj da)
 {
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -684,6 +699,7 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint(
         part_t += l[j] * p[j];
         part_r += p[j] * x[j];
     }
+    if constexpr (DA) dose_adjoint_row<V, EXACT>(o, da, a.inv_rho, (int32_t)c, q0, nq);
     store_slice<V, EXACT>(lam_n + c * (int64_t)nq, q0, nq, o);
 
     if (g_t) {
@@ -723,7 +739,9 @@ struct AdjCtx {
     uint32_t row_bytes;
     bool neumann;
     GT *g_t, *g_s, *g_r;
+    DoseAdj da;       // the dose functional's term of a reverse rollout (g_dose NULL: none)
 };
+
 
 template <int V, bool EXACT, int MF, bool DENSE, typename T, typename GT>
 __device__ __forceinline__ void adj_load_stage(AdjStage<V, MF, DENSE, T, GT>& d,
@@ -760,7 +778,7 @@ __device__ __forceinline__ void adj_load_stage(AdjStage<V, MF, DENSE, T, GT>& d,
     d.gr0 = x.g_r ? cell_val(x.g_r, c) : GT(0);
 }
 
-template <int V, bool EXACT, int MF, bool DENSE, typename T, typename GT>
+template <int V, bool EXACT, int MF, bool DENSE, typename T, typename GT, bool DA = false>
 __device__ __forceinline__ void adj_compute(const AdjStage<V, MF, DENSE, T, GT>& d,
                                             const T (&ox)[V], const T (&oy)[V],
                                             const T (&wi)[V], int32_t c, int32_t nq, int q0,
@@ -810,6 +828,7 @@ __device__ __forceinline__ void adj_compute(const AdjStage<V, MF, DENSE, T, GT>&
         part_t += d.l[j] * d.p[j];
         part_r += d.p[j] * xs[j];
     }
+    if constexpr (DA) dose_adjoint_row<V, EXACT>(o, x.da, a.inv_rho, c, q0, nq);
     buf_store_row<V, EXACT, T, kAuxStream>(x.out, (uint32_t)c * x.row_bytes, q0, nq, o);
     if (x.g_t) {
         const T s = cell_sum(part_t);
@@ -825,12 +844,13 @@ __device__ __forceinline__ void adj_compute(const AdjStage<V, MF, DENSE, T, GT>&
     }
 }
 
-template <int V, bool EXACT, int MF, bool DENSE, typename T, typename GT = T>
+template <int V, bool EXACT, int MF, bool DENSE, typename T, typename GT = T, bool DA = false>
 __global__ __launch_bounds__(kStepBlock) void k_adjoint_p(
     const typename GeomOf<T>::type* __restrict__ geom, int64_t nc, int32_t nq,
     const T* __restrict__ tab, typename ArgsOf<T>::type a, const T* __restrict__ psi_n,
     const T* __restrict__ lam_np1, T* __restrict__ lam_n, GT* __restrict__ g_t,
-    GT* __restrict__ g_s, GT* __restrict__ g_r, const T* __restrict__ G, int64_t items_per_xcd)
+    GT* __restrict__ g_s, GT* __restrict__ g_r, const T* __restrict__ G, int64_t items_per_xcd,
+    DoseAdj da)
 {
     const int x = blockIdx.x % kNumXcd;
     const int kx = blockIdx.x / kNumXcd;
@@ -855,6 +875,7 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint_p(
     cx.g_t = g_t;
     cx.g_s = g_s;
     cx.g_r = g_r;
+    cx.da = da;
     // prefetches address the clamped cell min(c', xend-1): always in bounds
     auto clampc = [xend](int32_t cc) { return uniform_cell(cc < xend ? cc : xend - 1); };
 
@@ -871,13 +892,15 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint_p(
     for (;;) {
         adj_load_stage<V, EXACT, MF, DENSE>(sb, n1, geom, clampc(c + stride), nq, q0, a, cx);
         fwd_load_nbr<MF, T>(n2, geom, clampc(c + 2 * stride));
-        adj_compute<V, EXACT, MF, DENSE>(sa, ox, oy, wi, clampc(c), nq, q0, lane, a, cx);
+        adj_compute<V, EXACT, MF, DENSE, T, GT, DA>(sa, ox, oy, wi, clampc(c), nq, q0, lane, a,
+                                                    cx);
         c += stride;
         if (c >= xend) break;
         n1 = n2;
         adj_load_stage<V, EXACT, MF, DENSE>(sa, n1, geom, clampc(c + stride), nq, q0, a, cx);
         fwd_load_nbr<MF, T>(n2, geom, clampc(c + 2 * stride));
-        adj_compute<V, EXACT, MF, DENSE>(sb, ox, oy, wi, clampc(c), nq, q0, lane, a, cx);
+        adj_compute<V, EXACT, MF, DENSE, T, GT, DA>(sb, ox, oy, wi, clampc(c), nq, q0, lane, a,
+                                                    cx);
         c += stride;
         if (c >= xend) break;
         n1 = n2;
@@ -1034,40 +1057,51 @@ template <typename T, typename GT = T>
 hipError_t launch_adjoint_t(const typename GeomOf<T>::type* geom, const snrt_mesh& m,
                             const T* tab, int32_t nq, const typename ArgsOf<T>::type& a,
                             const T* psi_n, const T* lam_np1, T* lam_n, GT* g_t, GT* g_s,
-                            GT* g_r, const T* G, hipStream_t st)
+                            GT* g_r, const T* G, hipStream_t st, const DoseAdj& da = DoseAdj())
 {
     if (m.nc == 0) return hipSuccess;
-    return dispatch_v<T>(nq, [&](auto vc, auto ex) {
-        constexpr int V = decltype(vc)::value;
-        constexpr bool E = decltype(ex)::value;
-        if constexpr (V * sizeof(T) > 32) {
-            const unsigned blocks = (unsigned)((m.nc + kCellsPerBlock - 1) / kCellsPerBlock);
-            if (G)
-                hipLaunchKernelGGL((k_adjoint<V, E, true, T, GT>), dim3(blocks),
-                                   dim3(kStepBlock), 0, st, geom, m.nc, m.mf, nq, tab, a, psi_n,
-                                   lam_np1, lam_n, g_t, g_s, g_r, G);
-            else
-                hipLaunchKernelGGL((k_adjoint<V, E, false, T, GT>), dim3(blocks),
-                                   dim3(kStepBlock), 0, st, geom, m.nc, m.mf, nq, tab, a, psi_n,
-                                   lam_np1, lam_n, g_t, g_s, g_r, G);
-            return hipGetLastError();
-        } else {
-            auto go = [&](auto mfc, auto dc) {
-                constexpr int MF = decltype(mfc)::value;
-                constexpr bool D = decltype(dc)::value;
-                static const int occ = resident_blocks(k_adjoint_p<V, E, MF, D, T, GT>);
-                const StepShape sh = step_shape(m, m.nc, 1, occ, tune().adjoint_blocks_per_cu);
-                hipLaunchKernelGGL((k_adjoint_p<V, E, MF, D, T, GT>), dim3(sh.blocks),
-                                   dim3(kStepBlock), 0, st, geom, m.nc, nq, tab, a, psi_n,
-                                   lam_np1, lam_n, g_t, g_s, g_r, G, sh.cells_per_xcd);
+    constexpr bool kCanDA = std::is_same<T, float>::value && std::is_same<GT, double>::value;
+    if (da.g_dose && !kCanDA) return hipErrorInvalidValue;
+    auto with_da = [&](auto da_c) {
+        constexpr bool DA = decltype(da_c)::value;
+        return dispatch_v<T>(nq, [&](auto vc, auto ex) {
+            constexpr int V = decltype(vc)::value;
+            constexpr bool E = decltype(ex)::value;
+            if constexpr (V * sizeof(T) > 32) {
+                const unsigned blocks = (unsigned)((m.nc + kCellsPerBlock - 1) / kCellsPerBlock);
+                if (G)
+                    hipLaunchKernelGGL((k_adjoint<V, E, true, T, GT, DA>), dim3(blocks),
+                                       dim3(kStepBlock), 0, st, geom, m.nc, m.mf, nq, tab, a,
+                                       psi_n, lam_np1, lam_n, g_t, g_s, g_r, G, da);
+                else
+                    hipLaunchKernelGGL((k_adjoint<V, E, false, T, GT, DA>), dim3(blocks),
+                                       dim3(kStepBlock), 0, st, geom, m.nc, m.mf, nq, tab, a,
+                                       psi_n, lam_np1, lam_n, g_t, g_s, g_r, G, da);
                 return hipGetLastError();
-            };
-            using I3 = std::integral_constant<int, 3>;
-            using I4 = std::integral_constant<int, 4>;
-            if (m.mf == 4) return G ? go(I4{}, std::true_type{}) : go(I4{}, std::false_type{});
-            return G ? go(I3{}, std::true_type{}) : go(I3{}, std::false_type{});
-        }
-    });
+            } else {
+                auto go = [&](auto mfc, auto dc) {
+                    constexpr int MF = decltype(mfc)::value;
+                    constexpr bool D = decltype(dc)::value;
+                    static const int occ = resident_blocks(k_adjoint_p<V, E, MF, D, T, GT, DA>);
+                    const StepShape sh =
+                        step_shape(m, m.nc, 1, occ, tune().adjoint_blocks_per_cu);
+                    hipLaunchKernelGGL((k_adjoint_p<V, E, MF, D, T, GT, DA>), dim3(sh.blocks),
+                                       dim3(kStepBlock), 0, st, geom, m.nc, nq, tab, a, psi_n,
+                                       lam_np1, lam_n, g_t, g_s, g_r, G, sh.cells_per_xcd, da);
+                    return hipGetLastError();
+                };
+                using I3 = std::integral_constant<int, 3>;
+                using I4 = std::integral_constant<int, 4>;
+                if (m.mf == 4)
+                    return G ? go(I4{}, std::true_type{}) : go(I4{}, std::false_type{});
+                return G ? go(I3{}, std::true_type{}) : go(I3{}, std::false_type{});
+            }
+        });
+    };
+    if constexpr (kCanDA) {
+        if (da.g_dose) return with_da(std::true_type{});
+    }
+    return with_da(std::false_type{});
 }
 
 }  // namespace snrt

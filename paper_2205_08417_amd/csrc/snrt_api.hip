@@ -917,7 +917,8 @@ template <typename GT>
 snrt_status step_adjoint32_t(const char* fn, const snrt_mesh* m, const snrt_quad* q,
                              const snrt_scatter* sc, const snrt_step_args* a,
                              const float* psi_n, const float* lam_np1, float* lam_n, GT* g_t,
-                             GT* g_s, GT* g_r, void* ws, size_t ws_bytes, void* stream) {
+                             GT* g_s, GT* g_r, void* ws, size_t ws_bytes, void* stream,
+                             const DoseAdj& da = DoseAdj()) {
     SNRT_TRY(check_step_common(fn, m, q, sc, a, sizeof(float), lam_np1, lam_n, ws, ws_bytes));
     if (m->nc == 0) return SNRT_OK;
     SNRT_REQUIRE(psi_n && aligned16(psi_n), SNRT_E_ARG,
@@ -936,7 +937,8 @@ snrt_status step_adjoint32_t(const char* fn, const snrt_mesh* m, const snrt_quad
     }
     hipError_t e;
     if constexpr (std::is_same<GT, double>::value)
-        e = launch_adjoint32_acc64(*m, *q, to32(a), psi_n, lam_np1, lam_n, g_t, g_s, g_r, G, st);
+        e = launch_adjoint32_acc64(*m, *q, to32(a), psi_n, lam_np1, lam_n, g_t, g_s, g_r, G, st,
+                                   da);
     else
         e = launch_adjoint32(*m, *q, to32(a), psi_n, lam_np1, lam_n, g_t, g_s, g_r, G, st);
     return e == hipSuccess ? SNRT_OK : hip_fail(e, (std::string(fn) + ": launch").c_str());
@@ -945,9 +947,10 @@ snrt_status step_adjoint32_t(const char* fn, const snrt_mesh* m, const snrt_quad
 snrt_status step_adjoint32_acc64(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
                                  const snrt_step_args* a, const float* psi_n,
                                  const float* lam_np1, float* lam_n, double* g_t, double* g_s,
-                                 double* g_r, void* ws, size_t ws_bytes, void* stream) {
+                                 double* g_r, void* ws, size_t ws_bytes, void* stream,
+                                 const DoseAdj& da) {
     return step_adjoint32_t<double>("snrt_rollout_adjoint", m, q, sc, a, psi_n, lam_np1, lam_n,
-                                    g_t, g_s, g_r, ws, ws_bytes, stream);
+                                    g_t, g_s, g_r, ws, ws_bytes, stream, da);
 }
 
 }  // namespace snrt

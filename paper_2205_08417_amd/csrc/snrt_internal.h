@@ -240,6 +240,14 @@ inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 
 void real_harmonics(int N, double x, double y, double z, double* out);
 
 // Kernel launchers (return hipGetLastError() after the launch).
+// The dose functional's term of a reverse rollout fused into the transposed step's output:
+// lam_q += coeff (1/rho_c) g_dose[c] w_q (FP64; w: FP64 weights [nq]); g_dose NULL: none.
+struct DoseAdj {
+    const double* w = nullptr;
+    double coeff = 0.0;
+    const double* g_dose = nullptr;
+};
+
 struct StepArgs32 {
     const float *sigma_t, *sigma_s, *inv_rho, *source, *inflow;
     float inflow_scale, dt, alpha_t, alpha_s;
@@ -262,7 +270,8 @@ StepArgs32 step_args32(const snrt_step_args* a);
 snrt_status step_adjoint32_acc64(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
                                  const snrt_step_args* a, const float* psi_n,
                                  const float* lam_np1, float* lam_n, double* g_t, double* g_s,
-                                 double* g_r, void* ws, size_t ws_bytes, void* stream);
+                                 double* g_r, void* ws, size_t ws_bytes, void* stream,
+                                 const DoseAdj& da = DoseAdj());
 
 // dose_part: with the fused dose, the [nc * items per row] FP64 weighted sums of psi_in
 hipError_t launch_step32(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
@@ -289,7 +298,8 @@ hipError_t launch_adjoint32(const snrt_mesh& m, const snrt_quad& q, const StepAr
 hipError_t launch_adjoint32_acc64(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
                                   const float* psi_n, const float* lam_np1, float* lam_n,
                                   double* g_t, double* g_s, double* g_r, const float* G,
-                                  hipStream_t st);
+                                  hipStream_t st,
+                                  const DoseAdj& da = DoseAdj());
 hipError_t launch_adjoint64(const snrt_mesh& m, const snrt_quad& q, const StepArgs64& a,
                             const double* psi_n, const double* lam_np1, double* lam_n,
                             double* g_t, double* g_s, double* g_r, const double* G,

@@ -31,12 +31,13 @@ template <> struct Api<float> {
                             void* st) {
         return snrt_step(m, q, sc, a, in, out, ws, wsb, st);
     }
-    // gradients accumulate in FP64 across the steps of a reverse pass
+    // gradients accumulate in FP64 across the steps of a reverse pass; da: the dose
+    // functional's term, added to the transposed step's output rows
     static snrt_status adjoint(const snrt_mesh* m, const snrt_quad* q, const snrt_scatter* sc,
                                const Args* a, const float* psi, const float* l1, float* l0,
                                double* gt, double* gs, double* gr, void* ws, size_t wsb,
-                               void* st) {
-        return step_adjoint32_acc64(m, q, sc, a, psi, l1, l0, gt, gs, gr, ws, wsb, st);
+                               void* st, const DoseAdj& da = DoseAdj()) {
+        return step_adjoint32_acc64(m, q, sc, a, psi, l1, l0, gt, gs, gr, ws, wsb, st, da);
     }
 };
 template <> struct Api<double> {
@@ -167,12 +168,24 @@ snrt_status rollout_adjoint_t(const char* fn, const snrt_mesh* m, const snrt_qua
         for (int64_t i = L - 1; i >= 0 && s == SNRT_OK; --i) {
             const int64_t n = n0 + i;
             const auto an = step_n(*a, sched, n);
-            s = Api<T>::adjoint(m, q, sc, &an, states[i], pl, pn, g_t, g_s, g_r, ws, ws_bytes,
-                                stream);
             if constexpr (std::is_same<T, float>::value) {
-                if (s == SNRT_OK && g_dose)
+                // the dose functional's term rides on the transposed step's output (one pass
+                // over lam instead of two); SNRT_STEP_FUSED=0 keeps it a pass of its own
+                DoseAdj da;
+                const bool fuse = g_dose && tune().step_fused;
+                if (fuse) {
+                    da.w = q->tab64 + 2 * (int64_t)q->nq;
+                    da.coeff = sched->dose_coeff[n];
+                    da.g_dose = g_dose;
+                }
+                s = Api<T>::adjoint(m, q, sc, &an, states[i], pl, pn, g_t, g_s, g_r, ws,
+                                    ws_bytes, stream, da);
+                if (s == SNRT_OK && g_dose && !fuse)
                     s = snrt_dose_adjoint(m, q, a->inv_rho, sched->dose_coeff[n], g_dose, pn,
                                           stream);
+            } else {
+                s = Api<T>::adjoint(m, q, sc, &an, states[i], pl, pn, g_t, g_s, g_r, ws,
+                                    ws_bytes, stream);
             }
             std::swap(pl, pn);
         }

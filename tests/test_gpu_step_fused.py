@@ -242,3 +242,53 @@ def test_fused_rollout_equals_two_launch_rollout_in_a_fresh_process():
         S.close()
         print(f"{name}: max |fused - two-launch| = {np.abs(got - sep).max():.3e}")
         assert np.array_equal(got, sep)
+
+
+def _dose_gradient(config):
+    """Density gradient of a target-minus-organ dose functional through the reverse rollout,
+    whose transposed steps carry the dose functional's term (fused unless SNRT_STEP_FUSED=0)."""
+    from paper_2205_08417_amd.solver import Solver, differentiable_rollout
+    npol, naz, precision = {"dense-64": (4, 16, "fp32"), "dense-256": (16, 16, "bf16x3")}[config]
+    P = I.build("csd_phantom_s512", n_side=14, n_polar=npol, n_azimuth=naz, nsteps=24,
+                rho_air=0.3)
+    n = P.nsteps
+    at = np.linspace(1.0, 1.3, n)
+    T = I.region_mask(P.mesh, (3.0, 7.0, 7.0, 10.0))
+    O = I.region_mask(P.mesh, (0.0, 3.5, 5.0, 10.0))
+    dJdD = P.mesh.area * (T.astype(float) - O.astype(float))
+    S = Solver(P, precision=precision)
+    r = S.cells_to_internal(P.rho).requires_grad_(True)
+    psiN, dose = differentiable_rollout(S, S.initial_state(), n, rho=r, ckpt_every=8,
+                                        alpha_t=at, alpha_s=at,
+                                        inflow_scale=np.asarray(P.meta["inflow_scale"]),
+                                        dose_coeff=np.asarray(P.meta["dose_coeff"]))
+    J = torch.sum(S.cells_to_internal(dJdD, torch.float64) * dose)
+    J.backward()
+    return r.grad.detach().cpu().numpy(), dose.detach().cpu().numpy()
+
+
+def test_reverse_rollout_dose_term_equals_separate_pass_in_a_fresh_process():
+    """The reverse rollout adds the dose functional's term to the transposed step's output
+    rows; a child process with SNRT_STEP_FUSED=0 adds it in a pass of its own (and runs the
+    forward dense steps in two launches).  The density gradients agree bit for bit; the doses
+    to FP64 rounding (the one-launch step sums them over 128-ordinate pieces, the two-launch
+    step over 256-ordinate chunks)."""
+    script = (
+        "import sys, numpy as np\n"
+        f"sys.path.insert(0, {ROOT!r}); sys.path.insert(0, {os.path.join(ROOT, 'tests')!r})\n"
+        "import test_gpu_step_fused as T\n"
+        "g, d = T._dose_gradient(sys.argv[1])\n"
+        "np.save(sys.argv[2], g); np.save(sys.argv[3], d)\n")
+    env = dict(os.environ, SNRT_STEP_FUSED="0")
+    for config in ("dense-64", "dense-256"):
+        with tempfile.TemporaryDirectory() as tmp:
+            pg, pd = os.path.join(tmp, "g.npy"), os.path.join(tmp, "d.npy")
+            print(f"child: separate dose-term pass, {config}", flush=True)
+            r = subprocess.run([sys.executable, "-c", script, config, pg, pd], env=env,
+                               capture_output=True, text=True, timeout=300)
+            assert r.returncode == 0, r.stderr[-2000:]
+            g_ref, d_ref = np.load(pg), np.load(pd)
+        g, d = _dose_gradient(config)
+        print(f"{config}: max |grad - separate| = {np.abs(g - g_ref).max():.3e}")
+        assert np.abs(d - d_ref).max() <= 1e-14 * np.abs(d_ref).max()
+        assert np.array_equal(g, g_ref)
