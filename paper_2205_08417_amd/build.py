@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libsnrt.so")
 # pool starts them early
 SOURCES = ["sn_pn13.hip", "sn_gemm_mfma.hip", "sn_step_fused.hip", "sn_step_fused_rho.hip",
            "sn_step_fused_dose.hip", "sn_step_fused_rho_dose.hip", "sn_step_fused_combine.hip",
-           "snrt_api.hip", "sn_step_f32.hip", "sn_step_f64.hip", "sn_adjoint.hip",
+           "sn_step_fused_adjoint.hip", "snrt_api.hip", "sn_step_f32.hip", "sn_step_f64.hip", "sn_adjoint.hip",
            "sn_reduce.hip", "sn_gemm_simple.hip", "sn_step2.hip", "sn_step_imex.hip",
            "sn_pn.hip", "snrt_pn_api.hip", "snrt_rollout.hip", "snrt_noalloc.hip",
            "snrt_eig.hip"]

@@ -438,15 +438,215 @@ __global__ __launch_bounds__(gemm::kThreads) void k_gemm_combine(
     }
 }
 
-inline hipError_t launch_gemm_combine_impl(const float* A, const uint16_t* Bhi,
-                                           const uint16_t* Blo, int64_t M, int32_t K,
-                                           int32_t N, int products, const int32_t* rexp,
-                                           int32_t eb, const CombineEpi& ce, hipStream_t st)
+
+// The transposed dense step of one block tile (the last transposed product's S holds
+// G = Lambda B^T for its cells and ordinates): the arithmetic of adj_compute for dense
+// scattering (adj_downwind_sum, adj_update, explicit FMAs), rows at full width through the
+// row slabs, four ordinates per lane; the cell data of the wave's cells in lanes.  DA: the
+// dose functional's term on the output rows.
+template <int BM, int BN, bool DA, int D, int IM, int JN, typename Acc, typename ExpOf>
+__device__ __forceinline__ void adjoint_tile(Acc (&acc)[IM][JN], const gemm::TileInfo& t,
+                                             int64_t row0, int64_t M, ExpOf exp_of,
+                                             float* __restrict__ sl, const AdjEpi& ae)
+{
+    constexpr int NS = BM * BN <= kSlabFloats ? 1 : 2;
+    static_assert(kRowSlabs || NS == 1, "the transposed step runs on row slabs");
+    constexpr bool RS = NS == 2;
+    constexpr int W = BN, V = W / 64;
+    constexpr int MF = 3;
+    using Stage = AdjStage<V, MF, true, float, double>;
+    const int lane = t.lane;
+    const int wave = __builtin_amdgcn_readfirstlane(t.wave);
+    const int64_t trows = M - t.m0 < BM ? M - t.m0 : BM;
+    const uint32_t row_bytes = (uint32_t)ae.nq * (uint32_t)sizeof(float);
+    const uint32_t state_bytes = (uint32_t)ae.nc * row_bytes;
+    const auto rlam = make_rsrc(ae.lam_np1, state_bytes);
+    const auto rpsi = make_rsrc(ae.psi_n, state_bytes);
+    const auto rout = make_rsrc(ae.lam_n, state_bytes);
+    const uint32_t cb = (uint32_t)t.n0 * (uint32_t)sizeof(float);
+    const int64_t base = row0 + t.m0;
+    const int q0 = lane * V;
+    const StepArgs32& a = ae.a;
+    const bool neumann = a.neumann != 0;
+    float ox[V], oy[V];
+    load_slice<V, true>(ae.tab, t.n0 + q0, ae.nq, ox);
+    load_slice<V, true>(ae.tab + ae.nq, t.n0 + q0, ae.nq, oy);
+    double wd[DA ? V : 1];
+    if constexpr (DA) load_slice<V, true>(ae.da.w, t.n0 + q0, ae.nq, wd);
+    const int npieces = ae.nq >> 7;
+    const int piece = (t.n0 >> 7) + (W == 256 ? (lane >> 5) : 0);
+    auto rl = [](float v, int l) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+    };
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int rs = RS && s == 1 ? kRowSplit : 0;
+        const int re = RS && s == 0 ? kRowSplit : BM;
+        __syncthreads();
+        slab_store<RS, NS, W, JN>(acc, t, s, rs, re, exp_of, sl);
+        __syncthreads();
+        const int nrow = (trows < re ? (int)trows : re) - rs;
+        if (wave >= nrow) continue;
+        auto cell = [&](int k) {
+            return uniform_cell((int32_t)(base + rs + (k < nrow ? k : nrow - 1)));
+        };
+        const int U = (nrow - wave + 7) / 8;                    // <= 32
+        // cell data of the wave's cell n in lane n, formed as adj_load_stage forms it
+        int32_t lsrc[MF];
+        float lian[MF], lnx[MF], lny[MF];
+        int lsign = 0;
+        float lia, lirho, lcabs, lcscat;
+        double lgd = 0.0;
+        {
+            const int kk = wave + 8 * (lane < 32 ? lane : 31);
+            const int32_t c = (int32_t)(base + rs + (kk < nrow ? kk : nrow - 1));
+            const CellGeom32* g = ae.geom + c;
+#pragma unroll
+            for (int f = 0; f < MF; ++f) {
+                const int32_t j = g->nbr[f];
+                const bool interior = j >= 0;
+                const int32_t src = interior ? j : c;
+                lsrc[f] = src;
+                lian[f] = interior ? ae.geom[src].inv_area : 0.0f;
+                lsign |= (!interior && neumann) ? (1 << f) : 0;
+                lnx[f] = g->n[f][0];
+                lny[f] = g->n[f][1];
+            }
+            lia = g->inv_area;
+            lirho = a.inv_rho ? a.inv_rho[c] : 1.0f;
+            lcabs = a.dt * a.alpha_t * a.sigma_t[c];
+            lcscat = a.dt * a.alpha_s * a.sigma_s[c];
+            if constexpr (DA)
+                lgd = ae.da.coeff * (a.inv_rho ? (double)a.inv_rho[c] : 1.0) * ae.da.g_dose[c];
+        }
+        Stage st[D + 1];
+        auto fetch = [&](auto slot_c, int n) {
+            constexpr int SL = decltype(slot_c)::value;
+            Stage& d = st[SL];
+            const int ln = n < 31 ? n : 31;
+            const uint32_t own = (uint32_t)cell(wave + 8 * n) * row_bytes + cb;
+            buf_load_row<V, true, float>(rlam, own, q0, ae.nq, d.l);
+            buf_load_row<V, true, float>(rpsi, own, q0, ae.nq, d.p);
+#pragma unroll
+            for (int f = 0; f < MF; ++f) {
+                const int32_t src = __builtin_amdgcn_readlane(lsrc[f], ln);
+                buf_load_row<V, true, float>(rlam, (uint32_t)src * row_bytes + cb, q0, ae.nq,
+                                             d.ln[f]);
+            }
+        };
+        auto update = [&](auto slot_c, int n) {
+            constexpr int SL = decltype(slot_c)::value;
+            Stage& d = st[SL];
+            const int k = wave + 8 * n;
+            const int sg = __builtin_amdgcn_readlane(lsign, n);
+#pragma unroll
+            for (int f = 0; f < MF; ++f) {
+                d.ia_n[f] = rl(lian[f], n);
+                d.nx[f] = rl(lnx[f], n);
+                d.ny[f] = rl(lny[f], n);
+                d.all_signs[f] = (sg >> f) & 1;
+            }
+            d.ia = rl(lia, n);
+            const float irho = rl(lirho, n);
+            const float cabs = rl(lcabs, n);
+            const float cscat = rl(lcscat, n);
+            const float* p = sl + k * W + (q0 ^ slab_swz(k));
+            float g[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) g[v] = p[v];
+            float xs[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) xs[v] = 0.0f;
+            adj_downwind_sum(d, ox, oy, xs);
+            const float cstream = a.dt * irho;
+            float o[V];
+            adj_update(d.l, xs, g, cabs, cstream, cscat, o);
+            float pt = 0.0f, ps = 0.0f, pr = 0.0f;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                pt = __builtin_fmaf(d.l[v], d.p[v], pt);
+                ps = __builtin_fmaf(d.p[v], g[v], ps);
+                pr = __builtin_fmaf(d.p[v], xs[v], pr);
+            }
+            if constexpr (DA) {
+                const double gd = __builtin_bit_cast(
+                    double, ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(
+                                 (int)(__builtin_bit_cast(uint64_t, lgd) >> 32), n) << 32) |
+                                (uint64_t)(uint32_t)__builtin_amdgcn_readlane(
+                                    (int)(uint32_t)__builtin_bit_cast(uint64_t, lgd), n));
+#pragma unroll
+                for (int v = 0; v < V; ++v) o[v] = (float)__builtin_fma(gd, wd[v], (double)o[v]);
+            }
+            const int32_t c = cell(k);
+            buf_store_row<V, true, float, kAuxStream>(rout, (uint32_t)c * row_bytes + cb, q0,
+                                                      ae.nq, o);
+            // the piece's gradient sums: the whole wave, or each half of it
+#pragma unroll
+            for (int off = (W == 256 ? 16 : 32); off >= 1; off >>= 1) {
+                pt += __shfl_xor(pt, off, kWave);
+                ps += __shfl_xor(ps, off, kWave);
+                pr += __shfl_xor(pr, off, kWave);
+            }
+            if ((lane & (W == 256 ? 31 : 63)) == 0) {
+                float* q = ae.part + ((int64_t)c * npieces + piece) * 3;
+                q[0] = pt;
+                q[1] = ps;
+                q[2] = pr;
+            }
+        };
+        static_for<0, D>([&](auto d_c) { fetch(d_c, decltype(d_c)::value); });
+        for (int n = 0; n < U; n += D + 1) {
+            static_for<0, D + 1>([&](auto p_c) {
+                constexpr int P = decltype(p_c)::value;
+                if (n + P < U) {
+                    fetch(std::integral_constant<int, (P + D) % (D + 1)>{}, n + P + D);
+                    update(p_c, n + P);
+                }
+            });
+        }
+    }
+}
+
+template <bool F16, int P, int TM, int TN, bool STAGGER, bool DA>
+__global__ __launch_bounds__(gemm::kThreads) void k_gemm_adjoint(
+    const float* __restrict__ A, const uint16_t* __restrict__ Bhi,
+    const uint16_t* __restrict__ Blo, int64_t M1, int64_t M, int32_t K, int32_t N,
+    const int32_t* __restrict__ rexp, int32_t eb, int64_t nmain, AdjEpi ae)
+{
+    constexpr int NP = P == 3 ? 4 : P == 2 ? 3 : 2;
+    constexpr int kPlanes = 2 * NP * gemm::kPlane;
+    constexpr int kSlab = kRowSlabs ? kRowSplit * 256 : kSlabFloats;
+    constexpr int kU16 = kPlanes > 2 * kSlab ? kPlanes : 2 * kSlab;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[kU16];
+    float* sl = reinterpret_cast<float*>(lds);
+    const int64_t b = blockIdx.x;
+    if (b < nmain) {
+        gemm::gemm_block<P, 256, 256, 1, STAGGER, F16>(
+            A, Bhi, Blo, M1, K, N, rexp, eb, xcd_remap(b, nmain), lds,
+            [&](auto& acc, const gemm::TileInfo& t, auto, auto exp_of) {
+                adjoint_tile<256, 256, DA, kAhead>(acc, t, 0, M1, exp_of, sl, ae);
+            });
+    } else {
+        const int64_t nt = (int64_t)gridDim.x - nmain;
+        gemm::gemm_block<P, TM, TN, 4, STAGGER, F16>(
+            A + M1 * K, Bhi, Blo, M - M1, K, N, F16 ? rexp + M1 : rexp, eb,
+            xcd_remap(b - nmain, nt), lds,
+            [&](auto& acc, const gemm::TileInfo& t, auto, auto exp_of) {
+                adjoint_tile<TM, TN, DA, kAhead>(acc, t, M1, M - M1, exp_of, sl, ae);
+            });
+    }
+}
+
+template <bool DA>
+hipError_t launch_gemm_adjoint_impl(const float* A, const uint16_t* Bhi, const uint16_t* Blo,
+                                    int64_t M, int32_t K, int32_t N, int products,
+                                    const int32_t* rexp, int32_t eb, const AdjEpi& ae,
+                                    hipStream_t st)
 {
     if (M == 0) return hipSuccess;
     if (products < 0 || products > 3) return hipErrorInvalidValue;
-    if (K % 32 != 0 || K == 0 || N % 256 != 0 || N != ce.nq || M != ce.nc ||
-        (products == 0 && !rexp))
+    if (K % 32 != 0 || K == 0 || N % 256 != 0 || N != ae.nq || M != ae.nc || !ae.part ||
+        (products == 0 && !rexp) || (DA && (!ae.da.w || !ae.da.g_dose)))
         return hipErrorNotSupported;
     const GemmPlan p = gemm_plan(M, N);
     if (p.mbn != 256) return hipErrorNotSupported;
@@ -458,9 +658,9 @@ inline hipError_t launch_gemm_combine_impl(const float* A, const uint16_t* Bhi,
         constexpr int PP = decltype(p_c)::value;
         constexpr int TN = decltype(tn_c)::value;
         constexpr bool SG = decltype(sg_c)::value;
-        hipLaunchKernelGGL((k_gemm_combine<PP == 0, PP == 0 ? 3 : PP, 64, TN, SG>), grid,
+        hipLaunchKernelGGL((k_gemm_adjoint<PP == 0, PP == 0 ? 3 : PP, 64, TN, SG, DA>), grid,
                            dim3(gemm::kThreads), 0, st, A, Bhi, Blo, p.rows1, M, K, N, rexp, eb,
-                           nmain, ce);
+                           nmain, ae);
         return hipGetLastError();
     };
     auto by_tn = [&](auto p_c, auto sg_c) {

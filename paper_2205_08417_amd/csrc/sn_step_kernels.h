@@ -588,9 +588,16 @@ __global__ __launch_bounds__(kStepBlock) void k_step_dose(
 
 // --------------------------------------------------------------------------- adjoint step
 
-// Adjoint for wide rows (more than 32 bytes of each row per lane, where the pipelined form
-// below would hold two stages of them in registers): one wavefront per cell.  GT is the type
-// of the gradient accumulators (T, or double so that long runs accumulate in FP64).
+// The dense transposed step's update as explicit FMAs (the transposed-step kernels and the
+// product tiles of the one-launch transposed step): o = l - cabs l - cstream xs + cscat G
+template <int V, typename T>
+__device__ __forceinline__ void adj_update(const T (&l)[V], const T (&xs)[V], const T (&g)[V],
+                                           T cabs, T cstream, T cscat, T (&o)[V]) {
+#pragma unroll
+    for (int j = 0; j < V; ++j)
+        o[j] = fma_t(cscat, g[j], fma_t(-cstream, xs[j], fma_t(-l[j], cabs, l[j])));
+}
+
 // lam_q += coeff (1/rho_c) g_dose[c] w_q in FP64 on an output row of the transposed step (the
 // dose functional's term of the reverse rollout, snrt_dose_adjoint's arithmetic).
 template <int V, bool EXACT>
@@ -604,6 +611,9 @@ __device__ __forceinline__ void dose_adjoint_row(float (&o)[V], const DoseAdj& d
     for (int k = 0; k < V; ++k) o[k] = (float)__builtin_fma(g, wv[k], (double)o[k]);
 }
 
+// Adjoint for wide rows (more than 32 bytes of each row per lane, where the pipelined form
+// below would hold two stages of them in registers): one wavefront per cell.  GT is the type
+// of the gradient accumulators (T, or double so that long runs accumulate in FP64).
 // DA: the dose functional's term (dose_adjoint_row) on the output rows (FP32 state, FP64
 // gradients only)
 template <int V, bool EXACT, bool DENSE, typename T, typename GT = T, bool DA = false>
@@ -659,9 +669,16 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint(
         const bool all_signs = !interior && a.neumann;   // Neumann ghost = own value
 #pragma unroll
         for (int j = 0; j < V; ++j) {
-            const T s = ox[j] * nx + oy[j] * ny;
-            const T d = l[j] * ia - ln[f][j] * ia_n[f];
-            x[j] += (s > T(0) || all_signs) ? s * d : T(0);
+            if constexpr (DENSE) {
+                // the explicit FMAs of adj_downwind_sum
+                const T s = fma_t(nx, ox[j], ny * oy[j]);
+                const T d = fma_t(-ln[f][j], ia_n[f], l[j] * ia);
+                x[j] = (s > T(0) || all_signs) ? fma_t(s, d, x[j]) : x[j];
+            } else {
+                const T s = ox[j] * nx + oy[j] * ny;
+                const T d = l[j] * ia - ln[f][j] * ia_n[f];
+                x[j] += (s > T(0) || all_signs) ? s * d : T(0);
+            }
         }
     }
 
@@ -693,9 +710,10 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint(
 
     T o[V];
     T part_t = T(0), part_r = T(0);
+    if constexpr (DENSE) adj_update(l, x, src, cabs, cstream, cscat, o);
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-        o[j] = (l[j] - cabs * l[j]) - cstream * x[j] + cscat * src[j];
+        if constexpr (!DENSE) o[j] = (l[j] - cabs * l[j]) - cstream * x[j] + cscat * src[j];
         part_t += l[j] * p[j];
         part_r += p[j] * x[j];
     }
@@ -743,6 +761,24 @@ struct AdjCtx {
 };
 
 
+// The dense transposed step's downwind sum as explicit FMAs (shared by the transposed-step
+// kernels and the product tiles of the one-launch transposed step):
+//   xs = sum_f [s_f > 0 or Neumann ghost] s_f (l/A - l_f/A_f),   s_f = Omega . n_f
+template <int V, int MF, bool DENSE, typename T, typename GT>
+__device__ __forceinline__ void adj_downwind_sum(const AdjStage<V, MF, DENSE, T, GT>& d,
+                                                 const T (&ox)[V], const T (&oy)[V],
+                                                 T (&xs)[V]) {
+#pragma unroll
+    for (int f = 0; f < MF; ++f) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const T s = fma_t(d.nx[f], ox[j], d.ny[f] * oy[j]);
+            const T dd = fma_t(-d.ln[f][j], d.ia_n[f], d.l[j] * d.ia);
+            xs[j] = (s > T(0) || d.all_signs[f]) ? fma_t(s, dd, xs[j]) : xs[j];
+        }
+    }
+}
+
 template <int V, bool EXACT, int MF, bool DENSE, typename T, typename GT>
 __device__ __forceinline__ void adj_load_stage(AdjStage<V, MF, DENSE, T, GT>& d,
                                                const NbrList<MF>& nb,
@@ -788,13 +824,18 @@ __device__ __forceinline__ void adj_compute(const AdjStage<V, MF, DENSE, T, GT>&
     T xs[V];
 #pragma unroll
     for (int j = 0; j < V; ++j) xs[j] = T(0);
+    if constexpr (DENSE) {
+        // explicit FMAs (as in the dense forward update): the same bits wherever inlined
+        adj_downwind_sum(d, ox, oy, xs);
+    } else {
 #pragma unroll
-    for (int f = 0; f < MF; ++f) {
+        for (int f = 0; f < MF; ++f) {
 #pragma unroll
-        for (int j = 0; j < V; ++j) {
-            const T s = ox[j] * d.nx[f] + oy[j] * d.ny[f];
-            const T dd = d.l[j] * d.ia - d.ln[f][j] * d.ia_n[f];
-            xs[j] += (s > T(0) || d.all_signs[f]) ? s * dd : T(0);
+            for (int j = 0; j < V; ++j) {
+                const T s = ox[j] * d.nx[f] + oy[j] * d.ny[f];
+                const T dd = d.l[j] * d.ia - d.ln[f][j] * d.ia_n[f];
+                xs[j] += (s > T(0) || d.all_signs[f]) ? s * dd : T(0);
+            }
         }
     }
     const T cstream = a.dt * d.irho;
@@ -822,11 +863,20 @@ __device__ __forceinline__ void adj_compute(const AdjStage<V, MF, DENSE, T, GT>&
     }
     T o[V];
     T part_t = T(0), part_r = T(0);
+    if constexpr (DENSE) {
+        adj_update(d.l, xs, src, d.cabs, cstream, d.cscat, o);
 #pragma unroll
-    for (int j = 0; j < V; ++j) {
-        o[j] = (d.l[j] - d.cabs * d.l[j]) - cstream * xs[j] + d.cscat * src[j];
-        part_t += d.l[j] * d.p[j];
-        part_r += d.p[j] * xs[j];
+        for (int j = 0; j < V; ++j) {
+            part_t += d.l[j] * d.p[j];
+            part_r += d.p[j] * xs[j];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            o[j] = (d.l[j] - d.cabs * d.l[j]) - cstream * xs[j] + d.cscat * src[j];
+            part_t += d.l[j] * d.p[j];
+            part_r += d.p[j] * xs[j];
+        }
     }
     if constexpr (DA) dose_adjoint_row<V, EXACT>(o, x.da, a.inv_rho, c, q0, nq);
     buf_store_row<V, EXACT, T, kAuxStream>(x.out, (uint32_t)c * x.row_bytes, q0, nq, o);

@@ -885,6 +885,46 @@ hipError_t fused_dense_step(const snrt_mesh& m, const snrt_quad& q, const StepAr
     return launch_gemm_step(A, op.hi, op.lo, m.nc, op.K, op.Np, products, rexp, op.eb, se, st);
 }
 
+// The transposed dense step in one launch, on the same conditions as the forward one for the
+// transposed chain's last factor.
+bool adjoint_fusable(const snrt_mesh& m, const snrt_quad& q, const DenseB& B) {
+    if (!tune().step_fused || B.precision == SNRT_FP32 || m.mf != 3 || q.nq % 256 != 0)
+        return false;
+    const GemmOperand& last = B.adj[B.chain - 1];
+    return last.N == q.nq && last.Np == q.nq && last.K % 32 == 0 && last.hi != nullptr;
+}
+
+// The fused transposed step: the moment form's first product into after_G, the FP16 row
+// exponents, then one launch forms G tile by tile and updates lam_n from it, leaving the
+// gradient sums per 128-ordinate piece in part ([nc][nq / 128][3] floats), which the fold
+// adds to the gradients.
+template <typename GT>
+hipError_t fused_dense_adjoint(const snrt_mesh& m, const snrt_quad& q, const StepArgs32& a,
+                               const DenseB& B, const float* psi_n, const float* lam_np1,
+                               float* lam_n, GT* g_t, GT* g_s, GT* g_r, float* part,
+                               float* after_G, hipStream_t st, const DoseAdj& da) {
+    int32_t* rexp = ws_rexp(B, after_G, m.nc);
+    const float* A = lam_np1;
+    hipError_t e = hipSuccess;
+    if (B.chain == 2) {
+        e = product32(B, B.adj[0], lam_np1, after_G, m.nc, rexp, st);
+        A = after_G;
+    }
+    const GemmOperand& op = B.adj[B.chain - 1];
+    const int products = B.precision == SNRT_FP16X3 ? 0
+                         : B.precision == SNRT_BF16X3 ? 3
+                         : B.precision == SNRT_BF16X2 ? 2 : 1;
+    if (e == hipSuccess && products == 0) e = launch_row_exp_f16(A, m.nc, op.K, rexp, st);
+    if (e != hipSuccess) return e;
+    const AdjEpi ae{m.geom32, q.tab32, a, psi_n, lam_np1, lam_n, m.nc, q.nq, part, da};
+    e = launch_gemm_adjoint(A, op.hi, op.lo, m.nc, op.K, op.Np, products, rexp, op.eb, ae, st);
+    if (e != hipSuccess) return e;
+    if constexpr (std::is_same<GT, double>::value)
+        return launch_adjoint_fold64(m.nc, q.nq / 128, a, part, g_t, g_s, g_r, st);
+    else
+        return launch_adjoint_fold32(m.nc, q.nq / 128, a, part, g_t, g_s, g_r, st);
+}
+
 hipError_t scatter_product64(const snrt_scatter* sc, const double* A, double* C, int64_t M,
                              bool transpose, double* scratch, hipStream_t st) {
     const DenseB& B = sc->B;
@@ -928,6 +968,14 @@ snrt_status step_adjoint32_t(const char* fn, const snrt_mesh* m, const snrt_quad
                  std::string(fn) + ": lam_n aliases psi_n");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const float* G = nullptr;
+    if (sc->dense && adjoint_fusable(*m, *q, sc->B)) {
+        float* Gbuf = static_cast<float*>(ws);
+        const hipError_t e = fused_dense_adjoint(*m, *q, to32(a), sc->B, psi_n, lam_np1, lam_n,
+                                                 g_t, g_s, g_r, Gbuf,
+                                                 Gbuf + (size_t)m->nc * q->nq, st, da);
+        return e == hipSuccess ? SNRT_OK
+                               : hip_fail(e, (std::string(fn) + ": fused transposed step").c_str());
+    }
     if (sc->dense) {
         float* Gbuf = static_cast<float*>(ws);
         hipError_t e = scatter_product32(sc, lam_np1, Gbuf, m->nc, true,

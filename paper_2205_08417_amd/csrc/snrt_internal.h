@@ -383,6 +383,36 @@ hipError_t launch_gemm_combine(const float* A, const uint16_t* Bhi, const uint16
                                const int32_t* rexp, int32_t eb, const CombineEpi& ce,
                                hipStream_t st);
 
+// The transposed dense step in the same one-launch form (snrt_step_adjoint and the reverse
+// rollout with a dense or moment-form kernel): the last transposed product's tiles update
+// lam_n from lam_np1, psi_n and G = Lambda B^T held in LDS, with the dose functional's term
+// (da); the per-cell gradient sums leave as FP32 partial sums over 128-ordinate pieces,
+// part[(c * (nq / 128) + piece) * 3 + {t, s, r}], for launch_adjoint_fold.
+struct AdjEpi {
+    const CellGeom32* geom;
+    const float* tab;
+    StepArgs32 a;
+    const float* psi_n;
+    const float* lam_np1;
+    float* lam_n;
+    int64_t nc;
+    int32_t nq;
+    float* part;
+    DoseAdj da;
+};
+hipError_t launch_gemm_adjoint(const float* A, const uint16_t* Bhi, const uint16_t* Blo,
+                               int64_t M, int32_t K, int32_t N, int products,
+                               const int32_t* rexp, int32_t eb, const AdjEpi& ae,
+                               hipStream_t st);
+// g_t[c] += -dt alpha_t sum_p part_t, g_s[c] += dt alpha_s sum_p part_s,
+// g_r[c] += dt (1/rho)^2 sum_p part_r (pieces summed in order in FP32; NULL outputs skipped)
+hipError_t launch_adjoint_fold32(int64_t nc, int32_t npieces, const StepArgs32& a,
+                                 const float* part, float* g_t, float* g_s, float* g_r,
+                                 hipStream_t st);
+hipError_t launch_adjoint_fold64(int64_t nc, int32_t npieces, const StepArgs32& a,
+                                 const float* part, double* g_t, double* g_s, double* g_r,
+                                 hipStream_t st);
+
 namespace fused {
 template <bool RHO, bool DOSE>
 hipError_t launch_gemm_step_t(const float* A, const uint16_t* Bhi, const uint16_t* Blo,

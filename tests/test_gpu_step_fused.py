@@ -129,6 +129,32 @@ def _one_step(name, precision):
     return P, kw, bc, res
 
 
+def _one_adjoint(name, precision):
+    """One transposed step (snrt_step_adjoint) from a seeded adjoint state, with the three
+    per-cell gradients accumulated onto nonzero values, in whichever form this process runs
+    it: lam_n and the gradients in user order."""
+    from paper_2205_08417_amd import snrt
+    from paper_2205_08417_amd.solver import Solver
+    P, kw, bc = _case(name, 17)
+    boundary = snrt.SNRT_BC_NEUMANN if bc == "neumann" else snrt.SNRT_BC_DIRICHLET
+    S = Solver(P, precision=precision, **kw)
+    lam = np.random.default_rng(29).standard_normal((P.ncells, S.nq))
+    # small starting values: the FP32 rounding of g0 + increment stays far below the
+    # increments (1e-2 to 1 here)
+    g0 = 1e-3 * np.random.default_rng(30).standard_normal((3, P.ncells))
+    psi = S.initial_state()
+    l1 = S.to_internal(lam)
+    l0 = torch.empty_like(l1)
+    g = [S.cells_to_internal(g0[i]).contiguous() for i in range(3)]
+    S.adjoint_step(psi, l1, l0, g[0], g[1], g[2] if P.rho is not None else None,
+                   alpha_t=1.2, alpha_s=0.8, boundary=boundary)
+    torch.cuda.synchronize()
+    res = (S.to_user(l0).cpu().numpy(),
+           np.stack([S.to_user(x.reshape(-1, 1)).cpu().numpy().ravel() for x in g]))
+    S.close()
+    return P, kw, bc, lam, g0, res
+
+
 @pytest.fixture(scope="module")
 def two_launch():
     """Every case's step and dose from a child process that runs the two launches."""
@@ -145,7 +171,10 @@ def two_launch():
         "        _, _, _, r = T._one_step(name, prec)\n"
         "        np.save(f'{out}/{name}-{prec}-step.npy', r[0])\n"
         "        np.save(f'{out}/{name}-{prec}-dose-step.npy', r[1])\n"
-        "        np.save(f'{out}/{name}-{prec}-dose.npy', r[2])\n")
+        "        np.save(f'{out}/{name}-{prec}-dose.npy', r[2])\n"
+        "        _, _, _, _, _, a = T._one_adjoint(name, prec)\n"
+        "        np.save(f'{out}/{name}-{prec}-adj.npy', a[0])\n"
+        "        np.save(f'{out}/{name}-{prec}-adj-grad.npy', a[1])\n")
     env = dict(os.environ, SNRT_STEP_FUSED="0")
     with tempfile.TemporaryDirectory() as tmp:
         print("child: two-launch steps of every case", flush=True)
@@ -211,6 +240,53 @@ def test_fused_step_equals_two_launch_step_and_oracle(two_launch, name, precisio
     assert dose_err <= 1e-12
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("name", CASES)
+def test_fused_adjoint_equals_two_launch_adjoint_and_oracle(two_launch, name, precision):
+    """The transposed step in one launch (G = Lambda B^T formed tile by tile, the adjoint
+    update on the tile's cells, per-piece gradient sums folded by a second small kernel):
+    lam_n bit for bit against the two launches; the gradients to FP32 rounding of their
+    sums (128-ordinate pieces here, whole rows there); both against the oracle's transposed
+    step to the product's precision."""
+    from oracle import oracle as o
+    if _skip(name, precision):
+        pytest.skip("the last-round tile shapes are covered by two precisions")
+    P, kw, bc, lam, g0, (out, grad) = _one_adjoint(name, precision)
+    nc = P.ncells
+    ref = np.load(os.path.join(two_launch, f"{name}-{precision}-adj.npy"))
+    ref_g = np.load(os.path.join(two_launch, f"{name}-{precision}-adj-grad.npy"))
+    if not np.array_equal(out, ref):
+        bad = np.argwhere(out != ref)
+        print(f"  lam_n: {bad.shape[0]} elements differ, max {np.abs(out - ref).max():.3e}; "
+              f"first {bad[:6].tolist()}", flush=True)
+    assert np.array_equal(out, ref), "one launch must equal two launches"
+    nr = 3 if P.rho is not None else 2
+    for i, what in enumerate(("sigma_t", "sigma_s", "rho")[:nr]):
+        d = grad[i] - g0[i]
+        dr = ref_g[i] - g0[i]
+        err = float(np.max(np.abs(d - dr)) / np.max(np.abs(dr)))
+        print(f"  {name} {precision} g_{what} increment vs two-launch: {err:.2e}")
+        assert err <= 1e-5, what
+    if P.rho is None:
+        assert np.array_equal(grad[2], g0[2].astype(np.float32))   # untouched
+    # the oracle's transposed step (FP64) on the same inputs
+    op = _oracle_problem(P, kw, bc == "neumann")
+    gt, gs = np.zeros(nc), np.zeros(nc)
+    gr = np.zeros(nc) if P.rho is not None else None
+    want = o.adjoint_step(op, P.psi0, lam, P.dt, 1.2, 0.8, gt, gs, gr)
+    err = rel_l2(out, want)
+    print(f"  lam_n vs oracle: rel-L2 {err:.2e}")
+    assert err <= TOL[precision]
+    # g_sigma_t and g_rho hold no product term (FP32 sums of lam psi and psi times the
+    # downwind sum); g_sigma_s sums psi G over the row, which cancels for an adjoint state of
+    # random sign, so its relative error exceeds the product's by up to an order of magnitude
+    for i, ref_i in enumerate((gt, gs, gr)[:nr]):
+        e = rel_l2(grad[i] - g0[i], ref_i)
+        bar = 10 * TOL[precision] if i == 1 else 1e-5
+        print(f"  gradient {i} vs oracle: rel-L2 {e:.2e} (bar {bar:.0e})")
+        assert e <= bar
+
+
 def test_fused_rollout_equals_two_launch_rollout_in_a_fresh_process():
     """SNRT_STEP_FUSED=0 (read once per process): the same 6-step rollouts with the product
     and the step kernel as two launches, dense BF16x3 on 512 ordinates and the moment form
@@ -272,7 +348,9 @@ def test_reverse_rollout_dose_term_equals_separate_pass_in_a_fresh_process():
     rows; a child process with SNRT_STEP_FUSED=0 adds it in a pass of its own (and runs the
     forward dense steps in two launches).  The density gradients agree bit for bit; the doses
     to FP64 rounding (the one-launch step sums them over 128-ordinate pieces, the two-launch
-    step over 256-ordinate chunks)."""
+    step over 256-ordinate chunks).  With BF16 products the transposed steps run in one
+    launch as well, whose gradient sums over 128-ordinate pieces round differently from the
+    whole-row sums: there the gradients agree to 1e-6 of their largest entry."""
     script = (
         "import sys, numpy as np\n"
         f"sys.path.insert(0, {ROOT!r}); sys.path.insert(0, {os.path.join(ROOT, 'tests')!r})\n"
@@ -291,4 +369,7 @@ def test_reverse_rollout_dose_term_equals_separate_pass_in_a_fresh_process():
         g, d = _dose_gradient(config)
         print(f"{config}: max |grad - separate| = {np.abs(g - g_ref).max():.3e}")
         assert np.abs(d - d_ref).max() <= 1e-14 * np.abs(d_ref).max()
-        assert np.array_equal(g, g_ref)
+        if config == "dense-64":
+            assert np.array_equal(g, g_ref)
+        else:
+            assert np.abs(g - g_ref).max() <= 1e-6 * np.abs(g_ref).max()
