@@ -267,7 +267,13 @@ snrt_status snrt_step_f64(const snrt_mesh* mesh, const snrt_quad* quad,
  *     g_sigma_s[c] += dt alpha_s sum_q lam_np1[c][q] S_n[c][q]
  *     g_rho[c]     += sum_q lam_np1 . d psi'/d rho_c   (needs args->inv_rho)
  * psi_n is the state the forward step was applied to.  args->source/inflow do not enter.
- * ws as for snrt_step. */
+ * ws as for snrt_step.  Dense scattering on the conditions of snrt_step's one-launch form
+ * (BF16 / FP16 products, triangles, nq a multiple of 256) runs as one launch as well: the
+ * transposed product's tiles update lam_n, which is bitwise the two-launch lam_n; each
+ * gradient sum then runs over 128-ordinate pieces (in FP32, added in order by a second small
+ * kernel) instead of whole rows, so the gradients differ from the two-launch form's in the
+ * last bits only.  lam_n must not overlap lam_np1 or psi_n, and with dense scattering the
+ * workspace must not overlap psi_n (SNRT_E_ALIAS). */
 snrt_status snrt_step_adjoint(const snrt_mesh* mesh, const snrt_quad* quad,
                               const snrt_scatter* scatter, const snrt_step_args* args,
                               const float* psi_n, const float* lam_np1, float* lam_n,

@@ -314,3 +314,10 @@ def test_errors_alias_alignment_workspace():
     with pytest.raises(snrt.SnrtError) as ei:
         S.step(psi, out, dt=float("nan"))
     assert ei.value.status == snrt.SNRT_E_NONFINITE
+    # a dense transposed step writes its product (or its gradient pieces) into the
+    # workspace: psi_n inside it is refused before anything runs
+    psi_ws = S.ws[: psi.numel() * 4].view(torch.float32)
+    with pytest.raises(snrt.SnrtError) as ei:
+        S.adjoint_step(psi_ws, psi, out)
+    assert ei.value.status == snrt.SNRT_E_ALIAS
+    assert "workspace aliases psi_n" in str(ei.value)
