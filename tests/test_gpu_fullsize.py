@@ -3,6 +3,8 @@
 - The transposed step on the full adjoint checkerboard (51 842 cells x 256 ordinates, the
   persistent pipelined kernel in the launch shape the benchmark times): the adjoint state
   and all three gradient contributions element by element.
+- The one-launch dense transposed step on the full CSD phantom (299 538 x 512, BF16 hi+lo):
+  the adjoint state and the three gradients of every cell.
 - The wide-row adjoint kernel (more than 32 bytes of a row per lane: FP32 at 1024
   ordinates, FP64 at 512), isotropic and dense, with density and both boundary modes.
 - A 40-step differentiable rollout on the full adjoint mesh (checkpoints every 20) against
@@ -101,6 +103,45 @@ def test_adjoint_step_full_size_elementwise(signed, neumann):
     check_elementwise("g_sigma_s", _cells_user(S, g[1]), gs, grad_rtol, grad_floor)
     check_elementwise("g_rho", _cells_user(S, g[2]), gr, 1e-5, 1e-6)
     S.close()
+
+
+def test_csd_transposed_step_full_size_one_launch():
+    """The dense transposed step at the full CSD phantom's size (299 538 cells x 512
+    ordinates, HG g = 0.95, densities, BF16 hi+lo) in the form the dose-gradient benchmark
+    runs it: one launch of the transposed product whose tiles update lam_n (256 x 256 tiles
+    and the last round's smaller ones), and the fold of the gradient pieces.  Every element
+    of lam_n and every cell's three gradients against oracle.adjoint_step over the whole
+    mesh.  Positive states and adjoint states: no cancellation in the gradient sums."""
+    from oracle import oracle as o
+    P = I.build("csd_phantom_s512")
+    rng = np.random.default_rng(21)
+    P.source = None
+    psi = I.random_state(P.ncells, P.nq, seed=22, decades=3)
+    lam = rng.uniform(0.5, 1.5, (P.ncells, P.nq))
+    # the device's FP32 inputs, so that only the step's own arithmetic differs
+    psi = psi.astype(np.float32).astype(np.float64)
+    lam = lam.astype(np.float32).astype(np.float64)
+    at, as_ = 1.1, 0.9
+    S = _solver(P, precision="bf16x3")
+    print(f"CSD transposed step: {P.ncells} cells x {P.nq} ordinates, BF16x3", flush=True)
+    p = S.to_internal(psi)
+    l1 = S.to_internal(lam)
+    l0 = torch.empty_like(l1)
+    g = [torch.zeros(P.ncells, dtype=torch.float32, device="cuda") for _ in range(3)]
+    S.adjoint_step(p, l1, l0, g[0], g[1], g[2], alpha_t=at, alpha_s=as_)
+    torch.cuda.synchronize()
+    got = S.to_user(l0).cpu().numpy()
+    gg = [_cells_user(S, x) for x in g]
+    S.close()
+    del p, l1, l0, g
+    print("oracle transposed step over the whole mesh", flush=True)
+    op = o.OracleProblem.from_problem(P)
+    gt, gs, gr = np.zeros(P.ncells), np.zeros(P.ncells), np.zeros(P.ncells)
+    ref = o.adjoint_step(op, psi, lam, P.dt, at, as_, gt, gs, gr)
+    check_elementwise("lam_n", got, ref, 1e-5, 1e-6)
+    check_elementwise("g_sigma_t", gg[0], gt, 1e-5, 0.0)
+    check_elementwise("g_sigma_s", gg[1], gs, 1e-5, 1e-7)
+    check_elementwise("g_rho", gg[2], gr, 1e-5, 1e-6)
 
 
 @pytest.mark.parametrize("fp64,nq,dense,rho,neumann", [
