@@ -177,6 +177,16 @@ def step_form() -> str:
             "their cells and ordinates (triangles, nq % 256 == 0, BF16/FP16 products)")
 
 
+def transposed_step_form() -> str:
+    """How the library runs a dense transposed step (the same switch as the forward)."""
+    if os.environ.get("SNRT_STEP_FUSED", "1") == "0":
+        return ("two launches: transposed product into the workspace, then k_adjoint_p with "
+                "the dose functional's term")
+    return ("one launch: k_gemm_adjoint, the transposed product whose tiles run the adjoint "
+            "update (with the dose functional's term) of their cells and ordinates, then "
+            "k_adjoint_fold adding the per-piece gradient sums")
+
+
 def bench_dense(steps, warmup: int):
     """Anisotropic HG line source (100 352 cells x 1024 ordinates) with the scattering product
     in each mixed precision (BF16 hi+lo in three and two products, FP16 hi+lo in three) and
@@ -460,7 +470,7 @@ def bench_dose_gradient(nsteps: int = 500, ckpt: int = 20):
     the full CSD phantom (299 538 cells x 512 ordinates, the first 500 energy steps, BF16 hi+lo
     products, checkpoints every 20): the differentiable rollout's forward pass (steps with the
     fused dose) against its backward pass (segment recompute, transposed steps with the
-    transposed product, the dose's adjoint terms), each one library call."""
+    transposed product and the dose's adjoint terms), each one library call."""
     import numpy as np
     import torch
     from paper_2205_08417_amd import inputs as I
@@ -500,8 +510,10 @@ def bench_dose_gradient(nsteps: int = 500, ckpt: int = 20):
             "checkpoint_every": ckpt, "precision": "bf16x3",
             "functional": "sum_T A D - sum_O A D, gradient w.r.t. per-cell density",
             "forward_ms": fwd, "backward_ms": bwd, "adjoint_forward_ratio": bwd / fwd,
-            "parity": "the same path on the reduced CSD workload over the whole energy range "
-                      "is checked against the oracle in tests/test_gpu_fullsize.py"}
+            "step_form": step_form(), "transposed_step_form": transposed_step_form(),
+            "parity": "the same path on the reduced CSD workload over the whole energy range, "
+                      "and one transposed step on this full phantom, are checked against the "
+                      "oracle in tests/test_gpu_fullsize.py"}
 
 
 def bench_moments(steps, warmup: int, degree: int = 8):
