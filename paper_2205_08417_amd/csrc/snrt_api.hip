@@ -966,8 +966,9 @@ snrt_status step_adjoint32_t(const char* fn, const snrt_mesh* m, const snrt_quad
     const size_t bytes = (size_t)m->nc * q->nq * sizeof(float);
     SNRT_REQUIRE(!ranges_overlap(psi_n, bytes, lam_n, bytes), SNRT_E_ALIAS,
                  std::string(fn) + ": lam_n aliases psi_n");
-    SNRT_REQUIRE(!sc->dense || !ranges_overlap(psi_n, bytes, ws, ws_bytes), SNRT_E_ALIAS,
-                 std::string(fn) + ": workspace aliases psi_n");
+    SNRT_REQUIRE(!sc->dense || !ranges_overlap(psi_n, bytes, ws,
+                                               product_ws_elems(sc, m->nc) * sizeof(float)),
+                 SNRT_E_ALIAS, std::string(fn) + ": workspace aliases psi_n");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const float* G = nullptr;
     if (sc->dense && adjoint_fusable(*m, *q, sc->B)) {
